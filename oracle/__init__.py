@@ -1,0 +1,255 @@
+"""Python access to the FP64 CPU oracle (``oracle/liboracle.so``).
+
+TEST INFRASTRUCTURE ONLY: used by ``tests/``, the smoke check and the CPU
+baseline leg of ``bench.py``.  The product library never loads it.
+
+The oracle is a plain sequential C transcription of the scheme of
+"AVIP: a low temperature plasma code" (arXiv 2201.01291); see ``oracle.c`` for
+the passages each function follows.  ``build()`` compiles it with gcc.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+MAXSP = 16
+
+# model / flux / limiter codes of the oracle
+GAS, DRIFT_DIFFUSION = 0, 1
+HLLC, ROE = 0, 1
+FIRST_ORDER, MINMOD, VANLEER, SWEBY, UNLIMITED = 0, 1, 2, 3, 4
+
+
+def build(verbose: bool = False) -> str:
+    """Compile liboracle.so (plain gcc, -O2, no fast-math, no FMA contraction)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
+           "-Wall", "-Wextra", "-o", LIB_PATH, os.path.join(HERE, "oracle.c"), "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    return LIB_PATH
+
+
+class _Phys(C.Structure):
+    _fields_ = [("model", C.c_int32), ("flux", C.c_int32), ("limiter", C.c_int32),
+                ("rk", C.c_int32), ("nspecies", C.c_int32), ("closure", C.c_int32),
+                ("beta", C.c_double), ("cfl", C.c_double), ("fourier", C.c_double),
+                ("gamma", C.c_double), ("entropy_fix", C.c_double),
+                ("z", C.c_double * MAXSP), ("mu", C.c_double * MAXSP),
+                ("D", C.c_double * MAXSP)]
+
+
+@dataclass
+class Phys:
+    model: int = GAS
+    flux: int = HLLC
+    limiter: int = MINMOD
+    rk: int = 2
+    nspecies: int = 0
+    closure: bool = True
+    beta: float = 1.0
+    cfl: float = 0.5
+    fourier: float = 0.25
+    gamma: float = 1.4
+    entropy_fix: float = 0.1
+    z: list = field(default_factory=list)
+    mu: list = field(default_factory=list)
+    D: list = field(default_factory=list)
+
+    def to_c(self) -> _Phys:
+        p = _Phys()
+        p.model, p.flux, p.limiter, p.rk = self.model, self.flux, self.limiter, self.rk
+        p.nspecies, p.closure = self.nspecies, int(bool(self.closure))
+        p.beta, p.cfl, p.fourier = self.beta, self.cfl, self.fourier
+        p.gamma, p.entropy_fix = self.gamma, self.entropy_fix
+        for k, (z, mu, D) in enumerate(zip(self.z, self.mu, self.D)):
+            p.z[k], p.mu[k], p.D[k] = z, mu, D
+        return p
+
+    def nvar(self, nd: int) -> int:
+        return self.nspecies if self.model == DRIFT_DIFFUSION else 2 + nd + self.nspecies
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = C.CDLL(LIB_PATH)
+        dp, ip = C.POINTER(C.c_double), C.POINTER(C.c_int64)
+        L.om_mesh_create.restype = C.c_void_p
+        L.om_mesh_create.argtypes = [C.c_int, C.c_int64, dp, C.c_int64, C.c_int, ip, dp,
+                                     C.POINTER(C.c_int)]
+        L.om_mesh_destroy.argtypes = [C.c_void_p]
+        L.om_mesh_counts.argtypes = [C.c_void_p, ip]
+        L.om_geometry.argtypes = [C.c_void_p, dp, dp, dp, dp]
+        L.om_edge_normals.argtypes = [C.c_void_p, dp, ip]
+        L.om_gradient.argtypes = [C.c_void_p, C.c_int, dp, dp]
+        L.om_slope_limiter.restype = C.c_double
+        L.om_slope_limiter.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double]
+        L.om_psi_limiter.restype = C.c_double
+        L.om_psi_limiter.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double]
+        L.om_euler_flux.argtypes = [C.c_int, C.c_int, dp, dp, dp]
+        L.om_hllc.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, dp, dp, dp, dp]
+        L.om_roe.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, dp, dp, dp, dp]
+        pp = C.POINTER(_Phys)
+        L.om_residual.argtypes = [C.c_void_p, pp, dp, dp, C.c_double, dp]
+        L.om_timestep.argtypes = [C.c_void_p, pp, dp, dp, dp]
+        L.om_step.argtypes = [C.c_void_p, pp, dp, dp, C.c_int, C.c_double, dp, dp,
+                              C.POINTER(C.c_int)]
+        L.om_sums.argtypes = [C.c_void_p, C.c_int, dp, dp, dp]
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _c64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"oracle {what} failed with status {code}")
+        self.code = code
+
+
+class OracleMesh:
+    """FP64 oracle view of a mesh (geometry computed once at construction)."""
+
+    def __init__(self, mesh):
+        L = lib()
+        self.nd, self.nn = mesh.ndim, mesh.nnodes
+        self.nc, self.nv = mesh.ncells, mesh.nv
+        self.ne = 3 if self.nv == 3 else 6
+        xyz = _c64(mesh.xyz)
+        cells = np.ascontiguousarray(mesh.cells, dtype=np.int64)
+        per = None if mesh.period is None else _c64(mesh.period)
+        st = C.c_int(0)
+        h = L.om_mesh_create(self.nd, self.nn, _d(xyz), self.nc, self.nv,
+                             cells.ctypes.data_as(C.POINTER(C.c_int64)),
+                             _d(per) if per is not None else None, C.byref(st))
+        if not h:
+            raise OracleError(st.value, "mesh_create")
+        self._h = C.c_void_p(h)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.om_mesh_destroy(h)
+            self._h = None
+
+    def counts(self):
+        out = np.zeros(4, dtype=np.int64)
+        lib().om_mesh_counts(self._h, out.ctypes.data_as(C.POINTER(C.c_int64)))
+        return dict(nn=int(out[0]), nc=int(out[1]), nbfaces=int(out[2]), nbnodes=int(out[3]))
+
+    def geometry(self):
+        S = np.zeros((self.nc, self.nv, self.nd))
+        Vc = np.zeros(self.nc)
+        Vn = np.zeros(self.nn)
+        Sb = np.zeros((self.nd, self.nn))
+        lib().om_geometry(self._h, _d(S), _d(Vc), _d(Vn), _d(Sb))
+        return dict(S=S, Vc=Vc, Vn=Vn, Sb=Sb)
+
+    def edge_normals(self):
+        Sij = np.zeros((self.nc, self.ne, self.nd))
+        ends = np.zeros((self.nc, self.ne, 2), dtype=np.int64)
+        lib().om_edge_normals(self._h, _d(Sij), ends.ctypes.data_as(C.POINTER(C.c_int64)))
+        return Sij, ends
+
+    def gradient(self, W):
+        W = _c64(W)
+        nvar = W.shape[0]
+        G = np.zeros((nvar, self.nd, self.nn))
+        lib().om_gradient(self._h, nvar, _d(W), _d(G))
+        return G
+
+    def residual(self, phys: Phys, U, E=None, dt: float = 0.0):
+        U = _c64(U)
+        r = np.zeros_like(U)
+        Ec = None if E is None else _c64(E)
+        p = phys.to_c()
+        st = lib().om_residual(self._h, C.byref(p), _d(U), _d(Ec) if Ec is not None else None,
+                               float(dt), _d(r))
+        if st:
+            raise OracleError(st, "residual")
+        return r
+
+    def timestep(self, phys: Phys, U, E=None) -> float:
+        U = _c64(U)
+        Ec = None if E is None else _c64(E)
+        dt = C.c_double(0.0)
+        p = phys.to_c()
+        st = lib().om_timestep(self._h, C.byref(p), _d(U), _d(Ec) if Ec is not None else None,
+                               C.byref(dt))
+        if st:
+            raise OracleError(st, "timestep")
+        return dt.value
+
+    def step(self, phys: Phys, U, E=None, nsteps: int = 1, t_end: float = 0.0, t0: float = 0.0,
+             check: bool = True):
+        U = _c64(U).copy()
+        Ec = None if E is None else _c64(E)
+        t, dtl, done = C.c_double(t0), C.c_double(0.0), C.c_int(0)
+        p = phys.to_c()
+        st = lib().om_step(self._h, C.byref(p), _d(U), _d(Ec) if Ec is not None else None,
+                           int(nsteps), float(t_end), C.byref(t), C.byref(dtl), C.byref(done))
+        if st and check:
+            raise OracleError(st, "step")
+        return U, t.value, dtl.value, done.value
+
+    def sums(self, U):
+        U = _c64(U)
+        nvar = U.shape[0]
+        s, a = np.zeros(nvar), np.zeros(nvar)
+        lib().om_sums(self._h, nvar, _d(U), _d(s), _d(a))
+        return s, a
+
+
+def slope_limiter(kind, beta, a, b) -> float:
+    return lib().om_slope_limiter(int(kind), float(beta), float(a), float(b))
+
+
+def psi_limiter(kind, beta, a, b) -> float:
+    return lib().om_psi_limiter(int(kind), float(beta), float(a), float(b))
+
+
+def euler_flux(nd, nsp, W, S):
+    W, S = _c64(W), _c64(S)
+    F = np.zeros(2 + nd + nsp)
+    lib().om_euler_flux(nd, nsp, _d(W), _d(S), _d(F))
+    return F
+
+
+def hllc(nd, nsp, WL, WR, S, gL=1.4, gR=None):
+    WL, WR, S = _c64(WL), _c64(WR), _c64(S)
+    F = np.zeros(2 + nd + nsp)
+    lib().om_hllc(nd, nsp, float(gL), float(gL if gR is None else gR), _d(WL), _d(WR), _d(S), _d(F))
+    return F
+
+
+def roe(nd, nsp, WL, WR, S, gamma=1.4, fix=0.1):
+    WL, WR, S = _c64(WL), _c64(WR), _c64(S)
+    F = np.zeros(2 + nd + nsp)
+    lib().om_roe(nd, nsp, float(gamma), float(fix), _d(WL), _d(WR), _d(S), _d(F))
+    return F
+
+
+def prim_to_W(rho, vel, p, gamma=1.4, Y=()):
+    """Reconstructed-variable vector (rho, rho u, rho E, rho Y, p) of one
+    state, for the point-wise flux functions."""
+    vel = np.asarray(vel, dtype=np.float64)
+    rE = p / (gamma - 1.0) + 0.5 * rho * float(vel @ vel)
+    return np.concatenate([[rho], rho * vel, [rE], rho * np.asarray(Y, dtype=np.float64), [p]])

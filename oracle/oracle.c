@@ -1,0 +1,766 @@
+/*
+ * oracle.c -- plain FP64 CPU oracle of the vertex-centred explicit residual
+ * described in "AVIP: a low temperature plasma code" (arXiv 2201.01291).
+ *
+ * TEST INFRASTRUCTURE ONLY.  The test-suite, the smoke check and the CPU
+ * baseline of the benchmark are the only users.  Nothing here is shared with
+ * the HIP library: geometry, gradients, limiters, fluxes and the time loop
+ * are written out again, sequentially, in the order the paper states them.
+ *
+ * Paper passages followed (section / equation names of the paper):
+ *   geometry      Sec. "Nomenclature and notations", eq. (node_normal); the
+ *                 dual normal identity sum_j S_ij = S_i/n_d and the 2D value
+ *                 n_ij = (n_i - n_j)/6 (Sec. "Integrating the Poisson
+ *                 equation", cartesian and axisymmetric parts)
+ *   cell gradient Sec. "Integrating the Poisson equation":
+ *                 grad phi_tau = -1/(V_tau n_d) sum_k phi_k S_k
+ *   residual      eq. (vertex_centered_flux): a sum over the cells around a
+ *                 node of the flux through each cell-edge piece of the dual
+ *                 surface
+ *   drift-diff.   Sec. "Limited Lax-Wendroff scheme" and "Central difference
+ *                 diffusive flux integration"
+ *   Euler         Sec. "The HLLC solver", eq. (hllc_formulation_mutlicomponent);
+ *                 Sec. "The MUSCL procedure implementation in AVIP",
+ *                 eq. (virtual_node_reconstruction) and the co-reconstruction
+ *                 of pressure
+ *   closure       Sec. "Boundary conditions in AVIP", first option (node flux)
+ *   time step     Sec. "Time step computation", eqs. (dt_conv), (dt_diff)
+ *   RK            Sec. "Time integration of the HLLC MUSCL-Hancock solver",
+ *                 table (rk_coeffs)
+ *
+ * Readings where the paper is silent or garbled (listed in the design notes):
+ *   nodal volume V_i = sum_tau V_tau / n_v (median dual);
+ *   nodal gradient = volume-weighted average of the cell gradients;
+ *   limiters in slope form from van Leer (1974) and Sweby (1984);
+ *   LLW ratio r = (u_w - u_k)/(u_m - u_w) (upwind node w, downwind m);
+ *   HLLC wave speeds: Davis estimates; species star entry = factor * rho*Y;
+ *   Roe flux (not in the paper): textbook, Harten fix on acoustic waves;
+ *   RK stage formula carries the time step: U(k) = U^n - a_k dt r/V;
+ *   cell size dx = 2 n_d V_tau / sum_k |S_k| (inscribed diameter).
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+struct om_mesh {
+  int nd, nv, ne;
+  int64_t nn, nc;
+  int64_t *cell; /* [nc][nv] */
+  double *X;     /* [nc][nv][nd] unwrapped vertex coordinates */
+  double *S;     /* [nc][nv][nd] node normals S_k (outward normal of the opposite face) */
+  double *Vc;    /* [nc] */
+  double *Vn;    /* [nn] */
+  double *Sb;    /* [nn][nd] boundary node normals */
+  char *bnd;     /* [nn] node lies on the domain boundary */
+  int64_t nbfaces;
+};
+
+/* local cell-edges, oriented from the lower to the higher local vertex */
+static const int TRI_EDGES[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+static const int TET_EDGES[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+
+static const int *edge_of(int nv, int e) {
+  return nv == 3 ? TRI_EDGES[e] : TET_EDGES[e];
+}
+
+int om_nvar(int nd, const om_phys *ph) {
+  if (ph->model == 1) return ph->nspecies;
+  return 2 + nd + ph->nspecies;
+}
+
+/* ------------------------------------------------------------------ */
+/* geometry                                                             */
+/* ------------------------------------------------------------------ */
+
+/* Node normal S_k of a simplex: for a simplex every face holds n_d nodes, so
+ * eq. (node_normal) gives S_k = (minus the sum of the faces through k), which
+ * equals the outward area vector of the face opposite k.  Computed directly
+ * as that face's area vector, oriented away from vertex k. */
+static void simplex_normals(int nd, const double *X, double *S, double *V) {
+  if (nd == 2) {
+    double e1x = X[2] - X[0], e1y = X[3] - X[1];
+    double e2x = X[4] - X[0], e2y = X[5] - X[1];
+    *V = 0.5 * fabs(e1x * e2y - e1y * e2x);
+    for (int k = 0; k < 3; k++) {
+      int a = (k + 1) % 3, b = (k + 2) % 3;
+      double tx = X[2 * b] - X[2 * a], ty = X[2 * b + 1] - X[2 * a + 1];
+      double nx = ty, ny = -tx;
+      double ox = X[2 * a] - X[2 * k], oy = X[2 * a + 1] - X[2 * k + 1];
+      if (nx * ox + ny * oy < 0.0) { nx = -nx; ny = -ny; }
+      S[2 * k] = nx;
+      S[2 * k + 1] = ny;
+    }
+  } else {
+    double e[3][3];
+    for (int q = 0; q < 3; q++)
+      for (int d = 0; d < 3; d++) e[q][d] = X[3 * (q + 1) + d] - X[d];
+    double det = e[0][0] * (e[1][1] * e[2][2] - e[1][2] * e[2][1]) -
+                 e[0][1] * (e[1][0] * e[2][2] - e[1][2] * e[2][0]) +
+                 e[0][2] * (e[1][0] * e[2][1] - e[1][1] * e[2][0]);
+    *V = fabs(det) / 6.0;
+    for (int k = 0; k < 4; k++) {
+      int f[3], q = 0;
+      for (int v = 0; v < 4; v++)
+        if (v != k) f[q++] = v;
+      double a[3], b[3], n[3], o[3];
+      for (int d = 0; d < 3; d++) {
+        a[d] = X[3 * f[1] + d] - X[3 * f[0] + d];
+        b[d] = X[3 * f[2] + d] - X[3 * f[0] + d];
+        o[d] = X[3 * f[0] + d] - X[3 * k + d];
+      }
+      n[0] = 0.5 * (a[1] * b[2] - a[2] * b[1]);
+      n[1] = 0.5 * (a[2] * b[0] - a[0] * b[2]);
+      n[2] = 0.5 * (a[0] * b[1] - a[1] * b[0]);
+      if (n[0] * o[0] + n[1] * o[1] + n[2] * o[2] < 0.0) {
+        n[0] = -n[0]; n[1] = -n[1]; n[2] = -n[2];
+      }
+      for (int d = 0; d < 3; d++) S[3 * k + d] = n[d];
+    }
+  }
+}
+
+typedef struct {
+  int64_t key[3];
+  int64_t cell;
+  int k;
+} face_rec;
+
+static int face_cmp(const void *pa, const void *pb) {
+  const face_rec *a = pa, *b = pb;
+  for (int q = 0; q < 3; q++) {
+    if (a->key[q] < b->key[q]) return -1;
+    if (a->key[q] > b->key[q]) return 1;
+  }
+  if (a->cell < b->cell) return -1;
+  if (a->cell > b->cell) return 1;
+  return 0;
+}
+
+static void sort_small(int64_t *v, int n) {
+  for (int i = 1; i < n; i++)
+    for (int j = i; j > 0 && v[j - 1] > v[j]; j--) {
+      int64_t t = v[j]; v[j] = v[j - 1]; v[j - 1] = t;
+    }
+}
+
+void om_mesh_destroy(om_mesh *m) {
+  if (!m) return;
+  free(m->cell); free(m->X); free(m->S); free(m->Vc); free(m->Vn); free(m->Sb); free(m->bnd);
+  free(m);
+}
+
+om_mesh *om_mesh_create(int nd, int64_t nn, const double *xyz, int64_t nc, int nv,
+                        const int64_t *cells, const double *period, int *status) {
+  *status = -1;
+  if (!(nd == 2 || nd == 3) || nv != nd + 1 || nn <= 0 || nc <= 0 || !xyz || !cells) return NULL;
+  om_mesh *m = calloc(1, sizeof(*m));
+  if (!m) { *status = -3; return NULL; }
+  m->nd = nd; m->nv = nv; m->ne = nd == 2 ? 3 : 6; m->nn = nn; m->nc = nc;
+  m->cell = malloc(sizeof(int64_t) * nc * nv);
+  m->X = malloc(sizeof(double) * nc * nv * nd);
+  m->S = malloc(sizeof(double) * nc * nv * nd);
+  m->Vc = malloc(sizeof(double) * nc);
+  m->Vn = calloc(nn, sizeof(double));
+  m->Sb = calloc(nn * nd, sizeof(double));
+  m->bnd = calloc(nn, 1);
+  if (!m->cell || !m->X || !m->S || !m->Vc || !m->Vn || !m->Sb || !m->bnd) {
+    om_mesh_destroy(m); *status = -3; return NULL;
+  }
+  double vmax = 0.0;
+  for (int64_t c = 0; c < nc; c++) {
+    for (int k = 0; k < nv; k++) {
+      int64_t i = cells[(int64_t)k * nc + c];
+      if (i < 0 || i >= nn) { om_mesh_destroy(m); *status = -2; return NULL; }
+      m->cell[c * nv + k] = i;
+    }
+    /* unwrap to the minimum image of the first vertex */
+    double *X = m->X + c * nv * nd;
+    for (int k = 0; k < nv; k++)
+      for (int d = 0; d < nd; d++) {
+        double x = xyz[(int64_t)d * nn + m->cell[c * nv + k]];
+        if (period && period[d] > 0.0 && k > 0) {
+          double x0 = X[d];
+          x -= period[d] * nearbyint((x - x0) / period[d]);
+        }
+        X[k * nd + d] = x;
+      }
+    simplex_normals(nd, X, m->S + c * nv * nd, &m->Vc[c]);
+    if (m->Vc[c] > vmax) vmax = m->Vc[c];
+  }
+  for (int64_t c = 0; c < nc; c++)
+    if (!(m->Vc[c] > 1e-12 * vmax)) { om_mesh_destroy(m); *status = -2; return NULL; }
+  for (int64_t c = 0; c < nc; c++)
+    for (int k = 0; k < nv; k++) m->Vn[m->cell[c * nv + k]] += m->Vc[c] / nv;
+
+  /* boundary faces: faces owned by exactly one cell */
+  int64_t nf = nc * nv;
+  face_rec *f = malloc(sizeof(face_rec) * nf);
+  if (!f) { om_mesh_destroy(m); *status = -3; return NULL; }
+  for (int64_t c = 0; c < nc; c++)
+    for (int k = 0; k < nv; k++) {
+      face_rec *r = &f[c * nv + k];
+      int q = 0;
+      r->key[0] = r->key[1] = r->key[2] = -1;
+      for (int v = 0; v < nv; v++)
+        if (v != k) r->key[q++] = m->cell[c * nv + v];
+      sort_small(r->key, nd);
+      r->cell = c;
+      r->k = k;
+    }
+  qsort(f, nf, sizeof(face_rec), face_cmp);
+  for (int64_t a = 0; a < nf;) {
+    int64_t b = a + 1;
+    while (b < nf && memcmp(f[b].key, f[a].key, sizeof(f[a].key)) == 0) b++;
+    if (b - a > 2) { free(f); om_mesh_destroy(m); *status = -2; return NULL; }
+    if (b - a == 1) {
+      /* the face opposite vertex k: its outward area vector is S_k; each of its
+       * n_d nodes receives an equal share (boundary node normal S_i^b) */
+      const double *Sk = m->S + (f[a].cell * nv + f[a].k) * nd;
+      for (int q = 0; q < nd; q++) {
+        int64_t i = f[a].key[q];
+        m->bnd[i] = 1;
+        for (int d = 0; d < nd; d++) m->Sb[i * nd + d] += Sk[d] / nd;
+      }
+      m->nbfaces++;
+    }
+    a = b;
+  }
+  free(f);
+  *status = 0;
+  return m;
+}
+
+void om_mesh_counts(const om_mesh *m, int64_t *out) {
+  int64_t nb = 0;
+  for (int64_t i = 0; i < m->nn; i++) nb += m->bnd[i];
+  out[0] = m->nn; out[1] = m->nc; out[2] = m->nbfaces; out[3] = nb;
+}
+
+void om_geometry(const om_mesh *m, double *S, double *Vc, double *Vn, double *Sb) {
+  if (S) memcpy(S, m->S, sizeof(double) * m->nc * m->nv * m->nd);
+  if (Vc) memcpy(Vc, m->Vc, sizeof(double) * m->nc);
+  if (Vn) memcpy(Vn, m->Vn, sizeof(double) * m->nn);
+  if (Sb)
+    for (int d = 0; d < m->nd; d++)
+      for (int64_t i = 0; i < m->nn; i++) Sb[d * m->nn + i] = m->Sb[i * m->nd + d];
+}
+
+/* dual-surface normal of cell-edge (a,b): S_ab = (S_a - S_b) / (n_d n_v) */
+static void edge_normal(const om_mesh *m, int64_t c, int a, int b, double *Sab) {
+  const double *S = m->S + c * m->nv * m->nd;
+  for (int d = 0; d < m->nd; d++)
+    Sab[d] = (S[a * m->nd + d] - S[b * m->nd + d]) / (double)(m->nd * m->nv);
+}
+
+void om_edge_normals(const om_mesh *m, double *Sij, int64_t *ends) {
+  for (int64_t c = 0; c < m->nc; c++)
+    for (int e = 0; e < m->ne; e++) {
+      const int *ab = edge_of(m->nv, e);
+      edge_normal(m, c, ab[0], ab[1], Sij + (c * m->ne + e) * m->nd);
+      ends[(c * m->ne + e) * 2] = m->cell[c * m->nv + ab[0]];
+      ends[(c * m->ne + e) * 2 + 1] = m->cell[c * m->nv + ab[1]];
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* gradients                                                            */
+/* ------------------------------------------------------------------ */
+
+/* cell gradient grad W_tau = -1/(n_d V_tau) sum_k W_k S_k, then the nodal
+ * gradient as the volume-weighted mean over the cells around the node:
+ * grad W_i = (1/V_i) sum_tau (V_tau/n_v) grad W_tau */
+void om_gradient(const om_mesh *m, int nvar, const double *W, double *G) {
+  int nd = m->nd, nv = m->nv;
+  int64_t nn = m->nn;
+  memset(G, 0, sizeof(double) * nvar * nd * nn);
+  for (int64_t c = 0; c < m->nc; c++) {
+    const double *S = m->S + c * nv * nd;
+    for (int v = 0; v < nvar; v++) {
+      double g[3] = {0, 0, 0};
+      for (int k = 0; k < nv; k++) {
+        double w = W[(int64_t)v * nn + m->cell[c * nv + k]];
+        for (int d = 0; d < nd; d++) g[d] += w * S[k * nd + d];
+      }
+      for (int d = 0; d < nd; d++) g[d] *= -1.0 / (nd * m->Vc[c]);
+      for (int k = 0; k < nv; k++) {
+        int64_t i = m->cell[c * nv + k];
+        for (int d = 0; d < nd; d++) G[((int64_t)v * nd + d) * nn + i] += m->Vc[c] / nv * g[d];
+      }
+    }
+  }
+  for (int v = 0; v < nvar; v++)
+    for (int d = 0; d < nd; d++)
+      for (int64_t i = 0; i < nn; i++) G[((int64_t)v * nd + d) * nn + i] /= m->Vn[i];
+}
+
+/* ------------------------------------------------------------------ */
+/* limiters                                                             */
+/* ------------------------------------------------------------------ */
+
+static double sgn(double x) { return x > 0 ? 1.0 : (x < 0 ? -1.0 : 0.0); }
+
+/* Slope form L(a, b) of the limited slope (van Leer 1974, Sweby 1984):
+ * 0 first order, 1 minmod, 2 van Leer harmonic mean, 3 Sweby-beta,
+ * 4 unlimited centred slope (a + b)/2. */
+double om_slope_limiter(int kind, double beta, double a, double b) {
+  if (kind == 0) return 0.0;
+  if (kind == 4) return 0.5 * (a + b);
+  if (a * b <= 0.0) return 0.0;
+  double aa = fabs(a), bb = fabs(b);
+  if (kind == 1) return sgn(a) * (aa < bb ? aa : bb);
+  if (kind == 2) return 2.0 * a * b / (a + b);
+  double m1 = beta * aa < bb ? beta * aa : bb;
+  double m2 = aa < beta * bb ? aa : beta * bb;
+  return sgn(a) * (m1 > m2 ? m1 : m2);
+}
+
+/* Flux-limiter form Psi(R) with R = a/b for the limited Lax-Wendroff flux:
+ * 0 upwind (Psi = 0), 1 minmod, 2 van Leer (R+|R|)/(1+|R|), 3 Sweby-beta
+ * max(0, min(beta R, 1), min(R, beta)), 4 plain Lax-Wendroff (Psi = 1).
+ * Psi = 0 when a*b <= 0 (which includes b = 0). */
+double om_psi_limiter(int kind, double beta, double a, double b) {
+  if (kind == 0) return 0.0;
+  if (kind == 4) return 1.0;
+  if (a * b <= 0.0) return 0.0;
+  double R = a / b;
+  if (kind == 2) return (R + fabs(R)) / (1.0 + fabs(R));
+  double bt = kind == 1 ? 1.0 : beta;
+  double m1 = bt * R < 1.0 ? bt * R : 1.0;
+  double m2 = R < bt ? R : bt;
+  double p = m1 > m2 ? m1 : m2;
+  return p > 0.0 ? p : 0.0;
+}
+
+/* ------------------------------------------------------------------ */
+/* gas fluxes; W = (rho, rho u_1..rho u_nd, rho E, rho Y_1..rho Y_ns, p)   */
+/* ------------------------------------------------------------------ */
+
+/* physical Euler flux F(W) . S (tensor form of Sec. "The HLLC solver") */
+void om_euler_flux(int nd, int nsp, const double *W, const double *S, double *F) {
+  double rho = W[0], rhoE = W[1 + nd], p = W[2 + nd + nsp];
+  double q = 0.0;
+  for (int d = 0; d < nd; d++) q += W[1 + d] / rho * S[d];
+  F[0] = rho * q;
+  for (int d = 0; d < nd; d++) F[1 + d] = W[1 + d] * q + p * S[d];
+  F[1 + nd] = (rhoE + p) * q;
+  for (int k = 0; k < nsp; k++) F[2 + nd + k] = W[2 + nd + k] * q;
+}
+
+/* HLLC flux through the area vector S (|S| times the unit-normal flux).
+ * The rotation to the edge frame of the paper is written without forming the
+ * rotation matrix: normal velocity q = u.n, tangential velocity kept as is.
+ * Star state: eq. (hllc_formulation_mutlicomponent).  gL, gR: ratio of
+ * specific heats of the two sides. */
+void om_hllc(int nd, int nsp, double gL, double gR, const double *WL, const double *WR,
+             const double *S, double *F) {
+  int nvar = 2 + nd + nsp;
+  double A = 0.0;
+  for (int d = 0; d < nd; d++) A += S[d] * S[d];
+  A = sqrt(A);
+  double n[3] = {0, 0, 0};
+  for (int d = 0; d < nd; d++) n[d] = S[d] / A;
+  double rL = WL[0], rR = WR[0], pL = WL[nvar], pR = WR[nvar];
+  double qL = 0, qR = 0;
+  for (int d = 0; d < nd; d++) { qL += WL[1 + d] / rL * n[d]; qR += WR[1 + d] / rR * n[d]; }
+  double aL = sqrt(gL * pL / rL), aR = sqrt(gR * pR / rR);
+  double SL = fmin(qL - aL, qR - aR), SR = fmax(qL + aL, qR + aR);
+  double Ss = (pR - pL + rL * qL * (SL - qL) - rR * qR * (SR - qR)) /
+              (rL * (SL - qL) - rR * (SR - qR));
+  double FK[2 + 3 + OM_MAXSP];
+  if (0.0 <= SL) {
+    om_euler_flux(nd, nsp, WL, n, FK);
+  } else if (SR < 0.0) {
+    om_euler_flux(nd, nsp, WR, n, FK);
+  } else {
+    const double *WK = (0.0 <= Ss) ? WL : WR;
+    double SK = (0.0 <= Ss) ? SL : SR;
+    double rK = WK[0], pK = WK[nvar];
+    double qK = (0.0 <= Ss) ? qL : qR;
+    om_euler_flux(nd, nsp, WK, n, FK);
+    double fac = rK * (SK - qK) / (SK - Ss);
+    double Us[2 + 3 + OM_MAXSP];
+    Us[0] = fac;
+    for (int d = 0; d < nd; d++) Us[1 + d] = fac * (WK[1 + d] / rK + (Ss - qK) * n[d]);
+    Us[1 + nd] = fac * (WK[1 + nd] / rK + (Ss - qK) * (Ss + pK / (rK * (SK - qK))));
+    for (int k = 0; k < nsp; k++) Us[2 + nd + k] = fac * WK[2 + nd + k] / rK;
+    for (int v = 0; v < nvar; v++) FK[v] += SK * (Us[v] - WK[v]);
+  }
+  for (int v = 0; v < nvar; v++) F[v] = A * FK[v];
+}
+
+/* Roe flux (textbook, not given in the paper): F = (F_L + F_R)/2 - 1/2 sum
+ * |lambda_k| alpha_k K_k with sqrt(rho)-weighted averages; passive species
+ * travel with the contact.  Harten's fix |l| -> (l^2 + d^2)/(2d) for |l| < d
+ * on the two acoustic waves, d = fix * (Roe sound speed). */
+void om_roe(int nd, int nsp, double gamma, double fix, const double *WL, const double *WR,
+            const double *S, double *F) {
+  int nvar = 2 + nd + nsp;
+  double A = 0.0;
+  for (int d = 0; d < nd; d++) A += S[d] * S[d];
+  A = sqrt(A);
+  double n[3] = {0, 0, 0};
+  for (int d = 0; d < nd; d++) n[d] = S[d] / A;
+  double rL = WL[0], rR = WR[0], pL = WL[nvar], pR = WR[nvar];
+  double uL[3] = {0, 0, 0}, uR[3] = {0, 0, 0};
+  for (int d = 0; d < nd; d++) { uL[d] = WL[1 + d] / rL; uR[d] = WR[1 + d] / rR; }
+  double HL = (WL[1 + nd] + pL) / rL, HR = (WR[1 + nd] + pR) / rR;
+  double sL = sqrt(rL), sR = sqrt(rR), w = sL + sR;
+  double u[3] = {0, 0, 0}, uu = 0.0, q = 0.0, qL = 0.0, qR = 0.0;
+  for (int d = 0; d < nd; d++) {
+    u[d] = (sL * uL[d] + sR * uR[d]) / w;
+    uu += u[d] * u[d];
+    q += u[d] * n[d];
+    qL += uL[d] * n[d];
+    qR += uR[d] * n[d];
+  }
+  double H = (sL * HL + sR * HR) / w;
+  double a = sqrt((gamma - 1.0) * (H - 0.5 * uu));
+  double rho = sL * sR;
+  double dr = rR - rL, dp = pR - pL, dq = qR - qL;
+  double a1 = (dp - rho * a * dq) / (2.0 * a * a);
+  double a5 = (dp + rho * a * dq) / (2.0 * a * a);
+  double a2 = dr - dp / (a * a);
+  double l1 = fabs(q - a), l2 = fabs(q), l5 = fabs(q + a);
+  double delta = fix * a;
+  if (delta > 0.0) {
+    if (l1 < delta) l1 = (l1 * l1 + delta * delta) / (2.0 * delta);
+    if (l5 < delta) l5 = (l5 * l5 + delta * delta) / (2.0 * delta);
+  }
+  double Dis[2 + 3 + OM_MAXSP];
+  /* acoustic waves */
+  Dis[0] = l1 * a1 + l2 * a2 + l5 * a5;
+  for (int d = 0; d < nd; d++)
+    Dis[1 + d] = l1 * a1 * (u[d] - a * n[d]) + l2 * a2 * u[d] + l5 * a5 * (u[d] + a * n[d]);
+  Dis[1 + nd] = l1 * a1 * (H - q * a) + l2 * a2 * 0.5 * uu + l5 * a5 * (H + q * a);
+  /* shear waves: jump of the tangential velocity */
+  double dut[3] = {0, 0, 0}, udut = 0.0;
+  for (int d = 0; d < nd; d++) {
+    dut[d] = (uR[d] - uL[d]) - dq * n[d];
+    udut += u[d] * dut[d];
+  }
+  for (int d = 0; d < nd; d++) Dis[1 + d] += l2 * rho * dut[d];
+  Dis[1 + nd] += l2 * rho * udut;
+  /* species: carried by the acoustic and entropy waves plus their own contact */
+  for (int k = 0; k < nsp; k++) {
+    double YL = WL[2 + nd + k] / rL, YR = WR[2 + nd + k] / rR;
+    double Y = (sL * YL + sR * YR) / w;
+    Dis[2 + nd + k] = (l1 * a1 + l2 * a2 + l5 * a5) * Y + l2 * rho * (YR - YL);
+  }
+  double FL[2 + 3 + OM_MAXSP], FR[2 + 3 + OM_MAXSP];
+  om_euler_flux(nd, nsp, WL, n, FL);
+  om_euler_flux(nd, nsp, WR, n, FR);
+  for (int v = 0; v < nvar; v++) F[v] = A * (0.5 * (FL[v] + FR[v]) - 0.5 * Dis[v]);
+}
+
+/* ------------------------------------------------------------------ */
+/* residuals                                                            */
+/* ------------------------------------------------------------------ */
+
+static double pressure_of(int nd, const double *U, int64_t nn, int64_t i, double gamma) {
+  double rho = U[i], ke = 0.0;
+  for (int d = 0; d < nd; d++) {
+    double m = U[(int64_t)(1 + d) * nn + i];
+    ke += m * m;
+  }
+  return (gamma - 1.0) * (U[(int64_t)(1 + nd) * nn + i] - 0.5 * ke / rho);
+}
+
+static int residual_gas(const om_mesh *m, const om_phys *ph, const double *U, double *r) {
+  int nd = m->nd, nv = m->nv, nsp = ph->nspecies;
+  int nvar = 2 + nd + nsp, nr = nvar + 1;
+  int64_t nn = m->nn;
+  /* reconstructed variables: conserved state plus pressure */
+  double *W = malloc(sizeof(double) * nr * nn);
+  double *G = malloc(sizeof(double) * nr * nd * nn);
+  if (!W || !G) { free(W); free(G); return -3; }
+  memcpy(W, U, sizeof(double) * nvar * nn);
+  for (int64_t i = 0; i < nn; i++) W[(int64_t)nvar * nn + i] = pressure_of(nd, U, nn, i, ph->gamma);
+  om_gradient(m, nr, W, G);
+  memset(r, 0, sizeof(double) * nvar * nn);
+  for (int64_t c = 0; c < m->nc; c++) {
+    const double *X = m->X + c * nv * nd;
+    for (int e = 0; e < m->ne; e++) {
+      const int *ab = edge_of(nv, e);
+      int64_t i = m->cell[c * nv + ab[0]], j = m->cell[c * nv + ab[1]];
+      double Sij[3], dx[3];
+      edge_normal(m, c, ab[0], ab[1], Sij);
+      for (int d = 0; d < nd; d++) dx[d] = X[ab[1] * nd + d] - X[ab[0] * nd + d];
+      double WL[2 + 3 + OM_MAXSP + 1], WR[2 + 3 + OM_MAXSP + 1];
+      for (int v = 0; v < nr; v++) {
+        double wi = W[(int64_t)v * nn + i], wj = W[(int64_t)v * nn + j];
+        double gi = 0.0, gj = 0.0;
+        for (int d = 0; d < nd; d++) {
+          gi += G[((int64_t)v * nd + d) * nn + i] * dx[d];
+          gj += G[((int64_t)v * nd + d) * nn + j] * dx[d];
+        }
+        double delta = wj - wi;
+        /* virtual upwind nodes: U_i - U_l = 2 grad U_i . ij - (U_j - U_i),
+         * U_k - U_j = 2 grad U_j . ij - (U_j - U_i) */
+        double d_li = 2.0 * gi - delta, d_jk = 2.0 * gj - delta;
+        double bar_i = om_slope_limiter(ph->limiter, ph->beta, d_li, delta);
+        double bar_j = om_slope_limiter(ph->limiter, ph->beta, delta, d_jk);
+        WL[v] = wi + 0.5 * bar_i;
+        WR[v] = wj - 0.5 * bar_j;
+      }
+      double F[2 + 3 + OM_MAXSP];
+      if (ph->flux == 0)
+        om_hllc(nd, nsp, ph->gamma, ph->gamma, WL, WR, Sij, F);
+      else
+        om_roe(nd, nsp, ph->gamma, ph->entropy_fix, WL, WR, Sij, F);
+      for (int v = 0; v < nvar; v++) {
+        r[(int64_t)v * nn + i] += F[v];
+        r[(int64_t)v * nn + j] -= F[v];
+      }
+    }
+  }
+  if (ph->closure) {
+    /* boundary closure, first option: the flux through the boundary part of
+     * the dual surface is the node flux F(U_i) . S_i^b */
+    double Wi[2 + 3 + OM_MAXSP + 1], F[2 + 3 + OM_MAXSP];
+    for (int64_t i = 0; i < nn; i++) {
+      if (!m->bnd[i]) continue;
+      for (int v = 0; v < nr; v++) Wi[v] = W[(int64_t)v * nn + i];
+      om_euler_flux(nd, nsp, Wi, m->Sb + i * nd, F);
+      for (int v = 0; v < nvar; v++) r[(int64_t)v * nn + i] += F[v];
+    }
+  }
+  free(W);
+  free(G);
+  return 0;
+}
+
+/* Limited Lax-Wendroff convective flux plus central diffusive flux for every
+ * charged species, per cell-edge (Sec. "Limited Lax-Wendroff scheme"). */
+static int residual_dd(const om_mesh *m, const om_phys *ph, const double *U, const double *E,
+                       double dt, double *r) {
+  int nd = m->nd, nv = m->nv, ns = ph->nspecies;
+  int64_t nn = m->nn;
+  double *G = malloc(sizeof(double) * ns * nd * nn);
+  if (!G) return -3;
+  om_gradient(m, ns, U, G);
+  memset(r, 0, sizeof(double) * ns * nn);
+  for (int64_t c = 0; c < m->nc; c++) {
+    const double *X = m->X + c * nv * nd;
+    for (int e = 0; e < m->ne; e++) {
+      const int *ab = edge_of(nv, e);
+      int64_t i = m->cell[c * nv + ab[0]], j = m->cell[c * nv + ab[1]];
+      double Sij[3], dx[3];
+      edge_normal(m, c, ab[0], ab[1], Sij);
+      for (int d = 0; d < nd; d++) dx[d] = X[ab[1] * nd + d] - X[ab[0] * nd + d];
+      for (int s = 0; s < ns; s++) {
+        const double *u = U + (int64_t)s * nn;
+        const double *g = G + (int64_t)s * nd * nn;
+        double zm = ph->z[s] * ph->mu[s];
+        double Vij[3], v = 0.0, gV = 0.0, gS = 0.0;
+        for (int d = 0; d < nd; d++) {
+          Vij[d] = 0.5 * (zm * E[(int64_t)d * nn + i] + zm * E[(int64_t)d * nn + j]);
+          v += Vij[d] * Sij[d];
+        }
+        for (int d = 0; d < nd; d++) {
+          double gbar = 0.5 * (g[(int64_t)d * nn + i] + g[(int64_t)d * nn + j]);
+          gV += gbar * Vij[d];
+          gS += gbar * Sij[d];
+        }
+        /* upwind node w and downwind node m of the edge, virtual node k
+         * upwind of w: u_w - u_k = grad u_w . (2 w->m) - (u_m - u_w) */
+        int64_t w = v >= 0.0 ? i : j, mm = v >= 0.0 ? j : i;
+        double sdir = v >= 0.0 ? 1.0 : -1.0;
+        double b = u[mm] - u[w];
+        double gw = 0.0;
+        for (int d = 0; d < nd; d++) gw += g[(int64_t)d * nn + w] * sdir * dx[d];
+        double a = 2.0 * gw - b;
+        double psi = om_psi_limiter(ph->limiter, ph->beta, a, b);
+        double uf = u[w] + (0.5 * b - 0.5 * dt * gV) * psi;
+        double F = uf * v - ph->D[s] * gS;
+        r[(int64_t)s * nn + i] += F;
+        r[(int64_t)s * nn + j] -= F;
+      }
+    }
+  }
+  if (ph->closure) {
+    /* supersonic-type boundary: F = F_C + F_D with node values */
+    for (int64_t i = 0; i < nn; i++) {
+      if (!m->bnd[i]) continue;
+      for (int s = 0; s < ns; s++) {
+        double zm = ph->z[s] * ph->mu[s], vb = 0.0, gb = 0.0;
+        for (int d = 0; d < nd; d++) {
+          vb += zm * E[(int64_t)d * nn + i] * m->Sb[i * nd + d];
+          gb += G[((int64_t)s * nd + d) * nn + i] * m->Sb[i * nd + d];
+        }
+        r[(int64_t)s * nn + i] += U[(int64_t)s * nn + i] * vb - ph->D[s] * gb;
+      }
+    }
+  }
+  free(G);
+  return 0;
+}
+
+int om_residual(const om_mesh *m, const om_phys *ph, const double *U, const double *E,
+                double dt, double *r) {
+  if (!m || !ph || !U || !r) return -1;
+  if (ph->nspecies < 0 || ph->nspecies > OM_MAXSP) return -1;
+  if (ph->model == 0) return residual_gas(m, ph, U, r);
+  if (ph->model == 1) {
+    if (!E || ph->nspecies < 1) return -1;
+    return residual_dd(m, ph, U, E, dt, r);
+  }
+  return -1;
+}
+
+/* ------------------------------------------------------------------ */
+/* time step                                                            */
+/* ------------------------------------------------------------------ */
+
+/* cell size: inscribed-sphere diameter 2 n_d V_tau / sum_k |S_k| */
+static double cell_size(const om_mesh *m, int64_t c) {
+  double sum = 0.0;
+  for (int k = 0; k < m->nv; k++) {
+    double s2 = 0.0;
+    for (int d = 0; d < m->nd; d++) {
+      double s = m->S[(c * m->nv + k) * m->nd + d];
+      s2 += s * s;
+    }
+    sum += sqrt(s2);
+  }
+  return 2.0 * m->nd * m->Vc[c] / sum;
+}
+
+int om_timestep(const om_mesh *m, const om_phys *ph, const double *U, const double *E,
+                double *dt_out) {
+  int nd = m->nd, nv = m->nv;
+  int64_t nn = m->nn;
+  double dt = INFINITY;
+  for (int64_t c = 0; c < m->nc; c++) {
+    double dx = cell_size(m, c);
+    if (ph->model == 0) {
+      double lam = 0.0;
+      for (int k = 0; k < nv; k++) {
+        int64_t i = m->cell[c * nv + k];
+        double rho = U[i], uu = 0.0;
+        for (int d = 0; d < nd; d++) {
+          double ud = U[(int64_t)(1 + d) * nn + i] / rho;
+          uu += ud * ud;
+        }
+        double p = pressure_of(nd, U, nn, i, ph->gamma);
+        double l = sqrt(uu) + sqrt(ph->gamma * p / rho);
+        if (l > lam) lam = l;
+      }
+      double t = ph->cfl * dx / lam;
+      if (t < dt) dt = t;
+    } else {
+      for (int s = 0; s < ph->nspecies; s++) {
+        double vmax = 0.0;
+        for (int k = 0; k < nv; k++) {
+          int64_t i = m->cell[c * nv + k];
+          double v2 = 0.0;
+          for (int d = 0; d < nd; d++) {
+            double vd = ph->z[s] * ph->mu[s] * E[(int64_t)d * nn + i];
+            v2 += vd * vd;
+          }
+          if (sqrt(v2) > vmax) vmax = sqrt(v2);
+        }
+        if (vmax > 0.0) {
+          double t = ph->cfl * dx / vmax;
+          if (t < dt) dt = t;
+        }
+        if (ph->D[s] > 0.0) {
+          double t = ph->fourier * dx * dx / ph->D[s];
+          if (t < dt) dt = t;
+        }
+      }
+    }
+  }
+  *dt_out = dt;
+  if (!(dt > 0.0) || !isfinite(dt)) return -5;
+  return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Runge-Kutta                                                          */
+/* ------------------------------------------------------------------ */
+
+/* alpha_2..alpha_4 of the low-storage table, beta_K = 1 */
+static const double RK_ALPHA[5][5] = {
+    {0, 0, 0, 0, 0},
+    {0, 0, 0, 0, 0},
+    {0, 0, 1.0 / 2.0, 0, 0},
+    {0, 0, 1.0 / 3.0, 1.0 / 2.0, 0},
+    {0, 0, 1.0 / 4.0, 1.0 / 3.0, 1.0 / 2.0},
+};
+
+static int state_ok(const om_mesh *m, const om_phys *ph, const double *U) {
+  int nvar = om_nvar(m->nd, ph);
+  int64_t nn = m->nn;
+  for (int64_t q = 0; q < (int64_t)nvar * nn; q++)
+    if (!isfinite(U[q])) return 0;
+  if (ph->model == 0)
+    for (int64_t i = 0; i < nn; i++) {
+      if (!(U[i] > 0.0)) return 0;
+      if (!(pressure_of(m->nd, U, nn, i, ph->gamma) > 0.0)) return 0;
+    }
+  return 1;
+}
+
+int om_step(const om_mesh *m, const om_phys *ph, double *U, const double *E, int nsteps,
+            double t_end, double *t, double *dt_last, int *steps_done) {
+  if (ph->rk < 1 || ph->rk > 4) return -1;
+  int nvar = om_nvar(m->nd, ph);
+  int64_t nn = m->nn, tot = (int64_t)nvar * nn;
+  double *U0 = malloc(sizeof(double) * tot), *Uk = malloc(sizeof(double) * tot);
+  double *r = malloc(sizeof(double) * tot);
+  if (!U0 || !Uk || !r) { free(U0); free(Uk); free(r); return -3; }
+  int st = 0, done = 0;
+  for (int n = 0; n < nsteps; n++) {
+    if (t_end > 0.0 && *t >= t_end) break;
+    double dt;
+    st = om_timestep(m, ph, U, E, &dt);
+    if (st) break;
+    if (t_end > 0.0 && *t + dt > t_end) dt = t_end - *t;
+    memcpy(U0, U, sizeof(double) * tot);
+    memcpy(Uk, U, sizeof(double) * tot);
+    for (int k = 2; k <= ph->rk + 1; k++) {
+      /* k <= K: intermediate stage U(k) = U^n - alpha_k dt r(U(k-1))/V;
+       * k == K+1: final update U^{n+1} = U^n - dt r(U(K))/V */
+      double a = k <= ph->rk ? RK_ALPHA[ph->rk][k] : 1.0;
+      st = om_residual(m, ph, Uk, E, dt, r);
+      if (st) break;
+      for (int v = 0; v < nvar; v++)
+        for (int64_t i = 0; i < nn; i++)
+          Uk[(int64_t)v * nn + i] = U0[(int64_t)v * nn + i] - a * dt * r[(int64_t)v * nn + i] / m->Vn[i];
+    }
+    if (st) break;
+    if (!state_ok(m, ph, Uk)) { st = -5; break; }
+    memcpy(U, Uk, sizeof(double) * tot);
+    *t += dt;
+    *dt_last = dt;
+    done++;
+  }
+  if (steps_done) *steps_done = done;
+  free(U0); free(Uk); free(r);
+  return st;
+}
+
+/* ------------------------------------------------------------------ */
+/* conservation diagnostic                                              */
+/* ------------------------------------------------------------------ */
+
+/* sum_i V_i U_i per variable with Neumaier-compensated summation, and the
+ * normalisation sum_i V_i |U_i| */
+void om_sums(const om_mesh *m, int nvar, const double *U, double *sums, double *abssums) {
+  for (int v = 0; v < nvar; v++) {
+    double s = 0.0, comp = 0.0, a = 0.0, acomp = 0.0;
+    for (int64_t i = 0; i < m->nn; i++) {
+      double x = m->Vn[i] * U[(int64_t)v * m->nn + i];
+      double t = s + x;
+      if (fabs(s) >= fabs(x)) comp += (s - t) + x; else comp += (x - t) + s;
+      s = t;
+      double ax = fabs(x), ta = a + ax;
+      if (a >= ax) acomp += (a - ta) + ax; else acomp += (ax - ta) + a;
+      a = ta;
+    }
+    sums[v] = s + comp;
+    if (abssums) abssums[v] = a + acomp;
+  }
+}

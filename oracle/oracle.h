@@ -1,0 +1,74 @@
+/*
+ * oracle.h -- plain FP64 CPU oracle for the vertex-centred explicit residual
+ * of "AVIP: a low temperature plasma code" (arXiv 2201.01291).
+ *
+ * TEST INFRASTRUCTURE.  Only the test-suite, the smoke check and the CPU
+ * baseline of the benchmark may load this library.  It shares no code,
+ * header, table or helper with the HIP library; it is a slow, literal,
+ * sequential transcription of the scheme used to check the GPU results.
+ *
+ * Array conventions (all caller-owned, host memory):
+ *   xyz    [nd][nn]      node coordinates
+ *   cells  [nv][nc]      simplex connectivity (int64), nv = nd + 1
+ *   period [nd] or NULL  box length of each periodic axis, 0 for an open axis
+ *   U      [nvar][nn]    nodal conserved state
+ *   E      [nd][nn]      prescribed electric field (drift-diffusion)
+ *   G      [nvar][nd][nn] nodal gradients
+ *   r      [nvar][nn]    residual = integrated net outflow, dU_i/dt = -r_i/V_i
+ *
+ * Status codes: 0 ok, -1 bad argument, -2 bad mesh, -3 out of memory,
+ * -5 unstable (non-finite state, rho<=0 or p<=0).
+ */
+#ifndef VCX_ORACLE_H
+#define VCX_ORACLE_H
+#include <stdint.h>
+
+#define OM_MAXSP 16
+
+typedef struct {
+  int32_t model;      /* 0 gas (Euler + passive species), 1 drift-diffusion */
+  int32_t flux;       /* gas: 0 HLLC, 1 Roe */
+  int32_t limiter;    /* 0 first order, 1 minmod, 2 van Leer, 3 Sweby(beta), 4 unlimited */
+  int32_t rk;         /* 1..4, low-storage table */
+  int32_t nspecies;   /* gas: passive species; drift-diffusion: charged species */
+  int32_t closure;    /* 1: add node-flux boundary closure on boundary nodes */
+  double beta;        /* Sweby parameter */
+  double cfl, fourier;
+  double gamma;
+  double entropy_fix; /* Roe: Harten delta as a fraction of the Roe sound speed */
+  double z[OM_MAXSP], mu[OM_MAXSP], D[OM_MAXSP];  /* drift-diffusion species */
+} om_phys;
+
+typedef struct om_mesh om_mesh;
+
+om_mesh *om_mesh_create(int nd, int64_t nn, const double *xyz, int64_t nc, int nv,
+                        const int64_t *cells, const double *period, int *status);
+void om_mesh_destroy(om_mesh *m);
+void om_mesh_counts(const om_mesh *m, int64_t *out /* nn, nc, nbnd_faces, nbnd_nodes */);
+
+/* geometry export: S [nc][nv][nd], Vc [nc], Vn [nn], Sb [nd][nn] */
+void om_geometry(const om_mesh *m, double *S, double *Vc, double *Vn, double *Sb);
+/* per cell-edge dual normals S_ij [nc][ne][nd] and endpoints [nc][ne][2] */
+void om_edge_normals(const om_mesh *m, double *Sij, int64_t *ends);
+
+void om_gradient(const om_mesh *m, int nvar, const double *W, double *G);
+
+/* point-wise building blocks */
+double om_slope_limiter(int kind, double beta, double a, double b);
+double om_psi_limiter(int kind, double beta, double a, double b);
+void om_euler_flux(int nd, int nsp, const double *W, const double *S, double *F);
+void om_hllc(int nd, int nsp, double gL, double gR, const double *WL, const double *WR,
+             const double *S, double *F);
+void om_roe(int nd, int nsp, double gamma, double fix, const double *WL, const double *WR,
+            const double *S, double *F);
+
+int om_residual(const om_mesh *m, const om_phys *ph, const double *U, const double *E,
+                double dt, double *r);
+int om_timestep(const om_mesh *m, const om_phys *ph, const double *U, const double *E,
+                double *dt);
+int om_step(const om_mesh *m, const om_phys *ph, double *U, const double *E, int nsteps,
+            double t_end, double *t, double *dt_last, int *steps_done);
+void om_sums(const om_mesh *m, int nvar, const double *U, double *sums, double *abssums);
+int om_nvar(int nd, const om_phys *ph);
+
+#endif

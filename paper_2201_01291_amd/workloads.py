@@ -1,0 +1,354 @@
+"""Seeded synthetic meshes and initial states.
+
+This module produces inputs only: node coordinates, simplex connectivity and
+initial nodal states.  It contains none of the finite-volume arithmetic (no
+normals, volumes, gradients, fluxes or time steps), so both the HIP library
+and the CPU oracle can be fed from it without sharing any of the method.
+
+Conventions shared by every generator
+-------------------------------------
+* coordinates ``xyz``: float64 array ``[ndim][nnodes]``;
+* connectivity ``cells``: int64 array ``[nv][ncells]`` (``nv`` = 3 triangles,
+  4 tetrahedra), vertices listed counter-clockwise / positively oriented on
+  the unjittered lattice;
+* ``period``: float64 ``[ndim]`` for a fully periodic box, else ``None``.
+  Periodic meshes store each node once; cells that straddle the seam refer to
+  the wrapped node indices.
+* every random draw comes from ``numpy.random.default_rng(seed)`` (PCG64).
+
+The workload recipes (domain sizes, jitter, blob counts) are the synthetic
+stand-ins for the paper's test problems: the shock tube (Sec. "One-dimensional
+shock tube"), drift-diffusion streamer meshes (Sec. "Bagheri benchmark") and
+3D/multi-species transport, which the paper runs but does not benchmark.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class Mesh:
+    xyz: np.ndarray          # [ndim][nnodes] float64
+    cells: np.ndarray        # [nv][ncells] int64
+    period: np.ndarray | None
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def ndim(self) -> int:
+        return int(self.xyz.shape[0])
+
+    @property
+    def nnodes(self) -> int:
+        return int(self.xyz.shape[1])
+
+    @property
+    def nv(self) -> int:
+        return int(self.cells.shape[0])
+
+    @property
+    def ncells(self) -> int:
+        return int(self.cells.shape[1])
+
+    @property
+    def nfaces(self) -> int:
+        """Cell-edges: 3 per triangle, 6 per tetrahedron."""
+        return self.ncells * (3 if self.nv == 3 else 6)
+
+
+# ---------------------------------------------------------------------------
+# meshes
+# ---------------------------------------------------------------------------
+
+def tri_rect_mesh(nx: int, ny: int, lx: float = 1.0, ly: float = 1.0, *,
+                  jitter: float = 0.0, seed: int = 0, periodic=False,
+                  origin=(0.0, 0.0)) -> Mesh:
+    """``nx`` x ``ny`` quads on ``[0,lx]x[0,ly]``, each split in two triangles
+    along its (0,0)->(1,1) diagonal.
+
+    ``periodic`` is a bool (both axes) or a pair of bools (per axis); the
+    returned ``period`` holds the box length for periodic axes and 0 for open
+    ones.  ``jitter`` moves each node by U(-jitter*h, jitter*h) per axis
+    (h = spacing of that axis); nodes on an open boundary do not move
+    normal to it, so the boundary stays straight.
+    """
+    if nx < 1 or ny < 1:
+        raise ValueError("need at least one quad per direction")
+    perx, pery = (periodic, periodic) if isinstance(periodic, bool) else tuple(periodic)
+    if (perx and nx < 3) or (pery and ny < 3):
+        raise ValueError("periodic axes need >= 3 quads")
+    hx, hy = lx / nx, ly / ny
+    px = nx if perx else nx + 1
+    py = ny if pery else ny + 1
+    I, J = np.meshgrid(np.arange(px), np.arange(py), indexing="ij")
+    x = origin[0] + I.astype(np.float64) * hx
+    y = origin[1] + J.astype(np.float64) * hy
+    if jitter > 0.0:
+        rng = np.random.default_rng(seed)
+        dx = rng.uniform(-jitter * hx, jitter * hx, size=x.shape)
+        dy = rng.uniform(-jitter * hy, jitter * hy, size=y.shape)
+        if not perx:
+            dx = np.where((I > 0) & (I < nx), dx, 0.0)
+        if not pery:
+            dy = np.where((J > 0) & (J < ny), dy, 0.0)
+        x = x + dx
+        y = y + dy
+        if perx:
+            x = origin[0] + np.mod(x - origin[0], lx)
+        if pery:
+            y = origin[1] + np.mod(y - origin[1], ly)
+
+    def nid(i, j):
+        return (i % px) * py + (j % py)
+
+    qi, qj = np.meshgrid(np.arange(nx), np.arange(ny), indexing="ij")
+    qi, qj = qi.ravel(), qj.ravel()
+    n00, n10 = nid(qi, qj), nid(qi + 1, qj)
+    n01, n11 = nid(qi, qj + 1), nid(qi + 1, qj + 1)
+    ta = np.stack([n00, n10, n11])
+    tb = np.stack([n00, n11, n01])
+    cells = np.empty((3, 2 * qi.size), dtype=np.int64)
+    cells[:, 0::2] = ta
+    cells[:, 1::2] = tb
+    xyz = np.stack([x.ravel(), y.ravel()]).astype(np.float64)
+    period = np.array([lx if perx else 0.0, ly if pery else 0.0]) if (perx or pery) else None
+    return Mesh(xyz, cells, period, name=f"tri{nx}x{ny}",
+                meta=dict(nx=nx, ny=ny, lx=lx, ly=ly, jitter=jitter, seed=seed))
+
+
+_KUHN_PERMS = ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0))
+
+
+def kuhn_tet_mesh(nx: int, ny: int, nz: int, lx: float = 1.0, ly: float = 1.0,
+                  lz: float = 1.0, *, jitter: float = 0.0, seed: int = 0,
+                  periodic: bool = True) -> Mesh:
+    """Cube lattice, each cube split into the 6 Kuhn tetrahedra
+    (corner 000 -> +e_a -> +e_a+e_b -> corner 111 for every axis order a,b,c).
+    The split is conforming across cubes and across the periodic seam."""
+    if min(nx, ny, nz) < 1:
+        raise ValueError("need at least one cube per direction")
+    if periodic and min(nx, ny, nz) < 3:
+        raise ValueError("periodic meshes need >= 3 cubes per direction")
+    n = (nx, ny, nz)
+    h = (lx / nx, ly / ny, lz / nz)
+    L = (lx, ly, lz)
+    p = tuple(k if periodic else k + 1 for k in n)
+    I, J, K = np.meshgrid(np.arange(p[0]), np.arange(p[1]), np.arange(p[2]), indexing="ij")
+    coords = [I.astype(np.float64) * h[0], J.astype(np.float64) * h[1], K.astype(np.float64) * h[2]]
+    if jitter > 0.0:
+        rng = np.random.default_rng(seed)
+        deltas = [rng.uniform(-jitter * h[a], jitter * h[a], size=I.shape) for a in range(3)]
+        if not periodic:
+            interior = ((I > 0) & (I < nx) & (J > 0) & (J < ny) & (K > 0) & (K < nz))
+            deltas = [np.where(interior, d, 0.0) for d in deltas]
+        coords = [c + d for c, d in zip(coords, deltas)]
+        if periodic:
+            coords = [np.mod(c, L[a]) for a, c in enumerate(coords)]
+
+    def nid(i, j, k):
+        if periodic:
+            return ((i % p[0]) * p[1] + (j % p[1])) * p[2] + (k % p[2])
+        return (i * p[1] + j) * p[2] + k
+
+    ci, cj, ck = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    base = np.stack([ci.ravel(), cj.ravel(), ck.ravel()])
+    tets = []
+    for perm in _KUHN_PERMS:
+        verts = [base.copy()]
+        cur = base.copy()
+        for a in perm:
+            cur = cur.copy()
+            cur[a] += 1
+            verts.append(cur)
+        tets.append(np.stack([nid(*v) for v in verts]))
+    # interleave the 6 tets of each cube so a cube's tets are consecutive
+    cells = np.stack(tets, axis=2).reshape(4, -1).astype(np.int64)
+    xyz = np.stack([c.ravel() for c in coords]).astype(np.float64)
+    period = np.array(L, dtype=np.float64) if periodic else None
+    return Mesh(xyz, cells, period, name=f"kuhn{nx}x{ny}x{nz}",
+                meta=dict(nx=nx, ny=ny, nz=nz, L=L, jitter=jitter, seed=seed))
+
+
+def fix_orientation_free(mesh: Mesh) -> Mesh:
+    """Return the mesh with the vertex order of every odd cell reversed.
+
+    Used by tests to check that consumers do not rely on a particular vertex
+    orientation.  (Pure relabelling, no geometry.)"""
+    cells = mesh.cells.copy()
+    odd = np.arange(mesh.ncells) % 2 == 1
+    cells[[1, 2]] = np.where(odd, cells[[2, 1]], cells[[1, 2]])
+    return Mesh(mesh.xyz, cells, mesh.period, mesh.name + "-flip", dict(mesh.meta))
+
+
+def shuffled(mesh: Mesh, seed: int = 0):
+    """Randomly renumber nodes and cells; returns (mesh, node_perm) where
+    ``node_perm[new] = old``."""
+    rng = np.random.default_rng(seed)
+    nperm = rng.permutation(mesh.nnodes)
+    inv = np.empty_like(nperm)
+    inv[nperm] = np.arange(mesh.nnodes)
+    cperm = rng.permutation(mesh.ncells)
+    cells = inv[mesh.cells[:, cperm]]
+    return Mesh(mesh.xyz[:, nperm].copy(), cells, mesh.period, mesh.name + "-shuf",
+                dict(mesh.meta)), nperm
+
+
+# ---------------------------------------------------------------------------
+# states
+# ---------------------------------------------------------------------------
+
+def _min_image(d: np.ndarray, L: float | None) -> np.ndarray:
+    if L is None:
+        return d
+    return d - L * np.round(d / L)
+
+
+def conserved_from_primitive(rho, vel, p, gamma, Y=None):
+    """Conserved gas state [rho, rho*u_1..rho*u_nd, rho*E, rho*Y_1..] from
+    primitives, ideal gas with constant gamma (input preparation only)."""
+    vel = np.atleast_2d(vel)
+    ke = 0.5 * rho * np.sum(vel * vel, axis=0)
+    rows = [rho] + [rho * v for v in vel] + [p / (gamma - 1.0) + ke]
+    if Y is not None:
+        rows += [rho * y for y in np.atleast_2d(Y)]
+    return np.stack(rows).astype(np.float64)
+
+
+def sod_state(mesh: Mesh, gamma: float = 1.4, x0: float = 0.5,
+              left=(1.0, 0.0, 1.0), right=(0.125, 0.0, 0.1)) -> np.ndarray:
+    """Shock-tube initial data (rho, u, p) split at x = x0, zero transverse velocity."""
+    x = mesh.xyz[0]
+    L = x < x0
+    rho = np.where(L, left[0], right[0])
+    u = np.where(L, left[1], right[1])
+    p = np.where(L, left[2], right[2])
+    vel = np.zeros((mesh.ndim, mesh.nnodes))
+    vel[0] = u
+    return conserved_from_primitive(rho, vel, p, gamma)
+
+
+def euler_blob_state(mesh: Mesh, *, nblobs: int = 8, amp: float = 0.1, sigma: float = 0.08,
+                     mach: float = 0.3, gamma: float = 1.4, seed: int = 1,
+                     nspecies: int = 0) -> np.ndarray:
+    """Uniform flow at the given Mach number along x (rho0 = 1, p0 = 1/gamma so
+    the sound speed is 1) with ``nblobs`` seeded Gaussian bumps multiplying
+    rho and p by (1 + amp*exp(-|x-c|^2/sigma^2)); periodic minimum image.
+    Optional passive species get seeded smooth mass fractions summing to 1."""
+    rng = np.random.default_rng(seed)
+    nd = mesh.ndim
+    lengths = mesh.period if mesh.period is not None else (mesh.xyz.max(1) - mesh.xyz.min(1))
+    lo = mesh.xyz.min(1)
+    centres = lo[:, None] + rng.uniform(0.0, 1.0, size=(nd, nblobs)) * np.asarray(lengths)[:, None]
+    bump = np.zeros(mesh.nnodes)
+    for b in range(nblobs):
+        r2 = np.zeros(mesh.nnodes)
+        for a in range(nd):
+            L = None if mesh.period is None else float(mesh.period[a])
+            d = _min_image(mesh.xyz[a] - centres[a, b], L)
+            r2 += d * d
+        bump += amp * np.exp(-r2 / (sigma * sigma))
+    rho = 1.0 * (1.0 + bump)
+    p = (1.0 / gamma) * (1.0 + bump)
+    vel = np.zeros((nd, mesh.nnodes))
+    vel[0] = mach
+    Y = None
+    if nspecies > 0:
+        w = rng.uniform(0.5, 1.5, size=(nspecies, nblobs))
+        raw = np.ones((nspecies, mesh.nnodes))
+        for b in range(nblobs):
+            r2 = np.zeros(mesh.nnodes)
+            for a in range(nd):
+                L = None if mesh.period is None else float(mesh.period[a])
+                d = _min_image(mesh.xyz[a] - centres[a, b], L)
+                r2 += d * d
+            raw += w[:, b:b + 1] * np.exp(-r2 / (4 * sigma * sigma))[None, :]
+        Y = raw / raw.sum(0, keepdims=True)
+    return conserved_from_primitive(rho, vel, p, gamma, Y)
+
+
+@dataclass
+class DDSpecies:
+    z: float      # charge sign (-1 electrons, +1 positive ions)
+    mu: float     # mobility [m^2/(V s)]
+    D: float      # diffusion coefficient [m^2/s]
+
+
+def dd_fields(mesh: Mesh, *, seed: int = 2, peak: float = 1e18, sigma: float = 5e-4,
+              nblobs: int = 4, e0: float = 1e6, bump_amp: float = 700.0,
+              bump_sigma: float = 2e-3, nspecies: int = 2):
+    """Drift-diffusion inputs: densities [nspecies][nnodes] made of ``nblobs``
+    seeded Gaussians (same for every species) and the electric field
+    E = -grad(phi) [ndim][nnodes] of phi = -e0*x + A*exp(-|x-xb|^2/sb^2)
+    (periodic image sum), evaluated analytically at the nodes."""
+    rng = np.random.default_rng(seed)
+    nd = mesh.ndim
+    lengths = mesh.period if mesh.period is not None else (mesh.xyz.max(1) - mesh.xyz.min(1))
+    lo = mesh.xyz.min(1)
+    centres = lo[:, None] + rng.uniform(0.0, 1.0, size=(nd, nblobs)) * np.asarray(lengths)[:, None]
+    xb = lo + rng.uniform(0.0, 1.0, size=nd) * np.asarray(lengths)
+    dens = np.zeros(mesh.nnodes)
+    for b in range(nblobs):
+        r2 = np.zeros(mesh.nnodes)
+        for a in range(nd):
+            L = None if mesh.period is None else float(mesh.period[a])
+            d = _min_image(mesh.xyz[a] - centres[a, b], L)
+            r2 += d * d
+        dens += peak * np.exp(-r2 / (sigma * sigma))
+    n = np.stack([dens.copy() for _ in range(nspecies)])
+    E = np.zeros((nd, mesh.nnodes))
+    E[0] = e0
+    shifts = [(-1, 0, 1) if mesh.period is not None else (0,)] * nd
+    for img in np.array(np.meshgrid(*shifts, indexing="ij")).reshape(nd, -1).T:
+        d = np.stack([mesh.xyz[a] - xb[a] - (img[a] * lengths[a] if mesh.period is not None else 0.0)
+                      for a in range(nd)])
+        g = bump_amp * np.exp(-np.sum(d * d, axis=0) / (bump_sigma ** 2))
+        # E = -grad(phi_bump) = A*exp(..)*2*d/sb^2
+        E += g[None, :] * 2.0 * d / (bump_sigma ** 2)
+    return n.astype(np.float64), E.astype(np.float64)
+
+
+DD_STREAMER_SPECIES = (DDSpecies(z=-1.0, mu=0.04, D=0.1), DDSpecies(z=+1.0, mu=0.04, D=0.1))
+
+
+# ---------------------------------------------------------------------------
+# named workloads
+# ---------------------------------------------------------------------------
+
+def sod_tube(nx: int = 100, ny: int = 10) -> Mesh:
+    """Shock tube: [0,1]x[0,0.1] with nx x ny quads split in two triangles,
+    periodic across the tube (y) and open at both ends (x)."""
+    return tri_rect_mesh(nx, ny, 1.0, 0.1, periodic=(False, True))
+
+
+def dd_streamer_mesh(nx: int = 400, ny: int = 250, jitter: float = 0.2, seed: int = 7) -> Mesh:
+    """Periodic [0,0.02]x[0,0.0125] m box (h = 50 um at 400x250), jittered
+    triangles: 2*nx*ny cells, nx*ny nodes."""
+    return tri_rect_mesh(nx, ny, 0.02 * nx / 400, 0.0125 * ny / 250, jitter=jitter,
+                         seed=seed, periodic=True)
+
+
+def euler3d_mesh(nx: int = 70, ny: int = 70, nz: int = 68, jitter: float = 0.1,
+                 seed: int = 11) -> Mesh:
+    """Periodic unit cube (for the default sizes), Kuhn-split, jittered."""
+    return kuhn_tet_mesh(nx, ny, nz, 1.0 * nx / 70, 1.0 * ny / 70, 1.0 * nz / 68,
+                         jitter=jitter, seed=seed, periodic=True)
+
+
+def serving_requests(n: int = 256, *, seed: int = 5, cell_min: float = 5e3,
+                     cell_max: float = 2e6, rate: float = 1.0):
+    """Request stream: log-uniform cell counts, Poisson arrival times at
+    ``rate`` requests per unit time; even ids gas, odd ids drift-diffusion."""
+    rng = np.random.default_rng(seed)
+    cells = np.exp(rng.uniform(math.log(cell_min), math.log(cell_max), size=n))
+    gaps = rng.exponential(1.0 / rate, size=n)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    out = []
+    for k in range(n):
+        # square-ish periodic tri mesh with ~cells[k] triangles
+        side = max(3, int(round(math.sqrt(cells[k] / 2.0))))
+        out.append(dict(id=k, kind="gas" if k % 2 == 0 else "dd", nx=side, ny=side,
+                        arrival=float(arrivals[k]), seed=int(rng.integers(1 << 30))))
+    return out
