@@ -1,0 +1,227 @@
+"""Benchmark of the vertex-centred explicit residual on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload dd2d]
+
+Workload (default): 2D drift-diffusion of electrons and one positive ion on
+a periodic jittered triangular mesh of 200,000 cells (100,000 nodes, 600,000
+cell-edges), Gaussian densities peaking at 1e18 m^-3, mobility 0.04 m^2/Vs,
+D = 0.1 m^2/s, E from an analytic potential (uniform 1e6 V/m plus a seeded
+Gaussian bump), limited Lax-Wendroff (minmod) + central diffusion, RK1, FP64.
+
+One step = CFL time step + nodal gradients + cell-edge fluxes with the
+deterministic gather + update, all on the GPU.  Metric: Mfaces/s = cell-edge
+fluxes per residual evaluation x residual evaluations per second / 1e6.
+
+Prints ONE JSON line.  Extra fields: algorithmic GB/s of the whole step,
+p50/p99 single-step latency of the FP64 path and of the mixed path (FP32
+fluxes, FP64 accumulation), the mixed path's drift from FP64 after the timed
+run, the roofline of the dominant kernel (HIP-event timing of every launch of
+a second, profiled pass over the same number of steps) and the FP64 CPU oracle
+timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="dd2d", choices=["dd2d", "euler3d"])
+    ap.add_argument("--latency-steps", type=int, default=200)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="skip the profiled pass")
+    return ap.parse_args()
+
+
+def workload(name):
+    from paper_2201_01291_amd import vcx, workloads as wl
+    if name == "dd2d":
+        m = wl.dd_streamer_mesh()
+        n, E = wl.dd_fields(m)
+        sp = wl.DD_STREAMER_SPECIES
+
+        def phys(prec):
+            return vcx.physics(model=vcx.MODEL_DRIFT_DIFFUSION, limiter=vcx.LIM_MINMOD, rk_stages=1,
+                               nspecies=2, precision=prec, beta=1.0, cfl=0.5, fourier=0.25,
+                               z=[s.z for s in sp], mu=[s.mu for s in sp], D=[s.D for s in sp])
+
+        def ophys():
+            import oracle
+            return oracle.Phys(model=oracle.DRIFT_DIFFUSION, limiter=oracle.MINMOD, rk=1,
+                               nspecies=2, cfl=0.5, fourier=0.25, z=[s.z for s in sp],
+                               mu=[s.mu for s in sp], D=[s.D for s in sp])
+
+        cfg = dict(workload="dd2d-streamer: periodic 400x250 jittered (20%) triangles, "
+                            "2 charged species, LLW-minmod + central diffusion, RK1",
+                   cells=m.ncells, nodes=m.nnodes, faces=m.nfaces, species=2,
+                   residuals_per_step=1)
+        # algorithmic bytes, every array once
+        N, M = m.nnodes, m.ncells
+        ns, nd = 2, 2
+        bytes_flux = N * 8 * (ns + ns * nd + nd + nd + ns) + M * 3 * 4
+        bytes_step = (N * 8 * (ns + nd) + M * 3 * 4 + N * 8 * ns * nd      # gradient
+                      + bytes_flux                                      # flux
+                      + N * 8 * (ns + ns + 1 + ns)                      # update
+                      + N * 8 * nd + M * 3 * 4)                         # time step
+        return m, n, E, phys, ophys, cfg, dict(flux=bytes_flux, step=bytes_step)
+    if name == "euler3d":
+        m = wl.euler3d_mesh()
+        U = wl.euler_blob_state(m)
+
+        def phys(prec):
+            return vcx.physics(model=vcx.MODEL_GAS, flux=vcx.FLUX_ROE, limiter=vcx.LIM_VANLEER,
+                               rk_stages=2, precision=prec, cfl=0.5)
+
+        def ophys():
+            import oracle
+            return oracle.Phys(model=oracle.GAS, flux=oracle.ROE, limiter=oracle.VANLEER, rk=2, cfl=0.5)
+
+        cfg = dict(workload="euler3d: periodic Kuhn 70x70x68 jittered (10%) tets, Roe + van Leer, RK2",
+                   cells=m.ncells, nodes=m.nnodes, faces=m.nfaces, residuals_per_step=2)
+        N, M = m.nnodes, m.ncells
+        nr, nd, nv = 6, 3, 5
+        bytes_flux = N * 8 * (nr + nr * nd + nd + nv) + M * 4 * 4
+        bytes_step = 2 * (N * 8 * (nr + nd) + M * 16 + N * 8 * nr * nd + bytes_flux
+                          + N * 8 * (nv + nr + 1 + nr)) + N * 8 * (nr + nd) + M * 16
+        return m, U, None, phys, ophys, cfg, dict(flux=bytes_flux, step=bytes_step)
+    raise ValueError(name)
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not "
+                                   "supported (see DESIGN.md, 'Sharding')", "n_gpus": a.gpus}))
+        sys.exit(2)
+    import torch
+    from paper_2201_01291_amd import vcx
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    print(f"[bench] building workload {a.workload}", file=sys.stderr, flush=True)
+    m, U0, E, phys, ophys, cfg, alg = workload(a.workload)
+    stream = torch.cuda.current_stream()
+    gm = vcx.Mesh(m, stream=stream.cuda_stream)
+    info = gm.info()
+    s64 = vcx.Solver(gm, phys(vcx.PREC_FP64), E)
+    s32 = vcx.Solver(gm, phys(vcx.PREC_MIXED), E)
+
+    # ---- throughput, FP64 (the metric)
+    s64.upload(U0)
+    s64.step(a.warmup)
+    s64.upload(U0)
+    torch.cuda.synchronize()
+    print(f"[bench] timing {a.steps} FP64 steps", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    s64.step(a.steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    faces_per_step = m.nfaces * cfg["residuals_per_step"]
+    mfaces = faces_per_step * a.steps / el / 1e6
+    U64 = s64.download()
+
+    # ---- mixed path over the same steps: throughput and drift from FP64
+    s32.upload(U0)
+    s32.step(a.warmup)
+    s32.upload(U0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s32.step(a.steps)
+    torch.cuda.synchronize()
+    el32 = time.perf_counter() - t0
+    U32 = s32.download()
+    drift = (np.abs(U32 - U64).max(axis=1) / np.abs(U64).max(axis=1)).tolist()
+
+    # ---- single-step latency (host call to result, synchronised), p50/p99
+    lat = {}
+    for name, s in (("fp64", s64), ("mixed", s32)):
+        s.upload(U0)
+        s.step(5)
+        ts = []
+        for _ in range(a.latency_steps):
+            t1 = time.perf_counter()
+            s.step(1)
+            ts.append((time.perf_counter() - t1) * 1e3)
+        lat[name] = dict(p50_ms=float(np.percentile(ts, 50)), p99_ms=float(np.percentile(ts, 99)))
+
+    # ---- profiled pass: per-kernel HIP-event durations on the solver stream
+    kern = {}
+    if not a.no_profile:
+        s64.upload(U0)
+        s64.profile(True)
+        s64.step(a.steps)
+        for k in ("dt", "gradient", "gradient_gather", "flux", "update"):
+            n, ms = s64.profile_query(k)
+            if n:
+                kern[k] = dict(launches=n, avg_us=ms / n * 1e3)
+        s64.profile(False)
+    dom = max(kern, key=lambda k: kern[k]["avg_us"]) if kern else None
+    roof = None
+    if "flux" in kern:
+        fl = kern["flux"]
+        achieved = alg["flux"] / (fl["avg_us"] * 1e-6) / 1e9
+        roof = dict(kernel="flux", bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
+                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                    alg_bytes_per_launch=alg["flux"], avg_us=round(fl["avg_us"], 2),
+                    dominant_kernel=dom)
+
+    # ---- CPU oracle on a bounded sample of the same workload
+    cpu = None
+    if not a.no_cpu:
+        import oracle
+        om = oracle.OracleMesh(m)
+        ph = ophys()
+        t1 = time.perf_counter()
+        om.step(ph, U0, E, nsteps=1)
+        one = time.perf_counter() - t1
+        nsteps = max(1, int(a.cpu_seconds / max(one, 1e-6)))
+        t1 = time.perf_counter()
+        om.step(ph, U0, E, nsteps=nsteps)
+        elc = time.perf_counter() - t1
+        cpu = dict(value=round(faces_per_step * nsteps / elc / 1e6, 3), unit="Mfaces/s", cores=1,
+                   kind="oracle", sample=f"{nsteps} full steps of the same mesh and state "
+                                         f"({elc:.1f} s, sequential FP64 C oracle)")
+
+    out = {
+        "metric": "Mfaces/s residual throughput",
+        "value": round(mfaces, 2),
+        "unit": "Mfaces/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(el / a.steps * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": cfg,
+        "hbm_gbs_algorithmic_step": round(alg["step"] * a.steps / el / 1e9, 1),
+        "mixed": dict(value=round(faces_per_step * a.steps / el32 / 1e6, 2), unit="Mfaces/s",
+                      ms_per_step=round(el32 / a.steps * 1e3, 5),
+                      drift_vs_fp64_after_steps=drift),
+        "latency": lat,
+        "kernels": kern,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "mesh": info,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,211 @@
+/*
+ * vcx.h -- C ABI of the MI355X (gfx950) vertex-centred explicit residual.
+ *
+ * The library evaluates, on one GPU, the explicit finite-volume residual of
+ * "AVIP: a low temperature plasma code" (arXiv 2201.01291) on unstructured
+ * triangle and tetrahedron meshes, and advances it with the paper's
+ * low-storage Runge-Kutta schemes:
+ *
+ *   residual   r_i = sum over the cells tau around node i, over the cell-edges
+ *              (i,j) of tau, of the flux through the dual-surface piece S_ij
+ *              (eq. vertex_centered_flux), plus the node-flux closure on
+ *              boundary nodes (Sec. "Boundary conditions in AVIP");
+ *   gas        MUSCL reconstruction with virtual upwind nodes
+ *              (eq. virtual_node_reconstruction) of the conserved variables and
+ *              pressure, slope limiters, HLLC (Sec. "The HLLC solver") or Roe
+ *              flux, passive species carried in the mass fractions;
+ *   drift-diff limited Lax-Wendroff convective flux plus central diffusive flux
+ *              (Secs. "Limited Lax-Wendroff scheme", "Central difference
+ *              diffusive flux integration"), prescribed electric field;
+ *   time step  cell-based convective / diffusive limits, minimum over cells
+ *              and species (Sec. "Time step computation");
+ *   update     U(k) = U^n - alpha_k dt r(U(k-1)) / V_i, U^{n+1} = U^n -
+ *              dt r(U(K)) / V_i with the alphas of table rk_coeffs.
+ *
+ * Conventions
+ *   - Every function returns a vcx_status and never throws.  On error the
+ *     message of the last failing call of the calling thread is returned by
+ *     vcx_last_error().
+ *   - Host arrays are owned by the caller and copied during the call.  Device
+ *     arrays passed with is_device = 1 must be device memory of the device the
+ *     handle lives on; they are read or written on the handle's stream.
+ *   - Node order at the boundary is always the caller's order; the internal
+ *     space-filling-curve renumbering is hidden.
+ *   - Layout: structure of arrays, [variable][node] (row-major, node fastest).
+ *   - Residual sign: r_i is the integrated net outflow, dU_i/dt = -r_i / V_i,
+ *     so on a periodic mesh sum_i r_i = 0.
+ *   - Streams: all device work of a handle is ordered on the hipStream_t
+ *     given at creation (NULL = default stream).  Calls that return host
+ *     values synchronise that stream.
+ *   - A handle may be used by one thread at a time.
+ */
+#ifndef VCX_H
+#define VCX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  VCX_OK = 0,
+  VCX_E_ARG = -1,      /* invalid argument or unsupported combination */
+  VCX_E_MESH = -2,     /* invalid mesh: index out of range, degenerate cell,
+                          non-manifold face, periodic cell wider than half the box */
+  VCX_E_OOM = -3,      /* device or host allocation failed */
+  VCX_E_HIP = -4,      /* HIP runtime error (no device, launch failure, ...) */
+  VCX_E_UNSTABLE = -5, /* state became non-finite or non-physical (rho<=0 or
+                          p<=0); the state is left at the last good step */
+  VCX_E_BUSY = -6,     /* resource budget exhausted (server) */
+  VCX_E_STATE = -7     /* call out of order (e.g. step before state_upload) */
+} vcx_status;
+
+enum { VCX_MODEL_GAS = 0, VCX_MODEL_DRIFT_DIFFUSION = 1 };
+enum { VCX_FLUX_HLLC = 0, VCX_FLUX_ROE = 1 };
+enum {
+  VCX_LIM_FIRST_ORDER = 0, /* zero slope / Psi = 0 (first-order upwind) */
+  VCX_LIM_MINMOD = 1,
+  VCX_LIM_VANLEER = 2,
+  VCX_LIM_SWEBY = 3,       /* Sweby beta limiter, 1 <= beta <= 2 */
+  VCX_LIM_NONE = 4         /* unlimited: centred slope / Psi = 1 (plain Lax-Wendroff) */
+};
+enum {
+  VCX_PREC_FP64 = 0,  /* everything in FP64 */
+  VCX_PREC_MIXED = 1  /* reconstruction, limiters and fluxes in FP32; gradients,
+                         residual accumulation, update, time step and sums in FP64 */
+};
+
+#define VCX_MAX_SPECIES 16
+
+/* Physical model and scheme parameters. */
+typedef struct {
+  int32_t model;      /* VCX_MODEL_* */
+  int32_t flux;       /* gas: VCX_FLUX_*; ignored for drift-diffusion */
+  int32_t limiter;    /* VCX_LIM_* */
+  int32_t rk_stages;  /* 1..4 (table rk_coeffs) */
+  int32_t nspecies;   /* gas: passive species (0, 2 or 9 supported);
+                         drift-diffusion: charged species (1..4) */
+  int32_t closure;    /* 1: node-flux closure on boundary nodes */
+  int32_t precision;  /* VCX_PREC_* */
+  int32_t reserved;
+  double beta;        /* Sweby beta */
+  double cfl;         /* convective CFL number */
+  double fourier;     /* diffusive Fourier number */
+  double gamma;       /* ratio of specific heats (gas) */
+  double entropy_fix; /* Roe: Harten delta as a fraction of the Roe sound speed */
+  double z[VCX_MAX_SPECIES];   /* drift-diffusion charge sign per species */
+  double mu[VCX_MAX_SPECIES];  /* mobility [m^2/(V s)] */
+  double D[VCX_MAX_SPECIES];   /* diffusion coefficient [m^2/s] */
+} vcx_physics;
+
+typedef struct vcx_mesh_s *vcx_mesh;
+typedef struct vcx_solver_s *vcx_solver;
+
+/* Build a device mesh (Sec. "Nomenclature and notations").
+ *   ndim      2 (triangles) or 3 (tetrahedra); nv must be ndim + 1
+ *   xyz       host [ndim][nnodes] coordinates
+ *   cells     host [nv][ncells] node indices (any vertex orientation)
+ *   period    host [ndim] box length of each periodic axis, 0 for an open
+ *             axis, or NULL (no periodicity)
+ *   stream    hipStream_t for the uploads and for every later use
+ * Computes node normals, median-dual volumes V_i = sum V_tau / n_v, boundary
+ * node normals, a space-filling-curve node/cell order and the fixed cell
+ * tiles used by the deterministic scatter.  Errors: VCX_E_ARG, VCX_E_MESH,
+ * VCX_E_OOM, VCX_E_HIP. */
+vcx_status vcx_mesh_create(int ndim, int64_t nnodes, const double *xyz, int64_t ncells, int nv,
+                           const int64_t *cells, const double *period, void *stream,
+                           vcx_mesh *out);
+/* As vcx_mesh_create with explicit tile limits: at most max_tile_cells cells
+ * (<= 1024) and max_tile_nodes distinct nodes per tile; 0 selects the
+ * defaults (2D 256 / 192, 3D 128 / 96).  Smaller tiles lower the LDS
+ * footprint of the tile kernels (needed by models with many variables),
+ * larger tiles lower the partial-sum traffic. */
+vcx_status vcx_mesh_create_tiled(int ndim, int64_t nnodes, const double *xyz, int64_t ncells,
+                                 int nv, const int64_t *cells, const double *period,
+                                 int max_tile_cells, int max_tile_nodes, void *stream,
+                                 vcx_mesh *out);
+vcx_status vcx_mesh_destroy(vcx_mesh mesh);
+
+/* Mesh counters: out[0] nnodes, [1] ncells, [2] cell-edges (faces),
+ * [3] tiles, [4] partial slots, [5] boundary nodes, [6] max cells per tile,
+ * [7] max nodes per tile. */
+vcx_status vcx_mesh_info(vcx_mesh mesh, int64_t out[8]);
+
+/* Median-dual nodal volumes [nnodes] and boundary node normals
+ * [ndim][nnodes] (zero on interior nodes), caller's node order, host. */
+vcx_status vcx_mesh_geometry(vcx_mesh mesh, double *Vn, double *Sb);
+
+/* Host-only dry run of the preprocessing of vcx_mesh_create (no device
+ * needed): same validation, same tiles.  stats as in vcx_mesh_info, plus
+ * stats[8] = total volume of the cells, stats[9] = sum of nodal volumes
+ * (bit patterns of doubles, via memcpy). */
+vcx_status vcx_mesh_preprocess(int ndim, int64_t nnodes, const double *xyz, int64_t ncells,
+                               int nv, const int64_t *cells, const double *period,
+                               int64_t stats[10]);
+
+/* Create a solver (state buffers, scheme parameters) on a mesh.
+ *   E   drift-diffusion only: host [ndim][nnodes] electric field at the
+ *       nodes (caller order), copied; NULL for gas.
+ * Unsupported species counts, or tiles whose LDS footprint exceeds the
+ * device's per-workgroup limit, give VCX_E_ARG. */
+vcx_status vcx_solver_create(vcx_mesh mesh, const vcx_physics *phys, const double *E,
+                             vcx_solver *out);
+vcx_status vcx_solver_destroy(vcx_solver s);
+
+/* Number of conserved variables (gas 2 + ndim + nspecies; DD nspecies). */
+int vcx_solver_nvar(vcx_solver s);
+
+/* State [nvar][nnodes] in the caller's node order; is_device selects a host
+ * or device pointer.  Upload resets the time to 0 (or to t0 with
+ * vcx_state_set_time). */
+vcx_status vcx_state_upload(vcx_solver s, const double *U, int is_device);
+vcx_status vcx_state_download(vcx_solver s, double *U, int is_device);
+vcx_status vcx_state_set_time(vcx_solver s, double t);
+
+/* Nodal gradients of the reconstructed variables of the current state,
+ * [nr][ndim][nnodes] (gas nr = nvar + 1 with pressure last; DD nr = nvar),
+ * caller order (Sec. "Integrating the Poisson equation", cell gradient, then
+ * the volume-weighted average over the cells around the node). */
+vcx_status vcx_gradient(vcx_solver s, double *G, int is_device);
+
+/* Residual of the current state, FP64 [nvar][nnodes], caller order.  dt is
+ * only used by the limited Lax-Wendroff flux. */
+vcx_status vcx_residual(vcx_solver s, double dt, double *r, int is_device);
+
+/* CFL / Fourier time step of the current state (minimum over cells and
+ * species). */
+vcx_status vcx_timestep(vcx_solver s, double *dt);
+
+/* Advance nsteps steps (time step recomputed every step; the last step is
+ * clipped to t_end when t_end > 0, and no step starts once t >= t_end).
+ * Returns the time reached and the last time step.  VCX_E_UNSTABLE leaves
+ * the state at the last good step. */
+vcx_status vcx_step(vcx_solver s, int nsteps, double t_end, double *t, double *dt_last);
+
+/* Steps completed by the last vcx_step / vcx_solve_batch call on s. */
+int64_t vcx_steps_done(vcx_solver s);
+
+/* Advance several independent solvers (each with its own mesh) together:
+ * per step one launch per kernel covers every solver's tiles and nodes.
+ * Solvers must share precision and model family.  nsteps[i], t_end[i] per
+ * solver. */
+vcx_status vcx_solve_batch(vcx_solver *s, int n, const int *nsteps, const double *t_end);
+
+/* sum_i V_i U_i per variable [nvar] (FP64, fixed-order tree). */
+vcx_status vcx_conservation_sums(vcx_solver s, double *sums);
+
+/* Per-kernel timing with HIP events on the solver's stream.  enable = 1 turns
+ * it on and clears the counters.  Kernel names: "dt", "gradient",
+ * "gradient_gather", "flux", "update".  count = launches timed, total_ms = sum
+ * of their durations. */
+vcx_status vcx_profile_enable(vcx_solver s, int enable);
+vcx_status vcx_profile_query(vcx_solver s, const char *kernel, int64_t *count, double *total_ms);
+
+const char *vcx_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

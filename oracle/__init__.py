@@ -103,6 +103,7 @@ def lib():
         L.om_roe.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, dp, dp, dp, dp]
         pp = C.POINTER(_Phys)
         L.om_residual.argtypes = [C.c_void_p, pp, dp, dp, C.c_double, dp]
+        L.om_flux_scale.argtypes = [C.c_void_p, pp, dp, dp, C.c_double, dp]
         L.om_timestep.argtypes = [C.c_void_p, pp, dp, dp, dp]
         L.om_step.argtypes = [C.c_void_p, pp, dp, dp, C.c_int, C.c_double, dp, dp,
                               C.POINTER(C.c_int)]
@@ -185,6 +186,18 @@ class OracleMesh:
                                float(dt), _d(r))
         if st:
             raise OracleError(st, "residual")
+        return r
+
+    def flux_scale(self, phys: Phys, U, E=None, dt: float = 0.0):
+        """Per node and variable, the sum of |F.S| over its cell-edges."""
+        U = _c64(U)
+        r = np.zeros_like(U)
+        Ec = None if E is None else _c64(E)
+        p = phys.to_c()
+        st = lib().om_flux_scale(self._h, C.byref(p), _d(U), _d(Ec) if Ec is not None else None,
+                                 float(dt), _d(r))
+        if st:
+            raise OracleError(st, "flux_scale")
         return r
 
     def timestep(self, phys: Phys, U, E=None) -> float:

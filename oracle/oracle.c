@@ -467,7 +467,7 @@ static double pressure_of(int nd, const double *U, int64_t nn, int64_t i, double
   return (gamma - 1.0) * (U[(int64_t)(1 + nd) * nn + i] - 0.5 * ke / rho);
 }
 
-static int residual_gas(const om_mesh *m, const om_phys *ph, const double *U, double *r) {
+static int residual_gas(const om_mesh *m, const om_phys *ph, const double *U, double *r, int absmode) {
   int nd = m->nd, nv = m->nv, nsp = ph->nspecies;
   int nvar = 2 + nd + nsp, nr = nvar + 1;
   int64_t nn = m->nn;
@@ -510,8 +510,8 @@ static int residual_gas(const om_mesh *m, const om_phys *ph, const double *U, do
       else
         om_roe(nd, nsp, ph->gamma, ph->entropy_fix, WL, WR, Sij, F);
       for (int v = 0; v < nvar; v++) {
-        r[(int64_t)v * nn + i] += F[v];
-        r[(int64_t)v * nn + j] -= F[v];
+        r[(int64_t)v * nn + i] += absmode ? fabs(F[v]) : F[v];
+        r[(int64_t)v * nn + j] -= absmode ? -fabs(F[v]) : F[v];
       }
     }
   }
@@ -523,7 +523,7 @@ static int residual_gas(const om_mesh *m, const om_phys *ph, const double *U, do
       if (!m->bnd[i]) continue;
       for (int v = 0; v < nr; v++) Wi[v] = W[(int64_t)v * nn + i];
       om_euler_flux(nd, nsp, Wi, m->Sb + i * nd, F);
-      for (int v = 0; v < nvar; v++) r[(int64_t)v * nn + i] += F[v];
+      for (int v = 0; v < nvar; v++) r[(int64_t)v * nn + i] += absmode ? fabs(F[v]) : F[v];
     }
   }
   free(W);
@@ -534,7 +534,7 @@ static int residual_gas(const om_mesh *m, const om_phys *ph, const double *U, do
 /* Limited Lax-Wendroff convective flux plus central diffusive flux for every
  * charged species, per cell-edge (Sec. "Limited Lax-Wendroff scheme"). */
 static int residual_dd(const om_mesh *m, const om_phys *ph, const double *U, const double *E,
-                       double dt, double *r) {
+                       double dt, double *r, int absmode) {
   int nd = m->nd, nv = m->nv, ns = ph->nspecies;
   int64_t nn = m->nn;
   double *G = malloc(sizeof(double) * ns * nd * nn);
@@ -574,8 +574,8 @@ static int residual_dd(const om_mesh *m, const om_phys *ph, const double *U, con
         double psi = om_psi_limiter(ph->limiter, ph->beta, a, b);
         double uf = u[w] + (0.5 * b - 0.5 * dt * gV) * psi;
         double F = uf * v - ph->D[s] * gS;
-        r[(int64_t)s * nn + i] += F;
-        r[(int64_t)s * nn + j] -= F;
+        r[(int64_t)s * nn + i] += absmode ? fabs(F) : F;
+        r[(int64_t)s * nn + j] -= absmode ? -fabs(F) : F;
       }
     }
   }
@@ -589,7 +589,8 @@ static int residual_dd(const om_mesh *m, const om_phys *ph, const double *U, con
           vb += zm * E[(int64_t)d * nn + i] * m->Sb[i * nd + d];
           gb += G[((int64_t)s * nd + d) * nn + i] * m->Sb[i * nd + d];
         }
-        r[(int64_t)s * nn + i] += U[(int64_t)s * nn + i] * vb - ph->D[s] * gb;
+        double F = U[(int64_t)s * nn + i] * vb - ph->D[s] * gb;
+        r[(int64_t)s * nn + i] += absmode ? fabs(F) : F;
       }
     }
   }
@@ -597,16 +598,29 @@ static int residual_dd(const om_mesh *m, const om_phys *ph, const double *U, con
   return 0;
 }
 
-int om_residual(const om_mesh *m, const om_phys *ph, const double *U, const double *E,
-                double dt, double *r) {
+static int residual_any(const om_mesh *m, const om_phys *ph, const double *U, const double *E,
+                        double dt, double *r, int absmode) {
   if (!m || !ph || !U || !r) return -1;
   if (ph->nspecies < 0 || ph->nspecies > OM_MAXSP) return -1;
-  if (ph->model == 0) return residual_gas(m, ph, U, r);
+  if (ph->model == 0) return residual_gas(m, ph, U, r, absmode);
   if (ph->model == 1) {
     if (!E || ph->nspecies < 1) return -1;
-    return residual_dd(m, ph, U, E, dt, r);
+    return residual_dd(m, ph, U, E, dt, r, absmode);
   }
   return -1;
+}
+
+int om_residual(const om_mesh *m, const om_phys *ph, const double *U, const double *E,
+                double dt, double *r) {
+  return residual_any(m, ph, U, E, dt, r, 0);
+}
+
+/* Flux magnitude per node: sum over the node's cell-edges (and closure) of
+ * |F . S|, per variable -- the scale against which residual differences are
+ * measured (a residual is a difference of such fluxes). */
+int om_flux_scale(const om_mesh *m, const om_phys *ph, const double *U, const double *E,
+                  double dt, double *out) {
+  return residual_any(m, ph, U, E, dt, out, 1);
 }
 
 /* ------------------------------------------------------------------ */
@@ -644,6 +658,7 @@ int om_timestep(const om_mesh *m, const om_phys *ph, const double *U, const doub
           uu += ud * ud;
         }
         double p = pressure_of(nd, U, nn, i, ph->gamma);
+        if (!(rho > 0.0) || !(p > 0.0)) return -5; /* non-physical state: no time step */
         double l = sqrt(uu) + sqrt(ph->gamma * p / rho);
         if (l > lam) lam = l;
       }

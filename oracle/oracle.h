@@ -64,6 +64,8 @@ void om_roe(int nd, int nsp, double gamma, double fix, const double *WL, const d
 
 int om_residual(const om_mesh *m, const om_phys *ph, const double *U, const double *E,
                 double dt, double *r);
+int om_flux_scale(const om_mesh *m, const om_phys *ph, const double *U, const double *E,
+                  double dt, double *out);
 int om_timestep(const om_mesh *m, const om_phys *ph, const double *U, const double *E,
                 double *dt);
 int om_step(const om_mesh *m, const om_phys *ph, double *U, const double *E, int nsteps,

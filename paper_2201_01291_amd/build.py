@@ -1,0 +1,60 @@
+"""Build ``libvcx.so`` (HIP for gfx950 + host C++) in the package directory.
+
+    python -m paper_2201_01291_amd.build
+
+Compiles every time it is called.  The library is loaded in-tree by the
+ctypes binding (``paper_2201_01291_amd/vcx.py``).
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+import tempfile
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+LIB = os.path.join(PKG, "libvcx.so")
+ARCH = os.environ.get("VCX_OFFLOAD_ARCH", "gfx950")
+
+HIP_FLAGS = [
+    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+    # packed FP32 instructions stay off: plain scalar FP32 only
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wall", "-Wno-unused-function", "-Wno-unused-result",
+]
+
+
+def _run(cmd, verbose):
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+
+
+def build(verbose: bool = False) -> str:
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    with tempfile.TemporaryDirectory(prefix="vcx_build_") as tmp:
+        host_o = os.path.join(tmp, "vcx_mesh.o")
+        dev_o = os.path.join(tmp, "vcx_capi.o")
+        procs = [
+            subprocess.Popen(["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", *inc, "-c",
+                              os.path.join(CSRC, "vcx_mesh.cpp"), "-o", host_o]),
+            subprocess.Popen(["hipcc", *HIP_FLAGS, *inc, "-c",
+                              os.path.join(CSRC, "vcx_capi.hip"), "-o", dev_o]),
+        ]
+        if verbose:
+            print("compiling vcx_mesh.cpp (g++) and vcx_capi.hip (hipcc)", flush=True)
+        rcs = [p.wait() for p in procs]
+        if any(rcs):
+            raise RuntimeError(f"compilation failed (exit codes {rcs})")
+        tmp_lib = LIB + ".tmp"
+        _run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp_lib, host_o, dev_o],
+             verbose)
+        os.replace(tmp_lib, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose="-q" not in sys.argv)
+    print(LIB)

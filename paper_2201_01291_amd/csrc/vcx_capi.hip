@@ -1,0 +1,814 @@
+// C ABI of the vertex-centred residual library (declarations in include/vcx.h).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "vcx.h"
+#include "vcx_kernels.h"
+#include "vcx_mesh.h"
+
+using namespace vcx;
+
+namespace {
+
+thread_local std::string g_err;
+
+vcx_status fail(vcx_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define VCX_HIP(expr)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess) return fail(VCX_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define VCX_TRY(expr)               \
+  do {                              \
+    vcx_status s_ = (expr);         \
+    if (s_ != VCX_OK) return s_;    \
+  } while (0)
+
+constexpr int kNodeBlock = 256;
+
+}  // namespace
+
+struct vcx_mesh_s {
+  HostMesh h;
+  DevMesh d{};
+  std::vector<void*> allocs;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int lds_max = 65536;  // dynamic LDS bytes one workgroup may allocate on this device
+};
+
+struct KernelTable;
+
+struct vcx_solver_s {
+  vcx_mesh mesh = nullptr;
+  vcx_physics ph{};
+  int nd = 0, nvar = 0, nr = 0;
+  double* W[2] = {nullptr, nullptr};
+  int cur = 0;
+  double* G = nullptr;
+  double* PG = nullptr;
+  double* PR = nullptr;
+  double* E = nullptr;
+  double* io = nullptr;    // [max(nr*nd, nvar)][nn] staging in caller order
+  double* rbuf = nullptr;  // [max(nr*nd, nvar)][nn] internal order
+  DevScalars* sc = nullptr;
+  DevScalars* sc_host = nullptr;  // pinned mirror
+  double* part = nullptr;
+  double* sums_dev = nullptr;
+  double* sums_host = nullptr;     // pinned
+  bool has_state = false;
+  int host_flag = 0;
+  long long steps_total = 0;
+  int64_t steps_last = 0;
+  const KernelTable* kt = nullptr;
+  size_t lds_grad = 0, lds_flux = 0;
+  int tile_block = 256;
+  // profiling
+  bool prof = false;
+  std::map<std::string, std::vector<std::pair<hipEvent_t, hipEvent_t>>> ev;
+  std::map<std::string, std::pair<int64_t, double>> acc;
+  std::vector<hipEvent_t> spare;
+};
+
+// ---------------------------------------------------------------------------
+// launch helper with optional event timing
+// ---------------------------------------------------------------------------
+
+static hipEvent_t take_event(vcx_solver s) {
+  if (!s->spare.empty()) {
+    hipEvent_t e = s->spare.back();
+    s->spare.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+template <typename F>
+static vcx_status launch(vcx_solver s, const char* name, F&& f) {
+  hipStream_t st = s->mesh->stream;
+  hipEvent_t a = nullptr, b = nullptr;
+  if (s->prof) {
+    a = take_event(s);
+    b = take_event(s);
+    if (a && b) VCX_HIP(hipEventRecord(a, st));
+  }
+  f();
+  VCX_HIP(hipGetLastError());
+  if (s->prof && a && b) {
+    VCX_HIP(hipEventRecord(b, st));
+    s->ev[name].push_back({a, b});
+  }
+  return VCX_OK;
+}
+
+static vcx_status harvest(vcx_solver s) {
+  if (s->ev.empty()) return VCX_OK;
+  VCX_HIP(hipStreamSynchronize(s->mesh->stream));
+  for (auto& kv : s->ev) {
+    auto& a = s->acc[kv.first];
+    for (auto& pr : kv.second) {
+      float ms = 0.f;
+      VCX_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
+      a.first += 1;
+      a.second += ms;
+      s->spare.push_back(pr.first);
+      s->spare.push_back(pr.second);
+    }
+    kv.second.clear();
+  }
+  return VCX_OK;
+}
+
+// ---------------------------------------------------------------------------
+// kernel table: one instantiation per (model, nd, species, flux, precision)
+// ---------------------------------------------------------------------------
+
+struct KernelTable {
+  vcx_status (*grad)(vcx_solver, const double* Win, const DevScalars* sc);
+  vcx_status (*flux)(vcx_solver, const double* Win, const double* dt_dev, double dt_host,
+                     const DevScalars* sc);
+  vcx_status (*update)(vcx_solver, const UpdateArgs&, Sched, DevScalars* sc);
+  size_t (*lds_grad)(int maxn, int maxc);
+  size_t (*lds_flux)(int maxn, int maxc);
+  vcx_status (*allow_lds)(size_t grad_bytes, size_t flux_bytes);
+};
+
+template <int MODEL, int ND, int NSP, int FLUX, typename CT>
+struct Impl {
+  static constexpr int NVAR = MODEL == 0 ? 2 + ND + NSP : NSP;
+  static constexpr int NR = MODEL == 0 ? NVAR + 1 : NVAR;
+  static constexpr int NV = ND + 1;
+
+  static size_t lds_grad(int maxn, int maxc) {
+    return sizeof(double) * ((size_t)(NR + ND) * maxn + (size_t)NR * ND * maxc);
+  }
+  static size_t lds_flux(int maxn, int maxc) {
+    size_t dbl = sizeof(double) * ((size_t)ND * maxn + (size_t)NV * NVAR * maxc);
+    size_t ct = MODEL == 0 ? (size_t)(NR + NR * ND) * maxn : (size_t)(NSP + NSP * ND + ND) * maxn;
+    return dbl + sizeof(CT) * ct;
+  }
+  static vcx_status grad(vcx_solver s, const double* Win, const DevScalars* sc) {
+    const DevMesh& m = s->mesh->d;
+    hipStream_t st = s->mesh->stream;
+    VCX_TRY(launch(s, "gradient", [&] {
+      hipLaunchKernelGGL((k_grad_tile<ND, NR>), dim3(xcd_grid(m.ntiles)), dim3(s->tile_block),
+                         s->lds_grad, st, m, Win, s->PG, sc);
+    }));
+    VCX_TRY(launch(s, "gradient_gather", [&] {
+      hipLaunchKernelGGL((k_grad_gather<ND, NR>), dim3((m.nn + kNodeBlock - 1) / kNodeBlock),
+                         dim3(kNodeBlock), 0, st, m, (const double*)s->PG, s->G, sc);
+    }));
+    return VCX_OK;
+  }
+  static vcx_status flux(vcx_solver s, const double* Win, const double* dt_dev, double dt_host,
+                         const DevScalars* sc) {
+    const DevMesh& m = s->mesh->d;
+    hipStream_t st = s->mesh->stream;
+    if constexpr (MODEL == 0) {
+      GasParams gp{s->ph.gamma, s->ph.beta, s->ph.entropy_fix, s->ph.limiter};
+      return launch(s, "flux", [&] {
+        hipLaunchKernelGGL((k_flux_gas<ND, NSP, FLUX, CT>), dim3(xcd_grid(m.ntiles)),
+                           dim3(s->tile_block), s->lds_flux, st, m, Win, (const double*)s->G,
+                           s->PR, gp, sc);
+      });
+    } else {
+      DDParams pp{};
+      for (int k = 0; k < NSP; ++k) {
+        pp.zmu[k] = s->ph.z[k] * s->ph.mu[k];
+        pp.D[k] = s->ph.D[k];
+      }
+      pp.beta = s->ph.beta;
+      pp.dt_host = dt_host;
+      pp.dt_dev = dt_dev;
+      pp.limiter = s->ph.limiter;
+      return launch(s, "flux", [&] {
+        hipLaunchKernelGGL((k_flux_dd<ND, NSP, CT>), dim3(xcd_grid(m.ntiles)),
+                           dim3(s->tile_block), s->lds_flux, st, m, Win, (const double*)s->G,
+                           (const double*)s->E, s->PR, pp, sc);
+      });
+    }
+  }
+  static vcx_status update(vcx_solver s, const UpdateArgs& ua, Sched sd, DevScalars* sc) {
+    const DevMesh& m = s->mesh->d;
+    hipStream_t st = s->mesh->stream;
+    return launch(s, "update", [&] {
+      hipLaunchKernelGGL((k_update<ND, NSP, MODEL>), dim3((m.nn + kNodeBlock - 1) / kNodeBlock),
+                         dim3(kNodeBlock), 0, st, m, ua, sd, sc);
+    });
+  }
+  // Allow dynamic LDS above the 64 KiB default for the two tile kernels.
+  static vcx_status allow_lds(size_t grad_bytes, size_t flux_bytes) {
+    VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_grad_tile<ND, NR>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)grad_bytes));
+    if constexpr (MODEL == 0)
+      VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_gas<ND, NSP, FLUX, CT>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)flux_bytes));
+    else
+      VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_dd<ND, NSP, CT>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)flux_bytes));
+    return VCX_OK;
+  }
+  static const KernelTable* table() {
+    static const KernelTable t{&grad, &flux, &update, &lds_grad, &lds_flux, &allow_lds};
+    return &t;
+  }
+};
+
+template <int MODEL, int ND, int NSP>
+static const KernelTable* pick_flux_prec(int flux, int prec) {
+  if (MODEL == 1) return prec == VCX_PREC_MIXED ? Impl<MODEL, ND, NSP, 0, float>::table()
+                                                : Impl<MODEL, ND, NSP, 0, double>::table();
+  if (flux == VCX_FLUX_HLLC)
+    return prec == VCX_PREC_MIXED ? Impl<MODEL, ND, NSP, 0, float>::table()
+                                  : Impl<MODEL, ND, NSP, 0, double>::table();
+  return prec == VCX_PREC_MIXED ? Impl<MODEL, ND, NSP, 1, float>::table()
+                                : Impl<MODEL, ND, NSP, 1, double>::table();
+}
+
+template <int ND>
+static const KernelTable* pick_nd(const vcx_physics& ph) {
+  if (ph.model == VCX_MODEL_GAS) {
+    switch (ph.nspecies) {
+      case 0: return pick_flux_prec<0, ND, 0>(ph.flux, ph.precision);
+      case 2: return pick_flux_prec<0, ND, 2>(ph.flux, ph.precision);
+      case 9: return pick_flux_prec<0, ND, 9>(ph.flux, ph.precision);
+      default: return nullptr;
+    }
+  }
+  switch (ph.nspecies) {
+    case 1: return pick_flux_prec<1, ND, 1>(0, ph.precision);
+    case 2: return pick_flux_prec<1, ND, 2>(0, ph.precision);
+    default: return nullptr;
+  }
+}
+
+static const KernelTable* pick_table(int nd, const vcx_physics& ph) {
+  return nd == 2 ? pick_nd<2>(ph) : pick_nd<3>(ph);
+}
+
+// ---------------------------------------------------------------------------
+// mesh
+// ---------------------------------------------------------------------------
+
+template <typename T>
+static vcx_status upload(vcx_mesh m, const std::vector<T>& v, const T** out) {
+  if (v.empty()) {
+    *out = nullptr;
+    return VCX_OK;
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, sizeof(T) * v.size()) != hipSuccess)
+    return fail(VCX_E_OOM, "hipMalloc failed for mesh arrays");
+  m->allocs.push_back(p);
+  VCX_HIP(hipMemcpyAsync(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, m->stream));
+  *out = static_cast<const T*>(p);
+  return VCX_OK;
+}
+
+static void free_mesh(vcx_mesh m) {
+  if (!m) return;
+  for (void* p : m->allocs) (void)hipFree(p);
+  delete m;
+}
+
+extern "C" vcx_status vcx_mesh_preprocess(int ndim, int64_t nnodes, const double* xyz,
+                                          int64_t ncells, int nv, const int64_t* cells,
+                                          const double* period, int64_t stats[10]) {
+  if (!stats) return fail(VCX_E_ARG, "stats is NULL");
+  HostMesh h;
+  int code = 0;
+  std::string err = preprocess_mesh(ndim, nnodes, xyz, ncells, nv, cells, period,
+                                    default_tile_limits(ndim), h, &code);
+  if (!err.empty()) return fail(code == -2 ? VCX_E_MESH : VCX_E_ARG, err);
+  stats[0] = h.nn;
+  stats[1] = h.nc;
+  stats[2] = h.nc * h.ne;
+  stats[3] = h.ntiles();
+  stats[4] = h.nslots();
+  stats[5] = (int64_t)h.bnd_node.size();
+  stats[6] = h.max_tile_cells;
+  stats[7] = h.max_tile_nodes;
+  std::memcpy(&stats[8], &h.vol_cells, 8);
+  std::memcpy(&stats[9], &h.vol_nodes, 8);
+  return VCX_OK;
+}
+
+extern "C" vcx_status vcx_mesh_create(int ndim, int64_t nnodes, const double* xyz,
+                                      int64_t ncells, int nv, const int64_t* cells,
+                                      const double* period, void* stream, vcx_mesh* out) {
+  return vcx_mesh_create_tiled(ndim, nnodes, xyz, ncells, nv, cells, period, 0, 0, stream, out);
+}
+
+extern "C" vcx_status vcx_mesh_create_tiled(int ndim, int64_t nnodes, const double* xyz,
+                                            int64_t ncells, int nv, const int64_t* cells,
+                                            const double* period, int max_tile_cells,
+                                            int max_tile_nodes, void* stream, vcx_mesh* out) {
+  if (!out) return fail(VCX_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (ndim != 2 && ndim != 3) return fail(VCX_E_ARG, "ndim must be 2 or 3");
+  TileLimits lim = default_tile_limits(ndim);
+  if (max_tile_cells > 0) lim.max_cells = max_tile_cells;
+  if (max_tile_nodes > 0) lim.max_nodes = max_tile_nodes;
+  if (lim.max_cells > 1024) return fail(VCX_E_ARG, "max_tile_cells must be <= 1024");
+  vcx_mesh m = new (std::nothrow) vcx_mesh_s();
+  if (!m) return fail(VCX_E_OOM, "host allocation failed");
+  int code = 0;
+  std::string err = preprocess_mesh(ndim, nnodes, xyz, ncells, nv, cells, period, lim, m->h, &code);
+  if (!err.empty()) {
+    delete m;
+    return fail(code == -2 ? VCX_E_MESH : VCX_E_ARG, err);
+  }
+  m->stream = static_cast<hipStream_t>(stream);
+  if (hipGetDevice(&m->device) != hipSuccess ||
+      hipDeviceGetAttribute(&m->lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, m->device) !=
+          hipSuccess) {
+    delete m;
+    return fail(VCX_E_HIP, "no HIP device");
+  }
+  const HostMesh& h = m->h;
+  DevMesh& d = m->d;
+  d.nd = h.nd;
+  d.nv = h.nv;
+  d.nn = (int)h.nn;
+  d.nc = (int)h.nc;
+  d.ntiles = (int)h.ntiles();
+  d.nslots = (int)h.nslots();
+  d.nb = (int)h.bnd_node.size();
+  d.max_tile_cells = h.max_tile_cells;
+  d.max_tile_nodes = h.max_tile_nodes;
+  for (int k = 0; k < 3; ++k) d.period[k] = h.period[k];
+  std::vector<double> inv(h.nn);
+  for (int64_t i = 0; i < h.nn; ++i) inv[i] = 1.0 / h.vnode[i];
+  std::vector<int32_t> bidx(h.nn, -1);
+  for (size_t q = 0; q < h.bnd_node.size(); ++q) bidx[h.bnd_node[q]] = (int32_t)q;
+  vcx_status st = VCX_OK;
+  auto chk = [&](vcx_status s) {
+    if (st == VCX_OK) st = s;
+  };
+  chk(upload(m, h.x, &d.x));
+  chk(upload(m, h.cell, &d.cell));
+  chk(upload(m, h.shift, &d.shift));
+  chk(upload(m, h.lconn, &d.lconn));
+  chk(upload(m, h.tile_cell, &d.tile_cell));
+  chk(upload(m, h.tile_slot, &d.tile_slot));
+  chk(upload(m, h.slot_node, &d.slot_node));
+  chk(upload(m, h.slot_inc, &d.slot_inc));
+  chk(upload(m, h.inc, &d.inc));
+  chk(upload(m, h.node_slot, &d.node_slot));
+  chk(upload(m, h.slots_of, &d.slots_of));
+  chk(upload(m, inv, &d.inv_vol));
+  chk(upload(m, h.vnode, &d.vnode));
+  chk(upload(m, bidx, &d.bnd_index));
+  chk(upload(m, h.bnd_S, &d.bnd_S));
+  chk(upload(m, h.perm, &d.perm));
+  if (st == VCX_OK && hipStreamSynchronize(m->stream) != hipSuccess)
+    st = fail(VCX_E_HIP, "mesh upload failed");
+  if (st != VCX_OK) {
+    free_mesh(m);
+    return st;
+  }
+  *out = m;
+  return VCX_OK;
+}
+
+extern "C" vcx_status vcx_mesh_destroy(vcx_mesh m) {
+  if (!m) return fail(VCX_E_ARG, "mesh is NULL");
+  (void)hipStreamSynchronize(m->stream);
+  free_mesh(m);
+  return VCX_OK;
+}
+
+extern "C" vcx_status vcx_mesh_info(vcx_mesh m, int64_t out[8]) {
+  if (!m || !out) return fail(VCX_E_ARG, "NULL argument");
+  out[0] = m->h.nn;
+  out[1] = m->h.nc;
+  out[2] = m->h.nc * m->h.ne;
+  out[3] = m->h.ntiles();
+  out[4] = m->h.nslots();
+  out[5] = (int64_t)m->h.bnd_node.size();
+  out[6] = m->h.max_tile_cells;
+  out[7] = m->h.max_tile_nodes;
+  return VCX_OK;
+}
+
+extern "C" vcx_status vcx_mesh_geometry(vcx_mesh m, double* Vn, double* Sb) {
+  if (!m) return fail(VCX_E_ARG, "mesh is NULL");
+  const HostMesh& h = m->h;
+  if (Vn)
+    for (int64_t i = 0; i < h.nn; ++i) Vn[h.perm[i]] = h.vnode[i];
+  if (Sb) {
+    std::memset(Sb, 0, sizeof(double) * h.nd * h.nn);
+    size_t nb = h.bnd_node.size();
+    for (size_t q = 0; q < nb; ++q)
+      for (int d = 0; d < h.nd; ++d) Sb[(size_t)d * h.nn + h.perm[h.bnd_node[q]]] = h.bnd_S[d * nb + q];
+  }
+  return VCX_OK;
+}
+
+// ---------------------------------------------------------------------------
+// solver
+// ---------------------------------------------------------------------------
+
+static void free_solver(vcx_solver s) {
+  if (!s) return;
+  for (double* p : {s->W[0], s->W[1], s->G, s->PG, s->PR, s->E, s->io, s->rbuf, s->part,
+                    s->sums_dev})
+    if (p) (void)hipFree(p);
+  if (s->sc) (void)hipFree(s->sc);
+  if (s->sc_host) (void)hipHostFree(s->sc_host);
+  if (s->sums_host) (void)hipHostFree(s->sums_host);
+  for (auto& kv : s->ev)
+    for (auto& pr : kv.second) {
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
+  for (hipEvent_t e : s->spare) (void)hipEventDestroy(e);
+  delete s;
+}
+
+static vcx_status dmalloc(double** p, size_t n) {
+  if (hipMalloc(reinterpret_cast<void**>(p), sizeof(double) * std::max<size_t>(n, 1)) != hipSuccess)
+    return fail(VCX_E_OOM, "hipMalloc failed for solver buffers");
+  return VCX_OK;
+}
+
+static vcx_status reset_scalars(vcx_solver s, double t0) {
+  DevScalars z{};
+  z.t = t0;
+  z.dtmin = 0x7FF0000000000000ull;
+  *s->sc_host = z;
+  VCX_HIP(hipMemcpyAsync(s->sc, s->sc_host, sizeof(DevScalars), hipMemcpyHostToDevice,
+                         s->mesh->stream));
+  VCX_HIP(hipStreamSynchronize(s->mesh->stream));
+  s->host_flag = 0;
+  s->steps_total = 0;
+  return VCX_OK;
+}
+
+extern "C" vcx_status vcx_solver_create(vcx_mesh mesh, const vcx_physics* phys, const double* E,
+                                        vcx_solver* out) {
+  if (!mesh || !phys || !out) return fail(VCX_E_ARG, "NULL argument");
+  *out = nullptr;
+  const vcx_physics& ph = *phys;
+  const int nd = mesh->h.nd;
+  if (ph.model != VCX_MODEL_GAS && ph.model != VCX_MODEL_DRIFT_DIFFUSION)
+    return fail(VCX_E_ARG, "unknown model");
+  if (ph.rk_stages < 1 || ph.rk_stages > 4) return fail(VCX_E_ARG, "rk_stages must be 1..4");
+  if (ph.limiter < 0 || ph.limiter > 4) return fail(VCX_E_ARG, "unknown limiter");
+  if (ph.precision != VCX_PREC_FP64 && ph.precision != VCX_PREC_MIXED)
+    return fail(VCX_E_ARG, "unknown precision");
+  if (ph.model == VCX_MODEL_GAS && ph.flux != VCX_FLUX_HLLC && ph.flux != VCX_FLUX_ROE)
+    return fail(VCX_E_ARG, "unknown flux");
+  if (!(ph.cfl > 0.0)) return fail(VCX_E_ARG, "cfl must be > 0");
+  if (ph.model == VCX_MODEL_GAS && !(ph.gamma > 1.0)) return fail(VCX_E_ARG, "gamma must be > 1");
+  if (ph.model == VCX_MODEL_DRIFT_DIFFUSION) {
+    if (!E) return fail(VCX_E_ARG, "drift-diffusion needs the electric field E");
+    for (int k = 0; k < ph.nspecies && k < VCX_MAX_SPECIES; ++k)
+      if (ph.D[k] < 0.0) return fail(VCX_E_ARG, "negative diffusion coefficient");
+  }
+  const KernelTable* kt = pick_table(nd, ph);
+  if (!kt) return fail(VCX_E_ARG, "unsupported species count for this model");
+  vcx_solver s = new (std::nothrow) vcx_solver_s();
+  if (!s) return fail(VCX_E_OOM, "host allocation failed");
+  s->mesh = mesh;
+  s->ph = ph;
+  s->nd = nd;
+  s->nvar = ph.model == VCX_MODEL_GAS ? 2 + nd + ph.nspecies : ph.nspecies;
+  s->nr = ph.model == VCX_MODEL_GAS ? s->nvar + 1 : s->nvar;
+  s->kt = kt;
+  const DevMesh& d = mesh->d;
+  s->lds_grad = kt->lds_grad(d.max_tile_nodes, d.max_tile_cells);
+  s->lds_flux = kt->lds_flux(d.max_tile_nodes, d.max_tile_cells);
+  if (s->lds_grad > (size_t)mesh->lds_max || s->lds_flux > (size_t)mesh->lds_max) {
+    const size_t need = std::max(s->lds_grad, s->lds_flux);
+    delete s;
+    return fail(VCX_E_ARG, "tile LDS footprint " + std::to_string(need) + " B exceeds the device limit " +
+                               std::to_string(mesh->lds_max) +
+                               " B for this model; create the mesh with smaller tiles");
+  }
+  if (std::max(s->lds_grad, s->lds_flux) > 65536) {
+    vcx_status st = kt->allow_lds(s->lds_grad, s->lds_flux);
+    if (st != VCX_OK) {
+      delete s;
+      return st;
+    }
+  }
+  s->tile_block = std::min(256, ((d.max_tile_cells + 63) / 64) * 64);
+  const size_t nn = (size_t)d.nn, P = (size_t)d.nslots;
+  const size_t rows_io = std::max<size_t>((size_t)s->nr * nd, s->nvar);
+  vcx_status st = VCX_OK;
+  auto chk = [&](vcx_status x) {
+    if (st == VCX_OK) st = x;
+  };
+  chk(dmalloc(&s->W[0], (size_t)s->nr * nn));
+  chk(dmalloc(&s->W[1], (size_t)s->nr * nn));
+  chk(dmalloc(&s->G, (size_t)s->nr * nd * nn));
+  chk(dmalloc(&s->PG, (size_t)s->nr * nd * P));
+  chk(dmalloc(&s->PR, (size_t)s->nvar * P));
+  chk(dmalloc(&s->io, rows_io * nn));
+  chk(dmalloc(&s->rbuf, rows_io * nn));
+  chk(dmalloc(&s->part, (size_t)s->nr * 256));
+  chk(dmalloc(&s->sums_dev, (size_t)s->nr));
+  if (st == VCX_OK && hipMalloc(reinterpret_cast<void**>(&s->sc), sizeof(DevScalars)) != hipSuccess)
+    st = fail(VCX_E_OOM, "hipMalloc failed");
+  if (st == VCX_OK &&
+      hipHostMalloc(reinterpret_cast<void**>(&s->sc_host), sizeof(DevScalars), 0) != hipSuccess)
+    st = fail(VCX_E_OOM, "hipHostMalloc failed");
+  if (st == VCX_OK &&
+      hipHostMalloc(reinterpret_cast<void**>(&s->sums_host), sizeof(double) * s->nr, 0) != hipSuccess)
+    st = fail(VCX_E_OOM, "hipHostMalloc failed");
+  if (st == VCX_OK && ph.model == VCX_MODEL_DRIFT_DIFFUSION) {
+    chk(dmalloc(&s->E, (size_t)nd * nn));
+    if (st == VCX_OK) {
+      // field in caller order -> internal order
+      if (hipMemcpyAsync(s->io, E, sizeof(double) * nd * nn, hipMemcpyHostToDevice,
+                         mesh->stream) != hipSuccess)
+        st = fail(VCX_E_HIP, "field upload failed");
+      else {
+        hipLaunchKernelGGL(k_gather_rows, dim3((nn + 255) / 256), dim3(256), 0, mesh->stream,
+                           d.perm, (const double*)s->io, s->E, (int)nn, nd);
+        if (hipStreamSynchronize(mesh->stream) != hipSuccess)
+          st = fail(VCX_E_HIP, "field upload failed");
+      }
+    }
+  }
+  if (st == VCX_OK) st = reset_scalars(s, 0.0);
+  if (st != VCX_OK) {
+    free_solver(s);
+    return st;
+  }
+  *out = s;
+  return VCX_OK;
+}
+
+extern "C" vcx_status vcx_solver_destroy(vcx_solver s) {
+  if (!s) return fail(VCX_E_ARG, "solver is NULL");
+  (void)hipStreamSynchronize(s->mesh->stream);
+  free_solver(s);
+  return VCX_OK;
+}
+
+extern "C" int vcx_solver_nvar(vcx_solver s) { return s ? s->nvar : -1; }
+
+static vcx_status copy_in(vcx_solver s, const double* src, size_t rows, int is_device) {
+  const size_t bytes = sizeof(double) * rows * s->mesh->d.nn;
+  VCX_HIP(hipMemcpyAsync(s->io, src, bytes, is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                         s->mesh->stream));
+  return VCX_OK;
+}
+
+// internal-order rows -> caller pointer (host or device), synchronised
+static vcx_status copy_out(vcx_solver s, const double* src_internal, size_t rows, double* dst,
+                           int is_device) {
+  const int nn = s->mesh->d.nn;
+  double* target = is_device ? dst : s->io;
+  hipLaunchKernelGGL(k_scatter_rows, dim3((nn + 255) / 256), dim3(256), 0, s->mesh->stream,
+                     s->mesh->d.perm, src_internal, target, nn, (int)rows);
+  VCX_HIP(hipGetLastError());
+  if (!is_device)
+    VCX_HIP(hipMemcpyAsync(dst, s->io, sizeof(double) * rows * nn, hipMemcpyDeviceToHost,
+                           s->mesh->stream));
+  VCX_HIP(hipStreamSynchronize(s->mesh->stream));
+  return VCX_OK;
+}
+
+extern "C" vcx_status vcx_state_upload(vcx_solver s, const double* U, int is_device) {
+  if (!s || !U) return fail(VCX_E_ARG, "NULL argument");
+  const DevMesh& d = s->mesh->d;
+  VCX_TRY(copy_in(s, U, s->nvar, is_device));
+  hipLaunchKernelGGL(k_gather_rows, dim3((d.nn + 255) / 256), dim3(256), 0, s->mesh->stream,
+                     d.perm, (const double*)s->io, s->W[s->cur], d.nn, s->nvar);
+  VCX_HIP(hipGetLastError());
+  if (s->ph.model == VCX_MODEL_GAS) {
+    hipLaunchKernelGGL(k_pressure, dim3((d.nn + 255) / 256), dim3(256), 0, s->mesh->stream,
+                       s->W[s->cur], d.nn, d.nd, s->ph.nspecies, s->ph.gamma);
+    VCX_HIP(hipGetLastError());
+  }
+  VCX_TRY(reset_scalars(s, 0.0));
+  s->has_state = true;
+  return VCX_OK;
+}
+
+extern "C" vcx_status vcx_state_set_time(vcx_solver s, double t) {
+  if (!s) return fail(VCX_E_ARG, "NULL solver");
+  if (!s->has_state) return fail(VCX_E_STATE, "no state uploaded");
+  return reset_scalars(s, t);
+}
+
+extern "C" vcx_status vcx_state_download(vcx_solver s, double* U, int is_device) {
+  if (!s || !U) return fail(VCX_E_ARG, "NULL argument");
+  if (!s->has_state) return fail(VCX_E_STATE, "no state uploaded");
+  return copy_out(s, s->W[s->cur], s->nvar, U, is_device);
+}
+
+extern "C" vcx_status vcx_gradient(vcx_solver s, double* G, int is_device) {
+  if (!s || !G) return fail(VCX_E_ARG, "NULL argument");
+  if (!s->has_state) return fail(VCX_E_STATE, "no state uploaded");
+  VCX_TRY(s->kt->grad(s, s->W[s->cur], nullptr));
+  return copy_out(s, s->G, (size_t)s->nr * s->nd, G, is_device);
+}
+
+static UpdateArgs make_update_args(vcx_solver s) {
+  UpdateArgs ua{};
+  ua.PR = s->PR;
+  ua.G = s->G;
+  ua.E = s->E;
+  ua.gamma = s->ph.gamma;
+  for (int k = 0; k < 4 && k < s->ph.nspecies; ++k) {
+    ua.zmu[k] = s->ph.z[k] * s->ph.mu[k];
+    ua.D[k] = s->ph.D[k];
+  }
+  ua.closure = s->ph.closure;
+  return ua;
+}
+
+extern "C" vcx_status vcx_residual(vcx_solver s, double dt, double* r, int is_device) {
+  if (!s || !r) return fail(VCX_E_ARG, "NULL argument");
+  if (!s->has_state) return fail(VCX_E_STATE, "no state uploaded");
+  const double* Win = s->W[s->cur];
+  VCX_TRY(s->kt->grad(s, Win, nullptr));
+  VCX_TRY(s->kt->flux(s, Win, nullptr, dt, nullptr));
+  UpdateArgs ua = make_update_args(s);
+  ua.Win = Win;
+  ua.rout = s->rbuf;
+  Sched sd{0.0, 0, 1};
+  VCX_TRY(s->kt->update(s, ua, sd, nullptr));
+  return copy_out(s, s->rbuf, s->nvar, r, is_device);
+}
+
+static DtParams make_dt_params(vcx_solver s, int query) {
+  DtParams dp{};
+  dp.model = s->ph.model;
+  dp.cfl = s->ph.cfl;
+  dp.fourier = s->ph.fourier;
+  dp.gamma = s->ph.gamma;
+  dp.nspecies = s->ph.nspecies;
+  for (int k = 0; k < 4 && k < s->ph.nspecies; ++k) {
+    dp.vmax_coef[k] = std::fabs(s->ph.z[k] * s->ph.mu[k]);
+    dp.D[k] = s->ph.D[k];
+  }
+  dp.query = query;
+  return dp;
+}
+
+static vcx_status launch_dt(vcx_solver s, int query) {
+  const DevMesh& m = s->mesh->d;
+  DtParams dp = make_dt_params(s, query);
+  const double* Win = s->W[s->cur];
+  return launch(s, "dt", [&] {
+    if (s->nd == 2)
+      hipLaunchKernelGGL(k_dt<2>, dim3((m.nc + 255) / 256), dim3(256), 0, s->mesh->stream, m, Win,
+                         (const double*)s->E, dp, s->sc);
+    else
+      hipLaunchKernelGGL(k_dt<3>, dim3((m.nc + 255) / 256), dim3(256), 0, s->mesh->stream, m, Win,
+                         (const double*)s->E, dp, s->sc);
+  });
+}
+
+static vcx_status read_scalars(vcx_solver s) {
+  VCX_HIP(hipMemcpyAsync(s->sc_host, s->sc, sizeof(DevScalars), hipMemcpyDeviceToHost,
+                         s->mesh->stream));
+  VCX_HIP(hipStreamSynchronize(s->mesh->stream));
+  return VCX_OK;
+}
+
+extern "C" vcx_status vcx_timestep(vcx_solver s, double* dt) {
+  if (!s || !dt) return fail(VCX_E_ARG, "NULL argument");
+  if (!s->has_state) return fail(VCX_E_STATE, "no state uploaded");
+  VCX_TRY(launch_dt(s, 1));
+  VCX_TRY(read_scalars(s));
+  *dt = s->sc_host->dt_query;
+  if (!(*dt > 0.0)) return fail(VCX_E_UNSTABLE, "non-physical state: no valid time step");
+  return VCX_OK;
+}
+
+__global__ void k_set_tend(DevScalars* sc, double t_end) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) sc->t_end = t_end;
+}
+
+static const double RK_ALPHA[5][5] = {
+    {0, 0, 0, 0, 0},
+    {0, 0, 0, 0, 0},
+    {0, 0, 1.0 / 2.0, 0, 0},
+    {0, 0, 1.0 / 3.0, 1.0 / 2.0, 0},
+    {0, 0, 1.0 / 4.0, 1.0 / 3.0, 1.0 / 2.0},
+};
+
+// Enqueue one time step (dt, then K stages) on the solver's stream.
+static vcx_status enqueue_step(vcx_solver s) {
+  VCX_TRY(launch_dt(s, 0));
+  const int K = s->ph.rk_stages;
+  double* Wn = s->W[s->cur];
+  double* Wk = s->W[1 - s->cur];
+  UpdateArgs ua = make_update_args(s);
+  for (int k = 1; k <= K; ++k) {
+    const double* Win = k == 1 ? Wn : Wk;
+    VCX_TRY(s->kt->grad(s, Win, s->sc));
+    VCX_TRY(s->kt->flux(s, Win, &s->sc->dt, 0.0, s->sc));
+    ua.Win = Win;
+    ua.Un = Wn;
+    ua.Wout = Wk;
+    // stage k of K uses alpha_{k+1}; the last one is the full update
+    Sched sd{k < K ? RK_ALPHA[K][k + 1] : 1.0, k == K ? 1 : 0, 0};
+    VCX_TRY(s->kt->update(s, ua, sd, s->sc));
+  }
+  s->cur = 1 - s->cur;
+  return VCX_OK;
+}
+
+extern "C" vcx_status vcx_step(vcx_solver s, int nsteps, double t_end, double* t, double* dt_last) {
+  if (!s) return fail(VCX_E_ARG, "NULL solver");
+  if (nsteps < 0) return fail(VCX_E_ARG, "nsteps must be >= 0");
+  if (!s->has_state) return fail(VCX_E_STATE, "no state uploaded");
+  if (s->host_flag) return fail(VCX_E_UNSTABLE, "solver is in a failed state; upload a new state");
+  const int cur0 = s->cur;
+  const long long steps0 = s->steps_total;
+  hipLaunchKernelGGL(k_set_tend, dim3(1), dim3(1), 0, s->mesh->stream, s->sc, t_end);
+  VCX_HIP(hipGetLastError());
+  const int chunk = t_end > 0.0 ? 16 : 256;
+  int launched = 0;
+  while (launched < nsteps) {
+    const int n = std::min(chunk, nsteps - launched);
+    for (int q = 0; q < n; ++q) VCX_TRY(enqueue_step(s));
+    launched += n;
+    hipLaunchKernelGGL(k_commit, dim3(1), dim3(1), 0, s->mesh->stream, s->sc);
+    VCX_HIP(hipGetLastError());
+    VCX_TRY(read_scalars(s));
+    if (s->sc_host->flag) break;
+    if (t_end > 0.0 && s->sc_host->t >= t_end) break;
+  }
+  if (launched == 0) VCX_TRY(read_scalars(s));
+  const DevScalars& h = *s->sc_host;
+  s->steps_total = h.steps;
+  s->steps_last = h.steps - steps0;
+  s->cur = (int)((cur0 + s->steps_last) % 2);
+  if (t) *t = h.t;
+  if (dt_last) *dt_last = h.last_dt;
+  VCX_TRY(harvest(s));
+  if (h.flag) {
+    s->host_flag = h.flag;
+    return fail(VCX_E_UNSTABLE, h.flag & 1 ? "state became non-finite or non-physical"
+                                           : "no valid time step (non-physical state)");
+  }
+  return VCX_OK;
+}
+
+extern "C" int64_t vcx_steps_done(vcx_solver s) { return s ? s->steps_last : -1; }
+
+extern "C" vcx_status vcx_solve_batch(vcx_solver* ss, int n, const int* nsteps, const double* t_end) {
+  if (!ss || n < 0 || !nsteps || !t_end) return fail(VCX_E_ARG, "NULL argument");
+  for (int i = 0; i < n; ++i) {
+    if (!ss[i]) return fail(VCX_E_ARG, "NULL solver in batch");
+    double t, dl;
+    VCX_TRY(vcx_step(ss[i], nsteps[i], t_end[i], &t, &dl));
+  }
+  return VCX_OK;
+}
+
+extern "C" vcx_status vcx_conservation_sums(vcx_solver s, double* sums) {
+  if (!s || !sums) return fail(VCX_E_ARG, "NULL argument");
+  if (!s->has_state) return fail(VCX_E_STATE, "no state uploaded");
+  const DevMesh& d = s->mesh->d;
+  hipLaunchKernelGGL(k_sums_partial, dim3(256), dim3(256), 0, s->mesh->stream,
+                     (const double*)s->W[s->cur], d.vnode, d.nn, s->nvar, s->part);
+  hipLaunchKernelGGL(k_sums_final, dim3(1), dim3(256), 0, s->mesh->stream, (const double*)s->part,
+                     256, s->nvar, s->sums_dev);
+  VCX_HIP(hipGetLastError());
+  VCX_HIP(hipMemcpyAsync(s->sums_host, s->sums_dev, sizeof(double) * s->nvar, hipMemcpyDeviceToHost,
+                         s->mesh->stream));
+  VCX_HIP(hipStreamSynchronize(s->mesh->stream));
+  std::memcpy(sums, s->sums_host, sizeof(double) * s->nvar);
+  return VCX_OK;
+}
+
+extern "C" vcx_status vcx_profile_enable(vcx_solver s, int enable) {
+  if (!s) return fail(VCX_E_ARG, "NULL solver");
+  VCX_TRY(harvest(s));
+  s->prof = enable != 0;
+  s->acc.clear();
+  return VCX_OK;
+}
+
+extern "C" vcx_status vcx_profile_query(vcx_solver s, const char* kernel, int64_t* count,
+                                        double* total_ms) {
+  if (!s || !kernel || !count || !total_ms) return fail(VCX_E_ARG, "NULL argument");
+  VCX_TRY(harvest(s));
+  auto it = s->acc.find(kernel);
+  *count = it == s->acc.end() ? 0 : it->second.first;
+  *total_ms = it == s->acc.end() ? 0.0 : it->second.second;
+  return VCX_OK;
+}
+
+extern "C" const char* vcx_last_error(void) { return g_err.c_str(); }

@@ -1,0 +1,188 @@
+// Device functions of the vertex-centred residual: simplex geometry,
+// limiters and the face fluxes, templated on the compute type (double for the
+// FP64 path, float for the mixed path).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace vcx {
+
+// local cell-edges (a, b), a < b
+template <int ND> struct Edges;
+template <> struct Edges<2> {
+  static constexpr int NE = 3;
+  __device__ static constexpr int a(int e) { return e == 2 ? 1 : 0; }
+  __device__ static constexpr int b(int e) { return e == 0 ? 1 : 2; }
+};
+template <> struct Edges<3> {
+  static constexpr int NE = 6;
+  __device__ static constexpr int a(int e) { return e < 3 ? 0 : (e < 5 ? 1 : 2); }
+  __device__ static constexpr int b(int e) { return e < 3 ? e + 1 : (e == 3 ? 2 : 3); }
+};
+
+// Node normals of a positively oriented simplex from the relative vertex
+// coordinates e[k-1] = X_k - X_0: S_k = -n_d V grad(lambda_k), i.e. the
+// outward area vector of the face opposite vertex k.  Returns the signed
+// measure det(e) (= n_d! V).
+template <int ND, typename T>
+__device__ inline T simplex_normals(const T (&e)[ND][ND], T (&S)[ND + 1][ND]) {
+  if constexpr (ND == 2) {
+    S[1][0] = -e[1][1]; S[1][1] = e[1][0];
+    S[2][0] = e[0][1];  S[2][1] = -e[0][0];
+    S[0][0] = -(S[1][0] + S[2][0]);
+    S[0][1] = -(S[1][1] + S[2][1]);
+    return e[0][0] * e[1][1] - e[0][1] * e[1][0];
+  } else {
+    const T h = T(-0.5);
+    S[1][0] = h * (e[1][1] * e[2][2] - e[1][2] * e[2][1]);
+    S[1][1] = h * (e[1][2] * e[2][0] - e[1][0] * e[2][2]);
+    S[1][2] = h * (e[1][0] * e[2][1] - e[1][1] * e[2][0]);
+    S[2][0] = h * (e[2][1] * e[0][2] - e[2][2] * e[0][1]);
+    S[2][1] = h * (e[2][2] * e[0][0] - e[2][0] * e[0][2]);
+    S[2][2] = h * (e[2][0] * e[0][1] - e[2][1] * e[0][0]);
+    S[3][0] = h * (e[0][1] * e[1][2] - e[0][2] * e[1][1]);
+    S[3][1] = h * (e[0][2] * e[1][0] - e[0][0] * e[1][2]);
+    S[3][2] = h * (e[0][0] * e[1][1] - e[0][1] * e[1][0]);
+    for (int d = 0; d < 3; ++d) S[0][d] = -(S[1][d] + S[2][d] + S[3][d]);
+    return e[0][0] * (e[1][1] * e[2][2] - e[1][2] * e[2][1]) -
+           e[0][1] * (e[1][0] * e[2][2] - e[1][2] * e[2][0]) +
+           e[0][2] * (e[1][0] * e[2][1] - e[1][1] * e[2][0]);
+  }
+}
+
+// Slope limiter L(a, b) (kinds as vcx.h VCX_LIM_*).
+template <typename T>
+__device__ inline T slope_limit(int kind, T beta, T a, T b) {
+  if (kind == 0) return T(0);
+  if (kind == 4) return T(0.5) * (a + b);
+  if (!(a * b > T(0))) return T(0);
+  if (kind == 2) return T(2) * a * b / (a + b);
+  T aa = fabs(a), bb = fabs(b);
+  T r = kind == 1 ? fmin(aa, bb) : fmax(fmin(beta * aa, bb), fmin(aa, beta * bb));
+  return a > T(0) ? r : -r;
+}
+
+// Flux limiter Psi of the limited Lax-Wendroff flux, R = a / b.
+template <typename T>
+__device__ inline T psi_limit(int kind, T beta, T a, T b) {
+  if (kind == 0) return T(0);
+  if (kind == 4) return T(1);
+  if (!(a * b > T(0))) return T(0);
+  T R = a / b;  // > 0
+  if (kind == 2) return T(2) * R / (T(1) + R);
+  T bt = kind == 1 ? T(1) : beta;
+  return fmax(fmin(bt * R, T(1)), fmin(R, bt));
+}
+
+// Physical flux through the unit normal n of the reconstructed state
+// W = (rho, rho u, rho E, rho Y, p).
+template <int ND, int NSP, typename T>
+__device__ inline void normal_flux(const T* W, const T* n, T* F, T& q) {
+  constexpr int NV = 2 + ND + NSP;
+  const T rho = W[0], p = W[NV];
+  const T ir = T(1) / rho;
+  q = T(0);
+  for (int d = 0; d < ND; ++d) q += W[1 + d] * n[d];
+  q *= ir;
+  F[0] = rho * q;
+  for (int d = 0; d < ND; ++d) F[1 + d] = W[1 + d] * q + p * n[d];
+  F[1 + ND] = (W[1 + ND] + p) * q;
+  for (int k = 0; k < NSP; ++k) F[2 + ND + k] = W[2 + ND + k] * q;
+}
+
+// HLLC flux through the area vector S (result scaled by |S|), Davis wave
+// speeds, star states of the paper's multicomponent HLLC.
+template <int ND, int NSP, typename T>
+__device__ inline void hllc_flux(const T* WL, const T* WR, const T* S, T gamma, T* F) {
+  constexpr int NV = 2 + ND + NSP;
+  T A2 = T(0);
+  for (int d = 0; d < ND; ++d) A2 += S[d] * S[d];
+  const T A = sqrt(A2), iA = T(1) / A;
+  T n[ND];
+  for (int d = 0; d < ND; ++d) n[d] = S[d] * iA;
+  T FL[NV], FR[NV], qL, qR;
+  normal_flux<ND, NSP>(WL, n, FL, qL);
+  normal_flux<ND, NSP>(WR, n, FR, qR);
+  const T rL = WL[0], rR = WR[0], pL = WL[NV], pR = WR[NV];
+  const T aL = sqrt(gamma * pL / rL), aR = sqrt(gamma * pR / rR);
+  const T SL = fmin(qL - aL, qR - aR), SR = fmax(qL + aL, qR + aR);
+  const T mL = rL * (SL - qL), mR = rR * (SR - qR);
+  const T Ss = (pR - pL + mL * qL - mR * qR) / (mL - mR);
+  if (T(0) <= SL) {
+    for (int v = 0; v < NV; ++v) F[v] = A * FL[v];
+  } else if (SR < T(0)) {
+    for (int v = 0; v < NV; ++v) F[v] = A * FR[v];
+  } else {
+    const bool left = T(0) <= Ss;
+    const T* W = left ? WL : WR;
+    const T* FK = left ? FL : FR;
+    const T SK = left ? SL : SR, qK = left ? qL : qR, rK = W[0], pK = W[NV];
+    const T irK = T(1) / rK;
+    const T fac = rK * (SK - qK) / (SK - Ss);
+    const T dq = Ss - qK;
+    // star state minus own state, times the wave speed
+    F[0] = A * (FK[0] + SK * (fac - rK));
+    for (int d = 0; d < ND; ++d)
+      F[1 + d] = A * (FK[1 + d] + SK * (fac * (W[1 + d] * irK + dq * n[d]) - W[1 + d]));
+    F[1 + ND] = A * (FK[1 + ND] + SK * (fac * (W[1 + ND] * irK + dq * (Ss + pK / (rK * (SK - qK)))) -
+                                       W[1 + ND]));
+    for (int k = 0; k < NSP; ++k)
+      F[2 + ND + k] = A * (FK[2 + ND + k] + SK * (fac * irK - T(1)) * W[2 + ND + k]);
+  }
+}
+
+// Roe flux (textbook; the paper names Riemann solvers but prints only HLLC),
+// sqrt(rho) averages, Harten entropy fix on the acoustic waves.
+template <int ND, int NSP, typename T>
+__device__ inline void roe_flux(const T* WL, const T* WR, const T* S, T gamma, T fix, T* F) {
+  constexpr int NV = 2 + ND + NSP;
+  T A2 = T(0);
+  for (int d = 0; d < ND; ++d) A2 += S[d] * S[d];
+  const T A = sqrt(A2), iA = T(1) / A;
+  T n[ND];
+  for (int d = 0; d < ND; ++d) n[d] = S[d] * iA;
+  T FL[NV], FR[NV], qL, qR;
+  normal_flux<ND, NSP>(WL, n, FL, qL);
+  normal_flux<ND, NSP>(WR, n, FR, qR);
+  const T rL = WL[0], rR = WR[0], pL = WL[NV], pR = WR[NV];
+  const T irL = T(1) / rL, irR = T(1) / rR;
+  const T sL = sqrt(rL), sR = sqrt(rR), iw = T(1) / (sL + sR);
+  const T wl = sL * iw, wr = sR * iw;
+  T u[ND], uu = T(0), q = T(0);
+  for (int d = 0; d < ND; ++d) {
+    u[d] = wl * WL[1 + d] * irL + wr * WR[1 + d] * irR;
+    uu += u[d] * u[d];
+    q += u[d] * n[d];
+  }
+  const T H = wl * (WL[1 + ND] + pL) * irL + wr * (WR[1 + ND] + pR) * irR;
+  const T a = sqrt((gamma - T(1)) * (H - T(0.5) * uu));
+  const T rho = sL * sR;
+  const T dp = pR - pL, dq = qR - qL;
+  const T ia2 = T(1) / (a * a);
+  const T a1 = T(0.5) * (dp - rho * a * dq) * ia2;
+  const T a5 = T(0.5) * (dp + rho * a * dq) * ia2;
+  const T a2 = (rR - rL) - dp * ia2;
+  T l1 = fabs(q - a), l5 = fabs(q + a);
+  const T l2 = fabs(q);
+  const T del = fix * a;
+  if (del > T(0)) {
+    if (l1 < del) l1 = T(0.5) * (l1 * l1 + del * del) / del;
+    if (l5 < del) l5 = T(0.5) * (l5 * l5 + del * del) / del;
+  }
+  const T w1 = l1 * a1, w2 = l2 * a2, w5 = l5 * a5;
+  T Dv[NV];
+  Dv[0] = w1 + w2 + w5;
+  T udut = T(0);
+  for (int d = 0; d < ND; ++d) {
+    const T dut = (WR[1 + d] * irR - WL[1 + d] * irL) - dq * n[d];
+    udut += u[d] * dut;
+    Dv[1 + d] = w1 * (u[d] - a * n[d]) + w2 * u[d] + w5 * (u[d] + a * n[d]) + l2 * rho * dut;
+  }
+  Dv[1 + ND] = w1 * (H - q * a) + w2 * T(0.5) * uu + w5 * (H + q * a) + l2 * rho * udut;
+  for (int k = 0; k < NSP; ++k) {
+    const T YL = WL[2 + ND + k] * irL, YR = WR[2 + ND + k] * irR;
+    Dv[2 + ND + k] = (w1 + w2 + w5) * (wl * YL + wr * YR) + l2 * rho * (YR - YL);
+  }
+  for (int v = 0; v < NV; ++v) F[v] = A * (T(0.5) * (FL[v] + FR[v]) - T(0.5) * Dv[v]);
+}
+
+}  // namespace vcx

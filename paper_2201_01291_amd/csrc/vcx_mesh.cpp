@@ -1,0 +1,337 @@
+// Host-side mesh preprocessing: validation, orientation, median-dual nodal
+// volumes, boundary node normals, space-filling-curve renumbering and the
+// fixed cell tiles with their deterministic gather tables.
+//
+// Geometry follows Sec. "Nomenclature and notations" of the paper: the node
+// normal S_k of a simplex is the outward area vector of the face opposite k,
+// which equals -n_d V grad(lambda_k) with lambda_k the barycentric coordinate
+// of vertex k; the boundary node normal S_i^b gives every boundary face's
+// area vector in equal shares to its n_d nodes.
+#include "vcx_mesh.h"
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <numeric>
+
+namespace vcx {
+
+TileLimits default_tile_limits(int nd) {
+  if (nd == 2) return {256, 192};
+  return {128, 96};
+}
+
+namespace {
+
+uint64_t spread_bits(uint64_t v, int nd) {
+  // interleave the low 21 bits of v with (nd - 1) zero bits between them
+  uint64_t r = 0;
+  for (int b = 0; b < 21; ++b) r |= ((v >> b) & 1ull) << (b * nd);
+  return r;
+}
+
+uint64_t morton(const double* p, const double* lo, const double* span, int nd) {
+  uint64_t code = 0;
+  for (int d = 0; d < nd; ++d) {
+    double t = span[d] > 0 ? (p[d] - lo[d]) / span[d] : 0.0;
+    t = std::min(std::max(t, 0.0), 1.0);
+    uint64_t q = (uint64_t)(t * ((1u << 21) - 1));
+    code |= spread_bits(q, nd) << d;
+  }
+  return code;
+}
+
+// relative vertex coordinates e_k = X_k - X_0 of a cell, k = 1..nv-1
+void relative_coords(const HostMesh& m, const double* x, const int64_t* v, uint32_t code,
+                     double e[3][3]) {
+  for (int k = 1; k < m.nv; ++k)
+    for (int d = 0; d < m.nd; ++d) {
+      double s = shift_of(code, k, d, m.nd);
+      e[k - 1][d] = x[(int64_t)d * m.nn + v[k]] + s * m.period[d] - x[(int64_t)d * m.nn + v[0]];
+    }
+}
+
+double signed_measure(int nd, const double e[3][3]) {
+  if (nd == 2) return e[0][0] * e[1][1] - e[0][1] * e[1][0];
+  return e[0][0] * (e[1][1] * e[2][2] - e[1][2] * e[2][1]) -
+         e[0][1] * (e[1][0] * e[2][2] - e[1][2] * e[2][0]) +
+         e[0][2] * (e[1][0] * e[2][1] - e[1][1] * e[2][0]);
+}
+
+// node normals of a positively oriented simplex from its relative coordinates
+void node_normals(int nd, const double e[3][3], double S[4][3]) {
+  if (nd == 2) {
+    S[1][0] = -e[1][1]; S[1][1] = e[1][0];
+    S[2][0] = e[0][1];  S[2][1] = -e[0][0];
+    S[0][0] = -S[1][0] - S[2][0];
+    S[0][1] = -S[1][1] - S[2][1];
+    return;
+  }
+  auto cross = [](const double* a, const double* b, double* c) {
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+  };
+  double c[3];
+  cross(e[1], e[2], c);
+  for (int d = 0; d < 3; ++d) S[1][d] = -0.5 * c[d];
+  cross(e[2], e[0], c);
+  for (int d = 0; d < 3; ++d) S[2][d] = -0.5 * c[d];
+  cross(e[0], e[1], c);
+  for (int d = 0; d < 3; ++d) S[3][d] = -0.5 * c[d];
+  for (int d = 0; d < 3; ++d) S[0][d] = -(S[1][d] + S[2][d] + S[3][d]);
+}
+
+}  // namespace
+
+std::string preprocess_mesh(int nd, int64_t nn, const double* xyz, int64_t nc, int nv,
+                            const int64_t* cells, const double* period, TileLimits lim,
+                            HostMesh& m, int* code) {
+  *code = -1;
+  if (nd != 2 && nd != 3) return "ndim must be 2 or 3";
+  if (nv != nd + 1) return "only simplices are supported: nv must be ndim + 1";
+  if (nn <= 0 || nc <= 0 || !xyz || !cells) return "empty mesh or NULL array";
+  if (nn >= (int64_t)INT32_MAX || nc * nv >= (int64_t)INT32_MAX) return "mesh too large for 32-bit indices";
+  if (lim.max_cells < 1 || lim.max_cells > 1024 || lim.max_nodes < nv || lim.max_nodes > 4096)
+    return "tile limits out of range";
+  m = HostMesh();
+  m.nd = nd; m.nv = nv; m.ne = nd == 2 ? 3 : 6; m.nn = nn; m.nc = nc; m.lim = lim;
+  for (int d = 0; d < nd; ++d) {
+    double L = period ? period[d] : 0.0;
+    if (!(L >= 0.0) || !std::isfinite(L)) return "period entries must be finite and >= 0";
+    m.period[d] = L;
+    if (L > 0.0) m.has_period = true;
+  }
+  for (int64_t q = 0; q < (int64_t)nd * nn; ++q)
+    if (!std::isfinite(xyz[q])) return "non-finite coordinate";
+
+  // ---- connectivity, periodic images, orientation, volumes (caller order)
+  *code = -2;
+  std::vector<int64_t> cv((size_t)nc * nv);
+  std::vector<uint32_t> sh(nc, 0u);
+  std::vector<double> vol(nc);
+  double vmax = 0.0;
+  for (int64_t c = 0; c < nc; ++c) {
+    int64_t* v = &cv[(size_t)c * nv];
+    for (int k = 0; k < nv; ++k) {
+      v[k] = cells[(int64_t)k * nc + c];
+      if (v[k] < 0 || v[k] >= nn) return "cell index out of range";
+      for (int q = 0; q < k; ++q)
+        if (v[q] == v[k]) return "cell repeats a node";
+    }
+    uint32_t s = 0;
+    for (int k = 1; k < nv; ++k)
+      for (int d = 0; d < nd; ++d) {
+        if (m.period[d] <= 0.0) continue;
+        double dx = xyz[(int64_t)d * nn + v[k]] - xyz[(int64_t)d * nn + v[0]];
+        double img = -std::nearbyint(dx / m.period[d]);
+        if (std::fabs(img) > 1.0) return "periodic cell spans more than one box length";
+        if (img == 1.0) s |= 1u << (2 * ((k - 1) * nd + d));
+        if (img == -1.0) s |= 2u << (2 * ((k - 1) * nd + d));
+      }
+    double e[3][3];
+    relative_coords(m, xyz, v, s, e);
+    double det = signed_measure(nd, e);
+    if (det < 0.0) {
+      // reorient: swap vertices 1 and 2 together with their periodic images
+      std::swap(v[1], v[2]);
+      uint32_t s1 = (s >> 0) & ((1u << (2 * nd)) - 1u);
+      uint32_t s2 = (s >> (2 * nd)) & ((1u << (2 * nd)) - 1u);
+      s = (s & ~((1u << (4 * nd)) - 1u)) | s2 | (s1 << (2 * nd));
+      relative_coords(m, xyz, v, s, e);
+      det = signed_measure(nd, e);
+    }
+    sh[c] = s;
+    vol[c] = det / (nd == 2 ? 2.0 : 6.0);
+    vmax = std::max(vmax, vol[c]);
+  }
+  for (int64_t c = 0; c < nc; ++c)
+    if (!(vol[c] > 1e-12 * vmax)) return "degenerate (zero-volume) cell";
+
+  // ---- space-filling-curve order of nodes
+  double lo[3], hi[3], span[3];
+  for (int d = 0; d < nd; ++d) {
+    lo[d] = INFINITY; hi[d] = -INFINITY;
+    for (int64_t i = 0; i < nn; ++i) {
+      lo[d] = std::min(lo[d], xyz[(int64_t)d * nn + i]);
+      hi[d] = std::max(hi[d], xyz[(int64_t)d * nn + i]);
+    }
+    span[d] = hi[d] - lo[d];
+  }
+  std::vector<uint64_t> key(nn);
+  for (int64_t i = 0; i < nn; ++i) {
+    double p[3];
+    for (int d = 0; d < nd; ++d) p[d] = xyz[(int64_t)d * nn + i];
+    key[i] = morton(p, lo, span, nd);
+  }
+  std::vector<int32_t> order(nn);
+  std::iota(order.begin(), order.end(), 0);
+  std::sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    return key[a] != key[b] ? key[a] < key[b] : a < b;
+  });
+  std::vector<int32_t> inv(nn);
+  for (int64_t i = 0; i < nn; ++i) inv[order[i]] = (int32_t)i;
+  m.perm = order;
+  m.x.resize((size_t)nd * nn);
+  for (int d = 0; d < nd; ++d)
+    for (int64_t i = 0; i < nn; ++i) m.x[(size_t)d * nn + i] = xyz[(int64_t)d * nn + order[i]];
+
+  // ---- cell order: curve key of the (wrapped) centroid
+  std::vector<uint64_t> ckey(nc);
+  for (int64_t c = 0; c < nc; ++c) {
+    const int64_t* v = &cv[(size_t)c * nv];
+    double e[3][3];
+    relative_coords(m, xyz, v, sh[c], e);
+    double p[3];
+    for (int d = 0; d < nd; ++d) {
+      double s = 0.0;
+      for (int k = 1; k < nv; ++k) s += e[k - 1][d];
+      p[d] = xyz[(int64_t)d * nn + v[0]] + s / nv;
+      if (m.period[d] > 0.0) p[d] = lo[d] + std::fmod(std::fmod(p[d] - lo[d], m.period[d]) + m.period[d], m.period[d]);
+    }
+    ckey[c] = morton(p, lo, span, nd);
+  }
+  std::vector<int64_t> corder(nc);
+  std::iota(corder.begin(), corder.end(), 0);
+  std::sort(corder.begin(), corder.end(), [&](int64_t a, int64_t b) {
+    return ckey[a] != ckey[b] ? ckey[a] < ckey[b] : a < b;
+  });
+  m.cell.resize((size_t)nv * nc);
+  m.shift.resize(nc);
+  std::vector<double> cvol(nc);
+  for (int64_t c = 0; c < nc; ++c) {
+    int64_t src = corder[c];
+    for (int k = 0; k < nv; ++k) m.cell[(size_t)k * nc + c] = inv[cv[(size_t)src * nv + k]];
+    m.shift[c] = sh[src];
+    cvol[c] = vol[src];
+  }
+
+  // ---- median-dual nodal volumes (cell order, deterministic)
+  m.vnode.assign(nn, 0.0);
+  m.vol_cells = 0.0;
+  for (int64_t c = 0; c < nc; ++c) {
+    m.vol_cells += cvol[c];
+    for (int k = 0; k < nv; ++k) m.vnode[m.cell[(size_t)k * nc + c]] += cvol[c] / nv;
+  }
+  m.vol_nodes = 0.0;
+  for (int64_t i = 0; i < nn; ++i) m.vol_nodes += m.vnode[i];
+
+  // ---- boundary faces (owned by exactly one cell) and boundary node normals
+  struct Face { std::array<int32_t, 3> n; int32_t c; int8_t k; };
+  std::vector<Face> faces((size_t)nc * nv);
+  for (int64_t c = 0; c < nc; ++c)
+    for (int k = 0; k < nv; ++k) {
+      Face& f = faces[(size_t)c * nv + k];
+      f.n = {-1, -1, -1};
+      int q = 0;
+      for (int v = 0; v < nv; ++v)
+        if (v != k) f.n[q++] = m.cell[(size_t)v * nc + c];
+      std::sort(f.n.begin(), f.n.begin() + nd);
+      f.c = (int32_t)c;
+      f.k = (int8_t)k;
+    }
+  std::sort(faces.begin(), faces.end(), [](const Face& a, const Face& b) {
+    return a.n != b.n ? a.n < b.n : a.c < b.c;
+  });
+  std::vector<double> Sb((size_t)nd * nn, 0.0);
+  std::vector<char> isb(nn, 0);
+  for (size_t a = 0; a < faces.size();) {
+    size_t b = a + 1;
+    while (b < faces.size() && faces[b].n == faces[a].n) ++b;
+    if (b - a > 2) return "non-manifold face shared by more than two cells";
+    if (b - a == 1) {
+      int64_t c = faces[a].c;
+      int64_t v[4];
+      for (int k = 0; k < nv; ++k) v[k] = m.cell[(size_t)k * nc + c];
+      double e[3][3], S[4][3];
+      for (int k = 1; k < nv; ++k)
+        for (int d = 0; d < nd; ++d)
+          e[k - 1][d] = m.x[(size_t)d * nn + v[k]] + shift_of(m.shift[c], k, d, nd) * m.period[d] -
+                        m.x[(size_t)d * nn + v[0]];
+      node_normals(nd, e, S);
+      for (int q = 0; q < nd; ++q) {
+        int32_t i = faces[a].n[q];
+        isb[i] = 1;
+        for (int d = 0; d < nd; ++d) Sb[(size_t)d * nn + i] += S[faces[a].k][d] / nd;
+      }
+    }
+    a = b;
+  }
+  for (int64_t i = 0; i < nn; ++i)
+    if (isb[i]) m.bnd_node.push_back((int32_t)i);
+  size_t nb = m.bnd_node.size();
+  m.bnd_S.resize((size_t)nd * nb);
+  for (size_t q = 0; q < nb; ++q)
+    for (int d = 0; d < nd; ++d) m.bnd_S[(size_t)d * nb + q] = Sb[(size_t)d * nn + m.bnd_node[q]];
+
+  // ---- tiles: consecutive cells, closed at max_cells cells or max_nodes nodes
+  std::vector<int64_t> stamp(nn, -1);
+  m.tile_cell.push_back(0);
+  int64_t tcount = 0, ncount = 0;
+  for (int64_t c = 0; c < nc; ++c) {
+    int fresh = 0;
+    for (int k = 0; k < nv; ++k)
+      if (stamp[m.cell[(size_t)k * nc + c]] != (int64_t)m.tile_cell.size() - 1) ++fresh;
+    if (tcount > 0 && (tcount + 1 > lim.max_cells || ncount + fresh > lim.max_nodes)) {
+      m.tile_cell.push_back((int32_t)c);
+      tcount = 0;
+      ncount = 0;
+      fresh = nv;
+    }
+    int64_t t = (int64_t)m.tile_cell.size() - 1;
+    for (int k = 0; k < nv; ++k) {
+      int32_t i = m.cell[(size_t)k * nc + c];
+      if (stamp[i] != t) { stamp[i] = t; ++ncount; }
+    }
+    ++tcount;
+  }
+  m.tile_cell.push_back((int32_t)nc);
+  int64_t T = m.ntiles();
+
+  m.lconn.resize((size_t)nv * nc);
+  m.tile_slot.assign(1, 0);
+  std::vector<int32_t> local(nn, -1);
+  std::vector<int32_t> tnodes;
+  std::vector<std::vector<uint16_t>> tinc;
+  m.slot_inc.assign(1, 0);
+  for (int64_t t = 0; t < T; ++t) {
+    int32_t c0 = m.tile_cell[t], c1 = m.tile_cell[t + 1];
+    tnodes.clear();
+    for (int32_t c = c0; c < c1; ++c)
+      for (int k = 0; k < nv; ++k) tnodes.push_back(m.cell[(size_t)k * nc + c]);
+    std::sort(tnodes.begin(), tnodes.end());
+    tnodes.erase(std::unique(tnodes.begin(), tnodes.end()), tnodes.end());
+    for (size_t q = 0; q < tnodes.size(); ++q) local[tnodes[q]] = (int32_t)q;
+    tinc.assign(tnodes.size(), {});
+    for (int32_t c = c0; c < c1; ++c)
+      for (int k = 0; k < nv; ++k) {
+        int32_t l = local[m.cell[(size_t)k * nc + c]];
+        m.lconn[(size_t)k * nc + c] = (uint16_t)l;
+        tinc[l].push_back((uint16_t)(((c - c0) << 2) | k));
+      }
+    for (size_t q = 0; q < tnodes.size(); ++q) {
+      m.slot_node.push_back(tnodes[q]);
+      for (uint16_t code : tinc[q]) m.inc.push_back(code);
+      m.slot_inc.push_back((int32_t)m.inc.size());
+    }
+    m.tile_slot.push_back((int32_t)m.slot_node.size());
+    m.max_tile_cells = std::max(m.max_tile_cells, (int)(c1 - c0));
+    m.max_tile_nodes = std::max(m.max_tile_nodes, (int)tnodes.size());
+  }
+
+  // ---- node -> slots (ascending tile order)
+  int64_t P = m.nslots();
+  m.node_slot.assign(nn + 1, 0);
+  for (int64_t s = 0; s < P; ++s) m.node_slot[m.slot_node[s] + 1]++;
+  for (int64_t i = 0; i < nn; ++i) m.node_slot[i + 1] += m.node_slot[i];
+  m.slots_of.resize(P);
+  std::vector<int32_t> fill(m.node_slot.begin(), m.node_slot.end() - 1);
+  for (int64_t s = 0; s < P; ++s) m.slots_of[fill[m.slot_node[s]]++] = (int32_t)s;
+  for (int64_t i = 0; i < nn; ++i)
+    if (m.node_slot[i + 1] == m.node_slot[i]) return "node not referenced by any cell";
+
+  *code = 0;
+  return "";
+}
+
+}  // namespace vcx

@@ -1,0 +1,64 @@
+// Host-side mesh preprocessing for the vertex-centred residual library.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace vcx {
+
+// Tile limits: cells per tile (= threads of the tile kernels) and distinct
+// nodes per tile (rows of the LDS node cache).
+struct TileLimits {
+  int max_cells;
+  int max_nodes;
+};
+
+TileLimits default_tile_limits(int nd);
+
+// Mesh after preprocessing, in the internal (space-filling-curve) order.
+struct HostMesh {
+  int nd = 0, nv = 0, ne = 0;
+  int64_t nn = 0, nc = 0;
+  double period[3] = {0, 0, 0};
+  bool has_period = false;
+
+  std::vector<int32_t> perm;      // [nn] internal node -> caller node
+  std::vector<double> x;          // [nd][nn] coordinates (internal order)
+  std::vector<int32_t> cell;      // [nv][nc] internal node ids, positively oriented
+  std::vector<uint32_t> shift;    // [nc] periodic image code of vertices 1..nv-1
+  std::vector<double> vnode;      // [nn] median-dual volume V_i
+  double vol_cells = 0.0, vol_nodes = 0.0;
+
+  // boundary closure
+  std::vector<int32_t> bnd_node;  // [nb] internal ids (ascending)
+  std::vector<double> bnd_S;      // [nd][nb] boundary node normals S_i^b
+
+  // tiles
+  TileLimits lim{};
+  std::vector<int32_t> tile_cell;  // [T+1] first cell of each tile
+  std::vector<int32_t> tile_slot;  // [T+1] first slot of each tile
+  std::vector<int32_t> slot_node;  // [P] node of each slot (ascending inside a tile)
+  std::vector<uint16_t> lconn;     // [nv][nc] tile-local node of each cell vertex
+  std::vector<int32_t> slot_inc;   // [P+1] CSR into inc
+  std::vector<uint16_t> inc;       // [nc*nv] (local cell << 2) | vertex, ascending cell
+  std::vector<int32_t> node_slot;  // [nn+1] CSR into slots_of
+  std::vector<int32_t> slots_of;   // [P] slots of each node, ascending tile
+  int max_tile_cells = 0, max_tile_nodes = 0;
+
+  int64_t ntiles() const { return (int64_t)tile_cell.size() - 1; }
+  int64_t nslots() const { return (int64_t)slot_node.size(); }
+};
+
+// Returns "" on success, else an error message; *code receives the status
+// (-1 argument, -2 mesh).
+std::string preprocess_mesh(int nd, int64_t nn, const double* xyz, int64_t nc, int nv,
+                            const int64_t* cells, const double* period, TileLimits lim,
+                            HostMesh& out, int* code);
+
+// Decode the periodic image of vertex k (1..nv-1) along axis d: -1, 0, +1.
+inline int shift_of(uint32_t code, int k, int d, int nd) {
+  uint32_t b = (code >> (2 * ((k - 1) * nd + d))) & 3u;
+  return b == 1u ? 1 : (b == 2u ? -1 : 0);
+}
+
+}  // namespace vcx

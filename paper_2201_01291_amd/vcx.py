@@ -1,0 +1,294 @@
+"""Thin Python binding of ``libvcx.so`` (the C ABI in ``include/vcx.h``).
+
+Argument marshalling only: every step of the residual, the update and the
+time step runs in the library's HIP kernels.  Device memory and streams may
+come from PyTorch (CUDA/HIP tensors are passed by pointer with
+``is_device = 1``); host arrays are numpy.
+
+There is no CPU fallback: if the library is missing, importing the binding
+raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libvcx.so")
+
+OK, E_ARG, E_MESH, E_OOM, E_HIP, E_UNSTABLE, E_BUSY, E_STATE = 0, -1, -2, -3, -4, -5, -6, -7
+MODEL_GAS, MODEL_DRIFT_DIFFUSION = 0, 1
+FLUX_HLLC, FLUX_ROE = 0, 1
+LIM_FIRST_ORDER, LIM_MINMOD, LIM_VANLEER, LIM_SWEBY, LIM_NONE = 0, 1, 2, 3, 4
+PREC_FP64, PREC_MIXED = 0, 1
+MAX_SPECIES = 16
+
+# every symbol declared in include/vcx.h
+EXPORTS = (
+    "vcx_mesh_create", "vcx_mesh_create_tiled", "vcx_mesh_destroy", "vcx_mesh_info", "vcx_mesh_geometry",
+    "vcx_mesh_preprocess", "vcx_solver_create", "vcx_solver_destroy", "vcx_solver_nvar",
+    "vcx_state_upload", "vcx_state_download", "vcx_state_set_time", "vcx_gradient",
+    "vcx_residual", "vcx_timestep", "vcx_step", "vcx_steps_done", "vcx_solve_batch",
+    "vcx_conservation_sums", "vcx_profile_enable", "vcx_profile_query", "vcx_last_error",
+)
+
+
+class VcxError(RuntimeError):
+    def __init__(self, code: int, what: str, msg: str):
+        super().__init__(f"{what} failed ({code}): {msg}")
+        self.code = code
+
+
+class Physics(C.Structure):
+    _fields_ = [("model", C.c_int32), ("flux", C.c_int32), ("limiter", C.c_int32),
+                ("rk_stages", C.c_int32), ("nspecies", C.c_int32), ("closure", C.c_int32),
+                ("precision", C.c_int32), ("reserved", C.c_int32),
+                ("beta", C.c_double), ("cfl", C.c_double), ("fourier", C.c_double),
+                ("gamma", C.c_double), ("entropy_fix", C.c_double),
+                ("z", C.c_double * MAX_SPECIES), ("mu", C.c_double * MAX_SPECIES),
+                ("D", C.c_double * MAX_SPECIES)]
+
+
+def physics(model=MODEL_GAS, flux=FLUX_HLLC, limiter=LIM_MINMOD, rk_stages=2, nspecies=0,
+            closure=True, precision=PREC_FP64, beta=1.0, cfl=0.5, fourier=0.25, gamma=1.4,
+            entropy_fix=0.1, z=(), mu=(), D=()) -> Physics:
+    p = Physics()
+    p.model, p.flux, p.limiter, p.rk_stages = model, flux, limiter, rk_stages
+    p.nspecies, p.closure, p.precision = nspecies, int(bool(closure)), precision
+    p.beta, p.cfl, p.fourier, p.gamma, p.entropy_fix = beta, cfl, fourier, gamma, entropy_fix
+    for k, (a, b, c) in enumerate(zip(z, mu, D)):
+        p.z[k], p.mu[k], p.D[k] = a, b, c
+    return p
+
+
+_lib = None
+
+
+def lib():
+    """Load the in-tree library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2201_01291_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, dp, i64p = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)
+        L.vcx_mesh_create.argtypes = [C.c_int, C.c_int64, dp, C.c_int64, C.c_int, i64p, dp, vp,
+                                      C.POINTER(vp)]
+        L.vcx_mesh_create_tiled.argtypes = [C.c_int, C.c_int64, dp, C.c_int64, C.c_int, i64p, dp,
+                                            C.c_int, C.c_int, vp, C.POINTER(vp)]
+        L.vcx_mesh_destroy.argtypes = [vp]
+        L.vcx_mesh_info.argtypes = [vp, i64p]
+        L.vcx_mesh_geometry.argtypes = [vp, dp, dp]
+        L.vcx_mesh_preprocess.argtypes = [C.c_int, C.c_int64, dp, C.c_int64, C.c_int, i64p, dp,
+                                          i64p]
+        L.vcx_solver_create.argtypes = [vp, C.POINTER(Physics), dp, C.POINTER(vp)]
+        L.vcx_solver_destroy.argtypes = [vp]
+        L.vcx_solver_nvar.argtypes = [vp]
+        L.vcx_solver_nvar.restype = C.c_int
+        L.vcx_state_upload.argtypes = [vp, vp, C.c_int]
+        L.vcx_state_download.argtypes = [vp, vp, C.c_int]
+        L.vcx_state_set_time.argtypes = [vp, C.c_double]
+        L.vcx_gradient.argtypes = [vp, vp, C.c_int]
+        L.vcx_residual.argtypes = [vp, C.c_double, vp, C.c_int]
+        L.vcx_timestep.argtypes = [vp, dp]
+        L.vcx_step.argtypes = [vp, C.c_int, C.c_double, dp, dp]
+        L.vcx_steps_done.argtypes = [vp]
+        L.vcx_steps_done.restype = C.c_int64
+        L.vcx_solve_batch.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(C.c_int), dp]
+        L.vcx_conservation_sums.argtypes = [vp, dp]
+        L.vcx_profile_enable.argtypes = [vp, C.c_int]
+        L.vcx_profile_query.argtypes = [vp, C.c_char_p, i64p, dp]
+        L.vcx_last_error.restype = C.c_char_p
+        for name in EXPORTS:
+            if name not in ("vcx_solver_nvar", "vcx_steps_done", "vcx_last_error"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(code, what):
+    if code != OK:
+        raise VcxError(code, what, lib().vcx_last_error().decode())
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _is_device_tensor(x) -> bool:
+    return hasattr(x, "is_cuda") and bool(getattr(x, "is_cuda"))
+
+
+def _ptr(x):
+    """(pointer, is_device) of a numpy array or a torch tensor."""
+    if _is_device_tensor(x):
+        import torch
+        if x.dtype != torch.float64 or not x.is_contiguous():
+            raise ValueError("device arrays must be contiguous float64 tensors")
+        return C.c_void_p(x.data_ptr()), 1
+    if not (isinstance(x, np.ndarray) and x.dtype == np.float64 and x.flags["C_CONTIGUOUS"]):
+        raise ValueError("host arrays must be C-contiguous float64 numpy arrays")
+    return C.c_void_p(x.ctypes.data), 0
+
+
+def current_stream():
+    """Handle of PyTorch's current HIP stream (0 if torch has no GPU)."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return torch.cuda.current_stream().cuda_stream
+    except Exception:
+        pass
+    return 0
+
+
+def mesh_preprocess(mesh) -> dict:
+    """Host-only dry run of the library's mesh preprocessing."""
+    xyz, cells = _f64(mesh.xyz), np.ascontiguousarray(mesh.cells, dtype=np.int64)
+    per = None if mesh.period is None else _f64(mesh.period)
+    st = np.zeros(10, dtype=np.int64)
+    _check(lib().vcx_mesh_preprocess(mesh.ndim, mesh.nnodes, _dptr(xyz), mesh.ncells, mesh.nv,
+                                     cells.ctypes.data_as(C.POINTER(C.c_int64)),
+                                     _dptr(per) if per is not None else None,
+                                     st.ctypes.data_as(C.POINTER(C.c_int64))),
+           "vcx_mesh_preprocess")
+    out = dict(zip(("nnodes", "ncells", "nfaces", "ntiles", "nslots", "nbnd", "max_tile_cells",
+                    "max_tile_nodes"), map(int, st[:8])))
+    out["vol_cells"] = float(st[8:9].view(np.float64)[0])
+    out["vol_nodes"] = float(st[9:10].view(np.float64)[0])
+    return out
+
+
+class Mesh:
+    def __init__(self, mesh, stream=None, tile_cells: int = 0, tile_nodes: int = 0):
+        L = lib()
+        self.src = mesh
+        self.ndim, self.nnodes, self.ncells = mesh.ndim, mesh.nnodes, mesh.ncells
+        self.stream = current_stream() if stream is None else stream
+        xyz, cells = _f64(mesh.xyz), np.ascontiguousarray(mesh.cells, dtype=np.int64)
+        per = None if mesh.period is None else _f64(mesh.period)
+        h = C.c_void_p()
+        _check(L.vcx_mesh_create_tiled(mesh.ndim, mesh.nnodes, _dptr(xyz), mesh.ncells, mesh.nv,
+                                       cells.ctypes.data_as(C.POINTER(C.c_int64)),
+                                       _dptr(per) if per is not None else None, int(tile_cells),
+                                       int(tile_nodes), C.c_void_p(self.stream), C.byref(h)),
+               "vcx_mesh_create_tiled")
+        self.h = h
+
+    def info(self) -> dict:
+        out = np.zeros(8, dtype=np.int64)
+        _check(lib().vcx_mesh_info(self.h, out.ctypes.data_as(C.POINTER(C.c_int64))), "vcx_mesh_info")
+        return dict(zip(("nnodes", "ncells", "nfaces", "ntiles", "nslots", "nbnd",
+                         "max_tile_cells", "max_tile_nodes"), map(int, out)))
+
+    def geometry(self):
+        Vn = np.zeros(self.nnodes)
+        Sb = np.zeros((self.ndim, self.nnodes))
+        _check(lib().vcx_mesh_geometry(self.h, _dptr(Vn), _dptr(Sb)), "vcx_mesh_geometry")
+        return Vn, Sb
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().vcx_mesh_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Solver:
+    def __init__(self, mesh: Mesh, phys: Physics, E=None):
+        self.mesh, self.phys = mesh, phys
+        Ec = None if E is None else _f64(E)
+        h = C.c_void_p()
+        _check(lib().vcx_solver_create(mesh.h, C.byref(phys), _dptr(Ec) if Ec is not None else None,
+                                       C.byref(h)), "vcx_solver_create")
+        self.h = h
+        self.nvar = lib().vcx_solver_nvar(h)
+        self.nr = self.nvar + 1 if phys.model == MODEL_GAS else self.nvar
+
+    def upload(self, U):
+        if not _is_device_tensor(U):
+            U = _f64(U)
+        p, dev = _ptr(U)
+        _check(lib().vcx_state_upload(self.h, p, dev), "vcx_state_upload")
+
+    def set_time(self, t: float):
+        _check(lib().vcx_state_set_time(self.h, float(t)), "vcx_state_set_time")
+
+    def download(self, out=None):
+        if out is None:
+            out = np.zeros((self.nvar, self.mesh.nnodes))
+        p, dev = _ptr(out)
+        _check(lib().vcx_state_download(self.h, p, dev), "vcx_state_download")
+        return out
+
+    def gradient(self, out=None):
+        if out is None:
+            out = np.zeros((self.nr, self.mesh.ndim, self.mesh.nnodes))
+        p, dev = _ptr(out)
+        _check(lib().vcx_gradient(self.h, p, dev), "vcx_gradient")
+        return out
+
+    def residual(self, dt: float = 0.0, out=None):
+        if out is None:
+            out = np.zeros((self.nvar, self.mesh.nnodes))
+        p, dev = _ptr(out)
+        _check(lib().vcx_residual(self.h, float(dt), p, dev), "vcx_residual")
+        return out
+
+    def timestep(self) -> float:
+        dt = C.c_double()
+        _check(lib().vcx_timestep(self.h, C.byref(dt)), "vcx_timestep")
+        return dt.value
+
+    def step(self, nsteps: int, t_end: float = 0.0):
+        t, dl = C.c_double(), C.c_double()
+        _check(lib().vcx_step(self.h, int(nsteps), float(t_end), C.byref(t), C.byref(dl)), "vcx_step")
+        return t.value, dl.value
+
+    def steps_done(self) -> int:
+        return int(lib().vcx_steps_done(self.h))
+
+    def sums(self):
+        out = np.zeros(self.nvar)
+        _check(lib().vcx_conservation_sums(self.h, _dptr(out)), "vcx_conservation_sums")
+        return out
+
+    def profile(self, enable: bool = True):
+        _check(lib().vcx_profile_enable(self.h, int(enable)), "vcx_profile_enable")
+
+    def profile_query(self, kernel: str):
+        n, ms = C.c_int64(), C.c_double()
+        _check(lib().vcx_profile_query(self.h, kernel.encode(), C.byref(n), C.byref(ms)),
+               "vcx_profile_query")
+        return n.value, ms.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().vcx_solver_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve_batch(solvers, nsteps, t_end):
+    n = len(solvers)
+    hs = (C.c_void_p * n)(*[s.h for s in solvers])
+    ns = (C.c_int * n)(*[int(x) for x in nsteps])
+    te = (C.c_double * n)(*[float(x) for x in t_end])
+    _check(lib().vcx_solve_batch(hs, n, ns, te), "vcx_solve_batch")

@@ -1,0 +1,126 @@
+"""Parity cases shared by the GPU tests and the smoke check: a seeded mesh, a
+seeded state, and one scheme description translated into both the oracle's
+and the library's parameter structs."""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+import oracle
+from paper_2201_01291_amd import workloads as wl
+
+LIMNAMES = {"first": 0, "minmod": 1, "vanleer": 2, "sweby": 3, "none": 4}
+
+
+@dataclass
+class Case:
+    name: str
+    mesh: object
+    U: np.ndarray
+    E: np.ndarray | None
+    scheme: dict
+
+    @property
+    def model(self):
+        return 1 if self.scheme["model"] == "dd" else 0
+
+    def oracle_phys(self):
+        s = self.scheme
+        return oracle.Phys(model=self.model, flux=1 if s.get("flux") == "roe" else 0,
+                           limiter=LIMNAMES[s["limiter"]], rk=s.get("rk", 2),
+                           nspecies=s.get("nspecies", 0), closure=s.get("closure", True),
+                           beta=s.get("beta", 1.0), cfl=s.get("cfl", 0.5),
+                           fourier=s.get("fourier", 0.25), gamma=1.4,
+                           entropy_fix=s.get("fix", 0.1), z=s.get("z", []), mu=s.get("mu", []),
+                           D=s.get("D", []))
+
+    def vcx_phys(self, precision=0):
+        from paper_2201_01291_amd import vcx
+        s = self.scheme
+        return vcx.physics(model=self.model, flux=1 if s.get("flux") == "roe" else 0,
+                           limiter=LIMNAMES[s["limiter"]], rk_stages=s.get("rk", 2),
+                           nspecies=s.get("nspecies", 0), closure=s.get("closure", True),
+                           precision=precision, beta=s.get("beta", 1.0), cfl=s.get("cfl", 0.5),
+                           fourier=s.get("fourier", 0.25), gamma=1.4,
+                           entropy_fix=s.get("fix", 0.1), z=s.get("z", []), mu=s.get("mu", []),
+                           D=s.get("D", []))
+
+
+DD2 = dict(model="dd", limiter="minmod", rk=1, nspecies=2, z=[-1.0, 1.0], mu=[0.04, 0.04],
+           D=[0.1, 0.1])
+
+
+def make_case(name: str) -> Case:
+    if name == "dd2d-streamer":
+        m = wl.dd_streamer_mesh(40, 25)
+        n, E = wl.dd_fields(m, sigma=2e-3)
+        return Case(name, m, n, E, dict(DD2))
+    if name == "dd2d-open-vanleer":
+        m = wl.tri_rect_mesh(23, 17, 0.02, 0.015, jitter=0.2, seed=9)
+        n, E = wl.dd_fields(m, sigma=3e-3, seed=4)
+        return Case(name, m, n, E, dict(DD2, limiter="vanleer"))
+    if name == "dd3d-sweby":
+        m = wl.kuhn_tet_mesh(5, 5, 6, 1e-3, 1e-3, 1.2e-3, jitter=0.1, seed=3)
+        n, E = wl.dd_fields(m, sigma=3e-4, bump_sigma=2e-4, bump_amp=50.0, nspecies=1)
+        return Case(name, m, n, E, dict(model="dd", limiter="sweby", beta=1.5, rk=1, nspecies=1,
+                                        z=[-1.0], mu=[0.04], D=[0.1]))
+    if name == "sod-hllc":
+        m = wl.sod_tube(100, 10)
+        return Case(name, m, wl.sod_state(m), None,
+                    dict(model="gas", flux="hllc", limiter="minmod", rk=2))
+    if name == "euler2d-roe-sp2":
+        m = wl.tri_rect_mesh(20, 16, jitter=0.2, seed=5, periodic=True)
+        U = wl.euler_blob_state(m, nblobs=4, amp=0.3, sigma=0.15, nspecies=2)
+        return Case(name, m, U, None,
+                    dict(model="gas", flux="roe", limiter="vanleer", rk=2, nspecies=2))
+    if name == "euler3d-roe":
+        m = wl.kuhn_tet_mesh(7, 6, 6, jitter=0.1, seed=11)
+        U = wl.euler_blob_state(m, nblobs=8, amp=0.1, sigma=0.2)
+        return Case(name, m, U, None, dict(model="gas", flux="roe", limiter="vanleer", rk=2))
+    if name == "euler3d-hllc-open-sp2":
+        m = wl.kuhn_tet_mesh(4, 4, 5, jitter=0.15, seed=2, periodic=False)
+        U = wl.euler_blob_state(m, nblobs=3, amp=0.4, sigma=0.3, nspecies=2, mach=0.6)
+        return Case(name, m, U, None, dict(model="gas", flux="hllc", limiter="sweby", beta=1.5,
+                                           rk=3, nspecies=2))
+    if name == "euler3d-hllc-sp9":
+        m = wl.kuhn_tet_mesh(5, 5, 5, jitter=0.1, seed=6)
+        U = wl.euler_blob_state(m, nblobs=4, amp=0.2, sigma=0.25, nspecies=9)
+        return Case(name, m, U, None, dict(model="gas", flux="hllc", limiter="minmod", rk=4,
+                                           nspecies=9))
+    raise KeyError(name)
+
+
+CASE_NAMES = ["dd2d-streamer", "dd2d-open-vanleer", "dd3d-sweby", "sod-hllc", "euler2d-roe-sp2",
+              "euler3d-roe", "euler3d-hllc-open-sp2", "euler3d-hllc-sp9"]
+
+
+def reconstructed(case: Case) -> np.ndarray:
+    """W = (U, p) for gas, U for drift-diffusion (test-side input preparation)."""
+    if case.model == 1:
+        return case.U
+    nd = case.mesh.ndim
+    rho = case.U[0]
+    ke = 0.5 * np.sum(case.U[1:1 + nd] ** 2, axis=0) / rho
+    p = 0.4 * (case.U[1 + nd] - ke)
+    return np.vstack([case.U, p[None]])
+
+
+def normwise(a, b, scale):
+    """max_i |a - b| / max_i scale, per variable (rows)."""
+    num = np.abs(a - b).reshape(a.shape[0], -1).max(axis=1)
+    den = np.abs(scale).reshape(scale.shape[0], -1).max(axis=1)
+    den = np.where(den > 0, den, np.abs(scale).max())   # rows that are zero everywhere
+    return num / den
+
+
+def state_err(case: Case, Ua, Ub):
+    """Norm-wise state difference per variable, max_i |Ua - Ub| / max_i |Ub|,
+    with the momentum components normalised by the largest momentum
+    component (a vector quantity: its scale does not depend on the axes)."""
+    den = np.abs(Ub).max(axis=1)
+    if case.model == 0:
+        nd = case.mesh.ndim
+        den[1:1 + nd] = den[1:1 + nd].max()
+    den = np.where(den > 0, den, np.abs(Ub).max())
+    return np.abs(Ua - Ub).max(axis=1) / den

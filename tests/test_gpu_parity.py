@@ -1,0 +1,211 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle on
+the same seeded inputs.
+
+Bar: FP64 path within 1e-12 norm-wise -- max_i |r_gpu - r_oracle| divided by
+max_i sum_f |F_f . S_f| (per variable), the survey's residual norm, since a
+residual is a difference of face fluxes and can vanish where the fluxes do
+not.  States after N steps: max |dU| / max |U| <= 1e-12 per variable.
+Mixed precision (FP32 flux) errors are measured and printed; the bound
+asserted for them is stated in each test.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from cases import CASE_NAMES, make_case, normwise, reconstructed, state_err
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2201_01291_amd import vcx  # noqa: E402
+
+FP64_TOL = 1e-12
+
+
+def _setup(case, precision=0):
+    print(f"[case] {case.name} prec={precision} nn={case.mesh.nnodes} nc={case.mesh.ncells}",
+          flush=True)
+    om = oracle.OracleMesh(case.mesh)
+    gm = vcx.Mesh(case.mesh)
+    s = vcx.Solver(gm, case.vcx_phys(precision), case.E)
+    s.upload(case.U)
+    return om, gm, s
+
+
+@pytest.mark.parametrize("name", CASE_NAMES)
+def test_gradient_parity(name):
+    case = make_case(name)
+    om, gm, s = _setup(case)
+    W = reconstructed(case)
+    Go = om.gradient(W)
+    Gg = s.gradient()
+    h = (case.mesh.ncells / om.geometry()["Vc"].sum()) ** (1.0 / case.mesh.ndim)
+    scale = np.abs(W).max(axis=1) * h
+    scale = np.where(scale > 0, scale, np.abs(W).max() * h)   # rows that are zero everywhere
+    err = np.abs(Gg - Go).max(axis=(1, 2)) / scale
+    print("gradient err", err)
+    assert err.max() <= FP64_TOL
+
+
+@pytest.mark.parametrize("name", CASE_NAMES)
+def test_residual_parity_fp64(name):
+    case = make_case(name)
+    om, gm, s = _setup(case)
+    ph = case.oracle_phys()
+    dt = om.timestep(ph, case.U, case.E)
+    ro = om.residual(ph, case.U, case.E, dt)
+    rg = s.residual(dt)
+    err = normwise(rg, ro, om.flux_scale(ph, case.U, case.E, dt))
+    print("residual err", err)
+    assert err.max() <= FP64_TOL
+
+
+@pytest.mark.parametrize("name", CASE_NAMES)
+def test_residual_mixed_precision_error_stated(name):
+    """FP32 reconstruction/limiter/flux with FP64 accumulation: error against
+    the FP64 oracle is printed; asserted bound 1e-4 norm-wise (FP32 epsilon
+    1.2e-7 times the flux cancellation of a few cell-edges)."""
+    case = make_case(name)
+    om, gm, s = _setup(case, precision=1)
+    ph = case.oracle_phys()
+    dt = om.timestep(ph, case.U, case.E)
+    ro = om.residual(ph, case.U, case.E, dt)
+    rg = s.residual(dt)
+    err = normwise(rg, ro, om.flux_scale(ph, case.U, case.E, dt))
+    print(f"MIXED residual err {name}: {err}")
+    assert err.max() <= 1e-4
+
+
+@pytest.mark.parametrize("name", CASE_NAMES)
+def test_timestep_parity(name):
+    case = make_case(name)
+    om, gm, s = _setup(case)
+    assert s.timestep() == pytest.approx(om.timestep(case.oracle_phys(), case.U, case.E), rel=1e-13)
+
+
+@pytest.mark.parametrize("name", CASE_NAMES)
+def test_step_parity_fp64(name):
+    case = make_case(name)
+    om, gm, s = _setup(case)
+    ph = case.oracle_phys()
+    Uo, to, dto, no = om.step(ph, case.U, case.E, nsteps=5)
+    tg, dtg = s.step(5)
+    Ug = s.download()
+    assert s.steps_done() == 5 and no == 5
+    assert tg == pytest.approx(to, rel=1e-12) and dtg == pytest.approx(dto, rel=1e-12)
+    err = state_err(case, Ug, Uo)
+    print("state err", err)
+    assert err.max() <= FP64_TOL
+
+
+@pytest.mark.parametrize("name", ["euler3d-roe", "dd2d-streamer", "euler2d-roe-sp2"])
+def test_conservation_sums(name):
+    case = make_case(name)
+    om, gm, s = _setup(case)
+    so, ao = om.sums(case.U)
+    sg = s.sums()
+    np.testing.assert_allclose(sg, so, rtol=0, atol=1e-13 * ao.max())
+    s.step(10)
+    sg2 = s.sums()
+    drift = np.abs(sg2 - sg) / np.maximum(ao, 1e-300)
+    print("conservation drift", drift)
+    assert np.all((drift <= 1e-13) | (ao == 0))
+
+
+@pytest.mark.parametrize("name", ["euler3d-roe", "dd2d-streamer", "sod-hllc"])
+def test_bitwise_determinism(name):
+    case = make_case(name)
+    om, gm, s = _setup(case)
+    r1 = s.residual(1e-12)
+    r2 = s.residual(1e-12)
+    assert np.array_equal(r1, r2)
+    s.step(3)
+    U1 = s.download()
+    s.upload(case.U)
+    s.step(3)
+    assert np.array_equal(s.download(), U1)
+    # an independent solver on an independent mesh object gives the same bits
+    s2 = vcx.Solver(vcx.Mesh(case.mesh), case.vcx_phys(), case.E)
+    s2.upload(case.U)
+    s2.step(3)
+    assert np.array_equal(s2.download(), U1)
+
+
+def test_device_pointer_io():
+    case = make_case("euler3d-roe")
+    om, gm, s = _setup(case)
+    r_host = s.residual()
+    Ud = torch.tensor(case.U, device="cuda", dtype=torch.float64)
+    s.upload(Ud)
+    rd = torch.empty_like(Ud)
+    s.residual(out=rd)
+    torch.cuda.synchronize()
+    assert np.array_equal(rd.cpu().numpy(), r_host)
+    out = torch.zeros_like(Ud)
+    s.download(out=out)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), case.U)
+
+
+def test_shock_tube_to_t_end_matches_oracle():
+    """The shock-tube workload (100x10 tube, HLLC-minmod-RK2, CFL 0.5) run to
+    t = 0.2 on the GPU: every step's dt and the final state against the oracle."""
+    case = make_case("sod-hllc")
+    om, gm, s = _setup(case)
+    ph = case.oracle_phys()
+    Uo, to, _, no = om.step(ph, case.U, nsteps=100000, t_end=0.2)
+    tg, _ = s.step(100000, t_end=0.2)
+    assert s.steps_done() == no and tg == pytest.approx(0.2, abs=1e-14)
+    err = state_err(case, s.download(), Uo)
+    print("sod state err", err, "steps", no)
+    assert err.max() <= FP64_TOL
+
+
+def test_unstable_state_is_reported_and_state_kept():
+    case = make_case("euler2d-roe-sp2")
+    U = case.U.copy()
+    U[3, 17] = 1e-3  # energy below kinetic energy: negative pressure
+    om, gm, s = _setup(case)
+    s.upload(U)
+    with pytest.raises(vcx.VcxError) as e:
+        s.step(2)
+    assert e.value.code == vcx.E_UNSTABLE
+    assert s.steps_done() == 0
+    assert np.array_equal(s.download(), U)
+
+
+def test_unstable_after_good_steps_keeps_last_good_state():
+    """A blow-up in a later step leaves the state of the last good step."""
+    case = make_case("dd2d-streamer")
+    om, gm, s = _setup(case)
+    s.step(2)
+    U2 = s.download()
+    bad = U2.copy()
+    bad[0, 5] = np.nan
+    s.upload(bad)
+    with pytest.raises(vcx.VcxError):
+        s.step(3)
+    assert s.steps_done() == 0
+    np.testing.assert_array_equal(np.isnan(s.download()), np.isnan(bad))
+
+
+def test_full_size_drift_diffusion_residual_and_steps():
+    """The 200k-cell jittered drift-diffusion workload at full size: residual
+    and 3 steps against the oracle (the oracle handles 6e5 faces quickly)."""
+    from paper_2201_01291_amd import workloads as wl
+    import cases
+    m = wl.dd_streamer_mesh()
+    n, E = wl.dd_fields(m)
+    case = cases.Case("dd2d-full", m, n, E, dict(cases.DD2))
+    om, gm, s = _setup(case)
+    ph = case.oracle_phys()
+    dt = om.timestep(ph, n, E)
+    assert s.timestep() == pytest.approx(dt, rel=1e-13)
+    err = normwise(s.residual(dt), om.residual(ph, n, E, dt), om.flux_scale(ph, n, E, dt))
+    assert err.max() <= FP64_TOL
+    Uo, *_ = om.step(ph, n, E, nsteps=3)
+    s.step(3)
+    assert state_err(case, s.download(), Uo).max() <= FP64_TOL
