@@ -164,7 +164,7 @@ def main():
         s64.upload(U0)
         s64.profile(True)
         s64.step(a.steps)
-        for k in ("dt", "gradient", "gradient_gather", "flux", "update"):
+        for k in ("gradient", "flux", "update"):
             n, ms = s64.profile_query(k)
             if n:
                 kern[k] = dict(launches=n, avg_us=ms / n * 1e3)

@@ -197,9 +197,11 @@ vcx_status vcx_solve_batch(vcx_solver *s, int n, const int *nsteps, const double
 vcx_status vcx_conservation_sums(vcx_solver s, double *sums);
 
 /* Per-kernel timing with HIP events on the solver's stream.  enable = 1 turns
- * it on and clears the counters.  Kernel names: "dt", "gradient",
- * "gradient_gather", "flux", "update".  count = launches timed, total_ms = sum
- * of their durations. */
+ * it on and clears the counters.  Kernel names: "gradient" (gradient tile
+ * pass; its first launch of a step also reduces the time step), "flux" (flux
+ * tile pass with the update of nodes owned by one tile), "update" (update of
+ * nodes shared by several tiles), "node_dt", "gradient_shared".  count =
+ * launches timed, total_ms = sum of their durations. */
 vcx_status vcx_profile_enable(vcx_solver s, int enable);
 vcx_status vcx_profile_query(vcx_solver s, const char *kernel, int64_t *count, double *total_ms);
 

@@ -63,6 +63,9 @@ struct vcx_solver_s {
   double* rbuf = nullptr;  // [max(nr*nd, nvar)][nn] internal order
   DevScalars* sc = nullptr;
   DevScalars* sc_host = nullptr;  // pinned mirror
+  double* dtp_node = nullptr;     // dt candidates of the node pass
+  double* dtp_step = nullptr;     // dt candidates of the step kernels
+  int n_dtp_node = 0, n_dtp_step = 0, nsh_blocks = 1;
   double* part = nullptr;
   double* sums_dev = nullptr;
   double* sums_host = nullptr;     // pinned
@@ -136,14 +139,31 @@ static vcx_status harvest(vcx_solver s) {
 // ---------------------------------------------------------------------------
 
 struct KernelTable {
-  vcx_status (*grad)(vcx_solver, const double* Win, const DevScalars* sc);
-  vcx_status (*flux)(vcx_solver, const double* Win, const double* dt_dev, double dt_host,
-                     const DevScalars* sc);
-  vcx_status (*update)(vcx_solver, const UpdateArgs&, Sched, DevScalars* sc);
+  vcx_status (*grad)(vcx_solver, const double* Win, const GradCtl& gc);
+  vcx_status (*grad_complete)(vcx_solver);
+  vcx_status (*flux)(vcx_solver, const double* Win, const Finish& f, double dt_host);
+  vcx_status (*update_shared)(vcx_solver, const Finish& f);
+  vcx_status (*node_dt)(vcx_solver, const double* W);
   size_t (*lds_grad)(int maxn, int maxc);
   size_t (*lds_flux)(int maxn, int maxc);
   vcx_status (*allow_lds)(size_t grad_bytes, size_t flux_bytes);
 };
+
+static DtParts dt_parts(vcx_solver s) {
+  return DtParts{s->dtp_node, s->n_dtp_node, s->dtp_step, s->n_dtp_step};
+}
+
+static DtCoef dt_coef(const vcx_physics& ph) {
+  DtCoef c{};
+  c.cfl = ph.cfl;
+  c.fourier = ph.fourier;
+  c.gamma = ph.gamma;
+  for (int k = 0; k < 4 && k < ph.nspecies; ++k) {
+    c.zmu[k] = ph.z[k] * ph.mu[k];
+    c.D[k] = ph.D[k];
+  }
+  return c;
+}
 
 template <int MODEL, int ND, int NSP, int FLUX, typename CT>
 struct Impl {
@@ -159,29 +179,31 @@ struct Impl {
     size_t ct = MODEL == 0 ? (size_t)(NR + NR * ND) * maxn : (size_t)(NSP + NSP * ND + ND) * maxn;
     return dbl + sizeof(CT) * ct;
   }
-  static vcx_status grad(vcx_solver s, const double* Win, const DevScalars* sc) {
+  static vcx_status grad(vcx_solver s, const double* Win, const GradCtl& gc) {
     const DevMesh& m = s->mesh->d;
-    hipStream_t st = s->mesh->stream;
-    VCX_TRY(launch(s, "gradient", [&] {
+    return launch(s, "gradient", [&] {
       hipLaunchKernelGGL((k_grad_tile<ND, NR>), dim3(xcd_grid(m.ntiles)), dim3(s->tile_block),
-                         s->lds_grad, st, m, Win, s->PG, sc);
-    }));
-    VCX_TRY(launch(s, "gradient_gather", [&] {
-      hipLaunchKernelGGL((k_grad_gather<ND, NR>), dim3((m.nn + kNodeBlock - 1) / kNodeBlock),
-                         dim3(kNodeBlock), 0, st, m, (const double*)s->PG, s->G, sc);
-    }));
-    return VCX_OK;
+                         s->lds_grad, s->mesh->stream, m, Win, s->G, s->PG, gc);
+    });
   }
-  static vcx_status flux(vcx_solver s, const double* Win, const double* dt_dev, double dt_host,
-                         const DevScalars* sc) {
+  static vcx_status grad_complete(vcx_solver s) {
+    const DevMesh& m = s->mesh->d;
+    if (m.nshared == 0) return VCX_OK;
+    return launch(s, "gradient_shared", [&] {
+      hipLaunchKernelGGL((k_grad_shared<ND, NR>), dim3((m.nshared + kNodeBlock - 1) / kNodeBlock),
+                         dim3(kNodeBlock), 0, s->mesh->stream, m, (const double*)s->PG, s->G);
+    });
+  }
+  static vcx_status flux(vcx_solver s, const double* Win, const Finish& f, double dt_host) {
     const DevMesh& m = s->mesh->d;
     hipStream_t st = s->mesh->stream;
+    DtParts parts = dt_parts(s);
     if constexpr (MODEL == 0) {
       GasParams gp{s->ph.gamma, s->ph.beta, s->ph.entropy_fix, s->ph.limiter};
       return launch(s, "flux", [&] {
         hipLaunchKernelGGL((k_flux_gas<ND, NSP, FLUX, CT>), dim3(xcd_grid(m.ntiles)),
                            dim3(s->tile_block), s->lds_flux, st, m, Win, (const double*)s->G,
-                           s->PR, gp, sc);
+                           s->PR, gp, f, parts);
       });
     } else {
       DDParams pp{};
@@ -191,21 +213,29 @@ struct Impl {
       }
       pp.beta = s->ph.beta;
       pp.dt_host = dt_host;
-      pp.dt_dev = dt_dev;
       pp.limiter = s->ph.limiter;
       return launch(s, "flux", [&] {
         hipLaunchKernelGGL((k_flux_dd<ND, NSP, CT>), dim3(xcd_grid(m.ntiles)),
                            dim3(s->tile_block), s->lds_flux, st, m, Win, (const double*)s->G,
-                           (const double*)s->E, s->PR, pp, sc);
+                           s->PR, pp, f, parts);
       });
     }
   }
-  static vcx_status update(vcx_solver s, const UpdateArgs& ua, Sched sd, DevScalars* sc) {
+  static vcx_status update_shared(vcx_solver s, const Finish& f) {
     const DevMesh& m = s->mesh->d;
-    hipStream_t st = s->mesh->stream;
+    DtParts parts = dt_parts(s);
     return launch(s, "update", [&] {
-      hipLaunchKernelGGL((k_update<ND, NSP, MODEL>), dim3((m.nn + kNodeBlock - 1) / kNodeBlock),
-                         dim3(kNodeBlock), 0, st, m, ua, sd, sc);
+      hipLaunchKernelGGL((k_update_shared<ND, NSP, MODEL>), dim3(s->nsh_blocks), dim3(kNodeBlock), 0,
+                         s->mesh->stream, m, (const double*)s->PR, f, parts);
+    });
+  }
+  static vcx_status node_dt(vcx_solver s, const double* W) {
+    const DevMesh& m = s->mesh->d;
+    DtParts parts = dt_parts(s);
+    DtCoef dc = dt_coef(s->ph);
+    return launch(s, "node_dt", [&] {
+      hipLaunchKernelGGL((k_node_dt<ND, NSP, MODEL>), dim3(s->n_dtp_node), dim3(kNodeBlock), 0,
+                         s->mesh->stream, m, W, (const double*)s->E, dc, parts, s->sc);
     });
   }
   // Allow dynamic LDS above the 64 KiB default for the two tile kernels.
@@ -221,7 +251,8 @@ struct Impl {
     return VCX_OK;
   }
   static const KernelTable* table() {
-    static const KernelTable t{&grad, &flux, &update, &lds_grad, &lds_flux, &allow_lds};
+    static const KernelTable t{&grad, &grad_complete, &flux, &update_shared, &node_dt,
+                               &lds_grad, &lds_flux, &allow_lds};
     return &t;
   }
 };
@@ -368,11 +399,36 @@ extern "C" vcx_status vcx_mesh_create_tiled(int ndim, int64_t nnodes, const doub
   chk(upload(m, h.inc, &d.inc));
   chk(upload(m, h.node_slot, &d.node_slot));
   chk(upload(m, h.slots_of, &d.slots_of));
+  chk(upload(m, h.shared, &d.shared));
+  {
+    const int32_t* run = nullptr;
+    chk(upload(m, h.slot_run, &run));
+    d.slot_run = reinterpret_cast<const int2*>(run);
+  }
+  d.nshared = (int)h.shared.size();
   chk(upload(m, inv, &d.inv_vol));
   chk(upload(m, h.vnode, &d.vnode));
   chk(upload(m, bidx, &d.bnd_index));
   chk(upload(m, h.bnd_S, &d.bnd_S));
   chk(upload(m, h.perm, &d.perm));
+  if (st == VCX_OK) {
+    // smallest inscribed diameter of the cells around each node (time step)
+    void* p = nullptr;
+    if (hipMalloc(&p, sizeof(double) * h.nn) != hipSuccess) {
+      st = fail(VCX_E_OOM, "hipMalloc failed for mesh arrays");
+    } else {
+      m->allocs.push_back(p);
+      d.dxmin = static_cast<const double*>(p);
+      auto* bits = static_cast<unsigned long long*>(p);
+      if (hipMemsetAsync(p, 0xFF, sizeof(double) * h.nn, m->stream) != hipSuccess)
+        st = fail(VCX_E_HIP, "hipMemsetAsync failed");
+      else if (d.nd == 2)
+        hipLaunchKernelGGL(k_cell_dx<2>, dim3((d.nc + 255) / 256), dim3(256), 0, m->stream, d, bits);
+      else
+        hipLaunchKernelGGL(k_cell_dx<3>, dim3((d.nc + 255) / 256), dim3(256), 0, m->stream, d, bits);
+      if (st == VCX_OK && hipGetLastError() != hipSuccess) st = fail(VCX_E_HIP, "k_cell_dx launch failed");
+    }
+  }
   if (st == VCX_OK && hipStreamSynchronize(m->stream) != hipSuccess)
     st = fail(VCX_E_HIP, "mesh upload failed");
   if (st != VCX_OK) {
@@ -424,7 +480,7 @@ extern "C" vcx_status vcx_mesh_geometry(vcx_mesh m, double* Vn, double* Sb) {
 static void free_solver(vcx_solver s) {
   if (!s) return;
   for (double* p : {s->W[0], s->W[1], s->G, s->PG, s->PR, s->E, s->io, s->rbuf, s->part,
-                    s->sums_dev})
+                    s->sums_dev, s->dtp_node, s->dtp_step})
     if (p) (void)hipFree(p);
   if (s->sc) (void)hipFree(s->sc);
   if (s->sc_host) (void)hipHostFree(s->sc_host);
@@ -444,13 +500,15 @@ static vcx_status dmalloc(double** p, size_t n) {
   return VCX_OK;
 }
 
-static vcx_status reset_scalars(vcx_solver s, double t0) {
+// Reset the time loop to t0 and compute the time-step candidates of the
+// current state (consumed by the first step).
+static vcx_status reset_scalars(vcx_solver s, double t0, bool prime) {
   DevScalars z{};
   z.t = t0;
-  z.dtmin = 0x7FF0000000000000ull;
   *s->sc_host = z;
   VCX_HIP(hipMemcpyAsync(s->sc, s->sc_host, sizeof(DevScalars), hipMemcpyHostToDevice,
                          s->mesh->stream));
+  if (prime) VCX_TRY(s->kt->node_dt(s, s->W[s->cur]));
   VCX_HIP(hipStreamSynchronize(s->mesh->stream));
   s->host_flag = 0;
   s->steps_total = 0;
@@ -521,6 +579,11 @@ extern "C" vcx_status vcx_solver_create(vcx_mesh mesh, const vcx_physics* phys, 
   chk(dmalloc(&s->rbuf, rows_io * nn));
   chk(dmalloc(&s->part, (size_t)s->nr * 256));
   chk(dmalloc(&s->sums_dev, (size_t)s->nr));
+  s->n_dtp_node = (int)((nn + kNodeBlock - 1) / kNodeBlock);
+  s->nsh_blocks = std::max(1, (d.nshared + kNodeBlock - 1) / kNodeBlock);
+  s->n_dtp_step = d.ntiles + s->nsh_blocks;
+  chk(dmalloc(&s->dtp_node, (size_t)s->n_dtp_node));
+  chk(dmalloc(&s->dtp_step, (size_t)s->n_dtp_step));
   if (st == VCX_OK && hipMalloc(reinterpret_cast<void**>(&s->sc), sizeof(DevScalars)) != hipSuccess)
     st = fail(VCX_E_OOM, "hipMalloc failed");
   if (st == VCX_OK &&
@@ -544,7 +607,7 @@ extern "C" vcx_status vcx_solver_create(vcx_mesh mesh, const vcx_physics* phys, 
       }
     }
   }
-  if (st == VCX_OK) st = reset_scalars(s, 0.0);
+  if (st == VCX_OK) st = reset_scalars(s, 0.0, false);
   if (st != VCX_OK) {
     free_solver(s);
     return st;
@@ -596,15 +659,14 @@ extern "C" vcx_status vcx_state_upload(vcx_solver s, const double* U, int is_dev
                        s->W[s->cur], d.nn, d.nd, s->ph.nspecies, s->ph.gamma);
     VCX_HIP(hipGetLastError());
   }
-  VCX_TRY(reset_scalars(s, 0.0));
   s->has_state = true;
-  return VCX_OK;
+  return reset_scalars(s, 0.0, true);
 }
 
 extern "C" vcx_status vcx_state_set_time(vcx_solver s, double t) {
   if (!s) return fail(VCX_E_ARG, "NULL solver");
   if (!s->has_state) return fail(VCX_E_STATE, "no state uploaded");
-  return reset_scalars(s, t);
+  return reset_scalars(s, t, true);
 }
 
 extern "C" vcx_status vcx_state_download(vcx_solver s, double* U, int is_device) {
@@ -616,65 +678,35 @@ extern "C" vcx_status vcx_state_download(vcx_solver s, double* U, int is_device)
 extern "C" vcx_status vcx_gradient(vcx_solver s, double* G, int is_device) {
   if (!s || !G) return fail(VCX_E_ARG, "NULL argument");
   if (!s->has_state) return fail(VCX_E_STATE, "no state uploaded");
-  VCX_TRY(s->kt->grad(s, s->W[s->cur], nullptr));
+  GradCtl gc{nullptr, dt_parts(s), 0};
+  VCX_TRY(s->kt->grad(s, s->W[s->cur], gc));
+  VCX_TRY(s->kt->grad_complete(s));
   return copy_out(s, s->G, (size_t)s->nr * s->nd, G, is_device);
 }
 
-static UpdateArgs make_update_args(vcx_solver s) {
-  UpdateArgs ua{};
-  ua.PR = s->PR;
-  ua.G = s->G;
-  ua.E = s->E;
-  ua.gamma = s->ph.gamma;
-  for (int k = 0; k < 4 && k < s->ph.nspecies; ++k) {
-    ua.zmu[k] = s->ph.z[k] * s->ph.mu[k];
-    ua.D[k] = s->ph.D[k];
-  }
-  ua.closure = s->ph.closure;
-  return ua;
+static Finish make_finish(vcx_solver s) {
+  Finish f{};
+  f.G = s->G;
+  f.PG = s->PG;
+  f.E = s->E;
+  f.dc = dt_coef(s->ph);
+  f.closure = s->ph.closure;
+  return f;
 }
 
 extern "C" vcx_status vcx_residual(vcx_solver s, double dt, double* r, int is_device) {
   if (!s || !r) return fail(VCX_E_ARG, "NULL argument");
   if (!s->has_state) return fail(VCX_E_STATE, "no state uploaded");
   const double* Win = s->W[s->cur];
-  VCX_TRY(s->kt->grad(s, Win, nullptr));
-  VCX_TRY(s->kt->flux(s, Win, nullptr, dt, nullptr));
-  UpdateArgs ua = make_update_args(s);
-  ua.Win = Win;
-  ua.rout = s->rbuf;
-  Sched sd{0.0, 0, 1};
-  VCX_TRY(s->kt->update(s, ua, sd, nullptr));
+  GradCtl gc{nullptr, dt_parts(s), 0};
+  VCX_TRY(s->kt->grad(s, Win, gc));
+  Finish f = make_finish(s);
+  f.Win = Win;
+  f.rout = s->rbuf;
+  f.residual_only = 1;
+  VCX_TRY(s->kt->flux(s, Win, f, dt));
+  VCX_TRY(s->kt->update_shared(s, f));
   return copy_out(s, s->rbuf, s->nvar, r, is_device);
-}
-
-static DtParams make_dt_params(vcx_solver s, int query) {
-  DtParams dp{};
-  dp.model = s->ph.model;
-  dp.cfl = s->ph.cfl;
-  dp.fourier = s->ph.fourier;
-  dp.gamma = s->ph.gamma;
-  dp.nspecies = s->ph.nspecies;
-  for (int k = 0; k < 4 && k < s->ph.nspecies; ++k) {
-    dp.vmax_coef[k] = std::fabs(s->ph.z[k] * s->ph.mu[k]);
-    dp.D[k] = s->ph.D[k];
-  }
-  dp.query = query;
-  return dp;
-}
-
-static vcx_status launch_dt(vcx_solver s, int query) {
-  const DevMesh& m = s->mesh->d;
-  DtParams dp = make_dt_params(s, query);
-  const double* Win = s->W[s->cur];
-  return launch(s, "dt", [&] {
-    if (s->nd == 2)
-      hipLaunchKernelGGL(k_dt<2>, dim3((m.nc + 255) / 256), dim3(256), 0, s->mesh->stream, m, Win,
-                         (const double*)s->E, dp, s->sc);
-    else
-      hipLaunchKernelGGL(k_dt<3>, dim3((m.nc + 255) / 256), dim3(256), 0, s->mesh->stream, m, Win,
-                         (const double*)s->E, dp, s->sc);
-  });
 }
 
 static vcx_status read_scalars(vcx_solver s) {
@@ -687,7 +719,9 @@ static vcx_status read_scalars(vcx_solver s) {
 extern "C" vcx_status vcx_timestep(vcx_solver s, double* dt) {
   if (!s || !dt) return fail(VCX_E_ARG, "NULL argument");
   if (!s->has_state) return fail(VCX_E_STATE, "no state uploaded");
-  VCX_TRY(launch_dt(s, 1));
+  VCX_TRY(s->kt->node_dt(s, s->W[s->cur]));
+  hipLaunchKernelGGL(k_dt_query, dim3(1), dim3(256), 0, s->mesh->stream, s->sc, dt_parts(s));
+  VCX_HIP(hipGetLastError());
   VCX_TRY(read_scalars(s));
   *dt = s->sc_host->dt_query;
   if (!(*dt > 0.0)) return fail(VCX_E_UNSTABLE, "non-physical state: no valid time step");
@@ -706,23 +740,28 @@ static const double RK_ALPHA[5][5] = {
     {0, 0, 1.0 / 4.0, 1.0 / 3.0, 1.0 / 2.0},
 };
 
-// Enqueue one time step (dt, then K stages) on the solver's stream.
+// Enqueue one time step on the solver's stream: K stages of (gradient tile
+// pass, flux tile pass, shared-node update).  The first gradient pass also
+// reduces the previous pass's time-step candidates and commits the previous
+// step; the last stage produces the candidates of the next step.
 static vcx_status enqueue_step(vcx_solver s) {
-  VCX_TRY(launch_dt(s, 0));
   const int K = s->ph.rk_stages;
   double* Wn = s->W[s->cur];
   double* Wk = s->W[1 - s->cur];
-  UpdateArgs ua = make_update_args(s);
+  Finish f = make_finish(s);
+  f.sc = s->sc;
+  f.Un = Wn;
+  f.Wout = Wk;
   for (int k = 1; k <= K; ++k) {
     const double* Win = k == 1 ? Wn : Wk;
-    VCX_TRY(s->kt->grad(s, Win, s->sc));
-    VCX_TRY(s->kt->flux(s, Win, &s->sc->dt, 0.0, s->sc));
-    ua.Win = Win;
-    ua.Un = Wn;
-    ua.Wout = Wk;
+    GradCtl gc{s->sc, dt_parts(s), k == 1 ? 1 : 0};
+    VCX_TRY(s->kt->grad(s, Win, gc));
     // stage k of K uses alpha_{k+1}; the last one is the full update
-    Sched sd{k < K ? RK_ALPHA[K][k + 1] : 1.0, k == K ? 1 : 0, 0};
-    VCX_TRY(s->kt->update(s, ua, sd, s->sc));
+    f.Win = Win;
+    f.alpha = k < K ? RK_ALPHA[K][k + 1] : 1.0;
+    f.final_stage = k == K ? 1 : 0;
+    VCX_TRY(s->kt->flux(s, Win, f, 0.0));
+    VCX_TRY(s->kt->update_shared(s, f));
   }
   s->cur = 1 - s->cur;
   return VCX_OK;

@@ -4,8 +4,9 @@
 //   W   [nr][nn]       reconstructed variables (gas: conserved + pressure;
 //                      drift-diffusion: densities)
 //   G   [nr*nd][nn]    nodal gradients, component v*nd + d
-//   PG  [nr*nd][P]     gradient partial sums, one per (tile, node) slot
-//   PR  [nvar][P]      residual partial sums per slot
+//   PG  [P][nr*nd]     gradient partial sums, one per (tile, node) slot (slot-major,
+//                      so gathering a node's partials touches one segment per slot)
+//   PR  [P][nvar]      residual partial sums per slot
 // Per step: dt -> K x (gradient tile pass, gradient gather, flux tile pass,
 // gather + closure + RK stage update).  No floating-point atomics: every sum
 // is taken in a fixed order (cells of a tile in curve order, then slots of a
@@ -20,48 +21,62 @@ namespace vcx {
 
 constexpr int NXCD = 8;  // MI355X: 8 accelerator complex dies, round-robin dispatch
 
+// Minimum waves per SIMD requested for the flux tile kernels (0: compiler
+// default).  Higher occupancy hides more memory latency but may spill.
+#ifndef VCX_FLUX_WAVES
+#define VCX_FLUX_WAVES 0
+#endif
+#if VCX_FLUX_WAVES > 0
+#define VCX_FLUX_BOUNDS __launch_bounds__(256, VCX_FLUX_WAVES)
+#else
+#define VCX_FLUX_BOUNDS __launch_bounds__(256)
+#endif
+
 struct DevMesh {
-  int nd, nv, nn, nc, ntiles, nslots, nb;
+  int nd, nv, nn, nc, ntiles, nslots, nb, nshared;
   int max_tile_cells, max_tile_nodes;
   double period[3];
-  const double* x;          // [nd][nn]
-  const int32_t* cell;      // [nv][nc]
-  const uint32_t* shift;    // [nc]
-  const uint16_t* lconn;    // [nv][nc]
-  const int32_t* tile_cell; // [T+1]
-  const int32_t* tile_slot; // [T+1]
-  const int32_t* slot_node; // [P]
-  const int32_t* slot_inc;  // [P+1]
-  const uint16_t* inc;      // [nc*nv]
-  const int32_t* node_slot; // [nn+1]
-  const int32_t* slots_of;  // [P]
-  const double* inv_vol;    // [nn]
-  const double* vnode;      // [nn]
-  const int32_t* bnd_index; // [nn] -1 or index into bnd_S
-  const double* bnd_S;      // [nd][nb]
-  const int32_t* perm;      // [nn] internal -> caller
+  const double* x;           // [nd][nn]
+  const int32_t* cell;       // [nv][nc]
+  const uint32_t* shift;     // [nc]
+  const uint16_t* lconn;     // [nv][nc]
+  const int32_t* tile_cell;  // [T+1]
+  const int32_t* tile_slot;  // [T+1]
+  const int32_t* slot_node;  // [P] node id, or ~node when the node has slots in other tiles
+  const int32_t* slot_inc;   // [P+1]
+  const uint16_t* inc;       // [nc*nv]
+  const int32_t* node_slot;  // [nn+1]
+  const int32_t* slots_of;   // [P]
+  const int2* slot_run;      // [P] [begin, end) of the slot's node run in slots_of
+  const int32_t* shared;     // [nshared] nodes with more than one slot (ascending)
+  const double* inv_vol;     // [nn]
+  const double* vnode;       // [nn]
+  const double* dxmin;       // [nn] smallest inscribed diameter of the cells around the node
+  const int32_t* bnd_index;  // [nn] -1 or index into bnd_S
+  const double* bnd_S;       // [nd][nb]
+  const int32_t* perm;       // [nn] internal -> caller
 };
 
 // Per-solve device scalars of the time loop.
 struct DevScalars {
-  double t;             // committed time
-  double dt;            // time step of the running step
-  double t_end;         // <= 0: none
+  double t;        // committed time
+  double dt;       // time step of the running step
+  double t_end;    // <= 0: none
   double last_dt;
   double dt_query;
-  unsigned long long dtmin;  // running minimum (bit pattern of a positive double)
-  unsigned int counter;      // blocks of the dt kernel that finished
-  int flag;                  // 1 unstable state, 2 invalid time step
-  int bad;                   // some cell produced an invalid time step
-  int active;                // the running step does work
-  int pending;               // a started step awaits its commit
-  long long steps;           // committed steps
+  int flag;        // 1 unstable state, 2 invalid time step
+  int active;      // the running step does work
+  int pending;     // a started step awaits its commit
+  int dt_src;      // 0: candidates from the node pass, 1: from the last step
+  long long steps; // committed steps
 };
 
-struct Sched {
-  double alpha;   // stage coefficient
-  int final_stage;
-  int residual_only;
+// dt candidate buffers (one minimum per block of the producing kernel)
+struct DtParts {
+  double* node;   // k_node_dt: one per 256 nodes
+  int nnode;
+  double* step;   // final stage: one per tile, then one per shared-update block
+  int nstep;
 };
 
 // ---------------------------------------------------------------------------
@@ -82,6 +97,20 @@ __device__ inline bool step_inactive(const DevScalars* sc) {
   return sc != nullptr && sc->active == 0;
 }
 
+// Minimum over the block (blockDim.x a multiple of 64, at most 256); valid in
+// thread 0.  Every thread of the block must call it.
+__device__ inline double block_min(double v) {
+  __shared__ double wmin[4];
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) wmin[wv] = v;
+  __syncthreads();
+  double b = wmin[0];
+  for (int q = 1; q < (int)(blockDim.x >> 6); ++q) b = fmin(b, wmin[q]);
+  return b;
+}
+
 template <int ND>
 __device__ inline void cell_rel_coords(const DevMesh& m, const double* sX, int maxn, const int (&l)[ND + 1],
                                        uint32_t code, double (&e)[ND][ND]) {
@@ -93,15 +122,106 @@ __device__ inline void cell_rel_coords(const DevMesh& m, const double* sX, int m
     }
 }
 
+__device__ inline int slot_node_id(int v) { return v >= 0 ? v : ~v; }
+
+// Reduce the dt candidates of the previous pass, commit the previous step and
+// start the next one (or stop at t_end / on failure).  Block-wide call.
+__device__ inline void dt_reduce_commit(DevScalars* sc, const DtParts parts) {
+  const bool from_step = sc->dt_src != 0;
+  const double* p = from_step ? parts.step : parts.node;
+  const int np = from_step ? parts.nstep : parts.nnode;
+  double v = INFINITY;
+  for (int q = threadIdx.x; q < np; q += blockDim.x) v = fmin(v, p[q]);
+  double d = block_min(v);
+  if (threadIdx.x == 0) {
+    if (sc->pending) {
+      if (sc->flag == 0) {
+        sc->t += sc->dt;
+        sc->last_dt = sc->dt;
+        sc->steps += 1;
+      }
+      sc->pending = 0;
+    }
+    sc->active = 0;
+    const bool done_t = sc->t_end > 0.0 && sc->t >= sc->t_end;
+    if (sc->flag == 0 && !done_t) {
+      if (!(d > 0.0) || !isfinite(d)) {
+        sc->flag |= 2;  // non-physical state or no limiting time scale
+      } else {
+        if (sc->t_end > 0.0 && sc->t + d > sc->t_end) d = sc->t_end - sc->t;
+        sc->dt = d;
+        sc->active = 1;
+        sc->pending = 1;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// per-node time-step candidate: CFL dx_min / lambda and Fourier dx_min^2 / D
+// with dx_min the smallest inscribed diameter of the cells around the node;
+// the minimum over nodes equals the minimum over cells of the cell-based
+// limits (the maximum speed of a cell is attained at one of its nodes).
+// Returns -1 for a non-physical gas state.
+// ---------------------------------------------------------------------------
+
+struct DtCoef {
+  double cfl, fourier, gamma;
+  double zmu[4], D[4];
+};
+
+template <int ND, int NSP, int MODEL>
+__device__ inline double node_dt(const DevMesh& m, const DtCoef& c, const double* E, int i,
+                                 const double* u, double p) {
+  const double dx = m.dxmin[i];
+  if constexpr (MODEL == 0) {
+    const double rho = u[0];
+    double uu = 0.0;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      const double ud = u[1 + d] / rho;
+      uu += ud * ud;
+    }
+    if (!(rho > 0.0) || !(p > 0.0)) return -1.0;
+    const double lam = sqrt(uu) + sqrt(c.gamma * p / rho);
+    return c.cfl * dx / lam;
+  } else {
+    double best = INFINITY;
+#pragma unroll
+    for (int s = 0; s < NSP; ++s) {
+      double v2 = 0.0;
+#pragma unroll
+      for (int d = 0; d < ND; ++d) {
+        const double vd = c.zmu[s] * E[(size_t)d * m.nn + i];
+        v2 += vd * vd;
+      }
+      const double vmax = sqrt(v2);
+      if (vmax > 0.0) best = fmin(best, c.cfl * dx / vmax);
+      if (c.D[s] > 0.0) best = fmin(best, c.fourier * dx * dx / c.D[s]);
+    }
+    return best;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // gradient: per cell  g_tau = sum_k W_k S_k ; per node  G_i = -1/(nd nv V_i) sum g_tau
+// A node whose cells all lie in the tile gets G directly; a node shared with
+// other tiles gets one partial sum per tile (PG), gathered by its readers.
 // ---------------------------------------------------------------------------
+
+struct GradCtl {
+  DevScalars* sc;  // null outside the time loop
+  DtParts parts;
+  int first_stage; // block 0 reduces the dt candidates and commits
+};
 
 template <int ND, int NR>
 __global__ void __launch_bounds__(256) k_grad_tile(DevMesh m, const double* __restrict__ W,
-                                                   double* __restrict__ PG, const DevScalars* sc) {
+                                                   double* __restrict__ G, double* __restrict__ PG,
+                                                   GradCtl ctl) {
   constexpr int NV = ND + 1, NC = NR * ND;
-  if (step_inactive(sc)) return;
+  if (ctl.sc && ctl.first_stage && blockIdx.x == 0) dt_reduce_commit(ctl.sc, ctl.parts);
   const int t = xcd_tile(m.ntiles);
   if (t >= m.ntiles) return;
   extern __shared__ double lds[];
@@ -112,7 +232,7 @@ __global__ void __launch_bounds__(256) k_grad_tile(DevMesh m, const double* __re
   const int c0 = m.tile_cell[t], nc = m.tile_cell[t + 1] - c0;
   const int s0 = m.tile_slot[t], ns = m.tile_slot[t + 1] - s0;
   for (int q = threadIdx.x; q < ns; q += blockDim.x) {
-    const int g = m.slot_node[s0 + q];
+    const int g = slot_node_id(m.slot_node[s0 + q]);
 #pragma unroll
     for (int v = 0; v < NR; ++v) sW[v * maxn + q] = W[(size_t)v * m.nn + g];
 #pragma unroll
@@ -153,26 +273,143 @@ __global__ void __launch_bounds__(256) k_grad_tile(DevMesh m, const double* __re
 #pragma unroll
       for (int j = 0; j < NC; ++j) acc[j] += sC[j * maxc + lc];
     }
+    const int sv = m.slot_node[s0 + q];
+    if (sv >= 0) {
+      const double coef = -m.inv_vol[sv] / double(ND * NV);
 #pragma unroll
-    for (int j = 0; j < NC; ++j) PG[(size_t)j * m.nslots + s0 + q] = acc[j];
+      for (int j = 0; j < NC; ++j) G[(size_t)j * m.nn + sv] = coef * acc[j];
+    } else {
+#pragma unroll
+      for (int j = 0; j < NC; ++j) PG[(size_t)(s0 + q) * NC + j] = acc[j];
+    }
   }
 }
 
-template <int ND, int NR>
-__global__ void __launch_bounds__(256) k_grad_gather(DevMesh m, const double* __restrict__ PG,
-                                                     double* __restrict__ G, const DevScalars* sc) {
-  constexpr int NC = NR * ND;
-  if (step_inactive(sc)) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m.nn) return;
-  const int a = m.node_slot[i], b = m.node_slot[i + 1];
-  const double coef = -m.inv_vol[i] / double(ND * (ND + 1));
+// gradient of a shared node g from its per-tile partial sums, taken over the
+// node's slots in ascending tile order (the same order for every reader)
+template <int NC, int ND>
+__device__ inline void shared_gradient(const DevMesh& m, const double* __restrict__ PG, int g,
+                                       int2 run, double (&out)[NC]) {
+  const double coef = -m.inv_vol[g] / double(ND * (ND + 1));
 #pragma unroll
-  for (int j = 0; j < NC; ++j) {
-    double s = 0.0;
-    for (int p = a; p < b; ++p) s += PG[(size_t)j * m.nslots + m.slots_of[p]];
-    G[(size_t)j * m.nn + i] = coef * s;
+  for (int j = 0; j < NC; ++j) out[j] = 0.0;
+  for (int p = run.x; p < run.y; ++p) {
+    const double* src = PG + (size_t)m.slots_of[p] * NC;
+#pragma unroll
+    for (int j = 0; j < NC; ++j) out[j] += src[j];
   }
+#pragma unroll
+  for (int j = 0; j < NC; ++j) out[j] *= coef;
+}
+
+// complete G on the shared nodes (gradient output only; the time loop reads
+// the partials directly)
+template <int ND, int NR>
+__global__ void __launch_bounds__(256) k_grad_shared(DevMesh m, const double* __restrict__ PG,
+                                                     double* __restrict__ G) {
+  constexpr int NC = NR * ND;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= m.nshared) return;
+  const int g = m.shared[k];
+  double out[NC];
+  shared_gradient<NC, ND>(m, PG, g, make_int2(m.node_slot[g], m.node_slot[g + 1]), out);
+#pragma unroll
+  for (int j = 0; j < NC; ++j) G[(size_t)j * m.nn + g] = out[j];
+}
+
+// ---------------------------------------------------------------------------
+// node finish: boundary closure + RK stage update (or residual output) + dt
+// candidate of the new state
+// ---------------------------------------------------------------------------
+
+struct Finish {
+  const double* Win;    // stage input W (closure)
+  const double* Un;     // U^n rows
+  double* Wout;         // stage output (may alias Win: each node is written by one thread)
+  double* rout;         // residual output (residual_only)
+  const double* G;      // gradients of complete nodes (drift-diffusion closure)
+  const double* PG;     // gradient partials of shared nodes
+  const double* E;      // field (drift-diffusion)
+  DevScalars* sc;       // null: residual only
+  DtCoef dc;
+  double alpha;
+  int closure, final_stage, residual_only;
+};
+
+template <int ND, int NSP, int MODEL, int NVAR>
+__device__ inline double finish_node(const DevMesh& m, const Finish& f, int i, bool shared,
+                                     double (&r)[NVAR]) {
+  if (f.closure && m.nb > 0) {
+    const int bi = m.bnd_index[i];
+    if (bi >= 0) {
+      double Sb[ND];
+#pragma unroll
+      for (int d = 0; d < ND; ++d) Sb[d] = m.bnd_S[(size_t)d * m.nb + bi];
+      if constexpr (MODEL == 0) {
+        // node flux F(W_i) . S_i^b
+        double Wi[NVAR + 1];
+#pragma unroll
+        for (int v = 0; v <= NVAR; ++v) Wi[v] = f.Win[(size_t)v * m.nn + i];
+        double q = 0.0;
+#pragma unroll
+        for (int d = 0; d < ND; ++d) q += Wi[1 + d] * Sb[d];
+        q /= Wi[0];
+        const double p = Wi[NVAR];
+        r[0] += Wi[0] * q;
+#pragma unroll
+        for (int d = 0; d < ND; ++d) r[1 + d] += Wi[1 + d] * q + p * Sb[d];
+        r[1 + ND] += (Wi[1 + ND] + p) * q;
+#pragma unroll
+        for (int k = 0; k < NSP; ++k) r[2 + ND + k] += Wi[2 + ND + k] * q;
+      } else {
+        // convective plus diffusive node flux
+        double gr[NSP * ND];
+        if (shared) {
+          shared_gradient<NSP * ND, ND>(m, f.PG, i, make_int2(m.node_slot[i], m.node_slot[i + 1]), gr);
+        } else {
+#pragma unroll
+          for (int j = 0; j < NSP * ND; ++j) gr[j] = f.G[(size_t)j * m.nn + i];
+        }
+#pragma unroll
+        for (int s = 0; s < NVAR; ++s) {
+          double vb = 0.0, gb = 0.0;
+#pragma unroll
+          for (int d = 0; d < ND; ++d) {
+            vb += f.dc.zmu[s] * f.E[(size_t)d * m.nn + i] * Sb[d];
+            gb += gr[s * ND + d] * Sb[d];
+          }
+          r[s] += f.Win[(size_t)s * m.nn + i] * vb - f.dc.D[s] * gb;
+        }
+      }
+    }
+  }
+  if (f.residual_only) {
+#pragma unroll
+    for (int v = 0; v < NVAR; ++v) f.rout[(size_t)v * m.nn + i] = r[v];
+    return INFINITY;
+  }
+  const double fac = f.alpha * f.sc->dt * m.inv_vol[i];
+  double u[NVAR];
+#pragma unroll
+  for (int v = 0; v < NVAR; ++v) {
+    u[v] = f.Un[(size_t)v * m.nn + i] - fac * r[v];
+    f.Wout[(size_t)v * m.nn + i] = u[v];
+  }
+  bool ok = true;
+  double p = 0.0;
+  if constexpr (MODEL == 0) {
+    double ke = 0.0;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) ke += u[1 + d] * u[1 + d];
+    p = (f.dc.gamma - 1.0) * (u[1 + ND] - 0.5 * ke / u[0]);
+    f.Wout[(size_t)NVAR * m.nn + i] = p;
+    ok = u[0] > 0.0 && p > 0.0;
+  }
+#pragma unroll
+  for (int v = 0; v < NVAR; ++v) ok = ok && isfinite(u[v]);
+  if (!f.final_stage) return INFINITY;
+  if (!ok) atomicOr(&f.sc->flag, 1);
+  return node_dt<ND, NSP, MODEL>(m, f.dc, f.E, i, u, p);
 }
 
 // ---------------------------------------------------------------------------
@@ -185,12 +422,12 @@ struct GasParams {
 };
 
 template <int ND, int NSP, int FLUX, typename CT>
-__global__ void __launch_bounds__(256) k_flux_gas(DevMesh m, const double* __restrict__ W,
+__global__ void VCX_FLUX_BOUNDS k_flux_gas(DevMesh m, const double* __restrict__ W,
                                                   const double* __restrict__ G,
-                                                  double* __restrict__ PR, GasParams gp,
-                                                  const DevScalars* sc) {
+                                                  double* __restrict__ PR, GasParams gp, Finish f,
+                                                  DtParts parts) {
   constexpr int NV = ND + 1, NVAR = 2 + ND + NSP, NR = NVAR + 1, NE = Edges<ND>::NE;
-  if (step_inactive(sc)) return;
+  if (step_inactive(f.sc)) return;
   const int t = xcd_tile(m.ntiles);
   if (t >= m.ntiles) return;
   extern __shared__ double lds[];
@@ -202,11 +439,19 @@ __global__ void __launch_bounds__(256) k_flux_gas(DevMesh m, const double* __res
   const int c0 = m.tile_cell[t], nc = m.tile_cell[t + 1] - c0;
   const int s0 = m.tile_slot[t], ns = m.tile_slot[t + 1] - s0;
   for (int q = threadIdx.x; q < ns; q += blockDim.x) {
-    const int g = m.slot_node[s0 + q];
+    const int sv = m.slot_node[s0 + q];
+    const int g = slot_node_id(sv);
 #pragma unroll
     for (int v = 0; v < NR; ++v) sW[v * maxn + q] = CT(W[(size_t)v * m.nn + g]);
+    if (sv >= 0) {
 #pragma unroll
-    for (int j = 0; j < NR * ND; ++j) sG[j * maxn + q] = CT(G[(size_t)j * m.nn + g]);
+      for (int j = 0; j < NR * ND; ++j) sG[j * maxn + q] = CT(G[(size_t)j * m.nn + g]);
+    } else {
+      double gr[NR * ND];
+      shared_gradient<NR * ND, ND>(m, f.PG, g, m.slot_run[s0 + q], gr);
+#pragma unroll
+      for (int j = 0; j < NR * ND; ++j) sG[j * maxn + q] = CT(gr[j]);
+    }
 #pragma unroll
     for (int d = 0; d < ND; ++d) sX[d * maxn + q] = m.x[(size_t)d * m.nn + g];
   }
@@ -268,19 +513,29 @@ __global__ void __launch_bounds__(256) k_flux_gas(DevMesh m, const double* __res
       for (int v = 0; v < NVAR; ++v) sR[(k * NVAR + v) * maxc + lc] = acc[k][v];
   }
   __syncthreads();
+  double cand = INFINITY;
   for (int q = threadIdx.x; q < ns; q += blockDim.x) {
-    double acc[NVAR];
+    double r[NVAR];
 #pragma unroll
-    for (int v = 0; v < NVAR; ++v) acc[v] = 0.0;
+    for (int v = 0; v < NVAR; ++v) r[v] = 0.0;
     const int p0 = m.slot_inc[s0 + q], p1 = m.slot_inc[s0 + q + 1];
     for (int p = p0; p < p1; ++p) {
       const int code = m.inc[p];
       const int lc = code >> 2, k = code & 3;
 #pragma unroll
-      for (int v = 0; v < NVAR; ++v) acc[v] += sR[(k * NVAR + v) * maxc + lc];
+      for (int v = 0; v < NVAR; ++v) r[v] += sR[(k * NVAR + v) * maxc + lc];
     }
+    const int sv = m.slot_node[s0 + q];
+    if (sv >= 0) {
+      cand = fmin(cand, finish_node<ND, NSP, 0, NVAR>(m, f, sv, false, r));
+    } else {
 #pragma unroll
-    for (int v = 0; v < NVAR; ++v) PR[(size_t)v * m.nslots + s0 + q] = acc[v];
+      for (int v = 0; v < NVAR; ++v) PR[(size_t)(s0 + q) * NVAR + v] = r[v];
+    }
+  }
+  if (f.final_stage && f.sc) {
+    const double b = block_min(cand);
+    if (threadIdx.x == 0) parts.step[t] = b;
   }
 }
 
@@ -292,19 +547,17 @@ struct DDParams {
   double zmu[4];   // z * mu per species
   double D[4];
   double beta;
-  double dt_host;  // used when dt_dev is null
-  const double* dt_dev;
+  double dt_host;  // residual only
   int limiter;
 };
 
 template <int ND, int NS, typename CT>
-__global__ void __launch_bounds__(256) k_flux_dd(DevMesh m, const double* __restrict__ U,
+__global__ void VCX_FLUX_BOUNDS k_flux_dd(DevMesh m, const double* __restrict__ U,
                                                  const double* __restrict__ G,
-                                                 const double* __restrict__ E,
-                                                 double* __restrict__ PR, DDParams pp,
-                                                 const DevScalars* sc) {
+                                                 double* __restrict__ PR, DDParams pp, Finish f,
+                                                 DtParts parts) {
   constexpr int NV = ND + 1, NE = Edges<ND>::NE;
-  if (step_inactive(sc)) return;
+  if (step_inactive(f.sc)) return;
   const int t = xcd_tile(m.ntiles);
   if (t >= m.ntiles) return;
   extern __shared__ double lds[];
@@ -314,14 +567,23 @@ __global__ void __launch_bounds__(256) k_flux_dd(DevMesh m, const double* __rest
   CT* sU = reinterpret_cast<CT*>(sR + NV * NS * maxc);  // [NS][maxn]
   CT* sG = sU + NS * maxn;               // [NS*ND][maxn]
   CT* sE = sG + NS * ND * maxn;          // [ND][maxn]
+  const double* E = f.E;
   const int c0 = m.tile_cell[t], nc = m.tile_cell[t + 1] - c0;
   const int s0 = m.tile_slot[t], ns = m.tile_slot[t + 1] - s0;
   for (int q = threadIdx.x; q < ns; q += blockDim.x) {
-    const int g = m.slot_node[s0 + q];
+    const int sv = m.slot_node[s0 + q];
+    const int g = slot_node_id(sv);
 #pragma unroll
     for (int s = 0; s < NS; ++s) sU[s * maxn + q] = CT(U[(size_t)s * m.nn + g]);
+    if (sv >= 0) {
 #pragma unroll
-    for (int j = 0; j < NS * ND; ++j) sG[j * maxn + q] = CT(G[(size_t)j * m.nn + g]);
+      for (int j = 0; j < NS * ND; ++j) sG[j * maxn + q] = CT(G[(size_t)j * m.nn + g]);
+    } else {
+      double gr[NS * ND];
+      shared_gradient<NS * ND, ND>(m, f.PG, g, m.slot_run[s0 + q], gr);
+#pragma unroll
+      for (int j = 0; j < NS * ND; ++j) sG[j * maxn + q] = CT(gr[j]);
+    }
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
       sX[d * maxn + q] = m.x[(size_t)d * m.nn + g];
@@ -329,7 +591,7 @@ __global__ void __launch_bounds__(256) k_flux_dd(DevMesh m, const double* __rest
     }
   }
   __syncthreads();
-  const CT dt = CT(pp.dt_dev ? *pp.dt_dev : pp.dt_host);
+  const CT dt = CT(f.sc ? f.sc->dt : pp.dt_host);
   const CT beta = CT(pp.beta);
   for (int lc = threadIdx.x; lc < nc; lc += blockDim.x) {
     const int c = c0 + lc;
@@ -390,258 +652,140 @@ __global__ void __launch_bounds__(256) k_flux_dd(DevMesh m, const double* __rest
       for (int s = 0; s < NS; ++s) sR[(k * NS + s) * maxc + lc] = acc[k][s];
   }
   __syncthreads();
+  double cand = INFINITY;
   for (int q = threadIdx.x; q < ns; q += blockDim.x) {
-    double acc[NS];
+    double r[NS];
 #pragma unroll
-    for (int s = 0; s < NS; ++s) acc[s] = 0.0;
+    for (int s = 0; s < NS; ++s) r[s] = 0.0;
     const int p0 = m.slot_inc[s0 + q], p1 = m.slot_inc[s0 + q + 1];
     for (int p = p0; p < p1; ++p) {
       const int code = m.inc[p];
       const int lc = code >> 2, k = code & 3;
 #pragma unroll
-      for (int s = 0; s < NS; ++s) acc[s] += sR[(k * NS + s) * maxc + lc];
+      for (int s = 0; s < NS; ++s) r[s] += sR[(k * NS + s) * maxc + lc];
     }
+    const int sv = m.slot_node[s0 + q];
+    if (sv >= 0) {
+      cand = fmin(cand, finish_node<ND, NS, 1, NS>(m, f, sv, false, r));
+    } else {
 #pragma unroll
-    for (int s = 0; s < NS; ++s) PR[(size_t)s * m.nslots + s0 + q] = acc[s];
+      for (int s = 0; s < NS; ++s) PR[(size_t)(s0 + q) * NS + s] = r[s];
+    }
+  }
+  if (f.final_stage && f.sc) {
+    const double b = block_min(cand);
+    if (threadIdx.x == 0) parts.step[t] = b;
   }
 }
 
 // ---------------------------------------------------------------------------
-// node pass: gather partials + boundary closure + RK stage update
+// shared nodes: gather the per-tile residual partials, then finish
 // ---------------------------------------------------------------------------
-
-struct UpdateArgs {
-  const double* PR;     // [nvar][P]
-  const double* Win;    // stage input W (closure uses it)
-  const double* Un;     // U^n rows
-  double* Wout;         // stage output (may alias Win)
-  double* rout;         // residual output (residual_only)
-  const double* G;      // gradients (drift-diffusion closure)
-  const double* E;      // field (drift-diffusion closure)
-  double gamma;
-  double zmu[4], D[4];
-  int closure;
-};
 
 template <int ND, int NSP, int MODEL>
-__global__ void __launch_bounds__(256) k_update(DevMesh m, UpdateArgs ua, Sched sd, DevScalars* sc) {
+__global__ void __launch_bounds__(256) k_update_shared(DevMesh m, const double* __restrict__ PR,
+                                                       Finish f, DtParts parts) {
   constexpr int NVAR = MODEL == 0 ? 2 + ND + NSP : NSP;
-  if (step_inactive(sc)) return;
+  if (step_inactive(f.sc)) return;
+  // the next step reduces the candidates written by this stage
+  if (f.final_stage && f.sc && blockIdx.x == 0 && threadIdx.x == 0) f.sc->dt_src = 1;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  double cand = INFINITY;
+  if (k < m.nshared) {
+    const int i = m.shared[k];
+    double r[NVAR];
+#pragma unroll
+    for (int v = 0; v < NVAR; ++v) r[v] = 0.0;
+    const int a = m.node_slot[i], b = m.node_slot[i + 1];
+    for (int p = a; p < b; ++p) {
+      const double* src = PR + (size_t)m.slots_of[p] * NVAR;
+#pragma unroll
+      for (int v = 0; v < NVAR; ++v) r[v] += src[v];
+    }
+    cand = finish_node<ND, NSP, MODEL, NVAR>(m, f, i, true, r);
+  }
+  if (f.final_stage && f.sc) {
+    const double b = block_min(cand);
+    if (threadIdx.x == 0) parts.step[m.ntiles + blockIdx.x] = b;
+  }
+}
+
+// dt candidates of the current state, one per 256 nodes (after an upload or
+// for a time-step query)
+template <int ND, int NSP, int MODEL>
+__global__ void __launch_bounds__(256) k_node_dt(DevMesh m, const double* __restrict__ W,
+                                                 const double* __restrict__ E, DtCoef dc,
+                                                 DtParts parts, DevScalars* sc) {
+  constexpr int NVAR = MODEL == 0 ? 2 + ND + NSP : NSP;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m.nn) return;
-  double r[NVAR];
-  const int a = m.node_slot[i], b = m.node_slot[i + 1];
+  double cand = INFINITY;
+  if (i < m.nn) {
+    double u[NVAR];
 #pragma unroll
-  for (int v = 0; v < NVAR; ++v) r[v] = 0.0;
-  for (int p = a; p < b; ++p) {
-    const int s = m.slots_of[p];
-#pragma unroll
-    for (int v = 0; v < NVAR; ++v) r[v] += ua.PR[(size_t)v * m.nslots + s];
+    for (int v = 0; v < NVAR; ++v) u[v] = W[(size_t)v * m.nn + i];
+    const double p = MODEL == 0 ? W[(size_t)NVAR * m.nn + i] : 0.0;
+    cand = node_dt<ND, NSP, MODEL>(m, dc, E, i, u, p);
   }
-  if (ua.closure && m.nb > 0) {
-    const int bi = m.bnd_index[i];
-    if (bi >= 0) {
-      double Sb[ND];
-#pragma unroll
-      for (int d = 0; d < ND; ++d) Sb[d] = m.bnd_S[(size_t)d * m.nb + bi];
-      if constexpr (MODEL == 0) {
-        // node flux F(W_i) . S_i^b
-        double Wi[NVAR + 1];
-#pragma unroll
-        for (int v = 0; v <= NVAR; ++v) Wi[v] = ua.Win[(size_t)v * m.nn + i];
-        double q = 0.0;
-#pragma unroll
-        for (int d = 0; d < ND; ++d) q += Wi[1 + d] * Sb[d];
-        q /= Wi[0];
-        const double p = Wi[NVAR];
-        r[0] += Wi[0] * q;
-#pragma unroll
-        for (int d = 0; d < ND; ++d) r[1 + d] += Wi[1 + d] * q + p * Sb[d];
-        r[1 + ND] += (Wi[1 + ND] + p) * q;
-#pragma unroll
-        for (int k = 0; k < NSP; ++k) r[2 + ND + k] += Wi[2 + ND + k] * q;
-      } else {
-        // convective plus diffusive node flux
-#pragma unroll
-        for (int s = 0; s < NVAR; ++s) {
-          double vb = 0.0, gb = 0.0;
-#pragma unroll
-          for (int d = 0; d < ND; ++d) {
-            vb += ua.zmu[s] * ua.E[(size_t)d * m.nn + i] * Sb[d];
-            gb += ua.G[(size_t)(s * ND + d) * m.nn + i] * Sb[d];
-          }
-          r[s] += ua.Win[(size_t)s * m.nn + i] * vb - ua.D[s] * gb;
-        }
-      }
-    }
-  }
-  if (sd.residual_only) {
-#pragma unroll
-    for (int v = 0; v < NVAR; ++v) ua.rout[(size_t)v * m.nn + i] = r[v];
-    return;
-  }
-  const double f = sd.alpha * sc->dt * m.inv_vol[i];
-  double u[NVAR];
-#pragma unroll
-  for (int v = 0; v < NVAR; ++v) {
-    u[v] = ua.Un[(size_t)v * m.nn + i] - f * r[v];
-    ua.Wout[(size_t)v * m.nn + i] = u[v];
-  }
-  bool ok = true;
-  if constexpr (MODEL == 0) {
-    double ke = 0.0;
-#pragma unroll
-    for (int d = 0; d < ND; ++d) ke += u[1 + d] * u[1 + d];
-    const double p = (ua.gamma - 1.0) * (u[1 + ND] - 0.5 * ke / u[0]);
-    ua.Wout[(size_t)NVAR * m.nn + i] = p;
-    ok = u[0] > 0.0 && p > 0.0;
-  }
-#pragma unroll
-  for (int v = 0; v < NVAR; ++v) ok = ok && isfinite(u[v]);
-  if (sd.final_stage && !ok) atomicOr(&sc->flag, 1);
-}
-
-// ---------------------------------------------------------------------------
-// time step: per cell, wave-level then block-level min, one atomic per block,
-// the last block finalises (min is order independent: deterministic)
-// ---------------------------------------------------------------------------
-
-struct DtParams {
-  int model;
-  double cfl, fourier, gamma;
-  double vmax_coef[4];  // |z mu| per species
-  double D[4];
-  int nspecies;
-  int query;           // 1: only store the minimum in dt_query
-};
-
-__device__ inline void dt_commit(DevScalars* sc) {
-  if (sc->pending) {
-    if (sc->flag == 0) {
-      sc->t += sc->dt;
-      sc->last_dt = sc->dt;
-      sc->steps += 1;
-    }
-    sc->pending = 0;
-  }
-}
-
-template <int ND>
-__global__ void __launch_bounds__(256) k_dt(DevMesh m, const double* __restrict__ W,
-                                            const double* __restrict__ E, DtParams dp,
-                                            DevScalars* sc) {
-  constexpr int NV = ND + 1;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  double dtc = INFINITY;
-  if (c < m.nc) {
-    int v[NV];
-#pragma unroll
-    for (int k = 0; k < NV; ++k) v[k] = m.cell[(size_t)k * m.nc + c];
-    const uint32_t code = m.shift[c];
-    double e[ND][ND], S[NV][ND];
-#pragma unroll
-    for (int k = 1; k <= ND; ++k)
-#pragma unroll
-      for (int d = 0; d < ND; ++d) {
-        const uint32_t b = (code >> (2 * ((k - 1) * ND + d))) & 3u;
-        const double s = b == 1u ? m.period[d] : (b == 2u ? -m.period[d] : 0.0);
-        e[k - 1][d] = m.x[(size_t)d * m.nn + v[k]] + s - m.x[(size_t)d * m.nn + v[0]];
-      }
-    const double det = simplex_normals<ND>(e, S);
-    double area = 0.0;
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-      double s2 = 0.0;
-#pragma unroll
-      for (int d = 0; d < ND; ++d) s2 += S[k][d] * S[k][d];
-      area += sqrt(s2);
-    }
-    // inscribed diameter 2 nd V / sum |S_k|, V = det / nd!
-    const double dx = 2.0 * ND * (det / (ND == 2 ? 2.0 : 6.0)) / area;
-    if (dp.model == 0) {
-      double lam = 0.0;
-      bool phys = true;
-#pragma unroll
-      for (int k = 0; k < NV; ++k) {
-        const double rho = W[v[k]];
-        double uu = 0.0;
-#pragma unroll
-        for (int d = 0; d < ND; ++d) {
-          const double ud = W[(size_t)(1 + d) * m.nn + v[k]] / rho;
-          uu += ud * ud;
-        }
-        const double p = W[(size_t)(m.nd + 2 + dp.nspecies) * m.nn + v[k]];
-        phys = phys && rho > 0.0 && p > 0.0;
-        lam = fmax(lam, sqrt(uu) + sqrt(dp.gamma * p / rho));
-      }
-      dtc = dp.cfl * dx / lam;
-      if (!phys || !(dtc > 0.0)) dtc = -1.0;  // non-physical state: flagged below
-    } else {
-      double emax = 0.0;
-#pragma unroll
-      for (int k = 0; k < NV; ++k) {
-        double e2 = 0.0;
-#pragma unroll
-        for (int d = 0; d < ND; ++d) {
-          const double ed = E[(size_t)d * m.nn + v[k]];
-          e2 += ed * ed;
-        }
-        emax = fmax(emax, sqrt(e2));
-      }
-      for (int s = 0; s < dp.nspecies; ++s) {
-        const double vmax = dp.vmax_coef[s] * emax;
-        if (vmax > 0.0) dtc = fmin(dtc, dp.cfl * dx / vmax);
-        if (dp.D[s] > 0.0) dtc = fmin(dtc, dp.fourier * dx * dx / dp.D[s]);
-      }
-    }
-  }
-  // wave64 minimum, then across the block's waves
-  for (int off = 32; off > 0; off >>= 1) dtc = fmin(dtc, __shfl_xor(dtc, off, 64));
-  __shared__ double wmin[4];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (lane == 0) wmin[wv] = dtc;
-  __syncthreads();
+  const double b = block_min(cand);
   if (threadIdx.x == 0) {
-    double b = wmin[0];
-    for (int q = 1; q < (int)(blockDim.x >> 6); ++q) b = fmin(b, wmin[q]);
-    if (b < 0.0) atomicOr(&sc->bad, 1);
-    else atomicMin(&sc->dtmin, (unsigned long long)__double_as_longlong(b));
-    __threadfence();
-    const unsigned int done = atomicAdd(&sc->counter, 1u);
-    if (done == gridDim.x - 1) {
-      __threadfence();
-      double d = __longlong_as_double((long long)atomicAdd(&sc->dtmin, 0ull));
-      const bool bad = atomicAdd(&sc->bad, 0) != 0;
-      if (dp.query) {
-        sc->dt_query = bad ? -1.0 : d;
-      } else {
-        dt_commit(sc);
-        sc->active = 0;
-        const bool done_t = sc->t_end > 0.0 && sc->t >= sc->t_end;
-        // a finished or failed solve ignores the (stale) state it was given
-        if (sc->flag == 0 && !done_t) {
-          if (sc->t_end > 0.0 && sc->t + d > sc->t_end) d = sc->t_end - sc->t;
-          if (!bad && d > 0.0 && isfinite(d)) {
-            sc->dt = d;
-            sc->active = 1;
-            sc->pending = 1;
-          } else {
-            sc->flag |= 2;
-          }
-        }
-      }
-      sc->dtmin = 0x7FF0000000000000ull;  // +inf
-      sc->bad = 0;
-      sc->counter = 0u;
-    }
+    parts.node[blockIdx.x] = b;
+    if (blockIdx.x == 0) sc->dt_src = 0;
   }
+}
+
+__global__ void __launch_bounds__(256) k_dt_query(DevScalars* sc, DtParts parts) {
+  double v = INFINITY;
+  for (int q = threadIdx.x; q < parts.nnode; q += blockDim.x) v = fmin(v, parts.node[q]);
+  const double d = block_min(v);
+  if (threadIdx.x == 0) sc->dt_query = (d > 0.0 && isfinite(d)) ? d : -1.0;
 }
 
 __global__ void k_commit(DevScalars* sc) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
-    dt_commit(sc);
+    if (sc->pending) {
+      if (sc->flag == 0) {
+        sc->t += sc->dt;
+        sc->last_dt = sc->dt;
+        sc->steps += 1;
+      }
+      sc->pending = 0;
+    }
     sc->active = 0;
   }
+}
+
+// smallest inscribed diameter 2 nd V / sum_k |S_k| over the cells of each node
+template <int ND>
+__global__ void __launch_bounds__(256) k_cell_dx(DevMesh m, unsigned long long* __restrict__ dxbits) {
+  constexpr int NV = ND + 1;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= m.nc) return;
+  int v[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = m.cell[(size_t)k * m.nc + c];
+  const uint32_t code = m.shift[c];
+  double e[ND][ND], S[NV][ND];
+#pragma unroll
+  for (int k = 1; k <= ND; ++k)
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      const uint32_t b = (code >> (2 * ((k - 1) * ND + d))) & 3u;
+      const double s = b == 1u ? m.period[d] : (b == 2u ? -m.period[d] : 0.0);
+      e[k - 1][d] = m.x[(size_t)d * m.nn + v[k]] + s - m.x[(size_t)d * m.nn + v[0]];
+    }
+  const double det = simplex_normals<ND>(e, S);
+  double area = 0.0;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double s2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) s2 += S[k][d] * S[k][d];
+    area += sqrt(s2);
+  }
+  const double dx = 2.0 * ND * (det / (ND == 2 ? 2.0 : 6.0)) / area;
+  const unsigned long long bits = (unsigned long long)__double_as_longlong(dx);
+#pragma unroll
+  for (int k = 0; k < NV; ++k) atomicMin(&dxbits[v[k]], bits);
 }
 
 // ---------------------------------------------------------------------------

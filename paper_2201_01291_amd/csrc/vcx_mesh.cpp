@@ -329,6 +329,16 @@ std::string preprocess_mesh(int nd, int64_t nn, const double* xyz, int64_t nc, i
   for (int64_t s = 0; s < P; ++s) m.slots_of[fill[m.slot_node[s]]++] = (int32_t)s;
   for (int64_t i = 0; i < nn; ++i)
     if (m.node_slot[i + 1] == m.node_slot[i]) return "node not referenced by any cell";
+  // nodes split over several tiles: gathered through partial sums
+  for (int64_t i = 0; i < nn; ++i)
+    if (m.node_slot[i + 1] - m.node_slot[i] > 1) m.shared.push_back((int32_t)i);
+  m.slot_run.resize(2 * P);
+  for (int64_t s = 0; s < P; ++s) {
+    int32_t g = m.slot_node[s];
+    m.slot_run[2 * s] = m.node_slot[g];
+    m.slot_run[2 * s + 1] = m.node_slot[g + 1];
+    if (m.node_slot[g + 1] - m.node_slot[g] > 1) m.slot_node[s] = ~g;
+  }
 
   *code = 0;
   return "";

@@ -37,12 +37,15 @@ struct HostMesh {
   TileLimits lim{};
   std::vector<int32_t> tile_cell;  // [T+1] first cell of each tile
   std::vector<int32_t> tile_slot;  // [T+1] first slot of each tile
-  std::vector<int32_t> slot_node;  // [P] node of each slot (ascending inside a tile)
+  std::vector<int32_t> slot_node;  // [P] node of each slot (ascending inside a tile); ~node
+                                   // when the node also has slots in other tiles
   std::vector<uint16_t> lconn;     // [nv][nc] tile-local node of each cell vertex
   std::vector<int32_t> slot_inc;   // [P+1] CSR into inc
   std::vector<uint16_t> inc;       // [nc*nv] (local cell << 2) | vertex, ascending cell
   std::vector<int32_t> node_slot;  // [nn+1] CSR into slots_of
   std::vector<int32_t> slots_of;   // [P] slots of each node, ascending tile
+  std::vector<int32_t> shared;     // nodes with more than one slot, ascending
+  std::vector<int32_t> slot_run;   // [2P] per slot: [begin, end) of its node's run in slots_of
   int max_tile_cells = 0, max_tile_nodes = 0;
 
   int64_t ntiles() const { return (int64_t)tile_cell.size() - 1; }
