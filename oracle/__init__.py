@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 MAXSP = 16
 
 # model / flux / limiter codes of the oracle
-GAS, DRIFT_DIFFUSION = 0, 1
+GAS, DRIFT_DIFFUSION, NAVIER_STOKES = 0, 1, 2
 HLLC, ROE = 0, 1
 FIRST_ORDER, MINMOD, VANLEER, SWEBY, UNLIMITED = 0, 1, 2, 3, 4
 
@@ -42,7 +42,11 @@ class _Phys(C.Structure):
                 ("beta", C.c_double), ("cfl", C.c_double), ("fourier", C.c_double),
                 ("gamma", C.c_double), ("entropy_fix", C.c_double),
                 ("z", C.c_double * MAXSP), ("mu", C.c_double * MAXSP),
-                ("D", C.c_double * MAXSP)]
+                ("D", C.c_double * MAXSP),
+                ("Wk", C.c_double * MAXSP), ("cpa", C.c_double * MAXSP),
+                ("cpb", C.c_double * MAXSP), ("cpc", C.c_double * MAXSP),
+                ("Sc", C.c_double * MAXSP), ("mu_ref", C.c_double), ("T_ref", C.c_double),
+                ("Pr", C.c_double)]
 
 
 @dataclass
@@ -61,6 +65,7 @@ class Phys:
     z: list = field(default_factory=list)
     mu: list = field(default_factory=list)
     D: list = field(default_factory=list)
+    mixture: object = None   # workloads.Mixture for the Navier-Stokes model
 
     def to_c(self) -> _Phys:
         p = _Phys()
@@ -70,6 +75,12 @@ class Phys:
         p.gamma, p.entropy_fix = self.gamma, self.entropy_fix
         for k, (z, mu, D) in enumerate(zip(self.z, self.mu, self.D)):
             p.z[k], p.mu[k], p.D[k] = z, mu, D
+        if self.mixture is not None:
+            mx = self.mixture
+            for k in range(mx.n):
+                p.Wk[k], p.cpa[k], p.cpb[k] = mx.W[k], mx.cp_a[k], mx.cp_b[k]
+                p.cpc[k], p.Sc[k] = mx.cp_c[k], mx.Sc[k]
+            p.mu_ref, p.T_ref, p.Pr = mx.mu_ref, mx.T_ref, mx.Pr
         return p
 
     def nvar(self, nd: int) -> int:
@@ -108,6 +119,9 @@ def lib():
         L.om_step.argtypes = [C.c_void_p, pp, dp, dp, C.c_int, C.c_double, dp, dp,
                               C.POINTER(C.c_int)]
         L.om_sums.argtypes = [C.c_void_p, C.c_int, dp, dp, dp]
+        L.om_ns_node.argtypes = [C.c_int, pp, dp, dp]
+        L.om_viscous_flux.argtypes = [C.c_int, C.c_int, dp, dp, C.c_double, C.c_double, dp, dp,
+                                      dp, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -258,6 +272,26 @@ def roe(nd, nsp, WL, WR, S, gamma=1.4, fix=0.1):
     F = np.zeros(2 + nd + nsp)
     lib().om_roe(nd, nsp, float(gamma), float(fix), _d(WL), _d(WR), _d(S), _d(F))
     return F
+
+
+def ns_node(nd, phys: Phys, Ui):
+    """(T, p, gamma, mu, lambda, D_k..., hs_k...) of one multi-species node state."""
+    Ui = _c64(Ui)
+    out = np.zeros(5 + 2 * phys.nspecies)
+    p = phys.to_c()
+    lib().om_ns_node(nd, C.byref(p), _d(Ui), _d(out))
+    return out
+
+
+def viscous_flux(nd, nsp, prim_i, prim_j, rho_i, rho_j, aux_i, aux_j, gprim_i, gprim_j, S):
+    args = [_c64(a) for a in (prim_i, prim_j)]
+    aux = [_c64(a) for a in (aux_i, aux_j)]
+    g = [_c64(a) for a in (gprim_i, gprim_j)]
+    S = _c64(S)
+    Fv = np.zeros(2 + nd + nsp)
+    lib().om_viscous_flux(nd, nsp, _d(args[0]), _d(args[1]), float(rho_i), float(rho_j),
+                          _d(aux[0]), _d(aux[1]), _d(g[0]), _d(g[1]), _d(S), _d(Fv))
+    return Fv
 
 
 def prim_to_W(rho, vel, p, gamma=1.4, Y=()):

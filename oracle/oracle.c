@@ -27,6 +27,11 @@
  *   time step     Sec. "Time step computation", eqs. (dt_conv), (dt_diff)
  *   RK            Sec. "Time integration of the HLLC MUSCL-Hancock solver",
  *                 table (rk_coeffs)
+ *   multi-species eq. (ns_reactive) without sources (transport only), total
+ *                 non-chemical energy; temperature from the sensible energy by
+ *                 iteration and pressure co-reconstructed (Sec. "Effect of
+ *                 multicomponent mixture"); central diffusive fluxes as in
+ *                 Sec. "Central difference diffusive flux integration"
  *
  * Readings where the paper is silent or garbled (listed in the design notes):
  *   nodal volume V_i = sum_tau V_tau / n_v (median dual);
@@ -36,7 +41,14 @@
  *   HLLC wave speeds: Davis estimates; species star entry = factor * rho*Y;
  *   Roe flux (not in the paper): textbook, Harten fix on acoustic waves;
  *   RK stage formula carries the time step: U(k) = U^n - a_k dt r/V;
- *   cell size dx = 2 n_d V_tau / sum_k |S_k| (inscribed diameter).
+ *   cell size dx = 2 n_d V_tau / sum_k |S_k| (inscribed diameter);
+ *   multi-species: synthetic species data (c_p polynomials, molar masses,
+ *   Schmidt numbers), mu = mu_ref (T/T_ref)^0.7, lambda = mu c_p / Pr,
+ *   D_k = mu / (rho Sc_k), Hirschfelder-Curtiss correction velocity,
+ *   Newtonian stress with Stokes' hypothesis, face values as means of the two
+ *   cell-edge nodes, temperature by 10 Newton iterations from 1000 K, the
+ *   HLLC sound speed of each side from its own node's gamma, inviscid node
+ *   flux closure on boundaries.
  */
 #include "oracle.h"
 
@@ -68,6 +80,121 @@ static const int *edge_of(int nv, int e) {
 int om_nvar(int nd, const om_phys *ph) {
   if (ph->model == 1) return ph->nspecies;
   return 2 + nd + ph->nspecies;
+}
+
+/* ------------------------------------------------------------------ */
+/* multi-species mixture (synthetic species data)                       */
+/* ------------------------------------------------------------------ */
+
+#define OM_RGAS 8.314462618
+#define OM_T0 298.15
+#define OM_NEWTON 10
+
+/* species sensible enthalpy hs_k(T) = int_{T0}^{T} c_p,k */
+static double species_hs(const om_phys *ph, int k, double T) {
+  double Rk = OM_RGAS / ph->Wk[k];
+  return Rk * (ph->cpa[k] * (T - OM_T0) + ph->cpb[k] * (T * T - OM_T0 * OM_T0) / 2000.0 +
+               ph->cpc[k] * (T * T * T - OM_T0 * OM_T0 * OM_T0) / 3.0e6);
+}
+
+static double species_cp(const om_phys *ph, int k, double T) {
+  double t = T / 1000.0;
+  return OM_RGAS / ph->Wk[k] * (ph->cpa[k] + ph->cpb[k] * t + ph->cpc[k] * t * t);
+}
+
+/* mixture sensible energy e_s(T) = sum Y_k (hs_k(T) - R_k T) and c_v(T) */
+static void mixture_es_cv(const om_phys *ph, const double *Y, double T, double *es, double *cv) {
+  double e = 0.0, c = 0.0;
+  for (int k = 0; k < ph->nspecies; k++) {
+    double Rk = OM_RGAS / ph->Wk[k];
+    e += Y[k] * (species_hs(ph, k, T) - Rk * T);
+    c += Y[k] * (species_cp(ph, k, T) - Rk);
+  }
+  *es = e;
+  *cv = c;
+}
+
+/* Node state of the multi-species model: out = T, p, gamma, mu, lambda,
+ * D_1..D_N, hs_1..hs_N (the temperature solves e_s(T) = E - |u|^2/2). */
+void om_ns_node(int nd, const om_phys *ph, const double *Ui, double *out) {
+  int ns = ph->nspecies;
+  double rho = Ui[0], uu = 0.0, Y[OM_MAXSP];
+  for (int d = 0; d < nd; d++) uu += (Ui[1 + d] / rho) * (Ui[1 + d] / rho);
+  double es_target = Ui[1 + nd] / rho - 0.5 * uu;
+  for (int k = 0; k < ns; k++) Y[k] = Ui[2 + nd + k] / rho;
+  double T = 1000.0, es, cv;
+  for (int it = 0; it < OM_NEWTON; it++) {
+    mixture_es_cv(ph, Y, T, &es, &cv);
+    T -= (es - es_target) / cv;
+  }
+  double r = 0.0, cp = 0.0;
+  for (int k = 0; k < ns; k++) {
+    r += Y[k] * OM_RGAS / ph->Wk[k];
+    cp += Y[k] * species_cp(ph, k, T);
+  }
+  double mu = ph->mu_ref * pow(T / ph->T_ref, 0.7);
+  out[0] = T;
+  out[1] = rho * r * T;
+  out[2] = cp / (cp - r);
+  out[3] = mu;
+  out[4] = mu * cp / ph->Pr;
+  for (int k = 0; k < ns; k++) {
+    out[5 + k] = mu / (rho * ph->Sc[k]);
+    out[5 + ns + k] = species_hs(ph, k, T);
+  }
+}
+
+/* Central diffusive fluxes through S (Sec. "Central difference diffusive flux
+ * integration" applied to every diffusive term of eq. ns_reactive): face
+ * values are means of the two nodes, gradients the means of the nodal
+ * gradients.  prim = (u_1..u_nd, T, Y_1..Y_N), aux = (gamma, mu, lambda,
+ * D_k, hs_k), gprim [np][nd].  Returns Fv = (0, tau.S, u.(tau.S) - q.S,
+ * -J_k.S), to be subtracted from the convective flux. */
+void om_viscous_flux(int nd, int nsp, const double *prim_i, const double *prim_j,
+                     double rho_i, double rho_j, const double *aux_i, const double *aux_j,
+                     const double *gprim_i, const double *gprim_j, const double *S, double *Fv) {
+  double rho = 0.5 * (rho_i + rho_j);
+  double mu = 0.5 * (aux_i[1] + aux_j[1]), lam = 0.5 * (aux_i[2] + aux_j[2]);
+  double u[3], Gu[3][3], div = 0.0;
+  for (int a = 0; a < nd; a++) {
+    u[a] = 0.5 * (prim_i[a] + prim_j[a]);
+    for (int b = 0; b < nd; b++) Gu[a][b] = 0.5 * (gprim_i[a * nd + b] + gprim_j[a * nd + b]);
+    div += Gu[a][a];
+  }
+  double tauS[3];
+  for (int a = 0; a < nd; a++) {
+    tauS[a] = 0.0;
+    for (int b = 0; b < nd; b++) {
+      double tau = mu * (Gu[a][b] + Gu[b][a] - (a == b ? 2.0 / 3.0 * div : 0.0));
+      tauS[a] += tau * S[b];
+    }
+  }
+  /* species diffusion with the correction velocity Vc = sum_k D_k grad Y_k */
+  double Vc[3] = {0, 0, 0}, gY[OM_MAXSP][3], D[OM_MAXSP], Yf[OM_MAXSP];
+  for (int k = 0; k < nsp; k++) {
+    D[k] = 0.5 * (aux_i[3 + k] + aux_j[3 + k]);
+    Yf[k] = 0.5 * (prim_i[nd + 1 + k] + prim_j[nd + 1 + k]);
+    for (int d = 0; d < nd; d++) {
+      gY[k][d] = 0.5 * (gprim_i[(nd + 1 + k) * nd + d] + gprim_j[(nd + 1 + k) * nd + d]);
+      Vc[d] += D[k] * gY[k][d];
+    }
+  }
+  double qS = 0.0;
+  for (int d = 0; d < nd; d++) qS += -lam * 0.5 * (gprim_i[nd * nd + d] + gprim_j[nd * nd + d]) * S[d];
+  Fv[0] = 0.0;
+  double utauS = 0.0;
+  for (int a = 0; a < nd; a++) {
+    Fv[1 + a] = tauS[a];
+    utauS += u[a] * tauS[a];
+  }
+  for (int k = 0; k < nsp; k++) {
+    double JS = 0.0;
+    for (int d = 0; d < nd; d++) JS += -rho * (D[k] * gY[k][d] - Yf[k] * Vc[d]) * S[d];
+    double hs = 0.5 * (aux_i[3 + nsp + k] + aux_j[3 + nsp + k]);
+    qS += hs * JS;
+    Fv[2 + nd + k] = -JS;
+  }
+  Fv[1 + nd] = utauS - qS;
 }
 
 /* ------------------------------------------------------------------ */
@@ -470,13 +597,37 @@ static double pressure_of(int nd, const double *U, int64_t nn, int64_t i, double
 static int residual_gas(const om_mesh *m, const om_phys *ph, const double *U, double *r, int absmode) {
   int nd = m->nd, nv = m->nv, nsp = ph->nspecies;
   int nvar = 2 + nd + nsp, nr = nvar + 1;
+  int ns_model = ph->model == 2;
+  int np = nd + 1 + nsp, na = 3 + 2 * nsp;
   int64_t nn = m->nn;
   /* reconstructed variables: conserved state plus pressure */
   double *W = malloc(sizeof(double) * nr * nn);
   double *G = malloc(sizeof(double) * nr * nd * nn);
-  if (!W || !G) { free(W); free(G); return -3; }
+  /* multi-species: primitive fields (u, T, Y), their gradients, node aux */
+  double *P = ns_model ? malloc(sizeof(double) * np * nn) : NULL;
+  double *GP = ns_model ? malloc(sizeof(double) * np * nd * nn) : NULL;
+  double *A = ns_model ? malloc(sizeof(double) * na * nn) : NULL;
+  if (!W || !G || (ns_model && (!P || !GP || !A))) {
+    free(W); free(G); free(P); free(GP); free(A);
+    return -3;
+  }
   memcpy(W, U, sizeof(double) * nvar * nn);
-  for (int64_t i = 0; i < nn; i++) W[(int64_t)nvar * nn + i] = pressure_of(nd, U, nn, i, ph->gamma);
+  if (!ns_model) {
+    for (int64_t i = 0; i < nn; i++) W[(int64_t)nvar * nn + i] = pressure_of(nd, U, nn, i, ph->gamma);
+  } else {
+    double Ui[2 + 3 + OM_MAXSP], out[5 + 2 * OM_MAXSP];
+    for (int64_t i = 0; i < nn; i++) {
+      for (int v = 0; v < nvar; v++) Ui[v] = U[(int64_t)v * nn + i];
+      om_ns_node(nd, ph, Ui, out);
+      W[(int64_t)nvar * nn + i] = out[1];
+      for (int d = 0; d < nd; d++) P[(int64_t)d * nn + i] = Ui[1 + d] / Ui[0];
+      P[(int64_t)nd * nn + i] = out[0];
+      for (int k = 0; k < nsp; k++) P[(int64_t)(nd + 1 + k) * nn + i] = Ui[2 + nd + k] / Ui[0];
+      A[i] = out[2];
+      for (int q = 1; q < na; q++) A[(int64_t)q * nn + i] = out[2 + q];
+    }
+    om_gradient(m, np, P, GP);
+  }
   om_gradient(m, nr, W, G);
   memset(r, 0, sizeof(double) * nvar * nn);
   for (int64_t c = 0; c < m->nc; c++) {
@@ -505,10 +656,30 @@ static int residual_gas(const om_mesh *m, const om_phys *ph, const double *U, do
         WR[v] = wj - 0.5 * bar_j;
       }
       double F[2 + 3 + OM_MAXSP];
-      if (ph->flux == 0)
+      if (ns_model) {
+        /* HLLC with each side's own node gamma, minus the diffusive flux */
+        om_hllc(nd, nsp, A[i], A[j], WL, WR, Sij, F);
+        double pi[3 + 1 + OM_MAXSP], pj[3 + 1 + OM_MAXSP], ai[3 + 2 * OM_MAXSP], aj[3 + 2 * OM_MAXSP];
+        double gi[(3 + 1 + OM_MAXSP) * 3], gj[(3 + 1 + OM_MAXSP) * 3], Fv[2 + 3 + OM_MAXSP];
+        for (int q = 0; q < np; q++) {
+          pi[q] = P[(int64_t)q * nn + i];
+          pj[q] = P[(int64_t)q * nn + j];
+          for (int d = 0; d < nd; d++) {
+            gi[q * nd + d] = GP[((int64_t)q * nd + d) * nn + i];
+            gj[q * nd + d] = GP[((int64_t)q * nd + d) * nn + j];
+          }
+        }
+        for (int q = 0; q < na; q++) {
+          ai[q] = A[(int64_t)q * nn + i];
+          aj[q] = A[(int64_t)q * nn + j];
+        }
+        om_viscous_flux(nd, nsp, pi, pj, U[i], U[j], ai, aj, gi, gj, Sij, Fv);
+        for (int v = 0; v < nvar; v++) F[v] -= Fv[v];
+      } else if (ph->flux == 0) {
         om_hllc(nd, nsp, ph->gamma, ph->gamma, WL, WR, Sij, F);
-      else
+      } else {
         om_roe(nd, nsp, ph->gamma, ph->entropy_fix, WL, WR, Sij, F);
+      }
       for (int v = 0; v < nvar; v++) {
         r[(int64_t)v * nn + i] += absmode ? fabs(F[v]) : F[v];
         r[(int64_t)v * nn + j] -= absmode ? -fabs(F[v]) : F[v];
@@ -528,6 +699,9 @@ static int residual_gas(const om_mesh *m, const om_phys *ph, const double *U, do
   }
   free(W);
   free(G);
+  free(P);
+  free(GP);
+  free(A);
   return 0;
 }
 
@@ -602,7 +776,7 @@ static int residual_any(const om_mesh *m, const om_phys *ph, const double *U, co
                         double dt, double *r, int absmode) {
   if (!m || !ph || !U || !r) return -1;
   if (ph->nspecies < 0 || ph->nspecies > OM_MAXSP) return -1;
-  if (ph->model == 0) return residual_gas(m, ph, U, r, absmode);
+  if (ph->model == 0 || ph->model == 2) return residual_gas(m, ph, U, r, absmode);
   if (ph->model == 1) {
     if (!E || ph->nspecies < 1) return -1;
     return residual_dd(m, ph, U, E, dt, r, absmode);
@@ -648,7 +822,35 @@ int om_timestep(const om_mesh *m, const om_phys *ph, const double *U, const doub
   double dt = INFINITY;
   for (int64_t c = 0; c < m->nc; c++) {
     double dx = cell_size(m, c);
-    if (ph->model == 0) {
+    if (ph->model == 2) {
+      /* convective limit with the mixture sound speed, viscous limit with the
+       * largest of nu, thermal diffusivity and species diffusivities */
+      double lam = 0.0, dmax = 0.0, Ui[2 + 3 + OM_MAXSP], out[5 + 2 * OM_MAXSP];
+      int nvar = 2 + nd + ph->nspecies;
+      for (int k = 0; k < nv; k++) {
+        int64_t i = m->cell[c * nv + k];
+        for (int v = 0; v < nvar; v++) Ui[v] = U[(int64_t)v * nn + i];
+        double rho = Ui[0], uu = 0.0;
+        if (!(rho > 0.0)) return -5;
+        for (int d = 0; d < nd; d++) uu += (Ui[1 + d] / rho) * (Ui[1 + d] / rho);
+        om_ns_node(nd, ph, Ui, out);
+        if (!(out[0] > 0.0)) return -5;
+        double l = sqrt(uu) + sqrt(out[2] * out[1] / rho);
+        if (l > lam) lam = l;
+        /* thermal diffusivity lambda / (rho c_p) = mu / (rho Pr) */
+        double nu = out[3] / rho, kap = out[3] / (rho * ph->Pr);
+        double dm = nu > kap ? nu : kap;
+        for (int s = 0; s < ph->nspecies; s++)
+          if (out[5 + s] > dm) dm = out[5 + s];
+        if (dm > dmax) dmax = dm;
+      }
+      double t = ph->cfl * dx / lam;
+      if (t < dt) dt = t;
+      if (dmax > 0.0) {
+        t = ph->fourier * dx * dx / dmax;
+        if (t < dt) dt = t;
+      }
+    } else if (ph->model == 0) {
       double lam = 0.0;
       for (int k = 0; k < nv; k++) {
         int64_t i = m->cell[c * nv + k];
@@ -715,6 +917,15 @@ static int state_ok(const om_mesh *m, const om_phys *ph, const double *U) {
       if (!(U[i] > 0.0)) return 0;
       if (!(pressure_of(m->nd, U, nn, i, ph->gamma) > 0.0)) return 0;
     }
+  if (ph->model == 2) {
+    double Ui[2 + 3 + OM_MAXSP], out[5 + 2 * OM_MAXSP];
+    for (int64_t i = 0; i < nn; i++) {
+      for (int v = 0; v < nvar; v++) Ui[v] = U[(int64_t)v * nn + i];
+      if (!(Ui[0] > 0.0)) return 0;
+      om_ns_node(m->nd, ph, Ui, out);
+      if (!(out[0] > 0.0) || !isfinite(out[0])) return 0;
+    }
+  }
   return 1;
 }
 

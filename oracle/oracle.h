@@ -26,7 +26,8 @@
 #define OM_MAXSP 16
 
 typedef struct {
-  int32_t model;      /* 0 gas (Euler + passive species), 1 drift-diffusion */
+  int32_t model;      /* 0 gas (Euler + passive species), 1 drift-diffusion,
+                         2 multi-species Navier-Stokes transport */
   int32_t flux;       /* gas: 0 HLLC, 1 Roe */
   int32_t limiter;    /* 0 first order, 1 minmod, 2 van Leer, 3 Sweby(beta), 4 unlimited */
   int32_t rk;         /* 1..4, low-storage table */
@@ -37,6 +38,11 @@ typedef struct {
   double gamma;
   double entropy_fix; /* Roe: Harten delta as a fraction of the Roe sound speed */
   double z[OM_MAXSP], mu[OM_MAXSP], D[OM_MAXSP];  /* drift-diffusion species */
+  /* multi-species Navier-Stokes: synthetic species data */
+  double Wk[OM_MAXSP];                 /* molar mass [kg/mol] */
+  double cpa[OM_MAXSP], cpb[OM_MAXSP], cpc[OM_MAXSP]; /* c_p = R/W (a + b t + c t^2), t = T/1000 */
+  double Sc[OM_MAXSP];                 /* Schmidt numbers */
+  double mu_ref, T_ref, Pr;            /* mu = mu_ref (T/T_ref)^0.7, lambda = mu c_p / Pr */
 } om_phys;
 
 typedef struct om_mesh om_mesh;
@@ -61,6 +67,15 @@ void om_hllc(int nd, int nsp, double gL, double gR, const double *WL, const doub
              const double *S, double *F);
 void om_roe(int nd, int nsp, double gamma, double fix, const double *WL, const double *WR,
             const double *S, double *F);
+
+/* multi-species node state from conserved U_i [nvar]: out = T, p, gamma, mu,
+ * lambda, D_1..D_N, hs_1..hs_N */
+void om_ns_node(int nd, const om_phys *ph, const double *Ui, double *out);
+/* central viscous + heat + species-diffusion flux through S (sign: to be
+ * subtracted from the convective flux) from face-end primitive data */
+void om_viscous_flux(int nd, int nsp, const double *prim_i, const double *prim_j,
+                     double rho_i, double rho_j, const double *aux_i, const double *aux_j,
+                     const double *gprim_i, const double *gprim_j, const double *S, double *Fv);
 
 int om_residual(const om_mesh *m, const om_phys *ph, const double *U, const double *E,
                 double dt, double *r);

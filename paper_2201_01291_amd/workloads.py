@@ -352,3 +352,85 @@ def serving_requests(n: int = 256, *, seed: int = 5, cell_min: float = 5e3,
         out.append(dict(id=k, kind="gas" if k % 2 == 0 else "dd", nx=side, ny=side,
                         arrival=float(arrivals[k]), seed=int(rng.integers(1 << 30))))
     return out
+
+
+# ---------------------------------------------------------------------------
+# synthetic multi-species mixture (no thermochemical tables are available)
+# ---------------------------------------------------------------------------
+
+R_GAS = 8.314462618  # J/(mol K)
+
+
+@dataclass
+class Mixture:
+    """Seeded synthetic species data for the multi-species transport model.
+
+    W      molar masses [kg/mol]
+    cp_a, cp_b, cp_c   c_p,k(T) = (R/W_k)(a + b tau + c tau^2), tau = T/1000
+    Sc     Schmidt numbers (D_k = mu / (rho Sc_k))
+    mu_ref, T_ref, Pr  mu = mu_ref (T/T_ref)^0.7, lambda = mu c_p / Pr
+    """
+    W: np.ndarray
+    cp_a: np.ndarray
+    cp_b: np.ndarray
+    cp_c: np.ndarray
+    Sc: np.ndarray
+    mu_ref: float = 1.8e-5
+    T_ref: float = 300.0
+    Pr: float = 0.72
+
+    @property
+    def n(self) -> int:
+        return int(self.W.size)
+
+
+def synthetic_mixture(nspecies: int = 9, seed: int = 3) -> Mixture:
+    rng = np.random.default_rng(seed)
+    W = np.sort(rng.uniform(0.002, 0.044, size=nspecies))
+    return Mixture(W=W, cp_a=rng.uniform(2.5, 4.0, size=nspecies),
+                   cp_b=rng.uniform(0.0, 1.0, size=nspecies),
+                   cp_c=rng.uniform(-0.2, 0.2, size=nspecies),
+                   Sc=rng.uniform(0.4, 1.2, size=nspecies))
+
+
+def ns_state(mesh: Mesh, mix: Mixture, *, seed: int = 4, lattice: int = 8,
+             theta_range=(300.0, 2000.0), rho_range=(0.2, 1.2),
+             vel=(100.0, 50.0, 25.0), cv_scale: float = 718.0) -> np.ndarray:
+    """Conserved multi-species state [rho, rho u, rho E, rho Y_1..rho Y_n].
+
+    Dirichlet(1) mass fractions, a temperature-like field theta ~ U(theta_range)
+    and a density ~ U(rho_range), each drawn on a periodic lattice^nd lattice
+    and interpolated (multi)linearly to the nodes (so Y stays on the simplex);
+    uniform velocity.  The sensible energy is set to cv_scale*(theta - 298.15)
+    J/kg -- a fixed species-independent scale, not the mixture model: the
+    temperature and pressure follow from each solver's own mixture
+    thermodynamics."""
+    rng = np.random.default_rng(seed)
+    nd = mesh.ndim
+    shape = (lattice,) * nd
+    Yl = rng.dirichlet(np.ones(mix.n), size=shape)          # [..., n]
+    Tl = rng.uniform(theta_range[0], theta_range[1], size=shape)
+    Rl = rng.uniform(rho_range[0], rho_range[1], size=shape)
+    lengths = mesh.period if mesh.period is not None else (mesh.xyz.max(1) - mesh.xyz.min(1))
+    lo = mesh.xyz.min(1)
+    t = [(mesh.xyz[a] - lo[a]) / lengths[a] * lattice for a in range(nd)]
+    i0 = [np.floor(ta).astype(np.int64) for ta in t]
+    fr = [ta - ia for ta, ia in zip(t, i0)]
+    Y = np.zeros((mix.n, mesh.nnodes))
+    theta = np.zeros(mesh.nnodes)
+    rho = np.zeros(mesh.nnodes)
+    for corner in np.ndindex(*(2,) * nd):
+        w = np.ones(mesh.nnodes)
+        idx = []
+        for a in range(nd):
+            w = w * (fr[a] if corner[a] else 1.0 - fr[a])
+            idx.append((i0[a] + corner[a]) % lattice)
+        Y += w[None, :] * Yl[tuple(idx)].T
+        theta += w * Tl[tuple(idx)]
+        rho += w * Rl[tuple(idx)]
+    Y = Y / Y.sum(axis=0, keepdims=True)
+    velv = np.tile(np.asarray(vel[:nd], dtype=np.float64)[:, None], (1, mesh.nnodes))
+    es = cv_scale * (theta - 298.15)
+    rows = [rho] + [rho * v for v in velv] + [rho * (es + 0.5 * np.sum(velv ** 2, axis=0))]
+    rows += [rho * y for y in Y]
+    return np.stack(rows)
