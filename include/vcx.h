@@ -62,7 +62,13 @@ typedef enum {
   VCX_E_STATE = -7     /* call out of order (e.g. step before state_upload) */
 } vcx_status;
 
-enum { VCX_MODEL_GAS = 0, VCX_MODEL_DRIFT_DIFFUSION = 1 };
+enum {
+  VCX_MODEL_GAS = 0,              /* Euler + passive species, ideal gas, constant gamma */
+  VCX_MODEL_DRIFT_DIFFUSION = 1,  /* charged species in a prescribed field */
+  VCX_MODEL_NAVIER_STOKES = 2     /* multi-species Navier-Stokes transport (eq. ns_reactive
+                                     without sources): HLLC + viscous, heat and species
+                                     diffusion; temperature from the sensible energy */
+};
 enum { VCX_FLUX_HLLC = 0, VCX_FLUX_ROE = 1 };
 enum {
   VCX_LIM_FIRST_ORDER = 0, /* zero slope / Psi = 0 (first-order upwind) */
@@ -86,7 +92,8 @@ typedef struct {
   int32_t limiter;    /* VCX_LIM_* */
   int32_t rk_stages;  /* 1..4 (table rk_coeffs) */
   int32_t nspecies;   /* gas: passive species (0, 2 or 9 supported);
-                         drift-diffusion: charged species (1..4) */
+                         drift-diffusion: charged species (1 or 2);
+                         Navier-Stokes: species (2 or 9), HLLC only */
   int32_t closure;    /* 1: node-flux closure on boundary nodes */
   int32_t precision;  /* VCX_PREC_* */
   int32_t reserved;
@@ -98,6 +105,15 @@ typedef struct {
   double z[VCX_MAX_SPECIES];   /* drift-diffusion charge sign per species */
   double mu[VCX_MAX_SPECIES];  /* mobility [m^2/(V s)] */
   double D[VCX_MAX_SPECIES];   /* diffusion coefficient [m^2/s] */
+  /* Navier-Stokes mixture: per species molar mass W [kg/mol], heat capacity
+   * c_p(T) = (R/W)(cpa + cpb t + cpc t^2) with t = T/1000, Schmidt number;
+   * mu = mu_ref (T/T_ref)^0.7, lambda = mu c_p / Pr, D_k = mu / (rho Sc_k).
+   * Sensible enthalpies are taken from 298.15 K; the total non-chemical energy
+   * is rho (e_s + |u|^2/2) with e_s = sum Y_k (h_s,k - R T / W_k). */
+  double Wk[VCX_MAX_SPECIES];
+  double cpa[VCX_MAX_SPECIES], cpb[VCX_MAX_SPECIES], cpc[VCX_MAX_SPECIES];
+  double Sc[VCX_MAX_SPECIES];
+  double mu_ref, T_ref, Pr;
 } vcx_physics;
 
 typedef struct vcx_mesh_s *vcx_mesh;

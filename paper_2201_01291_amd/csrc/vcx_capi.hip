@@ -53,6 +53,8 @@ struct vcx_solver_s {
   vcx_mesh mesh = nullptr;
   vcx_physics ph{};
   int nd = 0, nvar = 0, nr = 0;
+  int nw = 0;   // rows of a state buffer (conserved, pressure, Navier-Stokes primitives and aux)
+  int ngf = 0;  // fields whose nodal gradients are computed
   double* W[2] = {nullptr, nullptr};
   int cur = 0;
   double* G = nullptr;
@@ -147,10 +149,27 @@ struct KernelTable {
   size_t (*lds_grad)(int maxn, int maxc);
   size_t (*lds_flux)(int maxn, int maxc);
   vcx_status (*allow_lds)(size_t grad_bytes, size_t flux_bytes);
+  vcx_status (*aux)(vcx_solver, double* W);
+  int nw, ngf;
 };
 
 static DtParts dt_parts(vcx_solver s) {
   return DtParts{s->dtp_node, s->n_dtp_node, s->dtp_step, s->n_dtp_step};
+}
+
+static MixParams mix_params(const vcx_physics& ph) {
+  MixParams mp{};
+  for (int k = 0; k < 16; ++k) {
+    mp.W[k] = ph.Wk[k] > 0.0 ? ph.Wk[k] : 1.0;
+    mp.a[k] = ph.cpa[k];
+    mp.b[k] = ph.cpb[k];
+    mp.c[k] = ph.cpc[k];
+    mp.Sc[k] = ph.Sc[k] > 0.0 ? ph.Sc[k] : 1.0;
+  }
+  mp.mu_ref = ph.mu_ref;
+  mp.T_ref = ph.T_ref > 0.0 ? ph.T_ref : 300.0;
+  mp.Pr = ph.Pr > 0.0 ? ph.Pr : 1.0;
+  return mp;
 }
 
 static DtCoef dt_coef(const vcx_physics& ph) {
@@ -167,22 +186,28 @@ static DtCoef dt_coef(const vcx_physics& ph) {
 
 template <int MODEL, int ND, int NSP, int FLUX, typename CT>
 struct Impl {
-  static constexpr int NVAR = MODEL == 0 ? 2 + ND + NSP : NSP;
-  static constexpr int NR = MODEL == 0 ? NVAR + 1 : NVAR;
+  static constexpr int NVAR = MODEL == 1 ? NSP : 2 + ND + NSP;
+  static constexpr int NR = MODEL == 1 ? NVAR : NVAR + 1;
   static constexpr int NV = ND + 1;
+  static constexpr int NP = MODEL == 2 ? ND + 1 + NSP : 0;   // primitives (u, T, Y)
+  static constexpr int NA = MODEL == 2 ? 3 + 2 * NSP : 0;    // gamma, mu, lambda, D_k, hs_k
+  static constexpr int NGF = NR + NP;                        // fields with gradients
+  static constexpr int NW = NR + NP + NA;                    // rows of a state buffer
 
   static size_t lds_grad(int maxn, int maxc) {
-    return sizeof(double) * ((size_t)(NR + ND) * maxn + (size_t)NR * ND * maxc);
+    return sizeof(double) * ((size_t)(NGF + ND) * maxn + (size_t)NGF * ND * maxc);
   }
   static size_t lds_flux(int maxn, int maxc) {
     size_t dbl = sizeof(double) * ((size_t)ND * maxn + (size_t)NV * NVAR * maxc);
-    size_t ct = MODEL == 0 ? (size_t)(NR + NR * ND) * maxn : (size_t)(NSP + NSP * ND + ND) * maxn;
+    size_t ct = MODEL == 0   ? (size_t)(NR + NR * ND) * maxn
+                : MODEL == 1 ? (size_t)(NSP + NSP * ND + ND) * maxn
+                             : (size_t)(NW + NGF * ND) * maxn;
     return dbl + sizeof(CT) * ct;
   }
   static vcx_status grad(vcx_solver s, const double* Win, const GradCtl& gc) {
     const DevMesh& m = s->mesh->d;
     return launch(s, "gradient", [&] {
-      hipLaunchKernelGGL((k_grad_tile<ND, NR>), dim3(xcd_grid(m.ntiles)), dim3(s->tile_block),
+      hipLaunchKernelGGL((k_grad_tile<ND, NGF>), dim3(xcd_grid(m.ntiles)), dim3(s->tile_block),
                          s->lds_grad, s->mesh->stream, m, Win, s->G, s->PG, gc);
     });
   }
@@ -190,9 +215,21 @@ struct Impl {
     const DevMesh& m = s->mesh->d;
     if (m.nshared == 0) return VCX_OK;
     return launch(s, "gradient_shared", [&] {
-      hipLaunchKernelGGL((k_grad_shared<ND, NR>), dim3((m.nshared + kNodeBlock - 1) / kNodeBlock),
+      hipLaunchKernelGGL((k_grad_shared<ND, NGF>), dim3((m.nshared + kNodeBlock - 1) / kNodeBlock),
                          dim3(kNodeBlock), 0, s->mesh->stream, m, (const double*)s->PG, s->G);
     });
+  }
+  static vcx_status aux(vcx_solver s, double* W) {
+    const DevMesh& m = s->mesh->d;
+    if constexpr (MODEL == 0) {
+      hipLaunchKernelGGL(k_pressure, dim3((m.nn + 255) / 256), dim3(256), 0, s->mesh->stream, W, m.nn,
+                         m.nd, NSP, s->ph.gamma);
+    } else if constexpr (MODEL == 2) {
+      hipLaunchKernelGGL((k_ns_aux<ND, NSP>), dim3((m.nn + 255) / 256), dim3(256), 0, s->mesh->stream,
+                         W, m.nn, mix_params(s->ph));
+    }
+    VCX_HIP(hipGetLastError());
+    return VCX_OK;
   }
   static vcx_status flux(vcx_solver s, const double* Win, const Finish& f, double dt_host) {
     const DevMesh& m = s->mesh->d;
@@ -204,6 +241,12 @@ struct Impl {
         hipLaunchKernelGGL((k_flux_gas<ND, NSP, FLUX, CT>), dim3(xcd_grid(m.ntiles)),
                            dim3(s->tile_block), s->lds_flux, st, m, Win, (const double*)s->G,
                            s->PR, gp, f, parts);
+      });
+    } else if constexpr (MODEL == 2) {
+      GasParams gp{s->ph.gamma, s->ph.beta, s->ph.entropy_fix, s->ph.limiter};
+      return launch(s, "flux", [&] {
+        hipLaunchKernelGGL((k_flux_ns<ND, NSP, CT>), dim3(xcd_grid(m.ntiles)), dim3(s->tile_block),
+                           s->lds_flux, st, m, Win, (const double*)s->G, s->PR, gp, f, parts);
       });
     } else {
       DDParams pp{};
@@ -233,17 +276,21 @@ struct Impl {
     const DevMesh& m = s->mesh->d;
     DtParts parts = dt_parts(s);
     DtCoef dc = dt_coef(s->ph);
+    MixParams mp = mix_params(s->ph);
     return launch(s, "node_dt", [&] {
       hipLaunchKernelGGL((k_node_dt<ND, NSP, MODEL>), dim3(s->n_dtp_node), dim3(kNodeBlock), 0,
-                         s->mesh->stream, m, W, (const double*)s->E, dc, parts, s->sc);
+                         s->mesh->stream, m, W, (const double*)s->E, dc, mp, parts, s->sc);
     });
   }
   // Allow dynamic LDS above the 64 KiB default for the two tile kernels.
   static vcx_status allow_lds(size_t grad_bytes, size_t flux_bytes) {
-    VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_grad_tile<ND, NR>),
+    VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_grad_tile<ND, NGF>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)grad_bytes));
     if constexpr (MODEL == 0)
       VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_gas<ND, NSP, FLUX, CT>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)flux_bytes));
+    else if constexpr (MODEL == 2)
+      VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_ns<ND, NSP, CT>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)flux_bytes));
     else
       VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_dd<ND, NSP, CT>),
@@ -251,15 +298,15 @@ struct Impl {
     return VCX_OK;
   }
   static const KernelTable* table() {
-    static const KernelTable t{&grad, &grad_complete, &flux, &update_shared, &node_dt,
-                               &lds_grad, &lds_flux, &allow_lds};
+    static const KernelTable t{&grad,      &grad_complete, &flux, &update_shared, &node_dt,
+                               &lds_grad,  &lds_flux,      &allow_lds, &aux, NW, NGF};
     return &t;
   }
 };
 
 template <int MODEL, int ND, int NSP>
 static const KernelTable* pick_flux_prec(int flux, int prec) {
-  if (MODEL == 1) return prec == VCX_PREC_MIXED ? Impl<MODEL, ND, NSP, 0, float>::table()
+  if (MODEL != 0) return prec == VCX_PREC_MIXED ? Impl<MODEL, ND, NSP, 0, float>::table()
                                                 : Impl<MODEL, ND, NSP, 0, double>::table();
   if (flux == VCX_FLUX_HLLC)
     return prec == VCX_PREC_MIXED ? Impl<MODEL, ND, NSP, 0, float>::table()
@@ -275,6 +322,14 @@ static const KernelTable* pick_nd(const vcx_physics& ph) {
       case 0: return pick_flux_prec<0, ND, 0>(ph.flux, ph.precision);
       case 2: return pick_flux_prec<0, ND, 2>(ph.flux, ph.precision);
       case 9: return pick_flux_prec<0, ND, 9>(ph.flux, ph.precision);
+      default: return nullptr;
+    }
+  }
+  if (ph.model == VCX_MODEL_NAVIER_STOKES) {
+    if (ph.flux != VCX_FLUX_HLLC) return nullptr;
+    switch (ph.nspecies) {
+      case 2: return pick_flux_prec<2, ND, 2>(0, ph.precision);
+      case 9: return pick_flux_prec<2, ND, 9>(0, ph.precision);
       default: return nullptr;
     }
   }
@@ -521,8 +576,16 @@ extern "C" vcx_status vcx_solver_create(vcx_mesh mesh, const vcx_physics* phys, 
   *out = nullptr;
   const vcx_physics& ph = *phys;
   const int nd = mesh->h.nd;
-  if (ph.model != VCX_MODEL_GAS && ph.model != VCX_MODEL_DRIFT_DIFFUSION)
+  if (ph.model != VCX_MODEL_GAS && ph.model != VCX_MODEL_DRIFT_DIFFUSION &&
+      ph.model != VCX_MODEL_NAVIER_STOKES)
     return fail(VCX_E_ARG, "unknown model");
+  if (ph.model == VCX_MODEL_NAVIER_STOKES) {
+    for (int k = 0; k < ph.nspecies && k < VCX_MAX_SPECIES; ++k)
+      if (!(ph.Wk[k] > 0.0) || !(ph.Sc[k] > 0.0))
+        return fail(VCX_E_ARG, "Navier-Stokes species need positive molar masses and Schmidt numbers");
+    if (!(ph.mu_ref >= 0.0) || !(ph.T_ref > 0.0) || !(ph.Pr > 0.0))
+      return fail(VCX_E_ARG, "Navier-Stokes needs mu_ref >= 0, T_ref > 0, Pr > 0");
+  }
   if (ph.rk_stages < 1 || ph.rk_stages > 4) return fail(VCX_E_ARG, "rk_stages must be 1..4");
   if (ph.limiter < 0 || ph.limiter > 4) return fail(VCX_E_ARG, "unknown limiter");
   if (ph.precision != VCX_PREC_FP64 && ph.precision != VCX_PREC_MIXED)
@@ -543,8 +606,10 @@ extern "C" vcx_status vcx_solver_create(vcx_mesh mesh, const vcx_physics* phys, 
   s->mesh = mesh;
   s->ph = ph;
   s->nd = nd;
-  s->nvar = ph.model == VCX_MODEL_GAS ? 2 + nd + ph.nspecies : ph.nspecies;
-  s->nr = ph.model == VCX_MODEL_GAS ? s->nvar + 1 : s->nvar;
+  s->nvar = ph.model == VCX_MODEL_DRIFT_DIFFUSION ? ph.nspecies : 2 + nd + ph.nspecies;
+  s->nr = ph.model == VCX_MODEL_DRIFT_DIFFUSION ? s->nvar : s->nvar + 1;
+  s->nw = kt->nw;
+  s->ngf = kt->ngf;
   s->kt = kt;
   const DevMesh& d = mesh->d;
   s->lds_grad = kt->lds_grad(d.max_tile_nodes, d.max_tile_cells);
@@ -565,15 +630,15 @@ extern "C" vcx_status vcx_solver_create(vcx_mesh mesh, const vcx_physics* phys, 
   }
   s->tile_block = std::min(256, ((d.max_tile_cells + 63) / 64) * 64);
   const size_t nn = (size_t)d.nn, P = (size_t)d.nslots;
-  const size_t rows_io = std::max<size_t>((size_t)s->nr * nd, s->nvar);
+  const size_t rows_io = std::max<size_t>((size_t)s->ngf * nd, s->nw);
   vcx_status st = VCX_OK;
   auto chk = [&](vcx_status x) {
     if (st == VCX_OK) st = x;
   };
-  chk(dmalloc(&s->W[0], (size_t)s->nr * nn));
-  chk(dmalloc(&s->W[1], (size_t)s->nr * nn));
-  chk(dmalloc(&s->G, (size_t)s->nr * nd * nn));
-  chk(dmalloc(&s->PG, (size_t)s->nr * nd * P));
+  chk(dmalloc(&s->W[0], (size_t)s->nw * nn));
+  chk(dmalloc(&s->W[1], (size_t)s->nw * nn));
+  chk(dmalloc(&s->G, (size_t)s->ngf * nd * nn));
+  chk(dmalloc(&s->PG, (size_t)s->ngf * nd * P));
   chk(dmalloc(&s->PR, (size_t)s->nvar * P));
   chk(dmalloc(&s->io, rows_io * nn));
   chk(dmalloc(&s->rbuf, rows_io * nn));
@@ -654,11 +719,7 @@ extern "C" vcx_status vcx_state_upload(vcx_solver s, const double* U, int is_dev
   hipLaunchKernelGGL(k_gather_rows, dim3((d.nn + 255) / 256), dim3(256), 0, s->mesh->stream,
                      d.perm, (const double*)s->io, s->W[s->cur], d.nn, s->nvar);
   VCX_HIP(hipGetLastError());
-  if (s->ph.model == VCX_MODEL_GAS) {
-    hipLaunchKernelGGL(k_pressure, dim3((d.nn + 255) / 256), dim3(256), 0, s->mesh->stream,
-                       s->W[s->cur], d.nn, d.nd, s->ph.nspecies, s->ph.gamma);
-    VCX_HIP(hipGetLastError());
-  }
+  VCX_TRY(s->kt->aux(s, s->W[s->cur]));
   s->has_state = true;
   return reset_scalars(s, 0.0, true);
 }
@@ -690,6 +751,7 @@ static Finish make_finish(vcx_solver s) {
   f.PG = s->PG;
   f.E = s->E;
   f.dc = dt_coef(s->ph);
+  f.mix = mix_params(s->ph);
   f.closure = s->ph.closure;
   return f;
 }

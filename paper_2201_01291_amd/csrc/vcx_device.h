@@ -90,9 +90,10 @@ __device__ inline void normal_flux(const T* W, const T* n, T* F, T& q) {
 }
 
 // HLLC flux through the area vector S (result scaled by |S|), Davis wave
-// speeds, star states of the paper's multicomponent HLLC.
+// speeds, star states of the paper's multicomponent HLLC; gL, gR: ratio of
+// specific heats of the left and right states.
 template <int ND, int NSP, typename T>
-__device__ inline void hllc_flux(const T* WL, const T* WR, const T* S, T gamma, T* F) {
+__device__ inline void hllc_flux(const T* WL, const T* WR, const T* S, T gL, T gR, T* F) {
   constexpr int NV = 2 + ND + NSP;
   T A2 = T(0);
   for (int d = 0; d < ND; ++d) A2 += S[d] * S[d];
@@ -103,7 +104,7 @@ __device__ inline void hllc_flux(const T* WL, const T* WR, const T* S, T gamma, 
   normal_flux<ND, NSP>(WL, n, FL, qL);
   normal_flux<ND, NSP>(WR, n, FR, qR);
   const T rL = WL[0], rR = WR[0], pL = WL[NV], pR = WR[NV];
-  const T aL = sqrt(gamma * pL / rL), aR = sqrt(gamma * pR / rR);
+  const T aL = sqrt(gL * pL / rL), aR = sqrt(gR * pR / rR);
   const T SL = fmin(qL - aL, qR - aR), SR = fmax(qL + aL, qR + aR);
   const T mL = rL * (SL - qL), mR = rR * (SR - qR);
   const T Ss = (pR - pL + mL * qL - mR * qR) / (mL - mR);
@@ -183,6 +184,147 @@ __device__ inline void roe_flux(const T* WL, const T* WR, const T* S, T gamma, T
     Dv[2 + ND + k] = (w1 + w2 + w5) * (wl * YL + wr * YR) + l2 * rho * (YR - YL);
   }
   for (int v = 0; v < NV; ++v) F[v] = A * (T(0.5) * (FL[v] + FR[v]) - T(0.5) * Dv[v]);
+}
+
+// ---------------------------------------------------------------------------
+// multi-species mixture (species data supplied by the caller)
+// ---------------------------------------------------------------------------
+
+struct MixParams {
+  double W[16], a[16], b[16], c[16], Sc[16];
+  double mu_ref, T_ref, Pr;
+};
+
+constexpr double kRgas = 8.314462618;
+constexpr double kT0 = 298.15;
+constexpr int kNewtonIters = 10;
+
+// Sensible energy e_s(T) = sum_k Y_k (h_s,k(T) - R_k T) and c_v(T), with
+// h_s,k = R_k (T - T0)(a + b (T + T0)/2000 + c (T^2 + T T0 + T0^2)/3e6),
+// the integral of c_p,k = R_k (a + b T/1000 + c (T/1000)^2) from T0.
+template <int NSP>
+__device__ inline void mix_es_cv(const MixParams& mp, const double* Y, double T, double& es, double& cv) {
+  const double dT = T - kT0, sT = T + kT0, qT = T * T + T * kT0 + kT0 * kT0, t = T * 1e-3;
+  es = 0.0;
+  cv = 0.0;
+#pragma unroll
+  for (int k = 0; k < NSP; ++k) {
+    const double Rk = kRgas / mp.W[k];
+    const double hs = Rk * dT * (mp.a[k] + mp.b[k] * sT * (1.0 / 2000.0) + mp.c[k] * qT * (1.0 / 3.0e6));
+    es += Y[k] * (hs - Rk * T);
+    cv += Y[k] * Rk * (mp.a[k] - 1.0 + t * (mp.b[k] + mp.c[k] * t));
+  }
+}
+
+// Node state of the multi-species model from the conserved vector u[NVAR]:
+// pressure, primitive fields prim = (velocity, T, Y) and aux = (gamma, mu,
+// lambda, D_k, h_s,k).  The temperature solves e_s(T) = E - |u|^2/2 by a
+// fixed number of Newton steps from 1000 K.  Returns false for a
+// non-physical state.
+template <int ND, int NSP>
+__device__ inline bool ns_node_state(const MixParams& mp, const double* u, double& p, double* prim,
+                                     double* aux) {
+  const double rho = u[0], ir = 1.0 / rho;
+  double ke = 0.0;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    prim[d] = u[1 + d] * ir;
+    ke += prim[d] * prim[d];
+  }
+  double Y[NSP];
+#pragma unroll
+  for (int k = 0; k < NSP; ++k) Y[k] = u[2 + ND + k] * ir;
+  const double es_target = u[1 + ND] * ir - 0.5 * ke;
+  double T = 1000.0;
+  for (int it = 0; it < kNewtonIters; ++it) {
+    double es, cv;
+    mix_es_cv<NSP>(mp, Y, T, es, cv);
+    T -= (es - es_target) / cv;
+  }
+  double r = 0.0, cp = 0.0;
+  const double t = T * 1e-3;
+#pragma unroll
+  for (int k = 0; k < NSP; ++k) {
+    const double Rk = kRgas / mp.W[k];
+    r += Y[k] * Rk;
+    cp += Y[k] * Rk * (mp.a[k] + t * (mp.b[k] + mp.c[k] * t));
+  }
+  p = rho * r * T;
+  prim[ND] = T;
+#pragma unroll
+  for (int k = 0; k < NSP; ++k) prim[ND + 1 + k] = Y[k];
+  const double mu = mp.mu_ref * pow(T / mp.T_ref, 0.7);
+  aux[0] = cp / (cp - r);
+  aux[1] = mu;
+  aux[2] = mu * cp / mp.Pr;
+  const double dT = T - kT0, sT = T + kT0, qT = T * T + T * kT0 + kT0 * kT0;
+#pragma unroll
+  for (int k = 0; k < NSP; ++k) {
+    aux[3 + k] = mu / (rho * mp.Sc[k]);
+    aux[3 + NSP + k] = kRgas / mp.W[k] * dT *
+                       (mp.a[k] + mp.b[k] * sT * (1.0 / 2000.0) + mp.c[k] * qT * (1.0 / 3.0e6));
+  }
+  return rho > 0.0 && T > 0.0 && isfinite(T) && isfinite(p);
+}
+
+// Central diffusive flux through S of the multi-species Navier-Stokes
+// equations: Newtonian stress with Stokes' hypothesis, Fourier heat flux plus
+// species enthalpy transport, Fick species fluxes with the correction velocity
+// V_c = sum_k D_k grad Y_k.  Face values are means of the two nodes (pi, pj:
+// prim rows; ai, aj: aux rows; gi, gj: prim gradients [NP][ND]).  Writes Fv =
+// (0, tau S, u.(tau S) - q.S, -J_k.S), to be subtracted from the convective
+// flux.
+template <int ND, int NSP, typename T>
+__device__ inline void viscous_flux(const T* pi, const T* pj, T rhoi, T rhoj, const T* ai,
+                                    const T* aj, const T* gi, const T* gj, const T* S, T* Fv) {
+  const T h = T(0.5);
+  const T rho = h * (rhoi + rhoj), mu = h * (ai[1] + aj[1]), lam = h * (ai[2] + aj[2]);
+  T Gu[ND][ND], div = T(0);
+#pragma unroll
+  for (int a = 0; a < ND; ++a) {
+#pragma unroll
+    for (int b = 0; b < ND; ++b) Gu[a][b] = h * (gi[a * ND + b] + gj[a * ND + b]);
+    div += Gu[a][a];
+  }
+  T utS = T(0);
+#pragma unroll
+  for (int a = 0; a < ND; ++a) {
+    T ts = T(0);
+#pragma unroll
+    for (int b = 0; b < ND; ++b) ts += (Gu[a][b] + Gu[b][a]) * S[b];
+    ts = mu * (ts - T(2.0 / 3.0) * div * S[a]);
+    Fv[1 + a] = ts;
+    utS += h * (pi[a] + pj[a]) * ts;
+  }
+  T Vc[ND];
+#pragma unroll
+  for (int d = 0; d < ND; ++d) Vc[d] = T(0);
+#pragma unroll
+  for (int k = 0; k < NSP; ++k) {
+    const T Dk = h * (ai[3 + k] + aj[3 + k]);
+#pragma unroll
+    for (int d = 0; d < ND; ++d) Vc[d] += Dk * h * (gi[(ND + 1 + k) * ND + d] + gj[(ND + 1 + k) * ND + d]);
+  }
+  T VcS = T(0), gTS = T(0);
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    VcS += Vc[d] * S[d];
+    gTS += h * (gi[ND * ND + d] + gj[ND * ND + d]) * S[d];
+  }
+  T qS = -lam * gTS;
+#pragma unroll
+  for (int k = 0; k < NSP; ++k) {
+    const T Dk = h * (ai[3 + k] + aj[3 + k]);
+    const T Yk = h * (pi[ND + 1 + k] + pj[ND + 1 + k]);
+    T gYS = T(0);
+#pragma unroll
+    for (int d = 0; d < ND; ++d) gYS += h * (gi[(ND + 1 + k) * ND + d] + gj[(ND + 1 + k) * ND + d]) * S[d];
+    const T JS = -rho * (Dk * gYS - Yk * VcS);
+    qS += h * (ai[3 + NSP + k] + aj[3 + NSP + k]) * JS;
+    Fv[2 + ND + k] = -JS;
+  }
+  Fv[0] = T(0);
+  Fv[1 + ND] = utS - qS;
 }
 
 }  // namespace vcx

@@ -204,6 +204,25 @@ __device__ inline double node_dt(const DevMesh& m, const DtCoef& c, const double
   }
 }
 
+// Multi-species candidate: convective CFL dx/(|u| + a) with the mixture
+// sound speed, diffusive F dx^2 / max(nu, lambda/(rho c_p), D_k) where
+// lambda/(rho c_p) = mu/(rho Pr).
+template <int ND, int NSP>
+__device__ inline double ns_node_dt(double dx, const DtCoef& c, const MixParams& mp, double rho,
+                                    const double* prim, double p, const double* aux, bool ok) {
+  if (!ok) return -1.0;
+  double uu = 0.0;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) uu += prim[d] * prim[d];
+  const double lam = sqrt(uu) + sqrt(aux[0] * p / rho);
+  double dm = fmax(aux[1] / rho, aux[1] / (rho * mp.Pr));
+#pragma unroll
+  for (int k = 0; k < NSP; ++k) dm = fmax(dm, aux[3 + k]);
+  double t = c.cfl * dx / lam;
+  if (dm > 0.0) t = fmin(t, c.fourier * dx * dx / dm);
+  return t;
+}
+
 // ---------------------------------------------------------------------------
 // gradient: per cell  g_tau = sum_k W_k S_k ; per node  G_i = -1/(nd nv V_i) sum g_tau
 // A node whose cells all lie in the tile gets G directly; a node shared with
@@ -263,24 +282,31 @@ __global__ void __launch_bounds__(256) k_grad_tile(DevMesh m, const double* __re
     }
   }
   __syncthreads();
+  // components in chunks of JC to bound register use for many fields
+  constexpr int JC = NC <= 24 ? NC : 12;
   for (int q = threadIdx.x; q < ns; q += blockDim.x) {
-    double acc[NC];
-#pragma unroll
-    for (int j = 0; j < NC; ++j) acc[j] = 0.0;
     const int p0 = m.slot_inc[s0 + q], p1 = m.slot_inc[s0 + q + 1];
-    for (int p = p0; p < p1; ++p) {
-      const int lc = m.inc[p] >> 2;
-#pragma unroll
-      for (int j = 0; j < NC; ++j) acc[j] += sC[j * maxc + lc];
-    }
     const int sv = m.slot_node[s0 + q];
-    if (sv >= 0) {
-      const double coef = -m.inv_vol[sv] / double(ND * NV);
+    const double coef = sv >= 0 ? -m.inv_vol[sv] / double(ND * NV) : 0.0;
+    for (int j0 = 0; j0 < NC; j0 += JC) {
+      double acc[JC];
 #pragma unroll
-      for (int j = 0; j < NC; ++j) G[(size_t)j * m.nn + sv] = coef * acc[j];
-    } else {
+      for (int jj = 0; jj < JC; ++jj) acc[jj] = 0.0;
+      for (int p = p0; p < p1; ++p) {
+        const int lc = m.inc[p] >> 2;
 #pragma unroll
-      for (int j = 0; j < NC; ++j) PG[(size_t)(s0 + q) * NC + j] = acc[j];
+        for (int jj = 0; jj < JC; ++jj)
+          if (j0 + jj < NC) acc[jj] += sC[(j0 + jj) * maxc + lc];
+      }
+      if (sv >= 0) {
+#pragma unroll
+        for (int jj = 0; jj < JC; ++jj)
+          if (j0 + jj < NC) G[(size_t)(j0 + jj) * m.nn + sv] = coef * acc[jj];
+      } else {
+#pragma unroll
+        for (int jj = 0; jj < JC; ++jj)
+          if (j0 + jj < NC) PG[(size_t)(s0 + q) * NC + j0 + jj] = acc[jj];
+      }
     }
   }
 }
@@ -300,6 +326,36 @@ __device__ inline void shared_gradient(const DevMesh& m, const double* __restric
   }
 #pragma unroll
   for (int j = 0; j < NC; ++j) out[j] *= coef;
+}
+
+// Stage the NC gradient components of the tile's q-th node into LDS: read G
+// for a tile-owned node, gather the slot partials of a shared node.
+template <int NC, int ND, typename CT>
+__device__ inline void stage_gradient(const DevMesh& m, const double* __restrict__ G,
+                                      const double* __restrict__ PG, int sv, int2 run, CT* sG,
+                                      int maxn, int q) {
+  if (sv >= 0) {
+#pragma unroll 4
+    for (int j = 0; j < NC; ++j) sG[j * maxn + q] = CT(G[(size_t)j * m.nn + sv]);
+    return;
+  }
+  const int g = ~sv;
+  const double coef = -m.inv_vol[g] / double(ND * (ND + 1));
+  constexpr int JC = NC <= 24 ? NC : 12;
+  for (int j0 = 0; j0 < NC; j0 += JC) {
+    double acc[JC];
+#pragma unroll
+    for (int jj = 0; jj < JC; ++jj) acc[jj] = 0.0;
+    for (int p = run.x; p < run.y; ++p) {
+      const double* src = PG + (size_t)m.slots_of[p] * NC + j0;
+#pragma unroll
+      for (int jj = 0; jj < JC; ++jj)
+        if (j0 + jj < NC) acc[jj] += src[jj];
+    }
+#pragma unroll
+    for (int jj = 0; jj < JC; ++jj)
+      if (j0 + jj < NC) sG[(j0 + jj) * maxn + q] = CT(coef * acc[jj]);
+  }
 }
 
 // complete G on the shared nodes (gradient output only; the time loop reads
@@ -332,6 +388,7 @@ struct Finish {
   const double* E;      // field (drift-diffusion)
   DevScalars* sc;       // null: residual only
   DtCoef dc;
+  MixParams mix;        // Navier-Stokes species data
   double alpha;
   int closure, final_stage, residual_only;
 };
@@ -345,8 +402,8 @@ __device__ inline double finish_node(const DevMesh& m, const Finish& f, int i, b
       double Sb[ND];
 #pragma unroll
       for (int d = 0; d < ND; ++d) Sb[d] = m.bnd_S[(size_t)d * m.nb + bi];
-      if constexpr (MODEL == 0) {
-        // node flux F(W_i) . S_i^b
+      if constexpr (MODEL != 1) {
+        // node flux F(W_i) . S_i^b (inviscid part for Navier-Stokes)
         double Wi[NVAR + 1];
 #pragma unroll
         for (int v = 0; v <= NVAR; ++v) Wi[v] = f.Win[(size_t)v * m.nn + i];
@@ -405,6 +462,22 @@ __device__ inline double finish_node(const DevMesh& m, const Finish& f, int i, b
     f.Wout[(size_t)NVAR * m.nn + i] = p;
     ok = u[0] > 0.0 && p > 0.0;
   }
+  if constexpr (MODEL == 2) {
+    // node aux of the new state: temperature, pressure, primitives, transport
+    constexpr int NP = ND + 1 + NSP, NA = 3 + 2 * NSP;
+    double prim[NP], aux[NA];
+    ok = ns_node_state<ND, NSP>(f.mix, u, p, prim, aux);
+    f.Wout[(size_t)NVAR * m.nn + i] = p;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) f.Wout[(size_t)(NVAR + 1 + q) * m.nn + i] = prim[q];
+#pragma unroll
+    for (int q = 0; q < NA; ++q) f.Wout[(size_t)(NVAR + 1 + NP + q) * m.nn + i] = aux[q];
+#pragma unroll
+    for (int v = 0; v < NVAR; ++v) ok = ok && isfinite(u[v]);
+    if (!f.final_stage) return INFINITY;
+    if (!ok) atomicOr(&f.sc->flag, 1);
+    return ns_node_dt<ND, NSP>(m.dxmin[i], f.dc, f.mix, u[0], prim, p, aux, ok);
+  }
 #pragma unroll
   for (int v = 0; v < NVAR; ++v) ok = ok && isfinite(u[v]);
   if (!f.final_stage) return INFINITY;
@@ -443,15 +516,7 @@ __global__ void VCX_FLUX_BOUNDS k_flux_gas(DevMesh m, const double* __restrict__
     const int g = slot_node_id(sv);
 #pragma unroll
     for (int v = 0; v < NR; ++v) sW[v * maxn + q] = CT(W[(size_t)v * m.nn + g]);
-    if (sv >= 0) {
-#pragma unroll
-      for (int j = 0; j < NR * ND; ++j) sG[j * maxn + q] = CT(G[(size_t)j * m.nn + g]);
-    } else {
-      double gr[NR * ND];
-      shared_gradient<NR * ND, ND>(m, f.PG, g, m.slot_run[s0 + q], gr);
-#pragma unroll
-      for (int j = 0; j < NR * ND; ++j) sG[j * maxn + q] = CT(gr[j]);
-    }
+    stage_gradient<NR * ND, ND, CT>(m, G, f.PG, sv, m.slot_run[s0 + q], sG, maxn, q);
 #pragma unroll
     for (int d = 0; d < ND; ++d) sX[d * maxn + q] = m.x[(size_t)d * m.nn + g];
   }
@@ -498,7 +563,7 @@ __global__ void VCX_FLUX_BOUNDS k_flux_gas(DevMesh m, const double* __restrict__
       }
       CT F[NVAR];
       if constexpr (FLUX == 0)
-        hllc_flux<ND, NSP, CT>(WL, WR, S, gamma, F);
+        hllc_flux<ND, NSP, CT>(WL, WR, S, gamma, gamma, F);
       else
         roe_flux<ND, NSP, CT>(WL, WR, S, gamma, fix, F);
 #pragma unroll
@@ -575,15 +640,7 @@ __global__ void VCX_FLUX_BOUNDS k_flux_dd(DevMesh m, const double* __restrict__ 
     const int g = slot_node_id(sv);
 #pragma unroll
     for (int s = 0; s < NS; ++s) sU[s * maxn + q] = CT(U[(size_t)s * m.nn + g]);
-    if (sv >= 0) {
-#pragma unroll
-      for (int j = 0; j < NS * ND; ++j) sG[j * maxn + q] = CT(G[(size_t)j * m.nn + g]);
-    } else {
-      double gr[NS * ND];
-      shared_gradient<NS * ND, ND>(m, f.PG, g, m.slot_run[s0 + q], gr);
-#pragma unroll
-      for (int j = 0; j < NS * ND; ++j) sG[j * maxn + q] = CT(gr[j]);
-    }
+    stage_gradient<NS * ND, ND, CT>(m, G, f.PG, sv, m.slot_run[s0 + q], sG, maxn, q);
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
       sX[d * maxn + q] = m.x[(size_t)d * m.nn + g];
@@ -679,13 +736,163 @@ __global__ void VCX_FLUX_BOUNDS k_flux_dd(DevMesh m, const double* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
+// multi-species Navier-Stokes flux pass: MUSCL on (U, p), HLLC with each
+// side's own gamma, minus the central diffusive flux
+// W rows: U [NVAR], p, prim (velocity, T, Y) [NP], aux [NA]; gradients of the
+// first NR + NP rows.
+// ---------------------------------------------------------------------------
+
+template <int ND, int NSP, typename CT>
+__global__ void VCX_FLUX_BOUNDS k_flux_ns(DevMesh m, const double* __restrict__ W,
+                                          const double* __restrict__ G,
+                                          double* __restrict__ PR, GasParams gp, Finish f,
+                                          DtParts parts) {
+  constexpr int NV = ND + 1, NVAR = 2 + ND + NSP, NR = NVAR + 1, NE = Edges<ND>::NE;
+  constexpr int NP = ND + 1 + NSP, NA = 3 + 2 * NSP, NG = NR + NP;
+  if (step_inactive(f.sc)) return;
+  const int t = xcd_tile(m.ntiles);
+  if (t >= m.ntiles) return;
+  extern __shared__ double lds[];
+  const int maxn = m.max_tile_nodes, maxc = m.max_tile_cells;
+  double* sX = lds;                                        // [ND][maxn]
+  double* sR = sX + ND * maxn;                             // [NV*NVAR][maxc]
+  CT* sW = reinterpret_cast<CT*>(sR + NV * NVAR * maxc);   // [NR + NP + NA][maxn]
+  CT* sG = sW + (NR + NP + NA) * maxn;                     // [NG*ND][maxn]
+  const int c0 = m.tile_cell[t], nc = m.tile_cell[t + 1] - c0;
+  const int s0 = m.tile_slot[t], ns = m.tile_slot[t + 1] - s0;
+  for (int q = threadIdx.x; q < ns; q += blockDim.x) {
+    const int sv = m.slot_node[s0 + q];
+    const int g = slot_node_id(sv);
+#pragma unroll 4
+    for (int v = 0; v < NR + NP + NA; ++v) sW[v * maxn + q] = CT(W[(size_t)v * m.nn + g]);
+    stage_gradient<NG * ND, ND, CT>(m, G, f.PG, sv, m.slot_run[s0 + q], sG, maxn, q);
+#pragma unroll
+    for (int d = 0; d < ND; ++d) sX[d * maxn + q] = m.x[(size_t)d * m.nn + g];
+  }
+  __syncthreads();
+  const CT beta = CT(gp.beta);
+  for (int lc = threadIdx.x; lc < nc; lc += blockDim.x) {
+    const int c = c0 + lc;
+    int l[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) l[k] = m.lconn[(size_t)k * m.nc + c];
+    double e[ND][ND], Sd[NV][ND];
+    cell_rel_coords<ND>(m, sX, maxn, l, m.shift[c], e);
+    simplex_normals<ND>(e, Sd);
+    double acc[NV][NVAR];
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+#pragma unroll
+      for (int v = 0; v < NVAR; ++v) acc[k][v] = 0.0;
+    for (int ed = 0; ed < NE; ++ed) {
+      const int a = Edges<ND>::a(ed), b = Edges<ND>::b(ed);
+      const int la = l[a], lb = l[b];
+      CT S[ND], dx[ND];
+#pragma unroll
+      for (int d = 0; d < ND; ++d) {
+        S[d] = CT((Sd[a][d] - Sd[b][d]) * (1.0 / double(ND * NV)));
+        dx[d] = CT((a == 0 ? 0.0 : -e[a - 1][d]) + e[b - 1][d]);
+      }
+      CT WL[NR], WR[NR];
+#pragma unroll
+      for (int v = 0; v < NR; ++v) {
+        const CT wi = sW[v * maxn + la], wj = sW[v * maxn + lb];
+        CT gi = CT(0), gj = CT(0);
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+          gi += sG[(v * ND + d) * maxn + la] * dx[d];
+          gj += sG[(v * ND + d) * maxn + lb] * dx[d];
+        }
+        const CT delta = wj - wi;
+        const CT dli = CT(2) * gi - delta, djk = CT(2) * gj - delta;
+        WL[v] = wi + CT(0.5) * slope_limit<CT>(gp.limiter, beta, dli, delta);
+        WR[v] = wj - CT(0.5) * slope_limit<CT>(gp.limiter, beta, delta, djk);
+      }
+      CT F[NVAR];
+      // each side's ratio of specific heats: first aux row of its node
+      hllc_flux<ND, NSP, CT>(WL, WR, S, sW[(NR + NP) * maxn + la], sW[(NR + NP) * maxn + lb], F);
+      // diffusive part from the primitive fields, their gradients and aux
+      CT pi[NP], pj[NP], ai[NA], aj[NA], gi[NP * ND], gj[NP * ND], Fv[NVAR];
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+        pi[q] = sW[(NR + q) * maxn + la];
+        pj[q] = sW[(NR + q) * maxn + lb];
+      }
+#pragma unroll
+      for (int q = 0; q < NA; ++q) {
+        ai[q] = sW[(NR + NP + q) * maxn + la];
+        aj[q] = sW[(NR + NP + q) * maxn + lb];
+      }
+#pragma unroll
+      for (int q = 0; q < NP * ND; ++q) {
+        gi[q] = sG[(NR * ND + q) * maxn + la];
+        gj[q] = sG[(NR * ND + q) * maxn + lb];
+      }
+      viscous_flux<ND, NSP, CT>(pi, pj, sW[la], sW[lb], ai, aj, gi, gj, S, Fv);
+#pragma unroll
+      for (int v = 0; v < NVAR; ++v) {
+        const double fv = double(F[v]) - double(Fv[v]);
+        acc[a][v] += fv;
+        acc[b][v] -= fv;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+#pragma unroll
+      for (int v = 0; v < NVAR; ++v) sR[(k * NVAR + v) * maxc + lc] = acc[k][v];
+  }
+  __syncthreads();
+  double cand = INFINITY;
+  for (int q = threadIdx.x; q < ns; q += blockDim.x) {
+    double r[NVAR];
+#pragma unroll
+    for (int v = 0; v < NVAR; ++v) r[v] = 0.0;
+    const int p0 = m.slot_inc[s0 + q], p1 = m.slot_inc[s0 + q + 1];
+    for (int p = p0; p < p1; ++p) {
+      const int code = m.inc[p];
+      const int lc = code >> 2, k = code & 3;
+#pragma unroll
+      for (int v = 0; v < NVAR; ++v) r[v] += sR[(k * NVAR + v) * maxc + lc];
+    }
+    const int sv = m.slot_node[s0 + q];
+    if (sv >= 0) {
+      cand = fmin(cand, finish_node<ND, NSP, 2, NVAR>(m, f, sv, false, r));
+    } else {
+#pragma unroll
+      for (int v = 0; v < NVAR; ++v) PR[(size_t)(s0 + q) * NVAR + v] = r[v];
+    }
+  }
+  if (f.final_stage && f.sc) {
+    const double b = block_min(cand);
+    if (threadIdx.x == 0) parts.step[t] = b;
+  }
+}
+
+// multi-species node rows (p, primitives, aux) of an uploaded state
+template <int ND, int NSP>
+__global__ void __launch_bounds__(256) k_ns_aux(double* __restrict__ W, int nn, MixParams mp) {
+  constexpr int NVAR = 2 + ND + NSP, NP = ND + 1 + NSP, NA = 3 + 2 * NSP;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nn) return;
+  double u[NVAR], prim[NP], aux[NA], p;
+#pragma unroll
+  for (int v = 0; v < NVAR; ++v) u[v] = W[(size_t)v * nn + i];
+  ns_node_state<ND, NSP>(mp, u, p, prim, aux);
+  W[(size_t)NVAR * nn + i] = p;
+#pragma unroll
+  for (int q = 0; q < NP; ++q) W[(size_t)(NVAR + 1 + q) * nn + i] = prim[q];
+#pragma unroll
+  for (int q = 0; q < NA; ++q) W[(size_t)(NVAR + 1 + NP + q) * nn + i] = aux[q];
+}
+
+// ---------------------------------------------------------------------------
 // shared nodes: gather the per-tile residual partials, then finish
 // ---------------------------------------------------------------------------
 
 template <int ND, int NSP, int MODEL>
 __global__ void __launch_bounds__(256) k_update_shared(DevMesh m, const double* __restrict__ PR,
                                                        Finish f, DtParts parts) {
-  constexpr int NVAR = MODEL == 0 ? 2 + ND + NSP : NSP;
+  constexpr int NVAR = MODEL == 1 ? NSP : 2 + ND + NSP;
   if (step_inactive(f.sc)) return;
   // the next step reduces the candidates written by this stage
   if (f.final_stage && f.sc && blockIdx.x == 0 && threadIdx.x == 0) f.sc->dt_src = 1;
@@ -715,16 +922,27 @@ __global__ void __launch_bounds__(256) k_update_shared(DevMesh m, const double* 
 template <int ND, int NSP, int MODEL>
 __global__ void __launch_bounds__(256) k_node_dt(DevMesh m, const double* __restrict__ W,
                                                  const double* __restrict__ E, DtCoef dc,
-                                                 DtParts parts, DevScalars* sc) {
-  constexpr int NVAR = MODEL == 0 ? 2 + ND + NSP : NSP;
+                                                 MixParams mp, DtParts parts, DevScalars* sc) {
+  constexpr int NVAR = MODEL == 1 ? NSP : 2 + ND + NSP;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   double cand = INFINITY;
   if (i < m.nn) {
     double u[NVAR];
 #pragma unroll
     for (int v = 0; v < NVAR; ++v) u[v] = W[(size_t)v * m.nn + i];
-    const double p = MODEL == 0 ? W[(size_t)NVAR * m.nn + i] : 0.0;
-    cand = node_dt<ND, NSP, MODEL>(m, dc, E, i, u, p);
+    const double p = MODEL != 1 ? W[(size_t)NVAR * m.nn + i] : 0.0;
+    if constexpr (MODEL == 2) {
+      constexpr int NP = ND + 1 + NSP, NA = 3 + 2 * NSP;
+      double prim[NP], aux[NA];
+#pragma unroll
+      for (int q = 0; q < NP; ++q) prim[q] = W[(size_t)(NVAR + 1 + q) * m.nn + i];
+#pragma unroll
+      for (int q = 0; q < NA; ++q) aux[q] = W[(size_t)(NVAR + 1 + NP + q) * m.nn + i];
+      const bool ok = u[0] > 0.0 && prim[ND] > 0.0 && isfinite(prim[ND]);
+      cand = ns_node_dt<ND, NSP>(m.dxmin[i], dc, mp, u[0], prim, p, aux, ok);
+    } else {
+      cand = node_dt<ND, NSP, MODEL>(m, dc, E, i, u, p);
+    }
   }
   const double b = block_min(cand);
   if (threadIdx.x == 0) {

@@ -19,7 +19,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libvcx.so")
 
 OK, E_ARG, E_MESH, E_OOM, E_HIP, E_UNSTABLE, E_BUSY, E_STATE = 0, -1, -2, -3, -4, -5, -6, -7
-MODEL_GAS, MODEL_DRIFT_DIFFUSION = 0, 1
+MODEL_GAS, MODEL_DRIFT_DIFFUSION, MODEL_NAVIER_STOKES = 0, 1, 2
 FLUX_HLLC, FLUX_ROE = 0, 1
 LIM_FIRST_ORDER, LIM_MINMOD, LIM_VANLEER, LIM_SWEBY, LIM_NONE = 0, 1, 2, 3, 4
 PREC_FP64, PREC_MIXED = 0, 1
@@ -48,18 +48,27 @@ class Physics(C.Structure):
                 ("beta", C.c_double), ("cfl", C.c_double), ("fourier", C.c_double),
                 ("gamma", C.c_double), ("entropy_fix", C.c_double),
                 ("z", C.c_double * MAX_SPECIES), ("mu", C.c_double * MAX_SPECIES),
-                ("D", C.c_double * MAX_SPECIES)]
+                ("D", C.c_double * MAX_SPECIES),
+                ("Wk", C.c_double * MAX_SPECIES), ("cpa", C.c_double * MAX_SPECIES),
+                ("cpb", C.c_double * MAX_SPECIES), ("cpc", C.c_double * MAX_SPECIES),
+                ("Sc", C.c_double * MAX_SPECIES), ("mu_ref", C.c_double), ("T_ref", C.c_double),
+                ("Pr", C.c_double)]
 
 
 def physics(model=MODEL_GAS, flux=FLUX_HLLC, limiter=LIM_MINMOD, rk_stages=2, nspecies=0,
             closure=True, precision=PREC_FP64, beta=1.0, cfl=0.5, fourier=0.25, gamma=1.4,
-            entropy_fix=0.1, z=(), mu=(), D=()) -> Physics:
+            entropy_fix=0.1, z=(), mu=(), D=(), mixture=None) -> Physics:
     p = Physics()
     p.model, p.flux, p.limiter, p.rk_stages = model, flux, limiter, rk_stages
     p.nspecies, p.closure, p.precision = nspecies, int(bool(closure)), precision
     p.beta, p.cfl, p.fourier, p.gamma, p.entropy_fix = beta, cfl, fourier, gamma, entropy_fix
     for k, (a, b, c) in enumerate(zip(z, mu, D)):
         p.z[k], p.mu[k], p.D[k] = a, b, c
+    if mixture is not None:
+        for k in range(mixture.n):
+            p.Wk[k], p.cpa[k], p.cpb[k] = mixture.W[k], mixture.cp_a[k], mixture.cp_b[k]
+            p.cpc[k], p.Sc[k] = mixture.cp_c[k], mixture.Sc[k]
+        p.mu_ref, p.T_ref, p.Pr = mixture.mu_ref, mixture.T_ref, mixture.Pr
     return p
 
 
@@ -215,7 +224,7 @@ class Solver:
                                        C.byref(h)), "vcx_solver_create")
         self.h = h
         self.nvar = lib().vcx_solver_nvar(h)
-        self.nr = self.nvar + 1 if phys.model == MODEL_GAS else self.nvar
+        self.nr = self.nvar if phys.model == MODEL_DRIFT_DIFFUSION else self.nvar + 1
 
     def upload(self, U):
         if not _is_device_tensor(U):

@@ -20,10 +20,11 @@ class Case:
     U: np.ndarray
     E: np.ndarray | None
     scheme: dict
+    tiles: tuple = (0, 0)     # (max cells, max nodes) per tile; 0 = library default
 
     @property
     def model(self):
-        return 1 if self.scheme["model"] == "dd" else 0
+        return {"gas": 0, "dd": 1, "ns": 2}[self.scheme["model"]]
 
     def oracle_phys(self):
         s = self.scheme
@@ -33,7 +34,7 @@ class Case:
                            beta=s.get("beta", 1.0), cfl=s.get("cfl", 0.5),
                            fourier=s.get("fourier", 0.25), gamma=1.4,
                            entropy_fix=s.get("fix", 0.1), z=s.get("z", []), mu=s.get("mu", []),
-                           D=s.get("D", []))
+                           D=s.get("D", []), mixture=s.get("mixture"))
 
     def vcx_phys(self, precision=0):
         from paper_2201_01291_amd import vcx
@@ -44,7 +45,7 @@ class Case:
                            precision=precision, beta=s.get("beta", 1.0), cfl=s.get("cfl", 0.5),
                            fourier=s.get("fourier", 0.25), gamma=1.4,
                            entropy_fix=s.get("fix", 0.1), z=s.get("z", []), mu=s.get("mu", []),
-                           D=s.get("D", []))
+                           D=s.get("D", []), mixture=s.get("mixture"))
 
 
 DD2 = dict(model="dd", limiter="minmod", rk=1, nspecies=2, z=[-1.0, 1.0], mu=[0.04, 0.04],
@@ -88,17 +89,37 @@ def make_case(name: str) -> Case:
         U = wl.euler_blob_state(m, nblobs=4, amp=0.2, sigma=0.25, nspecies=9)
         return Case(name, m, U, None, dict(model="gas", flux="hllc", limiter="minmod", rk=4,
                                            nspecies=9))
+    if name == "ns3d-sp9":
+        mix = wl.synthetic_mixture(9, seed=3)
+        m = wl.kuhn_tet_mesh(5, 4, 5, 0.01, 0.008, 0.01, jitter=0.1, seed=8)
+        U = wl.ns_state(m, mix, lattice=4, seed=6)
+        return Case(name, m, U, None, dict(model="ns", flux="hllc", limiter="vanleer", rk=2,
+                                           nspecies=9, mixture=mix), tiles=(64, 48))
+    if name == "ns2d-sp2-open":
+        mix = wl.synthetic_mixture(2, seed=5)
+        mix.mu_ref = 2e-3    # visible diffusive fluxes at this resolution
+        m = wl.tri_rect_mesh(14, 11, 0.01, 0.008, jitter=0.2, seed=4)
+        U = wl.ns_state(m, mix, lattice=3, seed=9, vel=(30.0, -10.0))
+        return Case(name, m, U, None, dict(model="ns", flux="hllc", limiter="minmod", rk=3,
+                                           nspecies=2, mixture=mix))
     raise KeyError(name)
 
 
 CASE_NAMES = ["dd2d-streamer", "dd2d-open-vanleer", "dd3d-sweby", "sod-hllc", "euler2d-roe-sp2",
-              "euler3d-roe", "euler3d-hllc-open-sp2", "euler3d-hllc-sp9"]
+              "euler3d-roe", "euler3d-hllc-open-sp2", "euler3d-hllc-sp9", "ns3d-sp9",
+              "ns2d-sp2-open"]
 
 
 def reconstructed(case: Case) -> np.ndarray:
-    """W = (U, p) for gas, U for drift-diffusion (test-side input preparation)."""
+    """W = (U, p) for gas, U for drift-diffusion (test-side input preparation;
+    the multi-species pressure comes from the oracle's node state)."""
     if case.model == 1:
         return case.U
+    if case.model == 2:
+        ph = case.oracle_phys()
+        p = np.array([oracle.ns_node(case.mesh.ndim, ph, case.U[:, i])[1]
+                      for i in range(case.mesh.nnodes)])
+        return np.vstack([case.U, p[None]])
     nd = case.mesh.ndim
     rho = case.U[0]
     ke = 0.5 * np.sum(case.U[1:1 + nd] ** 2, axis=0) / rho
@@ -119,7 +140,7 @@ def state_err(case: Case, Ua, Ub):
     with the momentum components normalised by the largest momentum
     component (a vector quantity: its scale does not depend on the axes)."""
     den = np.abs(Ub).max(axis=1)
-    if case.model == 0:
+    if case.model != 1:
         nd = case.mesh.ndim
         den[1:1 + nd] = den[1:1 + nd].max()
     den = np.where(den > 0, den, np.abs(Ub).max())

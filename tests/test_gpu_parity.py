@@ -29,7 +29,7 @@ def _setup(case, precision=0):
     print(f"[case] {case.name} prec={precision} nn={case.mesh.nnodes} nc={case.mesh.ncells}",
           flush=True)
     om = oracle.OracleMesh(case.mesh)
-    gm = vcx.Mesh(case.mesh)
+    gm = vcx.Mesh(case.mesh, tile_cells=case.tiles[0], tile_nodes=case.tiles[1])
     s = vcx.Solver(gm, case.vcx_phys(precision), case.E)
     s.upload(case.U)
     return om, gm, s
