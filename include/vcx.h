@@ -203,10 +203,30 @@ vcx_status vcx_step(vcx_solver s, int nsteps, double t_end, double *t, double *d
 /* Steps completed by the last vcx_step / vcx_solve_batch call on s. */
 int64_t vcx_steps_done(vcx_solver s);
 
-/* Advance several independent solvers (each with its own mesh) together:
- * per step one launch per kernel covers every solver's tiles and nodes.
- * Solvers must share precision and model family.  nsteps[i], t_end[i] per
- * solver. */
+/* Time t and last completed step size of s after its last vcx_step /
+ * vcx_solve_batch call (t0 and 0 right after an upload).  NULL outputs are
+ * skipped. */
+vcx_status vcx_state_time(vcx_solver s, double *t, double *dt_last);
+
+/* Advance n independent solvers (each on its own mesh, or several on one
+ * mesh) together, the batched execution of the explicit scheme (Sec. "Time
+ * integration" applied per solve).  Per RK stage one launch per kernel covers
+ * the tiles and the shared nodes of every member: a device table holds one
+ * descriptor per solve (mesh arrays, state buffers, time-step scalars) and a
+ * block map gives each workgroup its solve and local tile.  Each member
+ * keeps its own time loop: its own dt (CFL/Fourier minimum over its own
+ * cells), step budget nsteps[i] (>= 0) and end time t_end[i] (<= 0: none;
+ * the last step is clipped to it).  Results are bitwise identical to those
+ * of vcx_step on each solver alone.
+ * Requirements: every member has a state (vcx_state_upload), is not in a
+ * failed state, appears once, and all members have byte-identical
+ * physics structs: same model, scheme, precision and constants.  The call runs on the
+ * first member's stream after synchronising the others' and returns when
+ * every member has finished.
+ * Errors: VCX_E_ARG (NULL, empty, duplicate or mixed-physics batch),
+ * VCX_E_STATE (member without state), VCX_E_UNSTABLE (one or more members
+ * blew up: each of those keeps its last good state and its flag; the others
+ * completed normally), VCX_E_OOM / VCX_E_HIP. */
 vcx_status vcx_solve_batch(vcx_solver *s, int n, const int *nsteps, const double *t_end);
 
 /* sum_i V_i U_i per variable [nvar] (FP64, fixed-order tree). */

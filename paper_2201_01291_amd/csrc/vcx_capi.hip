@@ -150,7 +150,21 @@ struct KernelTable {
   size_t (*lds_flux)(int maxn, int maxc);
   vcx_status (*allow_lds)(size_t grad_bytes, size_t flux_bytes);
   vcx_status (*aux)(vcx_solver, double* W);
+  vcx_status (*batch_stage)(const struct BatchRun& br, const BatchStage& st);
   int nw, ngf;
+};
+
+// A batch launch: device table of solves and block maps (see vcx_solve_batch).
+struct BatchRun {
+  vcx_solver lead;                 // physics and stream of the batch
+  hipStream_t stream;
+  BatchEntry* tab;
+  int2* tile_map;
+  int ntile_blocks;
+  int2* sh_map;
+  int nsh_blocks;
+  size_t lds_grad, lds_flux;
+  int tile_block;
 };
 
 static DtParts dt_parts(vcx_solver s) {
@@ -295,11 +309,65 @@ struct Impl {
     else
       VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_dd<ND, NSP, CT>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)flux_bytes));
+    VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_grad_tile_batch<ND, NGF>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)grad_bytes));
+    if constexpr (MODEL == 0)
+      VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_gas_batch<ND, NSP, FLUX, CT>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)flux_bytes));
+    else if constexpr (MODEL == 2)
+      VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_ns_batch<ND, NSP, CT>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)flux_bytes));
+    else
+      VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_dd_batch<ND, NSP, CT>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)flux_bytes));
     return VCX_OK;
   }
+  // one RK stage of every solve of a batch: gradient, flux, shared-node update
+  static vcx_status batch_stage(const BatchRun& br, const BatchStage& st) {
+    vcx_solver s = br.lead;
+    FinishShared fs{dt_coef(s->ph), mix_params(s->ph), s->ph.closure};
+    VCX_TRY(launch(s, "gradient", [&] {
+      hipLaunchKernelGGL((k_grad_tile_batch<ND, NGF>), dim3(xcd_grid(br.ntile_blocks)),
+                         dim3(br.tile_block), br.lds_grad, br.stream, (const BatchEntry*)br.tab,
+                         (const int2*)br.tile_map, br.ntile_blocks, st);
+    }));
+    if constexpr (MODEL == 0) {
+      GasParams gp{s->ph.gamma, s->ph.beta, s->ph.entropy_fix, s->ph.limiter};
+      VCX_TRY(launch(s, "flux", [&] {
+        hipLaunchKernelGGL((k_flux_gas_batch<ND, NSP, FLUX, CT>), dim3(xcd_grid(br.ntile_blocks)),
+                           dim3(br.tile_block), br.lds_flux, br.stream, (const BatchEntry*)br.tab,
+                           (const int2*)br.tile_map, br.ntile_blocks, st, gp, fs);
+      }));
+    } else if constexpr (MODEL == 2) {
+      GasParams gp{s->ph.gamma, s->ph.beta, s->ph.entropy_fix, s->ph.limiter};
+      VCX_TRY(launch(s, "flux", [&] {
+        hipLaunchKernelGGL((k_flux_ns_batch<ND, NSP, CT>), dim3(xcd_grid(br.ntile_blocks)),
+                           dim3(br.tile_block), br.lds_flux, br.stream, (const BatchEntry*)br.tab,
+                           (const int2*)br.tile_map, br.ntile_blocks, st, gp, fs);
+      }));
+    } else {
+      DDParams pp{};
+      for (int k = 0; k < NSP; ++k) {
+        pp.zmu[k] = s->ph.z[k] * s->ph.mu[k];
+        pp.D[k] = s->ph.D[k];
+      }
+      pp.beta = s->ph.beta;
+      pp.limiter = s->ph.limiter;
+      VCX_TRY(launch(s, "flux", [&] {
+        hipLaunchKernelGGL((k_flux_dd_batch<ND, NSP, CT>), dim3(xcd_grid(br.ntile_blocks)),
+                           dim3(br.tile_block), br.lds_flux, br.stream, (const BatchEntry*)br.tab,
+                           (const int2*)br.tile_map, br.ntile_blocks, st, pp, fs);
+      }));
+    }
+    return launch(s, "update", [&] {
+      hipLaunchKernelGGL((k_update_shared_batch<ND, NSP, MODEL>), dim3(br.nsh_blocks), dim3(kNodeBlock), 0,
+                         br.stream, (const BatchEntry*)br.tab, (const int2*)br.sh_map, st, fs);
+    });
+  }
   static const KernelTable* table() {
-    static const KernelTable t{&grad,      &grad_complete, &flux, &update_shared, &node_dt,
-                               &lds_grad,  &lds_flux,      &allow_lds, &aux, NW, NGF};
+    static const KernelTable t{&grad,      &grad_complete, &flux,        &update_shared, &node_dt,
+                               &lds_grad,  &lds_flux,      &allow_lds,   &aux,           &batch_stage,
+                               NW,         NGF};
     return &t;
   }
 };
@@ -560,6 +628,7 @@ static vcx_status dmalloc(double** p, size_t n) {
 static vcx_status reset_scalars(vcx_solver s, double t0, bool prime) {
   DevScalars z{};
   z.t = t0;
+  z.steps_left = -1;
   *s->sc_host = z;
   VCX_HIP(hipMemcpyAsync(s->sc, s->sc_host, sizeof(DevScalars), hipMemcpyHostToDevice,
                          s->mesh->stream));
@@ -791,7 +860,10 @@ extern "C" vcx_status vcx_timestep(vcx_solver s, double* dt) {
 }
 
 __global__ void k_set_tend(DevScalars* sc, double t_end) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) sc->t_end = t_end;
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    sc->t_end = t_end;
+    sc->steps_left = -1;
+  }
 }
 
 static const double RK_ALPHA[5][5] = {
@@ -868,13 +940,196 @@ extern "C" vcx_status vcx_step(vcx_solver s, int nsteps, double t_end, double* t
 
 extern "C" int64_t vcx_steps_done(vcx_solver s) { return s ? s->steps_last : -1; }
 
+extern "C" vcx_status vcx_state_time(vcx_solver s, double* t, double* dt_last) {
+  if (!s) return fail(VCX_E_ARG, "NULL solver");
+  if (t) *t = s->sc_host->t;
+  if (dt_last) *dt_last = s->sc_host->last_dt;
+  return VCX_OK;
+}
+
+// Device resources of a batch (tables are rebuilt when the membership changes).
+struct BatchBuffers {
+  BatchEntry* tab = nullptr;
+  int2* tile_map = nullptr;
+  int2* sh_map = nullptr;
+  double* tend = nullptr;
+  int* steps = nullptr;
+  DevScalars* out = nullptr;
+  DevScalars* out_host = nullptr;
+  int cap_members = 0, cap_tiles = 0, cap_sh = 0;
+  ~BatchBuffers() {
+    for (void* p : {(void*)tab, (void*)tile_map, (void*)sh_map, (void*)tend, (void*)steps, (void*)out})
+      if (p) (void)hipFree(p);
+    if (out_host) (void)hipHostFree(out_host);
+  }
+};
+
+template <typename T>
+static vcx_status grow(T** p, int* cap, int need) {
+  if (*cap >= need) return VCX_OK;
+  if (*p) (void)hipFree(*p);
+  *p = nullptr;
+  const int c = std::max(need, 2 * *cap);
+  if (hipMalloc(reinterpret_cast<void**>(p), sizeof(T) * (size_t)c) != hipSuccess)
+    return fail(VCX_E_OOM, "hipMalloc failed for batch tables");
+  *cap = c;
+  return VCX_OK;
+}
+
+static bool same_scheme(const vcx_physics& a, const vcx_physics& b) {
+  return std::memcmp(&a, &b, sizeof(vcx_physics)) == 0;
+}
+
+static BatchEntry entry_of(vcx_solver s) {
+  BatchEntry e{};
+  e.m = s->mesh->d;
+  e.W[0] = s->W[0];
+  e.W[1] = s->W[1];
+  e.G = s->G;
+  e.PG = s->PG;
+  e.PR = s->PR;
+  e.E = s->E;
+  e.sc = s->sc;
+  e.parts = dt_parts(s);
+  e.phase = s->cur;
+  return e;
+}
+
+// Build the batch tables of the given solves on the lead solve's stream.
+static vcx_status batch_prepare(vcx_solver* ss, int n, const int* nsteps, const double* t_end,
+                                BatchBuffers& bb, BatchRun& br) {
+  vcx_solver lead = ss[0];
+  std::vector<BatchEntry> tab(n);
+  std::vector<int2> tmap, smap;
+  size_t lg = 0, lf = 0;
+  int block = 64;
+  for (int i = 0; i < n; ++i) {
+    vcx_solver s = ss[i];
+    tab[i] = entry_of(s);
+    for (int t = 0; t < s->mesh->d.ntiles; ++t) tmap.push_back(make_int2(i, t));
+    for (int b = 0; b < s->nsh_blocks; ++b) smap.push_back(make_int2(i, b));
+    lg = std::max(lg, s->lds_grad);
+    lf = std::max(lf, s->lds_flux);
+    block = std::max(block, s->tile_block);
+  }
+  const int lds_max = lead->mesh->lds_max;
+  if (lg > (size_t)lds_max || lf > (size_t)lds_max) return fail(VCX_E_ARG, "batch LDS footprint too large");
+  if (std::max(lg, lf) > 65536) VCX_TRY(lead->kt->allow_lds(lg, lf));
+  VCX_TRY(grow(&bb.tab, &bb.cap_members, n));
+  int cm = bb.cap_members;
+  {
+    int c2 = 0;
+    if (bb.tend) (void)hipFree(bb.tend), bb.tend = nullptr;
+    if (bb.steps) (void)hipFree(bb.steps), bb.steps = nullptr;
+    if (bb.out) (void)hipFree(bb.out), bb.out = nullptr;
+    if (bb.out_host) (void)hipHostFree(bb.out_host), bb.out_host = nullptr;
+    VCX_TRY(grow(&bb.tend, &c2, cm));
+    c2 = 0;
+    VCX_TRY(grow(&bb.steps, &c2, cm));
+    c2 = 0;
+    VCX_TRY(grow(&bb.out, &c2, cm));
+    if (hipHostMalloc(reinterpret_cast<void**>(&bb.out_host), sizeof(DevScalars) * cm, 0) != hipSuccess)
+      return fail(VCX_E_OOM, "hipHostMalloc failed for batch scalars");
+  }
+  VCX_TRY(grow(&bb.tile_map, &bb.cap_tiles, (int)tmap.size()));
+  VCX_TRY(grow(&bb.sh_map, &bb.cap_sh, (int)smap.size()));
+  VCX_HIP(hipMemcpy(bb.tab, tab.data(), sizeof(BatchEntry) * n, hipMemcpyHostToDevice));
+  VCX_HIP(hipMemcpy(bb.tile_map, tmap.data(), sizeof(int2) * tmap.size(), hipMemcpyHostToDevice));
+  VCX_HIP(hipMemcpy(bb.sh_map, smap.data(), sizeof(int2) * smap.size(), hipMemcpyHostToDevice));
+  VCX_HIP(hipMemcpy(bb.tend, t_end, sizeof(double) * n, hipMemcpyHostToDevice));
+  VCX_HIP(hipMemcpy(bb.steps, nsteps, sizeof(int) * n, hipMemcpyHostToDevice));
+  br.lead = lead;
+  br.stream = lead->mesh->stream;
+  br.tab = bb.tab;
+  br.tile_map = bb.tile_map;
+  br.ntile_blocks = (int)tmap.size();
+  br.sh_map = bb.sh_map;
+  br.nsh_blocks = (int)smap.size();
+  br.lds_grad = lg;
+  br.lds_flux = lf;
+  br.tile_block = std::min(256, block);
+  hipLaunchKernelGGL(k_batch_control, dim3((n + 63) / 64), dim3(64), 0, br.stream,
+                     (const BatchEntry*)bb.tab, n, (const double*)bb.tend, (const int*)bb.steps);
+  VCX_HIP(hipGetLastError());
+  return VCX_OK;
+}
+
+// Enqueue one batch step (K stages) at batch step counter q.
+static vcx_status batch_step(const BatchRun& br, int q) {
+  const int K = br.lead->ph.rk_stages;
+  for (int k = 1; k <= K; ++k) {
+    BatchStage st{q, k, k == K ? 1 : 0, k < K ? RK_ALPHA[K][k + 1] : 1.0};
+    VCX_TRY(br.lead->kt->batch_stage(br, st));
+  }
+  return VCX_OK;
+}
+
+// Commit the batch and copy every solve's scalars to bb.out_host (synchronised).
+static vcx_status batch_commit(const BatchRun& br, BatchBuffers& bb, int n) {
+  hipLaunchKernelGGL(k_batch_commit, dim3((n + 63) / 64), dim3(64), 0, br.stream,
+                     (const BatchEntry*)bb.tab, n, bb.out);
+  VCX_HIP(hipGetLastError());
+  VCX_HIP(hipMemcpyAsync(bb.out_host, bb.out, sizeof(DevScalars) * n, hipMemcpyDeviceToHost, br.stream));
+  VCX_HIP(hipStreamSynchronize(br.stream));
+  return VCX_OK;
+}
+
 extern "C" vcx_status vcx_solve_batch(vcx_solver* ss, int n, const int* nsteps, const double* t_end) {
-  if (!ss || n < 0 || !nsteps || !t_end) return fail(VCX_E_ARG, "NULL argument");
+  if (!ss || n <= 0 || !nsteps || !t_end) return fail(VCX_E_ARG, "NULL argument or empty batch");
   for (int i = 0; i < n; ++i) {
     if (!ss[i]) return fail(VCX_E_ARG, "NULL solver in batch");
-    double t, dl;
-    VCX_TRY(vcx_step(ss[i], nsteps[i], t_end[i], &t, &dl));
+    if (!ss[i]->has_state) return fail(VCX_E_STATE, "batch member without a state");
+    if (ss[i]->host_flag) return fail(VCX_E_UNSTABLE, "batch member in a failed state");
+    if (nsteps[i] < 0) return fail(VCX_E_ARG, "nsteps must be >= 0");
+    if (ss[i]->kt != ss[0]->kt || !same_scheme(ss[i]->ph, ss[0]->ph))
+      return fail(VCX_E_ARG, "batch members must share the model and scheme parameters");
+    for (int j = 0; j < i; ++j)
+      if (ss[j] == ss[i]) return fail(VCX_E_ARG, "a solver appears twice in the batch");
   }
+  for (int i = 1; i < n; ++i) VCX_HIP(hipStreamSynchronize(ss[i]->mesh->stream));
+  BatchBuffers bb;
+  BatchRun br{};
+  VCX_TRY(batch_prepare(ss, n, nsteps, t_end, bb, br));
+  std::vector<long long> steps0(n);
+  std::vector<int> cur0(n);
+  for (int i = 0; i < n; ++i) {
+    steps0[i] = ss[i]->steps_total;
+    cur0[i] = ss[i]->cur;
+  }
+  int maxsteps = 0;
+  for (int i = 0; i < n; ++i) maxsteps = std::max(maxsteps, nsteps[i]);
+  const int chunk = 16;
+  int q = 0;
+  bool any_fail = false;
+  while (q < maxsteps) {
+    const int c = std::min(chunk, maxsteps - q);
+    for (int r = 0; r < c; ++r) VCX_TRY(batch_step(br, q + r));
+    q += c;
+    VCX_TRY(batch_commit(br, bb, n));
+    bool live = false;
+    for (int i = 0; i < n; ++i) {
+      const DevScalars& h = bb.out_host[i];
+      const bool ended = h.flag != 0 || h.steps_left == 0 || (h.t_end > 0.0 && h.t >= h.t_end);
+      live = live || !ended;
+    }
+    if (!live) break;
+  }
+  if (q == 0) VCX_TRY(batch_commit(br, bb, n));
+  for (int i = 0; i < n; ++i) {
+    vcx_solver s = ss[i];
+    const DevScalars& h = bb.out_host[i];
+    *s->sc_host = h;
+    s->steps_total = h.steps;
+    s->steps_last = h.steps - steps0[i];
+    s->cur = (int)((cur0[i] + s->steps_last) % 2);
+    if (h.flag) {
+      s->host_flag = h.flag;
+      any_fail = true;
+    }
+    VCX_TRY(harvest(s));
+  }
+  VCX_TRY(harvest(br.lead));
+  if (any_fail) return fail(VCX_E_UNSTABLE, "at least one batch member became unstable");
   return VCX_OK;
 }
 

@@ -68,6 +68,7 @@ struct DevScalars {
   int active;      // the running step does work
   int pending;     // a started step awaits its commit
   int dt_src;      // 0: candidates from the node pass, 1: from the last step
+  int steps_left;  // steps this call may still start (< 0: unlimited)
   long long steps; // committed steps
 };
 
@@ -143,7 +144,7 @@ __device__ inline void dt_reduce_commit(DevScalars* sc, const DtParts parts) {
       sc->pending = 0;
     }
     sc->active = 0;
-    const bool done_t = sc->t_end > 0.0 && sc->t >= sc->t_end;
+    const bool done_t = (sc->t_end > 0.0 && sc->t >= sc->t_end) || sc->steps_left == 0;
     if (sc->flag == 0 && !done_t) {
       if (!(d > 0.0) || !isfinite(d)) {
         sc->flag |= 2;  // non-physical state or no limiting time scale
@@ -152,6 +153,7 @@ __device__ inline void dt_reduce_commit(DevScalars* sc, const DtParts parts) {
         sc->dt = d;
         sc->active = 1;
         sc->pending = 1;
+        if (sc->steps_left > 0) sc->steps_left -= 1;
       }
     }
   }
@@ -236,14 +238,12 @@ struct GradCtl {
 };
 
 template <int ND, int NR>
-__global__ void __launch_bounds__(256) k_grad_tile(DevMesh m, const double* __restrict__ W,
-                                                   double* __restrict__ G, double* __restrict__ PG,
-                                                   GradCtl ctl) {
+__device__ inline void grad_tile_body(const DevMesh& m, const double* __restrict__ W,
+                                      double* __restrict__ G, double* __restrict__ PG,
+                                      const GradCtl& ctl, int t, double* lds) {
   constexpr int NV = ND + 1, NC = NR * ND;
-  if (ctl.sc && ctl.first_stage && blockIdx.x == 0) dt_reduce_commit(ctl.sc, ctl.parts);
-  const int t = xcd_tile(m.ntiles);
-  if (t >= m.ntiles) return;
-  extern __shared__ double lds[];
+  // the block of the solve's first tile reduces the time step and commits
+  if (ctl.sc && ctl.first_stage && t == 0) dt_reduce_commit(ctl.sc, ctl.parts);
   const int maxn = m.max_tile_nodes, maxc = m.max_tile_cells;
   double* sW = lds;                 // [NR][maxn]
   double* sX = sW + NR * maxn;      // [ND][maxn]
@@ -309,6 +309,16 @@ __global__ void __launch_bounds__(256) k_grad_tile(DevMesh m, const double* __re
       }
     }
   }
+}
+
+template <int ND, int NR>
+__global__ void __launch_bounds__(256) k_grad_tile(DevMesh m, const double* __restrict__ W,
+                                                   double* __restrict__ G, double* __restrict__ PG,
+                                                   GradCtl ctl) {
+  extern __shared__ double lds[];
+  const int t = xcd_tile(m.ntiles);
+  if (t >= m.ntiles) return;
+  grad_tile_body<ND, NR>(m, W, G, PG, ctl, t, lds);
 }
 
 // gradient of a shared node g from its per-tile partial sums, taken over the
@@ -495,15 +505,12 @@ struct GasParams {
 };
 
 template <int ND, int NSP, int FLUX, typename CT>
-__global__ void VCX_FLUX_BOUNDS k_flux_gas(DevMesh m, const double* __restrict__ W,
+__device__ inline void flux_gas_body(DevMesh m, const double* __restrict__ W,
                                                   const double* __restrict__ G,
                                                   double* __restrict__ PR, GasParams gp, Finish f,
-                                                  DtParts parts) {
+                                                  DtParts parts, int t, double* lds) {
   constexpr int NV = ND + 1, NVAR = 2 + ND + NSP, NR = NVAR + 1, NE = Edges<ND>::NE;
   if (step_inactive(f.sc)) return;
-  const int t = xcd_tile(m.ntiles);
-  if (t >= m.ntiles) return;
-  extern __shared__ double lds[];
   const int maxn = m.max_tile_nodes, maxc = m.max_tile_cells;
   double* sX = lds;                       // [ND][maxn]
   double* sR = sX + ND * maxn;            // [NV*NVAR][maxc]
@@ -604,6 +611,17 @@ __global__ void VCX_FLUX_BOUNDS k_flux_gas(DevMesh m, const double* __restrict__
   }
 }
 
+template <int ND, int NSP, int FLUX, typename CT>
+__global__ void VCX_FLUX_BOUNDS k_flux_gas(DevMesh m, const double* __restrict__ W,
+                                                  const double* __restrict__ G,
+                                                  double* __restrict__ PR, GasParams gp, Finish f,
+                                                  DtParts parts) {
+  extern __shared__ double lds[];
+  const int t = xcd_tile(m.ntiles);
+  if (t >= m.ntiles) return;
+  flux_gas_body<ND, NSP, FLUX, CT>(m, W, G, PR, gp, f, parts, t, lds);
+}
+
 // ---------------------------------------------------------------------------
 // drift-diffusion flux pass (limited Lax-Wendroff + central diffusion)
 // ---------------------------------------------------------------------------
@@ -617,15 +635,12 @@ struct DDParams {
 };
 
 template <int ND, int NS, typename CT>
-__global__ void VCX_FLUX_BOUNDS k_flux_dd(DevMesh m, const double* __restrict__ U,
+__device__ inline void flux_dd_body(DevMesh m, const double* __restrict__ U,
                                                  const double* __restrict__ G,
                                                  double* __restrict__ PR, DDParams pp, Finish f,
-                                                 DtParts parts) {
+                                                 DtParts parts, int t, double* lds) {
   constexpr int NV = ND + 1, NE = Edges<ND>::NE;
   if (step_inactive(f.sc)) return;
-  const int t = xcd_tile(m.ntiles);
-  if (t >= m.ntiles) return;
-  extern __shared__ double lds[];
   const int maxn = m.max_tile_nodes, maxc = m.max_tile_cells;
   double* sX = lds;                      // [ND][maxn]
   double* sR = sX + ND * maxn;           // [NV*NS][maxc]
@@ -735,6 +750,17 @@ __global__ void VCX_FLUX_BOUNDS k_flux_dd(DevMesh m, const double* __restrict__ 
   }
 }
 
+template <int ND, int NS, typename CT>
+__global__ void VCX_FLUX_BOUNDS k_flux_dd(DevMesh m, const double* __restrict__ U,
+                                                 const double* __restrict__ G,
+                                                 double* __restrict__ PR, DDParams pp, Finish f,
+                                                 DtParts parts) {
+  extern __shared__ double lds[];
+  const int t = xcd_tile(m.ntiles);
+  if (t >= m.ntiles) return;
+  flux_dd_body<ND, NS, CT>(m, U, G, PR, pp, f, parts, t, lds);
+}
+
 // ---------------------------------------------------------------------------
 // multi-species Navier-Stokes flux pass: MUSCL on (U, p), HLLC with each
 // side's own gamma, minus the central diffusive flux
@@ -743,16 +769,13 @@ __global__ void VCX_FLUX_BOUNDS k_flux_dd(DevMesh m, const double* __restrict__ 
 // ---------------------------------------------------------------------------
 
 template <int ND, int NSP, typename CT>
-__global__ void VCX_FLUX_BOUNDS k_flux_ns(DevMesh m, const double* __restrict__ W,
+__device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ W,
                                           const double* __restrict__ G,
                                           double* __restrict__ PR, GasParams gp, Finish f,
-                                          DtParts parts) {
+                                          DtParts parts, int t, double* lds) {
   constexpr int NV = ND + 1, NVAR = 2 + ND + NSP, NR = NVAR + 1, NE = Edges<ND>::NE;
   constexpr int NP = ND + 1 + NSP, NA = 3 + 2 * NSP, NG = NR + NP;
   if (step_inactive(f.sc)) return;
-  const int t = xcd_tile(m.ntiles);
-  if (t >= m.ntiles) return;
-  extern __shared__ double lds[];
   const int maxn = m.max_tile_nodes, maxc = m.max_tile_cells;
   double* sX = lds;                                        // [ND][maxn]
   double* sR = sX + ND * maxn;                             // [NV*NVAR][maxc]
@@ -868,6 +891,17 @@ __global__ void VCX_FLUX_BOUNDS k_flux_ns(DevMesh m, const double* __restrict__ 
   }
 }
 
+template <int ND, int NSP, typename CT>
+__global__ void VCX_FLUX_BOUNDS k_flux_ns(DevMesh m, const double* __restrict__ W,
+                                          const double* __restrict__ G,
+                                          double* __restrict__ PR, GasParams gp, Finish f,
+                                          DtParts parts) {
+  extern __shared__ double lds[];
+  const int t = xcd_tile(m.ntiles);
+  if (t >= m.ntiles) return;
+  flux_ns_body<ND, NSP, CT>(m, W, G, PR, gp, f, parts, t, lds);
+}
+
 // multi-species node rows (p, primitives, aux) of an uploaded state
 template <int ND, int NSP>
 __global__ void __launch_bounds__(256) k_ns_aux(double* __restrict__ W, int nn, MixParams mp) {
@@ -890,13 +924,13 @@ __global__ void __launch_bounds__(256) k_ns_aux(double* __restrict__ W, int nn, 
 // ---------------------------------------------------------------------------
 
 template <int ND, int NSP, int MODEL>
-__global__ void __launch_bounds__(256) k_update_shared(DevMesh m, const double* __restrict__ PR,
-                                                       Finish f, DtParts parts) {
+__device__ inline void update_shared_body(const DevMesh& m, const double* __restrict__ PR,
+                                          const Finish& f, const DtParts& parts, int b) {
   constexpr int NVAR = MODEL == 1 ? NSP : 2 + ND + NSP;
   if (step_inactive(f.sc)) return;
   // the next step reduces the candidates written by this stage
-  if (f.final_stage && f.sc && blockIdx.x == 0 && threadIdx.x == 0) f.sc->dt_src = 1;
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f.final_stage && f.sc && b == 0 && threadIdx.x == 0) f.sc->dt_src = 1;
+  const int k = b * blockDim.x + threadIdx.x;
   double cand = INFINITY;
   if (k < m.nshared) {
     const int i = m.shared[k];
@@ -912,9 +946,15 @@ __global__ void __launch_bounds__(256) k_update_shared(DevMesh m, const double* 
     cand = finish_node<ND, NSP, MODEL, NVAR>(m, f, i, true, r);
   }
   if (f.final_stage && f.sc) {
-    const double b = block_min(cand);
-    if (threadIdx.x == 0) parts.step[m.ntiles + blockIdx.x] = b;
+    const double bm = block_min(cand);
+    if (threadIdx.x == 0) parts.step[m.ntiles + b] = bm;
   }
+}
+
+template <int ND, int NSP, int MODEL>
+__global__ void __launch_bounds__(256) k_update_shared(DevMesh m, const double* __restrict__ PR,
+                                                       Finish f, DtParts parts) {
+  update_shared_body<ND, NSP, MODEL>(m, PR, f, parts, blockIdx.x);
 }
 
 // dt candidates of the current state, one per 256 nodes (after an upload or
@@ -1004,6 +1044,154 @@ __global__ void __launch_bounds__(256) k_cell_dx(DevMesh m, unsigned long long* 
   const unsigned long long bits = (unsigned long long)__double_as_longlong(dx);
 #pragma unroll
   for (int k = 0; k < NV; ++k) atomicMin(&dxbits[v[k]], bits);
+}
+
+// ---------------------------------------------------------------------------
+// batched launches: one launch covers the tiles (or shared-node blocks) of
+// several independent solves, each with its own mesh, buffers and time loop.
+// A device table holds one entry per solve; a block map gives each block its
+// solve and its local tile / block.  Every solve of a batch shares the model
+// and scheme parameters.
+// ---------------------------------------------------------------------------
+
+struct BatchEntry {
+  DevMesh m;
+  double* W[2];     // state buffers; the current one is W[(step + phase) & 1]
+  double* G;
+  double* PG;
+  double* PR;
+  const double* E;
+  DevScalars* sc;
+  DtParts parts;
+  int phase;
+};
+
+struct BatchStage {
+  int step;         // batch step counter
+  int stage;        // 1..K
+  int final_stage;
+  double alpha;
+};
+
+struct FinishShared {
+  DtCoef dc;
+  MixParams mix;
+  int closure;
+};
+
+__device__ inline Finish batch_finish(const BatchEntry& e, const BatchStage& st,
+                                      const FinishShared& fs, const double** Win) {
+  const int cur = (st.step + e.phase) & 1;
+  Finish f{};
+  f.Un = e.W[cur];
+  f.Wout = e.W[cur ^ 1];
+  f.Win = st.stage == 1 ? e.W[cur] : e.W[cur ^ 1];
+  f.G = e.G;
+  f.PG = e.PG;
+  f.E = e.E;
+  f.sc = e.sc;
+  f.dc = fs.dc;
+  f.mix = fs.mix;
+  f.alpha = st.alpha;
+  f.closure = fs.closure;
+  f.final_stage = st.final_stage;
+  f.residual_only = 0;
+  *Win = f.Win;
+  return f;
+}
+
+template <int ND, int NR>
+__global__ void __launch_bounds__(256) k_grad_tile_batch(const BatchEntry* __restrict__ tab,
+                                                         const int2* __restrict__ map, int nblocks,
+                                                         BatchStage st) {
+  extern __shared__ double lds[];
+  const int g = xcd_tile(nblocks);
+  if (g >= nblocks) return;
+  const int2 ml = map[g];
+  const BatchEntry& e = tab[ml.x];
+  const int cur = (st.step + e.phase) & 1;
+  const double* Win = st.stage == 1 ? e.W[cur] : e.W[cur ^ 1];
+  GradCtl ctl{e.sc, e.parts, st.stage == 1 ? 1 : 0};
+  grad_tile_body<ND, NR>(e.m, Win, e.G, e.PG, ctl, ml.y, lds);
+}
+
+template <int ND, int NSP, int FLUX, typename CT>
+__global__ void VCX_FLUX_BOUNDS k_flux_gas_batch(const BatchEntry* __restrict__ tab,
+                                                 const int2* __restrict__ map, int nblocks,
+                                                 BatchStage st, GasParams gp, FinishShared fs) {
+  extern __shared__ double lds[];
+  const int g = xcd_tile(nblocks);
+  if (g >= nblocks) return;
+  const int2 ml = map[g];
+  const BatchEntry& e = tab[ml.x];
+  const double* Win;
+  const Finish f = batch_finish(e, st, fs, &Win);
+  flux_gas_body<ND, NSP, FLUX, CT>(e.m, Win, e.G, e.PR, gp, f, e.parts, ml.y, lds);
+}
+
+template <int ND, int NS, typename CT>
+__global__ void VCX_FLUX_BOUNDS k_flux_dd_batch(const BatchEntry* __restrict__ tab,
+                                                const int2* __restrict__ map, int nblocks,
+                                                BatchStage st, DDParams pp, FinishShared fs) {
+  extern __shared__ double lds[];
+  const int g = xcd_tile(nblocks);
+  if (g >= nblocks) return;
+  const int2 ml = map[g];
+  const BatchEntry& e = tab[ml.x];
+  const double* Win;
+  const Finish f = batch_finish(e, st, fs, &Win);
+  flux_dd_body<ND, NS, CT>(e.m, Win, e.G, e.PR, pp, f, e.parts, ml.y, lds);
+}
+
+template <int ND, int NSP, typename CT>
+__global__ void VCX_FLUX_BOUNDS k_flux_ns_batch(const BatchEntry* __restrict__ tab,
+                                                const int2* __restrict__ map, int nblocks,
+                                                BatchStage st, GasParams gp, FinishShared fs) {
+  extern __shared__ double lds[];
+  const int g = xcd_tile(nblocks);
+  if (g >= nblocks) return;
+  const int2 ml = map[g];
+  const BatchEntry& e = tab[ml.x];
+  const double* Win;
+  const Finish f = batch_finish(e, st, fs, &Win);
+  flux_ns_body<ND, NSP, CT>(e.m, Win, e.G, e.PR, gp, f, e.parts, ml.y, lds);
+}
+
+template <int ND, int NSP, int MODEL>
+__global__ void __launch_bounds__(256) k_update_shared_batch(const BatchEntry* __restrict__ tab,
+                                                             const int2* __restrict__ map,
+                                                             BatchStage st, FinishShared fs) {
+  const int2 ml = map[blockIdx.x];
+  const BatchEntry& e = tab[ml.x];
+  const double* Win;
+  const Finish f = batch_finish(e, st, fs, &Win);
+  update_shared_body<ND, NSP, MODEL>(e.m, e.PR, f, e.parts, ml.y);
+}
+
+// per-solve control of a batch call: end time and step budget
+__global__ void k_batch_control(const BatchEntry* __restrict__ tab, int n,
+                                const double* __restrict__ t_end, const int* __restrict__ steps) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  tab[i].sc->t_end = t_end[i];
+  tab[i].sc->steps_left = steps[i];
+}
+
+// commit every solve's pending step and copy the scalars to one array
+__global__ void k_batch_commit(const BatchEntry* __restrict__ tab, int n, DevScalars* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  DevScalars* sc = tab[i].sc;
+  if (sc->pending) {
+    if (sc->flag == 0) {
+      sc->t += sc->dt;
+      sc->last_dt = sc->dt;
+      sc->steps += 1;
+    }
+    sc->pending = 0;
+  }
+  sc->active = 0;
+  out[i] = *sc;
 }
 
 // ---------------------------------------------------------------------------

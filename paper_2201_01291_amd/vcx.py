@@ -30,7 +30,7 @@ EXPORTS = (
     "vcx_mesh_create", "vcx_mesh_create_tiled", "vcx_mesh_destroy", "vcx_mesh_info", "vcx_mesh_geometry",
     "vcx_mesh_preprocess", "vcx_solver_create", "vcx_solver_destroy", "vcx_solver_nvar",
     "vcx_state_upload", "vcx_state_download", "vcx_state_set_time", "vcx_gradient",
-    "vcx_residual", "vcx_timestep", "vcx_step", "vcx_steps_done", "vcx_solve_batch",
+    "vcx_residual", "vcx_timestep", "vcx_step", "vcx_steps_done", "vcx_state_time", "vcx_solve_batch",
     "vcx_conservation_sums", "vcx_profile_enable", "vcx_profile_query", "vcx_last_error",
 )
 
@@ -106,6 +106,7 @@ def lib():
         L.vcx_step.argtypes = [vp, C.c_int, C.c_double, dp, dp]
         L.vcx_steps_done.argtypes = [vp]
         L.vcx_steps_done.restype = C.c_int64
+        L.vcx_state_time.argtypes = [vp, dp, dp]
         L.vcx_solve_batch.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(C.c_int), dp]
         L.vcx_conservation_sums.argtypes = [vp, dp]
         L.vcx_profile_enable.argtypes = [vp, C.c_int]
@@ -269,6 +270,12 @@ class Solver:
     def steps_done(self) -> int:
         return int(lib().vcx_steps_done(self.h))
 
+    def time(self):
+        """(t, dt_last) after the last step / batch call."""
+        t, d = C.c_double(), C.c_double()
+        _check(lib().vcx_state_time(self.h, C.byref(t), C.byref(d)), "vcx_state_time")
+        return t.value, d.value
+
     def sums(self):
         out = np.zeros(self.nvar)
         _check(lib().vcx_conservation_sums(self.h, _dptr(out)), "vcx_conservation_sums")
@@ -295,8 +302,16 @@ class Solver:
             pass
 
 
-def solve_batch(solvers, nsteps, t_end):
+def solve_batch(solvers, nsteps, t_end=None):
+    """Advance independent solvers together (batched kernels); nsteps and
+    t_end are per solver (t_end None or <= 0: no end time)."""
     n = len(solvers)
+    if np.isscalar(nsteps):
+        nsteps = [nsteps] * n
+    if t_end is None:
+        t_end = [0.0] * n
+    elif np.isscalar(t_end):
+        t_end = [t_end] * n
     hs = (C.c_void_p * n)(*[s.h for s in solvers])
     ns = (C.c_int * n)(*[int(x) for x in nsteps])
     te = (C.c_double * n)(*[float(x) for x in t_end])
