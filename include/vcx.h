@@ -118,6 +118,7 @@ typedef struct {
 
 typedef struct vcx_mesh_s *vcx_mesh;
 typedef struct vcx_solver_s *vcx_solver;
+typedef struct vcx_server_s *vcx_server;
 
 /* Build a device mesh (Sec. "Nomenclature and notations").
  *   ndim      2 (triangles) or 3 (tetrahedra); nv must be ndim + 1
@@ -228,6 +229,71 @@ vcx_status vcx_state_time(vcx_solver s, double *t, double *dt_last);
  * blew up: each of those keeps its last good state and its flag; the others
  * completed normally), VCX_E_OOM / VCX_E_HIP. */
 vcx_status vcx_solve_batch(vcx_solver *s, int n, const int *nsteps, const double *t_end);
+
+/* vcx_solve_batch with every kernel launched directly (vcx_solve_batch
+ * replays two batch steps captured once into a HIP graph).  Same results,
+ * bit for bit; for comparison and for callers that avoid graphs. */
+vcx_status vcx_solve_batch_eager(vcx_solver *s, int n, const int *nsteps, const double *t_end);
+
+/* Device bytes a solver with this physics on this mesh would allocate
+ * (state buffers, gradients, tile partials, staging, time-step scalars; the
+ * mesh's own arrays are not included).  Used for admission by device-memory
+ * footprint. */
+vcx_status vcx_solver_footprint(vcx_mesh mesh, const vcx_physics *phys, size_t *bytes);
+
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of independent solves
+ *
+ * A server owns a scheduler thread and a stream on the current device.
+ * Requests (a mesh, a physics struct, an initial state, a step budget and
+ * an end time) are queued by vcx_server_submit and admitted in arrival
+ * order while fewer than max_slots requests run and the sum of the running
+ * requests' vcx_solver_footprint stays within hbm_budget bytes.  Admitted
+ * states stay resident in device memory; all running requests with the same
+ * physics are advanced together by batched launches (as vcx_solve_batch, in
+ * chunks of at most chunk_steps steps), and a request that arrives while
+ * others run joins at the next chunk boundary.  Finished requests release
+ * their slot and memory at once.  Each result is bitwise identical to the
+ * same solve run alone with vcx_step.
+ * Meshes passed to submit must outlive their requests.  Server calls are
+ * thread-safe.
+ * --------------------------------------------------------------------------- */
+
+/* use_graphs = 1 replays captured HIP graphs (see vcx_solve_batch). */
+vcx_status vcx_server_create(size_t hbm_budget, int max_slots, int chunk_steps, int use_graphs,
+                             vcx_server *out);
+
+/* Queue a request.  U0: host [nvar][nnodes] in caller order; E: host
+ * [ndim][nnodes] electric field for drift-diffusion (else ignored, may be
+ * NULL); both copied.  nsteps >= 0; t_end <= 0: none.  *id identifies the
+ * request.  A request whose footprint exceeds the budget completes with
+ * VCX_E_OOM. */
+vcx_status vcx_server_submit(vcx_server sv, vcx_mesh mesh, const vcx_physics *phys, const double *U0,
+                             const double *E, int nsteps, double t_end, int64_t *id);
+
+/* *done = 1 once the request has finished; then *result holds its status
+ * (VCX_OK, VCX_E_UNSTABLE with the last good state, VCX_E_OOM, VCX_E_BUSY
+ * when the server shut down first, ...) and *t_out its time.  With a
+ * non-NULL U_out (host, [nvar][nnodes]) the final state is copied and the
+ * request is forgotten: later calls with its id return VCX_E_ARG.  result,
+ * U_out and t_out may be NULL. */
+vcx_status vcx_server_poll(vcx_server sv, int64_t id, int *done, vcx_status *result, double *U_out,
+                           double *t_out);
+
+/* Block until the request finished or timeout_s seconds passed (< 0: no
+ * limit); *done as in vcx_server_poll. */
+vcx_status vcx_server_wait(vcx_server sv, int64_t id, double timeout_s, int *done);
+
+/* out[16]: submitted, completed, failed, queued, running, member steps done,
+ * chunks run, mean running requests per chunk, request latency p50 / p99
+ * (submit to finish, ms), step latency p50 / p99 (chunk wall time / steps,
+ * ms), resident bytes, peak resident bytes, peak running requests, status
+ * of the last device error (0 = none). */
+vcx_status vcx_server_stats(vcx_server sv, double *out);
+
+/* Cancel queued requests (VCX_E_BUSY), finish running ones, stop the
+ * scheduler and free the server. */
+vcx_status vcx_server_destroy(vcx_server sv);
 
 /* sum_i V_i U_i per variable [nvar] (FP64, fixed-order tree). */
 vcx_status vcx_conservation_sums(vcx_solver s, double *sums);

@@ -36,20 +36,26 @@ def build(verbose: bool = False) -> str:
     inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
     with tempfile.TemporaryDirectory(prefix="vcx_build_") as tmp:
         host_o = os.path.join(tmp, "vcx_mesh.o")
+        serv_o = os.path.join(tmp, "vcx_server.o")
         dev_o = os.path.join(tmp, "vcx_capi.o")
+        rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
         procs = [
             subprocess.Popen(["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", *inc, "-c",
                               os.path.join(CSRC, "vcx_mesh.cpp"), "-o", host_o]),
+            subprocess.Popen(["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-pthread",
+                              "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(rocm, "include"), *inc,
+                              "-c", os.path.join(CSRC, "vcx_server.cpp"), "-o", serv_o]),
             subprocess.Popen(["hipcc", *HIP_FLAGS, *inc, "-c",
                               os.path.join(CSRC, "vcx_capi.hip"), "-o", dev_o]),
         ]
         if verbose:
-            print("compiling vcx_mesh.cpp (g++) and vcx_capi.hip (hipcc)", flush=True)
+            print("compiling vcx_mesh.cpp, vcx_server.cpp (g++) and vcx_capi.hip (hipcc)", flush=True)
         rcs = [p.wait() for p in procs]
         if any(rcs):
             raise RuntimeError(f"compilation failed (exit codes {rcs})")
         tmp_lib = LIB + ".tmp"
-        _run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp_lib, host_o, dev_o],
+        _run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", tmp_lib, host_o,
+              serv_o, dev_o],
              verbose)
         os.replace(tmp_lib, LIB)
     return LIB

@@ -1,13 +1,16 @@
 // C ABI of the vertex-centred residual library (declarations in include/vcx.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
 #include "vcx.h"
+#include "vcx_batch.h"
 #include "vcx_kernels.h"
 #include "vcx_mesh.h"
 
@@ -78,6 +81,7 @@ struct vcx_solver_s {
   const KernelTable* kt = nullptr;
   size_t lds_grad = 0, lds_flux = 0;
   int tile_block = 256;
+  size_t bytes = 0;  // device bytes held by the solver (mesh excluded)
   // profiling
   bool prof = false;
   std::map<std::string, std::vector<std::pair<hipEvent_t, hipEvent_t>>> ev;
@@ -101,21 +105,25 @@ static hipEvent_t take_event(vcx_solver s) {
 }
 
 template <typename F>
-static vcx_status launch(vcx_solver s, const char* name, F&& f) {
-  hipStream_t st = s->mesh->stream;
+static vcx_status launch_on(vcx_solver s, hipStream_t st, bool prof, const char* name, F&& f) {
   hipEvent_t a = nullptr, b = nullptr;
-  if (s->prof) {
+  if (prof) {
     a = take_event(s);
     b = take_event(s);
     if (a && b) VCX_HIP(hipEventRecord(a, st));
   }
   f();
   VCX_HIP(hipGetLastError());
-  if (s->prof && a && b) {
+  if (prof && a && b) {
     VCX_HIP(hipEventRecord(b, st));
     s->ev[name].push_back({a, b});
   }
   return VCX_OK;
+}
+
+template <typename F>
+static vcx_status launch(vcx_solver s, const char* name, F&& f) {
+  return launch_on(s, s->mesh->stream, s->prof, name, std::forward<F>(f));
 }
 
 static vcx_status harvest(vcx_solver s) {
@@ -150,14 +158,13 @@ struct KernelTable {
   size_t (*lds_flux)(int maxn, int maxc);
   vcx_status (*allow_lds)(size_t grad_bytes, size_t flux_bytes);
   vcx_status (*aux)(vcx_solver, double* W);
-  vcx_status (*batch_stage)(const struct BatchRun& br, const BatchStage& st);
+  vcx_status (*batch_stage)(const struct BatchRun& br, hipStream_t stream, const BatchStage& st, bool prof);
   int nw, ngf;
 };
 
 // A batch launch: device table of solves and block maps (see vcx_solve_batch).
 struct BatchRun {
-  vcx_solver lead;                 // physics and stream of the batch
-  hipStream_t stream;
+  vcx_solver lead;                 // physics of the batch
   BatchEntry* tab;
   int2* tile_map;
   int ntile_blocks;
@@ -323,26 +330,26 @@ struct Impl {
     return VCX_OK;
   }
   // one RK stage of every solve of a batch: gradient, flux, shared-node update
-  static vcx_status batch_stage(const BatchRun& br, const BatchStage& st) {
+  static vcx_status batch_stage(const BatchRun& br, hipStream_t stream, const BatchStage& st, bool prof) {
     vcx_solver s = br.lead;
     FinishShared fs{dt_coef(s->ph), mix_params(s->ph), s->ph.closure};
-    VCX_TRY(launch(s, "gradient", [&] {
+    VCX_TRY(launch_on(s, stream, prof, "gradient", [&] {
       hipLaunchKernelGGL((k_grad_tile_batch<ND, NGF>), dim3(xcd_grid(br.ntile_blocks)),
-                         dim3(br.tile_block), br.lds_grad, br.stream, (const BatchEntry*)br.tab,
+                         dim3(br.tile_block), br.lds_grad, stream, (const BatchEntry*)br.tab,
                          (const int2*)br.tile_map, br.ntile_blocks, st);
     }));
     if constexpr (MODEL == 0) {
       GasParams gp{s->ph.gamma, s->ph.beta, s->ph.entropy_fix, s->ph.limiter};
-      VCX_TRY(launch(s, "flux", [&] {
+      VCX_TRY(launch_on(s, stream, prof, "flux", [&] {
         hipLaunchKernelGGL((k_flux_gas_batch<ND, NSP, FLUX, CT>), dim3(xcd_grid(br.ntile_blocks)),
-                           dim3(br.tile_block), br.lds_flux, br.stream, (const BatchEntry*)br.tab,
+                           dim3(br.tile_block), br.lds_flux, stream, (const BatchEntry*)br.tab,
                            (const int2*)br.tile_map, br.ntile_blocks, st, gp, fs);
       }));
     } else if constexpr (MODEL == 2) {
       GasParams gp{s->ph.gamma, s->ph.beta, s->ph.entropy_fix, s->ph.limiter};
-      VCX_TRY(launch(s, "flux", [&] {
+      VCX_TRY(launch_on(s, stream, prof, "flux", [&] {
         hipLaunchKernelGGL((k_flux_ns_batch<ND, NSP, CT>), dim3(xcd_grid(br.ntile_blocks)),
-                           dim3(br.tile_block), br.lds_flux, br.stream, (const BatchEntry*)br.tab,
+                           dim3(br.tile_block), br.lds_flux, stream, (const BatchEntry*)br.tab,
                            (const int2*)br.tile_map, br.ntile_blocks, st, gp, fs);
       }));
     } else {
@@ -353,15 +360,15 @@ struct Impl {
       }
       pp.beta = s->ph.beta;
       pp.limiter = s->ph.limiter;
-      VCX_TRY(launch(s, "flux", [&] {
+      VCX_TRY(launch_on(s, stream, prof, "flux", [&] {
         hipLaunchKernelGGL((k_flux_dd_batch<ND, NSP, CT>), dim3(xcd_grid(br.ntile_blocks)),
-                           dim3(br.tile_block), br.lds_flux, br.stream, (const BatchEntry*)br.tab,
+                           dim3(br.tile_block), br.lds_flux, stream, (const BatchEntry*)br.tab,
                            (const int2*)br.tile_map, br.ntile_blocks, st, pp, fs);
       }));
     }
-    return launch(s, "update", [&] {
+    return launch_on(s, stream, prof, "update", [&] {
       hipLaunchKernelGGL((k_update_shared_batch<ND, NSP, MODEL>), dim3(br.nsh_blocks), dim3(kNodeBlock), 0,
-                         br.stream, (const BatchEntry*)br.tab, (const int2*)br.sh_map, st, fs);
+                         stream, (const BatchEntry*)br.tab, (const int2*)br.sh_map, st, fs);
     });
   }
   static const KernelTable* table() {
@@ -617,6 +624,35 @@ static void free_solver(vcx_solver s) {
   delete s;
 }
 
+// Device buffers of a solver, in doubles (one definition for creation and
+// for the footprint query used by admission control).
+struct SolverSizes {
+  size_t W = 0, G = 0, PG = 0, PR = 0, io = 0, part = 0, sums = 0, E = 0;
+  int n_dtp_node = 0, nsh_blocks = 1, n_dtp_step = 0;
+  size_t bytes() const {
+    auto r = [](size_t n) { return sizeof(double) * std::max<size_t>(n, 1); };
+    return 2 * r(W) + r(G) + r(PG) + r(PR) + 2 * r(io) + r(part) + r(sums) + (E ? r(E) : 0) +
+           r((size_t)n_dtp_node) + r((size_t)n_dtp_step) + sizeof(DevScalars);
+  }
+};
+
+static SolverSizes solver_sizes(const DevMesh& d, int nd, int nvar, int nr, int nw, int ngf, int model) {
+  SolverSizes z;
+  const size_t nn = (size_t)d.nn, P = (size_t)d.nslots;
+  z.W = (size_t)nw * nn;
+  z.G = (size_t)ngf * nd * nn;
+  z.PG = (size_t)ngf * nd * P;
+  z.PR = (size_t)nvar * P;
+  z.io = std::max<size_t>((size_t)ngf * nd, (size_t)nw) * nn;
+  z.part = (size_t)nr * 256;
+  z.sums = (size_t)nr;
+  z.E = model == VCX_MODEL_DRIFT_DIFFUSION ? (size_t)nd * nn : 0;
+  z.n_dtp_node = (int)((nn + kNodeBlock - 1) / kNodeBlock);
+  z.nsh_blocks = std::max(1, (d.nshared + kNodeBlock - 1) / kNodeBlock);
+  z.n_dtp_step = d.ntiles + z.nsh_blocks;
+  return z;
+}
+
 static vcx_status dmalloc(double** p, size_t n) {
   if (hipMalloc(reinterpret_cast<void**>(p), sizeof(double) * std::max<size_t>(n, 1)) != hipSuccess)
     return fail(VCX_E_OOM, "hipMalloc failed for solver buffers");
@@ -698,24 +734,25 @@ extern "C" vcx_status vcx_solver_create(vcx_mesh mesh, const vcx_physics* phys, 
     }
   }
   s->tile_block = std::min(256, ((d.max_tile_cells + 63) / 64) * 64);
-  const size_t nn = (size_t)d.nn, P = (size_t)d.nslots;
-  const size_t rows_io = std::max<size_t>((size_t)s->ngf * nd, s->nw);
+  const SolverSizes z = solver_sizes(d, nd, s->nvar, s->nr, s->nw, s->ngf, ph.model);
+  s->bytes = z.bytes();
+  const size_t nn = (size_t)d.nn;
   vcx_status st = VCX_OK;
   auto chk = [&](vcx_status x) {
     if (st == VCX_OK) st = x;
   };
-  chk(dmalloc(&s->W[0], (size_t)s->nw * nn));
-  chk(dmalloc(&s->W[1], (size_t)s->nw * nn));
-  chk(dmalloc(&s->G, (size_t)s->ngf * nd * nn));
-  chk(dmalloc(&s->PG, (size_t)s->ngf * nd * P));
-  chk(dmalloc(&s->PR, (size_t)s->nvar * P));
-  chk(dmalloc(&s->io, rows_io * nn));
-  chk(dmalloc(&s->rbuf, rows_io * nn));
-  chk(dmalloc(&s->part, (size_t)s->nr * 256));
-  chk(dmalloc(&s->sums_dev, (size_t)s->nr));
-  s->n_dtp_node = (int)((nn + kNodeBlock - 1) / kNodeBlock);
-  s->nsh_blocks = std::max(1, (d.nshared + kNodeBlock - 1) / kNodeBlock);
-  s->n_dtp_step = d.ntiles + s->nsh_blocks;
+  chk(dmalloc(&s->W[0], z.W));
+  chk(dmalloc(&s->W[1], z.W));
+  chk(dmalloc(&s->G, z.G));
+  chk(dmalloc(&s->PG, z.PG));
+  chk(dmalloc(&s->PR, z.PR));
+  chk(dmalloc(&s->io, z.io));
+  chk(dmalloc(&s->rbuf, z.io));
+  chk(dmalloc(&s->part, z.part));
+  chk(dmalloc(&s->sums_dev, z.sums));
+  s->n_dtp_node = z.n_dtp_node;
+  s->nsh_blocks = z.nsh_blocks;
+  s->n_dtp_step = z.n_dtp_step;
   chk(dmalloc(&s->dtp_node, (size_t)s->n_dtp_node));
   chk(dmalloc(&s->dtp_step, (size_t)s->n_dtp_step));
   if (st == VCX_OK && hipMalloc(reinterpret_cast<void**>(&s->sc), sizeof(DevScalars)) != hipSuccess)
@@ -727,7 +764,7 @@ extern "C" vcx_status vcx_solver_create(vcx_mesh mesh, const vcx_physics* phys, 
       hipHostMalloc(reinterpret_cast<void**>(&s->sums_host), sizeof(double) * s->nr, 0) != hipSuccess)
     st = fail(VCX_E_OOM, "hipHostMalloc failed");
   if (st == VCX_OK && ph.model == VCX_MODEL_DRIFT_DIFFUSION) {
-    chk(dmalloc(&s->E, (size_t)nd * nn));
+    chk(dmalloc(&s->E, z.E));
     if (st == VCX_OK) {
       // field in caller order -> internal order
       if (hipMemcpyAsync(s->io, E, sizeof(double) * nd * nn, hipMemcpyHostToDevice,
@@ -947,31 +984,20 @@ extern "C" vcx_status vcx_state_time(vcx_solver s, double* t, double* dt_last) {
   return VCX_OK;
 }
 
-// Device resources of a batch (tables are rebuilt when the membership changes).
-struct BatchBuffers {
-  BatchEntry* tab = nullptr;
-  int2* tile_map = nullptr;
-  int2* sh_map = nullptr;
-  double* tend = nullptr;
-  int* steps = nullptr;
-  DevScalars* out = nullptr;
-  DevScalars* out_host = nullptr;
-  int cap_members = 0, cap_tiles = 0, cap_sh = 0;
-  ~BatchBuffers() {
-    for (void* p : {(void*)tab, (void*)tile_map, (void*)sh_map, (void*)tend, (void*)steps, (void*)out})
-      if (p) (void)hipFree(p);
-    if (out_host) (void)hipHostFree(out_host);
-  }
-};
+// ---------------------------------------------------------------------------
+// batch groups: the solves advanced together by one launch per kernel
+// ---------------------------------------------------------------------------
 
 template <typename T>
-static vcx_status grow(T** p, int* cap, int need) {
-  if (*cap >= need) return VCX_OK;
+static vcx_status dev_array(T** p, int* cap, int need) {
+  if (*cap >= need && *p) return VCX_OK;
   if (*p) (void)hipFree(*p);
   *p = nullptr;
   const int c = std::max(need, 2 * *cap);
-  if (hipMalloc(reinterpret_cast<void**>(p), sizeof(T) * (size_t)c) != hipSuccess)
+  if (hipMalloc(reinterpret_cast<void**>(p), sizeof(T) * (size_t)std::max(c, 1)) != hipSuccess) {
+    *cap = 0;
     return fail(VCX_E_OOM, "hipMalloc failed for batch tables");
+  }
   *cap = c;
   return VCX_OK;
 }
@@ -979,6 +1005,34 @@ static vcx_status grow(T** p, int* cap, int need) {
 static bool same_scheme(const vcx_physics& a, const vcx_physics& b) {
   return std::memcmp(&a, &b, sizeof(vcx_physics)) == 0;
 }
+
+struct vcx::BatchGroup {
+  hipStream_t stream = nullptr;   // where the group's work is enqueued
+  hipStream_t cap = nullptr;      // private stream used only to capture graphs
+  bool graphs = false;
+  std::vector<vcx_solver> mem;
+  std::vector<long long> steps0;  // member step counters when the table was built
+  std::vector<int> phase0;        // member buffer parity when the table was built
+  int q = 0;                      // batch steps enqueued since the table was built
+  BatchRun br{};
+  // device tables
+  BatchEntry* tab = nullptr;
+  int2* tile_map = nullptr;
+  int2* sh_map = nullptr;
+  double* tend = nullptr;
+  int* steps = nullptr;
+  DevScalars* out = nullptr;
+  DevScalars* out_host = nullptr;  // pinned
+  int cap_tab = 0, cap_tiles = 0, cap_sh = 0, cap_tend = 0, cap_steps = 0, cap_out = 0, cap_host = 0;
+  hipGraphExec_t pair = nullptr;   // two batch steps (parities 0 and 1), captured once per table
+  ~BatchGroup() {
+    if (pair) (void)hipGraphExecDestroy(pair);
+    for (void* p : {(void*)tab, (void*)tile_map, (void*)sh_map, (void*)tend, (void*)steps, (void*)out})
+      if (p) (void)hipFree(p);
+    if (out_host) (void)hipHostFree(out_host);
+    if (cap) (void)hipStreamDestroy(cap);
+  }
+};
 
 static BatchEntry entry_of(vcx_solver s) {
   BatchEntry e{};
@@ -995,17 +1049,59 @@ static BatchEntry entry_of(vcx_solver s) {
   return e;
 }
 
-// Build the batch tables of the given solves on the lead solve's stream.
-static vcx_status batch_prepare(vcx_solver* ss, int n, const int* nsteps, const double* t_end,
-                                BatchBuffers& bb, BatchRun& br) {
+// Enqueue batch step q (all K stages) on stream st.
+static vcx_status batch_step(const BatchRun& br, hipStream_t st, int q, bool prof) {
+  const int K = br.lead->ph.rk_stages;
+  for (int k = 1; k <= K; ++k) {
+    BatchStage bs{q, k, k == K ? 1 : 0, k < K ? RK_ALPHA[K][k + 1] : 1.0};
+    VCX_TRY(br.lead->kt->batch_stage(br, st, bs, prof));
+  }
+  return VCX_OK;
+}
+
+vcx_status vcx::batch_create(hipStream_t stream, bool graphs, BatchGroup** out) {
+  auto* g = new (std::nothrow) BatchGroup();
+  if (!g) return fail(VCX_E_OOM, "host allocation failed");
+  g->stream = stream;
+  g->graphs = graphs;
+  if (graphs && hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking) != hipSuccess) {
+    delete g;
+    return fail(VCX_E_HIP, "stream creation failed");
+  }
+  *out = g;
+  return VCX_OK;
+}
+
+void vcx::batch_destroy(BatchGroup* g) {
+  if (!g) return;
+  (void)hipStreamSynchronize(g->stream);
+  delete g;
+}
+
+size_t vcx::batch_size(const BatchGroup* g) { return g ? g->mem.size() : 0; }
+
+vcx_status vcx::batch_set(BatchGroup* g, vcx_solver* ss, int n, const int* steps_left,
+                          const double* t_end) {
+  if (!g || n < 0 || (n > 0 && (!ss || !steps_left || !t_end))) return fail(VCX_E_ARG, "bad batch");
+  if (g->pair) {
+    (void)hipGraphExecDestroy(g->pair);
+    g->pair = nullptr;
+  }
+  g->mem.assign(ss, ss + n);
+  g->q = 0;
+  if (n == 0) return VCX_OK;
   vcx_solver lead = ss[0];
   std::vector<BatchEntry> tab(n);
   std::vector<int2> tmap, smap;
   size_t lg = 0, lf = 0;
   int block = 64;
+  g->steps0.resize(n);
+  g->phase0.resize(n);
   for (int i = 0; i < n; ++i) {
     vcx_solver s = ss[i];
     tab[i] = entry_of(s);
+    g->steps0[i] = s->steps_total;
+    g->phase0[i] = s->cur;
     for (int t = 0; t < s->mesh->d.ntiles; ++t) tmap.push_back(make_int2(i, t));
     for (int b = 0; b < s->nsh_blocks; ++b) smap.push_back(make_int2(i, b));
     lg = std::max(lg, s->lds_grad);
@@ -1015,122 +1111,170 @@ static vcx_status batch_prepare(vcx_solver* ss, int n, const int* nsteps, const 
   const int lds_max = lead->mesh->lds_max;
   if (lg > (size_t)lds_max || lf > (size_t)lds_max) return fail(VCX_E_ARG, "batch LDS footprint too large");
   if (std::max(lg, lf) > 65536) VCX_TRY(lead->kt->allow_lds(lg, lf));
-  VCX_TRY(grow(&bb.tab, &bb.cap_members, n));
-  int cm = bb.cap_members;
-  {
-    int c2 = 0;
-    if (bb.tend) (void)hipFree(bb.tend), bb.tend = nullptr;
-    if (bb.steps) (void)hipFree(bb.steps), bb.steps = nullptr;
-    if (bb.out) (void)hipFree(bb.out), bb.out = nullptr;
-    if (bb.out_host) (void)hipHostFree(bb.out_host), bb.out_host = nullptr;
-    VCX_TRY(grow(&bb.tend, &c2, cm));
-    c2 = 0;
-    VCX_TRY(grow(&bb.steps, &c2, cm));
-    c2 = 0;
-    VCX_TRY(grow(&bb.out, &c2, cm));
-    if (hipHostMalloc(reinterpret_cast<void**>(&bb.out_host), sizeof(DevScalars) * cm, 0) != hipSuccess)
+  VCX_TRY(dev_array(&g->tab, &g->cap_tab, n));
+  VCX_TRY(dev_array(&g->tend, &g->cap_tend, n));
+  VCX_TRY(dev_array(&g->steps, &g->cap_steps, n));
+  VCX_TRY(dev_array(&g->out, &g->cap_out, n));
+  VCX_TRY(dev_array(&g->tile_map, &g->cap_tiles, (int)tmap.size()));
+  VCX_TRY(dev_array(&g->sh_map, &g->cap_sh, (int)smap.size()));
+  if (g->cap_host < n) {
+    if (g->out_host) (void)hipHostFree(g->out_host);
+    g->out_host = nullptr;
+    g->cap_host = 0;
+    if (hipHostMalloc(reinterpret_cast<void**>(&g->out_host), sizeof(DevScalars) * g->cap_out, 0) != hipSuccess)
       return fail(VCX_E_OOM, "hipHostMalloc failed for batch scalars");
+    g->cap_host = g->cap_out;
   }
-  VCX_TRY(grow(&bb.tile_map, &bb.cap_tiles, (int)tmap.size()));
-  VCX_TRY(grow(&bb.sh_map, &bb.cap_sh, (int)smap.size()));
-  VCX_HIP(hipMemcpy(bb.tab, tab.data(), sizeof(BatchEntry) * n, hipMemcpyHostToDevice));
-  VCX_HIP(hipMemcpy(bb.tile_map, tmap.data(), sizeof(int2) * tmap.size(), hipMemcpyHostToDevice));
-  VCX_HIP(hipMemcpy(bb.sh_map, smap.data(), sizeof(int2) * smap.size(), hipMemcpyHostToDevice));
-  VCX_HIP(hipMemcpy(bb.tend, t_end, sizeof(double) * n, hipMemcpyHostToDevice));
-  VCX_HIP(hipMemcpy(bb.steps, nsteps, sizeof(int) * n, hipMemcpyHostToDevice));
+  // the members' own streams must be idle: the group's stream takes over
+  for (vcx_solver s : g->mem) VCX_HIP(hipStreamSynchronize(s->mesh->stream));
+  hipStream_t st = g->stream;
+  VCX_HIP(hipMemcpyAsync(g->tab, tab.data(), sizeof(BatchEntry) * n, hipMemcpyHostToDevice, st));
+  VCX_HIP(hipMemcpyAsync(g->tile_map, tmap.data(), sizeof(int2) * tmap.size(), hipMemcpyHostToDevice, st));
+  VCX_HIP(hipMemcpyAsync(g->sh_map, smap.data(), sizeof(int2) * smap.size(), hipMemcpyHostToDevice, st));
+  VCX_HIP(hipMemcpyAsync(g->tend, t_end, sizeof(double) * n, hipMemcpyHostToDevice, st));
+  VCX_HIP(hipMemcpyAsync(g->steps, steps_left, sizeof(int) * n, hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_batch_control, dim3((n + 63) / 64), dim3(64), 0, st, (const BatchEntry*)g->tab, n,
+                     (const double*)g->tend, (const int*)g->steps);
+  VCX_HIP(hipGetLastError());
+  // host arrays above are the caller's: wait for the copies before returning
+  VCX_HIP(hipStreamSynchronize(st));
+  BatchRun& br = g->br;
   br.lead = lead;
-  br.stream = lead->mesh->stream;
-  br.tab = bb.tab;
-  br.tile_map = bb.tile_map;
+  br.tab = g->tab;
+  br.tile_map = g->tile_map;
   br.ntile_blocks = (int)tmap.size();
-  br.sh_map = bb.sh_map;
+  br.sh_map = g->sh_map;
   br.nsh_blocks = (int)smap.size();
   br.lds_grad = lg;
   br.lds_flux = lf;
   br.tile_block = std::min(256, block);
-  hipLaunchKernelGGL(k_batch_control, dim3((n + 63) / 64), dim3(64), 0, br.stream,
-                     (const BatchEntry*)bb.tab, n, (const double*)bb.tend, (const int*)bb.steps);
-  VCX_HIP(hipGetLastError());
-  return VCX_OK;
-}
-
-// Enqueue one batch step (K stages) at batch step counter q.
-static vcx_status batch_step(const BatchRun& br, int q) {
-  const int K = br.lead->ph.rk_stages;
-  for (int k = 1; k <= K; ++k) {
-    BatchStage st{q, k, k == K ? 1 : 0, k < K ? RK_ALPHA[K][k + 1] : 1.0};
-    VCX_TRY(br.lead->kt->batch_stage(br, st));
+  if (g->graphs && !lead->prof) {
+    hipGraph_t graph = nullptr;
+    VCX_HIP(hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal));
+    vcx_status s0 = batch_step(br, g->cap, 0, false);
+    if (s0 == VCX_OK) s0 = batch_step(br, g->cap, 1, false);
+    hipError_t e = hipStreamEndCapture(g->cap, &graph);
+    if (s0 != VCX_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return s0;
+    }
+    if (e != hipSuccess) return fail(VCX_E_HIP, std::string("graph capture failed: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&g->pair, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      g->pair = nullptr;
+      return fail(VCX_E_HIP, std::string("graph instantiation failed: ") + hipGetErrorString(e));
+    }
   }
   return VCX_OK;
 }
 
-// Commit the batch and copy every solve's scalars to bb.out_host (synchronised).
-static vcx_status batch_commit(const BatchRun& br, BatchBuffers& bb, int n) {
-  hipLaunchKernelGGL(k_batch_commit, dim3((n + 63) / 64), dim3(64), 0, br.stream,
-                     (const BatchEntry*)bb.tab, n, bb.out);
-  VCX_HIP(hipGetLastError());
-  VCX_HIP(hipMemcpyAsync(bb.out_host, bb.out, sizeof(DevScalars) * n, hipMemcpyDeviceToHost, br.stream));
-  VCX_HIP(hipStreamSynchronize(br.stream));
+vcx_status vcx::batch_run(BatchGroup* g, int nsteps) {
+  if (!g || g->mem.empty() || nsteps <= 0) return VCX_OK;
+  const bool prof = g->br.lead->prof;
+  int left = nsteps;
+  // graph replays need an even step counter (the graph holds parities 0, 1)
+  if (g->pair && (g->q & 1) && left > 0) {
+    VCX_TRY(batch_step(g->br, g->stream, g->q, prof));
+    g->q += 1;
+    left -= 1;
+  }
+  if (g->pair) {
+    for (; left >= 2; left -= 2, g->q += 2) VCX_HIP(hipGraphLaunch(g->pair, g->stream));
+  }
+  for (; left > 0; --left, ++g->q) VCX_TRY(batch_step(g->br, g->stream, g->q, prof));
   return VCX_OK;
 }
 
-extern "C" vcx_status vcx_solve_batch(vcx_solver* ss, int n, const int* nsteps, const double* t_end) {
+vcx_status vcx::batch_sync(BatchGroup* g, std::vector<int>* ended) {
+  if (ended) ended->clear();
+  if (!g || g->mem.empty()) return VCX_OK;
+  const int n = (int)g->mem.size();
+  hipLaunchKernelGGL(k_batch_commit, dim3((n + 63) / 64), dim3(64), 0, g->stream, (const BatchEntry*)g->tab,
+                     n, g->out);
+  VCX_HIP(hipGetLastError());
+  VCX_HIP(hipMemcpyAsync(g->out_host, g->out, sizeof(DevScalars) * n, hipMemcpyDeviceToHost, g->stream));
+  VCX_HIP(hipStreamSynchronize(g->stream));
+  for (int i = 0; i < n; ++i) {
+    vcx_solver s = g->mem[i];
+    const DevScalars& h = g->out_host[i];
+    *s->sc_host = h;
+    s->steps_last = h.steps - s->steps_total;
+    s->steps_total = h.steps;
+    s->cur = (int)((g->phase0[i] + (h.steps - g->steps0[i])) % 2);
+    if (h.flag) s->host_flag = h.flag;
+    if (ended) ended->push_back(h.flag != 0 || h.steps_left == 0 || (h.t_end > 0.0 && h.t >= h.t_end));
+  }
+  VCX_TRY(harvest(g->br.lead));
+  return VCX_OK;
+}
+
+vcx_status vcx::solver_footprint(vcx_mesh mesh, const vcx_physics* ph, size_t* bytes) {
+  if (!mesh || !ph || !bytes) return fail(VCX_E_ARG, "NULL argument");
+  const KernelTable* kt = pick_table(mesh->h.nd, *ph);
+  if (!kt) return fail(VCX_E_ARG, "unsupported model / species count");
+  const int nd = mesh->h.nd;
+  const int nvar = ph->model == VCX_MODEL_DRIFT_DIFFUSION ? ph->nspecies : 2 + nd + ph->nspecies;
+  const int nr = ph->model == VCX_MODEL_DRIFT_DIFFUSION ? nvar : nvar + 1;
+  *bytes = solver_sizes(mesh->d, nd, nvar, nr, kt->nw, kt->ngf, ph->model).bytes();
+  return VCX_OK;
+}
+
+bool vcx::batch_compatible(vcx_solver a, vcx_solver b) { return a->kt == b->kt && same_scheme(a->ph, b->ph); }
+
+vcx_status vcx::set_error(vcx_status s, const char* msg) { return fail(s, msg ? msg : ""); }
+int vcx::mesh_ndim(vcx_mesh m) { return m ? m->h.nd : 0; }
+int64_t vcx::mesh_nnodes(vcx_mesh m) { return m ? m->d.nn : 0; }
+int vcx::solver_failed(vcx_solver s) { return s ? s->host_flag : 0; }
+
+extern "C" vcx_status vcx_solver_footprint(vcx_mesh mesh, const vcx_physics* phys, size_t* bytes) {
+  return vcx::solver_footprint(mesh, phys, bytes);
+}
+
+static vcx_status solve_batch(vcx_solver* ss, int n, const int* nsteps, const double* t_end, bool graphs) {
   if (!ss || n <= 0 || !nsteps || !t_end) return fail(VCX_E_ARG, "NULL argument or empty batch");
   for (int i = 0; i < n; ++i) {
     if (!ss[i]) return fail(VCX_E_ARG, "NULL solver in batch");
     if (!ss[i]->has_state) return fail(VCX_E_STATE, "batch member without a state");
     if (ss[i]->host_flag) return fail(VCX_E_UNSTABLE, "batch member in a failed state");
     if (nsteps[i] < 0) return fail(VCX_E_ARG, "nsteps must be >= 0");
-    if (ss[i]->kt != ss[0]->kt || !same_scheme(ss[i]->ph, ss[0]->ph))
+    if (!batch_compatible(ss[i], ss[0]))
       return fail(VCX_E_ARG, "batch members must share the model and scheme parameters");
     for (int j = 0; j < i; ++j)
       if (ss[j] == ss[i]) return fail(VCX_E_ARG, "a solver appears twice in the batch");
   }
-  for (int i = 1; i < n; ++i) VCX_HIP(hipStreamSynchronize(ss[i]->mesh->stream));
-  BatchBuffers bb;
-  BatchRun br{};
-  VCX_TRY(batch_prepare(ss, n, nsteps, t_end, bb, br));
+  BatchGroup* g = nullptr;
+  VCX_TRY(batch_create(ss[0]->mesh->stream, graphs, &g));
+  std::unique_ptr<BatchGroup, void (*)(BatchGroup*)> hold(g, batch_destroy);
   std::vector<long long> steps0(n);
-  std::vector<int> cur0(n);
-  for (int i = 0; i < n; ++i) {
-    steps0[i] = ss[i]->steps_total;
-    cur0[i] = ss[i]->cur;
-  }
+  for (int i = 0; i < n; ++i) steps0[i] = ss[i]->steps_total;
+  VCX_TRY(batch_set(g, ss, n, nsteps, t_end));
   int maxsteps = 0;
   for (int i = 0; i < n; ++i) maxsteps = std::max(maxsteps, nsteps[i]);
   const int chunk = 16;
+  std::vector<int> ended;
   int q = 0;
-  bool any_fail = false;
-  while (q < maxsteps) {
+  do {
     const int c = std::min(chunk, maxsteps - q);
-    for (int r = 0; r < c; ++r) VCX_TRY(batch_step(br, q + r));
+    VCX_TRY(batch_run(g, c));
     q += c;
-    VCX_TRY(batch_commit(br, bb, n));
-    bool live = false;
-    for (int i = 0; i < n; ++i) {
-      const DevScalars& h = bb.out_host[i];
-      const bool ended = h.flag != 0 || h.steps_left == 0 || (h.t_end > 0.0 && h.t >= h.t_end);
-      live = live || !ended;
-    }
-    if (!live) break;
-  }
-  if (q == 0) VCX_TRY(batch_commit(br, bb, n));
+    VCX_TRY(batch_sync(g, &ended));
+  } while (q < maxsteps && std::count(ended.begin(), ended.end(), 0) > 0);
+  bool any_fail = false;
   for (int i = 0; i < n; ++i) {
-    vcx_solver s = ss[i];
-    const DevScalars& h = bb.out_host[i];
-    *s->sc_host = h;
-    s->steps_total = h.steps;
-    s->steps_last = h.steps - steps0[i];
-    s->cur = (int)((cur0[i] + s->steps_last) % 2);
-    if (h.flag) {
-      s->host_flag = h.flag;
-      any_fail = true;
-    }
-    VCX_TRY(harvest(s));
+    ss[i]->steps_last = ss[i]->steps_total - steps0[i];
+    any_fail = any_fail || ss[i]->host_flag != 0;
   }
-  VCX_TRY(harvest(br.lead));
   if (any_fail) return fail(VCX_E_UNSTABLE, "at least one batch member became unstable");
   return VCX_OK;
+}
+
+extern "C" vcx_status vcx_solve_batch(vcx_solver* ss, int n, const int* nsteps, const double* t_end) {
+  return solve_batch(ss, n, nsteps, t_end, true);
+}
+
+extern "C" vcx_status vcx_solve_batch_eager(vcx_solver* ss, int n, const int* nsteps, const double* t_end) {
+  return solve_batch(ss, n, nsteps, t_end, false);
 }
 
 extern "C" vcx_status vcx_conservation_sums(vcx_solver s, double* sums) {

@@ -244,6 +244,8 @@ __device__ inline void grad_tile_body(const DevMesh& m, const double* __restrict
   constexpr int NV = ND + 1, NC = NR * ND;
   // the block of the solve's first tile reduces the time step and commits
   if (ctl.sc && ctl.first_stage && t == 0) dt_reduce_commit(ctl.sc, ctl.parts);
+  // later stages of a step that does no work (set by an earlier launch)
+  if (ctl.sc && !ctl.first_stage && ctl.sc->active == 0) return;
   const int maxn = m.max_tile_nodes, maxc = m.max_tile_cells;
   double* sW = lds;                 // [NR][maxn]
   double* sX = sW + NR * maxn;      // [ND][maxn]

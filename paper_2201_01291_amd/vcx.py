@@ -31,6 +31,8 @@ EXPORTS = (
     "vcx_mesh_preprocess", "vcx_solver_create", "vcx_solver_destroy", "vcx_solver_nvar",
     "vcx_state_upload", "vcx_state_download", "vcx_state_set_time", "vcx_gradient",
     "vcx_residual", "vcx_timestep", "vcx_step", "vcx_steps_done", "vcx_state_time", "vcx_solve_batch",
+    "vcx_solve_batch_eager", "vcx_solver_footprint", "vcx_server_create", "vcx_server_submit",
+    "vcx_server_poll", "vcx_server_wait", "vcx_server_stats", "vcx_server_destroy",
     "vcx_conservation_sums", "vcx_profile_enable", "vcx_profile_query", "vcx_last_error",
 )
 
@@ -108,6 +110,15 @@ def lib():
         L.vcx_steps_done.restype = C.c_int64
         L.vcx_state_time.argtypes = [vp, dp, dp]
         L.vcx_solve_batch.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(C.c_int), dp]
+        L.vcx_solve_batch_eager.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(C.c_int), dp]
+        L.vcx_solver_footprint.argtypes = [vp, C.POINTER(Physics), C.POINTER(C.c_size_t)]
+        L.vcx_server_create.argtypes = [C.c_size_t, C.c_int, C.c_int, C.c_int, C.POINTER(vp)]
+        L.vcx_server_submit.argtypes = [vp, vp, C.POINTER(Physics), dp, dp, C.c_int, C.c_double,
+                                        i64p]
+        L.vcx_server_poll.argtypes = [vp, C.c_int64, C.POINTER(C.c_int), C.POINTER(C.c_int), dp, dp]
+        L.vcx_server_wait.argtypes = [vp, C.c_int64, C.c_double, C.POINTER(C.c_int)]
+        L.vcx_server_stats.argtypes = [vp, dp]
+        L.vcx_server_destroy.argtypes = [vp]
         L.vcx_conservation_sums.argtypes = [vp, dp]
         L.vcx_profile_enable.argtypes = [vp, C.c_int]
         L.vcx_profile_query.argtypes = [vp, C.c_char_p, i64p, dp]
@@ -302,7 +313,77 @@ class Solver:
             pass
 
 
-def solve_batch(solvers, nsteps, t_end=None):
+def footprint(mesh: Mesh, phys: Physics) -> int:
+    """Device bytes a solver of this physics on this mesh allocates."""
+    b = C.c_size_t()
+    _check(lib().vcx_solver_footprint(mesh.h, C.byref(phys), C.byref(b)), "vcx_solver_footprint")
+    return int(b.value)
+
+
+SERVER_STATS = ("submitted", "completed", "failed", "queued", "running", "member_steps", "chunks",
+                "mean_running", "latency_p50_ms", "latency_p99_ms", "step_p50_ms", "step_p99_ms",
+                "resident_bytes", "peak_resident_bytes", "peak_running", "device_error")
+
+
+class Server:
+    """Continuous-batching request server (scheduler thread in the library)."""
+
+    def __init__(self, hbm_budget: int, max_slots: int = 64, chunk_steps: int = 16, graphs=True):
+        h = C.c_void_p()
+        _check(lib().vcx_server_create(int(hbm_budget), int(max_slots), int(chunk_steps),
+                                       int(bool(graphs)), C.byref(h)), "vcx_server_create")
+        self.h = h
+        self._req = {}    # id -> (mesh, nvar): meshes stay alive while their requests run
+
+    def submit(self, mesh: Mesh, phys: Physics, U0, E=None, nsteps: int = 1, t_end: float = 0.0):
+        U0 = _f64(U0)
+        Ec = None if E is None else _f64(E)
+        rid = C.c_int64()
+        _check(lib().vcx_server_submit(self.h, mesh.h, C.byref(phys), _dptr(U0),
+                                       _dptr(Ec) if Ec is not None else None, int(nsteps),
+                                       float(t_end), C.byref(rid)), "vcx_server_submit")
+        self._req[rid.value] = (mesh, U0.shape)
+        return rid.value
+
+    def poll(self, rid: int, take: bool = True):
+        """(done, status, U or None, t).  With take, a finished request's
+        state is returned and the request is forgotten."""
+        done, st, t = C.c_int(), C.c_int(), C.c_double()
+        mesh, shape = self._req.get(rid, (None, None))
+        U = np.zeros(shape) if take and shape is not None else None
+        _check(lib().vcx_server_poll(self.h, int(rid), C.byref(done), C.byref(st),
+                                     _dptr(U) if U is not None else None, C.byref(t)),
+               "vcx_server_poll")
+        if not done.value:
+            return False, None, None, None
+        if take:
+            del self._req[rid]
+        return True, st.value, U, t.value
+
+    def wait(self, rid: int, timeout: float = -1.0) -> bool:
+        done = C.c_int()
+        _check(lib().vcx_server_wait(self.h, int(rid), float(timeout), C.byref(done)),
+               "vcx_server_wait")
+        return bool(done.value)
+
+    def stats(self) -> dict:
+        out = np.zeros(16)
+        _check(lib().vcx_server_stats(self.h, _dptr(out)), "vcx_server_stats")
+        return dict(zip(SERVER_STATS, out.tolist()))
+
+    def close(self):
+        if getattr(self, "h", None):
+            _check(lib().vcx_server_destroy(self.h), "vcx_server_destroy")
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve_batch(solvers, nsteps, t_end=None, graphs=True):
     """Advance independent solvers together (batched kernels); nsteps and
     t_end are per solver (t_end None or <= 0: no end time)."""
     n = len(solvers)
@@ -315,4 +396,5 @@ def solve_batch(solvers, nsteps, t_end=None):
     hs = (C.c_void_p * n)(*[s.h for s in solvers])
     ns = (C.c_int * n)(*[int(x) for x in nsteps])
     te = (C.c_double * n)(*[float(x) for x in t_end])
-    _check(lib().vcx_solve_batch(hs, n, ns, te), "vcx_solve_batch")
+    fn = lib().vcx_solve_batch if graphs else lib().vcx_solve_batch_eager
+    _check(fn(hs, n, ns, te), "vcx_solve_batch")
