@@ -45,6 +45,16 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the profiled pass")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-requests", type=int, default=256)
+    ap.add_argument("--serve-pool", type=int, default=16)
+    ap.add_argument("--serve-steps", type=int, default=100)
+    ap.add_argument("--serve-budget-gb", type=float, default=8.0)
+    ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--serve-graphs", type=int, default=1, help="server replays captured graphs")
+    ap.add_argument("--serve-only", action="store_true", help="run the serving leg only")
+    ap.add_argument("--serve-load", type=float, default=0.8,
+                    help="arrival rate as a fraction of the measured batched capacity")
     return ap.parse_args()
 
 
@@ -102,6 +112,129 @@ def workload(name):
     raise ValueError(name)
 
 
+def serving_leg(a, stream):
+    """Serving workload: requests on 2D meshes of 5e3..2e6 cells (gas: HLLC +
+    van Leer, RK2 on the periodic unit square; drift-diffusion as the main
+    workload), a fixed number of steps each, served by the continuous-batching
+    server in mixed precision with graph replay under a device-memory budget.
+    1) capacity: every request submitted at once; 2) open loop: Poisson
+    arrivals at a fraction of that capacity, latency from arrival to result;
+    3) baseline: the same requests one at a time on the FP64 single-solve path
+    (vcx_step), FIFO latencies for the same arrival times from the measured
+    service times."""
+    import threading
+    from paper_2201_01291_amd import vcx, workloads as wl
+    pool, reqs = wl.serving_requests(a.serve_requests, npool=a.serve_pool)
+    sp = wl.DD_STREAMER_SPECIES
+    print(f"[bench] serving: building {len(pool)} x 2 pool meshes", file=sys.stderr, flush=True)
+    meshes = []
+    for k, p in enumerate(pool):
+        mg = wl.tri_rect_mesh(p["gas_side"], p["gas_side"], 1.0, 1.0, jitter=0.2, seed=1000 + k,
+                              periodic=True)
+        md = wl.dd_streamer_mesh(p["dd_nx"], p["dd_ny"], seed=2000 + k)
+        Ug = wl.euler_blob_state(mg, nblobs=4, amp=0.3, sigma=0.1, seed=k)
+        nd_, Ed = wl.dd_fields(md, seed=k)
+        meshes.append(dict(gas=(vcx.Mesh(mg, stream=stream), Ug, None, mg.nfaces * 2),
+                           dd=(vcx.Mesh(md, stream=stream), nd_, Ed, md.nfaces)))
+
+    def phys(kind, prec):
+        if kind == "gas":
+            return vcx.physics(model=vcx.MODEL_GAS, flux=vcx.FLUX_HLLC, limiter=vcx.LIM_VANLEER,
+                               rk_stages=2, precision=prec, cfl=0.5)
+        return vcx.physics(model=vcx.MODEL_DRIFT_DIFFUSION, limiter=vcx.LIM_MINMOD, rk_stages=1,
+                           nspecies=2, precision=prec, beta=1.0, cfl=0.5, fourier=0.25,
+                           z=[x.z for x in sp], mu=[x.mu for x in sp], D=[x.D for x in sp])
+
+    P = {(k, pr): phys(k, pr) for k in ("gas", "dd") for pr in (vcx.PREC_FP64, vcx.PREC_MIXED)}
+    nst = a.serve_steps
+    items = []
+    for r in reqs:
+        gm, U, E, fpr = meshes[r["pool"]][r["kind"]]
+        items.append((r["kind"], gm, U * r["scale"], E, fpr * nst))
+    total_faces = sum(x[4] for x in items)
+    budget = int(a.serve_budget_gb * (1 << 30))
+
+    def serve(todo, arrivals=None):
+        sv = vcx.Server(hbm_budget=budget, max_slots=a.serve_slots, chunk_steps=16,
+                        graphs=bool(a.serve_graphs))
+        ids = []
+        t0 = time.perf_counter()
+        for k, (kind, gm, U, E, _) in enumerate(todo):
+            if arrivals is not None:
+                dt = t0 + arrivals[k] - time.perf_counter()
+                if dt > 0:
+                    time.sleep(dt)
+            ids.append(sv.submit(gm, P[(kind, vcx.PREC_MIXED)], U, E, nsteps=nst))
+        done_t = []
+        for rid in ids:
+            sv.wait(rid)
+            done_t.append(time.perf_counter())
+        # completion times are observed in order; use the server's own latencies
+        st = sv.stats()
+        for rid in ids:
+            ok, code, _, _ = sv.poll(rid)
+            assert ok and code == vcx.OK, code
+        wall = max(done_t) - t0
+        sv.close()
+        return st, wall
+
+    serve(items[:8])   # warm-up: first launches and graph captures
+    print("[bench] serving: capacity run", file=sys.stderr, flush=True)
+    st_c, wall_c = serve(items)
+    cap = len(items) / wall_c
+    rate = a.serve_load * cap
+    gaps = np.array([r["gap"] for r in reqs]) / rate
+    arrivals = np.cumsum(gaps) - gaps[0]
+    print(f"[bench] serving: open loop at {rate:.1f} req/s", file=sys.stderr, flush=True)
+    st_o, wall_o = serve(items, arrivals)
+
+    # baseline: one request at a time, FP64 single-solve path
+    print("[bench] serving: sequential FP64 baseline", file=sys.stderr, flush=True)
+    svc = []
+    for kind, gm, U, E, _ in items:
+        t1 = time.perf_counter()
+        s = vcx.Solver(gm, P[(kind, vcx.PREC_FP64)], E)
+        s.upload(U)
+        s.step(nst)
+        s.download()
+        s.close()
+        svc.append(time.perf_counter() - t1)
+    svc = np.array(svc)
+    fin, lat = 0.0, []
+    for arr, sv_t in zip(arrivals, svc):
+        fin = max(fin, arr) + sv_t
+        lat.append((fin - arr) * 1e3)
+    base = dict(kind="one request at a time, FP64, vcx_step (no batching, no graphs)",
+                throughput_mfaces=round(total_faces / svc.sum() / 1e6, 1),
+                capacity_req_s=round(len(items) / svc.sum(), 2),
+                latency_p50_ms=round(float(np.percentile(lat, 50)), 2),
+                latency_p99_ms=round(float(np.percentile(lat, 99)), 2),
+                step_p50_ms=round(float(np.percentile(svc / nst * 1e3, 50)), 4),
+                step_p99_ms=round(float(np.percentile(svc / nst * 1e3, 99)), 4),
+                latency_note="FIFO queue over the same arrival times, from measured service times")
+    cells = np.array([pool[r["pool"]]["cells"] for r in reqs])
+    return dict(
+        workload=(f"{len(items)} requests, {nst} steps each, meshes of 5e3..2e6 cells "
+                  f"(pool of {len(pool)} sizes per kind), even ids gas HLLC-vanLeer-RK2, odd ids "
+                  f"drift-diffusion LLW-minmod-RK1; mixed precision; device budget "
+                  f"{a.serve_budget_gb:g} GiB, {a.serve_slots} slots, chunks of 16 steps, "
+                  f"{'graph replay' if a.serve_graphs else 'direct launches'}"),
+        mean_cells=round(float(cells.mean())),
+        capacity_req_s=round(cap, 2),
+        capacity_throughput_mfaces=round(total_faces / wall_c / 1e6, 1),
+        rate_req_s=round(rate, 2),
+        open_loop_throughput_mfaces=round(total_faces / wall_o / 1e6, 1),
+        latency_p50_ms=round(st_o["latency_p50_ms"], 2),
+        latency_p99_ms=round(st_o["latency_p99_ms"], 2),
+        step_p50_ms=round(st_o["step_p50_ms"], 4),
+        step_p99_ms=round(st_o["step_p99_ms"], 4),
+        mean_running=round(st_o["mean_running"], 2),
+        peak_running=int(st_o["peak_running"]),
+        peak_resident_gb=round(st_o["peak_resident_bytes"] / (1 << 30), 3),
+        baseline=base,
+    )
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -112,6 +245,9 @@ def main():
     from paper_2201_01291_amd import vcx
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if a.serve_only:
+        print(json.dumps({"serving": serving_leg(a, torch.cuda.current_stream().cuda_stream)}))
+        return
     print(f"[bench] building workload {a.workload}", file=sys.stderr, flush=True)
     m, U0, E, phys, ophys, cfg, alg = workload(a.workload)
     stream = torch.cuda.current_stream()
@@ -133,6 +269,24 @@ def main():
     faces_per_step = m.nfaces * cfg["residuals_per_step"]
     mfaces = faces_per_step * a.steps / el / 1e6
     U64 = s64.download()
+
+    # ---- the same solve as a batch of one (batched kernels, graph replay)
+    s64.upload(U0)
+    vcx.solve_batch([s64], [a.warmup])
+    s64.upload(U0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    vcx.solve_batch([s64], [a.steps])
+    torch.cuda.synchronize()
+    el_g = time.perf_counter() - t0
+    assert np.array_equal(s64.download(), U64), "batch-of-one result differs from vcx_step"
+    s64.upload(U0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    vcx.solve_batch([s64], [a.steps], graphs=False)
+    torch.cuda.synchronize()
+    el_e = time.perf_counter() - t0
+    assert np.array_equal(s64.download(), U64), "batch-of-one result differs from vcx_step"
 
     # ---- mixed path over the same steps: throughput and drift from FP64
     s32.upload(U0)
@@ -196,6 +350,10 @@ def main():
                    kind="oracle", sample=f"{nsteps} full steps of the same mesh and state "
                                          f"({elc:.1f} s, sequential FP64 C oracle)")
 
+    serve = None
+    if not a.no_serve:
+        serve = serving_leg(a, stream.cuda_stream)
+
     out = {
         "metric": "Mfaces/s residual throughput",
         "value": round(mfaces, 2),
@@ -211,6 +369,9 @@ def main():
         "data": "synthetic",
         "config": cfg,
         "hbm_gbs_algorithmic_step": round(alg["step"] * a.steps / el / 1e9, 1),
+        "batch_of_one": dict(graph=round(faces_per_step * a.steps / el_g / 1e6, 2),
+                             direct=round(faces_per_step * a.steps / el_e / 1e6, 2),
+                             unit="Mfaces/s", bitwise_equal_to_vcx_step=True),
         "mixed": dict(value=round(faces_per_step * a.steps / el32 / 1e6, 2), unit="Mfaces/s",
                       ms_per_step=round(el32 / a.steps * 1e3, 5),
                       drift_vs_fp64_after_steps=drift),
@@ -218,6 +379,7 @@ def main():
         "kernels": kern,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "serving": serve,
         "mesh": info,
     }
     print(json.dumps(out))

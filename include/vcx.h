@@ -284,11 +284,15 @@ vcx_status vcx_server_poll(vcx_server sv, int64_t id, int *done, vcx_status *res
  * limit); *done as in vcx_server_poll. */
 vcx_status vcx_server_wait(vcx_server sv, int64_t id, double timeout_s, int *done);
 
-/* out[16]: submitted, completed, failed, queued, running, member steps done,
+/* out[17]: submitted, completed, failed, queued, running, member steps done,
  * chunks run, mean running requests per chunk, request latency p50 / p99
- * (submit to finish, ms), step latency p50 / p99 (chunk wall time / steps,
- * ms), resident bytes, peak resident bytes, peak running requests, status
- * of the last device error (0 = none). */
+ * (submit to finish, ms), step latency p50 / p99 (wall time of a scheduler
+ * iteration / its steps, ms), bytes of running requests, peak bytes held
+ * (running plus idle), peak running requests, status of the last device
+ * error (0 = none), bytes of idle solvers.  Finished requests leave their
+ * solver idle for reuse by a later request with the same mesh and physics
+ * (idle solvers count against the budget and are freed, least recently
+ * used first, when a new request needs the room). */
 vcx_status vcx_server_stats(vcx_server sv, double *out);
 
 /* Cancel queued requests (VCX_E_BUSY), finish running ones, stop the

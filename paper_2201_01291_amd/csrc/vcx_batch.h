@@ -41,6 +41,11 @@ bool batch_compatible(vcx_solver a, vcx_solver b);
 // Device bytes a solver of this physics on this mesh allocates.
 vcx_status solver_footprint(vcx_mesh mesh, const vcx_physics* phys, size_t* bytes);
 
+// Reuse of a solver for a new request: same mesh and byte-identical
+// physics; a drift-diffusion solver takes the new request's field.
+bool solver_matches(vcx_solver s, vcx_mesh mesh, const vcx_physics* ph);
+vcx_status solver_set_field(vcx_solver s, const double* E);
+
 // Small accessors and the thread's error message (vcx_last_error).
 vcx_status set_error(vcx_status s, const char* msg);
 int mesh_ndim(vcx_mesh m);

@@ -624,6 +624,10 @@ static void free_solver(vcx_solver s) {
   delete s;
 }
 
+static bool same_scheme(const vcx_physics& a, const vcx_physics& b) {
+  return std::memcmp(&a, &b, sizeof(vcx_physics)) == 0;
+}
+
 // Device buffers of a solver, in doubles (one definition for creation and
 // for the footprint query used by admission control).
 struct SolverSizes {
@@ -673,6 +677,27 @@ static vcx_status reset_scalars(vcx_solver s, double t0, bool prime) {
   s->host_flag = 0;
   s->steps_total = 0;
   return VCX_OK;
+}
+
+// electric field (host, caller order) -> s->E (internal order), synchronised
+static vcx_status upload_field(vcx_solver s, const double* E) {
+  const DevMesh& d = s->mesh->d;
+  const size_t nn = (size_t)d.nn;
+  VCX_HIP(hipMemcpyAsync(s->io, E, sizeof(double) * s->nd * nn, hipMemcpyHostToDevice, s->mesh->stream));
+  hipLaunchKernelGGL(k_gather_rows, dim3((nn + 255) / 256), dim3(256), 0, s->mesh->stream, d.perm,
+                     (const double*)s->io, s->E, (int)nn, s->nd);
+  VCX_HIP(hipGetLastError());
+  VCX_HIP(hipStreamSynchronize(s->mesh->stream));
+  return VCX_OK;
+}
+
+vcx_status vcx::solver_set_field(vcx_solver s, const double* E) {
+  if (!s || !E || !s->E) return fail(VCX_E_ARG, "no field to set");
+  return upload_field(s, E);
+}
+
+bool vcx::solver_matches(vcx_solver s, vcx_mesh mesh, const vcx_physics* ph) {
+  return s && s->mesh == mesh && same_scheme(s->ph, *ph);
 }
 
 extern "C" vcx_status vcx_solver_create(vcx_mesh mesh, const vcx_physics* phys, const double* E,
@@ -736,7 +761,6 @@ extern "C" vcx_status vcx_solver_create(vcx_mesh mesh, const vcx_physics* phys, 
   s->tile_block = std::min(256, ((d.max_tile_cells + 63) / 64) * 64);
   const SolverSizes z = solver_sizes(d, nd, s->nvar, s->nr, s->nw, s->ngf, ph.model);
   s->bytes = z.bytes();
-  const size_t nn = (size_t)d.nn;
   vcx_status st = VCX_OK;
   auto chk = [&](vcx_status x) {
     if (st == VCX_OK) st = x;
@@ -765,18 +789,7 @@ extern "C" vcx_status vcx_solver_create(vcx_mesh mesh, const vcx_physics* phys, 
     st = fail(VCX_E_OOM, "hipHostMalloc failed");
   if (st == VCX_OK && ph.model == VCX_MODEL_DRIFT_DIFFUSION) {
     chk(dmalloc(&s->E, z.E));
-    if (st == VCX_OK) {
-      // field in caller order -> internal order
-      if (hipMemcpyAsync(s->io, E, sizeof(double) * nd * nn, hipMemcpyHostToDevice,
-                         mesh->stream) != hipSuccess)
-        st = fail(VCX_E_HIP, "field upload failed");
-      else {
-        hipLaunchKernelGGL(k_gather_rows, dim3((nn + 255) / 256), dim3(256), 0, mesh->stream,
-                           d.perm, (const double*)s->io, s->E, (int)nn, nd);
-        if (hipStreamSynchronize(mesh->stream) != hipSuccess)
-          st = fail(VCX_E_HIP, "field upload failed");
-      }
-    }
+    if (st == VCX_OK) st = upload_field(s, E);
   }
   if (st == VCX_OK) st = reset_scalars(s, 0.0, false);
   if (st != VCX_OK) {
@@ -1000,10 +1013,6 @@ static vcx_status dev_array(T** p, int* cap, int need) {
   }
   *cap = c;
   return VCX_OK;
-}
-
-static bool same_scheme(const vcx_physics& a, const vcx_physics& b) {
-  return std::memcmp(&a, &b, sizeof(vcx_physics)) == 0;
 }
 
 struct vcx::BatchGroup {
@@ -1251,11 +1260,19 @@ static vcx_status solve_batch(vcx_solver* ss, int n, const int* nsteps, const do
   VCX_TRY(batch_set(g, ss, n, nsteps, t_end));
   int maxsteps = 0;
   for (int i = 0; i < n; ++i) maxsteps = std::max(maxsteps, nsteps[i]);
-  const int chunk = 16;
-  std::vector<int> ended;
+  std::vector<int> ended(n, 0);
   int q = 0;
   do {
-    const int c = std::min(chunk, maxsteps - q);
+    // a chunk ends where the first live member's budget does (host checks in
+    // between); members with an end time are checked every 16 steps
+    int c = 256;
+    for (int i = 0; i < n; ++i) {
+      const long long left = nsteps[i] - (ss[i]->steps_total - steps0[i]);
+      if (ended[i] || left <= 0) continue;
+      c = (int)std::min<long long>(c, left);
+      if (t_end[i] > 0.0) c = std::min(c, 16);
+    }
+    c = std::max(1, std::min(c, maxsteps - q));
     VCX_TRY(batch_run(g, c));
     q += c;
     VCX_TRY(batch_sync(g, &ended));

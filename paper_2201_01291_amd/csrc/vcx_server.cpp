@@ -47,7 +47,14 @@ struct Request {
   std::vector<double> U;  // final state (caller node order)
   double t = 0.0, dt_last = 0.0;
   int64_t steps = 0;
+  bool ended = false;
   clk::time_point t_submit, t_admit, t_done;
+};
+
+struct Idle {
+  vcx_solver s;
+  size_t bytes;
+  clk::time_point since;
 };
 
 struct Group {
@@ -82,8 +89,10 @@ struct vcx_server_s {
   std::condition_variable cv_work, cv_done;
   std::deque<Request*> queue;
   std::unordered_map<int64_t, std::unique_ptr<Request>> reqs;
-  size_t resident = 0;
+  size_t resident = 0;    // bytes of running and idle solvers
+  size_t idle_bytes = 0;
   int running = 0;
+  std::vector<Idle> idle; // finished solvers kept for reuse (worker thread only)
   int64_t next_id = 1;
   bool stop = false;
   std::thread worker;
@@ -96,13 +105,22 @@ struct vcx_server_s {
   std::string worker_err;
 
   void run();
+  void admit(std::vector<Request*>& out, std::vector<vcx_solver>& evict);
+  void start(std::vector<Request*>& adm, std::vector<Group>& groups);
   void finish(Request* r, vcx_status st, const std::string& msg);
   void retire(Request* r);
 };
 
 void vcx_server_s::finish(Request* r, vcx_status st, const std::string& msg) {
+  bool keep = false;
   if (r->s) {
-    (void)vcx_solver_destroy(r->s);
+    // an intact solver waits in the idle pool for a request with the same
+    // mesh and physics; its bytes stay counted in the resident total
+    keep = st == VCX_OK || st == VCX_E_UNSTABLE;
+    if (keep)
+      idle.push_back(Idle{r->s, r->bytes, clk::now()});
+    else
+      (void)vcx_solver_destroy(r->s);
     r->s = nullptr;
   }
   std::lock_guard<std::mutex> lk(mu);
@@ -111,7 +129,10 @@ void vcx_server_s::finish(Request* r, vcx_status st, const std::string& msg) {
   r->state = DONE;
   r->t_done = clk::now();
   if (r->admitted) {
-    resident -= r->bytes;
+    if (keep)
+      idle_bytes += r->bytes;
+    else
+      resident -= r->bytes;
     running -= 1;
     r->admitted = false;
   }
@@ -142,12 +163,102 @@ void vcx_server_s::retire(Request* r) {
   finish(r, st, msg);
 }
 
+// Admission (under mu): requests leave the queue in arrival order while a
+// slot is free and their footprint fits the budget, counting idle solvers
+// that can be reused as free and evicting other idle solvers when needed.
+void vcx_server_s::admit(std::vector<Request*>& out, std::vector<vcx_solver>& evict) {
+  while (!queue.empty() && running < max_slots) {
+    Request* r = queue.front();
+    if (r->bytes > budget) {
+      queue.pop_front();
+      r->status = VCX_E_OOM;
+      r->err = "request footprint exceeds the server's device-memory budget";
+      r->state = DONE;
+      failed += 1;
+      cv_done.notify_all();
+      continue;
+    }
+    size_t reuse = idle.size();
+    for (size_t k = 0; k < idle.size(); ++k)
+      if (vcx::solver_matches(idle[k].s, r->mesh, &r->ph)) {
+        reuse = k;
+        break;
+      }
+    if (reuse < idle.size()) {
+      r->s = idle[reuse].s;
+      r->bytes = idle[reuse].bytes;
+      idle_bytes -= r->bytes;
+      idle.erase(idle.begin() + (long)reuse);
+    } else {
+      // evict the least recently used idle solvers until the request fits
+      while (resident + r->bytes > budget && !idle.empty()) {
+        auto lru = std::min_element(idle.begin(), idle.end(),
+                                    [](const Idle& x, const Idle& y) { return x.since < y.since; });
+        evict.push_back(lru->s);
+        resident -= lru->bytes;
+        idle_bytes -= lru->bytes;
+        idle.erase(lru);
+      }
+      if (resident + r->bytes > budget) break;  // first in, first admitted
+      resident += r->bytes;
+    }
+    queue.pop_front();
+    r->admitted = true;
+    running += 1;
+    peak_resident = std::max(peak_resident, resident);
+    peak_running = std::max(peak_running, running);
+    out.push_back(r);
+  }
+}
+
+// Solver creation (or reuse) and state upload of admitted requests; they
+// join their scheme's group at the next chunk.
+void vcx_server_s::start(std::vector<Request*>& adm, std::vector<Group>& groups) {
+  for (Request* r : adm) {
+    r->t_admit = clk::now();
+    vcx_status st = VCX_OK;
+    if (r->s) {
+      if (r->ph.model == VCX_MODEL_DRIFT_DIFFUSION) st = vcx::solver_set_field(r->s, r->E.data());
+    } else {
+      st = vcx_solver_create(r->mesh, &r->ph, r->E.empty() ? nullptr : r->E.data(), &r->s);
+    }
+    if (st == VCX_OK) st = vcx_state_upload(r->s, r->U0.data(), 0);
+    if (st != VCX_OK) {
+      finish(r, st, vcx_last_error());
+      continue;
+    }
+    std::vector<double>().swap(r->U0);
+    std::vector<double>().swap(r->E);
+    r->state = RUNNING;
+    if (r->nsteps == 0) {
+      retire(r);
+      continue;
+    }
+    Group* home = nullptr;
+    for (Group& g : groups)
+      if (!g.mem.empty() && vcx::batch_compatible(g.mem[0]->s, r->s)) home = &g;
+    if (!home) {
+      Group g;
+      if (vcx::batch_create(stream, graphs, &g.g) != VCX_OK) {
+        finish(r, VCX_E_HIP, vcx_last_error());
+        continue;
+      }
+      groups.push_back(g);
+      home = &groups.back();
+    }
+    home->mem.push_back(r);
+    home->dirty = true;
+  }
+  adm.clear();
+}
+
 void vcx_server_s::run() {
   (void)hipSetDevice(device);
   std::vector<Group> groups;
   std::vector<int> ended;
+  std::vector<Request*> adm;
+  std::vector<vcx_solver> evict;
   for (;;) {
-    std::vector<Request*> admitted;
     {
       std::unique_lock<std::mutex> lk(mu);
       cv_work.wait(lk, [&] { return stop || !queue.empty() || running > 0; });
@@ -163,61 +274,17 @@ void vcx_server_s::run() {
         cv_done.notify_all();
         if (running == 0) break;
       }
-      while (!queue.empty() && running + (int)admitted.size() < max_slots) {
-        Request* r = queue.front();
-        if (r->bytes > budget) {
-          queue.pop_front();
-          r->status = VCX_E_OOM;
-          r->err = "request footprint exceeds the server's device-memory budget";
-          r->state = DONE;
-          failed += 1;
-          cv_done.notify_all();
-          continue;
-        }
-        if (resident + r->bytes > budget) break;  // first in, first admitted
-        queue.pop_front();
-        r->admitted = true;
-        resident += r->bytes;
-        peak_resident = std::max(peak_resident, resident);
-        admitted.push_back(r);
-      }
-      running += (int)admitted.size();
-      peak_running = std::max(peak_running, running);
+      if (groups.empty()) admit(adm, evict);
     }
-    for (Request* r : admitted) {
-      r->t_admit = clk::now();
-      vcx_status st = vcx_solver_create(r->mesh, &r->ph, r->E.empty() ? nullptr : r->E.data(), &r->s);
-      if (st == VCX_OK) st = vcx_state_upload(r->s, r->U0.data(), 0);
-      if (st != VCX_OK) {
-        finish(r, st, vcx_last_error());
-        continue;
-      }
-      std::vector<double>().swap(r->U0);
-      r->state = RUNNING;
-      if (r->nsteps == 0) {
-        retire(r);
-        continue;
-      }
-      Group* home = nullptr;
-      for (Group& g : groups)
-        if (!g.mem.empty() && vcx::batch_compatible(g.mem[0]->s, r->s)) home = &g;
-      if (!home) {
-        Group g;
-        if (vcx::batch_create(stream, graphs, &g.g) != VCX_OK) {
-          finish(r, VCX_E_HIP, vcx_last_error());
-          continue;
-        }
-        groups.push_back(g);
-        home = &groups.back();
-      }
-      home->mem.push_back(r);
-      home->dirty = true;
-    }
+    for (vcx_solver s : evict) (void)vcx_solver_destroy(s);
+    evict.clear();
+    const auto t0 = clk::now();
+    if (groups.empty()) start(adm, groups);
     if (groups.empty()) continue;
     // steps of this chunk: no member runs past its budget inside the chunk
     int c = chunk;
     for (Group& g : groups)
-      for (Request* r : g.mem) c = std::min<int64_t>(c, std::max<int64_t>(1, r->nsteps - r->steps));
+      for (Request* r : g.mem) c = (int)std::min<int64_t>(c, std::max<int64_t>(1, r->nsteps - r->steps));
     vcx_status st = VCX_OK;
     for (Group& g : groups) {
       if (!g.dirty) continue;
@@ -233,14 +300,22 @@ void vcx_server_s::run() {
       if (st != VCX_OK) break;
       g.dirty = false;
     }
-    const auto t0 = clk::now();
     int members = 0;
-    int64_t done_steps = 0;
     for (Group& g : groups) {
       if (st != VCX_OK) break;
       st = vcx::batch_run(g.g, c);
       members += (int)g.mem.size();
     }
+    // while the chunk runs: admit and upload new requests for the next one
+    if (st == VCX_OK) {
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        if (!stop) admit(adm, evict);
+      }
+      for (vcx_solver s : evict) (void)vcx_solver_destroy(s);
+      evict.clear();
+    }
+    int64_t done_steps = 0;
     for (Group& g : groups) {
       if (st != VCX_OK) break;
       st = vcx::batch_sync(g.g, &ended);
@@ -248,17 +323,10 @@ void vcx_server_s::run() {
       for (size_t i = 0; i < g.mem.size(); ++i) {
         const int64_t k = vcx_steps_done(g.mem[i]->s);
         g.mem[i]->steps += k;
+        g.mem[i]->ended = ended[i] != 0;
         done_steps += k;
       }
-      for (size_t i = 0; i < g.mem.size(); ++i)
-        if (ended[i]) {
-          retire(g.mem[i]);
-          g.mem[i] = nullptr;
-          g.dirty = true;
-        }
-      g.mem.erase(std::remove(g.mem.begin(), g.mem.end(), nullptr), g.mem.end());
     }
-    const auto t1 = clk::now();
     if (st != VCX_OK) {
       // a device error ends every running request of the server
       const std::string msg = vcx_last_error();
@@ -266,10 +334,24 @@ void vcx_server_s::run() {
         for (Request* r : g.mem) finish(r, st, msg);
         g.mem.clear();
       }
+      for (Request* r : adm) finish(r, st, msg);
+      adm.clear();
       std::lock_guard<std::mutex> lk(mu);
       worker_status = st;
       worker_err = msg;
     }
+    for (Group& g : groups) {
+      for (Request*& r : g.mem)
+        if (r->ended) {
+          retire(r);
+          r = nullptr;
+          g.dirty = true;
+        }
+      g.mem.erase(std::remove(g.mem.begin(), g.mem.end(), nullptr), g.mem.end());
+    }
+    // requests admitted during the chunk join now
+    start(adm, groups);
+    const auto t1 = clk::now();
     {
       std::lock_guard<std::mutex> lk(mu);
       chunks += 1;
@@ -286,6 +368,8 @@ void vcx_server_s::run() {
                  groups.end());
   }
   for (Group& g : groups) vcx::batch_destroy(g.g);
+  for (Idle& x : idle) (void)vcx_solver_destroy(x.s);
+  idle.clear();
 }
 
 extern "C" vcx_status vcx_server_create(size_t hbm_budget, int max_slots, int chunk_steps, int use_graphs,
@@ -397,10 +481,11 @@ extern "C" vcx_status vcx_server_stats(vcx_server sv, double* out) {
   out[9] = pct(sv->lat_ms, 99.0);
   out[10] = pct(sv->step_ms, 50.0);
   out[11] = pct(sv->step_ms, 99.0);
-  out[12] = (double)sv->resident;
+  out[12] = (double)(sv->resident - sv->idle_bytes);
   out[13] = (double)sv->peak_resident;
   out[14] = (double)sv->peak_running;
   out[15] = (double)sv->worker_status;
+  out[16] = (double)sv->idle_bytes;
   return VCX_OK;
 }
 

@@ -322,7 +322,8 @@ def footprint(mesh: Mesh, phys: Physics) -> int:
 
 SERVER_STATS = ("submitted", "completed", "failed", "queued", "running", "member_steps", "chunks",
                 "mean_running", "latency_p50_ms", "latency_p99_ms", "step_p50_ms", "step_p99_ms",
-                "resident_bytes", "peak_resident_bytes", "peak_running", "device_error")
+                "resident_bytes", "peak_resident_bytes", "peak_running", "device_error",
+                "idle_bytes")
 
 
 class Server:
@@ -367,7 +368,7 @@ class Server:
         return bool(done.value)
 
     def stats(self) -> dict:
-        out = np.zeros(16)
+        out = np.zeros(17)
         _check(lib().vcx_server_stats(self.h, _dptr(out)), "vcx_server_stats")
         return dict(zip(SERVER_STATS, out.tolist()))
 

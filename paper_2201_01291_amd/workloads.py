@@ -337,21 +337,33 @@ def euler3d_mesh(nx: int = 70, ny: int = 70, nz: int = 68, jitter: float = 0.1,
                          jitter=jitter, seed=seed, periodic=True)
 
 
-def serving_requests(n: int = 256, *, seed: int = 5, cell_min: float = 5e3,
-                     cell_max: float = 2e6, rate: float = 1.0):
-    """Request stream: log-uniform cell counts, Poisson arrival times at
-    ``rate`` requests per unit time; even ids gas, odd ids drift-diffusion."""
+def serving_requests(n: int = 256, *, seed: int = 5, npool: int = 16, cell_min: float = 5e3,
+                     cell_max: float = 2e6):
+    """Request stream of the serving workload.
+
+    Returns ``(pool, requests)``.  ``pool`` holds ``npool`` cell counts,
+    log-uniform in [cell_min, cell_max]; each pool entry is meshed twice: a
+    periodic unit square for gas requests (side = sqrt(cells / 2)) and the
+    drift-diffusion box of ``dd_streamer_mesh`` at the matching resolution.
+    Each request picks a pool entry uniformly; even ids are gas, odd ids
+    drift-diffusion; ``scale`` (log-uniform in [0.5, 2]) multiplies the pool
+    entry's initial state, so requests on one mesh differ; ``gap`` is the
+    unit-rate exponential inter-arrival time (divide by the arrival rate).
+    """
     rng = np.random.default_rng(seed)
-    cells = np.exp(rng.uniform(math.log(cell_min), math.log(cell_max), size=n))
-    gaps = rng.exponential(1.0 / rate, size=n)
-    arrivals = np.cumsum(gaps) - gaps[0]
-    out = []
-    for k in range(n):
-        # square-ish periodic tri mesh with ~cells[k] triangles
-        side = max(3, int(round(math.sqrt(cells[k] / 2.0))))
-        out.append(dict(id=k, kind="gas" if k % 2 == 0 else "dd", nx=side, ny=side,
-                        arrival=float(arrivals[k]), seed=int(rng.integers(1 << 30))))
-    return out
+    cells = np.exp(rng.uniform(math.log(cell_min), math.log(cell_max), size=npool))
+    pool = []
+    for c in cells:
+        side = max(3, int(round(math.sqrt(c / 2.0))))
+        nx = max(3, int(round(math.sqrt(c / 2.0 * 1.6))))
+        ny = max(3, int(round(nx / 1.6)))
+        pool.append(dict(cells=float(c), gas_side=side, dd_nx=nx, dd_ny=ny))
+    which = rng.integers(npool, size=n)
+    scale = np.exp(rng.uniform(math.log(0.5), math.log(2.0), size=n))
+    gaps = rng.exponential(1.0, size=n)
+    reqs = [dict(id=k, kind="gas" if k % 2 == 0 else "dd", pool=int(which[k]),
+                 scale=float(scale[k]), gap=float(gaps[k])) for k in range(n)]
+    return pool, reqs
 
 
 # ---------------------------------------------------------------------------

@@ -73,6 +73,30 @@ def test_requests_in_a_mix_match_alone():
     assert st["completed"] == len(reqs) and st["failed"] == 0
     assert st["peak_running"] >= 2 and st["mean_running"] > 1.0
     assert st["resident_bytes"] == 0 and st["running"] == 0
+    assert st["peak_resident_bytes"] >= st["idle_bytes"] > 0
+    sv.close()
+
+
+def test_solver_reuse_on_a_shared_mesh():
+    """Requests on one mesh with different states and fields reuse finished
+    solvers (and their device memory) and still match the alone results."""
+    base = _request("dd", 33, 51)
+    gm = vcx.Mesh(base.mesh)
+    ins = []
+    for k in range(6):
+        n, E = wl.dd_fields(base.mesh, sigma=0.1, bump_sigma=0.1, seed=60 + k)
+        ins.append(cases.Case(f"dd-shared-{k}", base.mesh, n, E, dict(cases.DD2)))
+    ref = [_alone(c, gm, 6 + k) for k, c in enumerate(ins)]
+    fp = vcx.footprint(gm, base.vcx_phys())
+    sv = vcx.Server(hbm_budget=2 * fp, max_slots=2, chunk_steps=4)
+    ids = [sv.submit(gm, c.vcx_phys(), c.U, c.E, nsteps=6 + k) for k, c in enumerate(ins)]
+    for rid, (U, t) in zip(ids, ref):
+        assert sv.wait(rid, timeout=60)
+        done, st, Us, ts = sv.poll(rid)
+        assert st == vcx.OK and ts == t and np.array_equal(Us, U)
+    s = sv.stats()
+    assert s["peak_resident_bytes"] <= 2 * fp and s["running"] == 0
+    assert s["resident_bytes"] == 0 and s["idle_bytes"] > 0
     sv.close()
 
 
