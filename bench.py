@@ -33,6 +33,32 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+KERNEL_SOURCES = ("paper_2201_01291_amd/csrc/vcx_kernels.h", "paper_2201_01291_amd/csrc/vcx_device.h")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(record_file, kernel):
+    """HBM bytes per launch of `kernel` from a committed counter summary
+    (FETCH_SIZE and WRITE_SIZE passes, scaled by the copy-kernel
+    calibration), or None when the record is missing or the kernel sources
+    changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", record_file)
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.startswith("traffic-record:"):
+            kv = dict(x.split("=", 1) for x in line.split()[1:])
+            if kv.get("kernel") == kernel and kv.get("source") == kernel_source_hash():
+                return int(kv["bytes"])
+    return None
 
 
 def parse():
@@ -53,6 +79,8 @@ def parse():
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--serve-graphs", type=int, default=1, help="server replays captured graphs")
     ap.add_argument("--serve-only", action="store_true", help="run the serving leg only")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="end with plain 256 MiB device copies (counter calibration)")
     ap.add_argument("--serve-load", type=float, default=0.8,
                     help="arrival rate as a fraction of the measured batched capacity")
     return ap.parse_args()
@@ -88,7 +116,9 @@ def workload(name):
                       + bytes_flux                                      # flux
                       + N * 8 * (ns + ns + 1 + ns)                      # update
                       + N * 8 * nd + M * 3 * 4)                         # time step
-        return m, n, E, phys, ophys, cfg, dict(flux=bytes_flux, step=bytes_step)
+        return m, n, E, phys, ophys, cfg, dict(flux=bytes_flux, step=bytes_step,
+                                                traffic_record="traffic_flux_dd2d_streamer_200k.md",
+                                                flux_kernel="k_flux_dd<2,2,double>")
     if name == "euler3d":
         m = wl.euler3d_mesh()
         U = wl.euler_blob_state(m)
@@ -108,7 +138,9 @@ def workload(name):
         bytes_flux = N * 8 * (nr + nr * nd + nd + nv) + M * 4 * 4
         bytes_step = 2 * (N * 8 * (nr + nd) + M * 16 + N * 8 * nr * nd + bytes_flux
                           + N * 8 * (nv + nr + 1 + nr)) + N * 8 * (nr + nd) + M * 16
-        return m, U, None, phys, ophys, cfg, dict(flux=bytes_flux, step=bytes_step)
+        return m, U, None, phys, ophys, cfg, dict(flux=bytes_flux, step=bytes_step,
+                                                   traffic_record="traffic_flux_euler3d_2m.md",
+                                                   flux_kernel="k_flux_gas<3,0,1,double>")
     raise ValueError(name)
 
 
@@ -329,7 +361,8 @@ def main():
         fl = kern["flux"]
         achieved = alg["flux"] / (fl["avg_us"] * 1e-6) / 1e9
         roof = dict(kernel="flux", bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
-                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
+                    traffic=measured_traffic(alg["traffic_record"], alg["flux_kernel"]),
                     alg_bytes_per_launch=alg["flux"], avg_us=round(fl["avg_us"], 2),
                     dominant_kernel=dom)
 
@@ -383,6 +416,15 @@ def main():
         "mesh": info,
     }
     print(json.dumps(out))
+    if a.copy_calibration:
+        # a plain copy of known size: reads and writes 256 MiB per launch
+        x = torch.rand(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(f"[bench] copy calibration: {x.numel() * 8} bytes read and written per launch",
+              file=sys.stderr, flush=True)
 
 
 if __name__ == "__main__":

@@ -1,4 +1,5 @@
 // C ABI of the vertex-centred residual library (declarations in include/vcx.h).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -106,18 +107,17 @@ static hipEvent_t take_event(vcx_solver s) {
 
 template <typename F>
 static vcx_status launch_on(vcx_solver s, hipStream_t st, bool prof, const char* name, F&& f) {
+  // events are taken by the dispatch itself (start and end of the kernel)
   hipEvent_t a = nullptr, b = nullptr;
   if (prof) {
     a = take_event(s);
     b = take_event(s);
-    if (a && b) VCX_HIP(hipEventRecord(a, st));
+    if (!a || !b) a = b = nullptr;
   }
-  f();
+  (void)st;
+  f(a, b);
   VCX_HIP(hipGetLastError());
-  if (prof && a && b) {
-    VCX_HIP(hipEventRecord(b, st));
-    s->ev[name].push_back({a, b});
-  }
+  if (a && b) s->ev[name].push_back({a, b});
   return VCX_OK;
 }
 
@@ -227,17 +227,17 @@ struct Impl {
   }
   static vcx_status grad(vcx_solver s, const double* Win, const GradCtl& gc) {
     const DevMesh& m = s->mesh->d;
-    return launch(s, "gradient", [&] {
-      hipLaunchKernelGGL((k_grad_tile<ND, NGF>), dim3(xcd_grid(m.ntiles)), dim3(s->tile_block),
-                         s->lds_grad, s->mesh->stream, m, Win, s->G, s->PG, gc);
+    return launch(s, "gradient", [&](hipEvent_t ea, hipEvent_t eb) {
+      hipExtLaunchKernelGGL((k_grad_tile<ND, NGF>), dim3(xcd_grid(m.ntiles)), dim3(s->tile_block),
+                         s->lds_grad, s->mesh->stream, ea, eb, 0, m, Win, s->G, s->PG, gc);
     });
   }
   static vcx_status grad_complete(vcx_solver s) {
     const DevMesh& m = s->mesh->d;
     if (m.nshared == 0) return VCX_OK;
-    return launch(s, "gradient_shared", [&] {
-      hipLaunchKernelGGL((k_grad_shared<ND, NGF>), dim3((m.nshared + kNodeBlock - 1) / kNodeBlock),
-                         dim3(kNodeBlock), 0, s->mesh->stream, m, (const double*)s->PG, s->G);
+    return launch(s, "gradient_shared", [&](hipEvent_t ea, hipEvent_t eb) {
+      hipExtLaunchKernelGGL((k_grad_shared<ND, NGF>), dim3((m.nshared + kNodeBlock - 1) / kNodeBlock),
+                         dim3(kNodeBlock), 0, s->mesh->stream, ea, eb, 0, m, (const double*)s->PG, s->G);
     });
   }
   static vcx_status aux(vcx_solver s, double* W) {
@@ -258,16 +258,16 @@ struct Impl {
     DtParts parts = dt_parts(s);
     if constexpr (MODEL == 0) {
       GasParams gp{s->ph.gamma, s->ph.beta, s->ph.entropy_fix, s->ph.limiter};
-      return launch(s, "flux", [&] {
-        hipLaunchKernelGGL((k_flux_gas<ND, NSP, FLUX, CT>), dim3(xcd_grid(m.ntiles)),
-                           dim3(s->tile_block), s->lds_flux, st, m, Win, (const double*)s->G,
+      return launch(s, "flux", [&](hipEvent_t ea, hipEvent_t eb) {
+        hipExtLaunchKernelGGL((k_flux_gas<ND, NSP, FLUX, CT>), dim3(xcd_grid(m.ntiles)),
+                           dim3(s->tile_block), s->lds_flux, st, ea, eb, 0, m, Win, (const double*)s->G,
                            s->PR, gp, f, parts);
       });
     } else if constexpr (MODEL == 2) {
       GasParams gp{s->ph.gamma, s->ph.beta, s->ph.entropy_fix, s->ph.limiter};
-      return launch(s, "flux", [&] {
-        hipLaunchKernelGGL((k_flux_ns<ND, NSP, CT>), dim3(xcd_grid(m.ntiles)), dim3(s->tile_block),
-                           s->lds_flux, st, m, Win, (const double*)s->G, s->PR, gp, f, parts);
+      return launch(s, "flux", [&](hipEvent_t ea, hipEvent_t eb) {
+        hipExtLaunchKernelGGL((k_flux_ns<ND, NSP, CT>), dim3(xcd_grid(m.ntiles)), dim3(s->tile_block),
+                           s->lds_flux, st, ea, eb, 0, m, Win, (const double*)s->G, s->PR, gp, f, parts);
       });
     } else {
       DDParams pp{};
@@ -278,9 +278,9 @@ struct Impl {
       pp.beta = s->ph.beta;
       pp.dt_host = dt_host;
       pp.limiter = s->ph.limiter;
-      return launch(s, "flux", [&] {
-        hipLaunchKernelGGL((k_flux_dd<ND, NSP, CT>), dim3(xcd_grid(m.ntiles)),
-                           dim3(s->tile_block), s->lds_flux, st, m, Win, (const double*)s->G,
+      return launch(s, "flux", [&](hipEvent_t ea, hipEvent_t eb) {
+        hipExtLaunchKernelGGL((k_flux_dd<ND, NSP, CT>), dim3(xcd_grid(m.ntiles)),
+                           dim3(s->tile_block), s->lds_flux, st, ea, eb, 0, m, Win, (const double*)s->G,
                            s->PR, pp, f, parts);
       });
     }
@@ -288,9 +288,9 @@ struct Impl {
   static vcx_status update_shared(vcx_solver s, const Finish& f) {
     const DevMesh& m = s->mesh->d;
     DtParts parts = dt_parts(s);
-    return launch(s, "update", [&] {
-      hipLaunchKernelGGL((k_update_shared<ND, NSP, MODEL>), dim3(s->nsh_blocks), dim3(kNodeBlock), 0,
-                         s->mesh->stream, m, (const double*)s->PR, f, parts);
+    return launch(s, "update", [&](hipEvent_t ea, hipEvent_t eb) {
+      hipExtLaunchKernelGGL((k_update_shared<ND, NSP, MODEL>), dim3(s->nsh_blocks), dim3(kNodeBlock), 0,
+                         s->mesh->stream, ea, eb, 0, m, (const double*)s->PR, f, parts);
     });
   }
   static vcx_status node_dt(vcx_solver s, const double* W) {
@@ -298,9 +298,9 @@ struct Impl {
     DtParts parts = dt_parts(s);
     DtCoef dc = dt_coef(s->ph);
     MixParams mp = mix_params(s->ph);
-    return launch(s, "node_dt", [&] {
-      hipLaunchKernelGGL((k_node_dt<ND, NSP, MODEL>), dim3(s->n_dtp_node), dim3(kNodeBlock), 0,
-                         s->mesh->stream, m, W, (const double*)s->E, dc, mp, parts, s->sc);
+    return launch(s, "node_dt", [&](hipEvent_t ea, hipEvent_t eb) {
+      hipExtLaunchKernelGGL((k_node_dt<ND, NSP, MODEL>), dim3(s->n_dtp_node), dim3(kNodeBlock), 0,
+                         s->mesh->stream, ea, eb, 0, m, W, (const double*)s->E, dc, mp, parts, s->sc);
     });
   }
   // Allow dynamic LDS above the 64 KiB default for the two tile kernels.
@@ -333,23 +333,23 @@ struct Impl {
   static vcx_status batch_stage(const BatchRun& br, hipStream_t stream, const BatchStage& st, bool prof) {
     vcx_solver s = br.lead;
     FinishShared fs{dt_coef(s->ph), mix_params(s->ph), s->ph.closure};
-    VCX_TRY(launch_on(s, stream, prof, "gradient", [&] {
-      hipLaunchKernelGGL((k_grad_tile_batch<ND, NGF>), dim3(xcd_grid(br.ntile_blocks)),
-                         dim3(br.tile_block), br.lds_grad, stream, (const BatchEntry*)br.tab,
+    VCX_TRY(launch_on(s, stream, prof, "gradient", [&](hipEvent_t ea, hipEvent_t eb) {
+      hipExtLaunchKernelGGL((k_grad_tile_batch<ND, NGF>), dim3(xcd_grid(br.ntile_blocks)),
+                         dim3(br.tile_block), br.lds_grad, stream, ea, eb, 0, (const BatchEntry*)br.tab,
                          (const int2*)br.tile_map, br.ntile_blocks, st);
     }));
     if constexpr (MODEL == 0) {
       GasParams gp{s->ph.gamma, s->ph.beta, s->ph.entropy_fix, s->ph.limiter};
-      VCX_TRY(launch_on(s, stream, prof, "flux", [&] {
-        hipLaunchKernelGGL((k_flux_gas_batch<ND, NSP, FLUX, CT>), dim3(xcd_grid(br.ntile_blocks)),
-                           dim3(br.tile_block), br.lds_flux, stream, (const BatchEntry*)br.tab,
+      VCX_TRY(launch_on(s, stream, prof, "flux", [&](hipEvent_t ea, hipEvent_t eb) {
+        hipExtLaunchKernelGGL((k_flux_gas_batch<ND, NSP, FLUX, CT>), dim3(xcd_grid(br.ntile_blocks)),
+                           dim3(br.tile_block), br.lds_flux, stream, ea, eb, 0, (const BatchEntry*)br.tab,
                            (const int2*)br.tile_map, br.ntile_blocks, st, gp, fs);
       }));
     } else if constexpr (MODEL == 2) {
       GasParams gp{s->ph.gamma, s->ph.beta, s->ph.entropy_fix, s->ph.limiter};
-      VCX_TRY(launch_on(s, stream, prof, "flux", [&] {
-        hipLaunchKernelGGL((k_flux_ns_batch<ND, NSP, CT>), dim3(xcd_grid(br.ntile_blocks)),
-                           dim3(br.tile_block), br.lds_flux, stream, (const BatchEntry*)br.tab,
+      VCX_TRY(launch_on(s, stream, prof, "flux", [&](hipEvent_t ea, hipEvent_t eb) {
+        hipExtLaunchKernelGGL((k_flux_ns_batch<ND, NSP, CT>), dim3(xcd_grid(br.ntile_blocks)),
+                           dim3(br.tile_block), br.lds_flux, stream, ea, eb, 0, (const BatchEntry*)br.tab,
                            (const int2*)br.tile_map, br.ntile_blocks, st, gp, fs);
       }));
     } else {
@@ -360,15 +360,15 @@ struct Impl {
       }
       pp.beta = s->ph.beta;
       pp.limiter = s->ph.limiter;
-      VCX_TRY(launch_on(s, stream, prof, "flux", [&] {
-        hipLaunchKernelGGL((k_flux_dd_batch<ND, NSP, CT>), dim3(xcd_grid(br.ntile_blocks)),
-                           dim3(br.tile_block), br.lds_flux, stream, (const BatchEntry*)br.tab,
+      VCX_TRY(launch_on(s, stream, prof, "flux", [&](hipEvent_t ea, hipEvent_t eb) {
+        hipExtLaunchKernelGGL((k_flux_dd_batch<ND, NSP, CT>), dim3(xcd_grid(br.ntile_blocks)),
+                           dim3(br.tile_block), br.lds_flux, stream, ea, eb, 0, (const BatchEntry*)br.tab,
                            (const int2*)br.tile_map, br.ntile_blocks, st, pp, fs);
       }));
     }
-    return launch_on(s, stream, prof, "update", [&] {
-      hipLaunchKernelGGL((k_update_shared_batch<ND, NSP, MODEL>), dim3(br.nsh_blocks), dim3(kNodeBlock), 0,
-                         stream, (const BatchEntry*)br.tab, (const int2*)br.sh_map, st, fs);
+    return launch_on(s, stream, prof, "update", [&](hipEvent_t ea, hipEvent_t eb) {
+      hipExtLaunchKernelGGL((k_update_shared_batch<ND, NSP, MODEL>), dim3(br.nsh_blocks), dim3(kNodeBlock), 0,
+                         stream, ea, eb, 0, (const BatchEntry*)br.tab, (const int2*)br.sh_map, st, fs);
     });
   }
   static const KernelTable* table() {
