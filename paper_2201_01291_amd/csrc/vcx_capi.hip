@@ -216,19 +216,20 @@ struct Impl {
   static constexpr int NW = NR + NP + NA;                    // rows of a state buffer
 
   static size_t lds_grad(int maxn, int maxc) {
-    return sizeof(double) * ((size_t)(NGF + ND) * maxn + (size_t)NGF * ND * maxc);
+    return sizeof(double) * ((size_t)(NGF + ND) * maxn + (size_t)NGF * ND * maxc) + inc_lds_bytes(NV, maxc);
   }
   static size_t lds_flux(int maxn, int maxc) {
     size_t dbl = sizeof(double) * ((size_t)ND * maxn + (size_t)NV * NVAR * maxc);
     size_t ct = MODEL == 0   ? (size_t)(NR + NR * ND) * maxn
                 : MODEL == 1 ? (size_t)(NSP + NSP * ND + ND) * maxn
                              : (size_t)(NW + NGF * ND) * maxn;
-    return dbl + sizeof(CT) * ct;
+    return dbl + sizeof(CT) * ct + slot_lds_bytes(maxn) + inc_lds_bytes(NV, maxc);
   }
   static vcx_status grad(vcx_solver s, const double* Win, const GradCtl& gc) {
     const DevMesh& m = s->mesh->d;
     return launch(s, "gradient", [&](hipEvent_t ea, hipEvent_t eb) {
-      hipExtLaunchKernelGGL((k_grad_tile<ND, NGF>), dim3(xcd_grid(m.ntiles)), dim3(s->tile_block),
+      const int lead = gc.sc && gc.first_stage ? 1 : 0;
+      hipExtLaunchKernelGGL((k_grad_tile<ND, NGF>), dim3(xcd_grid(m.ntiles) + lead), dim3(s->tile_block),
                          s->lds_grad, s->mesh->stream, ea, eb, 0, m, Win, s->G, s->PG, gc);
     });
   }
@@ -514,6 +515,16 @@ extern "C" vcx_status vcx_mesh_create_tiled(int ndim, int64_t nnodes, const doub
   for (int64_t i = 0; i < h.nn; ++i) inv[i] = 1.0 / h.vnode[i];
   std::vector<int32_t> bidx(h.nn, -1);
   for (size_t q = 0; q < h.bnd_node.size(); ++q) bidx[h.bnd_node[q]] = (int32_t)q;
+  // derived tables: each tile's first incidence, each slot's position in its
+  // node's run (the index of its partial sums), each shared node's run
+  std::vector<int32_t> tile_inc(h.tile_slot.size()), slot_pos(h.slot_node.size());
+  for (size_t t = 0; t < h.tile_slot.size(); ++t) tile_inc[t] = h.slot_inc[h.tile_slot[t]];
+  for (size_t p = 0; p < h.slots_of.size(); ++p) slot_pos[h.slots_of[p]] = (int32_t)p;
+  std::vector<int32_t> srun(2 * h.shared.size());
+  for (size_t k = 0; k < h.shared.size(); ++k) {
+    srun[2 * k] = h.node_slot[h.shared[k]];
+    srun[2 * k + 1] = h.node_slot[h.shared[k] + 1];
+  }
   vcx_status st = VCX_OK;
   auto chk = [&](vcx_status s) {
     if (st == VCX_OK) st = s;
@@ -527,6 +538,13 @@ extern "C" vcx_status vcx_mesh_create_tiled(int ndim, int64_t nnodes, const doub
   chk(upload(m, h.slot_node, &d.slot_node));
   chk(upload(m, h.slot_inc, &d.slot_inc));
   chk(upload(m, h.inc, &d.inc));
+  {
+    chk(upload(m, tile_inc, &d.tile_inc));
+    chk(upload(m, slot_pos, &d.slot_pos));
+    const int32_t* sr = nullptr;
+    chk(upload(m, srun, &sr));
+    d.shared_run = reinterpret_cast<const int2*>(sr);
+  }
   chk(upload(m, h.node_slot, &d.node_slot));
   chk(upload(m, h.slots_of, &d.slots_of));
   chk(upload(m, h.shared, &d.shared));
@@ -1106,6 +1124,8 @@ vcx_status vcx::batch_set(BatchGroup* g, vcx_solver* ss, int n, const int* steps
   int block = 64;
   g->steps0.resize(n);
   g->phase0.resize(n);
+  // each solve's reducer entry first (dispatched early), then the tiles
+  for (int i = 0; i < n; ++i) tmap.push_back(make_int2(i, -1));
   for (int i = 0; i < n; ++i) {
     vcx_solver s = ss[i];
     tab[i] = entry_of(s);

@@ -45,10 +45,14 @@ struct DevMesh {
   const int32_t* slot_node;  // [P] node id, or ~node when the node has slots in other tiles
   const int32_t* slot_inc;   // [P+1]
   const uint16_t* inc;       // [nc*nv]
+  const int32_t* tile_inc;   // [T+1] first incidence of each tile
+  const int32_t* slot_pos;   // [P] position of the slot in its node's run of slots_of; the
+                             // index of the slot's partial sums (a node's partials are contiguous)
   const int32_t* node_slot;  // [nn+1]
   const int32_t* slots_of;   // [P]
   const int2* slot_run;      // [P] [begin, end) of the slot's node run in slots_of
   const int32_t* shared;     // [nshared] nodes with more than one slot (ascending)
+  const int2* shared_run;    // [nshared] [begin, end) of the shared node's run in slots_of
   const double* inv_vol;     // [nn]
   const double* vnode;       // [nn]
   const double* dxmin;       // [nn] smallest inscribed diameter of the cells around the node
@@ -86,11 +90,12 @@ struct DtParts {
 
 // Blocks are dispatched round-robin over the XCDs; give each XCD a contiguous
 // range of tiles so neighbouring tiles share node data in the same L2.
-__device__ inline int xcd_tile(int ntiles) {
+__device__ inline int xcd_tile_of(int b, int ntiles) {
   const int per = (ntiles + NXCD - 1) / NXCD;
-  const int b = blockIdx.x;
   return (b % NXCD) * per + b / NXCD;
 }
+
+__device__ inline int xcd_tile(int ntiles) { return xcd_tile_of(blockIdx.x, ntiles); }
 
 inline int xcd_grid(int ntiles) { return ((ntiles + NXCD - 1) / NXCD) * NXCD; }
 
@@ -124,6 +129,109 @@ __device__ inline void cell_rel_coords(const DevMesh& m, const double* sX, int m
 }
 
 __device__ inline int slot_node_id(int v) { return v >= 0 ? v : ~v; }
+
+// Tile topology read at the start of a tile pass, so that its loads are in
+// flight together with the staging of the node data: this thread's cell and
+// slot (the first iteration of the cell and slot loops) and up to NV of the
+// tile's incidence codes, which are stored to LDS after the staging.
+template <int NV>
+struct TilePre {
+  int c0, nc, s0, ns, pb, ninc;
+  int l[NV];
+  uint32_t shift;
+  int sv, pos, p0, p1;  // slot threadIdx.x: node, partial index, incidence range in the tile
+  int2 run;             // its node's run in slots_of
+  int inc[NV];
+};
+
+template <int NV>
+__device__ inline void tile_prefetch(const DevMesh& m, int t, TilePre<NV>& tp) {
+  tp.c0 = m.tile_cell[t];
+  tp.nc = m.tile_cell[t + 1] - tp.c0;
+  tp.s0 = m.tile_slot[t];
+  tp.ns = m.tile_slot[t + 1] - tp.s0;
+  tp.pb = m.tile_inc[t];
+  tp.ninc = m.tile_inc[t + 1] - tp.pb;
+  const int i = threadIdx.x;
+  if (i < tp.nc) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) tp.l[k] = m.lconn[(size_t)k * m.nc + tp.c0 + i];
+    tp.shift = m.shift[tp.c0 + i];
+  }
+  if (i < tp.ns) {
+    const int sl = tp.s0 + i;
+    tp.sv = m.slot_node[sl];
+    tp.pos = m.slot_pos[sl];
+    tp.p0 = m.slot_inc[sl] - tp.pb;
+    tp.p1 = m.slot_inc[sl + 1] - tp.pb;
+    tp.run = m.slot_run[sl];
+  }
+#pragma unroll
+  for (int j = 0; j < NV; ++j) {
+    const int p = i + j * (int)blockDim.x;
+    if (p < tp.ninc) tp.inc[j] = m.inc[tp.pb + p];
+  }
+}
+
+template <int NV>
+__device__ inline void tile_store_inc(const DevMesh& m, const TilePre<NV>& tp, uint16_t* sInc) {
+#pragma unroll
+  for (int j = 0; j < NV; ++j) {
+    const int p = (int)threadIdx.x + j * (int)blockDim.x;
+    if (p < tp.ninc) sInc[p] = (uint16_t)tp.inc[j];
+  }
+  for (int p = (int)threadIdx.x + NV * (int)blockDim.x; p < tp.ninc; p += blockDim.x)
+    sInc[p] = m.inc[tp.pb + p];
+}
+
+struct SlotTopo {
+  int sv, pos, p0, p1;
+  int2 run;
+};
+
+// Slot table of a tile in LDS ([4][maxn] ints: node, partial index,
+// incidence range), written while staging and read by the node pass, so
+// that no registers hold it through the cell pass.
+__device__ inline void slot_table_put(int* sSl, int maxn, int q, int sv, int pos, int p0, int p1) {
+  sSl[q] = sv;
+  sSl[maxn + q] = pos;
+  sSl[2 * maxn + q] = p0;
+  sSl[3 * maxn + q] = p1;
+}
+
+__device__ inline SlotTopo slot_table_get(const int* sSl, int maxn, int q) {
+  return SlotTopo{sSl[q], sSl[maxn + q], sSl[2 * maxn + q], sSl[3 * maxn + q], make_int2(0, 0)};
+}
+
+template <int NV>
+__device__ inline SlotTopo slot_topo(const DevMesh& m, const TilePre<NV>& tp, int q) {
+  if (q == (int)threadIdx.x) return SlotTopo{tp.sv, tp.pos, tp.p0, tp.p1, tp.run};
+  const int sl = tp.s0 + q;
+  return SlotTopo{m.slot_node[sl], m.slot_pos[sl], m.slot_inc[sl] - tp.pb, m.slot_inc[sl + 1] - tp.pb,
+                  m.slot_run[sl]};
+}
+
+template <int NV>
+__device__ inline void cell_topo(const DevMesh& m, const TilePre<NV>& tp, int lc, int (&l)[NV],
+                                 uint32_t& shift) {
+  if (lc == (int)threadIdx.x) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) l[k] = tp.l[k];
+    shift = tp.shift;
+    return;
+  }
+#pragma unroll
+  for (int k = 0; k < NV; ++k) l[k] = m.lconn[(size_t)k * m.nc + tp.c0 + lc];
+  shift = m.shift[tp.c0 + lc];
+}
+
+// bytes of the incidence codes staged in LDS, rounded to doubles
+__host__ __device__ inline size_t inc_lds_bytes(int nv, int maxc) {
+  return ((size_t)nv * maxc * sizeof(uint16_t) + 7) / 8 * 8;
+}
+
+// bytes of a tile's slot table in LDS
+__host__ __device__ inline size_t slot_lds_bytes(int maxn) { return (size_t)4 * maxn * sizeof(int); }
 
 // Reduce the dt candidates of the previous pass, commit the previous step and
 // start the next one (or stop at t_end / on failure).  Block-wide call.
@@ -174,9 +282,7 @@ struct DtCoef {
 };
 
 template <int ND, int NSP, int MODEL>
-__device__ inline double node_dt(const DevMesh& m, const DtCoef& c, const double* E, int i,
-                                 const double* u, double p) {
-  const double dx = m.dxmin[i];
+__device__ inline double node_dt(const DtCoef& c, double dx, const double* Ei, const double* u, double p) {
   if constexpr (MODEL == 0) {
     const double rho = u[0];
     double uu = 0.0;
@@ -195,7 +301,7 @@ __device__ inline double node_dt(const DevMesh& m, const DtCoef& c, const double
       double v2 = 0.0;
 #pragma unroll
       for (int d = 0; d < ND; ++d) {
-        const double vd = c.zmu[s] * E[(size_t)d * m.nn + i];
+        const double vd = c.zmu[s] * Ei[d];
         v2 += vd * vd;
       }
       const double vmax = sqrt(v2);
@@ -234,7 +340,7 @@ __device__ inline double ns_node_dt(double dx, const DtCoef& c, const MixParams&
 struct GradCtl {
   DevScalars* sc;  // null outside the time loop
   DtParts parts;
-  int first_stage; // block 0 reduces the dt candidates and commits
+  int first_stage; // first stage of a step: an extra block reduces the dt candidates and commits
 };
 
 template <int ND, int NR>
@@ -242,31 +348,45 @@ __device__ inline void grad_tile_body(const DevMesh& m, const double* __restrict
                                       double* __restrict__ G, double* __restrict__ PG,
                                       const GradCtl& ctl, int t, double* lds) {
   constexpr int NV = ND + 1, NC = NR * ND;
-  // the block of the solve's first tile reduces the time step and commits
-  if (ctl.sc && ctl.first_stage && t == 0) dt_reduce_commit(ctl.sc, ctl.parts);
   // later stages of a step that does no work (set by an earlier launch)
   if (ctl.sc && !ctl.first_stage && ctl.sc->active == 0) return;
+  TilePre<NV> tp;
+  tile_prefetch<NV>(m, t, tp);
   const int maxn = m.max_tile_nodes, maxc = m.max_tile_cells;
   double* sW = lds;                 // [NR][maxn]
   double* sX = sW + NR * maxn;      // [ND][maxn]
   double* sC = sX + ND * maxn;      // [NC][maxc]
-  const int c0 = m.tile_cell[t], nc = m.tile_cell[t + 1] - c0;
-  const int s0 = m.tile_slot[t], ns = m.tile_slot[t + 1] - s0;
+  uint16_t* sInc = reinterpret_cast<uint16_t*>(sC + NC * maxc);
+  const int nc = tp.nc, ns = tp.ns;
+  double iv = 0.0;  // 1/V of this thread's slot node (tile-owned nodes)
   for (int q = threadIdx.x; q < ns; q += blockDim.x) {
-    const int g = slot_node_id(m.slot_node[s0 + q]);
+    const int sv = q == (int)threadIdx.x ? tp.sv : m.slot_node[tp.s0 + q];
+    const int g = slot_node_id(sv);
+    if (q == (int)threadIdx.x && sv >= 0) iv = m.inv_vol[sv];
+    constexpr int WC = NR <= 16 ? NR : 16;
+    double xx[ND];
 #pragma unroll
-    for (int v = 0; v < NR; ++v) sW[v * maxn + q] = W[(size_t)v * m.nn + g];
+    for (int d = 0; d < ND; ++d) xx[d] = m.x[(size_t)d * m.nn + g];
+    for (int v0 = 0; v0 < NR; v0 += WC) {
+      double w[WC];
 #pragma unroll
-    for (int d = 0; d < ND; ++d) sX[d * maxn + q] = m.x[(size_t)d * m.nn + g];
+      for (int vv = 0; vv < WC; ++vv)
+        if (v0 + vv < NR) w[vv] = W[(size_t)(v0 + vv) * m.nn + g];
+#pragma unroll
+      for (int vv = 0; vv < WC; ++vv)
+        if (v0 + vv < NR) sW[(v0 + vv) * maxn + q] = w[vv];
+    }
+#pragma unroll
+    for (int d = 0; d < ND; ++d) sX[d * maxn + q] = xx[d];
   }
+  tile_store_inc<NV>(m, tp, sInc);
   __syncthreads();
   for (int lc = threadIdx.x; lc < nc; lc += blockDim.x) {
-    const int c = c0 + lc;
     int l[NV];
-#pragma unroll
-    for (int k = 0; k < NV; ++k) l[k] = m.lconn[(size_t)k * m.nc + c];
+    uint32_t sh;
+    cell_topo<NV>(m, tp, lc, l, sh);
     double e[ND][ND], S[NV][ND];
-    cell_rel_coords<ND>(m, sX, maxn, l, m.shift[c], e);
+    cell_rel_coords<ND>(m, sX, maxn, l, sh, e);
     simplex_normals<ND>(e, S);
 #pragma unroll
     for (int v = 0; v < NR; ++v) {
@@ -287,15 +407,16 @@ __device__ inline void grad_tile_body(const DevMesh& m, const double* __restrict
   // components in chunks of JC to bound register use for many fields
   constexpr int JC = NC <= 24 ? NC : 12;
   for (int q = threadIdx.x; q < ns; q += blockDim.x) {
-    const int p0 = m.slot_inc[s0 + q], p1 = m.slot_inc[s0 + q + 1];
-    const int sv = m.slot_node[s0 + q];
-    const double coef = sv >= 0 ? -m.inv_vol[sv] / double(ND * NV) : 0.0;
+    const SlotTopo st = slot_topo<NV>(m, tp, q);
+    const int sv = st.sv;
+    double coef = 0.0;
+    if (sv >= 0) coef = -(q == (int)threadIdx.x ? iv : m.inv_vol[sv]) / double(ND * NV);
     for (int j0 = 0; j0 < NC; j0 += JC) {
       double acc[JC];
 #pragma unroll
       for (int jj = 0; jj < JC; ++jj) acc[jj] = 0.0;
-      for (int p = p0; p < p1; ++p) {
-        const int lc = m.inc[p] >> 2;
+      for (int p = st.p0; p < st.p1; ++p) {
+        const int lc = sInc[p] >> 2;
 #pragma unroll
         for (int jj = 0; jj < JC; ++jj)
           if (j0 + jj < NC) acc[jj] += sC[(j0 + jj) * maxc + lc];
@@ -307,7 +428,7 @@ __device__ inline void grad_tile_body(const DevMesh& m, const double* __restrict
       } else {
 #pragma unroll
         for (int jj = 0; jj < JC; ++jj)
-          if (j0 + jj < NC) PG[(size_t)(s0 + q) * NC + j0 + jj] = acc[jj];
+          if (j0 + jj < NC) PG[(size_t)st.pos * NC + j0 + jj] = acc[jj];
       }
     }
   }
@@ -318,7 +439,14 @@ __global__ void __launch_bounds__(256) k_grad_tile(DevMesh m, const double* __re
                                                    double* __restrict__ G, double* __restrict__ PG,
                                                    GradCtl ctl) {
   extern __shared__ double lds[];
-  const int t = xcd_tile(m.ntiles);
+  // in the first stage of a step, block 0 reduces the time-step candidates
+  // and commits (the tiles take the other blocks, so that no tile waits on it)
+  const int lead = ctl.sc && ctl.first_stage ? 1 : 0;
+  if (lead && blockIdx.x == 0) {
+    dt_reduce_commit(ctl.sc, ctl.parts);
+    return;
+  }
+  const int t = xcd_tile_of((int)blockIdx.x - lead, m.ntiles);
   if (t >= m.ntiles) return;
   grad_tile_body<ND, NR>(m, W, G, PG, ctl, t, lds);
 }
@@ -332,7 +460,7 @@ __device__ inline void shared_gradient(const DevMesh& m, const double* __restric
 #pragma unroll
   for (int j = 0; j < NC; ++j) out[j] = 0.0;
   for (int p = run.x; p < run.y; ++p) {
-    const double* src = PG + (size_t)m.slots_of[p] * NC;
+    const double* src = PG + (size_t)p * NC;
 #pragma unroll
     for (int j = 0; j < NC; ++j) out[j] += src[j];
   }
@@ -341,14 +469,24 @@ __device__ inline void shared_gradient(const DevMesh& m, const double* __restric
 }
 
 // Stage the NC gradient components of the tile's q-th node into LDS: read G
-// for a tile-owned node, gather the slot partials of a shared node.
+// for a tile-owned node, gather the slot partials of a shared node (in
+// ascending partial order, the same for every reader).  Loads of a chunk of
+// components are all issued before the first store.
 template <int NC, int ND, typename CT>
 __device__ inline void stage_gradient(const DevMesh& m, const double* __restrict__ G,
                                       const double* __restrict__ PG, int sv, int2 run, CT* sG,
                                       int maxn, int q) {
   if (sv >= 0) {
-#pragma unroll 4
-    for (int j = 0; j < NC; ++j) sG[j * maxn + q] = CT(G[(size_t)j * m.nn + sv]);
+    constexpr int JC = NC <= 32 ? NC : 16;
+    for (int j0 = 0; j0 < NC; j0 += JC) {
+      double v[JC];
+#pragma unroll
+      for (int jj = 0; jj < JC; ++jj)
+        if (j0 + jj < NC) v[jj] = G[(size_t)(j0 + jj) * m.nn + sv];
+#pragma unroll
+      for (int jj = 0; jj < JC; ++jj)
+        if (j0 + jj < NC) sG[(j0 + jj) * maxn + q] = CT(v[jj]);
+    }
     return;
   }
   const int g = ~sv;
@@ -358,11 +496,26 @@ __device__ inline void stage_gradient(const DevMesh& m, const double* __restrict
     double acc[JC];
 #pragma unroll
     for (int jj = 0; jj < JC; ++jj) acc[jj] = 0.0;
-    for (int p = run.x; p < run.y; ++p) {
-      const double* src = PG + (size_t)m.slots_of[p] * NC + j0;
+    int p = run.x;
+    for (; p + 1 < run.y; p += 2) {
+      const double* s0 = PG + (size_t)p * NC + j0;
+      const double* s1 = s0 + NC;
+      double a[JC], b[JC];
 #pragma unroll
       for (int jj = 0; jj < JC; ++jj)
-        if (j0 + jj < NC) acc[jj] += src[jj];
+        if (j0 + jj < NC) {
+          a[jj] = s0[jj];
+          b[jj] = s1[jj];
+        }
+#pragma unroll
+      for (int jj = 0; jj < JC; ++jj)
+        if (j0 + jj < NC) acc[jj] = (acc[jj] + a[jj]) + b[jj];
+    }
+    if (p < run.y) {
+      const double* s0 = PG + (size_t)p * NC + j0;
+#pragma unroll
+      for (int jj = 0; jj < JC; ++jj)
+        if (j0 + jj < NC) acc[jj] += s0[jj];
     }
 #pragma unroll
     for (int jj = 0; jj < JC; ++jj)
@@ -380,7 +533,7 @@ __global__ void __launch_bounds__(256) k_grad_shared(DevMesh m, const double* __
   if (k >= m.nshared) return;
   const int g = m.shared[k];
   double out[NC];
-  shared_gradient<NC, ND>(m, PG, g, make_int2(m.node_slot[g], m.node_slot[g + 1]), out);
+  shared_gradient<NC, ND>(m, PG, g, m.shared_run[k], out);
 #pragma unroll
   for (int j = 0; j < NC; ++j) G[(size_t)j * m.nn + g] = out[j];
 }
@@ -405,9 +558,32 @@ struct Finish {
   int closure, final_stage, residual_only;
 };
 
+// Node inputs of the stage update, loaded ahead of the residual sums where
+// registers allow: U^n, alpha dt / V_i, the node's dx_min and its field.
+template <int NVAR, int ND>
+struct NodeIn {
+  double Un[NVAR];
+  double fac;
+  double dx;
+  double E[ND];
+};
+
+template <int ND, int MODEL, int NVAR>
+__device__ inline void node_in_load(const DevMesh& m, const Finish& f, int i, NodeIn<NVAR, ND>& ni) {
+  if (f.residual_only) return;
+#pragma unroll
+  for (int v = 0; v < NVAR; ++v) ni.Un[v] = f.Un[(size_t)v * m.nn + i];
+  ni.fac = f.alpha * f.sc->dt * m.inv_vol[i];
+  ni.dx = m.dxmin[i];
+  if constexpr (MODEL == 1) {
+#pragma unroll
+    for (int d = 0; d < ND; ++d) ni.E[d] = f.E[(size_t)d * m.nn + i];
+  }
+}
+
 template <int ND, int NSP, int MODEL, int NVAR>
 __device__ inline double finish_node(const DevMesh& m, const Finish& f, int i, bool shared,
-                                     double (&r)[NVAR]) {
+                                     double (&r)[NVAR], const NodeIn<NVAR, ND>& ni) {
   if (f.closure && m.nb > 0) {
     const int bi = m.bnd_index[i];
     if (bi >= 0) {
@@ -457,11 +633,10 @@ __device__ inline double finish_node(const DevMesh& m, const Finish& f, int i, b
     for (int v = 0; v < NVAR; ++v) f.rout[(size_t)v * m.nn + i] = r[v];
     return INFINITY;
   }
-  const double fac = f.alpha * f.sc->dt * m.inv_vol[i];
   double u[NVAR];
 #pragma unroll
   for (int v = 0; v < NVAR; ++v) {
-    u[v] = f.Un[(size_t)v * m.nn + i] - fac * r[v];
+    u[v] = ni.Un[v] - ni.fac * r[v];
     f.Wout[(size_t)v * m.nn + i] = u[v];
   }
   bool ok = true;
@@ -488,13 +663,13 @@ __device__ inline double finish_node(const DevMesh& m, const Finish& f, int i, b
     for (int v = 0; v < NVAR; ++v) ok = ok && isfinite(u[v]);
     if (!f.final_stage) return INFINITY;
     if (!ok) atomicOr(&f.sc->flag, 1);
-    return ns_node_dt<ND, NSP>(m.dxmin[i], f.dc, f.mix, u[0], prim, p, aux, ok);
+    return ns_node_dt<ND, NSP>(ni.dx, f.dc, f.mix, u[0], prim, p, aux, ok);
   }
 #pragma unroll
   for (int v = 0; v < NVAR; ++v) ok = ok && isfinite(u[v]);
   if (!f.final_stage) return INFINITY;
   if (!ok) atomicOr(&f.sc->flag, 1);
-  return node_dt<ND, NSP, MODEL>(m, f.dc, f.E, i, u, p);
+  return node_dt<ND, NSP, MODEL>(f.dc, ni.dx, ni.E, u, p);
 }
 
 // ---------------------------------------------------------------------------
@@ -513,31 +688,41 @@ __device__ inline void flux_gas_body(DevMesh m, const double* __restrict__ W,
                                                   DtParts parts, int t, double* lds) {
   constexpr int NV = ND + 1, NVAR = 2 + ND + NSP, NR = NVAR + 1, NE = Edges<ND>::NE;
   if (step_inactive(f.sc)) return;
+  TilePre<NV> tp;
+  tile_prefetch<NV>(m, t, tp);
   const int maxn = m.max_tile_nodes, maxc = m.max_tile_cells;
   double* sX = lds;                       // [ND][maxn]
   double* sR = sX + ND * maxn;            // [NV*NVAR][maxc]
   CT* sW = reinterpret_cast<CT*>(sR + NV * NVAR * maxc);  // [NR][maxn]
   CT* sG = sW + NR * maxn;                // [NR*ND][maxn]
-  const int c0 = m.tile_cell[t], nc = m.tile_cell[t + 1] - c0;
-  const int s0 = m.tile_slot[t], ns = m.tile_slot[t + 1] - s0;
+  int* sSl = reinterpret_cast<int*>(sG + NR * ND * maxn);
+  uint16_t* sInc = reinterpret_cast<uint16_t*>(sSl + 4 * maxn);
+  const int nc = tp.nc, ns = tp.ns;
   for (int q = threadIdx.x; q < ns; q += blockDim.x) {
-    const int sv = m.slot_node[s0 + q];
+    const SlotTopo st = slot_topo<NV>(m, tp, q);
+    slot_table_put(sSl, maxn, q, st.sv, st.pos, st.p0, st.p1);
+    const int sv = st.sv;
     const int g = slot_node_id(sv);
+    double w[NR], xx[ND];
 #pragma unroll
-    for (int v = 0; v < NR; ++v) sW[v * maxn + q] = CT(W[(size_t)v * m.nn + g]);
-    stage_gradient<NR * ND, ND, CT>(m, G, f.PG, sv, m.slot_run[s0 + q], sG, maxn, q);
+    for (int v = 0; v < NR; ++v) w[v] = W[(size_t)v * m.nn + g];
 #pragma unroll
-    for (int d = 0; d < ND; ++d) sX[d * maxn + q] = m.x[(size_t)d * m.nn + g];
+    for (int d = 0; d < ND; ++d) xx[d] = m.x[(size_t)d * m.nn + g];
+    stage_gradient<NR * ND, ND, CT>(m, G, f.PG, sv, st.run, sG, maxn, q);
+#pragma unroll
+    for (int v = 0; v < NR; ++v) sW[v * maxn + q] = CT(w[v]);
+#pragma unroll
+    for (int d = 0; d < ND; ++d) sX[d * maxn + q] = xx[d];
   }
+  tile_store_inc<NV>(m, tp, sInc);
   __syncthreads();
   const CT gamma = CT(gp.gamma), beta = CT(gp.beta), fix = CT(gp.entropy_fix);
   for (int lc = threadIdx.x; lc < nc; lc += blockDim.x) {
-    const int c = c0 + lc;
     int l[NV];
-#pragma unroll
-    for (int k = 0; k < NV; ++k) l[k] = m.lconn[(size_t)k * m.nc + c];
+    uint32_t sh;
+    cell_topo<NV>(m, tp, lc, l, sh);
     double e[ND][ND], Sd[NV][ND];
-    cell_rel_coords<ND>(m, sX, maxn, l, m.shift[c], e);
+    cell_rel_coords<ND>(m, sX, maxn, l, sh, e);
     simplex_normals<ND>(e, Sd);
     double acc[NV][NVAR];
 #pragma unroll
@@ -589,22 +774,23 @@ __device__ inline void flux_gas_body(DevMesh m, const double* __restrict__ W,
   __syncthreads();
   double cand = INFINITY;
   for (int q = threadIdx.x; q < ns; q += blockDim.x) {
+    const SlotTopo st = slot_table_get(sSl, maxn, q);
+    NodeIn<NVAR, ND> nq;
+    if (st.sv >= 0) node_in_load<ND, 0, NVAR>(m, f, st.sv, nq);
     double r[NVAR];
 #pragma unroll
     for (int v = 0; v < NVAR; ++v) r[v] = 0.0;
-    const int p0 = m.slot_inc[s0 + q], p1 = m.slot_inc[s0 + q + 1];
-    for (int p = p0; p < p1; ++p) {
-      const int code = m.inc[p];
+    for (int p = st.p0; p < st.p1; ++p) {
+      const int code = sInc[p];
       const int lc = code >> 2, k = code & 3;
 #pragma unroll
       for (int v = 0; v < NVAR; ++v) r[v] += sR[(k * NVAR + v) * maxc + lc];
     }
-    const int sv = m.slot_node[s0 + q];
-    if (sv >= 0) {
-      cand = fmin(cand, finish_node<ND, NSP, 0, NVAR>(m, f, sv, false, r));
+    if (st.sv >= 0) {
+      cand = fmin(cand, finish_node<ND, NSP, 0, NVAR>(m, f, st.sv, false, r, nq));
     } else {
 #pragma unroll
-      for (int v = 0; v < NVAR; ++v) PR[(size_t)(s0 + q) * NVAR + v] = r[v];
+      for (int v = 0; v < NVAR; ++v) PR[(size_t)st.pos * NVAR + v] = r[v];
     }
   }
   if (f.final_stage && f.sc) {
@@ -643,37 +829,50 @@ __device__ inline void flux_dd_body(DevMesh m, const double* __restrict__ U,
                                                  DtParts parts, int t, double* lds) {
   constexpr int NV = ND + 1, NE = Edges<ND>::NE;
   if (step_inactive(f.sc)) return;
+  TilePre<NV> tp;
+  tile_prefetch<NV>(m, t, tp);
   const int maxn = m.max_tile_nodes, maxc = m.max_tile_cells;
   double* sX = lds;                      // [ND][maxn]
   double* sR = sX + ND * maxn;           // [NV*NS][maxc]
   CT* sU = reinterpret_cast<CT*>(sR + NV * NS * maxc);  // [NS][maxn]
   CT* sG = sU + NS * maxn;               // [NS*ND][maxn]
   CT* sE = sG + NS * ND * maxn;          // [ND][maxn]
+  int* sSl = reinterpret_cast<int*>(sE + ND * maxn);
+  uint16_t* sInc = reinterpret_cast<uint16_t*>(sSl + 4 * maxn);
   const double* E = f.E;
-  const int c0 = m.tile_cell[t], nc = m.tile_cell[t + 1] - c0;
-  const int s0 = m.tile_slot[t], ns = m.tile_slot[t + 1] - s0;
+  const int nc = tp.nc, ns = tp.ns;
   for (int q = threadIdx.x; q < ns; q += blockDim.x) {
-    const int sv = m.slot_node[s0 + q];
+    const SlotTopo st = slot_topo<NV>(m, tp, q);
+    slot_table_put(sSl, maxn, q, st.sv, st.pos, st.p0, st.p1);
+    const int sv = st.sv;
     const int g = slot_node_id(sv);
+    double u[NS], xe[2 * ND];
 #pragma unroll
-    for (int s = 0; s < NS; ++s) sU[s * maxn + q] = CT(U[(size_t)s * m.nn + g]);
-    stage_gradient<NS * ND, ND, CT>(m, G, f.PG, sv, m.slot_run[s0 + q], sG, maxn, q);
+    for (int s = 0; s < NS; ++s) u[s] = U[(size_t)s * m.nn + g];
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
-      sX[d * maxn + q] = m.x[(size_t)d * m.nn + g];
-      sE[d * maxn + q] = CT(E[(size_t)d * m.nn + g]);
+      xe[d] = m.x[(size_t)d * m.nn + g];
+      xe[ND + d] = E[(size_t)d * m.nn + g];
+    }
+    stage_gradient<NS * ND, ND, CT>(m, G, f.PG, sv, st.run, sG, maxn, q);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) sU[s * maxn + q] = CT(u[s]);
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      sX[d * maxn + q] = xe[d];
+      sE[d * maxn + q] = CT(xe[ND + d]);
     }
   }
+  tile_store_inc<NV>(m, tp, sInc);
   __syncthreads();
   const CT dt = CT(f.sc ? f.sc->dt : pp.dt_host);
   const CT beta = CT(pp.beta);
   for (int lc = threadIdx.x; lc < nc; lc += blockDim.x) {
-    const int c = c0 + lc;
     int l[NV];
-#pragma unroll
-    for (int k = 0; k < NV; ++k) l[k] = m.lconn[(size_t)k * m.nc + c];
+    uint32_t sh;
+    cell_topo<NV>(m, tp, lc, l, sh);
     double e[ND][ND], Sd[NV][ND];
-    cell_rel_coords<ND>(m, sX, maxn, l, m.shift[c], e);
+    cell_rel_coords<ND>(m, sX, maxn, l, sh, e);
     simplex_normals<ND>(e, Sd);
     double acc[NV][NS];
 #pragma unroll
@@ -728,22 +927,24 @@ __device__ inline void flux_dd_body(DevMesh m, const double* __restrict__ U,
   __syncthreads();
   double cand = INFINITY;
   for (int q = threadIdx.x; q < ns; q += blockDim.x) {
+    const SlotTopo st = slot_table_get(sSl, maxn, q);
+    // update inputs first: their loads overlap the sums
+    NodeIn<NS, ND> nq;
+    if (st.sv >= 0) node_in_load<ND, 1, NS>(m, f, st.sv, nq);
     double r[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) r[s] = 0.0;
-    const int p0 = m.slot_inc[s0 + q], p1 = m.slot_inc[s0 + q + 1];
-    for (int p = p0; p < p1; ++p) {
-      const int code = m.inc[p];
+    for (int p = st.p0; p < st.p1; ++p) {
+      const int code = sInc[p];
       const int lc = code >> 2, k = code & 3;
 #pragma unroll
       for (int s = 0; s < NS; ++s) r[s] += sR[(k * NS + s) * maxc + lc];
     }
-    const int sv = m.slot_node[s0 + q];
-    if (sv >= 0) {
-      cand = fmin(cand, finish_node<ND, NS, 1, NS>(m, f, sv, false, r));
+    if (st.sv >= 0) {
+      cand = fmin(cand, finish_node<ND, NS, 1, NS>(m, f, st.sv, false, r, nq));
     } else {
 #pragma unroll
-      for (int s = 0; s < NS; ++s) PR[(size_t)(s0 + q) * NS + s] = r[s];
+      for (int s = 0; s < NS; ++s) PR[(size_t)st.pos * NS + s] = r[s];
     }
   }
   if (f.final_stage && f.sc) {
@@ -778,31 +979,47 @@ __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ W,
   constexpr int NV = ND + 1, NVAR = 2 + ND + NSP, NR = NVAR + 1, NE = Edges<ND>::NE;
   constexpr int NP = ND + 1 + NSP, NA = 3 + 2 * NSP, NG = NR + NP;
   if (step_inactive(f.sc)) return;
+  TilePre<NV> tp;
+  tile_prefetch<NV>(m, t, tp);
   const int maxn = m.max_tile_nodes, maxc = m.max_tile_cells;
   double* sX = lds;                                        // [ND][maxn]
   double* sR = sX + ND * maxn;                             // [NV*NVAR][maxc]
   CT* sW = reinterpret_cast<CT*>(sR + NV * NVAR * maxc);   // [NR + NP + NA][maxn]
   CT* sG = sW + (NR + NP + NA) * maxn;                     // [NG*ND][maxn]
-  const int c0 = m.tile_cell[t], nc = m.tile_cell[t + 1] - c0;
-  const int s0 = m.tile_slot[t], ns = m.tile_slot[t + 1] - s0;
+  int* sSl = reinterpret_cast<int*>(sG + NG * ND * maxn);
+  uint16_t* sInc = reinterpret_cast<uint16_t*>(sSl + 4 * maxn);
+  const int nc = tp.nc, ns = tp.ns;
   for (int q = threadIdx.x; q < ns; q += blockDim.x) {
-    const int sv = m.slot_node[s0 + q];
+    const SlotTopo st = slot_topo<NV>(m, tp, q);
+    slot_table_put(sSl, maxn, q, st.sv, st.pos, st.p0, st.p1);
+    const int sv = st.sv;
     const int g = slot_node_id(sv);
-#pragma unroll 4
-    for (int v = 0; v < NR + NP + NA; ++v) sW[v * maxn + q] = CT(W[(size_t)v * m.nn + g]);
-    stage_gradient<NG * ND, ND, CT>(m, G, f.PG, sv, m.slot_run[s0 + q], sG, maxn, q);
+    double xx[ND];
 #pragma unroll
-    for (int d = 0; d < ND; ++d) sX[d * maxn + q] = m.x[(size_t)d * m.nn + g];
+    for (int d = 0; d < ND; ++d) xx[d] = m.x[(size_t)d * m.nn + g];
+    constexpr int NWR = NR + NP + NA, WC = 16;
+    for (int v0 = 0; v0 < NWR; v0 += WC) {
+      double w[WC];
+#pragma unroll
+      for (int vv = 0; vv < WC; ++vv)
+        if (v0 + vv < NWR) w[vv] = W[(size_t)(v0 + vv) * m.nn + g];
+#pragma unroll
+      for (int vv = 0; vv < WC; ++vv)
+        if (v0 + vv < NWR) sW[(v0 + vv) * maxn + q] = CT(w[vv]);
+    }
+    stage_gradient<NG * ND, ND, CT>(m, G, f.PG, sv, st.run, sG, maxn, q);
+#pragma unroll
+    for (int d = 0; d < ND; ++d) sX[d * maxn + q] = xx[d];
   }
+  tile_store_inc<NV>(m, tp, sInc);
   __syncthreads();
   const CT beta = CT(gp.beta);
   for (int lc = threadIdx.x; lc < nc; lc += blockDim.x) {
-    const int c = c0 + lc;
     int l[NV];
-#pragma unroll
-    for (int k = 0; k < NV; ++k) l[k] = m.lconn[(size_t)k * m.nc + c];
+    uint32_t sh;
+    cell_topo<NV>(m, tp, lc, l, sh);
     double e[ND][ND], Sd[NV][ND];
-    cell_rel_coords<ND>(m, sX, maxn, l, m.shift[c], e);
+    cell_rel_coords<ND>(m, sX, maxn, l, sh, e);
     simplex_normals<ND>(e, Sd);
     double acc[NV][NVAR];
 #pragma unroll
@@ -869,22 +1086,23 @@ __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ W,
   __syncthreads();
   double cand = INFINITY;
   for (int q = threadIdx.x; q < ns; q += blockDim.x) {
+    const SlotTopo st = slot_table_get(sSl, maxn, q);
     double r[NVAR];
 #pragma unroll
     for (int v = 0; v < NVAR; ++v) r[v] = 0.0;
-    const int p0 = m.slot_inc[s0 + q], p1 = m.slot_inc[s0 + q + 1];
-    for (int p = p0; p < p1; ++p) {
-      const int code = m.inc[p];
+    for (int p = st.p0; p < st.p1; ++p) {
+      const int code = sInc[p];
       const int lc = code >> 2, k = code & 3;
 #pragma unroll
       for (int v = 0; v < NVAR; ++v) r[v] += sR[(k * NVAR + v) * maxc + lc];
     }
-    const int sv = m.slot_node[s0 + q];
-    if (sv >= 0) {
-      cand = fmin(cand, finish_node<ND, NSP, 2, NVAR>(m, f, sv, false, r));
+    if (st.sv >= 0) {
+      NodeIn<NVAR, ND> nq;
+      node_in_load<ND, 2, NVAR>(m, f, st.sv, nq);
+      cand = fmin(cand, finish_node<ND, NSP, 2, NVAR>(m, f, st.sv, false, r, nq));
     } else {
 #pragma unroll
-      for (int v = 0; v < NVAR; ++v) PR[(size_t)(s0 + q) * NVAR + v] = r[v];
+      for (int v = 0; v < NVAR; ++v) PR[(size_t)st.pos * NVAR + v] = r[v];
     }
   }
   if (f.final_stage && f.sc) {
@@ -936,16 +1154,18 @@ __device__ inline void update_shared_body(const DevMesh& m, const double* __rest
   double cand = INFINITY;
   if (k < m.nshared) {
     const int i = m.shared[k];
+    const int2 run = m.shared_run[k];
+    NodeIn<NVAR, ND> ni;
+    node_in_load<ND, MODEL, NVAR>(m, f, i, ni);
     double r[NVAR];
 #pragma unroll
     for (int v = 0; v < NVAR; ++v) r[v] = 0.0;
-    const int a = m.node_slot[i], b = m.node_slot[i + 1];
-    for (int p = a; p < b; ++p) {
-      const double* src = PR + (size_t)m.slots_of[p] * NVAR;
+    for (int p = run.x; p < run.y; ++p) {
+      const double* src = PR + (size_t)p * NVAR;
 #pragma unroll
       for (int v = 0; v < NVAR; ++v) r[v] += src[v];
     }
-    cand = finish_node<ND, NSP, MODEL, NVAR>(m, f, i, true, r);
+    cand = finish_node<ND, NSP, MODEL, NVAR>(m, f, i, true, r, ni);
   }
   if (f.final_stage && f.sc) {
     const double bm = block_min(cand);
@@ -983,7 +1203,12 @@ __global__ void __launch_bounds__(256) k_node_dt(DevMesh m, const double* __rest
       const bool ok = u[0] > 0.0 && prim[ND] > 0.0 && isfinite(prim[ND]);
       cand = ns_node_dt<ND, NSP>(m.dxmin[i], dc, mp, u[0], prim, p, aux, ok);
     } else {
-      cand = node_dt<ND, NSP, MODEL>(m, dc, E, i, u, p);
+      double Ei[ND] = {};
+      if constexpr (MODEL == 1) {
+#pragma unroll
+        for (int d = 0; d < ND; ++d) Ei[d] = E[(size_t)d * m.nn + i];
+      }
+      cand = node_dt<ND, NSP, MODEL>(dc, m.dxmin[i], Ei, u, p);
     }
   }
   const double b = block_min(cand);
@@ -1111,6 +1336,11 @@ __global__ void __launch_bounds__(256) k_grad_tile_batch(const BatchEntry* __res
   if (g >= nblocks) return;
   const int2 ml = map[g];
   const BatchEntry& e = tab[ml.x];
+  if (ml.y < 0) {
+    // the solve's reducer entry: time step of the step that starts now
+    if (st.stage == 1) dt_reduce_commit(e.sc, e.parts);
+    return;
+  }
   const int cur = (st.step + e.phase) & 1;
   const double* Win = st.stage == 1 ? e.W[cur] : e.W[cur ^ 1];
   GradCtl ctl{e.sc, e.parts, st.stage == 1 ? 1 : 0};
@@ -1125,6 +1355,7 @@ __global__ void VCX_FLUX_BOUNDS k_flux_gas_batch(const BatchEntry* __restrict__ 
   const int g = xcd_tile(nblocks);
   if (g >= nblocks) return;
   const int2 ml = map[g];
+  if (ml.y < 0) return;  // a solve's reducer entry of the gradient pass
   const BatchEntry& e = tab[ml.x];
   const double* Win;
   const Finish f = batch_finish(e, st, fs, &Win);
@@ -1139,6 +1370,7 @@ __global__ void VCX_FLUX_BOUNDS k_flux_dd_batch(const BatchEntry* __restrict__ t
   const int g = xcd_tile(nblocks);
   if (g >= nblocks) return;
   const int2 ml = map[g];
+  if (ml.y < 0) return;  // a solve's reducer entry of the gradient pass
   const BatchEntry& e = tab[ml.x];
   const double* Win;
   const Finish f = batch_finish(e, st, fs, &Win);
@@ -1153,6 +1385,7 @@ __global__ void VCX_FLUX_BOUNDS k_flux_ns_batch(const BatchEntry* __restrict__ t
   const int g = xcd_tile(nblocks);
   if (g >= nblocks) return;
   const int2 ml = map[g];
+  if (ml.y < 0) return;  // a solve's reducer entry of the gradient pass
   const BatchEntry& e = tab[ml.x];
   const double* Win;
   const Finish f = batch_finish(e, st, fs, &Win);
