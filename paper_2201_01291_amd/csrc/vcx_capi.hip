@@ -67,10 +67,11 @@ struct vcx_solver_s {
   double* E = nullptr;
   double* io = nullptr;    // [max(nr*nd, nvar)][nn] staging in caller order
   double* rbuf = nullptr;  // [max(nr*nd, nvar)][nn] internal order
-  DevScalars* sc = nullptr;
-  DevScalars* sc_host = nullptr;  // pinned mirror
+  DevLoop* lp = nullptr;          // time loop (two step states by parity)
+  DevScalars* sc_host = nullptr;  // pinned mirror of the current state
+  int spar = 0;                   // parity of the next step
   double* dtp_node = nullptr;     // dt candidates of the node pass
-  double* dtp_step = nullptr;     // dt candidates of the step kernels
+  double* dtp_step = nullptr;     // dt candidates of the step kernels, [2][n_dtp_step] by parity
   int n_dtp_node = 0, n_dtp_step = 0, nsh_blocks = 1;
   double* part = nullptr;
   double* sums_dev = nullptr;
@@ -228,7 +229,7 @@ struct Impl {
   static vcx_status grad(vcx_solver s, const double* Win, const GradCtl& gc) {
     const DevMesh& m = s->mesh->d;
     return launch(s, "gradient", [&](hipEvent_t ea, hipEvent_t eb) {
-      const int lead = gc.sc && gc.first_stage ? 1 : 0;
+      const int lead = gc.lp && gc.first_stage ? 1 : 0;
       hipExtLaunchKernelGGL((k_grad_tile<ND, NGF>), dim3(xcd_grid(m.ntiles) + lead), dim3(s->tile_block),
                          s->lds_grad, s->mesh->stream, ea, eb, 0, m, Win, s->G, s->PG, gc);
     });
@@ -256,19 +257,18 @@ struct Impl {
   static vcx_status flux(vcx_solver s, const double* Win, const Finish& f, double dt_host) {
     const DevMesh& m = s->mesh->d;
     hipStream_t st = s->mesh->stream;
-    DtParts parts = dt_parts(s);
     if constexpr (MODEL == 0) {
       GasParams gp{s->ph.gamma, s->ph.beta, s->ph.entropy_fix, s->ph.limiter};
       return launch(s, "flux", [&](hipEvent_t ea, hipEvent_t eb) {
         hipExtLaunchKernelGGL((k_flux_gas<ND, NSP, FLUX, CT>), dim3(xcd_grid(m.ntiles)),
                            dim3(s->tile_block), s->lds_flux, st, ea, eb, 0, m, Win, (const double*)s->G,
-                           s->PR, gp, f, parts);
+                           s->PR, gp, f);
       });
     } else if constexpr (MODEL == 2) {
       GasParams gp{s->ph.gamma, s->ph.beta, s->ph.entropy_fix, s->ph.limiter};
       return launch(s, "flux", [&](hipEvent_t ea, hipEvent_t eb) {
         hipExtLaunchKernelGGL((k_flux_ns<ND, NSP, CT>), dim3(xcd_grid(m.ntiles)), dim3(s->tile_block),
-                           s->lds_flux, st, ea, eb, 0, m, Win, (const double*)s->G, s->PR, gp, f, parts);
+                           s->lds_flux, st, ea, eb, 0, m, Win, (const double*)s->G, s->PR, gp, f);
       });
     } else {
       DDParams pp{};
@@ -282,16 +282,15 @@ struct Impl {
       return launch(s, "flux", [&](hipEvent_t ea, hipEvent_t eb) {
         hipExtLaunchKernelGGL((k_flux_dd<ND, NSP, CT>), dim3(xcd_grid(m.ntiles)),
                            dim3(s->tile_block), s->lds_flux, st, ea, eb, 0, m, Win, (const double*)s->G,
-                           s->PR, pp, f, parts);
+                           s->PR, pp, f);
       });
     }
   }
   static vcx_status update_shared(vcx_solver s, const Finish& f) {
     const DevMesh& m = s->mesh->d;
-    DtParts parts = dt_parts(s);
     return launch(s, "update", [&](hipEvent_t ea, hipEvent_t eb) {
       hipExtLaunchKernelGGL((k_update_shared<ND, NSP, MODEL>), dim3(s->nsh_blocks), dim3(kNodeBlock), 0,
-                         s->mesh->stream, ea, eb, 0, m, (const double*)s->PR, f, parts);
+                         s->mesh->stream, ea, eb, 0, m, (const double*)s->PR, f);
     });
   }
   static vcx_status node_dt(vcx_solver s, const double* W) {
@@ -301,7 +300,7 @@ struct Impl {
     MixParams mp = mix_params(s->ph);
     return launch(s, "node_dt", [&](hipEvent_t ea, hipEvent_t eb) {
       hipExtLaunchKernelGGL((k_node_dt<ND, NSP, MODEL>), dim3(s->n_dtp_node), dim3(kNodeBlock), 0,
-                         s->mesh->stream, ea, eb, 0, m, W, (const double*)s->E, dc, mp, parts, s->sc);
+                         s->mesh->stream, ea, eb, 0, m, W, (const double*)s->E, dc, mp, parts, s->lp);
     });
   }
   // Allow dynamic LDS above the 64 KiB default for the two tile kernels.
@@ -630,7 +629,7 @@ static void free_solver(vcx_solver s) {
   for (double* p : {s->W[0], s->W[1], s->G, s->PG, s->PR, s->E, s->io, s->rbuf, s->part,
                     s->sums_dev, s->dtp_node, s->dtp_step})
     if (p) (void)hipFree(p);
-  if (s->sc) (void)hipFree(s->sc);
+  if (s->lp) (void)hipFree(s->lp);
   if (s->sc_host) (void)hipHostFree(s->sc_host);
   if (s->sums_host) (void)hipHostFree(s->sums_host);
   for (auto& kv : s->ev)
@@ -654,7 +653,7 @@ struct SolverSizes {
   size_t bytes() const {
     auto r = [](size_t n) { return sizeof(double) * std::max<size_t>(n, 1); };
     return 2 * r(W) + r(G) + r(PG) + r(PR) + 2 * r(io) + r(part) + r(sums) + (E ? r(E) : 0) +
-           r((size_t)n_dtp_node) + r((size_t)n_dtp_step) + sizeof(DevScalars);
+           r((size_t)n_dtp_node) + r(2 * (size_t)n_dtp_step) + sizeof(DevLoop);
   }
 };
 
@@ -687,11 +686,13 @@ static vcx_status reset_scalars(vcx_solver s, double t0, bool prime) {
   DevScalars z{};
   z.t = t0;
   z.steps_left = -1;
+  DevLoop l{};
+  l.s[0] = l.s[1] = z;
   *s->sc_host = z;
-  VCX_HIP(hipMemcpyAsync(s->sc, s->sc_host, sizeof(DevScalars), hipMemcpyHostToDevice,
-                         s->mesh->stream));
+  VCX_HIP(hipMemcpyAsync(s->lp, &l, sizeof(DevLoop), hipMemcpyHostToDevice, s->mesh->stream));
   if (prime) VCX_TRY(s->kt->node_dt(s, s->W[s->cur]));
   VCX_HIP(hipStreamSynchronize(s->mesh->stream));
+  s->spar = 0;
   s->host_flag = 0;
   s->steps_total = 0;
   return VCX_OK;
@@ -796,8 +797,8 @@ extern "C" vcx_status vcx_solver_create(vcx_mesh mesh, const vcx_physics* phys, 
   s->nsh_blocks = z.nsh_blocks;
   s->n_dtp_step = z.n_dtp_step;
   chk(dmalloc(&s->dtp_node, (size_t)s->n_dtp_node));
-  chk(dmalloc(&s->dtp_step, (size_t)s->n_dtp_step));
-  if (st == VCX_OK && hipMalloc(reinterpret_cast<void**>(&s->sc), sizeof(DevScalars)) != hipSuccess)
+  chk(dmalloc(&s->dtp_step, 2 * (size_t)s->n_dtp_step));
+  if (st == VCX_OK && hipMalloc(reinterpret_cast<void**>(&s->lp), sizeof(DevLoop)) != hipSuccess)
     st = fail(VCX_E_OOM, "hipMalloc failed");
   if (st == VCX_OK &&
       hipHostMalloc(reinterpret_cast<void**>(&s->sc_host), sizeof(DevScalars), 0) != hipSuccess)
@@ -876,7 +877,7 @@ extern "C" vcx_status vcx_state_download(vcx_solver s, double* U, int is_device)
 extern "C" vcx_status vcx_gradient(vcx_solver s, double* G, int is_device) {
   if (!s || !G) return fail(VCX_E_ARG, "NULL argument");
   if (!s->has_state) return fail(VCX_E_STATE, "no state uploaded");
-  GradCtl gc{nullptr, dt_parts(s), 0};
+  GradCtl gc{nullptr, dt_parts(s), 0, 0};
   VCX_TRY(s->kt->grad(s, s->W[s->cur], gc));
   VCX_TRY(s->kt->grad_complete(s));
   return copy_out(s, s->G, (size_t)s->nr * s->nd, G, is_device);
@@ -897,7 +898,7 @@ extern "C" vcx_status vcx_residual(vcx_solver s, double dt, double* r, int is_de
   if (!s || !r) return fail(VCX_E_ARG, "NULL argument");
   if (!s->has_state) return fail(VCX_E_STATE, "no state uploaded");
   const double* Win = s->W[s->cur];
-  GradCtl gc{nullptr, dt_parts(s), 0};
+  GradCtl gc{nullptr, dt_parts(s), 0, 0};
   VCX_TRY(s->kt->grad(s, Win, gc));
   Finish f = make_finish(s);
   f.Win = Win;
@@ -909,7 +910,8 @@ extern "C" vcx_status vcx_residual(vcx_solver s, double dt, double* r, int is_de
 }
 
 static vcx_status read_scalars(vcx_solver s) {
-  VCX_HIP(hipMemcpyAsync(s->sc_host, s->sc, sizeof(DevScalars), hipMemcpyDeviceToHost,
+  // the state of the last launched step (parity spar ^ 1)
+  VCX_HIP(hipMemcpyAsync(s->sc_host, &s->lp->s[s->spar ^ 1], sizeof(DevScalars), hipMemcpyDeviceToHost,
                          s->mesh->stream));
   VCX_HIP(hipStreamSynchronize(s->mesh->stream));
   return VCX_OK;
@@ -919,7 +921,7 @@ extern "C" vcx_status vcx_timestep(vcx_solver s, double* dt) {
   if (!s || !dt) return fail(VCX_E_ARG, "NULL argument");
   if (!s->has_state) return fail(VCX_E_STATE, "no state uploaded");
   VCX_TRY(s->kt->node_dt(s, s->W[s->cur]));
-  hipLaunchKernelGGL(k_dt_query, dim3(1), dim3(256), 0, s->mesh->stream, s->sc, dt_parts(s));
+  hipLaunchKernelGGL(k_dt_query, dim3(1), dim3(256), 0, s->mesh->stream, s->lp, dt_parts(s));
   VCX_HIP(hipGetLastError());
   VCX_TRY(read_scalars(s));
   *dt = s->sc_host->dt_query;
@@ -927,10 +929,11 @@ extern "C" vcx_status vcx_timestep(vcx_solver s, double* dt) {
   return VCX_OK;
 }
 
-__global__ void k_set_tend(DevScalars* sc, double t_end) {
+// end time of a host call, set in the state the next step starts from
+__global__ void k_set_tend(DevLoop* lp, int par_prev, double t_end) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
-    sc->t_end = t_end;
-    sc->steps_left = -1;
+    lp->s[par_prev].t_end = t_end;
+    lp->s[par_prev].steps_left = -1;
   }
 }
 
@@ -950,13 +953,16 @@ static vcx_status enqueue_step(vcx_solver s) {
   const int K = s->ph.rk_stages;
   double* Wn = s->W[s->cur];
   double* Wk = s->W[1 - s->cur];
+  const int par = s->spar;
   Finish f = make_finish(s);
-  f.sc = s->sc;
+  f.sc = &s->lp->s[par];
+  f.found = &s->lp->found[par];
+  f.cand = s->dtp_step + (size_t)par * s->n_dtp_step;
   f.Un = Wn;
   f.Wout = Wk;
   for (int k = 1; k <= K; ++k) {
     const double* Win = k == 1 ? Wn : Wk;
-    GradCtl gc{s->sc, dt_parts(s), k == 1 ? 1 : 0};
+    GradCtl gc{s->lp, dt_parts(s), par, k == 1 ? 1 : 0};
     VCX_TRY(s->kt->grad(s, Win, gc));
     // stage k of K uses alpha_{k+1}; the last one is the full update
     f.Win = Win;
@@ -966,6 +972,7 @@ static vcx_status enqueue_step(vcx_solver s) {
     VCX_TRY(s->kt->update_shared(s, f));
   }
   s->cur = 1 - s->cur;
+  s->spar ^= 1;
   return VCX_OK;
 }
 
@@ -976,7 +983,7 @@ extern "C" vcx_status vcx_step(vcx_solver s, int nsteps, double t_end, double* t
   if (s->host_flag) return fail(VCX_E_UNSTABLE, "solver is in a failed state; upload a new state");
   const int cur0 = s->cur;
   const long long steps0 = s->steps_total;
-  hipLaunchKernelGGL(k_set_tend, dim3(1), dim3(1), 0, s->mesh->stream, s->sc, t_end);
+  hipLaunchKernelGGL(k_set_tend, dim3(1), dim3(1), 0, s->mesh->stream, s->lp, s->spar ^ 1, t_end);
   VCX_HIP(hipGetLastError());
   const int chunk = t_end > 0.0 ? 16 : 256;
   int launched = 0;
@@ -984,7 +991,7 @@ extern "C" vcx_status vcx_step(vcx_solver s, int nsteps, double t_end, double* t
     const int n = std::min(chunk, nsteps - launched);
     for (int q = 0; q < n; ++q) VCX_TRY(enqueue_step(s));
     launched += n;
-    hipLaunchKernelGGL(k_commit, dim3(1), dim3(1), 0, s->mesh->stream, s->sc);
+    hipLaunchKernelGGL(k_commit, dim3(1), dim3(1), 0, s->mesh->stream, s->lp, s->spar ^ 1);
     VCX_HIP(hipGetLastError());
     VCX_TRY(read_scalars(s));
     if (s->sc_host->flag) break;
@@ -1040,6 +1047,7 @@ struct vcx::BatchGroup {
   std::vector<vcx_solver> mem;
   std::vector<long long> steps0;  // member step counters when the table was built
   std::vector<int> phase0;        // member buffer parity when the table was built
+  std::vector<int> spar0;         // member step parity when the table was built
   int q = 0;                      // batch steps enqueued since the table was built
   BatchRun br{};
   // device tables
@@ -1070,7 +1078,8 @@ static BatchEntry entry_of(vcx_solver s) {
   e.PG = s->PG;
   e.PR = s->PR;
   e.E = s->E;
-  e.sc = s->sc;
+  e.lp = s->lp;
+  e.spar = s->spar;
   e.parts = dt_parts(s);
   e.phase = s->cur;
   return e;
@@ -1124,6 +1133,7 @@ vcx_status vcx::batch_set(BatchGroup* g, vcx_solver* ss, int n, const int* steps
   int block = 64;
   g->steps0.resize(n);
   g->phase0.resize(n);
+  g->spar0.resize(n);
   // each solve's reducer entry first (dispatched early), then the tiles
   for (int i = 0; i < n; ++i) tmap.push_back(make_int2(i, -1));
   for (int i = 0; i < n; ++i) {
@@ -1131,6 +1141,7 @@ vcx_status vcx::batch_set(BatchGroup* g, vcx_solver* ss, int n, const int* steps
     tab[i] = entry_of(s);
     g->steps0[i] = s->steps_total;
     g->phase0[i] = s->cur;
+    g->spar0[i] = s->spar;
     for (int t = 0; t < s->mesh->d.ntiles; ++t) tmap.push_back(make_int2(i, t));
     for (int b = 0; b < s->nsh_blocks; ++b) smap.push_back(make_int2(i, b));
     lg = std::max(lg, s->lds_grad);
@@ -1220,7 +1231,7 @@ vcx_status vcx::batch_sync(BatchGroup* g, std::vector<int>* ended) {
   if (!g || g->mem.empty()) return VCX_OK;
   const int n = (int)g->mem.size();
   hipLaunchKernelGGL(k_batch_commit, dim3((n + 63) / 64), dim3(64), 0, g->stream, (const BatchEntry*)g->tab,
-                     n, g->out);
+                     n, g->q, g->out);
   VCX_HIP(hipGetLastError());
   VCX_HIP(hipMemcpyAsync(g->out_host, g->out, sizeof(DevScalars) * n, hipMemcpyDeviceToHost, g->stream));
   VCX_HIP(hipStreamSynchronize(g->stream));
@@ -1228,6 +1239,7 @@ vcx_status vcx::batch_sync(BatchGroup* g, std::vector<int>* ended) {
     vcx_solver s = g->mem[i];
     const DevScalars& h = g->out_host[i];
     *s->sc_host = h;
+    s->spar = (g->spar0[i] + g->q) & 1;
     s->steps_last = h.steps - s->steps_total;
     s->steps_total = h.steps;
     s->cur = (int)((g->phase0[i] + (h.steps - g->steps0[i])) % 2);

@@ -61,7 +61,7 @@ struct DevMesh {
   const int32_t* perm;       // [nn] internal -> caller
 };
 
-// Per-solve device scalars of the time loop.
+// Per-solve device scalars of the time loop: the state of one step.
 struct DevScalars {
   double t;        // committed time
   double dt;       // time step of the running step
@@ -76,11 +76,22 @@ struct DevScalars {
   long long steps; // committed steps
 };
 
+// The time loop of a solve.  Steps alternate between two parities: a step
+// of parity p decides from the state s[p ^ 1] (the previous step's, or the
+// one set up by the host) into s[p], raises failures in found[p] and posts
+// the time-step candidates of its new state in cand[p].  So no kernel of a
+// step writes what another block of the same launch reads.
+struct DevLoop {
+  DevScalars s[2];
+  int found[2];   // failures (1: unstable state) raised by a step's final stage
+  int pad[2];
+};
+
 // dt candidate buffers (one minimum per block of the producing kernel)
 struct DtParts {
   double* node;   // k_node_dt: one per 256 nodes
   int nnode;
-  double* step;   // final stage: one per tile, then one per shared-update block
+  double* step;   // [2][nstep] by parity: one per tile, then one per shared-update block
   int nstep;
 };
 
@@ -233,39 +244,74 @@ __host__ __device__ inline size_t inc_lds_bytes(int nv, int maxc) {
 // bytes of a tile's slot table in LDS
 __host__ __device__ inline size_t slot_lds_bytes(int maxn) { return (size_t)4 * maxn * sizeof(int); }
 
-// Reduce the dt candidates of the previous pass, commit the previous step and
-// start the next one (or stop at t_end / on failure).  Block-wide call.
-__device__ inline void dt_reduce_commit(DevScalars* sc, const DtParts parts) {
-  const bool from_step = sc->dt_src != 0;
-  const double* p = from_step ? parts.step : parts.node;
-  const int np = from_step ? parts.nstep : parts.nnode;
-  double v = INFINITY;
-  for (int q = threadIdx.x; q < np; q += blockDim.x) v = fmin(v, p[q]);
-  double d = block_min(v);
-  if (threadIdx.x == 0) {
-    if (sc->pending) {
-      if (sc->flag == 0) {
-        sc->t += sc->dt;
-        sc->last_dt = sc->dt;
-        sc->steps += 1;
-      }
-      sc->pending = 0;
+// Decision of a step from the state it starts from: commit the previous
+// step unless it failed, then start this one (or stop at the end time, the
+// step budget or on failure).  d is the smallest candidate of the state.
+__device__ inline void step_decide(const DevScalars& prev, int found_prev, double d, DevScalars& n) {
+  n = prev;
+  const int fl = prev.flag | found_prev;
+  if (n.pending) {
+    if (fl == 0) {
+      n.t += n.dt;
+      n.last_dt = n.dt;
+      n.steps += 1;
     }
-    sc->active = 0;
-    const bool done_t = (sc->t_end > 0.0 && sc->t >= sc->t_end) || sc->steps_left == 0;
-    if (sc->flag == 0 && !done_t) {
-      if (!(d > 0.0) || !isfinite(d)) {
-        sc->flag |= 2;  // non-physical state or no limiting time scale
-      } else {
-        if (sc->t_end > 0.0 && sc->t + d > sc->t_end) d = sc->t_end - sc->t;
-        sc->dt = d;
-        sc->active = 1;
-        sc->pending = 1;
-        if (sc->steps_left > 0) sc->steps_left -= 1;
-      }
+    n.pending = 0;
+  }
+  n.flag = fl;
+  n.active = 0;
+  const bool done_t = (n.t_end > 0.0 && n.t >= n.t_end) || n.steps_left == 0;
+  if (n.flag == 0 && !done_t) {
+    if (!(d > 0.0) || !isfinite(d)) {
+      n.flag |= 2;  // non-physical state or no limiting time scale
+    } else {
+      if (n.t_end > 0.0 && n.t + d > n.t_end) d = n.t_end - n.t;
+      n.dt = d;
+      n.active = 1;
+      n.pending = 1;
+      if (n.steps_left > 0) n.steps_left -= 1;
     }
   }
+}
+
+// Smallest candidate of the state a step of parity par starts from
+// (block-wide; valid in thread 0).
+__device__ inline double step_candidate(const DevLoop* lp, int par, const DtParts& parts) {
+  const DevScalars& prev = lp->s[par ^ 1];
+  const double* p = prev.dt_src ? parts.step + (size_t)(par ^ 1) * parts.nstep : parts.node;
+  const int np = prev.dt_src ? parts.nstep : parts.nnode;
+  double v = INFINITY;
+  for (int q = threadIdx.x; q < np; q += blockDim.x) v = fmin(v, p[q]);
+  return block_min(v);
+}
+
+// One block decides the step of parity par and writes its state.
+__device__ inline void step_start(DevLoop* lp, int par, const DtParts& parts) {
+  const double d = step_candidate(lp, par, parts);
+  if (threadIdx.x == 0) {
+    DevScalars n;
+    step_decide(lp->s[par ^ 1], lp->found[par ^ 1], d, n);
+    lp->s[par] = n;
+    lp->found[par ^ 1] = 0;
+  }
   __syncthreads();
+}
+
+// Commit the pending step of the state of parity par (end of a host call).
+__device__ inline void step_finish(DevLoop* lp, int par) {
+  DevScalars& sc = lp->s[par];
+  const int fl = sc.flag | lp->found[par];
+  if (sc.pending) {
+    if (fl == 0) {
+      sc.t += sc.dt;
+      sc.last_dt = sc.dt;
+      sc.steps += 1;
+    }
+    sc.pending = 0;
+  }
+  sc.flag = fl;
+  lp->found[par] = 0;
+  sc.active = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -338,9 +384,10 @@ __device__ inline double ns_node_dt(double dx, const DtCoef& c, const MixParams&
 // ---------------------------------------------------------------------------
 
 struct GradCtl {
-  DevScalars* sc;  // null outside the time loop
+  DevLoop* lp;     // null outside the time loop
   DtParts parts;
-  int first_stage; // first stage of a step: an extra block reduces the dt candidates and commits
+  int par;         // parity of the step
+  int first_stage; // first stage: an extra block decides the step
 };
 
 template <int ND, int NR>
@@ -349,7 +396,7 @@ __device__ inline void grad_tile_body(const DevMesh& m, const double* __restrict
                                       const GradCtl& ctl, int t, double* lds) {
   constexpr int NV = ND + 1, NC = NR * ND;
   // later stages of a step that does no work (set by an earlier launch)
-  if (ctl.sc && !ctl.first_stage && ctl.sc->active == 0) return;
+  if (ctl.lp && !ctl.first_stage && ctl.lp->s[ctl.par].active == 0) return;
   TilePre<NV> tp;
   tile_prefetch<NV>(m, t, tp);
   const int maxn = m.max_tile_nodes, maxc = m.max_tile_cells;
@@ -441,9 +488,9 @@ __global__ void __launch_bounds__(256) k_grad_tile(DevMesh m, const double* __re
   extern __shared__ double lds[];
   // in the first stage of a step, block 0 reduces the time-step candidates
   // and commits (the tiles take the other blocks, so that no tile waits on it)
-  const int lead = ctl.sc && ctl.first_stage ? 1 : 0;
+  const int lead = ctl.lp && ctl.first_stage ? 1 : 0;
   if (lead && blockIdx.x == 0) {
-    dt_reduce_commit(ctl.sc, ctl.parts);
+    step_start(ctl.lp, ctl.par, ctl.parts);
     return;
   }
   const int t = xcd_tile_of((int)blockIdx.x - lead, m.ntiles);
@@ -551,7 +598,9 @@ struct Finish {
   const double* G;      // gradients of complete nodes (drift-diffusion closure)
   const double* PG;     // gradient partials of shared nodes
   const double* E;      // field (drift-diffusion)
-  DevScalars* sc;       // null: residual only
+  DevScalars* sc;       // state of the running step; null: residual only
+  int* found;           // failures raised by this step
+  double* cand;         // time-step candidates of this step's new state
   DtCoef dc;
   MixParams mix;        // Navier-Stokes species data
   double alpha;
@@ -662,13 +711,13 @@ __device__ inline double finish_node(const DevMesh& m, const Finish& f, int i, b
 #pragma unroll
     for (int v = 0; v < NVAR; ++v) ok = ok && isfinite(u[v]);
     if (!f.final_stage) return INFINITY;
-    if (!ok) atomicOr(&f.sc->flag, 1);
+    if (!ok) atomicOr(f.found, 1);
     return ns_node_dt<ND, NSP>(ni.dx, f.dc, f.mix, u[0], prim, p, aux, ok);
   }
 #pragma unroll
   for (int v = 0; v < NVAR; ++v) ok = ok && isfinite(u[v]);
   if (!f.final_stage) return INFINITY;
-  if (!ok) atomicOr(&f.sc->flag, 1);
+  if (!ok) atomicOr(f.found, 1);
   return node_dt<ND, NSP, MODEL>(f.dc, ni.dx, ni.E, u, p);
 }
 
@@ -684,8 +733,7 @@ struct GasParams {
 template <int ND, int NSP, int FLUX, typename CT>
 __device__ inline void flux_gas_body(DevMesh m, const double* __restrict__ W,
                                                   const double* __restrict__ G,
-                                                  double* __restrict__ PR, GasParams gp, Finish f,
-                                                  DtParts parts, int t, double* lds) {
+                                                  double* __restrict__ PR, GasParams gp, Finish f, int t, double* lds) {
   constexpr int NV = ND + 1, NVAR = 2 + ND + NSP, NR = NVAR + 1, NE = Edges<ND>::NE;
   if (step_inactive(f.sc)) return;
   TilePre<NV> tp;
@@ -795,19 +843,18 @@ __device__ inline void flux_gas_body(DevMesh m, const double* __restrict__ W,
   }
   if (f.final_stage && f.sc) {
     const double b = block_min(cand);
-    if (threadIdx.x == 0) parts.step[t] = b;
+    if (threadIdx.x == 0) f.cand[t] = b;
   }
 }
 
 template <int ND, int NSP, int FLUX, typename CT>
 __global__ void VCX_FLUX_BOUNDS k_flux_gas(DevMesh m, const double* __restrict__ W,
                                                   const double* __restrict__ G,
-                                                  double* __restrict__ PR, GasParams gp, Finish f,
-                                                  DtParts parts) {
+                                                  double* __restrict__ PR, GasParams gp, Finish f) {
   extern __shared__ double lds[];
   const int t = xcd_tile(m.ntiles);
   if (t >= m.ntiles) return;
-  flux_gas_body<ND, NSP, FLUX, CT>(m, W, G, PR, gp, f, parts, t, lds);
+  flux_gas_body<ND, NSP, FLUX, CT>(m, W, G, PR, gp, f, t, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -825,8 +872,7 @@ struct DDParams {
 template <int ND, int NS, typename CT>
 __device__ inline void flux_dd_body(DevMesh m, const double* __restrict__ U,
                                                  const double* __restrict__ G,
-                                                 double* __restrict__ PR, DDParams pp, Finish f,
-                                                 DtParts parts, int t, double* lds) {
+                                                 double* __restrict__ PR, DDParams pp, Finish f, int t, double* lds) {
   constexpr int NV = ND + 1, NE = Edges<ND>::NE;
   if (step_inactive(f.sc)) return;
   TilePre<NV> tp;
@@ -949,19 +995,18 @@ __device__ inline void flux_dd_body(DevMesh m, const double* __restrict__ U,
   }
   if (f.final_stage && f.sc) {
     const double b = block_min(cand);
-    if (threadIdx.x == 0) parts.step[t] = b;
+    if (threadIdx.x == 0) f.cand[t] = b;
   }
 }
 
 template <int ND, int NS, typename CT>
 __global__ void VCX_FLUX_BOUNDS k_flux_dd(DevMesh m, const double* __restrict__ U,
                                                  const double* __restrict__ G,
-                                                 double* __restrict__ PR, DDParams pp, Finish f,
-                                                 DtParts parts) {
+                                                 double* __restrict__ PR, DDParams pp, Finish f) {
   extern __shared__ double lds[];
   const int t = xcd_tile(m.ntiles);
   if (t >= m.ntiles) return;
-  flux_dd_body<ND, NS, CT>(m, U, G, PR, pp, f, parts, t, lds);
+  flux_dd_body<ND, NS, CT>(m, U, G, PR, pp, f, t, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -974,8 +1019,7 @@ __global__ void VCX_FLUX_BOUNDS k_flux_dd(DevMesh m, const double* __restrict__ 
 template <int ND, int NSP, typename CT>
 __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ W,
                                           const double* __restrict__ G,
-                                          double* __restrict__ PR, GasParams gp, Finish f,
-                                          DtParts parts, int t, double* lds) {
+                                          double* __restrict__ PR, GasParams gp, Finish f, int t, double* lds) {
   constexpr int NV = ND + 1, NVAR = 2 + ND + NSP, NR = NVAR + 1, NE = Edges<ND>::NE;
   constexpr int NP = ND + 1 + NSP, NA = 3 + 2 * NSP, NG = NR + NP;
   if (step_inactive(f.sc)) return;
@@ -1107,19 +1151,18 @@ __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ W,
   }
   if (f.final_stage && f.sc) {
     const double b = block_min(cand);
-    if (threadIdx.x == 0) parts.step[t] = b;
+    if (threadIdx.x == 0) f.cand[t] = b;
   }
 }
 
 template <int ND, int NSP, typename CT>
 __global__ void VCX_FLUX_BOUNDS k_flux_ns(DevMesh m, const double* __restrict__ W,
                                           const double* __restrict__ G,
-                                          double* __restrict__ PR, GasParams gp, Finish f,
-                                          DtParts parts) {
+                                          double* __restrict__ PR, GasParams gp, Finish f) {
   extern __shared__ double lds[];
   const int t = xcd_tile(m.ntiles);
   if (t >= m.ntiles) return;
-  flux_ns_body<ND, NSP, CT>(m, W, G, PR, gp, f, parts, t, lds);
+  flux_ns_body<ND, NSP, CT>(m, W, G, PR, gp, f, t, lds);
 }
 
 // multi-species node rows (p, primitives, aux) of an uploaded state
@@ -1145,7 +1188,7 @@ __global__ void __launch_bounds__(256) k_ns_aux(double* __restrict__ W, int nn, 
 
 template <int ND, int NSP, int MODEL>
 __device__ inline void update_shared_body(const DevMesh& m, const double* __restrict__ PR,
-                                          const Finish& f, const DtParts& parts, int b) {
+                                          const Finish& f, int b) {
   constexpr int NVAR = MODEL == 1 ? NSP : 2 + ND + NSP;
   if (step_inactive(f.sc)) return;
   // the next step reduces the candidates written by this stage
@@ -1169,14 +1212,14 @@ __device__ inline void update_shared_body(const DevMesh& m, const double* __rest
   }
   if (f.final_stage && f.sc) {
     const double bm = block_min(cand);
-    if (threadIdx.x == 0) parts.step[m.ntiles + b] = bm;
+    if (threadIdx.x == 0) f.cand[m.ntiles + b] = bm;
   }
 }
 
 template <int ND, int NSP, int MODEL>
 __global__ void __launch_bounds__(256) k_update_shared(DevMesh m, const double* __restrict__ PR,
-                                                       Finish f, DtParts parts) {
-  update_shared_body<ND, NSP, MODEL>(m, PR, f, parts, blockIdx.x);
+                                                       Finish f) {
+  update_shared_body<ND, NSP, MODEL>(m, PR, f, blockIdx.x);
 }
 
 // dt candidates of the current state, one per 256 nodes (after an upload or
@@ -1184,7 +1227,7 @@ __global__ void __launch_bounds__(256) k_update_shared(DevMesh m, const double* 
 template <int ND, int NSP, int MODEL>
 __global__ void __launch_bounds__(256) k_node_dt(DevMesh m, const double* __restrict__ W,
                                                  const double* __restrict__ E, DtCoef dc,
-                                                 MixParams mp, DtParts parts, DevScalars* sc) {
+                                                 MixParams mp, DtParts parts, DevLoop* lp) {
   constexpr int NVAR = MODEL == 1 ? NSP : 2 + ND + NSP;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   double cand = INFINITY;
@@ -1214,29 +1257,21 @@ __global__ void __launch_bounds__(256) k_node_dt(DevMesh m, const double* __rest
   const double b = block_min(cand);
   if (threadIdx.x == 0) {
     parts.node[blockIdx.x] = b;
-    if (blockIdx.x == 0) sc->dt_src = 0;
+    // the next step (either parity) takes its candidates from this pass
+    if (blockIdx.x == 0) lp->s[0].dt_src = lp->s[1].dt_src = 0;
   }
 }
 
-__global__ void __launch_bounds__(256) k_dt_query(DevScalars* sc, DtParts parts) {
+__global__ void __launch_bounds__(256) k_dt_query(DevLoop* lp, DtParts parts) {
   double v = INFINITY;
   for (int q = threadIdx.x; q < parts.nnode; q += blockDim.x) v = fmin(v, parts.node[q]);
   const double d = block_min(v);
-  if (threadIdx.x == 0) sc->dt_query = (d > 0.0 && isfinite(d)) ? d : -1.0;
+  if (threadIdx.x == 0) lp->s[0].dt_query = lp->s[1].dt_query = (d > 0.0 && isfinite(d)) ? d : -1.0;
 }
 
-__global__ void k_commit(DevScalars* sc) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    if (sc->pending) {
-      if (sc->flag == 0) {
-        sc->t += sc->dt;
-        sc->last_dt = sc->dt;
-        sc->steps += 1;
-      }
-      sc->pending = 0;
-    }
-    sc->active = 0;
-  }
+// end of a host call: commit the last step (of parity par)
+__global__ void k_commit(DevLoop* lp, int par) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) step_finish(lp, par);
 }
 
 // smallest inscribed diameter 2 nd V / sum_k |S_k| over the cells of each node
@@ -1288,9 +1323,10 @@ struct BatchEntry {
   double* PG;
   double* PR;
   const double* E;
-  DevScalars* sc;
+  DevLoop* lp;
   DtParts parts;
-  int phase;
+  int phase;        // buffer parity of the solve at batch step 0
+  int spar;         // step parity of the solve at batch step 0
 };
 
 struct BatchStage {
@@ -1316,7 +1352,10 @@ __device__ inline Finish batch_finish(const BatchEntry& e, const BatchStage& st,
   f.G = e.G;
   f.PG = e.PG;
   f.E = e.E;
-  f.sc = e.sc;
+  const int par = (st.step + e.spar) & 1;
+  f.sc = &e.lp->s[par];
+  f.found = &e.lp->found[par];
+  f.cand = e.parts.step + (size_t)par * e.parts.nstep;
   f.dc = fs.dc;
   f.mix = fs.mix;
   f.alpha = st.alpha;
@@ -1336,14 +1375,15 @@ __global__ void __launch_bounds__(256) k_grad_tile_batch(const BatchEntry* __res
   if (g >= nblocks) return;
   const int2 ml = map[g];
   const BatchEntry& e = tab[ml.x];
+  const int par = (st.step + e.spar) & 1;
   if (ml.y < 0) {
-    // the solve's reducer entry: time step of the step that starts now
-    if (st.stage == 1) dt_reduce_commit(e.sc, e.parts);
+    // the solve's decision entry: the step that starts now
+    if (st.stage == 1) step_start(e.lp, par, e.parts);
     return;
   }
   const int cur = (st.step + e.phase) & 1;
   const double* Win = st.stage == 1 ? e.W[cur] : e.W[cur ^ 1];
-  GradCtl ctl{e.sc, e.parts, st.stage == 1 ? 1 : 0};
+  GradCtl ctl{e.lp, e.parts, par, st.stage == 1 ? 1 : 0};
   grad_tile_body<ND, NR>(e.m, Win, e.G, e.PG, ctl, ml.y, lds);
 }
 
@@ -1359,7 +1399,7 @@ __global__ void VCX_FLUX_BOUNDS k_flux_gas_batch(const BatchEntry* __restrict__ 
   const BatchEntry& e = tab[ml.x];
   const double* Win;
   const Finish f = batch_finish(e, st, fs, &Win);
-  flux_gas_body<ND, NSP, FLUX, CT>(e.m, Win, e.G, e.PR, gp, f, e.parts, ml.y, lds);
+  flux_gas_body<ND, NSP, FLUX, CT>(e.m, Win, e.G, e.PR, gp, f, ml.y, lds);
 }
 
 template <int ND, int NS, typename CT>
@@ -1374,7 +1414,7 @@ __global__ void VCX_FLUX_BOUNDS k_flux_dd_batch(const BatchEntry* __restrict__ t
   const BatchEntry& e = tab[ml.x];
   const double* Win;
   const Finish f = batch_finish(e, st, fs, &Win);
-  flux_dd_body<ND, NS, CT>(e.m, Win, e.G, e.PR, pp, f, e.parts, ml.y, lds);
+  flux_dd_body<ND, NS, CT>(e.m, Win, e.G, e.PR, pp, f, ml.y, lds);
 }
 
 template <int ND, int NSP, typename CT>
@@ -1389,7 +1429,7 @@ __global__ void VCX_FLUX_BOUNDS k_flux_ns_batch(const BatchEntry* __restrict__ t
   const BatchEntry& e = tab[ml.x];
   const double* Win;
   const Finish f = batch_finish(e, st, fs, &Win);
-  flux_ns_body<ND, NSP, CT>(e.m, Win, e.G, e.PR, gp, f, e.parts, ml.y, lds);
+  flux_ns_body<ND, NSP, CT>(e.m, Win, e.G, e.PR, gp, f, ml.y, lds);
 }
 
 template <int ND, int NSP, int MODEL>
@@ -1400,7 +1440,7 @@ __global__ void __launch_bounds__(256) k_update_shared_batch(const BatchEntry* _
   const BatchEntry& e = tab[ml.x];
   const double* Win;
   const Finish f = batch_finish(e, st, fs, &Win);
-  update_shared_body<ND, NSP, MODEL>(e.m, e.PR, f, e.parts, ml.y);
+  update_shared_body<ND, NSP, MODEL>(e.m, e.PR, f, ml.y);
 }
 
 // per-solve control of a batch call: end time and step budget
@@ -1408,25 +1448,21 @@ __global__ void k_batch_control(const BatchEntry* __restrict__ tab, int n,
                                 const double* __restrict__ t_end, const int* __restrict__ steps) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  tab[i].sc->t_end = t_end[i];
-  tab[i].sc->steps_left = steps[i];
+  // the state the first batch step starts from
+  DevScalars& sc = tab[i].lp->s[tab[i].spar ^ 1];
+  sc.t_end = t_end[i];
+  sc.steps_left = steps[i];
 }
 
-// commit every solve's pending step and copy the scalars to one array
-__global__ void k_batch_commit(const BatchEntry* __restrict__ tab, int n, DevScalars* __restrict__ out) {
+// after nq batch steps: commit every solve's last step and copy the
+// scalars to one array
+__global__ void k_batch_commit(const BatchEntry* __restrict__ tab, int n, int nq,
+                               DevScalars* __restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  DevScalars* sc = tab[i].sc;
-  if (sc->pending) {
-    if (sc->flag == 0) {
-      sc->t += sc->dt;
-      sc->last_dt = sc->dt;
-      sc->steps += 1;
-    }
-    sc->pending = 0;
-  }
-  sc->active = 0;
-  out[i] = *sc;
+  const int par = (tab[i].spar + nq + 1) & 1;  // parity of batch step nq - 1
+  step_finish(tab[i].lp, par);
+  out[i] = tab[i].lp->s[par];
 }
 
 // ---------------------------------------------------------------------------

@@ -340,8 +340,98 @@ std::string preprocess_mesh(int nd, int64_t nn, const double* xyz, int64_t nc, i
     if (m.node_slot[g + 1] - m.node_slot[g] > 1) m.slot_node[s] = ~g;
   }
 
+  if (nd == 2) build_halos(m);
   *code = 0;
   return "";
+}
+
+void build_halos(HostMesh& m) {
+  const int nv = m.nv;
+  const int64_t nn = m.nn, nc = m.nc, T = m.ntiles();
+  // cells around each node, ascending cell id
+  std::vector<int32_t> cstart(nn + 1, 0), cells_of((size_t)nc * nv);
+  for (int64_t c = 0; c < nc; ++c)
+    for (int k = 0; k < nv; ++k) cstart[m.cell[(size_t)k * nc + c] + 1]++;
+  for (int64_t i = 0; i < nn; ++i) cstart[i + 1] += cstart[i];
+  {
+    std::vector<int32_t> fill(cstart.begin(), cstart.end() - 1);
+    for (int64_t c = 0; c < nc; ++c)
+      for (int k = 0; k < nv; ++k) cells_of[fill[m.cell[(size_t)k * nc + c]]++] = (int32_t)c;
+  }
+  std::vector<int32_t> loc(nn, -1), hc, hn;
+  std::vector<std::vector<uint16_t>> hl(nv);
+  m.tile_hcell.assign(1, 0);
+  m.tile_hnode.assign(1, 0);
+  m.slot_ginc.assign(1, 0);
+  m.ginc.clear();
+  m.hnode.clear();
+  m.hshift.clear();
+  m.max_ext_cells = m.max_ext_nodes = m.max_tile_ginc = 0;
+  for (int64_t t = 0; t < T; ++t) {
+    const int32_t c0 = m.tile_cell[t], c1 = m.tile_cell[t + 1];
+    const int32_t s0 = m.tile_slot[t], s1 = m.tile_slot[t + 1];
+    const int32_t ncl = c1 - c0, ns = s1 - s0;
+    for (int32_t s = s0; s < s1; ++s) {
+      const int32_t v = m.slot_node[s];
+      loc[v >= 0 ? v : ~v] = s - s0;
+    }
+    // halo cells: cells of the tile's shared nodes outside the tile
+    hc.clear();
+    for (int32_t s = s0; s < s1; ++s) {
+      const int32_t v = m.slot_node[s];
+      if (v >= 0) continue;
+      const int32_t g = ~v;
+      for (int32_t p = cstart[g]; p < cstart[g + 1]; ++p)
+        if (cells_of[p] < c0 || cells_of[p] >= c1) hc.push_back(cells_of[p]);
+    }
+    std::sort(hc.begin(), hc.end());
+    hc.erase(std::unique(hc.begin(), hc.end()), hc.end());
+    // halo nodes: vertices of halo cells that are not slots of the tile
+    hn.clear();
+    for (int32_t c : hc)
+      for (int k = 0; k < nv; ++k) {
+        const int32_t i = m.cell[(size_t)k * nc + c];
+        if (loc[i] < 0) hn.push_back(i);
+      }
+    std::sort(hn.begin(), hn.end());
+    hn.erase(std::unique(hn.begin(), hn.end()), hn.end());
+    for (size_t q = 0; q < hn.size(); ++q) loc[hn[q]] = ns + (int32_t)q;
+    for (int32_t c : hc) {
+      for (int k = 0; k < nv; ++k) hl[k].push_back((uint16_t)loc[m.cell[(size_t)k * nc + c]]);
+      m.hshift.push_back(m.shift[c]);
+    }
+    for (int32_t i : hn) m.hnode.push_back(i);
+    // cells around each slot node in ascending cell id, extended-local
+    const size_t g0 = m.ginc.size();
+    for (int32_t s = s0; s < s1; ++s) {
+      const int32_t v = m.slot_node[s], g = v >= 0 ? v : ~v;
+      for (int32_t p = cstart[g]; p < cstart[g + 1]; ++p) {
+        const int32_t c = cells_of[p];
+        int32_t e;
+        if (c >= c0 && c < c1) {
+          e = c - c0;
+        } else {
+          e = ncl + (int32_t)(std::lower_bound(hc.begin(), hc.end(), c) - hc.begin());
+        }
+        m.ginc.push_back((uint16_t)e);
+      }
+      m.slot_ginc.push_back((int32_t)m.ginc.size());
+    }
+    m.tile_hcell.push_back(m.tile_hcell.back() + (int32_t)hc.size());
+    m.tile_hnode.push_back(m.tile_hnode.back() + (int32_t)hn.size());
+    m.max_ext_cells = std::max(m.max_ext_cells, ncl + (int)hc.size());
+    m.max_ext_nodes = std::max(m.max_ext_nodes, ns + (int)hn.size());
+    m.max_tile_ginc = std::max(m.max_tile_ginc, (int)(m.ginc.size() - g0));
+    for (int32_t s = s0; s < s1; ++s) {
+      const int32_t v = m.slot_node[s];
+      loc[v >= 0 ? v : ~v] = -1;
+    }
+    for (int32_t i : hn) loc[i] = -1;
+  }
+  const size_t H = m.hshift.size();
+  m.hlconn.resize((size_t)nv * H);
+  for (int k = 0; k < nv; ++k) std::copy(hl[k].begin(), hl[k].end(), m.hlconn.begin() + (size_t)k * H);
+  m.has_halo = m.max_ext_cells < 65536 && m.max_ext_nodes < 65536;
 }
 
 }  // namespace vcx

@@ -48,6 +48,20 @@ struct HostMesh {
   std::vector<int32_t> slot_run;   // [2P] per slot: [begin, end) of its node's run in slots_of
   int max_tile_cells = 0, max_tile_nodes = 0;
 
+  // extended tiles (2D): each tile plus the halo cells around its shared
+  // nodes, so that a tile pass can form complete nodal gradients itself.
+  // Extended-local nodes: the tile's slots first, then its halo nodes;
+  // extended-local cells: the tile's cells first, then its halo cells.
+  bool has_halo = false;
+  std::vector<int32_t> tile_hcell;  // [T+1] offsets of each tile's halo cells
+  std::vector<uint16_t> hlconn;     // [nv][H] extended-local node of each halo cell vertex
+  std::vector<uint32_t> hshift;     // [H] periodic image code of each halo cell
+  std::vector<int32_t> tile_hnode;  // [T+1] offsets of each tile's halo nodes
+  std::vector<int32_t> hnode;       // halo nodes (internal ids), ascending inside a tile
+  std::vector<int32_t> slot_ginc;   // [P+1] CSR into ginc
+  std::vector<uint16_t> ginc;       // extended-local cells around each slot's node, ascending cell id
+  int max_ext_cells = 0, max_ext_nodes = 0, max_tile_ginc = 0;
+
   int64_t ntiles() const { return (int64_t)tile_cell.size() - 1; }
   int64_t nslots() const { return (int64_t)slot_node.size(); }
 };
@@ -57,6 +71,9 @@ struct HostMesh {
 std::string preprocess_mesh(int nd, int64_t nn, const double* xyz, int64_t nc, int nv,
                             const int64_t* cells, const double* period, TileLimits lim,
                             HostMesh& out, int* code);
+
+// Build the extended-tile tables of a preprocessed mesh (any dimension).
+void build_halos(HostMesh& m);
 
 // Decode the periodic image of vertex k (1..nv-1) along axis d: -1, 0, +1.
 inline int shift_of(uint32_t code, int k, int d, int nd) {
