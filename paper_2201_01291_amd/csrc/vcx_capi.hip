@@ -70,9 +70,7 @@ struct vcx_solver_s {
   DevLoop* lp = nullptr;          // time loop (two step states by parity)
   DevScalars* sc_host = nullptr;  // pinned mirror of the current state
   int spar = 0;                   // parity of the next step
-  double* dtp_node = nullptr;     // dt candidates of the node pass
-  double* dtp_step = nullptr;     // dt candidates of the step kernels, [2][n_dtp_step] by parity
-  int n_dtp_node = 0, n_dtp_step = 0, nsh_blocks = 1;
+  int node_blocks = 0, nsh_blocks = 1;
   double* part = nullptr;
   double* sums_dev = nullptr;
   double* sums_host = nullptr;     // pinned
@@ -81,7 +79,9 @@ struct vcx_solver_s {
   long long steps_total = 0;
   int64_t steps_last = 0;
   const KernelTable* kt = nullptr;
-  size_t lds_grad = 0, lds_flux = 0;
+  size_t lds_grad = 0, lds_flux = 0, lds_fused = 0;
+  bool fused = false;      // time loop and residual run the fused gradient + flux pass
+  double* gout = nullptr;  // fused passes: node gradients for the boundary closure, or null
   int tile_block = 256;
   size_t bytes = 0;  // device bytes held by the solver (mesh excluded)
   // profiling
@@ -157,7 +157,9 @@ struct KernelTable {
   vcx_status (*node_dt)(vcx_solver, const double* W);
   size_t (*lds_grad)(int maxn, int maxc);
   size_t (*lds_flux)(int maxn, int maxc);
-  vcx_status (*allow_lds)(size_t grad_bytes, size_t flux_bytes);
+  size_t (*lds_fused)(const DevMesh& d);  // 0: no fused pass for this model
+  vcx_status (*fused)(vcx_solver, const double* Win, const Finish& f, const FusedCtl& fc, double dt_host);
+  vcx_status (*allow_lds)(size_t grad_bytes, size_t flux_bytes, size_t fused_bytes);
   vcx_status (*aux)(vcx_solver, double* W);
   vcx_status (*batch_stage)(const struct BatchRun& br, hipStream_t stream, const BatchStage& st, bool prof);
   int nw, ngf;
@@ -173,11 +175,9 @@ struct BatchRun {
   int nsh_blocks;
   size_t lds_grad, lds_flux;
   int tile_block;
+  bool fused;
 };
 
-static DtParts dt_parts(vcx_solver s) {
-  return DtParts{s->dtp_node, s->n_dtp_node, s->dtp_step, s->n_dtp_step};
-}
 
 static MixParams mix_params(const vcx_physics& ph) {
   MixParams mp{};
@@ -225,6 +225,40 @@ struct Impl {
                 : MODEL == 1 ? (size_t)(NSP + NSP * ND + ND) * maxn
                              : (size_t)(NW + NGF * ND) * maxn;
     return dbl + sizeof(CT) * ct + slot_lds_bytes(maxn) + inc_lds_bytes(NV, maxc);
+  }
+  static constexpr bool FUSABLE = ND == 2 && MODEL != 2;
+  static size_t lds_fused(const DevMesh& d) {
+    if constexpr (FUSABLE) {
+      if (!d.has_halo) return 0;
+      return fused_lds_bytes<ND, NSP, MODEL, CT>(d.max_tile_nodes, d.max_tile_cells, d.max_ext_nodes,
+                                                 d.max_ext_cells, d.max_tile_ginc);
+    } else {
+      return 0;
+    }
+  }
+  static DDParams dd_params(const vcx_physics& ph, double dt_host) {
+    DDParams pp{};
+    for (int k = 0; k < NSP && k < 4; ++k) {
+      pp.zmu[k] = ph.z[k] * ph.mu[k];
+      pp.D[k] = ph.D[k];
+    }
+    pp.beta = ph.beta;
+    pp.dt_host = dt_host;
+    pp.limiter = ph.limiter;
+    return pp;
+  }
+  static vcx_status fused(vcx_solver s, const double* Win, const Finish& f, const FusedCtl& fc, double dt_host) {
+    if constexpr (FUSABLE) {
+      const DevMesh& m = s->mesh->d;
+      GasParams gp{s->ph.gamma, s->ph.beta, s->ph.entropy_fix, s->ph.limiter};
+      DDParams pp = dd_params(s->ph, dt_host);
+      return launch(s, "flux", [&](hipEvent_t ea, hipEvent_t eb) {
+        hipExtLaunchKernelGGL((k_fused<ND, NSP, MODEL, FLUX, CT>), dim3(xcd_grid(m.ntiles)), dim3(s->tile_block),
+                              s->lds_fused, s->mesh->stream, ea, eb, 0, m, Win, s->PR, gp, pp, f, fc);
+      });
+    } else {
+      return fail(VCX_E_ARG, "no fused pass for this model");
+    }
   }
   static vcx_status grad(vcx_solver s, const double* Win, const GradCtl& gc) {
     const DevMesh& m = s->mesh->d;
@@ -295,16 +329,25 @@ struct Impl {
   }
   static vcx_status node_dt(vcx_solver s, const double* W) {
     const DevMesh& m = s->mesh->d;
-    DtParts parts = dt_parts(s);
     DtCoef dc = dt_coef(s->ph);
     MixParams mp = mix_params(s->ph);
+    hipLaunchKernelGGL(k_node_slots_clear, dim3(1), dim3(kCandSlots), 0, s->mesh->stream, s->lp);
+    VCX_HIP(hipGetLastError());
     return launch(s, "node_dt", [&](hipEvent_t ea, hipEvent_t eb) {
-      hipExtLaunchKernelGGL((k_node_dt<ND, NSP, MODEL>), dim3(s->n_dtp_node), dim3(kNodeBlock), 0,
-                         s->mesh->stream, ea, eb, 0, m, W, (const double*)s->E, dc, mp, parts, s->lp);
+      hipExtLaunchKernelGGL((k_node_dt<ND, NSP, MODEL>), dim3(s->node_blocks), dim3(kNodeBlock), 0,
+                         s->mesh->stream, ea, eb, 0, m, W, (const double*)s->E, dc, mp, s->lp);
     });
   }
   // Allow dynamic LDS above the 64 KiB default for the two tile kernels.
-  static vcx_status allow_lds(size_t grad_bytes, size_t flux_bytes) {
+  static vcx_status allow_lds(size_t grad_bytes, size_t flux_bytes, size_t fused_bytes) {
+    if constexpr (FUSABLE) {
+      if (fused_bytes > 0) {
+        VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fused<ND, NSP, MODEL, FLUX, CT>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)fused_bytes));
+        VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fused_batch<ND, NSP, MODEL, FLUX, CT>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)fused_bytes));
+      }
+    }
     VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_grad_tile<ND, NGF>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)grad_bytes));
     if constexpr (MODEL == 0)
@@ -332,7 +375,22 @@ struct Impl {
   // one RK stage of every solve of a batch: gradient, flux, shared-node update
   static vcx_status batch_stage(const BatchRun& br, hipStream_t stream, const BatchStage& st, bool prof) {
     vcx_solver s = br.lead;
-    FinishShared fs{dt_coef(s->ph), mix_params(s->ph), s->ph.closure};
+    FinishShared fs{dt_coef(s->ph), mix_params(s->ph), s->ph.closure, br.fused ? 1 : 0};
+    if constexpr (FUSABLE) {
+      if (br.fused) {
+        GasParams gp{s->ph.gamma, s->ph.beta, s->ph.entropy_fix, s->ph.limiter};
+        DDParams pp = dd_params(s->ph, 0.0);
+        VCX_TRY(launch_on(s, stream, prof, "flux", [&](hipEvent_t ea, hipEvent_t eb) {
+          hipExtLaunchKernelGGL((k_fused_batch<ND, NSP, MODEL, FLUX, CT>), dim3(xcd_grid(br.ntile_blocks)),
+                                dim3(br.tile_block), br.lds_flux, stream, ea, eb, 0, (const BatchEntry*)br.tab,
+                                (const int2*)br.tile_map, br.ntile_blocks, st, gp, pp, fs);
+        }));
+        return launch_on(s, stream, prof, "update", [&](hipEvent_t ea, hipEvent_t eb) {
+          hipExtLaunchKernelGGL((k_update_shared_batch<ND, NSP, MODEL>), dim3(br.nsh_blocks), dim3(kNodeBlock),
+                                0, stream, ea, eb, 0, (const BatchEntry*)br.tab, (const int2*)br.sh_map, st, fs);
+        });
+      }
+    }
     VCX_TRY(launch_on(s, stream, prof, "gradient", [&](hipEvent_t ea, hipEvent_t eb) {
       hipExtLaunchKernelGGL((k_grad_tile_batch<ND, NGF>), dim3(xcd_grid(br.ntile_blocks)),
                          dim3(br.tile_block), br.lds_grad, stream, ea, eb, 0, (const BatchEntry*)br.tab,
@@ -372,9 +430,9 @@ struct Impl {
     });
   }
   static const KernelTable* table() {
-    static const KernelTable t{&grad,      &grad_complete, &flux,        &update_shared, &node_dt,
-                               &lds_grad,  &lds_flux,      &allow_lds,   &aux,           &batch_stage,
-                               NW,         NGF};
+    static const KernelTable t{&grad,     &grad_complete, &flux,      &update_shared, &node_dt,
+                               &lds_grad, &lds_flux,      &lds_fused, &fused,         &allow_lds,
+                               &aux,      &batch_stage,   NW,         NGF};
     return &t;
   }
 };
@@ -519,6 +577,11 @@ extern "C" vcx_status vcx_mesh_create_tiled(int ndim, int64_t nnodes, const doub
   std::vector<int32_t> tile_inc(h.tile_slot.size()), slot_pos(h.slot_node.size());
   for (size_t t = 0; t < h.tile_slot.size(); ++t) tile_inc[t] = h.slot_inc[h.tile_slot[t]];
   for (size_t p = 0; p < h.slots_of.size(); ++p) slot_pos[h.slots_of[p]] = (int32_t)p;
+  std::vector<int32_t> tile_ginc;
+  if (h.has_halo) {
+    tile_ginc.resize(h.tile_slot.size());
+    for (size_t t = 0; t < h.tile_slot.size(); ++t) tile_ginc[t] = h.slot_ginc[h.tile_slot[t]];
+  }
   std::vector<int32_t> srun(2 * h.shared.size());
   for (size_t k = 0; k < h.shared.size(); ++k) {
     srun[2 * k] = h.node_slot[h.shared[k]];
@@ -553,6 +616,21 @@ extern "C" vcx_status vcx_mesh_create_tiled(int ndim, int64_t nnodes, const doub
     d.slot_run = reinterpret_cast<const int2*>(run);
   }
   d.nshared = (int)h.shared.size();
+  if (h.has_halo) {
+    d.has_halo = 1;
+    d.nhalo = (int)h.hshift.size();
+    d.max_ext_cells = h.max_ext_cells;
+    d.max_ext_nodes = h.max_ext_nodes;
+    d.max_tile_ginc = h.max_tile_ginc;
+    chk(upload(m, h.tile_hcell, &d.tile_hcell));
+    chk(upload(m, h.hlconn, &d.hlconn));
+    chk(upload(m, h.hshift, &d.hshift));
+    chk(upload(m, h.tile_hnode, &d.tile_hnode));
+    chk(upload(m, h.hnode, &d.hnode));
+    chk(upload(m, h.slot_ginc, &d.slot_ginc));
+    chk(upload(m, h.ginc, &d.ginc));
+    chk(upload(m, tile_ginc, &d.tile_ginc));
+  }
   chk(upload(m, inv, &d.inv_vol));
   chk(upload(m, h.vnode, &d.vnode));
   chk(upload(m, bidx, &d.bnd_index));
@@ -627,7 +705,7 @@ extern "C" vcx_status vcx_mesh_geometry(vcx_mesh m, double* Vn, double* Sb) {
 static void free_solver(vcx_solver s) {
   if (!s) return;
   for (double* p : {s->W[0], s->W[1], s->G, s->PG, s->PR, s->E, s->io, s->rbuf, s->part,
-                    s->sums_dev, s->dtp_node, s->dtp_step})
+                    s->sums_dev})
     if (p) (void)hipFree(p);
   if (s->lp) (void)hipFree(s->lp);
   if (s->sc_host) (void)hipHostFree(s->sc_host);
@@ -649,11 +727,11 @@ static bool same_scheme(const vcx_physics& a, const vcx_physics& b) {
 // for the footprint query used by admission control).
 struct SolverSizes {
   size_t W = 0, G = 0, PG = 0, PR = 0, io = 0, part = 0, sums = 0, E = 0;
-  int n_dtp_node = 0, nsh_blocks = 1, n_dtp_step = 0;
+  int node_blocks = 0, nsh_blocks = 1;
   size_t bytes() const {
     auto r = [](size_t n) { return sizeof(double) * std::max<size_t>(n, 1); };
     return 2 * r(W) + r(G) + r(PG) + r(PR) + 2 * r(io) + r(part) + r(sums) + (E ? r(E) : 0) +
-           r((size_t)n_dtp_node) + r(2 * (size_t)n_dtp_step) + sizeof(DevLoop);
+           sizeof(DevLoop);
   }
 };
 
@@ -668,9 +746,8 @@ static SolverSizes solver_sizes(const DevMesh& d, int nd, int nvar, int nr, int 
   z.part = (size_t)nr * 256;
   z.sums = (size_t)nr;
   z.E = model == VCX_MODEL_DRIFT_DIFFUSION ? (size_t)nd * nn : 0;
-  z.n_dtp_node = (int)((nn + kNodeBlock - 1) / kNodeBlock);
+  z.node_blocks = (int)((nn + kNodeBlock - 1) / kNodeBlock);
   z.nsh_blocks = std::max(1, (d.nshared + kNodeBlock - 1) / kNodeBlock);
-  z.n_dtp_step = d.ntiles + z.nsh_blocks;
   return z;
 }
 
@@ -688,6 +765,7 @@ static vcx_status reset_scalars(vcx_solver s, double t0, bool prime) {
   z.steps_left = -1;
   DevLoop l{};
   l.s[0] = l.s[1] = z;
+  for (int q = 0; q < kCandSlots; ++q) l.cand[0][q] = l.cand[1][q] = l.cnode[q] = cand_empty();
   *s->sc_host = z;
   VCX_HIP(hipMemcpyAsync(s->lp, &l, sizeof(DevLoop), hipMemcpyHostToDevice, s->mesh->stream));
   if (prime) VCX_TRY(s->kt->node_dt(s, s->W[s->cur]));
@@ -770,8 +848,13 @@ extern "C" vcx_status vcx_solver_create(vcx_mesh mesh, const vcx_physics* phys, 
                                std::to_string(mesh->lds_max) +
                                " B for this model; create the mesh with smaller tiles");
   }
-  if (std::max(s->lds_grad, s->lds_flux) > 65536) {
-    vcx_status st = kt->allow_lds(s->lds_grad, s->lds_flux);
+  // the fused gradient + flux pass where the mesh has extended tiles and
+  // they fit the device's LDS
+  s->lds_fused = kt->lds_fused(d);
+  s->fused = s->lds_fused > 0 && s->lds_fused <= (size_t)mesh->lds_max;
+  if (!s->fused) s->lds_fused = 0;
+  if (std::max({s->lds_grad, s->lds_flux, s->lds_fused}) > 65536) {
+    vcx_status st = kt->allow_lds(s->lds_grad, s->lds_flux, s->lds_fused);
     if (st != VCX_OK) {
       delete s;
       return st;
@@ -787,17 +870,15 @@ extern "C" vcx_status vcx_solver_create(vcx_mesh mesh, const vcx_physics* phys, 
   chk(dmalloc(&s->W[0], z.W));
   chk(dmalloc(&s->W[1], z.W));
   chk(dmalloc(&s->G, z.G));
+  if (s->fused && ph.model == VCX_MODEL_DRIFT_DIFFUSION && ph.closure && d.nb > 0) s->gout = s->G;
   chk(dmalloc(&s->PG, z.PG));
   chk(dmalloc(&s->PR, z.PR));
   chk(dmalloc(&s->io, z.io));
   chk(dmalloc(&s->rbuf, z.io));
   chk(dmalloc(&s->part, z.part));
   chk(dmalloc(&s->sums_dev, z.sums));
-  s->n_dtp_node = z.n_dtp_node;
+  s->node_blocks = z.node_blocks;
   s->nsh_blocks = z.nsh_blocks;
-  s->n_dtp_step = z.n_dtp_step;
-  chk(dmalloc(&s->dtp_node, (size_t)s->n_dtp_node));
-  chk(dmalloc(&s->dtp_step, 2 * (size_t)s->n_dtp_step));
   if (st == VCX_OK && hipMalloc(reinterpret_cast<void**>(&s->lp), sizeof(DevLoop)) != hipSuccess)
     st = fail(VCX_E_OOM, "hipMalloc failed");
   if (st == VCX_OK &&
@@ -877,7 +958,7 @@ extern "C" vcx_status vcx_state_download(vcx_solver s, double* U, int is_device)
 extern "C" vcx_status vcx_gradient(vcx_solver s, double* G, int is_device) {
   if (!s || !G) return fail(VCX_E_ARG, "NULL argument");
   if (!s->has_state) return fail(VCX_E_STATE, "no state uploaded");
-  GradCtl gc{nullptr, dt_parts(s), 0, 0};
+  GradCtl gc{nullptr, 0, 0};
   VCX_TRY(s->kt->grad(s, s->W[s->cur], gc));
   VCX_TRY(s->kt->grad_complete(s));
   return copy_out(s, s->G, (size_t)s->nr * s->nd, G, is_device);
@@ -891,6 +972,7 @@ static Finish make_finish(vcx_solver s) {
   f.dc = dt_coef(s->ph);
   f.mix = mix_params(s->ph);
   f.closure = s->ph.closure;
+  f.gfull = s->fused && s->gout != nullptr;
   return f;
 }
 
@@ -898,13 +980,18 @@ extern "C" vcx_status vcx_residual(vcx_solver s, double dt, double* r, int is_de
   if (!s || !r) return fail(VCX_E_ARG, "NULL argument");
   if (!s->has_state) return fail(VCX_E_STATE, "no state uploaded");
   const double* Win = s->W[s->cur];
-  GradCtl gc{nullptr, dt_parts(s), 0, 0};
-  VCX_TRY(s->kt->grad(s, Win, gc));
   Finish f = make_finish(s);
   f.Win = Win;
   f.rout = s->rbuf;
   f.residual_only = 1;
-  VCX_TRY(s->kt->flux(s, Win, f, dt));
+  if (s->fused) {
+    FusedCtl fc{nullptr, 0, 0, s->gout};
+    VCX_TRY(s->kt->fused(s, Win, f, fc, dt));
+  } else {
+    GradCtl gc{nullptr, 0, 0};
+    VCX_TRY(s->kt->grad(s, Win, gc));
+    VCX_TRY(s->kt->flux(s, Win, f, dt));
+  }
   VCX_TRY(s->kt->update_shared(s, f));
   return copy_out(s, s->rbuf, s->nvar, r, is_device);
 }
@@ -921,7 +1008,7 @@ extern "C" vcx_status vcx_timestep(vcx_solver s, double* dt) {
   if (!s || !dt) return fail(VCX_E_ARG, "NULL argument");
   if (!s->has_state) return fail(VCX_E_STATE, "no state uploaded");
   VCX_TRY(s->kt->node_dt(s, s->W[s->cur]));
-  hipLaunchKernelGGL(k_dt_query, dim3(1), dim3(256), 0, s->mesh->stream, s->lp, dt_parts(s));
+  hipLaunchKernelGGL(k_dt_query, dim3(1), dim3(256), 0, s->mesh->stream, s->lp);
   VCX_HIP(hipGetLastError());
   VCX_TRY(read_scalars(s));
   *dt = s->sc_host->dt_query;
@@ -957,18 +1044,27 @@ static vcx_status enqueue_step(vcx_solver s) {
   Finish f = make_finish(s);
   f.sc = &s->lp->s[par];
   f.found = &s->lp->found[par];
-  f.cand = s->dtp_step + (size_t)par * s->n_dtp_step;
+  f.cand = s->lp->cand[par];
   f.Un = Wn;
   f.Wout = Wk;
   for (int k = 1; k <= K; ++k) {
     const double* Win = k == 1 ? Wn : Wk;
-    GradCtl gc{s->lp, dt_parts(s), par, k == 1 ? 1 : 0};
-    VCX_TRY(s->kt->grad(s, Win, gc));
     // stage k of K uses alpha_{k+1}; the last one is the full update
     f.Win = Win;
     f.alpha = k < K ? RK_ALPHA[K][k + 1] : 1.0;
     f.final_stage = k == K ? 1 : 0;
-    VCX_TRY(s->kt->flux(s, Win, f, 0.0));
+    if (s->fused) {
+      // the first stage decides the step in every block; its shared-node
+      // pass rolls the candidate slots over
+      FusedCtl fc{s->lp, par, k == 1 ? 1 : 0, s->gout};
+      f.roll = k == 1 ? s->lp : nullptr;
+      f.roll_par = par;
+      VCX_TRY(s->kt->fused(s, Win, f, fc, 0.0));
+    } else {
+      GradCtl gc{s->lp, par, k == 1 ? 1 : 0};
+      VCX_TRY(s->kt->grad(s, Win, gc));
+      VCX_TRY(s->kt->flux(s, Win, f, 0.0));
+    }
     VCX_TRY(s->kt->update_shared(s, f));
   }
   s->cur = 1 - s->cur;
@@ -1079,8 +1175,8 @@ static BatchEntry entry_of(vcx_solver s) {
   e.PR = s->PR;
   e.E = s->E;
   e.lp = s->lp;
+  e.gout = s->gout;
   e.spar = s->spar;
-  e.parts = dt_parts(s);
   e.phase = s->cur;
   return e;
 }
@@ -1129,7 +1225,7 @@ vcx_status vcx::batch_set(BatchGroup* g, vcx_solver* ss, int n, const int* steps
   vcx_solver lead = ss[0];
   std::vector<BatchEntry> tab(n);
   std::vector<int2> tmap, smap;
-  size_t lg = 0, lf = 0;
+  size_t lg = 0, lf = 0, lfu = 0;
   int block = 64;
   g->steps0.resize(n);
   g->phase0.resize(n);
@@ -1146,11 +1242,14 @@ vcx_status vcx::batch_set(BatchGroup* g, vcx_solver* ss, int n, const int* steps
     for (int b = 0; b < s->nsh_blocks; ++b) smap.push_back(make_int2(i, b));
     lg = std::max(lg, s->lds_grad);
     lf = std::max(lf, s->lds_flux);
+    lfu = std::max(lfu, s->lds_fused);
     block = std::max(block, s->tile_block);
   }
+  const bool fused = lead->fused;
   const int lds_max = lead->mesh->lds_max;
-  if (lg > (size_t)lds_max || lf > (size_t)lds_max) return fail(VCX_E_ARG, "batch LDS footprint too large");
-  if (std::max(lg, lf) > 65536) VCX_TRY(lead->kt->allow_lds(lg, lf));
+  if (lg > (size_t)lds_max || lf > (size_t)lds_max || lfu > (size_t)lds_max)
+    return fail(VCX_E_ARG, "batch LDS footprint too large");
+  if (std::max({lg, lf, lfu}) > 65536) VCX_TRY(lead->kt->allow_lds(lg, lf, lfu));
   VCX_TRY(dev_array(&g->tab, &g->cap_tab, n));
   VCX_TRY(dev_array(&g->tend, &g->cap_tend, n));
   VCX_TRY(dev_array(&g->steps, &g->cap_steps, n));
@@ -1186,7 +1285,8 @@ vcx_status vcx::batch_set(BatchGroup* g, vcx_solver* ss, int n, const int* steps
   br.sh_map = g->sh_map;
   br.nsh_blocks = (int)smap.size();
   br.lds_grad = lg;
-  br.lds_flux = lf;
+  br.fused = fused;
+  br.lds_flux = fused ? lfu : lf;
   br.tile_block = std::min(256, block);
   if (g->graphs && !lead->prof) {
     hipGraph_t graph = nullptr;
@@ -1261,7 +1361,9 @@ vcx_status vcx::solver_footprint(vcx_mesh mesh, const vcx_physics* ph, size_t* b
   return VCX_OK;
 }
 
-bool vcx::batch_compatible(vcx_solver a, vcx_solver b) { return a->kt == b->kt && same_scheme(a->ph, b->ph); }
+bool vcx::batch_compatible(vcx_solver a, vcx_solver b) {
+  return a->kt == b->kt && a->fused == b->fused && same_scheme(a->ph, b->ph);
+}
 
 vcx_status vcx::set_error(vcx_status s, const char* msg) { return fail(s, msg ? msg : ""); }
 int vcx::mesh_ndim(vcx_mesh m) { return m ? m->h.nd : 0; }

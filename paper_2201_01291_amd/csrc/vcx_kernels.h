@@ -32,6 +32,11 @@ constexpr int NXCD = 8;  // MI355X: 8 accelerator complex dies, round-robin disp
 #define VCX_FLUX_BOUNDS __launch_bounds__(256)
 #endif
 
+// The fused drift-diffusion pass aims at four 256-thread blocks per CU (all
+// tiles of a 200k-cell mesh resident at once); the gas passes need their
+// registers more than the occupancy.
+#define VCX_FUSED_BOUNDS __launch_bounds__(256, (MODEL == 1 ? 4 : 1))
+
 struct DevMesh {
   int nd, nv, nn, nc, ntiles, nslots, nb, nshared;
   int max_tile_cells, max_tile_nodes;
@@ -53,6 +58,17 @@ struct DevMesh {
   const int2* slot_run;      // [P] [begin, end) of the slot's node run in slots_of
   const int32_t* shared;     // [nshared] nodes with more than one slot (ascending)
   const int2* shared_run;    // [nshared] [begin, end) of the shared node's run in slots_of
+  // extended tiles (2D meshes): halo cells and nodes of each tile, and the
+  // cells around each slot's node in ascending cell order (extended-local)
+  int has_halo, nhalo, max_ext_cells, max_ext_nodes, max_tile_ginc;
+  const int32_t* tile_hcell;  // [T+1]
+  const uint16_t* hlconn;     // [nv][nhalo]
+  const uint32_t* hshift;     // [nhalo]
+  const int32_t* tile_hnode;  // [T+1]
+  const int32_t* hnode;       // halo nodes (internal ids)
+  const int32_t* slot_ginc;   // [P+1]
+  const uint16_t* ginc;
+  const int32_t* tile_ginc;   // [T+1]
   const double* inv_vol;     // [nn]
   const double* vnode;       // [nn]
   const double* dxmin;       // [nn] smallest inscribed diameter of the cells around the node
@@ -76,6 +92,11 @@ struct DevScalars {
   long long steps; // committed steps
 };
 
+// Time-step candidates are posted by atomic minimum into a few slots (block
+// b into slot b mod kCandSlots), on an integer key that orders like the
+// double, so that a reader takes the minimum of kCandSlots values.
+constexpr int kCandSlots = 64;
+
 // The time loop of a solve.  Steps alternate between two parities: a step
 // of parity p decides from the state s[p ^ 1] (the previous step's, or the
 // one set up by the host) into s[p], raises failures in found[p] and posts
@@ -85,15 +106,25 @@ struct DevLoop {
   DevScalars s[2];
   int found[2];   // failures (1: unstable state) raised by a step's final stage
   int pad[2];
+  long long cand[2][kCandSlots];  // candidates of each parity's new state
+  long long cnode[kCandSlots];    // candidates of the node pass (after an upload or a query)
 };
 
-// dt candidate buffers (one minimum per block of the producing kernel)
-struct DtParts {
-  double* node;   // k_node_dt: one per 256 nodes
-  int nnode;
-  double* step;   // [2][nstep] by parity: one per tile, then one per shared-update block
-  int nstep;
-};
+__host__ __device__ constexpr long long cand_empty() { return 0x7FF0000000000000ll; }  // +infinity
+
+__device__ inline long long cand_key(double v) {
+  const long long b = __double_as_longlong(v);
+  return b >= 0 ? b : (b ^ 0x7FFFFFFFFFFFFFFFll);
+}
+
+__device__ inline double key_cand(long long k) {
+  return __longlong_as_double(k >= 0 ? k : (k ^ 0x7FFFFFFFFFFFFFFFll));
+}
+
+__device__ inline void post_candidate(long long* slots, int b, double v) {
+  __hip_atomic_fetch_min(&slots[b & (kCandSlots - 1)], cand_key(v), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // ---------------------------------------------------------------------------
 // helpers
@@ -275,26 +306,39 @@ __device__ inline void step_decide(const DevScalars& prev, int found_prev, doubl
 }
 
 // Smallest candidate of the state a step of parity par starts from
-// (block-wide; valid in thread 0).
-__device__ inline double step_candidate(const DevLoop* lp, int par, const DtParts& parts) {
-  const DevScalars& prev = lp->s[par ^ 1];
-  const double* p = prev.dt_src ? parts.step + (size_t)(par ^ 1) * parts.nstep : parts.node;
-  const int np = prev.dt_src ? parts.nstep : parts.nnode;
-  double v = INFINITY;
-  for (int q = threadIdx.x; q < np; q += blockDim.x) v = fmin(v, p[q]);
+// (block-wide, at least kCandSlots threads; valid in thread 0).
+__device__ inline double step_candidate(const DevLoop* lp, int par) {
+  const long long* slots = lp->s[par ^ 1].dt_src ? lp->cand[par ^ 1] : lp->cnode;
+  const double v = threadIdx.x < kCandSlots ? key_cand(slots[threadIdx.x]) : INFINITY;
   return block_min(v);
 }
 
+// After the step of parity par has been decided (and before it posts): the
+// candidates of the state it started from move on to parity par when the
+// step does no work (the state stays the same), and the previous parity's
+// slots and failures are emptied for the next step.  So after every step of
+// parity q, cand[q] holds the current state's candidates and cand[q ^ 1] is
+// empty.
+__device__ inline void step_rollover(DevLoop* lp, int par, int active) {
+  if (threadIdx.x < kCandSlots) {
+    if (!active) lp->cand[par][threadIdx.x] = lp->cand[par ^ 1][threadIdx.x];
+    lp->cand[par ^ 1][threadIdx.x] = cand_empty();
+  }
+  if (threadIdx.x == 0) lp->found[par ^ 1] = 0;
+}
+
 // One block decides the step of parity par and writes its state.
-__device__ inline void step_start(DevLoop* lp, int par, const DtParts& parts) {
-  const double d = step_candidate(lp, par, parts);
+__device__ inline void step_start(DevLoop* lp, int par) {
+  const double d = step_candidate(lp, par);
+  __shared__ int act;
   if (threadIdx.x == 0) {
     DevScalars n;
     step_decide(lp->s[par ^ 1], lp->found[par ^ 1], d, n);
     lp->s[par] = n;
-    lp->found[par ^ 1] = 0;
+    act = n.active;
   }
   __syncthreads();
+  step_rollover(lp, par, act);
 }
 
 // Commit the pending step of the state of parity par (end of a host call).
@@ -385,7 +429,6 @@ __device__ inline double ns_node_dt(double dx, const DtCoef& c, const MixParams&
 
 struct GradCtl {
   DevLoop* lp;     // null outside the time loop
-  DtParts parts;
   int par;         // parity of the step
   int first_stage; // first stage: an extra block decides the step
 };
@@ -490,7 +533,7 @@ __global__ void __launch_bounds__(256) k_grad_tile(DevMesh m, const double* __re
   // and commits (the tiles take the other blocks, so that no tile waits on it)
   const int lead = ctl.lp && ctl.first_stage ? 1 : 0;
   if (lead && blockIdx.x == 0) {
-    step_start(ctl.lp, ctl.par, ctl.parts);
+    step_start(ctl.lp, ctl.par);
     return;
   }
   const int t = xcd_tile_of((int)blockIdx.x - lead, m.ntiles);
@@ -600,7 +643,10 @@ struct Finish {
   const double* E;      // field (drift-diffusion)
   DevScalars* sc;       // state of the running step; null: residual only
   int* found;           // failures raised by this step
-  double* cand;         // time-step candidates of this step's new state
+  long long* cand;      // candidate slots of this step's new state
+  DevLoop* roll;        // fused passes: the shared-node pass of the first stage rolls the
+  int roll_par;         //   candidate slots over (step_rollover) for this parity
+  int gfull;            // G holds the gradients of shared nodes too (fused passes)
   DtCoef dc;
   MixParams mix;        // Navier-Stokes species data
   double alpha;
@@ -618,11 +664,12 @@ struct NodeIn {
 };
 
 template <int ND, int MODEL, int NVAR>
-__device__ inline void node_in_load(const DevMesh& m, const Finish& f, int i, NodeIn<NVAR, ND>& ni) {
+__device__ inline void node_in_load(const DevMesh& m, const Finish& f, double dt, int i,
+                                    NodeIn<NVAR, ND>& ni) {
   if (f.residual_only) return;
 #pragma unroll
   for (int v = 0; v < NVAR; ++v) ni.Un[v] = f.Un[(size_t)v * m.nn + i];
-  ni.fac = f.alpha * f.sc->dt * m.inv_vol[i];
+  ni.fac = f.alpha * dt * m.inv_vol[i];
   ni.dx = m.dxmin[i];
   if constexpr (MODEL == 1) {
 #pragma unroll
@@ -658,7 +705,7 @@ __device__ inline double finish_node(const DevMesh& m, const Finish& f, int i, b
       } else {
         // convective plus diffusive node flux
         double gr[NSP * ND];
-        if (shared) {
+        if (shared && !f.gfull) {
           shared_gradient<NSP * ND, ND>(m, f.PG, i, make_int2(m.node_slot[i], m.node_slot[i + 1]), gr);
         } else {
 #pragma unroll
@@ -730,47 +777,38 @@ struct GasParams {
   int limiter;
 };
 
-template <int ND, int NSP, int FLUX, typename CT>
-__device__ inline void flux_gas_body(DevMesh m, const double* __restrict__ W,
-                                                  const double* __restrict__ G,
-                                                  double* __restrict__ PR, GasParams gp, Finish f, int t, double* lds) {
-  constexpr int NV = ND + 1, NVAR = 2 + ND + NSP, NR = NVAR + 1, NE = Edges<ND>::NE;
-  if (step_inactive(f.sc)) return;
-  TilePre<NV> tp;
-  tile_prefetch<NV>(m, t, tp);
-  const int maxn = m.max_tile_nodes, maxc = m.max_tile_cells;
-  double* sX = lds;                       // [ND][maxn]
-  double* sR = sX + ND * maxn;            // [NV*NVAR][maxc]
-  CT* sW = reinterpret_cast<CT*>(sR + NV * NVAR * maxc);  // [NR][maxn]
-  CT* sG = sW + NR * maxn;                // [NR*ND][maxn]
-  int* sSl = reinterpret_cast<int*>(sG + NR * ND * maxn);
-  uint16_t* sInc = reinterpret_cast<uint16_t*>(sSl + 4 * maxn);
-  const int nc = tp.nc, ns = tp.ns;
-  for (int q = threadIdx.x; q < ns; q += blockDim.x) {
-    const SlotTopo st = slot_topo<NV>(m, tp, q);
-    slot_table_put(sSl, maxn, q, st.sv, st.pos, st.p0, st.p1);
-    const int sv = st.sv;
-    const int g = slot_node_id(sv);
-    double w[NR], xx[ND];
-#pragma unroll
-    for (int v = 0; v < NR; ++v) w[v] = W[(size_t)v * m.nn + g];
-#pragma unroll
-    for (int d = 0; d < ND; ++d) xx[d] = m.x[(size_t)d * m.nn + g];
-    stage_gradient<NR * ND, ND, CT>(m, G, f.PG, sv, st.run, sG, maxn, q);
-#pragma unroll
-    for (int v = 0; v < NR; ++v) sW[v * maxn + q] = CT(w[v]);
-#pragma unroll
-    for (int d = 0; d < ND; ++d) sX[d * maxn + q] = xx[d];
-  }
-  tile_store_inc<NV>(m, tp, sInc);
-  __syncthreads();
+// ---------------------------------------------------------------------------
+// drift-diffusion parameters (limited Lax-Wendroff + central diffusion)
+// ---------------------------------------------------------------------------
+
+struct DDParams {
+  double zmu[4];   // z * mu per species
+  double D[4];
+  double beta;
+  double dt_host;  // residual only
+  int limiter;
+};
+
+// LDS strides of the arrays read by the cell flux loops: coordinates (ldx),
+// reconstructed rows (ldw), gradients and field (ldg), cell accumulators (ldc)
+struct CellLd {
+  int ldx, ldw, ldg, ldc;
+};
+
+// Gas fluxes of the tile's cells: MUSCL with virtual upwind nodes, slope
+// limiter, HLLC or Roe; accumulated per cell vertex into sR.
+template <int ND, int NSP, int FLUX, typename CT, int NV>
+__device__ inline void gas_cell_fluxes(const DevMesh& m, const TilePre<NV>& tp, const double* sX,
+                                       const CT* sW, const CT* sG, double* sR, CellLd L,
+                                       const GasParams& gp) {
+  constexpr int NVAR = 2 + ND + NSP, NR = NVAR + 1, NE = Edges<ND>::NE;
   const CT gamma = CT(gp.gamma), beta = CT(gp.beta), fix = CT(gp.entropy_fix);
-  for (int lc = threadIdx.x; lc < nc; lc += blockDim.x) {
+  for (int lc = threadIdx.x; lc < tp.nc; lc += blockDim.x) {
     int l[NV];
     uint32_t sh;
     cell_topo<NV>(m, tp, lc, l, sh);
     double e[ND][ND], Sd[NV][ND];
-    cell_rel_coords<ND>(m, sX, maxn, l, sh, e);
+    cell_rel_coords<ND>(m, sX, L.ldx, l, sh, e);
     simplex_normals<ND>(e, Sd);
     double acc[NV][NVAR];
 #pragma unroll
@@ -790,12 +828,12 @@ __device__ inline void flux_gas_body(DevMesh m, const double* __restrict__ W,
       CT WL[NR], WR[NR];
 #pragma unroll
       for (int v = 0; v < NR; ++v) {
-        const CT wi = sW[v * maxn + la], wj = sW[v * maxn + lb];
+        const CT wi = sW[v * L.ldw + la], wj = sW[v * L.ldw + lb];
         CT gi = CT(0), gj = CT(0);
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
-          gi += sG[(v * ND + d) * maxn + la] * dx[d];
-          gj += sG[(v * ND + d) * maxn + lb] * dx[d];
+          gi += sG[(v * ND + d) * L.ldg + la] * dx[d];
+          gj += sG[(v * ND + d) * L.ldg + lb] * dx[d];
         }
         const CT delta = wj - wi;
         // virtual upwind nodes l (behind i) and k (ahead of j)
@@ -817,14 +855,92 @@ __device__ inline void flux_gas_body(DevMesh m, const double* __restrict__ W,
 #pragma unroll
     for (int k = 0; k < NV; ++k)
 #pragma unroll
-      for (int v = 0; v < NVAR; ++v) sR[(k * NVAR + v) * maxc + lc] = acc[k][v];
+      for (int v = 0; v < NVAR; ++v) sR[(k * NVAR + v) * L.ldc + lc] = acc[k][v];
   }
-  __syncthreads();
+}
+
+// Drift-diffusion fluxes of the tile's cells: limited Lax-Wendroff
+// convective flux (upwind node w, downwind node m, virtual node upwind of w)
+// plus central diffusion; accumulated per cell vertex into sR.
+template <int ND, int NS, typename CT, int NV>
+__device__ inline void dd_cell_fluxes(const DevMesh& m, const TilePre<NV>& tp, const double* sX,
+                                      const CT* sU, const CT* sG, const CT* sE, double* sR, CellLd L,
+                                      CT dt, const DDParams& pp) {
+  constexpr int NE = Edges<ND>::NE;
+  const CT beta = CT(pp.beta);
+  for (int lc = threadIdx.x; lc < tp.nc; lc += blockDim.x) {
+    int l[NV];
+    uint32_t sh;
+    cell_topo<NV>(m, tp, lc, l, sh);
+    double e[ND][ND], Sd[NV][ND];
+    cell_rel_coords<ND>(m, sX, L.ldx, l, sh, e);
+    simplex_normals<ND>(e, Sd);
+    double acc[NV][NS];
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+#pragma unroll
+      for (int s = 0; s < NS; ++s) acc[k][s] = 0.0;
+#pragma unroll
+    for (int ed = 0; ed < NE; ++ed) {
+      const int a = Edges<ND>::a(ed), b = Edges<ND>::b(ed);
+      const int la = l[a], lb = l[b];
+      CT S[ND], dx[ND], Ebar[ND];
+#pragma unroll
+      for (int d = 0; d < ND; ++d) {
+        S[d] = CT((Sd[a][d] - Sd[b][d]) * (1.0 / double(ND * NV)));
+        dx[d] = CT((a == 0 ? 0.0 : -e[a - 1][d]) + e[b - 1][d]);
+        Ebar[d] = CT(0.5) * (sE[d * L.ldg + la] + sE[d * L.ldg + lb]);
+      }
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const CT zm = CT(pp.zmu[s]);
+        CT v = CT(0), gV = CT(0), gS = CT(0), gA = CT(0), gB = CT(0);
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+          const CT Vd = zm * Ebar[d];
+          const CT ga = sG[(s * ND + d) * L.ldg + la], gb = sG[(s * ND + d) * L.ldg + lb];
+          const CT gbar = CT(0.5) * (ga + gb);
+          v += Vd * S[d];
+          gV += gbar * Vd;
+          gS += gbar * S[d];
+          gA += ga * dx[d];
+          gB += gb * dx[d];
+        }
+        const CT ua = sU[s * L.ldw + la], ub = sU[s * L.ldw + lb];
+        // upwind node w, downwind node m; the virtual node upwind of w
+        const bool fwd = v >= CT(0);
+        const CT uw = fwd ? ua : ub;
+        const CT bb = fwd ? (ub - ua) : (ua - ub);
+        const CT gw = fwd ? gA : -gB;
+        const CT aa = CT(2) * gw - bb;
+        const CT psi = psi_limit<CT>(pp.limiter, beta, aa, bb);
+        const CT uf = uw + (CT(0.5) * bb - CT(0.5) * dt * gV) * psi;
+        const CT F = uf * v - CT(pp.D[s]) * gS;
+        acc[a][s] += double(F);
+        acc[b][s] -= double(F);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+#pragma unroll
+      for (int s = 0; s < NS; ++s) sR[(k * NS + s) * L.ldc + lc] = acc[k][s];
+  }
+}
+
+// Node pass of a tile: residual sums of each slot over its incidences in a
+// fixed order; a tile-owned node is finished (stage update, time-step
+// candidate), a shared node's partial is stored at its partial index.
+// Returns this thread's smallest candidate.
+template <int ND, int NSP, int MODEL, int NVAR>
+__device__ inline double tile_node_pass(const DevMesh& m, const Finish& f, double dt, double* PR, int ns,
+                                        const int* sSl, int ldsl, const uint16_t* sInc, const double* sR,
+                                        int ldc) {
   double cand = INFINITY;
   for (int q = threadIdx.x; q < ns; q += blockDim.x) {
-    const SlotTopo st = slot_table_get(sSl, maxn, q);
+    const SlotTopo st = slot_table_get(sSl, ldsl, q);
+    // update inputs first: their loads overlap the sums
     NodeIn<NVAR, ND> nq;
-    if (st.sv >= 0) node_in_load<ND, 0, NVAR>(m, f, st.sv, nq);
+    if (st.sv >= 0) node_in_load<ND, MODEL, NVAR>(m, f, dt, st.sv, nq);
     double r[NVAR];
 #pragma unroll
     for (int v = 0; v < NVAR; ++v) r[v] = 0.0;
@@ -832,18 +948,60 @@ __device__ inline void flux_gas_body(DevMesh m, const double* __restrict__ W,
       const int code = sInc[p];
       const int lc = code >> 2, k = code & 3;
 #pragma unroll
-      for (int v = 0; v < NVAR; ++v) r[v] += sR[(k * NVAR + v) * maxc + lc];
+      for (int v = 0; v < NVAR; ++v) r[v] += sR[(k * NVAR + v) * ldc + lc];
     }
     if (st.sv >= 0) {
-      cand = fmin(cand, finish_node<ND, NSP, 0, NVAR>(m, f, st.sv, false, r, nq));
+      cand = fmin(cand, finish_node<ND, NSP, MODEL, NVAR>(m, f, st.sv, false, r, nq));
     } else {
 #pragma unroll
       for (int v = 0; v < NVAR; ++v) PR[(size_t)st.pos * NVAR + v] = r[v];
     }
   }
+  return cand;
+}
+
+template <int ND, int NSP, int FLUX, typename CT>
+__device__ inline void flux_gas_body(DevMesh m, const double* __restrict__ W,
+                                                  const double* __restrict__ G,
+                                                  double* __restrict__ PR, GasParams gp, Finish f,
+                                                  int t, double* lds) {
+  constexpr int NV = ND + 1, NVAR = 2 + ND + NSP, NR = NVAR + 1;
+  if (step_inactive(f.sc)) return;
+  TilePre<NV> tp;
+  tile_prefetch<NV>(m, t, tp);
+  const int maxn = m.max_tile_nodes, maxc = m.max_tile_cells;
+  double* sX = lds;                       // [ND][maxn]
+  double* sR = sX + ND * maxn;            // [NV*NVAR][maxc]
+  CT* sW = reinterpret_cast<CT*>(sR + NV * NVAR * maxc);  // [NR][maxn]
+  CT* sG = sW + NR * maxn;                // [NR*ND][maxn]
+  int* sSl = reinterpret_cast<int*>(sG + NR * ND * maxn);
+  uint16_t* sInc = reinterpret_cast<uint16_t*>(sSl + 4 * maxn);
+  const int ns = tp.ns;
+  for (int q = threadIdx.x; q < ns; q += blockDim.x) {
+    const SlotTopo st = slot_topo<NV>(m, tp, q);
+    slot_table_put(sSl, maxn, q, st.sv, st.pos, st.p0, st.p1);
+    const int sv = st.sv;
+    const int g = slot_node_id(sv);
+    double w[NR], xx[ND];
+#pragma unroll
+    for (int v = 0; v < NR; ++v) w[v] = W[(size_t)v * m.nn + g];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) xx[d] = m.x[(size_t)d * m.nn + g];
+    stage_gradient<NR * ND, ND, CT>(m, G, f.PG, sv, st.run, sG, maxn, q);
+#pragma unroll
+    for (int v = 0; v < NR; ++v) sW[v * maxn + q] = CT(w[v]);
+#pragma unroll
+    for (int d = 0; d < ND; ++d) sX[d * maxn + q] = xx[d];
+  }
+  tile_store_inc<NV>(m, tp, sInc);
+  __syncthreads();
+  gas_cell_fluxes<ND, NSP, FLUX, CT, NV>(m, tp, sX, sW, sG, sR, CellLd{maxn, maxn, maxn, maxc}, gp);
+  __syncthreads();
+  const double dt = f.sc ? f.sc->dt : 0.0;
+  const double cand = tile_node_pass<ND, NSP, 0, NVAR>(m, f, dt, PR, ns, sSl, maxn, sInc, sR, maxc);
   if (f.final_stage && f.sc) {
     const double b = block_min(cand);
-    if (threadIdx.x == 0) f.cand[t] = b;
+    if (threadIdx.x == 0) post_candidate(f.cand, t, b);
   }
 }
 
@@ -858,22 +1016,15 @@ __global__ void VCX_FLUX_BOUNDS k_flux_gas(DevMesh m, const double* __restrict__
 }
 
 // ---------------------------------------------------------------------------
-// drift-diffusion flux pass (limited Lax-Wendroff + central diffusion)
+// drift-diffusion flux pass
 // ---------------------------------------------------------------------------
-
-struct DDParams {
-  double zmu[4];   // z * mu per species
-  double D[4];
-  double beta;
-  double dt_host;  // residual only
-  int limiter;
-};
 
 template <int ND, int NS, typename CT>
 __device__ inline void flux_dd_body(DevMesh m, const double* __restrict__ U,
                                                  const double* __restrict__ G,
-                                                 double* __restrict__ PR, DDParams pp, Finish f, int t, double* lds) {
-  constexpr int NV = ND + 1, NE = Edges<ND>::NE;
+                                                 double* __restrict__ PR, DDParams pp, Finish f,
+                                                 int t, double* lds) {
+  constexpr int NV = ND + 1;
   if (step_inactive(f.sc)) return;
   TilePre<NV> tp;
   tile_prefetch<NV>(m, t, tp);
@@ -886,7 +1037,7 @@ __device__ inline void flux_dd_body(DevMesh m, const double* __restrict__ U,
   int* sSl = reinterpret_cast<int*>(sE + ND * maxn);
   uint16_t* sInc = reinterpret_cast<uint16_t*>(sSl + 4 * maxn);
   const double* E = f.E;
-  const int nc = tp.nc, ns = tp.ns;
+  const int ns = tp.ns;
   for (int q = threadIdx.x; q < ns; q += blockDim.x) {
     const SlotTopo st = slot_topo<NV>(m, tp, q);
     slot_table_put(sSl, maxn, q, st.sv, st.pos, st.p0, st.p1);
@@ -911,91 +1062,13 @@ __device__ inline void flux_dd_body(DevMesh m, const double* __restrict__ U,
   }
   tile_store_inc<NV>(m, tp, sInc);
   __syncthreads();
-  const CT dt = CT(f.sc ? f.sc->dt : pp.dt_host);
-  const CT beta = CT(pp.beta);
-  for (int lc = threadIdx.x; lc < nc; lc += blockDim.x) {
-    int l[NV];
-    uint32_t sh;
-    cell_topo<NV>(m, tp, lc, l, sh);
-    double e[ND][ND], Sd[NV][ND];
-    cell_rel_coords<ND>(m, sX, maxn, l, sh, e);
-    simplex_normals<ND>(e, Sd);
-    double acc[NV][NS];
-#pragma unroll
-    for (int k = 0; k < NV; ++k)
-#pragma unroll
-      for (int s = 0; s < NS; ++s) acc[k][s] = 0.0;
-#pragma unroll
-    for (int ed = 0; ed < NE; ++ed) {
-      const int a = Edges<ND>::a(ed), b = Edges<ND>::b(ed);
-      const int la = l[a], lb = l[b];
-      CT S[ND], dx[ND], Ebar[ND];
-#pragma unroll
-      for (int d = 0; d < ND; ++d) {
-        S[d] = CT((Sd[a][d] - Sd[b][d]) * (1.0 / double(ND * NV)));
-        dx[d] = CT((a == 0 ? 0.0 : -e[a - 1][d]) + e[b - 1][d]);
-        Ebar[d] = CT(0.5) * (sE[d * maxn + la] + sE[d * maxn + lb]);
-      }
-#pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        const CT zm = CT(pp.zmu[s]);
-        CT v = CT(0), gV = CT(0), gS = CT(0), gA = CT(0), gB = CT(0);
-#pragma unroll
-        for (int d = 0; d < ND; ++d) {
-          const CT Vd = zm * Ebar[d];
-          const CT ga = sG[(s * ND + d) * maxn + la], gb = sG[(s * ND + d) * maxn + lb];
-          const CT gbar = CT(0.5) * (ga + gb);
-          v += Vd * S[d];
-          gV += gbar * Vd;
-          gS += gbar * S[d];
-          gA += ga * dx[d];
-          gB += gb * dx[d];
-        }
-        const CT ua = sU[s * maxn + la], ub = sU[s * maxn + lb];
-        // upwind node w, downwind node m; the virtual node upwind of w
-        const bool fwd = v >= CT(0);
-        const CT uw = fwd ? ua : ub;
-        const CT bb = fwd ? (ub - ua) : (ua - ub);
-        const CT gw = fwd ? gA : -gB;
-        const CT aa = CT(2) * gw - bb;
-        const CT psi = psi_limit<CT>(pp.limiter, beta, aa, bb);
-        const CT uf = uw + (CT(0.5) * bb - CT(0.5) * dt * gV) * psi;
-        const CT F = uf * v - CT(pp.D[s]) * gS;
-        acc[a][s] += double(F);
-        acc[b][s] -= double(F);
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < NV; ++k)
-#pragma unroll
-      for (int s = 0; s < NS; ++s) sR[(k * NS + s) * maxc + lc] = acc[k][s];
-  }
+  const double dt = f.sc ? f.sc->dt : pp.dt_host;
+  dd_cell_fluxes<ND, NS, CT, NV>(m, tp, sX, sU, sG, sE, sR, CellLd{maxn, maxn, maxn, maxc}, CT(dt), pp);
   __syncthreads();
-  double cand = INFINITY;
-  for (int q = threadIdx.x; q < ns; q += blockDim.x) {
-    const SlotTopo st = slot_table_get(sSl, maxn, q);
-    // update inputs first: their loads overlap the sums
-    NodeIn<NS, ND> nq;
-    if (st.sv >= 0) node_in_load<ND, 1, NS>(m, f, st.sv, nq);
-    double r[NS];
-#pragma unroll
-    for (int s = 0; s < NS; ++s) r[s] = 0.0;
-    for (int p = st.p0; p < st.p1; ++p) {
-      const int code = sInc[p];
-      const int lc = code >> 2, k = code & 3;
-#pragma unroll
-      for (int s = 0; s < NS; ++s) r[s] += sR[(k * NS + s) * maxc + lc];
-    }
-    if (st.sv >= 0) {
-      cand = fmin(cand, finish_node<ND, NS, 1, NS>(m, f, st.sv, false, r, nq));
-    } else {
-#pragma unroll
-      for (int s = 0; s < NS; ++s) PR[(size_t)st.pos * NS + s] = r[s];
-    }
-  }
+  const double cand = tile_node_pass<ND, NS, 1, NS>(m, f, dt, PR, ns, sSl, maxn, sInc, sR, maxc);
   if (f.final_stage && f.sc) {
     const double b = block_min(cand);
-    if (threadIdx.x == 0) f.cand[t] = b;
+    if (threadIdx.x == 0) post_candidate(f.cand, t, b);
   }
 }
 
@@ -1007,6 +1080,270 @@ __global__ void VCX_FLUX_BOUNDS k_flux_dd(DevMesh m, const double* __restrict__ 
   const int t = xcd_tile(m.ntiles);
   if (t >= m.ntiles) return;
   flux_dd_body<ND, NS, CT>(m, U, G, PR, pp, f, t, lds);
+}
+
+// ---------------------------------------------------------------------------
+// fused gradient + flux pass over extended tiles (2D meshes): the tile's
+// slots and halo nodes are staged, the gradient contributions of the tile's
+// cells and halo cells are formed, every slot node's gradient is summed over
+// all its cells in ascending cell order (so every tile forms the same sum for
+// a shared node), and the flux and node passes follow in the same launch.
+// In the first stage of a step every block decides the step itself from the
+// previous parity's state; the block of tile 0 stores the decision.
+// ---------------------------------------------------------------------------
+
+struct FusedCtl {
+  DevLoop* lp;     // null outside the time loop
+  int par;         // parity of the step
+  int first_stage;
+  double* Gout;    // gradients of the slot nodes (drift-diffusion boundary closure) or null
+};
+
+template <int MODEL, int NSP, int ND>
+struct FusedDims {
+  static constexpr int NVAR = MODEL == 1 ? NSP : 2 + ND + NSP;
+  static constexpr int NGF = MODEL == 1 ? NSP : NVAR + 1;  // rows with gradients
+  static constexpr int NC = NGF * ND;
+};
+
+// LDS bytes of the fused pass
+template <int ND, int NSP, int MODEL, typename CT>
+__host__ __device__ inline size_t fused_lds_bytes(int maxn, int maxc, int maxne, int maxce, int maxgi) {
+  using D = FusedDims<MODEL, NSP, ND>;
+  constexpr int NV = ND + 1;
+  const size_t cr = (size_t)D::NC * maxce > (size_t)NV * D::NVAR * maxc ? (size_t)D::NC * maxce
+                                                                         : (size_t)NV * D::NVAR * maxc;
+  size_t b = sizeof(double) * ((size_t)ND * maxne + (size_t)D::NGF * maxne + cr);
+  b += sizeof(CT) * ((size_t)D::NC * maxn + (sizeof(CT) == sizeof(double) ? 0 : (size_t)D::NGF * maxn) +
+                     (MODEL == 1 ? (size_t)ND * maxn : 0));
+  b = (b + 7) / 8 * 8;
+  b += slot_lds_bytes(maxn) + inc_lds_bytes(NV, maxc) + ((size_t)maxgi * sizeof(uint16_t) + 7) / 8 * 8;
+  return b;
+}
+
+// Stage n 16-bit values to LDS: up to K per thread loaded before any store.
+template <int K>
+__device__ inline void stage_u16(const uint16_t* __restrict__ src, int n, uint16_t* dst) {
+  uint16_t v[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const int p = (int)threadIdx.x + j * (int)blockDim.x;
+    if (p < n) v[j] = src[p];
+  }
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const int p = (int)threadIdx.x + j * (int)blockDim.x;
+    if (p < n) dst[p] = v[j];
+  }
+  for (int p = (int)threadIdx.x + K * (int)blockDim.x; p < n; p += blockDim.x) dst[p] = src[p];
+}
+
+template <int ND, int NSP, int MODEL, int FLUX, typename CT>
+__device__ inline void fused_body(DevMesh m, const double* __restrict__ W, double* __restrict__ PR,
+                                  GasParams gp, DDParams pp, Finish f, FusedCtl fc, int t, double* lds) {
+  using D = FusedDims<MODEL, NSP, ND>;
+  constexpr int NV = ND + 1, NVAR = D::NVAR, NGF = D::NGF, NC = D::NC;
+  constexpr bool WCOPY = sizeof(CT) != sizeof(double);
+  // the step: decided here in its first stage, read from its state after
+  __shared__ double s_dt;
+  __shared__ int s_act;
+  const bool loop = fc.lp != nullptr;
+  if (loop && fc.first_stage) {
+    const double d = step_candidate(fc.lp, fc.par);
+    if (threadIdx.x == 0) {
+      DevScalars n;
+      step_decide(fc.lp->s[fc.par ^ 1], fc.lp->found[fc.par ^ 1], d, n);
+      if (t == 0) fc.lp->s[fc.par] = n;
+      s_dt = n.dt;
+      s_act = n.active;
+    }
+    __syncthreads();
+    if (!s_act) return;
+  } else if (loop && fc.lp->s[fc.par].active == 0) {
+    return;
+  } else if (threadIdx.x == 0) {
+    s_dt = loop ? fc.lp->s[fc.par].dt : pp.dt_host;
+  }
+  // (the step size is read from LDS where it is used, not held in registers)
+
+  TilePre<NV> tp;
+  tile_prefetch<NV>(m, t, tp);
+  const int hc0 = m.tile_hcell[t], nhc = m.tile_hcell[t + 1] - hc0;
+  const int hn0 = m.tile_hnode[t], nhn = m.tile_hnode[t + 1] - hn0;
+  const int gb = m.tile_ginc[t], ngi = m.tile_ginc[t + 1] - gb;
+  const int nc = tp.nc, ns = tp.ns, nce = nc + nhc;
+  const int maxn = m.max_tile_nodes, maxc = m.max_tile_cells;
+  const int maxne = m.max_ext_nodes, maxce = m.max_ext_cells;
+  double* sX = lds;                                  // [ND][maxne]
+  double* sWd = sX + ND * maxne;                     // [NGF][maxne]
+  double* sCR = sWd + NGF * maxne;                   // gradient parts [NC][maxce], then residual parts
+  const size_t ncr = (size_t)NC * maxce > (size_t)NV * NVAR * maxc ? (size_t)NC * maxce : (size_t)NV * NVAR * maxc;
+  CT* sG = reinterpret_cast<CT*>(sCR + ncr);         // [NC][maxn]
+  CT* sWc = sG + NC * maxn;                          // [NGF][maxn] when CT is not double
+  CT* sE = sWc + (WCOPY ? NGF * maxn : 0);           // [ND][maxn] drift-diffusion field
+  size_t off = (size_t)(sE + (MODEL == 1 ? ND * maxn : 0)) - (size_t)lds;
+  off = (off + 7) / 8 * 8;
+  int* sSl = reinterpret_cast<int*>(reinterpret_cast<char*>(lds) + off);
+  uint16_t* sInc = reinterpret_cast<uint16_t*>(sSl + 4 * maxn);
+  uint16_t* sGi = sInc + (inc_lds_bytes(NV, maxc) / sizeof(uint16_t));
+
+  // halo cell topology of this thread's first two extended cells
+  const int H = m.nhalo;
+  int hl[2][NV];
+  uint32_t hsh[2] = {0u, 0u};
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int h = (int)threadIdx.x + j * (int)blockDim.x - nc;
+    if (h >= 0 && h < nhc) {
+#pragma unroll
+      for (int k = 0; k < NV; ++k) hl[j][k] = m.hlconn[(size_t)k * H + hc0 + h];
+      hsh[j] = m.hshift[hc0 + h];
+    }
+  }
+  // ---- stage the slots and the halo nodes
+  double iv = 0.0;     // 1/V of this thread's slot node
+  int g0 = 0, g1 = 0;  // its cells in sGi
+  bool gw = false;     // this tile writes the node's gradient (closure output)
+  for (int q = threadIdx.x; q < ns; q += blockDim.x) {
+    const SlotTopo st = slot_topo<NV>(m, tp, q);
+    slot_table_put(sSl, maxn, q, st.sv, st.pos, st.p0, st.p1);
+    const int g = slot_node_id(st.sv);
+    double w[NGF], xe[2 * ND];
+#pragma unroll
+    for (int v = 0; v < NGF; ++v) w[v] = W[(size_t)v * m.nn + g];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      xe[d] = m.x[(size_t)d * m.nn + g];
+      if constexpr (MODEL == 1) xe[ND + d] = f.E[(size_t)d * m.nn + g];
+    }
+    if (q == (int)threadIdx.x) {
+      iv = m.inv_vol[g];
+      g0 = m.slot_ginc[tp.s0 + q] - gb;
+      g1 = m.slot_ginc[tp.s0 + q + 1] - gb;
+      gw = st.pos == st.run.x;
+    }
+#pragma unroll
+    for (int v = 0; v < NGF; ++v) {
+      sWd[v * maxne + q] = w[v];
+      if constexpr (WCOPY) sWc[v * maxn + q] = CT(w[v]);
+    }
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      sX[d * maxne + q] = xe[d];
+      if constexpr (MODEL == 1) sE[d * maxn + q] = CT(xe[ND + d]);
+    }
+  }
+  for (int h = threadIdx.x; h < nhn; h += blockDim.x) {
+    const int g = m.hnode[hn0 + h];
+    double w[NGF], xx[ND];
+#pragma unroll
+    for (int v = 0; v < NGF; ++v) w[v] = W[(size_t)v * m.nn + g];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) xx[d] = m.x[(size_t)d * m.nn + g];
+#pragma unroll
+    for (int v = 0; v < NGF; ++v) sWd[v * maxne + ns + h] = w[v];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) sX[d * maxne + ns + h] = xx[d];
+  }
+  tile_store_inc<NV>(m, tp, sInc);
+  stage_u16<6>(m.ginc + gb, ngi, sGi);
+  __syncthreads();
+  // ---- gradient parts of the tile's cells and halo cells: sum_k W_k S_k
+  for (int ec = threadIdx.x; ec < nce; ec += blockDim.x) {
+    int l[NV];
+    uint32_t sh;
+    if (ec < nc) {
+      cell_topo<NV>(m, tp, ec, l, sh);
+    } else {
+      const int j = (ec - (int)threadIdx.x) / (int)blockDim.x;
+      if (j < 2) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) l[k] = j == 0 ? hl[0][k] : hl[1][k];
+        sh = j == 0 ? hsh[0] : hsh[1];
+      } else {
+        const int h = ec - nc;
+#pragma unroll
+        for (int k = 0; k < NV; ++k) l[k] = m.hlconn[(size_t)k * H + hc0 + h];
+        sh = m.hshift[hc0 + h];
+      }
+    }
+    double e[ND][ND], S[NV][ND];
+    cell_rel_coords<ND>(m, sX, maxne, l, sh, e);
+    simplex_normals<ND>(e, S);
+#pragma unroll
+    for (int v = 0; v < NGF; ++v) {
+      double acc[ND];
+#pragma unroll
+      for (int d = 0; d < ND; ++d) acc[d] = 0.0;
+#pragma unroll
+      for (int k = 0; k < NV; ++k) {
+        const double w = sWd[v * maxne + l[k]];
+#pragma unroll
+        for (int d = 0; d < ND; ++d) acc[d] += w * S[k][d];
+      }
+#pragma unroll
+      for (int d = 0; d < ND; ++d) sCR[(v * ND + d) * maxce + ec] = acc[d];
+    }
+  }
+  __syncthreads();
+  // ---- node gradients of the slots over all their cells, ascending cell id
+  constexpr int JC = NC <= 16 ? NC : 8;
+  for (int q = threadIdx.x; q < ns; q += blockDim.x) {
+    int a0 = g0, a1 = g1;
+    double c = iv;
+    bool wg = gw;
+    if (q != (int)threadIdx.x) {
+      const SlotTopo st = slot_topo<NV>(m, tp, q);
+      c = m.inv_vol[slot_node_id(st.sv)];
+      a0 = m.slot_ginc[tp.s0 + q] - gb;
+      a1 = m.slot_ginc[tp.s0 + q + 1] - gb;
+      wg = st.pos == st.run.x;
+    }
+    const double coef = -c / double(ND * NV);
+    const int g = slot_node_id(sSl[q]);
+    for (int j0 = 0; j0 < NC; j0 += JC) {
+      double acc[JC];
+#pragma unroll
+      for (int jj = 0; jj < JC; ++jj) acc[jj] = 0.0;
+      for (int p = a0; p < a1; ++p) {
+        const int ec = sGi[p];
+#pragma unroll
+        for (int jj = 0; jj < JC; ++jj)
+          if (j0 + jj < NC) acc[jj] += sCR[(j0 + jj) * maxce + ec];
+      }
+#pragma unroll
+      for (int jj = 0; jj < JC; ++jj)
+        if (j0 + jj < NC) {
+          const double gv = coef * acc[jj];
+          sG[(j0 + jj) * maxn + q] = CT(gv);
+          if (fc.Gout && wg) fc.Gout[(size_t)(j0 + jj) * m.nn + g] = gv;
+        }
+    }
+  }
+  __syncthreads();
+  // ---- fluxes of the tile's cells (the residual parts take the gradient parts' place)
+  double* sR = sCR;
+  const CT* sW = WCOPY ? sWc : reinterpret_cast<const CT*>(sWd);
+  const int ldw = WCOPY ? maxn : maxne;
+  if constexpr (MODEL == 1)
+    dd_cell_fluxes<ND, NSP, CT, NV>(m, tp, sX, sW, sG, sE, sR, CellLd{maxne, ldw, maxn, maxc}, CT(s_dt), pp);
+  else
+    gas_cell_fluxes<ND, NSP, FLUX, CT, NV>(m, tp, sX, sW, sG, sR, CellLd{maxne, ldw, maxn, maxc}, gp);
+  __syncthreads();
+  const double cand = tile_node_pass<ND, NSP, MODEL, NVAR>(m, f, s_dt, PR, ns, sSl, maxn, sInc, sR, maxc);
+  if (f.final_stage && loop) {
+    const double b = block_min(cand);
+    if (threadIdx.x == 0) post_candidate(f.cand, t, b);
+  }
+}
+
+template <int ND, int NSP, int MODEL, int FLUX, typename CT>
+__global__ void VCX_FUSED_BOUNDS k_fused(DevMesh m, const double* __restrict__ W, double* __restrict__ PR,
+                                        GasParams gp, DDParams pp, Finish f, FusedCtl fc) {
+  extern __shared__ double lds[];
+  const int t = xcd_tile(m.ntiles);
+  if (t >= m.ntiles) return;
+  fused_body<ND, NSP, MODEL, FLUX, CT>(m, W, PR, gp, pp, f, fc, t, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1142,7 +1479,7 @@ __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ W,
     }
     if (st.sv >= 0) {
       NodeIn<NVAR, ND> nq;
-      node_in_load<ND, 2, NVAR>(m, f, st.sv, nq);
+      node_in_load<ND, 2, NVAR>(m, f, f.sc ? f.sc->dt : 0.0, st.sv, nq);
       cand = fmin(cand, finish_node<ND, NSP, 2, NVAR>(m, f, st.sv, false, r, nq));
     } else {
 #pragma unroll
@@ -1151,7 +1488,7 @@ __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ W,
   }
   if (f.final_stage && f.sc) {
     const double b = block_min(cand);
-    if (threadIdx.x == 0) f.cand[t] = b;
+    if (threadIdx.x == 0) post_candidate(f.cand, t, b);
   }
 }
 
@@ -1190,16 +1527,17 @@ template <int ND, int NSP, int MODEL>
 __device__ inline void update_shared_body(const DevMesh& m, const double* __restrict__ PR,
                                           const Finish& f, int b) {
   constexpr int NVAR = MODEL == 1 ? NSP : 2 + ND + NSP;
+  if (f.roll && b == 0) step_rollover(f.roll, f.roll_par, f.roll->s[f.roll_par].active);
   if (step_inactive(f.sc)) return;
   // the next step reduces the candidates written by this stage
-  if (f.final_stage && f.sc && b == 0 && threadIdx.x == 0) f.sc->dt_src = 1;
+  if (f.final_stage && f.sc && b == 0 && threadIdx.x == 0) f.sc->dt_src = 1;  // cand[par] from now on
   const int k = b * blockDim.x + threadIdx.x;
   double cand = INFINITY;
   if (k < m.nshared) {
     const int i = m.shared[k];
     const int2 run = m.shared_run[k];
     NodeIn<NVAR, ND> ni;
-    node_in_load<ND, MODEL, NVAR>(m, f, i, ni);
+    node_in_load<ND, MODEL, NVAR>(m, f, f.sc ? f.sc->dt : 0.0, i, ni);
     double r[NVAR];
 #pragma unroll
     for (int v = 0; v < NVAR; ++v) r[v] = 0.0;
@@ -1212,7 +1550,7 @@ __device__ inline void update_shared_body(const DevMesh& m, const double* __rest
   }
   if (f.final_stage && f.sc) {
     const double bm = block_min(cand);
-    if (threadIdx.x == 0) f.cand[m.ntiles + b] = bm;
+    if (threadIdx.x == 0) post_candidate(f.cand, m.ntiles + b, bm);
   }
 }
 
@@ -1227,7 +1565,7 @@ __global__ void __launch_bounds__(256) k_update_shared(DevMesh m, const double* 
 template <int ND, int NSP, int MODEL>
 __global__ void __launch_bounds__(256) k_node_dt(DevMesh m, const double* __restrict__ W,
                                                  const double* __restrict__ E, DtCoef dc,
-                                                 MixParams mp, DtParts parts, DevLoop* lp) {
+                                                 MixParams mp, DevLoop* lp) {
   constexpr int NVAR = MODEL == 1 ? NSP : 2 + ND + NSP;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   double cand = INFINITY;
@@ -1256,15 +1594,19 @@ __global__ void __launch_bounds__(256) k_node_dt(DevMesh m, const double* __rest
   }
   const double b = block_min(cand);
   if (threadIdx.x == 0) {
-    parts.node[blockIdx.x] = b;
+    post_candidate(lp->cnode, blockIdx.x, b);
     // the next step (either parity) takes its candidates from this pass
     if (blockIdx.x == 0) lp->s[0].dt_src = lp->s[1].dt_src = 0;
   }
 }
 
-__global__ void __launch_bounds__(256) k_dt_query(DevLoop* lp, DtParts parts) {
-  double v = INFINITY;
-  for (int q = threadIdx.x; q < parts.nnode; q += blockDim.x) v = fmin(v, parts.node[q]);
+// empty the node-pass slots (before a node pass)
+__global__ void k_node_slots_clear(DevLoop* lp) {
+  if (threadIdx.x < kCandSlots) lp->cnode[threadIdx.x] = cand_empty();
+}
+
+__global__ void __launch_bounds__(256) k_dt_query(DevLoop* lp) {
+  const double v = threadIdx.x < kCandSlots ? key_cand(lp->cnode[threadIdx.x]) : INFINITY;
   const double d = block_min(v);
   if (threadIdx.x == 0) lp->s[0].dt_query = lp->s[1].dt_query = (d > 0.0 && isfinite(d)) ? d : -1.0;
 }
@@ -1324,7 +1666,7 @@ struct BatchEntry {
   double* PR;
   const double* E;
   DevLoop* lp;
-  DtParts parts;
+  double* gout;     // fused passes: node gradients for the boundary closure, or null
   int phase;        // buffer parity of the solve at batch step 0
   int spar;         // step parity of the solve at batch step 0
 };
@@ -1340,6 +1682,7 @@ struct FinishShared {
   DtCoef dc;
   MixParams mix;
   int closure;
+  int fused;        // the stage runs the fused gradient + flux pass
 };
 
 __device__ inline Finish batch_finish(const BatchEntry& e, const BatchStage& st,
@@ -1355,7 +1698,12 @@ __device__ inline Finish batch_finish(const BatchEntry& e, const BatchStage& st,
   const int par = (st.step + e.spar) & 1;
   f.sc = &e.lp->s[par];
   f.found = &e.lp->found[par];
-  f.cand = e.parts.step + (size_t)par * e.parts.nstep;
+  f.cand = e.lp->cand[par];
+  if (fs.fused && st.stage == 1) {
+    f.roll = e.lp;
+    f.roll_par = par;
+  }
+  f.gfull = fs.fused && e.gout != nullptr;
   f.dc = fs.dc;
   f.mix = fs.mix;
   f.alpha = st.alpha;
@@ -1378,12 +1726,12 @@ __global__ void __launch_bounds__(256) k_grad_tile_batch(const BatchEntry* __res
   const int par = (st.step + e.spar) & 1;
   if (ml.y < 0) {
     // the solve's decision entry: the step that starts now
-    if (st.stage == 1) step_start(e.lp, par, e.parts);
+    if (st.stage == 1) step_start(e.lp, par);
     return;
   }
   const int cur = (st.step + e.phase) & 1;
   const double* Win = st.stage == 1 ? e.W[cur] : e.W[cur ^ 1];
-  GradCtl ctl{e.lp, e.parts, par, st.stage == 1 ? 1 : 0};
+  GradCtl ctl{e.lp, par, st.stage == 1 ? 1 : 0};
   grad_tile_body<ND, NR>(e.m, Win, e.G, e.PG, ctl, ml.y, lds);
 }
 
@@ -1430,6 +1778,23 @@ __global__ void VCX_FLUX_BOUNDS k_flux_ns_batch(const BatchEntry* __restrict__ t
   const double* Win;
   const Finish f = batch_finish(e, st, fs, &Win);
   flux_ns_body<ND, NSP, CT>(e.m, Win, e.G, e.PR, gp, f, ml.y, lds);
+}
+
+template <int ND, int NSP, int MODEL, int FLUX, typename CT>
+__global__ void VCX_FUSED_BOUNDS k_fused_batch(const BatchEntry* __restrict__ tab,
+                                              const int2* __restrict__ map, int nblocks, BatchStage st,
+                                              GasParams gp, DDParams pp, FinishShared fs) {
+  extern __shared__ double lds[];
+  const int g = xcd_tile(nblocks);
+  if (g >= nblocks) return;
+  const int2 ml = map[g];
+  if (ml.y < 0) return;
+  const BatchEntry& e = tab[ml.x];
+  const double* Win;
+  const Finish f = batch_finish(e, st, fs, &Win);
+  const int par = (st.step + e.spar) & 1;
+  FusedCtl fc{e.lp, par, st.stage == 1 ? 1 : 0, e.gout};
+  fused_body<ND, NSP, MODEL, FLUX, CT>(e.m, Win, e.PR, gp, pp, f, fc, ml.y, lds);
 }
 
 template <int ND, int NSP, int MODEL>
