@@ -677,6 +677,31 @@ __device__ inline void node_in_load(const DevMesh& m, const Finish& f, double dt
   }
 }
 
+// Update inputs staged in LDS by a tile pass, by slot (null members: read
+// from global memory).
+struct NodeLds {
+  const double* un;  // [NVAR][ldu] U^n rows
+  int ldu;
+  const double* iv;  // [maxn] 1/V
+  const double* dx;  // [maxn] dx_min
+  const double* e;   // [ND][lde] field (drift-diffusion)
+  int lde;
+};
+
+template <int ND, int MODEL, int NVAR>
+__device__ inline void node_in_lds(const DevMesh& m, const Finish& f, double dt, int i, int q,
+                                   const NodeLds& nl, NodeIn<NVAR, ND>& ni) {
+  if (f.residual_only) return;
+#pragma unroll
+  for (int v = 0; v < NVAR; ++v) ni.Un[v] = nl.un ? nl.un[v * nl.ldu + q] : f.Un[(size_t)v * m.nn + i];
+  ni.fac = f.alpha * dt * (nl.iv ? nl.iv[q] : m.inv_vol[i]);
+  ni.dx = nl.dx ? nl.dx[q] : m.dxmin[i];
+  if constexpr (MODEL == 1) {
+#pragma unroll
+    for (int d = 0; d < ND; ++d) ni.E[d] = nl.e ? nl.e[d * nl.lde + q] : f.E[(size_t)d * m.nn + i];
+  }
+}
+
 template <int ND, int NSP, int MODEL, int NVAR>
 __device__ inline double finish_node(const DevMesh& m, const Finish& f, int i, bool shared,
                                      double (&r)[NVAR], const NodeIn<NVAR, ND>& ni) {
@@ -934,13 +959,13 @@ __device__ inline void dd_cell_fluxes(const DevMesh& m, const TilePre<NV>& tp, c
 template <int ND, int NSP, int MODEL, int NVAR>
 __device__ inline double tile_node_pass(const DevMesh& m, const Finish& f, double dt, double* PR, int ns,
                                         const int* sSl, int ldsl, const uint16_t* sInc, const double* sR,
-                                        int ldc) {
+                                        int ldc, const NodeLds& nl = NodeLds{}) {
   double cand = INFINITY;
   for (int q = threadIdx.x; q < ns; q += blockDim.x) {
     const SlotTopo st = slot_table_get(sSl, ldsl, q);
     // update inputs first: their loads overlap the sums
     NodeIn<NVAR, ND> nq;
-    if (st.sv >= 0) node_in_load<ND, MODEL, NVAR>(m, f, dt, st.sv, nq);
+    if (st.sv >= 0) node_in_lds<ND, MODEL, NVAR>(m, f, dt, st.sv, q, nl, nq);
     double r[NVAR];
 #pragma unroll
     for (int v = 0; v < NVAR; ++v) r[v] = 0.0;
@@ -1144,25 +1169,17 @@ __device__ inline void fused_body(DevMesh m, const double* __restrict__ W, doubl
   using D = FusedDims<MODEL, NSP, ND>;
   constexpr int NV = ND + 1, NVAR = D::NVAR, NGF = D::NGF, NC = D::NC;
   constexpr bool WCOPY = sizeof(CT) != sizeof(double);
-  // the step: decided here in its first stage, read from its state after
+  // the step: decided here in its first stage (after the staging, which
+  // does not depend on it), read from its state in later stages
   __shared__ double s_dt;
   __shared__ int s_act;
   const bool loop = fc.lp != nullptr;
-  if (loop && fc.first_stage) {
-    const double d = step_candidate(fc.lp, fc.par);
-    if (threadIdx.x == 0) {
-      DevScalars n;
-      step_decide(fc.lp->s[fc.par ^ 1], fc.lp->found[fc.par ^ 1], d, n);
-      if (t == 0) fc.lp->s[fc.par] = n;
-      s_dt = n.dt;
-      s_act = n.active;
-    }
-    __syncthreads();
-    if (!s_act) return;
-  } else if (loop && fc.lp->s[fc.par].active == 0) {
-    return;
-  } else if (threadIdx.x == 0) {
-    s_dt = loop ? fc.lp->s[fc.par].dt : pp.dt_host;
+  const bool decide = loop && fc.first_stage;
+  if (loop && !decide && fc.lp->s[fc.par].active == 0) return;
+  double ck = INFINITY;  // this thread's candidate slot of the previous state
+  if (decide && threadIdx.x < kCandSlots) {
+    const long long* slots = fc.lp->s[fc.par ^ 1].dt_src ? fc.lp->cand[fc.par ^ 1] : fc.lp->cnode;
+    ck = key_cand(slots[threadIdx.x]);
   }
   // (the step size is read from LDS where it is used, not held in registers)
 
@@ -1202,6 +1219,7 @@ __device__ inline void fused_body(DevMesh m, const double* __restrict__ W, doubl
   }
   // ---- stage the slots and the halo nodes
   double iv = 0.0;     // 1/V of this thread's slot node
+  double dxm = 0.0;    // its dx_min
   int g0 = 0, g1 = 0;  // its cells in sGi
   bool gw = false;     // this tile writes the node's gradient (closure output)
   for (int q = threadIdx.x; q < ns; q += blockDim.x) {
@@ -1218,6 +1236,7 @@ __device__ inline void fused_body(DevMesh m, const double* __restrict__ W, doubl
     }
     if (q == (int)threadIdx.x) {
       iv = m.inv_vol[g];
+      dxm = m.dxmin[g];
       g0 = m.slot_ginc[tp.s0 + q] - gb;
       g1 = m.slot_ginc[tp.s0 + q + 1] - gb;
       gw = st.pos == st.run.x;
@@ -1247,7 +1266,21 @@ __device__ inline void fused_body(DevMesh m, const double* __restrict__ W, doubl
   }
   tile_store_inc<NV>(m, tp, sInc);
   stage_u16<6>(m.ginc + gb, ngi, sGi);
+  if (decide) {
+    const double d = block_min(ck);
+    if (threadIdx.x == 0) {
+      DevScalars n;
+      step_decide(fc.lp->s[fc.par ^ 1], fc.lp->found[fc.par ^ 1], d, n);
+      if (t == 0) fc.lp->s[fc.par] = n;
+      s_dt = n.dt;
+      s_act = n.active;
+    }
+  } else if (threadIdx.x == 0) {
+    s_dt = loop ? fc.lp->s[fc.par].dt : pp.dt_host;
+    s_act = 1;
+  }
   __syncthreads();
+  if (!s_act) return;
   // ---- gradient parts of the tile's cells and halo cells: sum_k W_k S_k
   for (int ec = threadIdx.x; ec < nce; ec += blockDim.x) {
     int l[NV];
@@ -1321,8 +1354,24 @@ __device__ inline void fused_body(DevMesh m, const double* __restrict__ W, doubl
     }
   }
   __syncthreads();
-  // ---- fluxes of the tile's cells (the residual parts take the gradient parts' place)
+  // ---- fluxes of the tile's cells (the residual parts take the gradient parts' place);
+  // the slots' 1/V and dx_min go to the part of the gradient area that the
+  // residual parts leave free, for the node pass
   double* sR = sCR;
+  const size_t tail = (size_t)NV * NVAR * maxc;
+  const bool tail_ok = ncr >= tail + 2 * (size_t)maxn;
+  if (tail_ok) {
+    for (int q = threadIdx.x; q < ns; q += blockDim.x) {
+      double a = iv, b = dxm;
+      if (q != (int)threadIdx.x) {
+        const int g = slot_node_id(sSl[q]);
+        a = m.inv_vol[g];
+        b = m.dxmin[g];
+      }
+      sCR[tail + q] = a;
+      sCR[tail + maxn + q] = b;
+    }
+  }
   const CT* sW = WCOPY ? sWc : reinterpret_cast<const CT*>(sWd);
   const int ldw = WCOPY ? maxn : maxne;
   if constexpr (MODEL == 1)
@@ -1330,7 +1379,20 @@ __device__ inline void fused_body(DevMesh m, const double* __restrict__ W, doubl
   else
     gas_cell_fluxes<ND, NSP, FLUX, CT, NV>(m, tp, sX, sW, sG, sR, CellLd{maxne, ldw, maxn, maxc}, gp);
   __syncthreads();
-  const double cand = tile_node_pass<ND, NSP, MODEL, NVAR>(m, f, s_dt, PR, ns, sSl, maxn, sInc, sR, maxc);
+  NodeLds nl{};
+  if (f.Un == f.Win) {  // U^n is the staged state (first stage)
+    nl.un = sWd;
+    nl.ldu = maxne;
+  }
+  if (tail_ok) {
+    nl.iv = sCR + tail;
+    nl.dx = sCR + tail + maxn;
+  }
+  if constexpr (MODEL == 1 && !WCOPY) {
+    nl.e = reinterpret_cast<const double*>(sE);
+    nl.lde = maxn;
+  }
+  const double cand = tile_node_pass<ND, NSP, MODEL, NVAR>(m, f, s_dt, PR, ns, sSl, maxn, sInc, sR, maxc, nl);
   if (f.final_stage && loop) {
     const double b = block_min(cand);
     if (threadIdx.x == 0) post_candidate(f.cand, t, b);
