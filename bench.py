@@ -77,7 +77,7 @@ def parse():
     ap.add_argument("--serve-steps", type=int, default=100)
     ap.add_argument("--serve-budget-gb", type=float, default=8.0)
     ap.add_argument("--serve-slots", type=int, default=64)
-    ap.add_argument("--serve-graphs", type=int, default=1, help="server replays captured graphs")
+    ap.add_argument("--serve-graphs", type=int, default=0, help="server replays captured graphs")
     ap.add_argument("--serve-only", action="store_true", help="run the serving leg only")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with plain 256 MiB device copies (counter calibration)")

@@ -1,11 +1,14 @@
 // Request scheduler of the serving API (declarations in include/vcx.h).
 //
-// Continuous batching of independent solves: a worker thread admits queued
-// requests in arrival order while the slot count and the device-memory
-// budget allow, keeps every admitted state resident, advances all running
-// requests of one scheme together (one launch per kernel per RK stage over
-// every member's tiles), and retires requests as they finish, so that
-// requests arriving while others run join at the next chunk boundary.
+// Continuous batching of independent solves.  A scheduler thread admits
+// queued requests in arrival order while the slot count and the
+// device-memory budget allow, advances all running requests of one scheme
+// together (one launch per kernel per RK stage over every member's tiles) in
+// chunks of a few steps, and hands requests that ended back for retirement.
+// An I/O thread does the host work around the device loop: solver set-up (or
+// reuse of an idle solver on the same mesh and physics), state upload, and
+// result download, so the scheduler's chunks are not held up by transfers.
+// Uploaded requests join their batch at the next chunk boundary.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -86,16 +89,20 @@ struct vcx_server_s {
   int device = 0;
   hipStream_t stream = nullptr;
   std::mutex mu;
-  std::condition_variable cv_work, cv_done;
-  std::deque<Request*> queue;
+  std::condition_variable cv_work, cv_io, cv_done;
+  std::deque<Request*> queue;      // submitted, waiting for admission
+  std::deque<Request*> io_start;   // admitted: solver set-up and state upload (I/O thread)
+  std::deque<Request*> io_finish;  // ended: state download and release (I/O thread)
+  std::deque<Request*> ready;      // uploaded: join a batch at the next chunk
   std::unordered_map<int64_t, std::unique_ptr<Request>> reqs;
-  size_t resident = 0;    // bytes of running and idle solvers
+  size_t resident = 0;    // bytes of admitted and idle solvers
   size_t idle_bytes = 0;
-  int running = 0;
-  std::vector<Idle> idle; // finished solvers kept for reuse (worker thread only)
+  int running = 0;        // admitted and not finished
+  std::vector<Idle> idle; // finished solvers kept for reuse
   int64_t next_id = 1;
+  uint64_t events = 0;  // submissions, finished requests and shutdown, counted
   bool stop = false;
-  std::thread worker;
+  std::thread worker, io;
   // statistics (under mu)
   int64_t submitted = 0, completed = 0, failed = 0, member_steps = 0, chunks = 0, member_chunks = 0;
   std::vector<double> lat_ms, step_ms;
@@ -105,25 +112,16 @@ struct vcx_server_s {
   std::string worker_err;
 
   void run();
-  void admit(std::vector<Request*>& out, std::vector<vcx_solver>& evict);
-  void start(std::vector<Request*>& adm, std::vector<Group>& groups);
-  void finish(Request* r, vcx_status st, const std::string& msg);
+  void run_io();
+  void admit(std::vector<vcx_solver>& evict);
+  void start(Request* r);
   void retire(Request* r);
+  void finish_locked(Request* r, vcx_status st, const std::string& msg, bool keep);
 };
 
-void vcx_server_s::finish(Request* r, vcx_status st, const std::string& msg) {
-  bool keep = false;
-  if (r->s) {
-    // an intact solver waits in the idle pool for a request with the same
-    // mesh and physics; its bytes stay counted in the resident total
-    keep = st == VCX_OK || st == VCX_E_UNSTABLE;
-    if (keep)
-      idle.push_back(Idle{r->s, r->bytes, clk::now()});
-    else
-      (void)vcx_solver_destroy(r->s);
-    r->s = nullptr;
-  }
-  std::lock_guard<std::mutex> lk(mu);
+// Bookkeeping of a finished request (mu held).  keep: its solver goes to the
+// idle pool (bytes stay resident), else it has been destroyed.
+void vcx_server_s::finish_locked(Request* r, vcx_status st, const std::string& msg, bool keep) {
   r->status = st;
   r->err = msg;
   r->state = DONE;
@@ -142,31 +140,15 @@ void vcx_server_s::finish(Request* r, vcx_status st, const std::string& msg) {
   } else {
     failed += 1;
   }
+  events += 1;
   cv_done.notify_all();
+  cv_work.notify_all();
 }
 
-void vcx_server_s::retire(Request* r) {
-  const int nvar = vcx_solver_nvar(r->s);
-  vcx_status st = VCX_OK;
-  std::string msg;
-  std::vector<double> U((size_t)std::max(nvar, 0) * (size_t)vcx::mesh_nnodes(r->mesh));
-  if (vcx_state_download(r->s, U.data(), 0) != VCX_OK) {
-    st = VCX_E_HIP;
-    msg = vcx_last_error();
-  }
-  (void)vcx_state_time(r->s, &r->t, &r->dt_last);
-  if (st == VCX_OK && vcx::solver_failed(r->s)) {
-    st = VCX_E_UNSTABLE;
-    msg = "the solve became unstable; the result holds its last good state";
-  }
-  r->U.swap(U);
-  finish(r, st, msg);
-}
-
-// Admission (under mu): requests leave the queue in arrival order while a
+// Admission (mu held): requests leave the queue in arrival order while a
 // slot is free and their footprint fits the budget, counting idle solvers
 // that can be reused as free and evicting other idle solvers when needed.
-void vcx_server_s::admit(std::vector<Request*>& out, std::vector<vcx_solver>& evict) {
+void vcx_server_s::admit(std::vector<vcx_solver>& evict) {
   while (!queue.empty() && running < max_slots) {
     Request* r = queue.front();
     if (r->bytes > budget) {
@@ -207,63 +189,112 @@ void vcx_server_s::admit(std::vector<Request*>& out, std::vector<vcx_solver>& ev
     running += 1;
     peak_resident = std::max(peak_resident, resident);
     peak_running = std::max(peak_running, running);
-    out.push_back(r);
+    io_start.push_back(r);
   }
+  if (!io_start.empty()) cv_io.notify_one();
 }
 
-// Solver creation (or reuse) and state upload of admitted requests; they
-// join their scheme's group at the next chunk.
-void vcx_server_s::start(std::vector<Request*>& adm, std::vector<Group>& groups) {
-  for (Request* r : adm) {
-    r->t_admit = clk::now();
-    vcx_status st = VCX_OK;
-    if (r->s) {
-      if (r->ph.model == VCX_MODEL_DRIFT_DIFFUSION) st = vcx::solver_set_field(r->s, r->E.data());
-    } else {
-      st = vcx_solver_create(r->mesh, &r->ph, r->E.empty() ? nullptr : r->E.data(), &r->s);
-    }
-    if (st == VCX_OK) st = vcx_state_upload(r->s, r->U0.data(), 0);
-    if (st != VCX_OK) {
-      finish(r, st, vcx_last_error());
-      continue;
-    }
-    std::vector<double>().swap(r->U0);
-    std::vector<double>().swap(r->E);
-    r->state = RUNNING;
-    if (r->nsteps == 0) {
-      retire(r);
-      continue;
-    }
-    Group* home = nullptr;
-    for (Group& g : groups)
-      if (!g.mem.empty() && vcx::batch_compatible(g.mem[0]->s, r->s)) home = &g;
-    if (!home) {
-      Group g;
-      if (vcx::batch_create(stream, graphs, &g.g) != VCX_OK) {
-        finish(r, VCX_E_HIP, vcx_last_error());
-        continue;
-      }
-      groups.push_back(g);
-      home = &groups.back();
-    }
-    home->mem.push_back(r);
-    home->dirty = true;
+// I/O thread: solver set-up (or reuse) and state upload of an admitted request.
+void vcx_server_s::start(Request* r) {
+  r->t_admit = clk::now();
+  vcx_status st = VCX_OK;
+  if (r->s) {
+    if (r->ph.model == VCX_MODEL_DRIFT_DIFFUSION) st = vcx::solver_set_field(r->s, r->E.data());
+  } else {
+    st = vcx_solver_create(r->mesh, &r->ph, r->E.empty() ? nullptr : r->E.data(), &r->s);
   }
-  adm.clear();
+  if (st == VCX_OK) st = vcx_state_upload(r->s, r->U0.data(), 0);
+  std::vector<double>().swap(r->U0);
+  std::vector<double>().swap(r->E);
+  if (st != VCX_OK) {
+    const std::string msg = vcx_last_error();
+    if (r->s) (void)vcx_solver_destroy(r->s);
+    r->s = nullptr;
+    std::lock_guard<std::mutex> lk(mu);
+    finish_locked(r, st, msg, false);
+    return;
+  }
+  if (r->nsteps == 0) {
+    retire(r);
+    return;
+  }
+  std::lock_guard<std::mutex> lk(mu);
+  r->state = RUNNING;
+  ready.push_back(r);
+  cv_work.notify_all();
+}
+
+// I/O thread: result download of an ended request, then its solver goes idle.
+void vcx_server_s::retire(Request* r) {
+  const int nvar = vcx_solver_nvar(r->s);
+  vcx_status st = VCX_OK;
+  std::string msg;
+  std::vector<double> U((size_t)std::max(nvar, 0) * (size_t)vcx::mesh_nnodes(r->mesh));
+  if (vcx_state_download(r->s, U.data(), 0) != VCX_OK) {
+    st = VCX_E_HIP;
+    msg = vcx_last_error();
+  }
+  (void)vcx_state_time(r->s, &r->t, &r->dt_last);
+  if (st == VCX_OK && vcx::solver_failed(r->s)) {
+    st = VCX_E_UNSTABLE;
+    msg = "the solve became unstable; the result holds its last good state";
+  }
+  r->U.swap(U);
+  const bool keep = st == VCX_OK || st == VCX_E_UNSTABLE;
+  if (!keep) {
+    (void)vcx_solver_destroy(r->s);
+  }
+  std::lock_guard<std::mutex> lk(mu);
+  if (keep) idle.push_back(Idle{r->s, r->bytes, clk::now()});
+  r->s = nullptr;
+  finish_locked(r, st, msg, keep);
+}
+
+void vcx_server_s::run_io() {
+  (void)hipSetDevice(device);
+  for (;;) {
+    Request* r = nullptr;
+    bool fin = false;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      cv_io.wait(lk, [&] { return !io_finish.empty() || !io_start.empty() || (stop && running == 0); });
+      if (!io_finish.empty()) {  // results first: they free memory and slots
+        r = io_finish.front();
+        io_finish.pop_front();
+        fin = true;
+      } else if (!io_start.empty()) {
+        r = io_start.front();
+        io_start.pop_front();
+      } else {
+        break;
+      }
+    }
+    if (fin)
+      retire(r);
+    else
+      start(r);
+  }
 }
 
 void vcx_server_s::run() {
   (void)hipSetDevice(device);
   std::vector<Group> groups;
   std::vector<int> ended;
-  std::vector<Request*> adm;
   std::vector<vcx_solver> evict;
+  std::vector<Request*> joined;
+  uint64_t seen = ~(uint64_t)0;
   for (;;) {
     {
       std::unique_lock<std::mutex> lk(mu);
-      cv_work.wait(lk, [&] { return stop || !queue.empty() || running > 0; });
+      if (groups.empty()) {
+        // nothing runs: sleep until a request is ready to join or something
+        // that can change the admission decision happened (a submission, a
+        // finished request, shutdown)
+        cv_work.wait(lk, [&] { return !ready.empty() || events != seen || (stop && running == 0); });
+      }
+      seen = events;
       if (stop) {
-        // cancel what has not started; running requests are finished below
+        // cancel what has not been admitted; admitted requests are finished
         for (Request* r : queue) {
           r->status = VCX_E_BUSY;
           r->err = "server shut down before the request started";
@@ -273,14 +304,36 @@ void vcx_server_s::run() {
         queue.clear();
         cv_done.notify_all();
         if (running == 0) break;
+      } else {
+        admit(evict);
       }
-      if (groups.empty()) admit(adm, evict);
+      joined.assign(ready.begin(), ready.end());
+      ready.clear();
     }
     for (vcx_solver s : evict) (void)vcx_solver_destroy(s);
     evict.clear();
-    const auto t0 = clk::now();
-    if (groups.empty()) start(adm, groups);
+    for (Request* r : joined) {
+      Group* home = nullptr;
+      for (Group& g : groups)
+        if (!g.mem.empty() && vcx::batch_compatible(g.mem[0]->s, r->s)) home = &g;
+      if (!home) {
+        Group g;
+        if (vcx::batch_create(stream, graphs, &g.g) != VCX_OK) {
+          // no batch for it: the request ends with its uploaded state
+          std::lock_guard<std::mutex> lk(mu);
+          r->ended = true;
+          io_finish.push_back(r);
+          cv_io.notify_one();
+          continue;
+        }
+        groups.push_back(g);
+        home = &groups.back();
+      }
+      home->mem.push_back(r);
+      home->dirty = true;
+    }
     if (groups.empty()) continue;
+    const auto t0 = clk::now();
     // steps of this chunk: no member runs past its budget inside the chunk
     int c = chunk;
     for (Group& g : groups)
@@ -306,15 +359,6 @@ void vcx_server_s::run() {
       st = vcx::batch_run(g.g, c);
       members += (int)g.mem.size();
     }
-    // while the chunk runs: admit and upload new requests for the next one
-    if (st == VCX_OK) {
-      {
-        std::lock_guard<std::mutex> lk(mu);
-        if (!stop) admit(adm, evict);
-      }
-      for (vcx_solver s : evict) (void)vcx_solver_destroy(s);
-      evict.clear();
-    }
     int64_t done_steps = 0;
     for (Group& g : groups) {
       if (st != VCX_OK) break;
@@ -330,27 +374,32 @@ void vcx_server_s::run() {
     if (st != VCX_OK) {
       // a device error ends every running request of the server
       const std::string msg = vcx_last_error();
+      std::lock_guard<std::mutex> lk(mu);
       for (Group& g : groups) {
-        for (Request* r : g.mem) finish(r, st, msg);
+        for (Request* r : g.mem) {
+          if (r->s) (void)vcx_solver_destroy(r->s);
+          r->s = nullptr;
+          finish_locked(r, st, msg, false);
+        }
         g.mem.clear();
       }
-      for (Request* r : adm) finish(r, st, msg);
-      adm.clear();
-      std::lock_guard<std::mutex> lk(mu);
       worker_status = st;
       worker_err = msg;
     }
-    for (Group& g : groups) {
-      for (Request*& r : g.mem)
-        if (r->ended) {
-          retire(r);
-          r = nullptr;
-          g.dirty = true;
-        }
-      g.mem.erase(std::remove(g.mem.begin(), g.mem.end(), nullptr), g.mem.end());
+    {
+      // ended requests go to the I/O thread for their results
+      std::lock_guard<std::mutex> lk(mu);
+      for (Group& g : groups) {
+        for (Request*& r : g.mem)
+          if (r->ended) {
+            io_finish.push_back(r);
+            r = nullptr;
+            g.dirty = true;
+          }
+        g.mem.erase(std::remove(g.mem.begin(), g.mem.end(), nullptr), g.mem.end());
+      }
+      if (!io_finish.empty()) cv_io.notify_one();
     }
-    // requests admitted during the chunk join now
-    start(adm, groups);
     const auto t1 = clk::now();
     {
       std::lock_guard<std::mutex> lk(mu);
@@ -368,8 +417,10 @@ void vcx_server_s::run() {
                  groups.end());
   }
   for (Group& g : groups) vcx::batch_destroy(g.g);
-  for (Idle& x : idle) (void)vcx_solver_destroy(x.s);
-  idle.clear();
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    cv_io.notify_all();
+  }
 }
 
 extern "C" vcx_status vcx_server_create(size_t hbm_budget, int max_slots, int chunk_steps, int use_graphs,
@@ -388,8 +439,17 @@ extern "C" vcx_status vcx_server_create(size_t hbm_budget, int max_slots, int ch
     return set_err(VCX_E_HIP, "no device or stream");
   }
   try {
+    sv->io = std::thread([sv] { sv->run_io(); });
     sv->worker = std::thread([sv] { sv->run(); });
   } catch (...) {
+    if (sv->io.joinable()) {
+      {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->stop = true;
+      }
+      sv->cv_io.notify_all();
+      sv->io.join();
+    }
     (void)hipStreamDestroy(sv->stream);
     delete sv;
     return set_err(VCX_E_OOM, "cannot start the scheduler thread");
@@ -426,6 +486,7 @@ extern "C" vcx_status vcx_server_submit(vcx_server sv, vcx_mesh mesh, const vcx_
     sv->queue.push_back(r.get());
     sv->reqs.emplace(r->id, std::move(r));
     sv->submitted += 1;
+    sv->events += 1;
   }
   sv->cv_work.notify_one();
   return VCX_OK;
@@ -494,9 +555,14 @@ extern "C" vcx_status vcx_server_destroy(vcx_server sv) {
   {
     std::lock_guard<std::mutex> lk(sv->mu);
     sv->stop = true;
+    sv->events += 1;
   }
   sv->cv_work.notify_all();
+  sv->cv_io.notify_all();
   if (sv->worker.joinable()) sv->worker.join();
+  if (sv->io.joinable()) sv->io.join();
+  for (Idle& x : sv->idle) (void)vcx_solver_destroy(x.s);
+  sv->idle.clear();
   (void)hipStreamSynchronize(sv->stream);
   (void)hipStreamDestroy(sv->stream);
   delete sv;
