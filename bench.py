@@ -66,7 +66,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="dd2d", choices=["dd2d", "euler3d"])
+    ap.add_argument("--workload", default="dd2d", choices=["dd2d", "euler3d", "ns3d"])
+    ap.add_argument("--tiles", default="", help="CELLS,NODES per tile (default: the workload's)")
     ap.add_argument("--latency-steps", type=int, default=200)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -81,6 +82,10 @@ def parse():
     ap.add_argument("--serve-only", action="store_true", help="run the serving leg only")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with plain 256 MiB device copies (counter calibration)")
+    ap.add_argument("--sweep", default="",
+                    help="comma-separated NXxNY sizes of the drift-diffusion mesh family (h = 50 um) "
+                         "timed after the main run, e.g. 1200x750,2400x1500")
+    ap.add_argument("--sweep-only", action="store_true", help="run the size sweep only")
     ap.add_argument("--serve-load", type=float, default=0.8,
                     help="arrival rate as a fraction of the measured batched capacity")
     return ap.parse_args()
@@ -134,12 +139,41 @@ def workload(name):
                    cells=m.ncells, nodes=m.nnodes, faces=m.nfaces, residuals_per_step=2)
         N, M = m.nnodes, m.ncells
         nr, nd, nv = 6, 3, 5
-        bytes_flux = N * 8 * (nr + nr * nd + nd + nv) + M * 4 * 4
+        # flux pass: reads W, G, x, U^n, 1/V, dx_min per node and the cell
+        # topology (4 x u16 local vertices + u32 periodic code), writes W
+        bytes_flux = N * 8 * (nr + nr * nd + nd + nv + 2 + nr) + M * (4 * 2 + 4)
         bytes_step = 2 * (N * 8 * (nr + nd) + M * 16 + N * 8 * nr * nd + bytes_flux
                           + N * 8 * (nv + nr + 1 + nr)) + N * 8 * (nr + nd) + M * 16
         return m, U, None, phys, ophys, cfg, dict(flux=bytes_flux, step=bytes_step,
                                                    traffic_record="traffic_flux_euler3d_2m.md",
                                                    flux_kernel="k_flux_gas<3,0,1,double>")
+    if name == "ns3d":
+        mix = wl.synthetic_mixture(9, seed=3)
+        m = wl.ns3d_mesh()
+        U = wl.ns_state(m, mix, lattice=8, seed=4)
+
+        def phys(prec):
+            return vcx.physics(model=vcx.MODEL_NAVIER_STOKES, flux=vcx.FLUX_HLLC,
+                               limiter=vcx.LIM_VANLEER, rk_stages=2, nspecies=9, precision=prec,
+                               cfl=0.5, fourier=0.25, mixture=mix)
+
+        def ophys():
+            import oracle
+            return oracle.Phys(model=oracle.NAVIER_STOKES, flux=oracle.HLLC, limiter=oracle.VANLEER,
+                               rk=2, nspecies=9, cfl=0.5, fourier=0.25, mixture=mix)
+
+        cfg = dict(workload="ns3d: periodic 1 cm cube, Kuhn 110^3 jittered (10%) tets, 9 synthetic "
+                            "species, HLLC + van Leer + central viscous/heat/species diffusion, RK2",
+                   cells=m.ncells, nodes=m.nnodes, faces=m.nfaces, species=9,
+                   residuals_per_step=2, primary="mixed", tiles=(64, 48))
+        N, M = m.nnodes, m.ncells
+        nrow = 15 + 13 + 21       # conserved + p, primitives, transport/thermo aux
+        ng = (15 + 13) * 3        # gradients of the reconstructed rows and primitives
+        bytes_flux = N * 8 * (nrow + ng + 3 + 14 + 2 + nrow) + M * (4 * 2 + 4)
+        bytes_step = 2 * (N * 8 * (28 + 3) + M * 12 + N * 8 * ng + bytes_flux)
+        return m, U, None, phys, ophys, cfg, dict(flux=bytes_flux, step=bytes_step,
+                                                   traffic_record="traffic_flux_ns3d_8m.md",
+                                                   flux_kernel="k_flux_ns<3,9,float>")
     raise ValueError(name)
 
 
@@ -266,6 +300,54 @@ def serving_leg(a, stream):
     )
 
 
+def size_sweep(a, stream):
+    """FP64 throughput and the fused pass's algorithmic bandwidth of the
+    drift-diffusion workload at larger sizes of the same mesh family (fixed
+    spacing, larger box): from cache-resident to HBM-resident working sets."""
+    import torch
+    from paper_2201_01291_amd import vcx, workloads as wl
+    out = []
+    sp = wl.DD_STREAMER_SPECIES
+    for item in a.sweep.split(","):
+        nx, ny = (int(v) for v in item.lower().split("x"))
+        print(f"[bench] sweep: dd2d {nx}x{ny}", file=sys.stderr, flush=True)
+        m = wl.dd_streamer_mesh(nx, ny)
+        n, E = wl.dd_fields(m)
+        gm = vcx.Mesh(m, stream=stream)
+        ph = vcx.physics(model=vcx.MODEL_DRIFT_DIFFUSION, limiter=vcx.LIM_MINMOD, rk_stages=1,
+                         nspecies=2, precision=vcx.PREC_FP64, beta=1.0, cfl=0.5, fourier=0.25,
+                         z=[s.z for s in sp], mu=[s.mu for s in sp], D=[s.D for s in sp])
+        s = vcx.Solver(gm, ph, E)
+        s.upload(n)
+        s.step(10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(10)
+        torch.cuda.synchronize()
+        k = max(10, min(2000, int(2.0 / max(time.perf_counter() - t0, 1e-6) * 10)))
+        s.upload(n)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(k)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        s.profile(True)
+        s.step(min(k, 200))
+        nl, ms = s.profile_query("flux")
+        s.profile(False)
+        N, M = m.nnodes, m.ncells
+        alg = N * 8 * (2 + 2 + 2 + 1 + 1 + 2) + M * (3 * 2 + 4)
+        us = ms / nl * 1e3
+        gbs = alg / (us * 1e-6) / 1e9
+        out.append(dict(cells=M, nodes=N, faces=m.nfaces, steps=k,
+                        mfaces=round(m.nfaces * k / el / 1e6, 1), ms_per_step=round(el / k * 1e3, 4),
+                        fused_avg_us=round(us, 2), fused_alg_bytes=alg, fused_gbs=round(gbs, 1),
+                        fused_frac=round(gbs / HBM_PEAK_GBS, 4)))
+        s.close()
+        gm.close()
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -279,10 +361,15 @@ def main():
     if a.serve_only:
         print(json.dumps({"serving": serving_leg(a, torch.cuda.current_stream().cuda_stream)}))
         return
+    if a.sweep_only:
+        print(json.dumps({"size_sweep": size_sweep(a, torch.cuda.current_stream().cuda_stream)}))
+        return
     print(f"[bench] building workload {a.workload}", file=sys.stderr, flush=True)
     m, U0, E, phys, ophys, cfg, alg = workload(a.workload)
+    primary = cfg.pop("primary", "fp64")    # precision of the reported value
+    tiles = tuple(int(v) for v in a.tiles.split(",")) if a.tiles else cfg.get("tiles", (0, 0))
     stream = torch.cuda.current_stream()
-    gm = vcx.Mesh(m, stream=stream.cuda_stream)
+    gm = vcx.Mesh(m, stream=stream.cuda_stream, tile_cells=tiles[0], tile_nodes=tiles[1])
     info = gm.info()
     s64 = vcx.Solver(gm, phys(vcx.PREC_FP64), E)
     s32 = vcx.Solver(gm, phys(vcx.PREC_MIXED), E)
@@ -345,15 +432,16 @@ def main():
 
     # ---- profiled pass: per-kernel HIP-event durations on the solver stream
     kern = {}
+    sp = s32 if primary == "mixed" else s64
     if not a.no_profile:
-        s64.upload(U0)
-        s64.profile(True)
-        s64.step(a.steps)
+        sp.upload(U0)
+        sp.profile(True)
+        sp.step(a.steps)
         for k in ("gradient", "flux", "update"):
-            n, ms = s64.profile_query(k)   # 2D meshes: "flux" is the fused gradient + flux pass
+            n, ms = sp.profile_query(k)   # 2D meshes: "flux" is the fused gradient + flux pass
             if n:
                 kern[k] = dict(launches=n, avg_us=ms / n * 1e3)
-        s64.profile(False)
+        sp.profile(False)
     dom = max(kern, key=lambda k: kern[k]["avg_us"]) if kern else None
     roof = None
     if "flux" in kern:
@@ -382,25 +470,28 @@ def main():
                    kind="oracle", sample=f"{nsteps} full steps of the same mesh and state "
                                          f"({elc:.1f} s, sequential FP64 C oracle)")
 
+    sweep = size_sweep(a, stream.cuda_stream) if a.sweep else None
     serve = None
     if not a.no_serve:
         serve = serving_leg(a, stream.cuda_stream)
 
+    el_p = el32 if primary == "mixed" else el
     out = {
         "metric": "Mfaces/s residual throughput",
-        "value": round(mfaces, 2),
+        "value": round(faces_per_step * a.steps / el_p / 1e6, 2),
         "unit": "Mfaces/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": round(el / a.steps * 1e3, 5),
+        "ms_per_step": round(el_p / a.steps * 1e3, 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32 flux, f64 accumulation" if primary == "mixed" else "f64",
         "data": "synthetic",
         "config": cfg,
-        "hbm_gbs_algorithmic_step": round(alg["step"] * a.steps / el / 1e9, 1),
+        "hbm_gbs_algorithmic_step": round(alg["step"] * a.steps / el_p / 1e9, 1),
+        "fp64": dict(value=round(mfaces, 2), unit="Mfaces/s", ms_per_step=round(el / a.steps * 1e3, 5)),
         "batch_of_one": dict(graph=round(faces_per_step * a.steps / el_g / 1e6, 2),
                              direct=round(faces_per_step * a.steps / el_e / 1e6, 2),
                              unit="Mfaces/s", bitwise_equal_to_vcx_step=True),
@@ -412,6 +503,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "serving": serve,
+        "size_sweep": sweep,
         "mesh": info,
     }
     print(json.dumps(out))

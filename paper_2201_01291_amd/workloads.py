@@ -337,6 +337,11 @@ def euler3d_mesh(nx: int = 70, ny: int = 70, nz: int = 68, jitter: float = 0.1,
                          jitter=jitter, seed=seed, periodic=True)
 
 
+def ns3d_mesh(n: int = 110, jitter: float = 0.1, seed: int = 13) -> Mesh:
+    """Periodic cube of side 1 cm, Kuhn-split n^3 cubes (6 n^3 tets), jittered."""
+    return kuhn_tet_mesh(n, n, n, 0.01, 0.01, 0.01, jitter=jitter, seed=seed, periodic=True)
+
+
 def serving_requests(n: int = 256, *, seed: int = 5, npool: int = 16, cell_min: float = 5e3,
                      cell_max: float = 2e6):
     """Request stream of the serving workload.
