@@ -209,3 +209,70 @@ def test_full_size_drift_diffusion_residual_and_steps():
     Uo, *_ = om.step(ph, n, E, nsteps=3)
     s.step(3)
     assert state_err(case, s.download(), Uo).max() <= FP64_TOL
+
+
+def test_full_size_euler3d_residual_and_steps():
+    """The 2M-tet periodic 3D Euler workload (Roe + van Leer, RK2) at full
+    size and in the benchmark's tiling: time step, FP64 residual and two
+    steps against the oracle (about 15 s of oracle work)."""
+    from paper_2201_01291_amd import workloads as wl
+    import cases
+    m = wl.euler3d_mesh()
+    U = wl.euler_blob_state(m)
+    case = cases.Case("euler3d-full", m, U, None,
+                      dict(model="gas", flux="roe", limiter="vanleer", rk=2))
+    om, gm, s = _setup(case)
+    ph = case.oracle_phys()
+    dt = om.timestep(ph, U, None)
+    assert s.timestep() == pytest.approx(dt, rel=1e-13)
+    err = normwise(s.residual(dt), om.residual(ph, U, None, dt), om.flux_scale(ph, U, None, dt))
+    print("euler3d full residual err", err)
+    assert err.max() <= FP64_TOL
+    Uo, to, _, _ = om.step(ph, U, None, nsteps=2)
+    tg, _ = s.step(2)
+    assert tg == pytest.approx(to, rel=1e-12)
+    assert state_err(case, s.download(), Uo).max() <= FP64_TOL
+
+
+def test_full_size_ns3d_properties():
+    """The 8M-tet, 9-species Navier-Stokes workload at full size, in the
+    benchmark's 64-cell tiling (the oracle needs minutes here, so properties
+    that hold at any size): the residual of a periodic mesh sums to zero per
+    variable, the mixed-precision residual stays within its stated bound of
+    the FP64 one, two steps conserve every total, and FP64 and mixed states
+    agree after them."""
+    from paper_2201_01291_amd import workloads as wl
+    import cases
+    mix = wl.synthetic_mixture(9, seed=3)
+    m = wl.ns3d_mesh()
+    U = wl.ns_state(m, mix, lattice=8, seed=4)
+    case = cases.Case("ns3d-full", m, U, None,
+                      dict(model="ns", flux="hllc", limiter="vanleer", rk=2, nspecies=9,
+                           mixture=mix), tiles=(64, 48))
+    print(f"[case] {case.name} nn={m.nnodes} nc={m.ncells}", flush=True)
+    gm = vcx.Mesh(m, tile_cells=64, tile_nodes=48)
+    s64 = vcx.Solver(gm, case.vcx_phys(0), None)
+    s32 = vcx.Solver(gm, case.vcx_phys(1), None)
+    s64.upload(U)
+    s32.upload(U)
+    dt = s64.timestep()
+    assert dt > 0 and s32.timestep() == dt      # the time step is FP64 on both paths
+    r64, r32 = s64.residual(dt), s32.residual(dt)
+    mag = np.abs(r64).sum(axis=1)
+    assert np.all(np.abs(r64.sum(axis=1)) <= 1e-11 * mag)
+    mixed = np.abs(r32 - r64).max(axis=1) / np.abs(r64).max(axis=1)
+    print("ns3d full: mixed residual vs FP64", mixed)
+    assert mixed.max() <= 1e-3
+    Vn, _ = gm.geometry()
+    absum = (np.abs(U) * Vn[None, :]).sum(axis=1)
+    t0 = s64.sums()
+    s64.step(2)
+    s32.step(2)
+    drift = np.abs(s64.sums() - t0) / absum
+    print("ns3d full: conservation drift", drift)
+    assert np.all(drift <= 1e-13)
+    U64, U32 = s64.download(), s32.download()
+    assert np.all(np.isfinite(U64))
+    dev = np.abs(U32 - U64).max(axis=1) / np.abs(U64).max(axis=1)
+    print("ns3d full: mixed state vs FP64 after 2 steps", dev)
+    assert dev.max() <= 1e-5
