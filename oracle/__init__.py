@@ -119,6 +119,8 @@ def lib():
         L.om_step.argtypes = [C.c_void_p, pp, dp, dp, C.c_int, C.c_double, dp, dp,
                               C.POINTER(C.c_int)]
         L.om_sums.argtypes = [C.c_void_p, C.c_int, dp, dp, dp]
+        L.om_poisson_coo.argtypes = [C.c_void_p, ip, ip, dp]
+        L.om_boundary_measure.argtypes = [C.c_void_p, dp]
         L.om_ns_node.argtypes = [C.c_int, pp, dp, dp]
         L.om_viscous_flux.argtypes = [C.c_int, C.c_int, dp, dp, C.c_double, C.c_double, dp, dp,
                                       dp, dp, dp, dp]
@@ -236,6 +238,63 @@ class OracleMesh:
         if st and check:
             raise OracleError(st, "step")
         return U, t.value, dtl.value, done.value
+
+    def poisson_matrix(self):
+        """Matrix of -lap phi integrated over the nodal volumes (Sec.
+        "Integrating the Poisson equation"), scipy CSR [nn x nn]."""
+        import scipy.sparse as sp
+        n = self.nc * self.nv * self.nv
+        I = np.zeros(n, dtype=np.int64)
+        K = np.zeros(n, dtype=np.int64)
+        v = np.zeros(n)
+        lib().om_poisson_coo(self._h, I.ctypes.data_as(C.POINTER(C.c_int64)),
+                             K.ctypes.data_as(C.POINTER(C.c_int64)), _d(v))
+        return sp.coo_matrix((v, (I, K)), shape=(self.nn, self.nn)).tocsr()
+
+    def boundary_measure(self):
+        out = np.zeros(self.nn)
+        lib().om_boundary_measure(self._h, _d(out))
+        return out
+
+    def poisson_solve(self, q, dirichlet=None, phi_D=None, En=None):
+        """Potential phi of -lap phi = q (q = rho / eps0 at the nodes),
+        integrated over the nodal volumes:
+
+          sum_k L_ik phi_k = q_i V_i - E_n,i |S_i^b|   (free node i)
+          phi_i = phi_D,i                              (Dirichlet node i)
+
+        (Sec. "Boundary conditions": Dirichlet rows replaced by the imposed
+        value, Neumann data on the right-hand side, zero Neumann where
+        nothing is imposed).  Without Dirichlet nodes the matrix is
+        singular: a uniform background charge makes the right-hand side
+        compatible (q minus its volume mean) and phi is returned with zero
+        volume mean.  Solved by a sparse direct factorisation."""
+        import scipy.sparse as sp
+        import scipy.sparse.linalg as spla
+        L = self.poisson_matrix()
+        Vn = self.geometry()["Vn"]
+        b = np.asarray(q, dtype=np.float64) * Vn
+        if En is not None:
+            b = b - np.asarray(En, dtype=np.float64) * self.boundary_measure()
+        if dirichlet is not None and np.any(dirichlet):
+            dmask = np.asarray(dirichlet, dtype=bool)
+            free = ~dmask
+            phi = np.zeros(self.nn)
+            phi[dmask] = np.asarray(phi_D, dtype=np.float64)[dmask]
+            rhs = b[free] - L[free][:, dmask] @ phi[dmask]
+            phi[free] = spla.spsolve(L[free][:, free].tocsc(), rhs)
+            return phi
+        b = b - Vn * (b.sum() / Vn.sum())
+        one = np.ones((self.nn, 1))
+        B = sp.bmat([[L, sp.csr_matrix(one)], [sp.csr_matrix(one.T), None]]).tocsc()
+        sol = spla.spsolve(B, np.concatenate([b, [0.0]]))
+        phi = sol[:self.nn]
+        return phi - (Vn @ phi) / Vn.sum()
+
+    def electric_field(self, phi):
+        """E = -grad phi with the nodal gradient of the scheme (volume-weighted
+        mean of the cell gradients), [nd][nn]."""
+        return -self.gradient(np.asarray(phi, dtype=np.float64)[None, :])[0]
 
     def sums(self, U):
         U = _c64(U)

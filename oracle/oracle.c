@@ -990,3 +990,43 @@ void om_sums(const om_mesh *m, int nvar, const double *U, double *sums, double *
     if (abssums) abssums[v] = a + acomp;
   }
 }
+
+/* ------------------------------------------------------------------ */
+/* Poisson operator (Sec. "Integrating the Poisson equation")           */
+/* ------------------------------------------------------------------ */
+
+/* Matrix of -lap phi integrated over the nodal volumes, eq.
+ * (poisson_discretization_cartesian) with its sign turned as in the
+ * remark on the implementation: row i, column k receives
+ * S_i . S_k / (V_tau n_d^2) from every cell tau holding both nodes (the
+ * paper's coefficient a_ik with the opposite sign).  Written as coordinate
+ * triplets, nv * nv per cell in cell order; equal (i, k) pairs are to be
+ * summed by the caller. */
+void om_poisson_coo(const om_mesh *m, int64_t *I, int64_t *K, double *val) {
+  const int nd = m->nd, nv = m->nv;
+  int64_t q = 0;
+  for (int64_t c = 0; c < m->nc; c++) {
+    const double *S = m->S + c * nv * nd;
+    const double w = 1.0 / (m->Vc[c] * nd * nd);
+    for (int a = 0; a < nv; a++)
+      for (int b = 0; b < nv; b++) {
+        double dot = 0.0;
+        for (int d = 0; d < nd; d++) dot += S[a * nd + d] * S[b * nd + d];
+        I[q] = m->cell[c * nv + a];
+        K[q] = m->cell[c * nv + b];
+        val[q] = dot * w;
+        q++;
+      }
+  }
+}
+
+/* |S_i^b| per node: length (2D) or area (3D) of the boundary normal of a
+ * node, 0 away from the boundary; weights the Neumann data E_n (Sec.
+ * "Neumann boundary conditions"). */
+void om_boundary_measure(const om_mesh *m, double *out) {
+  for (int64_t i = 0; i < m->nn; i++) {
+    double s = 0.0;
+    for (int d = 0; d < m->nd; d++) s += m->Sb[i * m->nd + d] * m->Sb[i * m->nd + d];
+    out[i] = m->bnd[i] ? sqrt(s) : 0.0;
+  }
+}

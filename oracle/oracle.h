@@ -86,6 +86,11 @@ int om_timestep(const om_mesh *m, const om_phys *ph, const double *U, const doub
 int om_step(const om_mesh *m, const om_phys *ph, double *U, const double *E, int nsteps,
             double t_end, double *t, double *dt_last, int *steps_done);
 void om_sums(const om_mesh *m, int nvar, const double *U, double *sums, double *abssums);
+
+/* Poisson operator: coordinate triplets (nv*nv per cell) of the matrix of
+ * -lap phi integrated over the nodal volumes, and |S_i^b| per node */
+void om_poisson_coo(const om_mesh *m, int64_t *I, int64_t *K, double *val);
+void om_boundary_measure(const om_mesh *m, double *out);
 int om_nvar(int nd, const om_phys *ph);
 
 #endif

@@ -172,6 +172,54 @@ __device__ inline void cell_rel_coords(const DevMesh& m, const double* sX, int m
 
 __device__ inline int slot_node_id(int v) { return v >= 0 ? v : ~v; }
 
+// Element i (not a compile-time constant) of a small register array, by a
+// chain of selects, so that the array stays in registers inside a loop that
+// is not unrolled.
+template <int N, typename T>
+__device__ __attribute__((always_inline)) inline T pick(const T (&x)[N], int i) {
+  T r = x[0];
+#pragma unroll
+  for (int k = 1; k < N; ++k) r = i == k ? x[k] : r;
+  return r;
+}
+
+// Cell-edge ed (not unrolled) of a cell: its vertices a < b, their tile-local
+// nodes, the dual-face vector S_ab = (S_a - S_b)/(n_d n_v) and the edge
+// vector X_b - X_a from the relative coordinates e[k-1] = X_k - X_0, with the
+// same arithmetic as the unrolled form; coef[k] = +1 (k = a), -1 (k = b) or 0
+// carries the flux to the cell vertex sums as fma(F, coef[k], acc[k]), which
+// rounds like acc[a] + F and acc[b] - F.
+template <int ND, typename CT>
+struct EdgeRolled {
+  int a, b, la, lb;
+  CT S[ND], dx[ND];
+  double coef[ND + 1];
+};
+
+template <int ND, typename CT>
+__device__ __attribute__((always_inline)) inline void edge_rolled(int ed, const int (&l)[ND + 1],
+                                                                  const double (&e)[ND][ND],
+                                                                  const double (&Sd)[ND + 1][ND],
+                                                                  EdgeRolled<ND, CT>& g) {
+  constexpr int NV = ND + 1;
+  g.a = Edges<ND>::a(ed);
+  g.b = Edges<ND>::b(ed);
+  g.la = pick(l, g.a);
+  g.lb = pick(l, g.b);
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    double sc[NV], ec[ND];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) sc[k] = Sd[k][d];
+#pragma unroll
+    for (int k = 0; k < ND; ++k) ec[k] = e[k][d];
+    g.S[d] = CT((pick(sc, g.a) - pick(sc, g.b)) * (1.0 / double(ND * NV)));
+    g.dx[d] = CT((g.a == 0 ? 0.0 : -pick(ec, g.a - 1)) + pick(ec, g.b - 1));
+  }
+#pragma unroll
+  for (int k = 0; k < NV; ++k) g.coef[k] = k == g.a ? 1.0 : (k == g.b ? -1.0 : 0.0);
+}
+
 // Tile topology read at the start of a tile pass, so that its loads are in
 // flight together with the staging of the node data: this thread's cell and
 // slot (the first iteration of the cell and slot loops) and up to NV of the
@@ -1469,15 +1517,15 @@ __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ W,
     for (int k = 0; k < NV; ++k)
 #pragma unroll
       for (int v = 0; v < NVAR; ++v) acc[k][v] = 0.0;
+    // one edge at a time: the multi-species fluxes have many temporaries,
+    // and the cell vertex sums stay in registers (static indices)
+#pragma unroll 1
     for (int ed = 0; ed < NE; ++ed) {
-      const int a = Edges<ND>::a(ed), b = Edges<ND>::b(ed);
-      const int la = l[a], lb = l[b];
-      CT S[ND], dx[ND];
-#pragma unroll
-      for (int d = 0; d < ND; ++d) {
-        S[d] = CT((Sd[a][d] - Sd[b][d]) * (1.0 / double(ND * NV)));
-        dx[d] = CT((a == 0 ? 0.0 : -e[a - 1][d]) + e[b - 1][d]);
-      }
+      EdgeRolled<ND, CT> g;
+      edge_rolled<ND, CT>(ed, l, e, Sd, g);
+      const int la = g.la, lb = g.lb;
+      const CT(&S)[ND] = g.S;
+      const CT(&dx)[ND] = g.dx;
       CT WL[NR], WR[NR];
 #pragma unroll
       for (int v = 0; v < NR; ++v) {
@@ -1517,8 +1565,8 @@ __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ W,
 #pragma unroll
       for (int v = 0; v < NVAR; ++v) {
         const double fv = double(F[v]) - double(Fv[v]);
-        acc[a][v] += fv;
-        acc[b][v] -= fv;
+#pragma unroll
+        for (int k = 0; k < NV; ++k) acc[k][v] = fma(fv, g.coef[k], acc[k][v]);
       }
     }
 #pragma unroll
