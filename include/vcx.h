@@ -171,6 +171,16 @@ vcx_status vcx_solver_create(vcx_mesh mesh, const vcx_physics *phys, const doubl
                              vcx_solver *out);
 vcx_status vcx_solver_destroy(vcx_solver s);
 
+/* Replace the prescribed electric field of a drift-diffusion solver
+ * (E [ndim][nnodes], caller order, host or device per is_device), e.g. with
+ * the field of vcx_poisson_field for a step coupled to the Poisson
+ * equation.  The time-step candidates of the current state are recomputed
+ * with the new field (Sec. "Time step computation"), so the next step's
+ * time step uses it; time and step count are kept.  Synchronises the
+ * mesh's stream.  Errors: VCX_E_ARG (NULL argument, or a model without a
+ * field), VCX_E_HIP. */
+vcx_status vcx_solver_set_field(vcx_solver s, const double *E, int is_device);
+
 /* Number of conserved variables (gas 2 + ndim + nspecies; DD nspecies). */
 int vcx_solver_nvar(vcx_solver s);
 
@@ -298,6 +308,53 @@ vcx_status vcx_server_stats(vcx_server sv, double *out);
 /* Cancel queued requests (VCX_E_BUSY), finish running ones, stop the
  * scheduler and free the server. */
 vcx_status vcx_server_destroy(vcx_server sv);
+
+/* ---- Poisson solve for the electric field (Sec. "Integrating the Poisson
+ * equation", Sec. "Boundary conditions") ------------------------------- */
+typedef struct vcx_poisson_s *vcx_poisson;
+
+/* Operator of a mesh: the matrix of -lap phi integrated over the nodal
+ * volumes (eq. poisson_discretization_cartesian with the sign of the remark
+ * on the implementation), L_ik = sum over the cells holding nodes i and k of
+ * S_i . S_k / (V_tau n_d^2), assembled in FP64 on the host and kept on the
+ * device, with the nodal-gradient operator of E = -grad phi.
+ * dirichlet: [nnodes] (caller order), nonzero marks a Dirichlet node, or
+ *   NULL for none.  Every other node is free; a free boundary node takes
+ *   Neumann data (zero normal field unless E_n is given to the solve).
+ * Without Dirichlet nodes (periodic or all-Neumann meshes) the system is
+ * singular: a uniform background charge makes it compatible (the solve
+ * removes the volume mean of q) and phi is returned with zero volume mean.
+ * The operator lives on the mesh's stream; the mesh must outlive it.
+ * Errors: VCX_E_ARG (NULL mesh or out, too large for 32-bit indices),
+ * VCX_E_OOM, VCX_E_HIP. */
+vcx_status vcx_poisson_create(vcx_mesh mesh, const int32_t *dirichlet, vcx_poisson *out);
+vcx_status vcx_poisson_destroy(vcx_poisson p);
+
+/* Solve sum_k L_ik phi_k = q_i V_i - En_i |S_i^b| on free nodes with
+ * phi_i = phiD_i on Dirichlet nodes, by Jacobi-preconditioned conjugate
+ * gradients in FP64 on the device (dot products reduced in a fixed order:
+ * bitwise reproducible).  Arrays are [nnodes] in caller order, all host or
+ * all device (is_device):
+ *   q    rho / eps0 at the nodes (required);
+ *   phiD imposed potential, read on Dirichlet nodes only (NULL: zero);
+ *   En   imposed normal field, read on free boundary nodes (NULL: zero);
+ *   phi  in: initial guess on free nodes; out: the potential.
+ * Stops when |r| <= tol |b - L_fD phi_D| (or tol |r_0| when that is zero),
+ * or after max_iter iterations.  iters and relres (may be NULL) receive
+ * the iteration count and |r| over that reference.  Returns VCX_E_STATE,
+ * with phi holding the last iterate, when max_iter is reached first;
+ * VCX_E_ARG for NULL q or phi, tol <= 0 or max_iter < 0; VCX_E_HIP. */
+vcx_status vcx_poisson_solve(vcx_poisson p, const double *q, const double *phiD, const double *En,
+                             double *phi, int is_device, double tol, int max_iter, int *iters,
+                             double *relres);
+
+/* E = -grad phi at the nodes with the nodal gradient of the scheme (the
+ * volume-weighted mean of the cell gradients): phi [nnodes] in, E
+ * [ndim][nnodes] out, caller order, host or device (is_device).  A
+ * drift-diffusion solver takes the result through vcx_solver_create or, for
+ * a coupled step, vcx_solver_set_field. */
+vcx_status vcx_poisson_field(vcx_poisson p, const double *phi, double *E, int is_device);
+
 
 /* sum_i V_i U_i per variable [nvar] (FP64, fixed-order tree). */
 vcx_status vcx_conservation_sums(vcx_solver s, double *sums);

@@ -41,6 +41,7 @@ def build(verbose: bool = False) -> str:
         host_o = os.path.join(tmp, "vcx_mesh.o")
         serv_o = os.path.join(tmp, "vcx_server.o")
         dev_o = os.path.join(tmp, "vcx_capi.o")
+        poi_o = os.path.join(tmp, "vcx_poisson.o")
         rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
         procs = [
             subprocess.Popen(["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", *inc, "-c",
@@ -50,15 +51,18 @@ def build(verbose: bool = False) -> str:
                               "-c", os.path.join(CSRC, "vcx_server.cpp"), "-o", serv_o]),
             subprocess.Popen(["hipcc", *HIP_FLAGS, *inc, "-c",
                               os.path.join(CSRC, "vcx_capi.hip"), "-o", dev_o]),
+            subprocess.Popen(["hipcc", *HIP_FLAGS, *inc, "-c",
+                              os.path.join(CSRC, "vcx_poisson.hip"), "-o", poi_o]),
         ]
         if verbose:
-            print("compiling vcx_mesh.cpp, vcx_server.cpp (g++) and vcx_capi.hip (hipcc)", flush=True)
+            print("compiling vcx_mesh.cpp, vcx_server.cpp (g++), vcx_capi.hip and vcx_poisson.hip (hipcc)",
+                  flush=True)
         rcs = [p.wait() for p in procs]
         if any(rcs):
             raise RuntimeError(f"compilation failed (exit codes {rcs})")
         tmp_lib = LIB + ".tmp"
         _run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", tmp_lib, host_o,
-              serv_o, dev_o],
+              serv_o, dev_o, poi_o],
              verbose)
         os.replace(tmp_lib, LIB)
     return LIB

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "vcx.h"
+#include "vcx_mesh.h"
 
 namespace vcx {
 
@@ -50,6 +51,9 @@ vcx_status solver_set_field(vcx_solver s, const double* E);
 vcx_status set_error(vcx_status s, const char* msg);
 int mesh_ndim(vcx_mesh m);
 int64_t mesh_nnodes(vcx_mesh m);
+const HostMesh* mesh_host(vcx_mesh m);        // preprocessed mesh, internal order
+hipStream_t mesh_stream(vcx_mesh m);          // stream of the mesh and its solvers
+const int32_t* mesh_perm_device(vcx_mesh m);  // [nn] internal node -> caller node (device)
 int solver_failed(vcx_solver s);
 
 }  // namespace vcx

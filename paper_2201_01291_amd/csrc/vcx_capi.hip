@@ -776,11 +776,12 @@ static vcx_status reset_scalars(vcx_solver s, double t0, bool prime) {
   return VCX_OK;
 }
 
-// electric field (host, caller order) -> s->E (internal order), synchronised
-static vcx_status upload_field(vcx_solver s, const double* E) {
+// electric field (host or device, caller order) -> s->E (internal order), synchronised
+static vcx_status upload_field(vcx_solver s, const double* E, int is_device = 0) {
   const DevMesh& d = s->mesh->d;
   const size_t nn = (size_t)d.nn;
-  VCX_HIP(hipMemcpyAsync(s->io, E, sizeof(double) * s->nd * nn, hipMemcpyHostToDevice, s->mesh->stream));
+  VCX_HIP(hipMemcpyAsync(s->io, E, sizeof(double) * s->nd * nn,
+                         is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s->mesh->stream));
   hipLaunchKernelGGL(k_gather_rows, dim3((nn + 255) / 256), dim3(256), 0, s->mesh->stream, d.perm,
                      (const double*)s->io, s->E, (int)nn, s->nd);
   VCX_HIP(hipGetLastError());
@@ -791,6 +792,18 @@ static vcx_status upload_field(vcx_solver s, const double* E) {
 vcx_status vcx::solver_set_field(vcx_solver s, const double* E) {
   if (!s || !E || !s->E) return fail(VCX_E_ARG, "no field to set");
   return upload_field(s, E);
+}
+
+extern "C" vcx_status vcx_solver_set_field(vcx_solver s, const double* E, int is_device) {
+  if (!s || !E) return fail(VCX_E_ARG, "NULL argument");
+  if (!s->E) return fail(VCX_E_ARG, "the solver's model has no electric field");
+  VCX_TRY(upload_field(s, E, is_device));
+  if (s->has_state) {
+    // the time-step candidates of the current state follow the new field
+    VCX_TRY(s->kt->node_dt(s, s->W[s->cur]));
+    VCX_HIP(hipStreamSynchronize(s->mesh->stream));
+  }
+  return VCX_OK;
 }
 
 bool vcx::solver_matches(vcx_solver s, vcx_mesh mesh, const vcx_physics* ph) {
@@ -1368,6 +1381,9 @@ bool vcx::batch_compatible(vcx_solver a, vcx_solver b) {
 vcx_status vcx::set_error(vcx_status s, const char* msg) { return fail(s, msg ? msg : ""); }
 int vcx::mesh_ndim(vcx_mesh m) { return m ? m->h.nd : 0; }
 int64_t vcx::mesh_nnodes(vcx_mesh m) { return m ? m->d.nn : 0; }
+const vcx::HostMesh* vcx::mesh_host(vcx_mesh m) { return m ? &m->h : nullptr; }
+hipStream_t vcx::mesh_stream(vcx_mesh m) { return m ? m->stream : nullptr; }
+const int32_t* vcx::mesh_perm_device(vcx_mesh m) { return m ? m->d.perm : nullptr; }
 int vcx::solver_failed(vcx_solver s) { return s ? s->host_flag : 0; }
 
 extern "C" vcx_status vcx_solver_footprint(vcx_mesh mesh, const vcx_physics* phys, size_t* bytes) {

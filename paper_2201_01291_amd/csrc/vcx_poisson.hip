@@ -1,0 +1,601 @@
+// Poisson solve for the electric potential (declarations in include/vcx.h).
+//
+// Sec. "Integrating the Poisson equation": integrating -lap phi = rho/eps0
+// over the nodal volume V_i, with the cell gradient constant in each cell,
+// gives row i of a sparse symmetric system whose coefficient for node k is
+// the sum over the cells holding i and k of S_i . S_k / (V_tau n_d^2).  Since
+// S_k = -n_d V_tau grad(lambda_k) (lambda: barycentric coordinates), this is
+// V_tau grad(lambda_i) . grad(lambda_k), the form assembled here.
+// Sec. "Boundary conditions": Dirichlet rows carry the imposed value,
+// Neumann data enter the right-hand side as -E_n |S_i^b|, and a boundary
+// node with nothing imposed has a zero normal field.
+//
+// Device layout: CSR rows in the internal node order (space-filling curve),
+// FP64 values.  The solve is Jacobi-preconditioned conjugate gradients with
+// two kernels per iteration.  Every dot product is reduced in a fixed order:
+// each block writes one partial, and every block of the next kernel sums all
+// partials in the same order, so all blocks take the same scalars and the
+// iterates are bitwise reproducible.  Convergence is decided on the device;
+// the host launches iterations in chunks and reads one small record per
+// chunk.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "vcx.h"
+#include "vcx_batch.h"
+
+namespace {
+
+using vcx::HostMesh;
+
+constexpr int kThreads = 256;
+constexpr int kMaxBlocks = 1024;
+
+vcx_status err(vcx_status s, const std::string& m) { return vcx::set_error(s, m.c_str()); }
+
+#define PS_HIP(expr)                                                                    \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) return err(VCX_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+struct PoissonDev {
+  int n, nd, nnz, singular;
+  const int* rp;        // [n+1]
+  const int* col;       // [nnz]
+  const double* val;    // [nnz] matrix of -lap phi over the nodal volumes
+  const double* gval;   // [nd][nnz] E = -grad phi: E_d,i = sum_k gval_d,ik phi_k
+  const double* dinv;   // [n] 1 / L_ii on free nodes, 0 on Dirichlet nodes
+  const double* vn;     // [n] nodal volumes
+  const double* sbm;    // [n] |S_i^b| on boundary nodes, 0 elsewhere
+  const int32_t* perm;  // [n] internal -> caller
+};
+
+// Partial-sum rows (one double per block each)
+enum { P_RZ0 = 0, P_RZ1, P_RR0, P_RR1, P_PQ, P_B, P_V, P_BB, P_VX, P_RRI, P_NROWS };
+
+struct CgCtl {
+  int done;       // converged (iterations stop)
+  int iters;      // iterations taken when done
+  int last;       // last iteration started
+  int pad;
+  double rr;      // squared residual norm of the last iterate
+  double ref2;    // squared norm the tolerance is relative to
+};
+
+struct CgVec {
+  double *x, *r, *z, *p0, *p1, *q, *b;
+  double* part;  // [P_NROWS][nb]
+  CgCtl* ctl;
+  int nb;
+};
+
+__device__ double block_sum(double v) {
+  __shared__ double red[kThreads];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double out = red[0];
+  __syncthreads();
+  return out;
+}
+
+// Sum of one row of block partials in a fixed order (same in every block).
+__device__ double sum_partials(const double* row, int nb) {
+  double s = 0.0;
+  for (int k = threadIdx.x; k < nb; k += kThreads) s += row[k];
+  return block_sum(s);
+}
+
+// The stop flag as one value for the whole block (it may be written by
+// block 0 of the same launch while other blocks read it).
+__device__ bool block_done(const CgCtl* ctl) {
+  __shared__ int flag;
+  if (threadIdx.x == 0) flag = __hip_atomic_load(&ctl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  const bool d = flag != 0;
+  __syncthreads();
+  return d;
+}
+
+__device__ void put_partial(double* row, double v) {
+  const double s = block_sum(v);
+  if (threadIdx.x == 0) row[blockIdx.x] = s;
+}
+
+// Right-hand side q V - E_n |S^b| on free nodes, the initial iterate (guess
+// on free nodes, imposed values on Dirichlet nodes); partial sums of b and V.
+__global__ void __launch_bounds__(kThreads) k_cg_init1(PoissonDev P, CgVec X, const double* __restrict__ q,
+                                                        const double* __restrict__ phiD,
+                                                        const double* __restrict__ En,
+                                                        const double* __restrict__ phi0) {
+  double sb = 0.0, sv = 0.0;
+  for (int i = blockIdx.x * kThreads + threadIdx.x; i < P.n; i += X.nb * kThreads) {
+    const int o = P.perm[i];
+    const bool free = P.dinv[i] != 0.0;
+    double b = 0.0;
+    if (free) {
+      b = q[o] * P.vn[i];
+      if (En) b -= En[o] * P.sbm[i];
+      X.x[i] = phi0 ? phi0[o] : 0.0;
+    } else {
+      X.x[i] = phiD ? phiD[o] : 0.0;
+    }
+    X.b[i] = b;
+    sb += b;
+    sv += P.vn[i];
+  }
+  put_partial(X.part + P_B * X.nb, sb);
+  put_partial(X.part + P_V * X.nb, sv);
+}
+
+// Singular systems: the uniform background that makes b sum to zero.
+// Initial residual r = b - L x on free rows, z = D^-1 r, p = 0; partial sums
+// of r.z, r.r and |b - L_fD x_D|^2 (the norm the tolerance refers to).
+__global__ void __launch_bounds__(kThreads) k_cg_init2(PoissonDev P, CgVec X) {
+  double bmean = 0.0;
+  if (P.singular) bmean = sum_partials(X.part + P_B * X.nb, X.nb) / sum_partials(X.part + P_V * X.nb, X.nb);
+  double rz = 0.0, rr = 0.0, bb = 0.0;
+  for (int i = blockIdx.x * kThreads + threadIdx.x; i < P.n; i += X.nb * kThreads) {
+    const double di = P.dinv[i];
+    double r = 0.0;
+    if (di != 0.0) {
+      double b = X.b[i];
+      if (P.singular) {
+        b -= P.vn[i] * bmean;
+        X.b[i] = b;
+      }
+      double ax = 0.0, ad = 0.0;
+      for (int e = P.rp[i]; e < P.rp[i + 1]; ++e) {
+        const int k = P.col[e];
+        const double t = P.val[e] * X.x[k];
+        ax += t;
+        if (P.dinv[k] == 0.0) ad += t;
+      }
+      r = b - ax;
+      const double bt = b - ad;
+      bb += bt * bt;
+    }
+    const double z = di * r;
+    X.r[i] = r;
+    X.z[i] = z;
+    X.p0[i] = 0.0;
+    X.p1[i] = 0.0;
+    rz += r * z;
+    rr += r * r;
+  }
+  put_partial(X.part + P_RZ0 * X.nb, rz);
+  put_partial(X.part + P_RR0 * X.nb, rr);
+  put_partial(X.part + P_RRI * X.nb, rr);
+  put_partial(X.part + P_BB * X.nb, bb);
+}
+
+// Iteration k, first half: stop test on the residual of iterate k; else
+// beta = (r.z)_k / (r.z)_(k-1), p_k = z + beta p_(k-1) and q = L p_k (rows
+// form p_k of their neighbours themselves, in the same arithmetic as the
+// neighbour's own row), partial sums of p.q.
+__global__ void __launch_bounds__(kThreads) k_cg_a(PoissonDev P, CgVec X, int k, double tol2) {
+  if (block_done(X.ctl)) return;
+  const int cur = k & 1;
+  const double rz = sum_partials(X.part + (P_RZ0 + cur) * X.nb, X.nb);
+  const double rr = sum_partials(X.part + (P_RR0 + cur) * X.nb, X.nb);
+  // relative to |b - L_fD x_D| (the free system's right-hand side), or to
+  // the initial residual when that is zero
+  const double bb = sum_partials(X.part + P_BB * X.nb, X.nb);
+  const double ref2 = bb > 0.0 ? bb : sum_partials(X.part + P_RRI * X.nb, X.nb);
+  const bool conv = !(rr > tol2 * ref2);  // also stops on rr = 0
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    X.ctl->last = k;
+    X.ctl->rr = rr;
+    X.ctl->ref2 = ref2;
+    if (conv) {
+      __hip_atomic_store(&X.ctl->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      X.ctl->iters = k;
+    }
+  }
+  if (conv) return;
+  const double beta = k == 0 ? 0.0 : rz / sum_partials(X.part + (P_RZ0 + (cur ^ 1)) * X.nb, X.nb);
+  const double* po = cur ? X.p1 : X.p0;  // p_(k-1) (zero at k = 0)
+  double* pn = cur ? X.p0 : X.p1;        // p_k
+  double pq = 0.0;
+  for (int i = blockIdx.x * kThreads + threadIdx.x; i < P.n; i += X.nb * kThreads) {
+    double p = 0.0, qv = 0.0;
+    if (P.dinv[i] != 0.0) {
+      p = X.z[i] + beta * po[i];
+      for (int e = P.rp[i]; e < P.rp[i + 1]; ++e) {
+        const int j = P.col[e];
+        qv += P.val[e] * (X.z[j] + beta * po[j]);
+      }
+    }
+    pn[i] = p;
+    X.q[i] = qv;
+    pq += p * qv;
+  }
+  put_partial(X.part + P_PQ * X.nb, pq);
+}
+
+// Iteration k, second half: alpha = (r.z)_k / (p.q); x += alpha p,
+// r -= alpha q, z = D^-1 r; partial sums of r.z and r.r of iterate k+1.
+__global__ void __launch_bounds__(kThreads) k_cg_b(PoissonDev P, CgVec X, int k) {
+  if (block_done(X.ctl)) return;
+  const int cur = k & 1, nxt = cur ^ 1;
+  const double alpha = sum_partials(X.part + (P_RZ0 + cur) * X.nb, X.nb) / sum_partials(X.part + P_PQ * X.nb, X.nb);
+  const double* pn = cur ? X.p0 : X.p1;
+  double rz = 0.0, rr = 0.0;
+  for (int i = blockIdx.x * kThreads + threadIdx.x; i < P.n; i += X.nb * kThreads) {
+    const double di = P.dinv[i];
+    if (di == 0.0) continue;
+    X.x[i] += alpha * pn[i];
+    const double r = X.r[i] - alpha * X.q[i];
+    const double z = di * r;
+    X.r[i] = r;
+    X.z[i] = z;
+    rz += r * z;
+    rr += r * r;
+  }
+  put_partial(X.part + (P_RZ0 + nxt) * X.nb, rz);
+  put_partial(X.part + (P_RR0 + nxt) * X.nb, rr);
+}
+
+// Singular systems: phi with zero volume mean.
+__global__ void __launch_bounds__(kThreads) k_cg_mean1(PoissonDev P, CgVec X) {
+  double s = 0.0;
+  for (int i = blockIdx.x * kThreads + threadIdx.x; i < P.n; i += X.nb * kThreads) s += P.vn[i] * X.x[i];
+  put_partial(X.part + P_VX * X.nb, s);
+}
+
+__global__ void __launch_bounds__(kThreads) k_cg_mean2(PoissonDev P, CgVec X) {
+  const double m = sum_partials(X.part + P_VX * X.nb, X.nb) / sum_partials(X.part + P_V * X.nb, X.nb);
+  for (int i = blockIdx.x * kThreads + threadIdx.x; i < P.n; i += X.nb * kThreads) X.x[i] -= m;
+}
+
+__global__ void __launch_bounds__(kThreads) k_cg_scatter(PoissonDev P, const double* __restrict__ x,
+                                                          double* __restrict__ out) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i < P.n) out[P.perm[i]] = x[i];
+}
+
+__global__ void __launch_bounds__(kThreads) k_gather(PoissonDev P, const double* __restrict__ in,
+                                                      double* __restrict__ x) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i < P.n) x[i] = in[P.perm[i]];
+}
+
+// E = -grad phi at the nodes (phi in internal order), out in caller order.
+__global__ void __launch_bounds__(kThreads) k_field(PoissonDev P, const double* __restrict__ phi,
+                                                     double* __restrict__ E) {
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i >= P.n) return;
+  double e[3] = {0.0, 0.0, 0.0};
+  for (int q = P.rp[i]; q < P.rp[i + 1]; ++q) {
+    const double f = phi[P.col[q]];
+    for (int d = 0; d < P.nd; ++d) e[d] += P.gval[(size_t)d * P.nnz + q] * f;
+  }
+  const int o = P.perm[i];
+  for (int d = 0; d < P.nd; ++d) E[(size_t)d * P.n + o] = e[d];
+}
+
+// Host assembly: per node, the (column, value, gradient weights) entries of
+// its cells, sorted by column with equal columns summed in cell order.
+struct Entry {
+  int col;
+  int cell;
+  double v, g[3];
+};
+
+void simplex_grads(int nd, const double (&X)[4][3], double (&grad)[4][3], double& vol) {
+  if (nd == 2) {
+    const double ax = X[1][0] - X[0][0], ay = X[1][1] - X[0][1];
+    const double bx = X[2][0] - X[0][0], by = X[2][1] - X[0][1];
+    const double det = ax * by - ay * bx;
+    vol = 0.5 * std::fabs(det);
+    // rows of the inverse of [e1 e2]^T: grad lambda_1, grad lambda_2
+    grad[1][0] = by / det;
+    grad[1][1] = -bx / det;
+    grad[2][0] = -ay / det;
+    grad[2][1] = ax / det;
+    grad[0][0] = -(grad[1][0] + grad[2][0]);
+    grad[0][1] = -(grad[1][1] + grad[2][1]);
+    return;
+  }
+  double e[3][3];
+  for (int k = 0; k < 3; ++k)
+    for (int d = 0; d < 3; ++d) e[k][d] = X[k + 1][d] - X[0][d];
+  // grad lambda_k (k = 1..3) are the rows of the inverse transpose of the
+  // matrix with rows e_k: cross products of the other two edge vectors / det
+  const double c0[3] = {e[1][1] * e[2][2] - e[1][2] * e[2][1], e[1][2] * e[2][0] - e[1][0] * e[2][2],
+                        e[1][0] * e[2][1] - e[1][1] * e[2][0]};
+  const double c1[3] = {e[2][1] * e[0][2] - e[2][2] * e[0][1], e[2][2] * e[0][0] - e[2][0] * e[0][2],
+                        e[2][0] * e[0][1] - e[2][1] * e[0][0]};
+  const double c2[3] = {e[0][1] * e[1][2] - e[0][2] * e[1][1], e[0][2] * e[1][0] - e[0][0] * e[1][2],
+                        e[0][0] * e[1][1] - e[0][1] * e[1][0]};
+  const double det = e[0][0] * c0[0] + e[0][1] * c0[1] + e[0][2] * c0[2];
+  vol = std::fabs(det) / 6.0;
+  for (int d = 0; d < 3; ++d) {
+    grad[1][d] = c0[d] / det;
+    grad[2][d] = c1[d] / det;
+    grad[3][d] = c2[d] / det;
+    grad[0][d] = -(grad[1][d] + grad[2][d] + grad[3][d]);
+  }
+}
+
+}  // namespace
+
+struct vcx_poisson_s {
+  vcx_mesh mesh = nullptr;
+  hipStream_t stream = nullptr;
+  PoissonDev P{};
+  CgVec X{};
+  std::vector<void*> allocs;
+  double* stage = nullptr;  // [4][n] caller-order inputs
+  double* fbuf = nullptr;   // [nd][n] field rows for host outputs
+  CgCtl* ctl_host = nullptr;
+  int n = 0, nd = 0;
+};
+
+static vcx_status dev_alloc(vcx_poisson p, size_t bytes, void** out) {
+  PS_HIP(hipMalloc(out, std::max<size_t>(bytes, 8)));
+  p->allocs.push_back(*out);
+  return VCX_OK;
+}
+
+template <typename T>
+static vcx_status upload(vcx_poisson p, const std::vector<T>& h, const T** out) {
+  void* d = nullptr;
+  vcx_status st = dev_alloc(p, sizeof(T) * h.size(), &d);
+  if (st != VCX_OK) return st;
+  if (!h.empty()) PS_HIP(hipMemcpy(d, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice));
+  *out = static_cast<const T*>(d);
+  return VCX_OK;
+}
+
+static void release(vcx_poisson p) {
+  if (p->stream) (void)hipStreamSynchronize(p->stream);
+  for (void* a : p->allocs) (void)hipFree(a);
+  if (p->ctl_host) (void)hipHostFree(p->ctl_host);
+  delete p;
+}
+
+extern "C" vcx_status vcx_poisson_create(vcx_mesh mesh, const int32_t* dirichlet, vcx_poisson* out) {
+  if (!mesh || !out) return err(VCX_E_ARG, "NULL argument");
+  *out = nullptr;
+  const HostMesh& h = *vcx::mesh_host(mesh);
+  const int nd = h.nd, nv = h.nv;
+  const int64_t n = h.nn, nc = h.nc;
+  if (n >= (int64_t)1 << 31) return err(VCX_E_ARG, "mesh too large for 32-bit rows");
+  // Dirichlet flags in the internal order
+  std::vector<char> dir((size_t)n, 0);
+  bool any_dir = false;
+  if (dirichlet)
+    for (int64_t i = 0; i < n; ++i)
+      if (dirichlet[h.perm[i]]) dir[(size_t)i] = 1, any_dir = true;
+  // node -> cells incidence, cells ascending
+  std::vector<int64_t> nc_ptr((size_t)n + 1, 0);
+  for (int64_t c = 0; c < nc; ++c)
+    for (int k = 0; k < nv; ++k) nc_ptr[(size_t)h.cell[(size_t)k * nc + c] + 1]++;
+  for (int64_t i = 0; i < n; ++i) nc_ptr[(size_t)i + 1] += nc_ptr[(size_t)i];
+  std::vector<int64_t> fill(nc_ptr.begin(), nc_ptr.end() - 1);
+  std::vector<int32_t> nc_cell((size_t)nc_ptr[(size_t)n]);
+  std::vector<int8_t> nc_vert((size_t)nc_ptr[(size_t)n]);
+  for (int64_t c = 0; c < nc; ++c)
+    for (int k = 0; k < nv; ++k) {
+      const int64_t i = h.cell[(size_t)k * nc + c];
+      nc_cell[(size_t)fill[(size_t)i]] = (int32_t)c;
+      nc_vert[(size_t)fill[(size_t)i]++] = (int8_t)k;
+    }
+  // rows
+  std::vector<int32_t> rp((size_t)n + 1, 0), col;
+  std::vector<double> val, gv[3], dinv((size_t)n, 0.0), sbm((size_t)n, 0.0);
+  col.reserve((size_t)n * (nd == 2 ? 7 : 15));
+  val.reserve(col.capacity());
+  std::vector<Entry> ent;
+  for (int64_t i = 0; i < n; ++i) {
+    ent.clear();
+    for (int64_t t = nc_ptr[(size_t)i]; t < nc_ptr[(size_t)i + 1]; ++t) {
+      const int64_t c = nc_cell[(size_t)t];
+      const int a = nc_vert[(size_t)t];
+      double X[4][3] = {}, grad[4][3] = {}, vol = 0.0;
+      for (int k = 0; k < nv; ++k) {
+        const int64_t g = h.cell[(size_t)k * nc + c];
+        for (int d = 0; d < nd; ++d) {
+          double x = h.x[(size_t)d * n + g];
+          if (k > 0 && h.has_period) x += vcx::shift_of(h.shift[(size_t)c], k, d, nd) * h.period[d];
+          X[k][d] = x;
+        }
+      }
+      simplex_grads(nd, X, grad, vol);
+      for (int k = 0; k < nv; ++k) {
+        Entry e{};
+        e.col = h.cell[(size_t)k * nc + c];
+        e.cell = (int)c;
+        double dot = 0.0;
+        for (int d = 0; d < nd; ++d) dot += grad[a][d] * grad[k][d];
+        e.v = vol * dot;
+        // E_i = -(1/V_i) sum_tau (V_tau/n_v) grad phi_tau, grad phi_tau = sum_k phi_k grad lambda_k
+        for (int d = 0; d < nd; ++d) e.g[d] = -(vol / nv) * grad[k][d];
+        ent.push_back(e);
+      }
+    }
+    std::stable_sort(ent.begin(), ent.end(), [](const Entry& x, const Entry& y) { return x.col < y.col; });
+    const double inv_v = 1.0 / h.vnode[(size_t)i];
+    size_t q = 0;
+    while (q < ent.size()) {
+      const int c = ent[q].col;
+      double v = 0.0, g[3] = {0, 0, 0};
+      for (; q < ent.size() && ent[q].col == c; ++q) {
+        v += ent[q].v;
+        for (int d = 0; d < nd; ++d) g[d] += ent[q].g[d];
+      }
+      if (dir[(size_t)i] && c != i) v = 0.0;  // Dirichlet row: identity (kept out of the CG)
+      col.push_back(c);
+      val.push_back(v);
+      for (int d = 0; d < nd; ++d) gv[d].push_back(g[d] * inv_v);
+      if (c == i && !dir[(size_t)i]) dinv[(size_t)i] = 1.0 / v;
+    }
+    rp[(size_t)i + 1] = (int32_t)col.size();
+  }
+  if (col.size() >= ((size_t)1 << 31)) return err(VCX_E_ARG, "operator too large for 32-bit indices");
+  for (size_t b = 0; b < h.bnd_node.size(); ++b) {
+    double s = 0.0;
+    for (int d = 0; d < nd; ++d) s += h.bnd_S[(size_t)d * h.bnd_node.size() + b] * h.bnd_S[(size_t)d * h.bnd_node.size() + b];
+    sbm[(size_t)h.bnd_node[b]] = std::sqrt(s);
+  }
+  std::vector<double> gall;
+  gall.reserve(col.size() * nd);
+  for (int d = 0; d < nd; ++d) gall.insert(gall.end(), gv[d].begin(), gv[d].end());
+
+  auto* p = new (std::nothrow) vcx_poisson_s();
+  if (!p) return err(VCX_E_OOM, "host allocation failed");
+  p->mesh = mesh;
+  p->stream = vcx::mesh_stream(mesh);
+  p->n = (int)n;
+  p->nd = nd;
+  PoissonDev& P = p->P;
+  P.n = (int)n;
+  P.nd = nd;
+  P.nnz = (int)col.size();
+  P.singular = any_dir ? 0 : 1;
+  P.perm = vcx::mesh_perm_device(mesh);
+  vcx_status st = VCX_OK;
+  auto chk = [&](vcx_status s) {
+    if (st == VCX_OK) st = s;
+  };
+  chk(upload(p, rp, &P.rp));
+  chk(upload(p, col, &P.col));
+  chk(upload(p, val, &P.val));
+  chk(upload(p, gall, &P.gval));
+  chk(upload(p, dinv, &P.dinv));
+  chk(upload(p, h.vnode, &P.vn));
+  chk(upload(p, sbm, &P.sbm));
+  CgVec& X = p->X;
+  X.nb = (int)std::min<int64_t>(kMaxBlocks, (n + kThreads - 1) / kThreads);
+  double** vecs[7] = {&X.x, &X.r, &X.z, &X.p0, &X.p1, &X.q, &X.b};
+  for (double** v : vecs) {
+    void* d = nullptr;
+    chk(dev_alloc(p, sizeof(double) * (size_t)n, &d));
+    *v = static_cast<double*>(d);
+  }
+  void* d = nullptr;
+  chk(dev_alloc(p, sizeof(double) * P_NROWS * (size_t)X.nb, &d));
+  X.part = static_cast<double*>(d);
+  chk(dev_alloc(p, sizeof(CgCtl), &d));
+  X.ctl = static_cast<CgCtl*>(d);
+  chk(dev_alloc(p, sizeof(double) * 4 * (size_t)n, &d));
+  p->stage = static_cast<double*>(d);
+  chk(dev_alloc(p, sizeof(double) * nd * (size_t)n, &d));
+  p->fbuf = static_cast<double*>(d);
+  if (st == VCX_OK && hipHostMalloc(reinterpret_cast<void**>(&p->ctl_host), sizeof(CgCtl)) != hipSuccess)
+    st = err(VCX_E_OOM, "pinned host allocation failed");
+  if (st != VCX_OK) {
+    release(p);
+    return st;
+  }
+  *out = p;
+  return VCX_OK;
+}
+
+extern "C" vcx_status vcx_poisson_destroy(vcx_poisson p) {
+  if (!p) return err(VCX_E_ARG, "NULL handle");
+  release(p);
+  return VCX_OK;
+}
+
+// caller-order input: device pointer as is, host array staged on the device
+static vcx_status stage_in(vcx_poisson p, const double* src, int slot, int is_device, const double** out) {
+  if (!src) {
+    *out = nullptr;
+    return VCX_OK;
+  }
+  if (is_device) {
+    *out = src;
+    return VCX_OK;
+  }
+  double* dst = p->stage + (size_t)slot * p->n;
+  PS_HIP(hipMemcpyAsync(dst, src, sizeof(double) * p->n, hipMemcpyHostToDevice, p->stream));
+  *out = dst;
+  return VCX_OK;
+}
+
+extern "C" vcx_status vcx_poisson_solve(vcx_poisson p, const double* q, const double* phiD, const double* En,
+                                        double* phi, int is_device, double tol, int max_iter, int* iters,
+                                        double* relres) {
+  if (!p || !q || !phi) return err(VCX_E_ARG, "NULL argument");
+  if (!(tol > 0.0) || max_iter < 0) return err(VCX_E_ARG, "need tol > 0 and max_iter >= 0");
+  const double *dq, *dD, *dE, *d0;
+  vcx_status st = stage_in(p, q, 0, is_device, &dq);
+  if (st == VCX_OK) st = stage_in(p, phiD, 1, is_device, &dD);
+  if (st == VCX_OK) st = stage_in(p, En, 2, is_device, &dE);
+  if (st == VCX_OK) st = stage_in(p, phi, 3, is_device, &d0);
+  if (st != VCX_OK) return st;
+  const dim3 grid(p->X.nb), block(kThreads);
+  PS_HIP(hipMemsetAsync(p->X.ctl, 0, sizeof(CgCtl), p->stream));
+  hipLaunchKernelGGL(k_cg_init1, grid, block, 0, p->stream, p->P, p->X, dq, dD, dE, d0);
+  hipLaunchKernelGGL(k_cg_init2, grid, block, 0, p->stream, p->P, p->X);
+  PS_HIP(hipGetLastError());
+  const double tol2 = tol * tol;
+  int k = 0, chunk = 8;
+  bool done = false;
+  while (!done) {
+    // iterations k .. k+c-1, then the stop test of iterate k+c (which also
+    // does the first half of iteration k+c when it does not stop)
+    const int c = std::min(chunk, max_iter - k);
+    for (int j = 0; j < c; ++j) {
+      hipLaunchKernelGGL(k_cg_a, grid, block, 0, p->stream, p->P, p->X, k + j, tol2);
+      hipLaunchKernelGGL(k_cg_b, grid, block, 0, p->stream, p->P, p->X, k + j);
+    }
+    k += c;
+    hipLaunchKernelGGL(k_cg_a, grid, block, 0, p->stream, p->P, p->X, k, tol2);
+    PS_HIP(hipGetLastError());
+    PS_HIP(hipMemcpyAsync(p->ctl_host, p->X.ctl, sizeof(CgCtl), hipMemcpyDeviceToHost, p->stream));
+    PS_HIP(hipStreamSynchronize(p->stream));
+    done = p->ctl_host->done || k >= max_iter;
+    chunk = std::min(chunk * 2, 256);
+    if (!done) {
+      // the test launch above did iteration k's first half: finish it
+      hipLaunchKernelGGL(k_cg_b, grid, block, 0, p->stream, p->P, p->X, k);
+      k += 1;
+    }
+  }
+  if (p->P.singular) {
+    hipLaunchKernelGGL(k_cg_mean1, grid, block, 0, p->stream, p->P, p->X);
+    hipLaunchKernelGGL(k_cg_mean2, grid, block, 0, p->stream, p->P, p->X);
+  }
+  double* dst = is_device ? phi : p->stage;
+  hipLaunchKernelGGL(k_cg_scatter, dim3((p->n + kThreads - 1) / kThreads), block, 0, p->stream, p->P,
+                     (const double*)p->X.x, dst);
+  PS_HIP(hipGetLastError());
+  if (!is_device) PS_HIP(hipMemcpyAsync(phi, p->stage, sizeof(double) * p->n, hipMemcpyDeviceToHost, p->stream));
+  PS_HIP(hipStreamSynchronize(p->stream));
+  const CgCtl& c = *p->ctl_host;
+  const int it = c.done ? c.iters : c.last;
+  const double rel = c.ref2 > 0.0 ? std::sqrt(c.rr / c.ref2) : std::sqrt(c.rr);
+  if (iters) *iters = it;
+  if (relres) *relres = rel;
+  if (!c.done) return err(VCX_E_STATE, "conjugate gradients did not reach the tolerance within max_iter");
+  return VCX_OK;
+}
+
+extern "C" vcx_status vcx_poisson_field(vcx_poisson p, const double* phi, double* E, int is_device) {
+  if (!p || !phi || !E) return err(VCX_E_ARG, "NULL argument");
+  const double* dphi;
+  vcx_status st = stage_in(p, phi, 0, is_device, &dphi);
+  if (st != VCX_OK) return st;
+  const dim3 g1((p->n + kThreads - 1) / kThreads), block(kThreads);
+  double* tmp = p->stage + (size_t)p->n;  // phi in the internal order
+  hipLaunchKernelGGL(k_gather, g1, block, 0, p->stream, p->P, dphi, tmp);
+  double* rows = is_device ? E : p->fbuf;
+  hipLaunchKernelGGL(k_field, g1, block, 0, p->stream, p->P, (const double*)tmp, rows);
+  PS_HIP(hipGetLastError());
+  if (!is_device)
+    PS_HIP(hipMemcpyAsync(E, p->fbuf, sizeof(double) * (size_t)p->nd * p->n, hipMemcpyDeviceToHost, p->stream));
+  PS_HIP(hipStreamSynchronize(p->stream));
+  return VCX_OK;
+}

@@ -34,6 +34,8 @@ EXPORTS = (
     "vcx_solve_batch_eager", "vcx_solver_footprint", "vcx_server_create", "vcx_server_submit",
     "vcx_server_poll", "vcx_server_wait", "vcx_server_stats", "vcx_server_destroy",
     "vcx_conservation_sums", "vcx_profile_enable", "vcx_profile_query", "vcx_last_error",
+    "vcx_solver_set_field", "vcx_poisson_create", "vcx_poisson_destroy", "vcx_poisson_solve",
+    "vcx_poisson_field",
 )
 
 
@@ -123,6 +125,12 @@ def lib():
         L.vcx_profile_enable.argtypes = [vp, C.c_int]
         L.vcx_profile_query.argtypes = [vp, C.c_char_p, i64p, dp]
         L.vcx_last_error.restype = C.c_char_p
+        L.vcx_solver_set_field.argtypes = [vp, vp, C.c_int]
+        L.vcx_poisson_create.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(vp)]
+        L.vcx_poisson_destroy.argtypes = [vp]
+        L.vcx_poisson_solve.argtypes = [vp, vp, vp, vp, vp, C.c_int, C.c_double, C.c_int,
+                                        C.POINTER(C.c_int), dp]
+        L.vcx_poisson_field.argtypes = [vp, vp, vp, C.c_int]
         for name in EXPORTS:
             if name not in ("vcx_solver_nvar", "vcx_steps_done", "vcx_last_error"):
                 getattr(L, name).restype = C.c_int
@@ -243,6 +251,13 @@ class Solver:
             U = _f64(U)
         p, dev = _ptr(U)
         _check(lib().vcx_state_upload(self.h, p, dev), "vcx_state_upload")
+
+    def set_field(self, E):
+        """Replace the drift-diffusion field E [ndim][nnodes] (host or device)."""
+        if not _is_device_tensor(E):
+            E = _f64(E)
+        p, dev = _ptr(E)
+        _check(lib().vcx_solver_set_field(self.h, p, dev), "vcx_solver_set_field")
 
     def set_time(self, t: float):
         _check(lib().vcx_state_set_time(self.h, float(t)), "vcx_state_set_time")
@@ -375,6 +390,84 @@ class Server:
     def close(self):
         if getattr(self, "h", None):
             _check(lib().vcx_server_destroy(self.h), "vcx_server_destroy")
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Poisson:
+    """Poisson operator of a mesh: potential of -lap phi = q (q = rho/eps0)
+    and the field E = -grad phi (vcx_poisson_*)."""
+
+    def __init__(self, mesh: Mesh, dirichlet=None):
+        self.mesh = mesh
+        h = C.c_void_p()
+        dm = None
+        if dirichlet is not None:
+            dm = np.ascontiguousarray(np.asarray(dirichlet) != 0, dtype=np.int32)
+        _check(lib().vcx_poisson_create(mesh.h, dm.ctypes.data_as(C.POINTER(C.c_int32))
+                                        if dm is not None else None, C.byref(h)), "vcx_poisson_create")
+        self.h = h
+
+    def solve(self, q, phiD=None, En=None, phi0=None, tol: float = 1e-12, max_iter: int = 10000,
+              out=None):
+        """Returns (phi, iterations, relative residual); all arrays host or all
+        device tensors."""
+        dev = _is_device_tensor(q)
+        n = self.mesh.nnodes
+
+        def arr(x):
+            if x is None:
+                return None, None
+            if dev:
+                return x, C.c_void_p(x.data_ptr())
+            a = _f64(x)
+            return a, C.c_void_p(a.ctypes.data)
+
+        qa, qp = arr(q)
+        Da, Dp = arr(phiD)
+        Ea, Ep = arr(En)
+        if out is None:
+            if dev:
+                import torch
+                out = torch.zeros(n, dtype=torch.float64, device=q.device)
+            else:
+                out = np.zeros(n)
+        if phi0 is not None:
+            if dev:
+                out.copy_(phi0)
+            else:
+                out[:] = phi0
+        op = C.c_void_p(out.data_ptr()) if dev else C.c_void_p(out.ctypes.data)
+        it, rel = C.c_int(), C.c_double()
+        _check(lib().vcx_poisson_solve(self.h, qp, Dp, Ep, op, int(dev), float(tol), int(max_iter),
+                                       C.byref(it), C.byref(rel)), "vcx_poisson_solve")
+        return out, it.value, rel.value
+
+    def field(self, phi, out=None):
+        dev = _is_device_tensor(phi)
+        n, nd = self.mesh.nnodes, self.mesh.ndim
+        if out is None:
+            if dev:
+                import torch
+                out = torch.zeros((nd, n), dtype=torch.float64, device=phi.device)
+            else:
+                out = np.zeros((nd, n))
+        if dev:
+            pp, op = C.c_void_p(phi.data_ptr()), C.c_void_p(out.data_ptr())
+        else:
+            phi = _f64(phi)
+            pp, op = C.c_void_p(phi.ctypes.data), C.c_void_p(out.ctypes.data)
+        _check(lib().vcx_poisson_field(self.h, pp, op, int(dev)), "vcx_poisson_field")
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().vcx_poisson_destroy(self.h)
             self.h = None
 
     def __del__(self):

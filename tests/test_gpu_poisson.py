@@ -1,0 +1,183 @@
+"""GPU Poisson solve and field against the oracle's direct solve.
+
+The library solves by conjugate gradients to a relative residual tol, the
+oracle by a sparse direct factorisation of its own operator.  Bars:
+  * the oracle operator's residual of the GPU potential is at the CG
+    tolerance (this checks the GPU operator against the oracle's);
+  * potentials agree within kappa(L) * tol, bounded here by 1e-9 relative
+    (kappa below 1e4 on these meshes, tol 1e-13);
+  * the field of one potential agrees with the oracle's nodal gradient to
+    1e-12 relative (a plain FP64 sum on both sides).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2201_01291_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2201_01291_amd import vcx  # noqa: E402
+
+TOL = 1e-13
+PHI_BAR = 1e-9
+FIELD_BAR = 1e-12
+
+
+def _open_square(n=30, seed=4):
+    m = wl.tri_rect_mesh(n, n, jitter=0.2, seed=seed)
+    x, y = m.xyz
+    bnd = (x < 1e-12) | (x > 1 - 1e-12) | (y < 1e-12) | (y > 1 - 1e-12)
+    return m, bnd
+
+
+def _open_cube(n=8, seed=5):
+    m = wl.kuhn_tet_mesh(n, n, n, jitter=0.15, seed=seed, periodic=False)
+    lo, hi = m.xyz.min(axis=1), m.xyz.max(axis=1)
+    bnd = np.any((m.xyz < lo[:, None] + 1e-12) | (m.xyz > hi[:, None] - 1e-12), axis=0)
+    return m, bnd
+
+
+def _charge(m, seed=1):
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(0.2, 0.8, size=(m.ndim, 3))
+    q = np.zeros(m.nnodes)
+    for k in range(3):
+        q += (k + 1) * np.exp(-np.sum((m.xyz - c[:, k:k + 1]) ** 2, axis=0) / 0.02)
+    return q
+
+
+def _residual(om, phi, q, dirichlet=None, phiD=None, En=None):
+    L = om.poisson_matrix()
+    Vn = om.geometry()["Vn"]
+    b = q * Vn
+    if En is not None:
+        b = b - En * om.boundary_measure()
+    if dirichlet is None:
+        b = b - Vn * (b.sum() / Vn.sum())
+        free = np.ones(len(q), dtype=bool)
+        bt = b
+    else:
+        free = ~dirichlet
+        xd = np.where(dirichlet, phiD, 0.0)
+        bt = (b - L @ xd)[free]
+    r = (b - L @ phi)[free]
+    return np.linalg.norm(r) / np.linalg.norm(bt)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_dirichlet_solve_matches_the_direct_solve(dim):
+    m, bnd = _open_square() if dim == 2 else _open_cube()
+    print(f"[case] poisson dirichlet {dim}D nn={m.nnodes}", flush=True)
+    om = oracle.OracleMesh(m)
+    q = _charge(m)
+    phiD = 0.3 * m.xyz[0] - 0.1 * m.xyz[1] + 0.05
+    ref = om.poisson_solve(q, dirichlet=bnd, phi_D=phiD)
+    gm = vcx.Mesh(m)
+    ps = vcx.Poisson(gm, dirichlet=bnd)
+    phi, it, rel = ps.solve(q, phiD=phiD, tol=TOL)
+    print("iterations", it, "relres", rel)
+    assert rel <= TOL
+    assert np.array_equal(phi[bnd], phiD[bnd])
+    assert _residual(om, phi, q, bnd, phiD) <= 10 * TOL
+    assert np.abs(phi - ref).max() <= PHI_BAR * np.abs(ref).max()
+    E = ps.field(phi)
+    Eo = om.electric_field(phi)
+    assert np.abs(E - Eo).max() <= FIELD_BAR * np.abs(Eo).max()
+
+
+def test_periodic_solve_with_background_and_zero_mean():
+    m = wl.tri_rect_mesh(40, 30, 1.0, 0.75, jitter=0.2, seed=8, periodic=True)
+    print(f"[case] poisson periodic nn={m.nnodes}", flush=True)
+    om = oracle.OracleMesh(m)
+    q = _charge(m, seed=3) + 2.0       # net charge: the background neutralises it
+    ref = om.poisson_solve(q)
+    gm = vcx.Mesh(m)
+    ps = vcx.Poisson(gm)
+    phi, it, rel = ps.solve(q, tol=TOL)
+    print("iterations", it, "relres", rel)
+    Vn = om.geometry()["Vn"]
+    assert abs(Vn @ phi) <= 1e-12 * (Vn @ np.abs(phi))
+    assert _residual(om, phi, q) <= 10 * TOL
+    assert np.abs(phi - ref).max() <= PHI_BAR * np.abs(ref).max()
+    E = ps.field(phi)
+    assert np.abs(E - om.electric_field(phi)).max() <= FIELD_BAR * np.abs(E).max()
+
+
+def test_neumann_strip_is_linear():
+    m = wl.tri_rect_mesh(20, 6, 1.0, 0.3, jitter=0.2, seed=2, periodic=(False, True))
+    x = m.xyz[0]
+    left, right = x < 1e-12, x > 1 - 1e-12
+    ps = vcx.Poisson(vcx.Mesh(m), dirichlet=left)
+    phi, it, rel = ps.solve(np.zeros(m.nnodes), phiD=np.zeros(m.nnodes),
+                            En=np.where(right, 3.0, 0.0), tol=TOL)
+    np.testing.assert_allclose(phi, -3.0 * x, rtol=0, atol=1e-11)
+    np.testing.assert_allclose(ps.field(phi)[0], 3.0, rtol=0, atol=1e-9)
+
+
+def test_bitwise_reproducible_and_device_io():
+    m, bnd = _open_square(24, seed=6)
+    gm = vcx.Mesh(m)
+    ps = vcx.Poisson(gm, dirichlet=bnd)
+    q = _charge(m, seed=5)
+    phiD = np.zeros(m.nnodes)
+    a, ia, _ = ps.solve(q, phiD=phiD, tol=TOL)
+    b, ib, _ = ps.solve(q, phiD=phiD, tol=TOL)
+    assert ia == ib and np.array_equal(a, b)
+    qd = torch.tensor(q, device="cuda")
+    dd = torch.tensor(phiD, device="cuda")
+    c, ic, _ = ps.solve(qd, phiD=dd, tol=TOL)
+    torch.cuda.synchronize()
+    assert ic == ia and np.array_equal(c.cpu().numpy(), a)
+    Ed = ps.field(c)
+    torch.cuda.synchronize()
+    assert np.array_equal(Ed.cpu().numpy(), ps.field(a))
+    # a warm start from the solution stops at once
+    w, iw, _ = ps.solve(q, phiD=phiD, phi0=a, tol=1e-10)
+    assert iw == 0 and np.array_equal(w, a)
+
+
+def test_iteration_cap_is_reported():
+    m, bnd = _open_square(30)
+    ps = vcx.Poisson(vcx.Mesh(m), dirichlet=bnd)
+    with pytest.raises(vcx.VcxError) as e:
+        ps.solve(_charge(m), tol=1e-14, max_iter=5)
+    assert e.value.code == vcx.E_STATE
+
+
+def test_step_coupled_to_the_poisson_field_matches_the_oracle():
+    """Drift-diffusion of electrons and ions with E = E_background - grad phi,
+    phi from the space charge e (n_i - n_e) / eps0 (periodic box, neutralising
+    background): Poisson solve, field, one step, on both sides."""
+    import cases
+    m = wl.dd_streamer_mesh(40, 25)
+    n, E0 = wl.dd_fields(m, sigma=2e-3)
+    n[1] *= 1.0 + 0.2 * np.exp(-np.sum((m.xyz - m.xyz.mean(axis=1, keepdims=True)) ** 2, axis=0) / 4e-6)
+    q = 1.602176634e-19 * (n[1] - n[0]) / 8.8541878128e-12
+    Ebg = np.zeros_like(E0)
+    Ebg[0] = 1e6
+    case = cases.Case("dd-poisson", m, n, Ebg, dict(cases.DD2))
+    om = oracle.OracleMesh(m)
+    phi_o = om.poisson_solve(q)
+    E_o = Ebg + om.electric_field(phi_o)
+    U_o, t_o, _, _ = om.step(case.oracle_phys(), n, E_o, nsteps=1)
+
+    gm = vcx.Mesh(m)
+    ps = vcx.Poisson(gm)
+    s = vcx.Solver(gm, case.vcx_phys(), Ebg)
+    s.upload(n)
+    phi, it, _ = ps.solve(q, tol=TOL)
+    E = Ebg + ps.field(phi)
+    s.set_field(E)
+    t, _ = s.step(1)
+    print("coupled: iterations", it, "max |E - E_o| / max |E_o|", np.abs(E - E_o).max() / np.abs(E_o).max())
+    assert np.abs(E - E_o).max() <= PHI_BAR * np.abs(E_o).max()
+    assert t == pytest.approx(t_o, rel=1e-9)
+    U = s.download()
+    err = (np.abs(U - U_o).max(axis=1) / np.abs(U_o).max(axis=1))
+    print("coupled state err", err)
+    assert err.max() <= 1e-8
