@@ -86,6 +86,7 @@ def parse():
                     help="comma-separated NXxNY sizes of the drift-diffusion mesh family (h = 50 um) "
                          "timed after the main run, e.g. 1200x750,2400x1500")
     ap.add_argument("--sweep-only", action="store_true", help="run the size sweep only")
+    ap.add_argument("--no-poisson", action="store_true", help="skip the Poisson leg")
     ap.add_argument("--serve-load", type=float, default=0.8,
                     help="arrival rate as a fraction of the measured batched capacity")
     return ap.parse_args()
@@ -300,6 +301,69 @@ def serving_leg(a, stream):
     )
 
 
+def poisson_leg(a, stream):
+    """Poisson solve on the drift-diffusion mesh: space charge e (n_i - n_e)
+    / eps0 of the workload's densities with a 20% ion excess in a central
+    Gaussian, periodic box (neutralising background), Jacobi-PCG to a
+    relative residual of 1e-10.  Cold start (zero guess), then steps coupled
+    to the field: Poisson solve warm-started from the previous potential,
+    E = E_background - grad phi, one drift-diffusion step."""
+    import torch
+    from paper_2201_01291_amd import vcx, workloads as wl
+    m = wl.dd_streamer_mesh()
+    n, E0 = wl.dd_fields(m)
+    c = m.xyz.mean(axis=1, keepdims=True)
+    n[1] *= 1.0 + 0.2 * np.exp(-np.sum((m.xyz - c) ** 2, axis=0) / 4e-6)
+    sp = wl.DD_STREAMER_SPECIES
+    ph = vcx.physics(model=vcx.MODEL_DRIFT_DIFFUSION, limiter=vcx.LIM_MINMOD, rk_stages=1, nspecies=2,
+                     precision=vcx.PREC_FP64, beta=1.0, cfl=0.5, fourier=0.25,
+                     z=[s.z for s in sp], mu=[s.mu for s in sp], D=[s.D for s in sp])
+    gm = vcx.Mesh(m, stream=stream)
+    ps = vcx.Poisson(gm)
+    e_eps0 = 1.602176634e-19 / 8.8541878128e-12
+    zs = torch.tensor([s.z for s in sp], dtype=torch.float64, device="cuda")[:, None]
+    Ebg = torch.zeros((2, m.nnodes), dtype=torch.float64, device="cuda")
+    Ebg[0] = 1e6
+    nd_ = torch.tensor(n, device="cuda")
+    q = e_eps0 * (zs * nd_).sum(dim=0)
+    tol = 1e-10
+    ps.solve(q, tol=tol)               # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    phi, it_cold, rel = ps.solve(q, tol=tol)
+    torch.cuda.synchronize()
+    cold = time.perf_counter() - t0
+    s = vcx.Solver(gm, ph, E0)
+    s.upload(nd_)
+    U = torch.empty_like(nd_)
+    its, times = [], []
+    K = 50
+    for _ in range(K + 3):
+        t1 = time.perf_counter()
+        s.download(out=U)
+        q = e_eps0 * (zs * U).sum(dim=0)
+        phi, it, _ = ps.solve(q, phi0=phi, tol=tol, out=torch.empty_like(phi))
+        E = Ebg + ps.field(phi)
+        s.set_field(E)
+        s.step(1)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t1)
+        its.append(it)
+    times, its = times[3:], its[3:]
+    nnz_est = 7 * m.nnodes
+    # bytes of one CG iteration, every array once: CSR (rp, col, val), and
+    # z, p_old, p_new, q (first half); x, p, r, q, D^-1, r, z, x (second half)
+    it_bytes = 4 * (m.nnodes + 1) + 12 * nnz_est + 8 * m.nnodes * 12
+    ms_it = cold / max(it_cold, 1) * 1e3
+    return dict(workload="dd2d-streamer mesh (periodic, 100,000 nodes), space charge of the densities "
+                         "with a 20% central ion excess, Jacobi-PCG to relative residual 1e-10",
+                cold_iterations=it_cold, cold_ms=round(cold * 1e3, 3), ms_per_iteration=round(ms_it, 4),
+                alg_gbs_per_iteration=round(it_bytes / (ms_it * 1e-3) / 1e9, 1),
+                coupled_step_ms_p50=round(float(np.percentile(times, 50)) * 1e3, 3),
+                coupled_iterations_mean=round(float(np.mean(its)), 2), coupled_steps=K,
+                coupled_faces_per_s_M=round(m.nfaces / float(np.percentile(times, 50)) / 1e6, 1))
+
+
 def size_sweep(a, stream):
     """FP64 throughput and the fused pass's algorithmic bandwidth of the
     drift-diffusion workload at larger sizes of the same mesh family (fixed
@@ -471,6 +535,10 @@ def main():
                                          f"({elc:.1f} s, sequential FP64 C oracle)")
 
     sweep = size_sweep(a, stream.cuda_stream) if a.sweep else None
+    pois = None
+    if not a.no_poisson and a.workload == "dd2d":
+        print("[bench] Poisson leg", file=sys.stderr, flush=True)
+        pois = poisson_leg(a, stream.cuda_stream)
     serve = None
     if not a.no_serve:
         serve = serving_leg(a, stream.cuda_stream)
@@ -504,6 +572,7 @@ def main():
         "cpu_baseline": cpu,
         "serving": serve,
         "size_sweep": sweep,
+        "poisson": pois,
         "mesh": info,
     }
     print(json.dumps(out))
