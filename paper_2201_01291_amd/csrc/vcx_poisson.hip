@@ -11,8 +11,12 @@
 // node with nothing imposed has a zero normal field.
 //
 // Device layout: CSR rows in the internal node order (space-filling curve),
-// FP64 values.  The solve is Jacobi-preconditioned conjugate gradients with
-// two kernels per iteration.  Every dot product is reduced in a fixed order:
+// FP64 values.  The solve is preconditioned conjugate gradients with a
+// two-level additive preconditioner: Jacobi plus a coarse space of
+// aggregates (runs of consecutive curve-ordered nodes, piecewise-constant
+// prolongation), whose small dense operator is inverted on the host; three
+// kernels per iteration (coarse correction, search direction and product,
+// update).  Every dot product is reduced in a fixed order:
 // each block writes one partial, and every block of the next kernel sums all
 // partials in the same order, so all blocks take the same scalars and the
 // iterates are bitwise reproducible.  Convergence is decided on the device;
@@ -34,7 +38,6 @@ namespace {
 using vcx::HostMesh;
 
 constexpr int kThreads = 256;
-constexpr int kMaxBlocks = 1024;
 
 vcx_status err(vcx_status s, const std::string& m) { return vcx::set_error(s, m.c_str()); }
 
@@ -46,6 +49,8 @@ vcx_status err(vcx_status s, const std::string& m) { return vcx::set_error(s, m.
 
 struct PoissonDev {
   int n, nd, nnz, singular;
+  int agg;              // nodes per aggregate (a multiple of kThreads); block b owns aggregate b
+  int nc;               // aggregates = blocks of the CG kernels
   const int* rp;        // [n+1]
   const int* col;       // [nnz]
   const double* val;    // [nnz] matrix of -lap phi over the nodal volumes
@@ -53,11 +58,20 @@ struct PoissonDev {
   const double* dinv;   // [n] 1 / L_ii on free nodes, 0 on Dirichlet nodes
   const double* vn;     // [n] nodal volumes
   const double* sbm;    // [n] |S_i^b| on boundary nodes, 0 elsewhere
+  const double* ainv;   // [nc][nc] inverse of the coarse operator R L R^T
   const int32_t* perm;  // [n] internal -> caller
 };
 
-// Partial-sum rows (one double per block each)
-enum { P_RZ0 = 0, P_RZ1, P_RR0, P_RR1, P_PQ, P_B, P_V, P_BB, P_VX, P_RRI, P_NROWS };
+// Partial-sum rows (one double per block each); rows ending in 0/1 are
+// double-buffered by iteration parity.
+enum {
+  P_DRR0 = 0, P_DRR1,  // sum D^-1 r^2 (fine part of r.z)
+  P_RR0, P_RR1,        // r.r
+  P_PQ,                // p.q
+  P_GC,                // g_b c_b (coarse part of r.z)
+  P_B, P_V, P_BB, P_VX, P_RRI,
+  P_NROWS
+};
 
 struct CgCtl {
   int done;       // converged (iterations stop)
@@ -66,13 +80,15 @@ struct CgCtl {
   int pad;
   double rr;      // squared residual norm of the last iterate
   double ref2;    // squared norm the tolerance is relative to
+  double rz[2];   // r.z of the iterates, by parity
 };
 
 struct CgVec {
-  double *x, *r, *z, *p0, *p1, *q, *b;
-  double* part;  // [P_NROWS][nb]
+  double *x, *r, *p0, *p1, *q, *b;
+  double* g;     // [nc] restriction R r (sum of r over each aggregate's free nodes)
+  double* c;     // [nc] coarse correction A_c^-1 g
+  double* part;  // [P_NROWS][nc]
   CgCtl* ctl;
-  int nb;
 };
 
 __device__ double block_sum(double v) {
@@ -111,18 +127,33 @@ __device__ void put_partial(double* row, double v) {
   if (threadIdx.x == 0) row[blockIdx.x] = s;
 }
 
+// Rows of this block's aggregate: [i0, i1)
+__device__ inline void agg_rows(const PoissonDev& P, int& i0, int& i1) {
+  i0 = blockIdx.x * P.agg;
+  i1 = min(P.n, i0 + P.agg);
+}
+
+// Preconditioned residual of node j: z = D^-1 r + c_(aggregate of j) on free
+// nodes (two-level additive: Jacobi plus the aggregation coarse space), 0 on
+// Dirichlet nodes.
+__device__ inline double precond(const PoissonDev& P, const CgVec& X, int j) {
+  const double dj = P.dinv[j];
+  return dj != 0.0 ? dj * X.r[j] + X.c[j / P.agg] : 0.0;
+}
+
 // Right-hand side q V - E_n |S^b| on free nodes, the initial iterate (guess
 // on free nodes, imposed values on Dirichlet nodes); partial sums of b and V.
 __global__ void __launch_bounds__(kThreads) k_cg_init1(PoissonDev P, CgVec X, const double* __restrict__ q,
                                                         const double* __restrict__ phiD,
                                                         const double* __restrict__ En,
                                                         const double* __restrict__ phi0) {
+  int i0, i1;
+  agg_rows(P, i0, i1);
   double sb = 0.0, sv = 0.0;
-  for (int i = blockIdx.x * kThreads + threadIdx.x; i < P.n; i += X.nb * kThreads) {
+  for (int i = i0 + threadIdx.x; i < i1; i += kThreads) {
     const int o = P.perm[i];
-    const bool free = P.dinv[i] != 0.0;
     double b = 0.0;
-    if (free) {
+    if (P.dinv[i] != 0.0) {
       b = q[o] * P.vn[i];
       if (En) b -= En[o] * P.sbm[i];
       X.x[i] = phi0 ? phi0[o] : 0.0;
@@ -133,18 +164,20 @@ __global__ void __launch_bounds__(kThreads) k_cg_init1(PoissonDev P, CgVec X, co
     sb += b;
     sv += P.vn[i];
   }
-  put_partial(X.part + P_B * X.nb, sb);
-  put_partial(X.part + P_V * X.nb, sv);
+  put_partial(X.part + P_B * P.nc, sb);
+  put_partial(X.part + P_V * P.nc, sv);
 }
 
 // Singular systems: the uniform background that makes b sum to zero.
-// Initial residual r = b - L x on free rows, z = D^-1 r, p = 0; partial sums
-// of r.z, r.r and |b - L_fD x_D|^2 (the norm the tolerance refers to).
+// Initial residual r = b - L x on free rows, p = 0; partial sums of D^-1 r^2,
+// r.r and |b - L_fD x_D|^2 (the norm the tolerance refers to), and g = R r.
 __global__ void __launch_bounds__(kThreads) k_cg_init2(PoissonDev P, CgVec X) {
   double bmean = 0.0;
-  if (P.singular) bmean = sum_partials(X.part + P_B * X.nb, X.nb) / sum_partials(X.part + P_V * X.nb, X.nb);
-  double rz = 0.0, rr = 0.0, bb = 0.0;
-  for (int i = blockIdx.x * kThreads + threadIdx.x; i < P.n; i += X.nb * kThreads) {
+  if (P.singular) bmean = sum_partials(X.part + P_B * P.nc, P.nc) / sum_partials(X.part + P_V * P.nc, P.nc);
+  int i0, i1;
+  agg_rows(P, i0, i1);
+  double drr = 0.0, rr = 0.0, bb = 0.0, gs = 0.0;
+  for (int i = i0 + threadIdx.x; i < i1; i += kThreads) {
     const double di = P.dinv[i];
     double r = 0.0;
     if (di != 0.0) {
@@ -164,97 +197,123 @@ __global__ void __launch_bounds__(kThreads) k_cg_init2(PoissonDev P, CgVec X) {
       const double bt = b - ad;
       bb += bt * bt;
     }
-    const double z = di * r;
     X.r[i] = r;
-    X.z[i] = z;
     X.p0[i] = 0.0;
     X.p1[i] = 0.0;
-    rz += r * z;
+    drr += di * r * r;
     rr += r * r;
+    gs += r;
   }
-  put_partial(X.part + P_RZ0 * X.nb, rz);
-  put_partial(X.part + P_RR0 * X.nb, rr);
-  put_partial(X.part + P_RRI * X.nb, rr);
-  put_partial(X.part + P_BB * X.nb, bb);
+  put_partial(X.part + P_DRR0 * P.nc, drr);
+  put_partial(X.part + P_RR0 * P.nc, rr);
+  put_partial(X.part + P_RRI * P.nc, rr);
+  put_partial(X.part + P_BB * P.nc, bb);
+  const double g = block_sum(gs);
+  if (threadIdx.x == 0) X.g[blockIdx.x] = g;
+}
+
+// Coarse correction of iterate k: c_b = (A_c^-1 g)_b for this block's
+// aggregate, and the coarse part g_b c_b of r.z.
+__global__ void __launch_bounds__(kThreads) k_cg_c(PoissonDev P, CgVec X) {
+  if (block_done(X.ctl)) return;
+  const double* row = P.ainv + (size_t)blockIdx.x * P.nc;
+  double s = 0.0;
+  for (int a = threadIdx.x; a < P.nc; a += kThreads) s += row[a] * X.g[a];
+  const double cb = block_sum(s);
+  if (threadIdx.x == 0) {
+    X.c[blockIdx.x] = cb;
+    X.part[P_GC * P.nc + blockIdx.x] = X.g[blockIdx.x] * cb;
+  }
 }
 
 // Iteration k, first half: stop test on the residual of iterate k; else
-// beta = (r.z)_k / (r.z)_(k-1), p_k = z + beta p_(k-1) and q = L p_k (rows
-// form p_k of their neighbours themselves, in the same arithmetic as the
-// neighbour's own row), partial sums of p.q.
+// r.z, beta = (r.z)_k / (r.z)_(k-1), p_k = z + beta p_(k-1) and q = L p_k
+// (rows form z and p_k of their neighbours themselves, in the same
+// arithmetic as the neighbour's own row), partial sums of p.q.
 __global__ void __launch_bounds__(kThreads) k_cg_a(PoissonDev P, CgVec X, int k, double tol2) {
   if (block_done(X.ctl)) return;
   const int cur = k & 1;
-  const double rz = sum_partials(X.part + (P_RZ0 + cur) * X.nb, X.nb);
-  const double rr = sum_partials(X.part + (P_RR0 + cur) * X.nb, X.nb);
+  const double rr = sum_partials(X.part + (P_RR0 + cur) * P.nc, P.nc);
   // relative to |b - L_fD x_D| (the free system's right-hand side), or to
   // the initial residual when that is zero
-  const double bb = sum_partials(X.part + P_BB * X.nb, X.nb);
-  const double ref2 = bb > 0.0 ? bb : sum_partials(X.part + P_RRI * X.nb, X.nb);
+  const double bb = sum_partials(X.part + P_BB * P.nc, P.nc);
+  const double ref2 = bb > 0.0 ? bb : sum_partials(X.part + P_RRI * P.nc, P.nc);
   const bool conv = !(rr > tol2 * ref2);  // also stops on rr = 0
+  const double rz = sum_partials(X.part + (P_DRR0 + cur) * P.nc, P.nc) + sum_partials(X.part + P_GC * P.nc, P.nc);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     X.ctl->last = k;
     X.ctl->rr = rr;
     X.ctl->ref2 = ref2;
+    X.ctl->rz[cur] = rz;
     if (conv) {
-      __hip_atomic_store(&X.ctl->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       X.ctl->iters = k;
+      __hip_atomic_store(&X.ctl->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
   if (conv) return;
-  const double beta = k == 0 ? 0.0 : rz / sum_partials(X.part + (P_RZ0 + (cur ^ 1)) * X.nb, X.nb);
+  const double beta = k == 0 ? 0.0 : rz / X.ctl->rz[cur ^ 1];
   const double* po = cur ? X.p1 : X.p0;  // p_(k-1) (zero at k = 0)
   double* pn = cur ? X.p0 : X.p1;        // p_k
+  int i0, i1;
+  agg_rows(P, i0, i1);
   double pq = 0.0;
-  for (int i = blockIdx.x * kThreads + threadIdx.x; i < P.n; i += X.nb * kThreads) {
+  for (int i = i0 + threadIdx.x; i < i1; i += kThreads) {
     double p = 0.0, qv = 0.0;
     if (P.dinv[i] != 0.0) {
-      p = X.z[i] + beta * po[i];
+      p = precond(P, X, i) + beta * po[i];
       for (int e = P.rp[i]; e < P.rp[i + 1]; ++e) {
         const int j = P.col[e];
-        qv += P.val[e] * (X.z[j] + beta * po[j]);
+        qv += P.val[e] * (precond(P, X, j) + beta * po[j]);
       }
     }
     pn[i] = p;
     X.q[i] = qv;
     pq += p * qv;
   }
-  put_partial(X.part + P_PQ * X.nb, pq);
+  put_partial(X.part + P_PQ * P.nc, pq);
 }
 
 // Iteration k, second half: alpha = (r.z)_k / (p.q); x += alpha p,
-// r -= alpha q, z = D^-1 r; partial sums of r.z and r.r of iterate k+1.
+// r -= alpha q; partial sums of D^-1 r^2 and r.r of iterate k+1 and its
+// restriction g = R r.
 __global__ void __launch_bounds__(kThreads) k_cg_b(PoissonDev P, CgVec X, int k) {
   if (block_done(X.ctl)) return;
   const int cur = k & 1, nxt = cur ^ 1;
-  const double alpha = sum_partials(X.part + (P_RZ0 + cur) * X.nb, X.nb) / sum_partials(X.part + P_PQ * X.nb, X.nb);
+  const double alpha = X.ctl->rz[cur] / sum_partials(X.part + P_PQ * P.nc, P.nc);
   const double* pn = cur ? X.p0 : X.p1;
-  double rz = 0.0, rr = 0.0;
-  for (int i = blockIdx.x * kThreads + threadIdx.x; i < P.n; i += X.nb * kThreads) {
+  int i0, i1;
+  agg_rows(P, i0, i1);
+  double drr = 0.0, rr = 0.0, gs = 0.0;
+  for (int i = i0 + threadIdx.x; i < i1; i += kThreads) {
     const double di = P.dinv[i];
     if (di == 0.0) continue;
     X.x[i] += alpha * pn[i];
     const double r = X.r[i] - alpha * X.q[i];
-    const double z = di * r;
     X.r[i] = r;
-    X.z[i] = z;
-    rz += r * z;
+    drr += di * r * r;
     rr += r * r;
+    gs += r;
   }
-  put_partial(X.part + (P_RZ0 + nxt) * X.nb, rz);
-  put_partial(X.part + (P_RR0 + nxt) * X.nb, rr);
+  put_partial(X.part + (P_DRR0 + nxt) * P.nc, drr);
+  put_partial(X.part + (P_RR0 + nxt) * P.nc, rr);
+  const double g = block_sum(gs);
+  if (threadIdx.x == 0) X.g[blockIdx.x] = g;
 }
 
 // Singular systems: phi with zero volume mean.
 __global__ void __launch_bounds__(kThreads) k_cg_mean1(PoissonDev P, CgVec X) {
+  int i0, i1;
+  agg_rows(P, i0, i1);
   double s = 0.0;
-  for (int i = blockIdx.x * kThreads + threadIdx.x; i < P.n; i += X.nb * kThreads) s += P.vn[i] * X.x[i];
-  put_partial(X.part + P_VX * X.nb, s);
+  for (int i = i0 + threadIdx.x; i < i1; i += kThreads) s += P.vn[i] * X.x[i];
+  put_partial(X.part + P_VX * P.nc, s);
 }
 
 __global__ void __launch_bounds__(kThreads) k_cg_mean2(PoissonDev P, CgVec X) {
-  const double m = sum_partials(X.part + P_VX * X.nb, X.nb) / sum_partials(X.part + P_V * X.nb, X.nb);
-  for (int i = blockIdx.x * kThreads + threadIdx.x; i < P.n; i += X.nb * kThreads) X.x[i] -= m;
+  const double m = sum_partials(X.part + P_VX * P.nc, P.nc) / sum_partials(X.part + P_V * P.nc, P.nc);
+  int i0, i1;
+  agg_rows(P, i0, i1);
+  for (int i = i0 + threadIdx.x; i < i1; i += kThreads) X.x[i] -= m;
 }
 
 __global__ void __launch_bounds__(kThreads) k_cg_scatter(PoissonDev P, const double* __restrict__ x,
@@ -326,6 +385,45 @@ void simplex_grads(int nd, const double (&X)[4][3], double (&grad)[4][3], double
     grad[0][d] = -(grad[1][d] + grad[2][d] + grad[3][d]);
   }
 }
+
+// Inverse of a dense SPD matrix (row-major, n x n) by Cholesky: A = L L^T,
+// A^-1 = L^-T L^-1.  Returns false if A is not numerically positive definite.
+bool spd_inverse(std::vector<double>& A, int n) {
+  std::vector<double> L((size_t)n * n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    double d = A[(size_t)j * n + j];
+    for (int k = 0; k < j; ++k) d -= L[(size_t)j * n + k] * L[(size_t)j * n + k];
+    if (!(d > 0.0)) return false;
+    const double ljj = std::sqrt(d);
+    L[(size_t)j * n + j] = ljj;
+    for (int i = j + 1; i < n; ++i) {
+      double v = A[(size_t)i * n + j];
+      for (int k = 0; k < j; ++k) v -= L[(size_t)i * n + k] * L[(size_t)j * n + k];
+      L[(size_t)i * n + j] = v / ljj;
+    }
+  }
+  // M = L^-1 (lower triangular), column by column
+  std::vector<double> M((size_t)n * n, 0.0);
+  for (int c = 0; c < n; ++c) {
+    M[(size_t)c * n + c] = 1.0 / L[(size_t)c * n + c];
+    for (int i = c + 1; i < n; ++i) {
+      double v = 0.0;
+      for (int k = c; k < i; ++k) v -= L[(size_t)i * n + k] * M[(size_t)k * n + c];
+      M[(size_t)i * n + c] = v / L[(size_t)i * n + i];
+    }
+  }
+  // A^-1 = M^T M
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j <= i; ++j) {
+      double v = 0.0;
+      for (int k = i; k < n; ++k) v += M[(size_t)k * n + i] * M[(size_t)k * n + j];
+      A[(size_t)i * n + j] = v;
+      A[(size_t)j * n + i] = v;
+    }
+  return true;
+}
+
+constexpr int kMaxCoarse = 1024;
 
 }  // namespace
 
@@ -475,16 +573,47 @@ extern "C" vcx_status vcx_poisson_create(vcx_mesh mesh, const int32_t* dirichlet
   chk(upload(p, dinv, &P.dinv));
   chk(upload(p, h.vnode, &P.vn));
   chk(upload(p, sbm, &P.sbm));
+  // aggregates: consecutive nodes of the space-filling curve, a multiple of
+  // the block size each, at most kMaxCoarse of them; coarse operator
+  // A_c = R L R^T over free nodes, inverted densely on the host
+  const int64_t per = (n + kMaxCoarse - 1) / kMaxCoarse;
+  P.agg = (int)(((per + kThreads - 1) / kThreads) * kThreads);
+  P.nc = (int)((n + P.agg - 1) / P.agg);
+  const int ncg = P.nc;
+  std::vector<double> Ac((size_t)ncg * ncg, 0.0);
+  for (int64_t i = 0; i < n; ++i) {
+    if (dir[(size_t)i]) continue;
+    const int a = (int)(i / P.agg);
+    for (int32_t e = rp[(size_t)i]; e < rp[(size_t)i + 1]; ++e) {
+      const int j = col[(size_t)e];
+      if (!dir[(size_t)j]) Ac[(size_t)a * ncg + j / P.agg] += val[(size_t)e];
+    }
+  }
+  double tr = 0.0;
+  for (int a = 0; a < ncg; ++a) tr += Ac[(size_t)a * ncg + a];
+  for (int a = 0; a < ncg; ++a)
+    if (Ac[(size_t)a * ncg + a] == 0.0) Ac[(size_t)a * ncg + a] = tr > 0.0 ? tr / ncg : 1.0;  // no free node
+  if (!any_dir) {
+    // constants are the null space: (A_c + mu 1 1^T)^-1 acts as the
+    // pseudo-inverse on restrictions of residuals, which sum to zero
+    const double mu = tr / ((double)ncg * ncg);
+    for (double& v : Ac) v += mu;
+  }
+  if (!spd_inverse(Ac, ncg)) st = err(VCX_E_MESH, "coarse Poisson operator is not positive definite");
+  chk(upload(p, Ac, &P.ainv));
   CgVec& X = p->X;
-  X.nb = (int)std::min<int64_t>(kMaxBlocks, (n + kThreads - 1) / kThreads);
-  double** vecs[7] = {&X.x, &X.r, &X.z, &X.p0, &X.p1, &X.q, &X.b};
+  double** vecs[6] = {&X.x, &X.r, &X.p0, &X.p1, &X.q, &X.b};
   for (double** v : vecs) {
     void* d = nullptr;
     chk(dev_alloc(p, sizeof(double) * (size_t)n, &d));
     *v = static_cast<double*>(d);
   }
   void* d = nullptr;
-  chk(dev_alloc(p, sizeof(double) * P_NROWS * (size_t)X.nb, &d));
+  chk(dev_alloc(p, sizeof(double) * ncg, &d));
+  X.g = static_cast<double*>(d);
+  chk(dev_alloc(p, sizeof(double) * ncg, &d));
+  X.c = static_cast<double*>(d);
+  chk(dev_alloc(p, sizeof(double) * P_NROWS * (size_t)ncg, &d));
   X.part = static_cast<double*>(d);
   chk(dev_alloc(p, sizeof(CgCtl), &d));
   X.ctl = static_cast<CgCtl*>(d);
@@ -535,7 +664,7 @@ extern "C" vcx_status vcx_poisson_solve(vcx_poisson p, const double* q, const do
   if (st == VCX_OK) st = stage_in(p, En, 2, is_device, &dE);
   if (st == VCX_OK) st = stage_in(p, phi, 3, is_device, &d0);
   if (st != VCX_OK) return st;
-  const dim3 grid(p->X.nb), block(kThreads);
+  const dim3 grid(p->P.nc), block(kThreads);
   PS_HIP(hipMemsetAsync(p->X.ctl, 0, sizeof(CgCtl), p->stream));
   hipLaunchKernelGGL(k_cg_init1, grid, block, 0, p->stream, p->P, p->X, dq, dD, dE, d0);
   hipLaunchKernelGGL(k_cg_init2, grid, block, 0, p->stream, p->P, p->X);
@@ -548,10 +677,12 @@ extern "C" vcx_status vcx_poisson_solve(vcx_poisson p, const double* q, const do
     // does the first half of iteration k+c when it does not stop)
     const int c = std::min(chunk, max_iter - k);
     for (int j = 0; j < c; ++j) {
+      hipLaunchKernelGGL(k_cg_c, grid, block, 0, p->stream, p->P, p->X);
       hipLaunchKernelGGL(k_cg_a, grid, block, 0, p->stream, p->P, p->X, k + j, tol2);
       hipLaunchKernelGGL(k_cg_b, grid, block, 0, p->stream, p->P, p->X, k + j);
     }
     k += c;
+    hipLaunchKernelGGL(k_cg_c, grid, block, 0, p->stream, p->P, p->X);
     hipLaunchKernelGGL(k_cg_a, grid, block, 0, p->stream, p->P, p->X, k, tol2);
     PS_HIP(hipGetLastError());
     PS_HIP(hipMemcpyAsync(p->ctl_host, p->X.ctl, sizeof(CgCtl), hipMemcpyDeviceToHost, p->stream));
