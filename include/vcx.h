@@ -114,6 +114,10 @@ typedef struct {
   double cpa[VCX_MAX_SPECIES], cpb[VCX_MAX_SPECIES], cpc[VCX_MAX_SPECIES];
   double Sc[VCX_MAX_SPECIES];
   double mu_ref, T_ref, Pr;
+  /* drift-diffusion: constant A_D of the dielectric time step A_D eps0 /
+   * sum_s |q_s n_s mu_s| (Sec. "Time step computation"), taken per node;
+   * 0 leaves the limit out (the paper gives no value) */
+  double diel;
 } vcx_physics;
 
 typedef struct vcx_mesh_s *vcx_mesh;

@@ -46,7 +46,7 @@ class _Phys(C.Structure):
                 ("Wk", C.c_double * MAXSP), ("cpa", C.c_double * MAXSP),
                 ("cpb", C.c_double * MAXSP), ("cpc", C.c_double * MAXSP),
                 ("Sc", C.c_double * MAXSP), ("mu_ref", C.c_double), ("T_ref", C.c_double),
-                ("Pr", C.c_double)]
+                ("Pr", C.c_double), ("diel", C.c_double)]
 
 
 @dataclass
@@ -66,6 +66,7 @@ class Phys:
     mu: list = field(default_factory=list)
     D: list = field(default_factory=list)
     mixture: object = None   # workloads.Mixture for the Navier-Stokes model
+    diel: float = 0.0        # drift-diffusion: dielectric time-step constant A_D (0: off)
 
     def to_c(self) -> _Phys:
         p = _Phys()
@@ -73,6 +74,7 @@ class Phys:
         p.nspecies, p.closure = self.nspecies, int(bool(self.closure))
         p.beta, p.cfl, p.fourier = self.beta, self.cfl, self.fourier
         p.gamma, p.entropy_fix = self.gamma, self.entropy_fix
+        p.diel = self.diel
         for k, (z, mu, D) in enumerate(zip(self.z, self.mu, self.D)):
             p.z[k], p.mu[k], p.D[k] = z, mu, D
         if self.mixture is not None:

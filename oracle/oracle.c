@@ -24,7 +24,8 @@
  *                 eq. (virtual_node_reconstruction) and the co-reconstruction
  *                 of pressure
  *   closure       Sec. "Boundary conditions in AVIP", first option (node flux)
- *   time step     Sec. "Time step computation", eqs. (dt_conv), (dt_diff)
+ *   time step     Sec. "Time step computation", eqs. (dt_conv), (dt_diff) and
+ *                 the dielectric time step
  *   RK            Sec. "Time integration of the HLLC MUSCL-Hancock solver",
  *                 table (rk_coeffs)
  *   multi-species eq. (ns_reactive) without sources (transport only), total
@@ -89,6 +90,8 @@ int om_nvar(int nd, const om_phys *ph) {
 #define OM_RGAS 8.314462618
 #define OM_T0 298.15
 #define OM_NEWTON 10
+#define OM_ECHARGE 1.602176634e-19  /* elementary charge [C] */
+#define OM_EPS0 8.8541878128e-12    /* vacuum permittivity [F/m] */
 
 /* species sensible enthalpy hs_k(T) = int_{T0}^{T} c_p,k */
 static double species_hs(const om_phys *ph, int k, double T) {
@@ -884,6 +887,22 @@ int om_timestep(const om_mesh *m, const om_phys *ph, const double *U, const doub
         }
         if (ph->D[s] > 0.0) {
           double t = ph->fourier * dx * dx / ph->D[s];
+          if (t < dt) dt = t;
+        }
+      }
+      /* dielectric limit A_D eps0 / sum_s |q_s n_s mu_s|, with the
+       * conductivity of the cell taken at its most conductive node */
+      if (ph->diel > 0.0) {
+        double smax = 0.0;
+        for (int k = 0; k < nv; k++) {
+          int64_t i = m->cell[c * nv + k];
+          double sig = 0.0;
+          for (int s = 0; s < ph->nspecies; s++)
+            sig += fabs(OM_ECHARGE * ph->z[s] * U[(int64_t)s * nn + i] * ph->mu[s]);
+          if (sig > smax) smax = sig;
+        }
+        if (smax > 0.0) {
+          double t = ph->diel * OM_EPS0 / smax;
           if (t < dt) dt = t;
         }
       }

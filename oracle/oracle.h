@@ -43,6 +43,7 @@ typedef struct {
   double cpa[OM_MAXSP], cpb[OM_MAXSP], cpc[OM_MAXSP]; /* c_p = R/W (a + b t + c t^2), t = T/1000 */
   double Sc[OM_MAXSP];                 /* Schmidt numbers */
   double mu_ref, T_ref, Pr;            /* mu = mu_ref (T/T_ref)^0.7, lambda = mu c_p / Pr */
+  double diel;                         /* drift-diffusion: dielectric time-step constant A_D (0: off) */
 } om_phys;
 
 typedef struct om_mesh om_mesh;

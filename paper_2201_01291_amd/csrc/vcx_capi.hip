@@ -202,7 +202,10 @@ static DtCoef dt_coef(const vcx_physics& ph) {
   for (int k = 0; k < 4 && k < ph.nspecies; ++k) {
     c.zmu[k] = ph.z[k] * ph.mu[k];
     c.D[k] = ph.D[k];
+    c.ez[k] = 1.602176634e-19 * ph.z[k];  // elementary charge [C] times the charge number
+    c.mu[k] = ph.mu[k];
   }
+  if (ph.model == VCX_MODEL_DRIFT_DIFFUSION && ph.diel > 0.0) c.adeps = ph.diel * 8.8541878128e-12;  // eps0 [F/m]
   return c;
 }
 

@@ -417,6 +417,9 @@ __device__ inline void step_finish(DevLoop* lp, int par) {
 struct DtCoef {
   double cfl, fourier, gamma;
   double zmu[4], D[4];
+  // dielectric limit A_D eps0 / sum_s |q_s n_s mu_s| (0: off): A_D eps0,
+  // e z_s and mu_s per species
+  double adeps, ez[4], mu[4];
 };
 
 template <int ND, int NSP, int MODEL>
@@ -445,6 +448,12 @@ __device__ inline double node_dt(const DtCoef& c, double dx, const double* Ei, c
       const double vmax = sqrt(v2);
       if (vmax > 0.0) best = fmin(best, c.cfl * dx / vmax);
       if (c.D[s] > 0.0) best = fmin(best, c.fourier * dx * dx / c.D[s]);
+    }
+    if (c.adeps > 0.0) {
+      double sig = 0.0;
+#pragma unroll
+      for (int s = 0; s < NSP; ++s) sig += fabs(c.ez[s] * u[s] * c.mu[s]);
+      if (sig > 0.0) best = fmin(best, c.adeps / sig);
     }
     return best;
   }

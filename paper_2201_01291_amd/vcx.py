@@ -56,16 +56,17 @@ class Physics(C.Structure):
                 ("Wk", C.c_double * MAX_SPECIES), ("cpa", C.c_double * MAX_SPECIES),
                 ("cpb", C.c_double * MAX_SPECIES), ("cpc", C.c_double * MAX_SPECIES),
                 ("Sc", C.c_double * MAX_SPECIES), ("mu_ref", C.c_double), ("T_ref", C.c_double),
-                ("Pr", C.c_double)]
+                ("Pr", C.c_double), ("diel", C.c_double)]
 
 
 def physics(model=MODEL_GAS, flux=FLUX_HLLC, limiter=LIM_MINMOD, rk_stages=2, nspecies=0,
             closure=True, precision=PREC_FP64, beta=1.0, cfl=0.5, fourier=0.25, gamma=1.4,
-            entropy_fix=0.1, z=(), mu=(), D=(), mixture=None) -> Physics:
+            entropy_fix=0.1, z=(), mu=(), D=(), mixture=None, diel=0.0) -> Physics:
     p = Physics()
     p.model, p.flux, p.limiter, p.rk_stages = model, flux, limiter, rk_stages
     p.nspecies, p.closure, p.precision = nspecies, int(bool(closure)), precision
     p.beta, p.cfl, p.fourier, p.gamma, p.entropy_fix = beta, cfl, fourier, gamma, entropy_fix
+    p.diel = diel
     for k, (a, b, c) in enumerate(zip(z, mu, D)):
         p.z[k], p.mu[k], p.D[k] = a, b, c
     if mixture is not None:

@@ -34,7 +34,7 @@ class Case:
                            beta=s.get("beta", 1.0), cfl=s.get("cfl", 0.5),
                            fourier=s.get("fourier", 0.25), gamma=1.4,
                            entropy_fix=s.get("fix", 0.1), z=s.get("z", []), mu=s.get("mu", []),
-                           D=s.get("D", []), mixture=s.get("mixture"))
+                           D=s.get("D", []), mixture=s.get("mixture"), diel=s.get("diel", 0.0))
 
     def vcx_phys(self, precision=0):
         from paper_2201_01291_amd import vcx
@@ -45,7 +45,7 @@ class Case:
                            precision=precision, beta=s.get("beta", 1.0), cfl=s.get("cfl", 0.5),
                            fourier=s.get("fourier", 0.25), gamma=1.4,
                            entropy_fix=s.get("fix", 0.1), z=s.get("z", []), mu=s.get("mu", []),
-                           D=s.get("D", []), mixture=s.get("mixture"))
+                           D=s.get("D", []), mixture=s.get("mixture"), diel=s.get("diel", 0.0))
 
 
 DD2 = dict(model="dd", limiter="minmod", rk=1, nspecies=2, z=[-1.0, 1.0], mu=[0.04, 0.04],
@@ -57,6 +57,11 @@ def make_case(name: str) -> Case:
         m = wl.dd_streamer_mesh(40, 25)
         n, E = wl.dd_fields(m, sigma=2e-3)
         return Case(name, m, n, E, dict(DD2))
+    if name == "dd2d-diel":
+        # dense plasma: the dielectric limit sets the time step
+        m = wl.dd_streamer_mesh(40, 25, seed=3)
+        n, E = wl.dd_fields(m, sigma=2e-3, seed=8, peak=2e19)
+        return Case(name, m, n, E, dict(DD2, diel=0.8))
     if name == "dd2d-open-vanleer":
         m = wl.tri_rect_mesh(23, 17, 0.02, 0.015, jitter=0.2, seed=9)
         n, E = wl.dd_fields(m, sigma=3e-3, seed=4)
@@ -105,7 +110,7 @@ def make_case(name: str) -> Case:
     raise KeyError(name)
 
 
-CASE_NAMES = ["dd2d-streamer", "dd2d-open-vanleer", "dd3d-sweby", "sod-hllc", "euler2d-roe-sp2",
+CASE_NAMES = ["dd2d-streamer", "dd2d-diel", "dd2d-open-vanleer", "dd3d-sweby", "sod-hllc", "euler2d-roe-sp2",
               "euler3d-roe", "euler3d-hllc-open-sp2", "euler3d-hllc-sp9", "ns3d-sp9",
               "ns2d-sp2-open"]
 

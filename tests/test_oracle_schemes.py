@@ -332,3 +332,21 @@ def test_unstable_state_is_reported():
     with pytest.raises(oracle.OracleError) as e:
         oracle.OracleMesh(m).step(oracle.Phys(model=GAS), U, nsteps=1)
     assert e.value.code == -5
+
+
+def test_dielectric_time_step_by_hand():
+    """Sec. "Time step computation": with the dielectric constant A_D set,
+    uniform dense charges and no field the time step is A_D eps0 /
+    sum_s |q_s n_s mu_s| (the diffusive limit is far larger here)."""
+    m = wl.tri_rect_mesh(6, 5, 1e-3, 1e-3, jitter=0.2, seed=2, periodic=True)
+    om = oracle.OracleMesh(m)
+    n = np.vstack([np.full(m.nnodes, 3e18), np.full(m.nnodes, 1e18)])
+    E = np.zeros((2, m.nnodes))
+    base = dict(model=oracle.DRIFT_DIFFUSION, limiter=oracle.MINMOD, rk=1, nspecies=2,
+                z=[-1.0, 1.0], mu=[0.05, 0.002], D=[1e-3, 1e-3], cfl=0.5, fourier=0.25)
+    e, eps0 = 1.602176634e-19, 8.8541878128e-12
+    expect = 0.7 * eps0 / (e * (3e18 * 0.05 + 1e18 * 0.002))
+    dt = om.timestep(oracle.Phys(**base, diel=0.7), n, E)
+    assert dt == pytest.approx(expect, rel=1e-14)
+    # without the limit the diffusive one applies, and it is much larger
+    assert om.timestep(oracle.Phys(**base), n, E) > 100 * expect
