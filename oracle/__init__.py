@@ -102,6 +102,10 @@ def lib():
         L.om_mesh_create.restype = C.c_void_p
         L.om_mesh_create.argtypes = [C.c_int, C.c_int64, dp, C.c_int64, C.c_int, ip, dp,
                                      C.POINTER(C.c_int)]
+        L.om_mesh_create_axi.restype = C.c_void_p
+        L.om_mesh_create_axi.argtypes = [C.c_int, C.c_int64, dp, C.c_int64, C.c_int, ip, dp, C.c_int,
+                                         C.POINTER(C.c_int)]
+        L.om_axi_geometry.argtypes = [C.c_void_p, dp, dp]
         L.om_mesh_destroy.argtypes = [C.c_void_p]
         L.om_mesh_counts.argtypes = [C.c_void_p, ip]
         L.om_geometry.argtypes = [C.c_void_p, dp, dp, dp, dp]
@@ -147,8 +151,9 @@ class OracleError(RuntimeError):
 class OracleMesh:
     """FP64 oracle view of a mesh (geometry computed once at construction)."""
 
-    def __init__(self, mesh):
+    def __init__(self, mesh, axisymmetric: bool = False):
         L = lib()
+        self.axi = bool(axisymmetric)
         self.nd, self.nn = mesh.ndim, mesh.nnodes
         self.nc, self.nv = mesh.ncells, mesh.nv
         self.ne = 3 if self.nv == 3 else 6
@@ -156,9 +161,9 @@ class OracleMesh:
         cells = np.ascontiguousarray(mesh.cells, dtype=np.int64)
         per = None if mesh.period is None else _c64(mesh.period)
         st = C.c_int(0)
-        h = L.om_mesh_create(self.nd, self.nn, _d(xyz), self.nc, self.nv,
-                             cells.ctypes.data_as(C.POINTER(C.c_int64)),
-                             _d(per) if per is not None else None, C.byref(st))
+        h = L.om_mesh_create_axi(self.nd, self.nn, _d(xyz), self.nc, self.nv,
+                                 cells.ctypes.data_as(C.POINTER(C.c_int64)),
+                                 _d(per) if per is not None else None, int(self.axi), C.byref(st))
         if not h:
             raise OracleError(st.value, "mesh_create")
         self._h = C.c_void_p(h)
@@ -181,6 +186,14 @@ class OracleMesh:
         Sb = np.zeros((self.nd, self.nn))
         lib().om_geometry(self._h, _d(S), _d(Vc), _d(Vn), _d(Sb))
         return dict(S=S, Vc=Vc, Vn=Vn, Sb=Sb)
+
+    def axi_geometry(self):
+        """Axisymmetric meshes: node volumes int r dA over 2 pi and the
+        radius-weighted boundary normals [nd][nn]."""
+        Vp = np.zeros(self.nn)
+        Sbr = np.zeros((self.nd, self.nn))
+        lib().om_axi_geometry(self._h, _d(Vp), _d(Sbr))
+        return Vp, Sbr
 
     def edge_normals(self):
         Sij = np.zeros((self.nc, self.ne, self.nd))

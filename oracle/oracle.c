@@ -24,6 +24,8 @@
  *                 eq. (virtual_node_reconstruction) and the co-reconstruction
  *                 of pressure
  *   closure       Sec. "Boundary conditions in AVIP", first option (node flux)
+ *   axisymmetry   Sec. "Cylindrical frames" (Pappus-Guldinus theorems) and
+ *                 eq. (vertex_centered_flux_axi), drift-diffusion only
  *   time step     Sec. "Time step computation", eqs. (dt_conv), (dt_diff) and
  *                 the dielectric time step
  *   RK            Sec. "Time integration of the HLLC MUSCL-Hancock solver",
@@ -68,6 +70,14 @@ struct om_mesh {
   double *Sb;    /* [nn][nd] boundary node normals */
   char *bnd;     /* [nn] node lies on the domain boundary */
   int64_t nbfaces;
+  /* axisymmetric (x, r) meshes (Sec. "Cylindrical frames"): the second
+   * coordinate is the radius; fluxes through revolved dual faces carry the
+   * centroid radius of the face (first Pappus-Guldinus theorem), node volumes
+   * are int r dA over the dual region (second theorem), both over 2 pi */
+  int axi;
+  double *Rf;    /* [nc][ne] centroid radius of each cell-edge piece of the dual surface */
+  double *Vp;    /* [nn] int_{A_i} r dA */
+  double *Sbr;   /* [nn][nd] boundary node normals weighted by the centroid radius */
 };
 
 /* local cell-edges, oriented from the lower to the higher local vertex */
@@ -278,13 +288,23 @@ static void sort_small(int64_t *v, int n) {
 void om_mesh_destroy(om_mesh *m) {
   if (!m) return;
   free(m->cell); free(m->X); free(m->S); free(m->Vc); free(m->Vn); free(m->Sb); free(m->bnd);
+  free(m->Rf); free(m->Vp); free(m->Sbr);
   free(m);
 }
 
 om_mesh *om_mesh_create(int nd, int64_t nn, const double *xyz, int64_t nc, int nv,
                         const int64_t *cells, const double *period, int *status) {
+  return om_mesh_create_axi(nd, nn, xyz, nc, nv, cells, period, 0, status);
+}
+
+om_mesh *om_mesh_create_axi(int nd, int64_t nn, const double *xyz, int64_t nc, int nv,
+                            const int64_t *cells, const double *period, int axi, int *status) {
   *status = -1;
   if (!(nd == 2 || nd == 3) || nv != nd + 1 || nn <= 0 || nc <= 0 || !xyz || !cells) return NULL;
+  if (axi && (nd != 2 || (period && period[1] > 0.0))) return NULL;  /* (x, r) plane, r not periodic */
+  if (axi)
+    for (int64_t i = 0; i < nn; i++)
+      if (xyz[nn + i] < 0.0) return NULL;
   om_mesh *m = calloc(1, sizeof(*m));
   if (!m) { *status = -3; return NULL; }
   m->nd = nd; m->nv = nv; m->ne = nd == 2 ? 3 : 6; m->nn = nn; m->nc = nc;
@@ -323,6 +343,32 @@ om_mesh *om_mesh_create(int nd, int64_t nn, const double *xyz, int64_t nc, int n
     if (!(m->Vc[c] > 1e-12 * vmax)) { om_mesh_destroy(m); *status = -2; return NULL; }
   for (int64_t c = 0; c < nc; c++)
     for (int k = 0; k < nv; k++) m->Vn[m->cell[c * nv + k]] += m->Vc[c] / nv;
+  if (axi) {
+    m->axi = 1;
+    m->Rf = malloc(sizeof(double) * nc * 3);
+    m->Vp = calloc(nn, sizeof(double));
+    m->Sbr = calloc(nn * nd, sizeof(double));
+    if (!m->Rf || !m->Vp || !m->Sbr) { om_mesh_destroy(m); *status = -3; return NULL; }
+    for (int64_t c = 0; c < nc; c++) {
+      const double *X = m->X + c * 3 * 2;
+      const double r[3] = {X[1], X[3], X[5]};
+      const double rc = (r[0] + r[1] + r[2]) / 3.0;
+      /* dual piece of edge (a, b): from the edge midpoint to the centroid */
+      for (int e = 0; e < 3; e++) {
+        const int *ab = edge_of(3, e);
+        const double rm = 0.5 * (r[ab[0]] + r[ab[1]]);
+        m->Rf[c * 3 + e] = 0.5 * (rm + rc);
+      }
+      /* node k's dual region in the triangle: the quadrilateral (X_k,
+       * midpoint k-l, centroid, midpoint k-m), two triangles of area A/6 */
+      for (int k = 0; k < 3; k++) {
+        const int l = (k + 1) % 3, q = (k + 2) % 3;
+        const double ml = 0.5 * (r[k] + r[l]), mq = 0.5 * (r[k] + r[q]);
+        const double mom = m->Vc[c] / 6.0 * ((r[k] + ml + rc) / 3.0 + (r[k] + rc + mq) / 3.0);
+        m->Vp[m->cell[c * 3 + k]] += mom;
+      }
+    }
+  }
 
   /* boundary faces: faces owned by exactly one cell */
   int64_t nf = nc * nv;
@@ -352,6 +398,12 @@ om_mesh *om_mesh_create(int nd, int64_t nn, const double *xyz, int64_t nc, int n
         int64_t i = f[a].key[q];
         m->bnd[i] = 1;
         for (int d = 0; d < nd; d++) m->Sb[i * nd + d] += Sk[d] / nd;
+        if (m->axi) {
+          /* node i's half of the boundary edge: centroid radius (3 r_i + r_j)/4 */
+          const int64_t j = f[a].key[1 - q];
+          const double rf = 0.75 * xyz[nn + i] + 0.25 * xyz[nn + j];
+          for (int d = 0; d < nd; d++) m->Sbr[i * nd + d] += Sk[d] / nd * rf;
+        }
       }
       m->nbfaces++;
     }
@@ -366,6 +418,16 @@ void om_mesh_counts(const om_mesh *m, int64_t *out) {
   int64_t nb = 0;
   for (int64_t i = 0; i < m->nn; i++) nb += m->bnd[i];
   out[0] = m->nn; out[1] = m->nc; out[2] = m->nbfaces; out[3] = nb;
+}
+
+/* axisymmetric meshes: int_{A_i} r dA per node (else copies V_i), and the
+ * radius-weighted boundary normals [nd][nn] */
+void om_axi_geometry(const om_mesh *m, double *Vp, double *Sbr) {
+  for (int64_t i = 0; i < m->nn; i++) {
+    if (Vp) Vp[i] = m->axi ? m->Vp[i] : m->Vn[i];
+    if (Sbr)
+      for (int d = 0; d < m->nd; d++) Sbr[d * m->nn + i] = m->axi ? m->Sbr[i * m->nd + d] : m->Sb[i * m->nd + d];
+  }
 }
 
 void om_geometry(const om_mesh *m, double *S, double *Vc, double *Vn, double *Sb) {
@@ -751,6 +813,7 @@ static int residual_dd(const om_mesh *m, const om_phys *ph, const double *U, con
         double psi = om_psi_limiter(ph->limiter, ph->beta, a, b);
         double uf = u[w] + (0.5 * b - 0.5 * dt * gV) * psi;
         double F = uf * v - ph->D[s] * gS;
+        if (m->axi) F *= m->Rf[c * 3 + e]; /* flux through the revolved face, over 2 pi */
         r[(int64_t)s * nn + i] += absmode ? fabs(F) : F;
         r[(int64_t)s * nn + j] -= absmode ? -fabs(F) : F;
       }
@@ -760,11 +823,12 @@ static int residual_dd(const om_mesh *m, const om_phys *ph, const double *U, con
     /* supersonic-type boundary: F = F_C + F_D with node values */
     for (int64_t i = 0; i < nn; i++) {
       if (!m->bnd[i]) continue;
+      const double *Sb = m->axi ? m->Sbr + i * nd : m->Sb + i * nd;
       for (int s = 0; s < ns; s++) {
         double zm = ph->z[s] * ph->mu[s], vb = 0.0, gb = 0.0;
         for (int d = 0; d < nd; d++) {
-          vb += zm * E[(int64_t)d * nn + i] * m->Sb[i * nd + d];
-          gb += G[((int64_t)s * nd + d) * nn + i] * m->Sb[i * nd + d];
+          vb += zm * E[(int64_t)d * nn + i] * Sb[d];
+          gb += G[((int64_t)s * nd + d) * nn + i] * Sb[d];
         }
         double F = U[(int64_t)s * nn + i] * vb - ph->D[s] * gb;
         r[(int64_t)s * nn + i] += absmode ? fabs(F) : F;
@@ -779,7 +843,10 @@ static int residual_any(const om_mesh *m, const om_phys *ph, const double *U, co
                         double dt, double *r, int absmode) {
   if (!m || !ph || !U || !r) return -1;
   if (ph->nspecies < 0 || ph->nspecies > OM_MAXSP) return -1;
-  if (ph->model == 0 || ph->model == 2) return residual_gas(m, ph, U, r, absmode);
+  if (ph->model == 0 || ph->model == 2) {
+    if (m->axi) return -1; /* axisymmetric gas needs the geometric source terms: not built */
+    return residual_gas(m, ph, U, r, absmode);
+  }
   if (ph->model == 1) {
     if (!E || ph->nspecies < 1) return -1;
     return residual_dd(m, ph, U, E, dt, r, absmode);
@@ -953,6 +1020,7 @@ int om_step(const om_mesh *m, const om_phys *ph, double *U, const double *E, int
   if (ph->rk < 1 || ph->rk > 4) return -1;
   int nvar = om_nvar(m->nd, ph);
   int64_t nn = m->nn, tot = (int64_t)nvar * nn;
+  const double *vol = m->axi ? m->Vp : m->Vn; /* the node volume the update divides by */
   double *U0 = malloc(sizeof(double) * tot), *Uk = malloc(sizeof(double) * tot);
   double *r = malloc(sizeof(double) * tot);
   if (!U0 || !Uk || !r) { free(U0); free(Uk); free(r); return -3; }
@@ -973,7 +1041,7 @@ int om_step(const om_mesh *m, const om_phys *ph, double *U, const double *E, int
       if (st) break;
       for (int v = 0; v < nvar; v++)
         for (int64_t i = 0; i < nn; i++)
-          Uk[(int64_t)v * nn + i] = U0[(int64_t)v * nn + i] - a * dt * r[(int64_t)v * nn + i] / m->Vn[i];
+          Uk[(int64_t)v * nn + i] = U0[(int64_t)v * nn + i] - a * dt * r[(int64_t)v * nn + i] / vol[i];
     }
     if (st) break;
     if (!state_ok(m, ph, Uk)) { st = -5; break; }
@@ -997,7 +1065,7 @@ void om_sums(const om_mesh *m, int nvar, const double *U, double *sums, double *
   for (int v = 0; v < nvar; v++) {
     double s = 0.0, comp = 0.0, a = 0.0, acomp = 0.0;
     for (int64_t i = 0; i < m->nn; i++) {
-      double x = m->Vn[i] * U[(int64_t)v * m->nn + i];
+      double x = (m->axi ? m->Vp[i] : m->Vn[i]) * U[(int64_t)v * m->nn + i];
       double t = s + x;
       if (fabs(s) >= fabs(x)) comp += (s - t) + x; else comp += (x - t) + s;
       s = t;

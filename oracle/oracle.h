@@ -50,6 +50,11 @@ typedef struct om_mesh om_mesh;
 
 om_mesh *om_mesh_create(int nd, int64_t nn, const double *xyz, int64_t nc, int nv,
                         const int64_t *cells, const double *period, int *status);
+/* axi = 1: (x, r) plane of an axisymmetric domain (2D, r >= 0, r not
+ * periodic): radius-weighted fluxes and node volumes over 2 pi */
+om_mesh *om_mesh_create_axi(int nd, int64_t nn, const double *xyz, int64_t nc, int nv,
+                            const int64_t *cells, const double *period, int axi, int *status);
+void om_axi_geometry(const om_mesh *m, double *Vp, double *Sbr);
 void om_mesh_destroy(om_mesh *m);
 void om_mesh_counts(const om_mesh *m, int64_t *out /* nn, nc, nbnd_faces, nbnd_nodes */);
 
