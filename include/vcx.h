@@ -147,6 +147,21 @@ vcx_status vcx_mesh_create_tiled(int ndim, int64_t nnodes, const double *xyz, in
                                  int nv, const int64_t *cells, const double *period,
                                  int max_tile_cells, int max_tile_nodes, void *stream,
                                  vcx_mesh *out);
+/* Axisymmetric domain (Sec. "Cylindrical frames", eq. vertex_centered_flux_axi):
+ * a triangle mesh of the (x, r) half-plane, xr host [2][nnodes] with r >= 0,
+ * cells host [3][ncells]; period_x > 0 makes x periodic (r never is).  Fluxes
+ * through the revolved dual faces carry the centroid radius of each dual
+ * face piece (first Pappus-Guldinus theorem), node volumes of the update and
+ * of vcx_conservation_sums are int r dA over each node's dual region (second
+ * theorem; exact, and non-zero on the axis), and boundary closures use the
+ * radius-weighted boundary normals; all over 2 pi.  Nodal gradients stay
+ * planar.  Drift-diffusion solvers only; such solvers are not batched or
+ * served (VCX_E_ARG).  vcx_mesh_geometry returns the planar V_i and the
+ * radius-weighted S_i^b.  Errors as vcx_mesh_create_tiled, and VCX_E_ARG
+ * for r < 0. */
+vcx_status vcx_mesh_create_axisymmetric(int64_t nnodes, const double *xr, int64_t ncells,
+                                        const int64_t *cells, double period_x, int max_tile_cells,
+                                        int max_tile_nodes, void *stream, vcx_mesh *out);
 vcx_status vcx_mesh_destroy(vcx_mesh mesh);
 
 /* Mesh counters: out[0] nnodes, [1] ncells, [2] cell-edges (faces),

@@ -52,6 +52,7 @@ vcx_status set_error(vcx_status s, const char* msg);
 int mesh_ndim(vcx_mesh m);
 int64_t mesh_nnodes(vcx_mesh m);
 const HostMesh* mesh_host(vcx_mesh m);        // preprocessed mesh, internal order
+bool mesh_axisymmetric(vcx_mesh m);
 hipStream_t mesh_stream(vcx_mesh m);          // stream of the mesh and its solvers
 const int32_t* mesh_perm_device(vcx_mesh m);  // [nn] internal node -> caller node (device)
 int solver_failed(vcx_solver s);

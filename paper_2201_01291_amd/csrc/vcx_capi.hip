@@ -316,6 +316,14 @@ struct Impl {
       pp.beta = s->ph.beta;
       pp.dt_host = dt_host;
       pp.limiter = s->ph.limiter;
+      if constexpr (ND == 2) {
+        if (m.axi)
+          return launch(s, "flux", [&](hipEvent_t ea, hipEvent_t eb) {
+            hipExtLaunchKernelGGL((k_flux_dd<ND, NSP, CT, true>), dim3(xcd_grid(m.ntiles)),
+                               dim3(s->tile_block), s->lds_flux, st, ea, eb, 0, m, Win, (const double*)s->G,
+                               s->PR, pp, f);
+          });
+      }
       return launch(s, "flux", [&](hipEvent_t ea, hipEvent_t eb) {
         hipExtLaunchKernelGGL((k_flux_dd<ND, NSP, CT>), dim3(xcd_grid(m.ntiles)),
                            dim3(s->tile_block), s->lds_flux, st, ea, eb, 0, m, Win, (const double*)s->G,
@@ -359,9 +367,13 @@ struct Impl {
     else if constexpr (MODEL == 2)
       VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_ns<ND, NSP, CT>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)flux_bytes));
-    else
+    else {
       VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_dd<ND, NSP, CT>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)flux_bytes));
+      if constexpr (ND == 2)
+        VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_dd<ND, NSP, CT, true>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)flux_bytes));
+    }
     VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_grad_tile_batch<ND, NGF>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)grad_bytes));
     if constexpr (MODEL == 0)
@@ -533,10 +545,29 @@ extern "C" vcx_status vcx_mesh_create(int ndim, int64_t nnodes, const double* xy
   return vcx_mesh_create_tiled(ndim, nnodes, xyz, ncells, nv, cells, period, 0, 0, stream, out);
 }
 
+static vcx_status create_mesh(int ndim, int64_t nnodes, const double* xyz, int64_t ncells, int nv,
+                              const int64_t* cells, const double* period, int max_tile_cells,
+                              int max_tile_nodes, void* stream, bool axi, vcx_mesh* out);
+
 extern "C" vcx_status vcx_mesh_create_tiled(int ndim, int64_t nnodes, const double* xyz,
                                             int64_t ncells, int nv, const int64_t* cells,
                                             const double* period, int max_tile_cells,
                                             int max_tile_nodes, void* stream, vcx_mesh* out) {
+  return create_mesh(ndim, nnodes, xyz, ncells, nv, cells, period, max_tile_cells, max_tile_nodes, stream,
+                     false, out);
+}
+
+extern "C" vcx_status vcx_mesh_create_axisymmetric(int64_t nnodes, const double* xr, int64_t ncells,
+                                                   const int64_t* cells, double period_x, int max_tile_cells,
+                                                   int max_tile_nodes, void* stream, vcx_mesh* out) {
+  const double period[2] = {period_x, 0.0};
+  return create_mesh(2, nnodes, xr, ncells, 3, cells, period, max_tile_cells, max_tile_nodes, stream, true,
+                     out);
+}
+
+static vcx_status create_mesh(int ndim, int64_t nnodes, const double* xyz, int64_t ncells, int nv,
+                              const int64_t* cells, const double* period, int max_tile_cells,
+                              int max_tile_nodes, void* stream, bool axi, vcx_mesh* out) {
   if (!out) return fail(VCX_E_ARG, "out is NULL");
   *out = nullptr;
   if (ndim != 2 && ndim != 3) return fail(VCX_E_ARG, "ndim must be 2 or 3");
@@ -547,7 +578,7 @@ extern "C" vcx_status vcx_mesh_create_tiled(int ndim, int64_t nnodes, const doub
   vcx_mesh m = new (std::nothrow) vcx_mesh_s();
   if (!m) return fail(VCX_E_OOM, "host allocation failed");
   int code = 0;
-  std::string err = preprocess_mesh(ndim, nnodes, xyz, ncells, nv, cells, period, lim, m->h, &code);
+  std::string err = preprocess_mesh(ndim, nnodes, xyz, ncells, nv, cells, period, lim, m->h, &code, axi);
   if (!err.empty()) {
     delete m;
     return fail(code == -2 ? VCX_E_MESH : VCX_E_ARG, err);
@@ -636,6 +667,17 @@ extern "C" vcx_status vcx_mesh_create_tiled(int ndim, int64_t nnodes, const doub
   }
   chk(upload(m, inv, &d.inv_vol));
   chk(upload(m, h.vnode, &d.vnode));
+  d.axi = h.axi ? 1 : 0;
+  if (h.axi) {
+    // the update and the conservation sums use the revolved volumes
+    std::vector<double> invu(h.nn);
+    for (int64_t i = 0; i < h.nn; ++i) invu[i] = 1.0 / h.vupd[i];
+    chk(upload(m, invu, &d.inv_vupd));
+    chk(upload(m, h.vupd, &d.vupd));
+  } else {
+    d.inv_vupd = d.inv_vol;
+    d.vupd = d.vnode;
+  }
   chk(upload(m, bidx, &d.bnd_index));
   chk(upload(m, h.bnd_S, &d.bnd_S));
   chk(upload(m, h.perm, &d.perm));
@@ -829,6 +871,8 @@ extern "C" vcx_status vcx_solver_create(vcx_mesh mesh, const vcx_physics* phys, 
     if (!(ph.mu_ref >= 0.0) || !(ph.T_ref > 0.0) || !(ph.Pr > 0.0))
       return fail(VCX_E_ARG, "Navier-Stokes needs mu_ref >= 0, T_ref > 0, Pr > 0");
   }
+  if (mesh->h.axi && ph.model != VCX_MODEL_DRIFT_DIFFUSION)
+    return fail(VCX_E_ARG, "axisymmetric meshes support the drift-diffusion model only");
   if (ph.rk_stages < 1 || ph.rk_stages > 4) return fail(VCX_E_ARG, "rk_stages must be 1..4");
   if (ph.limiter < 0 || ph.limiter > 4) return fail(VCX_E_ARG, "unknown limiter");
   if (ph.precision != VCX_PREC_FP64 && ph.precision != VCX_PREC_MIXED)
@@ -867,7 +911,9 @@ extern "C" vcx_status vcx_solver_create(vcx_mesh mesh, const vcx_physics* phys, 
   // the fused gradient + flux pass where the mesh has extended tiles and
   // they fit the device's LDS
   s->lds_fused = kt->lds_fused(d);
-  s->fused = s->lds_fused > 0 && s->lds_fused <= (size_t)mesh->lds_max;
+  // the fused pass is for plane meshes; axisymmetric ones take the
+  // gradient + flux passes, whose flux carries the face radii
+  s->fused = !d.axi && s->lds_fused > 0 && s->lds_fused <= (size_t)mesh->lds_max;
   if (!s->fused) s->lds_fused = 0;
   if (std::max({s->lds_grad, s->lds_flux, s->lds_fused}) > 65536) {
     vcx_status st = kt->allow_lds(s->lds_grad, s->lds_flux, s->lds_fused);
@@ -1235,6 +1281,8 @@ vcx_status vcx::batch_set(BatchGroup* g, vcx_solver* ss, int n, const int* steps
     (void)hipGraphExecDestroy(g->pair);
     g->pair = nullptr;
   }
+  for (int i = 0; i < n; ++i)
+    if (ss[i] && ss[i]->mesh->h.axi) return fail(VCX_E_ARG, "solvers on axisymmetric meshes are not batched");
   g->mem.assign(ss, ss + n);
   g->q = 0;
   if (n == 0) return VCX_OK;
@@ -1385,6 +1433,7 @@ vcx_status vcx::set_error(vcx_status s, const char* msg) { return fail(s, msg ? 
 int vcx::mesh_ndim(vcx_mesh m) { return m ? m->h.nd : 0; }
 int64_t vcx::mesh_nnodes(vcx_mesh m) { return m ? m->d.nn : 0; }
 const vcx::HostMesh* vcx::mesh_host(vcx_mesh m) { return m ? &m->h : nullptr; }
+bool vcx::mesh_axisymmetric(vcx_mesh m) { return m && m->h.axi; }
 hipStream_t vcx::mesh_stream(vcx_mesh m) { return m ? m->stream : nullptr; }
 const int32_t* vcx::mesh_perm_device(vcx_mesh m) { return m ? m->d.perm : nullptr; }
 int vcx::solver_failed(vcx_solver s) { return s ? s->host_flag : 0; }
@@ -1400,6 +1449,7 @@ static vcx_status solve_batch(vcx_solver* ss, int n, const int* nsteps, const do
     if (!ss[i]->has_state) return fail(VCX_E_STATE, "batch member without a state");
     if (ss[i]->host_flag) return fail(VCX_E_UNSTABLE, "batch member in a failed state");
     if (nsteps[i] < 0) return fail(VCX_E_ARG, "nsteps must be >= 0");
+    if (ss[i]->mesh->h.axi) return fail(VCX_E_ARG, "solvers on axisymmetric meshes are not batched");
     if (!batch_compatible(ss[i], ss[0]))
       return fail(VCX_E_ARG, "batch members must share the model and scheme parameters");
     for (int j = 0; j < i; ++j)
@@ -1452,7 +1502,7 @@ extern "C" vcx_status vcx_conservation_sums(vcx_solver s, double* sums) {
   if (!s->has_state) return fail(VCX_E_STATE, "no state uploaded");
   const DevMesh& d = s->mesh->d;
   hipLaunchKernelGGL(k_sums_partial, dim3(256), dim3(256), 0, s->mesh->stream,
-                     (const double*)s->W[s->cur], d.vnode, d.nn, s->nvar, s->part);
+                     (const double*)s->W[s->cur], d.vupd, d.nn, s->nvar, s->part);
   hipLaunchKernelGGL(k_sums_final, dim3(1), dim3(256), 0, s->mesh->stream, (const double*)s->part,
                      256, s->nvar, s->sums_dev);
   VCX_HIP(hipGetLastError());

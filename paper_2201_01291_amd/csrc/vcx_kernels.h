@@ -69,8 +69,13 @@ struct DevMesh {
   const int32_t* slot_ginc;   // [P+1]
   const uint16_t* ginc;
   const int32_t* tile_ginc;   // [T+1]
-  const double* inv_vol;     // [nn]
+  const double* inv_vol;     // [nn] 1 / V_i (gradients; the update on plane meshes)
   const double* vnode;       // [nn]
+  // volumes of the update and of the conservation sums: V_i, or on
+  // axisymmetric (x, r) meshes int r dA over the dual region (over 2 pi)
+  const double* inv_vupd;    // [nn]
+  const double* vupd;        // [nn]
+  int axi;                   // axisymmetric (x, r) mesh
   const double* dxmin;       // [nn] smallest inscribed diameter of the cells around the node
   const int32_t* bnd_index;  // [nn] -1 or index into bnd_S
   const double* bnd_S;       // [nd][nb]
@@ -726,7 +731,7 @@ __device__ inline void node_in_load(const DevMesh& m, const Finish& f, double dt
   if (f.residual_only) return;
 #pragma unroll
   for (int v = 0; v < NVAR; ++v) ni.Un[v] = f.Un[(size_t)v * m.nn + i];
-  ni.fac = f.alpha * dt * m.inv_vol[i];
+  ni.fac = f.alpha * dt * m.inv_vupd[i];
   ni.dx = m.dxmin[i];
   if constexpr (MODEL == 1) {
 #pragma unroll
@@ -751,7 +756,7 @@ __device__ inline void node_in_lds(const DevMesh& m, const Finish& f, double dt,
   if (f.residual_only) return;
 #pragma unroll
   for (int v = 0; v < NVAR; ++v) ni.Un[v] = nl.un ? nl.un[v * nl.ldu + q] : f.Un[(size_t)v * m.nn + i];
-  ni.fac = f.alpha * dt * (nl.iv ? nl.iv[q] : m.inv_vol[i]);
+  ni.fac = f.alpha * dt * (nl.iv ? nl.iv[q] : m.inv_vupd[i]);
   ni.dx = nl.dx ? nl.dx[q] : m.dxmin[i];
   if constexpr (MODEL == 1) {
 #pragma unroll
@@ -944,11 +949,12 @@ __device__ inline void gas_cell_fluxes(const DevMesh& m, const TilePre<NV>& tp, 
 // Drift-diffusion fluxes of the tile's cells: limited Lax-Wendroff
 // convective flux (upwind node w, downwind node m, virtual node upwind of w)
 // plus central diffusion; accumulated per cell vertex into sR.
-template <int ND, int NS, typename CT, int NV>
+template <int ND, int NS, typename CT, int NV, bool AXI = false>
 __device__ inline void dd_cell_fluxes(const DevMesh& m, const TilePre<NV>& tp, const double* sX,
                                       const CT* sU, const CT* sG, const CT* sE, double* sR, CellLd L,
                                       CT dt, const DDParams& pp) {
   constexpr int NE = Edges<ND>::NE;
+  static_assert(!AXI || ND == 2, "axisymmetric meshes are (x, r) planes");
   const CT beta = CT(pp.beta);
   for (int lc = threadIdx.x; lc < tp.nc; lc += blockDim.x) {
     int l[NV];
@@ -972,6 +978,17 @@ __device__ inline void dd_cell_fluxes(const DevMesh& m, const TilePre<NV>& tp, c
         S[d] = CT((Sd[a][d] - Sd[b][d]) * (1.0 / double(ND * NV)));
         dx[d] = CT((a == 0 ? 0.0 : -e[a - 1][d]) + e[b - 1][d]);
         Ebar[d] = CT(0.5) * (sE[d * L.ldg + la] + sE[d * L.ldg + lb]);
+      }
+      // axisymmetric (x, r): the dual face piece of the edge, from its
+      // midpoint to the centroid, revolves at the mean of their radii (first
+      // Pappus-Guldinus theorem; the radius is never periodic)
+      double rw = 1.0;
+      if constexpr (AXI) {
+        double r[NV];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) r[k] = sX[L.ldx + l[k]];
+        const double rc = (r[0] + r[1] + r[2]) / 3.0;
+        rw = 0.5 * (0.5 * (r[a] + r[b]) + rc);
       }
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
@@ -998,8 +1015,8 @@ __device__ inline void dd_cell_fluxes(const DevMesh& m, const TilePre<NV>& tp, c
         const CT psi = psi_limit<CT>(pp.limiter, beta, aa, bb);
         const CT uf = uw + (CT(0.5) * bb - CT(0.5) * dt * gV) * psi;
         const CT F = uf * v - CT(pp.D[s]) * gS;
-        acc[a][s] += double(F);
-        acc[b][s] -= double(F);
+        acc[a][s] += double(F) * rw;
+        acc[b][s] -= double(F) * rw;
       }
     }
 #pragma unroll
@@ -1101,7 +1118,7 @@ __global__ void VCX_FLUX_BOUNDS k_flux_gas(DevMesh m, const double* __restrict__
 // drift-diffusion flux pass
 // ---------------------------------------------------------------------------
 
-template <int ND, int NS, typename CT>
+template <int ND, int NS, typename CT, bool AXI = false>
 __device__ inline void flux_dd_body(DevMesh m, const double* __restrict__ U,
                                                  const double* __restrict__ G,
                                                  double* __restrict__ PR, DDParams pp, Finish f,
@@ -1145,7 +1162,7 @@ __device__ inline void flux_dd_body(DevMesh m, const double* __restrict__ U,
   tile_store_inc<NV>(m, tp, sInc);
   __syncthreads();
   const double dt = f.sc ? f.sc->dt : pp.dt_host;
-  dd_cell_fluxes<ND, NS, CT, NV>(m, tp, sX, sU, sG, sE, sR, CellLd{maxn, maxn, maxn, maxc}, CT(dt), pp);
+  dd_cell_fluxes<ND, NS, CT, NV, AXI>(m, tp, sX, sU, sG, sE, sR, CellLd{maxn, maxn, maxn, maxc}, CT(dt), pp);
   __syncthreads();
   const double cand = tile_node_pass<ND, NS, 1, NS>(m, f, dt, PR, ns, sSl, maxn, sInc, sR, maxc);
   if (f.final_stage && f.sc) {
@@ -1154,14 +1171,14 @@ __device__ inline void flux_dd_body(DevMesh m, const double* __restrict__ U,
   }
 }
 
-template <int ND, int NS, typename CT>
+template <int ND, int NS, typename CT, bool AXI = false>
 __global__ void VCX_FLUX_BOUNDS k_flux_dd(DevMesh m, const double* __restrict__ U,
                                                  const double* __restrict__ G,
                                                  double* __restrict__ PR, DDParams pp, Finish f) {
   extern __shared__ double lds[];
   const int t = xcd_tile(m.ntiles);
   if (t >= m.ntiles) return;
-  flux_dd_body<ND, NS, CT>(m, U, G, PR, pp, f, t, lds);
+  flux_dd_body<ND, NS, CT, AXI>(m, U, G, PR, pp, f, t, lds);
 }
 
 // ---------------------------------------------------------------------------

@@ -86,7 +86,7 @@ void node_normals(int nd, const double e[3][3], double S[4][3]) {
 
 std::string preprocess_mesh(int nd, int64_t nn, const double* xyz, int64_t nc, int nv,
                             const int64_t* cells, const double* period, TileLimits lim,
-                            HostMesh& m, int* code) {
+                            HostMesh& m, int* code, bool axisymmetric) {
   *code = -1;
   if (nd != 2 && nd != 3) return "ndim must be 2 or 3";
   if (nv != nd + 1) return "only simplices are supported: nv must be ndim + 1";
@@ -104,6 +104,13 @@ std::string preprocess_mesh(int nd, int64_t nn, const double* xyz, int64_t nc, i
   }
   for (int64_t q = 0; q < (int64_t)nd * nn; ++q)
     if (!std::isfinite(xyz[q])) return "non-finite coordinate";
+  if (axisymmetric) {
+    if (nd != 2) return "axisymmetric meshes are two-dimensional (x, r)";
+    if (m.period[1] > 0.0) return "the radius of an axisymmetric mesh cannot be periodic";
+    for (int64_t i = 0; i < nn; ++i)
+      if (xyz[nn + i] < 0.0) return "axisymmetric meshes need r >= 0";
+    m.axi = true;
+  }
 
   // ---- connectivity, periodic images, orientation, volumes (caller order)
   *code = -2;
@@ -215,6 +222,25 @@ std::string preprocess_mesh(int nd, int64_t nn, const double* xyz, int64_t nc, i
   }
   m.vol_nodes = 0.0;
   for (int64_t i = 0; i < nn; ++i) m.vol_nodes += m.vnode[i];
+  m.vupd = m.vnode;
+  if (m.axi) {
+    // int r dA over node k's dual region in each triangle: the quadrilateral
+    // (X_k, midpoint k-l, centroid, midpoint k-m), two triangles of area A/6
+    // whose first moments are area times the mean vertex radius (second
+    // Pappus-Guldinus theorem over 2 pi); r is not periodic
+    std::fill(m.vupd.begin(), m.vupd.end(), 0.0);
+    for (int64_t c = 0; c < nc; ++c) {
+      double r[3];
+      for (int k = 0; k < 3; ++k) r[k] = m.x[(size_t)nn + m.cell[(size_t)k * nc + c]];
+      const double rc = (r[0] + r[1] + r[2]) / 3.0;
+      for (int k = 0; k < 3; ++k) {
+        const double ml = 0.5 * (r[k] + r[(k + 1) % 3]), mq = 0.5 * (r[k] + r[(k + 2) % 3]);
+        m.vupd[m.cell[(size_t)k * nc + c]] += cvol[c] / 6.0 * ((r[k] + ml + rc) / 3.0 + (r[k] + rc + mq) / 3.0);
+      }
+    }
+    for (int64_t i = 0; i < nn; ++i)
+      if (!(m.vupd[i] > 0.0)) return "axisymmetric node with a zero revolved volume";
+  }
 
   // ---- boundary faces (owned by exactly one cell) and boundary node normals
   struct Face { std::array<int32_t, 3> n; int32_t c; int8_t k; };
@@ -252,7 +278,9 @@ std::string preprocess_mesh(int nd, int64_t nn, const double* xyz, int64_t nc, i
       for (int q = 0; q < nd; ++q) {
         int32_t i = faces[a].n[q];
         isb[i] = 1;
-        for (int d = 0; d < nd; ++d) Sb[(size_t)d * nn + i] += S[faces[a].k][d] / nd;
+        // axisymmetric: node i's half of the edge revolves at radius (3 r_i + r_j)/4
+        const double w = m.axi ? 0.75 * m.x[(size_t)nn + i] + 0.25 * m.x[(size_t)nn + faces[a].n[1 - q]] : 1.0;
+        for (int d = 0; d < nd; ++d) Sb[(size_t)d * nn + i] += S[faces[a].k][d] / nd * w;
       }
     }
     a = b;

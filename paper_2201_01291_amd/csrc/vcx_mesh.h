@@ -28,6 +28,12 @@ struct HostMesh {
   std::vector<uint32_t> shift;    // [nc] periodic image code of vertices 1..nv-1
   std::vector<double> vnode;      // [nn] median-dual volume V_i
   double vol_cells = 0.0, vol_nodes = 0.0;
+  // axisymmetric (x, r) meshes: the update divides by int r dA over each
+  // node's dual region (vupd; equal to vnode otherwise), fluxes carry the
+  // centroid radius of their dual face piece, and bnd_S is weighted by the
+  // centroid radius of each node's share of its boundary edges
+  bool axi = false;
+  std::vector<double> vupd;       // [nn]
 
   // boundary closure
   std::vector<int32_t> bnd_node;  // [nb] internal ids (ascending)
@@ -70,7 +76,7 @@ struct HostMesh {
 // (-1 argument, -2 mesh).
 std::string preprocess_mesh(int nd, int64_t nn, const double* xyz, int64_t nc, int nv,
                             const int64_t* cells, const double* period, TileLimits lim,
-                            HostMesh& out, int* code);
+                            HostMesh& out, int* code, bool axisymmetric = false);
 
 // Build the extended-tile tables of a preprocessed mesh (any dimension).
 void build_halos(HostMesh& m);

@@ -464,6 +464,7 @@ extern "C" vcx_status vcx_server_submit(vcx_server sv, vcx_mesh mesh, const vcx_
   if (nsteps < 0) return set_err(VCX_E_ARG, "nsteps must be >= 0");
   if (phys->model == VCX_MODEL_DRIFT_DIFFUSION && !E)
     return set_err(VCX_E_ARG, "drift-diffusion needs the electric field E");
+  if (vcx::mesh_axisymmetric(mesh)) return set_err(VCX_E_ARG, "axisymmetric meshes are not served (not batched)");
   size_t bytes = 0;
   if (vcx::solver_footprint(mesh, phys, &bytes) != VCX_OK) return set_err(VCX_E_ARG, vcx_last_error());
   auto r = std::make_unique<Request>();

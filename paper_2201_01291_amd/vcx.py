@@ -35,7 +35,7 @@ EXPORTS = (
     "vcx_server_poll", "vcx_server_wait", "vcx_server_stats", "vcx_server_destroy",
     "vcx_conservation_sums", "vcx_profile_enable", "vcx_profile_query", "vcx_last_error",
     "vcx_solver_set_field", "vcx_poisson_create", "vcx_poisson_destroy", "vcx_poisson_solve",
-    "vcx_poisson_field",
+    "vcx_poisson_field", "vcx_mesh_create_axisymmetric",
 )
 
 
@@ -127,6 +127,8 @@ def lib():
         L.vcx_profile_query.argtypes = [vp, C.c_char_p, i64p, dp]
         L.vcx_last_error.restype = C.c_char_p
         L.vcx_solver_set_field.argtypes = [vp, vp, C.c_int]
+        L.vcx_mesh_create_axisymmetric.argtypes = [C.c_int64, dp, C.c_int64, i64p, C.c_double, C.c_int,
+                                                   C.c_int, vp, C.POINTER(vp)]
         L.vcx_poisson_create.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(vp)]
         L.vcx_poisson_destroy.argtypes = [vp]
         L.vcx_poisson_solve.argtypes = [vp, vp, vp, vp, vp, C.c_int, C.c_double, C.c_int,
@@ -197,7 +199,10 @@ def mesh_preprocess(mesh) -> dict:
 
 
 class Mesh:
-    def __init__(self, mesh, stream=None, tile_cells: int = 0, tile_nodes: int = 0):
+    def __init__(self, mesh, stream=None, tile_cells: int = 0, tile_nodes: int = 0,
+                 axisymmetric: bool = False):
+        """axisymmetric: mesh of the (x, r) half-plane (second coordinate the
+        radius; only x may be periodic)."""
         L = lib()
         self.src = mesh
         self.ndim, self.nnodes, self.ncells = mesh.ndim, mesh.nnodes, mesh.ncells
@@ -205,11 +210,18 @@ class Mesh:
         xyz, cells = _f64(mesh.xyz), np.ascontiguousarray(mesh.cells, dtype=np.int64)
         per = None if mesh.period is None else _f64(mesh.period)
         h = C.c_void_p()
-        _check(L.vcx_mesh_create_tiled(mesh.ndim, mesh.nnodes, _dptr(xyz), mesh.ncells, mesh.nv,
-                                       cells.ctypes.data_as(C.POINTER(C.c_int64)),
-                                       _dptr(per) if per is not None else None, int(tile_cells),
-                                       int(tile_nodes), C.c_void_p(self.stream), C.byref(h)),
-               "vcx_mesh_create_tiled")
+        cp = cells.ctypes.data_as(C.POINTER(C.c_int64))
+        if axisymmetric:
+            px = float(per[0]) if per is not None else 0.0
+            _check(L.vcx_mesh_create_axisymmetric(mesh.nnodes, _dptr(xyz), mesh.ncells, cp, px,
+                                                  int(tile_cells), int(tile_nodes),
+                                                  C.c_void_p(self.stream), C.byref(h)),
+                   "vcx_mesh_create_axisymmetric")
+        else:
+            _check(L.vcx_mesh_create_tiled(mesh.ndim, mesh.nnodes, _dptr(xyz), mesh.ncells, mesh.nv, cp,
+                                           _dptr(per) if per is not None else None, int(tile_cells),
+                                           int(tile_nodes), C.c_void_p(self.stream), C.byref(h)),
+                   "vcx_mesh_create_tiled")
         self.h = h
 
     def info(self) -> dict:

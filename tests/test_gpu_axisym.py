@@ -1,0 +1,127 @@
+"""GPU axisymmetric drift-diffusion against the oracle (Sec. "Cylindrical
+frames", eq. vertex_centered_flux_axi).  Bars as the plane parity tests:
+FP64 residual and states within 1e-12 norm-wise, time steps to 1e-13."""
+import numpy as np
+import pytest
+
+import oracle
+from cases import normwise
+from paper_2201_01291_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2201_01291_amd import vcx  # noqa: E402
+
+TOL = 1e-12
+SP = dict(z=[-1.0, 1.0], mu=[0.04, 0.01], D=[0.1, 0.02])
+
+
+def _case(nx=36, nr=18, seed=3):
+    """(x, r) strip [-1 mm, 1 mm] x [0, 1 mm], periodic in x, jittered; two
+    charged species in a Gaussian cloud on the axis; E = uniform axial field
+    plus a radial component growing with r."""
+    m = wl.tri_rect_mesh(nx, nr, 2e-3, 1e-3, jitter=0.2, seed=seed, periodic=(True, False),
+                         origin=(-1e-3, 0.0))
+    x, r = m.xyz
+    n0 = 1e18 * np.exp(-(x ** 2 + r ** 2) / (3e-4) ** 2)
+    U = np.vstack([n0, 0.8 * n0 + 1e16])
+    E = np.vstack([np.full(m.nnodes, 1e6), 2e8 * r])
+    return m, U, E
+
+
+def _phys_o(**kw):
+    base = dict(model=oracle.DRIFT_DIFFUSION, limiter=oracle.MINMOD, rk=1, nspecies=2, cfl=0.5,
+                fourier=0.25, **SP)
+    base.update(kw)
+    return oracle.Phys(**base)
+
+
+def _phys_v(prec=0, **kw):
+    base = dict(model=vcx.MODEL_DRIFT_DIFFUSION, limiter=vcx.LIM_MINMOD, rk_stages=1, nspecies=2,
+                precision=prec, cfl=0.5, fourier=0.25, **SP)
+    base.update(kw)
+    return vcx.physics(**base)
+
+
+def _setup(prec=0, **kw):
+    m, U, E = _case()
+    print(f"[case] axisymmetric dd nn={m.nnodes} prec={prec}", flush=True)
+    om = oracle.OracleMesh(m, axisymmetric=True)
+    gm = vcx.Mesh(m, axisymmetric=True)
+    s = vcx.Solver(gm, _phys_v(prec, **kw), E)
+    s.upload(U)
+    return m, U, E, om, gm, s
+
+
+def test_axisymmetric_residual_timestep_and_steps_match_the_oracle():
+    m, U, E, om, gm, s = _setup()
+    ph = _phys_o()
+    dt = om.timestep(ph, U, E)
+    assert s.timestep() == pytest.approx(dt, rel=1e-13)
+    err = normwise(s.residual(dt), om.residual(ph, U, E, dt), om.flux_scale(ph, U, E, dt))
+    print("axisymmetric residual err", err)
+    assert err.max() <= TOL
+    Uo, to, _, no = om.step(ph, U, E, nsteps=5)
+    tg, _ = s.step(5)
+    assert s.steps_done() == no == 5 and tg == pytest.approx(to, rel=1e-12)
+    Ug = s.download()
+    serr = np.abs(Ug - Uo).max(axis=1) / np.abs(Uo).max(axis=1)
+    print("axisymmetric state err", serr)
+    assert serr.max() <= TOL
+    so, ao = om.sums(Uo)
+    np.testing.assert_allclose(s.sums(), so, rtol=0, atol=1e-13 * ao.max())
+
+
+def test_axisymmetric_mixed_precision_error_stated():
+    m, U, E, om, gm, s = _setup(prec=1)
+    ph = _phys_o()
+    dt = om.timestep(ph, U, E)
+    err = normwise(s.residual(dt), om.residual(ph, U, E, dt), om.flux_scale(ph, U, E, dt))
+    print("axisymmetric MIXED residual err", err)
+    assert err.max() <= 1e-4
+
+
+def test_axisymmetric_diffusion_follows_the_3d_heat_kernel():
+    """The oracle's convergence pin run on the GPU: pure diffusion of a
+    Gaussian centred on the axis to t = 5 ms, state equal to the oracle's."""
+    m = wl.tri_rect_mesh(64, 32, 2.0, 1.0, jitter=0.1, seed=7, periodic=(True, False),
+                         origin=(-1.0, 0.0))
+    x, r = m.xyz
+    U = np.exp(-(x ** 2 + r ** 2) / 0.15 ** 2)[None, :]
+    E = np.zeros((2, m.nnodes))
+    kw = dict(nspecies=1, z=[1.0], mu=[0.0], D=[1.0])
+    ph = oracle.Phys(model=oracle.DRIFT_DIFFUSION, limiter=oracle.MINMOD, rk=1, cfl=0.5, fourier=0.25, **kw)
+    Uo, to, _, no = oracle.OracleMesh(m, axisymmetric=True).step(ph, U, E, nsteps=100000, t_end=0.005)
+    s = vcx.Solver(vcx.Mesh(m, axisymmetric=True),
+                   vcx.physics(model=vcx.MODEL_DRIFT_DIFFUSION, limiter=vcx.LIM_MINMOD, rk_stages=1,
+                               cfl=0.5, fourier=0.25, **kw), E)
+    s.upload(U)
+    tg, _ = s.step(100000, t_end=0.005)
+    assert s.steps_done() == no and tg == pytest.approx(0.005, abs=1e-15)
+    err = np.abs(s.download() - Uo).max() / np.abs(Uo).max()
+    print("heat kernel GPU vs oracle", err, "steps", no)
+    assert err <= TOL
+    s2 = 0.15 ** 2 + 4 * 0.005
+    exact = (0.15 ** 2 / s2) ** 1.5 * np.exp(-(x ** 2 + r ** 2) / s2)
+    assert np.abs(s.download()[0] - exact).max() < 3e-2   # 32 cells per radius (the oracle pin: second order)
+
+
+def test_axisymmetric_restrictions():
+    m, U, E = _case(12, 6)
+    gm = vcx.Mesh(m, axisymmetric=True)
+    with pytest.raises(vcx.VcxError) as e:
+        vcx.Solver(gm, vcx.physics(model=vcx.MODEL_GAS), None)
+    assert e.value.code == vcx.E_ARG
+    s = vcx.Solver(gm, _phys_v(), E)
+    s.upload(U)
+    with pytest.raises(vcx.VcxError) as e:
+        vcx.solve_batch([s], [2], graphs=False)
+    assert e.value.code == vcx.E_ARG
+    bad = wl.tri_rect_mesh(4, 4, 1.0, 1.0, origin=(0.0, -0.5))
+    with pytest.raises(vcx.VcxError) as e:
+        vcx.Mesh(bad, axisymmetric=True)
+    assert e.value.code == vcx.E_ARG
