@@ -280,14 +280,16 @@ class OracleMesh:
 
         (Sec. "Boundary conditions": Dirichlet rows replaced by the imposed
         value, Neumann data on the right-hand side, zero Neumann where
-        nothing is imposed).  Without Dirichlet nodes the matrix is
+        nothing is imposed).  On axisymmetric meshes V_i and |S_i^b| are the
+        revolved ones over 2 pi and the matrix is not symmetric (Sec.
+        "Axisymmetric configuration").  Without Dirichlet nodes the matrix is
         singular: a uniform background charge makes the right-hand side
         compatible (q minus its volume mean) and phi is returned with zero
         volume mean.  Solved by a sparse direct factorisation."""
         import scipy.sparse as sp
         import scipy.sparse.linalg as spla
         L = self.poisson_matrix()
-        Vn = self.geometry()["Vn"]
+        Vn = self.axi_geometry()[0] if self.axi else self.geometry()["Vn"]
         b = np.asarray(q, dtype=np.float64) * Vn
         if En is not None:
             b = b - np.asarray(En, dtype=np.float64) * self.boundary_measure()

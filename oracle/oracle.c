@@ -1092,6 +1092,33 @@ void om_sums(const om_mesh *m, int nvar, const double *U, double *sums, double *
 void om_poisson_coo(const om_mesh *m, int64_t *I, int64_t *K, double *val) {
   const int nd = m->nd, nv = m->nv;
   int64_t q = 0;
+  if (m->axi) {
+    /* axisymmetric (Sec. "Axisymmetric configuration"): the planar cell
+     * gradient -1/(A n_d) sum_k phi_k n_k dotted with int r n dl over node
+     * i's dual boundary inside the triangle, (1/24)[(4 r_c + 2 r_i + r_j +
+     * r_k) n_i - (2 r_c + r_i + r_j) n_j - (2 r_c + r_i + r_k) n_k] with r_c
+     * the centroid radius (the 2 pi cancels against the revolved volumes);
+     * the matrix is not symmetric */
+    for (int64_t c = 0; c < m->nc; c++) {
+      const double *S = m->S + c * 6, *X = m->X + c * 6;
+      const double r[3] = {X[1], X[3], X[5]};
+      const double rc = (r[0] + r[1] + r[2]) / 3.0;
+      for (int a = 0; a < 3; a++) {
+        const int j = (a + 1) % 3, k = (a + 2) % 3;
+        double wv[2];
+        for (int d = 0; d < 2; d++)
+          wv[d] = ((4 * rc + 2 * r[a] + r[j] + r[k]) * S[a * 2 + d] - (2 * rc + r[a] + r[j]) * S[j * 2 + d] -
+                   (2 * rc + r[a] + r[k]) * S[k * 2 + d]) / 24.0;
+        for (int b = 0; b < 3; b++) {
+          I[q] = m->cell[c * 3 + a];
+          K[q] = m->cell[c * 3 + b];
+          val[q] = (S[b * 2] * wv[0] + S[b * 2 + 1] * wv[1]) / (2.0 * m->Vc[c]);
+          q++;
+        }
+      }
+    }
+    return;
+  }
   for (int64_t c = 0; c < m->nc; c++) {
     const double *S = m->S + c * nv * nd;
     const double w = 1.0 / (m->Vc[c] * nd * nd);
@@ -1111,9 +1138,10 @@ void om_poisson_coo(const om_mesh *m, int64_t *I, int64_t *K, double *val) {
  * node, 0 away from the boundary; weights the Neumann data E_n (Sec.
  * "Neumann boundary conditions"). */
 void om_boundary_measure(const om_mesh *m, double *out) {
+  const double *Sb = m->axi ? m->Sbr : m->Sb; /* revolved boundary surface over 2 pi */
   for (int64_t i = 0; i < m->nn; i++) {
     double s = 0.0;
-    for (int d = 0; d < m->nd; d++) s += m->Sb[i * m->nd + d] * m->Sb[i * m->nd + d];
+    for (int d = 0; d < m->nd; d++) s += Sb[i * m->nd + d] * Sb[i * m->nd + d];
     out[i] = m->bnd[i] ? sqrt(s) : 0.0;
   }
 }

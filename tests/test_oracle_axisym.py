@@ -94,3 +94,45 @@ def test_conservation_of_the_revolved_total():
     assert abs(Vp @ Un[0] - s0) <= 1e-13 * s0
     so, _ = om.sums(Un)
     assert so[0] == pytest.approx(Vp @ Un[0], rel=1e-13)
+
+
+def test_axisymmetric_poisson_operator_identities():
+    """Sec. "Axisymmetric configuration": the matrix of -lap phi over the
+    revolved nodal volumes is not symmetric, but rows and columns sum to
+    zero (constants are its null space on both sides); it annihilates
+    a + b x away from the outer boundary, and -lap r = -1/r integrates to
+    -A_i (int over the revolved volume of 1/r, over 2 pi), axis nodes
+    included."""
+    m = wl.tri_rect_mesh(10, 8, 2.0, 1.0, jitter=0.2, seed=3, origin=(-1.0, 0.0))
+    om = oracle.OracleMesh(m, axisymmetric=True)
+    L = om.poisson_matrix()
+    one = np.ones(m.nnodes)
+    scale = abs(L).max()
+    assert abs(L - L.T).max() > 1e-3 * scale
+    assert np.abs(L @ one).max() <= 1e-14 * scale and np.abs(L.T @ one).max() <= 1e-14 * scale
+    x, r = m.xyz
+    outer = om.boundary_measure() > 0          # the axis carries no boundary surface
+    A = om.geometry()["Vn"]
+    assert np.abs((L @ (0.3 + 2.0 * x))[~outer]).max() <= 1e-14 * scale
+    np.testing.assert_allclose((L @ r)[~outer], -A[~outer], rtol=0, atol=1e-14 * scale)
+
+
+def test_axisymmetric_poisson_converges_to_a_3d_solution():
+    """phi = exp(-(x^2 + r^2)/s^2) with q = -lap phi (three-dimensional
+    Laplacian), Dirichlet values on x = +-1 and r = 1, nothing imposed on
+    the axis: second-order convergence, axis nodes included."""
+    s2 = 0.2
+    errs = []
+    for n in (12, 24, 48):
+        m = wl.tri_rect_mesh(2 * n, n, 2.0, 1.0, jitter=0.15, seed=n, origin=(-1.0, 0.0))
+        om = oracle.OracleMesh(m, axisymmetric=True)
+        x, r = m.xyz
+        rho2 = x * x + r * r
+        exact = np.exp(-rho2 / s2)
+        q = -exact * (4 * rho2 / s2 ** 2 - 6 / s2)
+        dirichlet = (np.abs(np.abs(x) - 1) < 1e-12) | (np.abs(r - 1) < 1e-12)
+        phi = om.poisson_solve(q, dirichlet=dirichlet, phi_D=exact)
+        errs.append(np.abs(phi - exact).max())
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    print("axisymmetric Poisson errors", errs, rates)
+    assert min(rates) > 1.7 and errs[-1] < 2e-3
