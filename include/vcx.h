@@ -343,6 +343,10 @@ typedef struct vcx_poisson_s *vcx_poisson;
  * Without Dirichlet nodes (periodic or all-Neumann meshes) the system is
  * singular: a uniform background charge makes it compatible (the solve
  * removes the volume mean of q) and phi is returned with zero volume mean.
+ * On an axisymmetric mesh (vcx_mesh_create_axisymmetric) the operator is
+ * that of Sec. "Axisymmetric configuration": the planar cell gradient
+ * dotted with int r n dl over each node's dual boundary, with revolved
+ * volumes and boundary surfaces (all over 2 pi); it is not symmetric.
  * The operator lives on the mesh's stream; the mesh must outlive it.
  * Errors: VCX_E_ARG (NULL mesh or out, too large for 32-bit indices),
  * VCX_E_OOM, VCX_E_HIP. */
@@ -350,9 +354,11 @@ vcx_status vcx_poisson_create(vcx_mesh mesh, const int32_t *dirichlet, vcx_poiss
 vcx_status vcx_poisson_destroy(vcx_poisson p);
 
 /* Solve sum_k L_ik phi_k = q_i V_i - En_i |S_i^b| on free nodes with
- * phi_i = phiD_i on Dirichlet nodes, by Jacobi-preconditioned conjugate
- * gradients in FP64 on the device (dot products reduced in a fixed order:
- * bitwise reproducible).  Arrays are [nnodes] in caller order, all host or
+ * phi_i = phiD_i on Dirichlet nodes in FP64 on the device: conjugate
+ * gradients with a two-level preconditioner (Jacobi plus an aggregation
+ * coarse space), or on axisymmetric meshes BiCGStab with Jacobi; dot
+ * products are reduced in a fixed order, so results are bitwise
+ * reproducible.  Arrays are [nnodes] in caller order, all host or
  * all device (is_device):
  *   q    rho / eps0 at the nodes (required);
  *   phiD imposed potential, read on Dirichlet nodes only (NULL: zero);

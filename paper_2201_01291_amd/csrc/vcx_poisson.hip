@@ -16,7 +16,10 @@
 // aggregates (runs of consecutive curve-ordered nodes, piecewise-constant
 // prolongation), whose small dense operator is inverted on the host; three
 // kernels per iteration (coarse correction, search direction and product,
-// update).  Every dot product is reduced in a fixed order:
+// update).  The operator of an axisymmetric mesh (Sec. "Axisymmetric
+// configuration") is not symmetric: it is solved by BiCGStab with Jacobi
+// preconditioning, three kernels per iteration, with the same fixed-order
+// reductions.  Every dot product is reduced in a fixed order:
 // each block writes one partial, and every block of the next kernel sums all
 // partials in the same order, so all blocks take the same scalars and the
 // iterates are bitwise reproducible.  Convergence is decided on the device;
@@ -70,6 +73,8 @@ enum {
   P_PQ,                // p.q
   P_GC,                // g_b c_b (coarse part of r.z)
   P_B, P_V, P_BB, P_VX, P_RRI,
+  P_RHO0, P_RHO1,      // BiCGStab: r^.r
+  P_RV, P_TS, P_TT,    // BiCGStab: r^.v, t.s, t.t
   P_NROWS
 };
 
@@ -80,11 +85,13 @@ struct CgCtl {
   int pad;
   double rr;      // squared residual norm of the last iterate
   double ref2;    // squared norm the tolerance is relative to
-  double rz[2];   // r.z of the iterates, by parity
+  double rz[2];   // r.z of the iterates, by parity (BiCGStab: r^.r)
+  double alpha, omega;  // BiCGStab step lengths of the last iteration
 };
 
 struct CgVec {
   double *x, *r, *p0, *p1, *q, *b;
+  double *rh, *v0, *v1, *t;  // BiCGStab: shadow residual, A p^ (by parity), A s^
   double* g;     // [nc] restriction R r (sum of r over each aggregate's free nodes)
   double* c;     // [nc] coarse correction A_c^-1 g
   double* part;  // [P_NROWS][nc]
@@ -300,6 +307,165 @@ __global__ void __launch_bounds__(kThreads) k_cg_b(PoissonDev P, CgVec X, int k)
   if (threadIdx.x == 0) X.g[blockIdx.x] = g;
 }
 
+// ---- BiCGStab (non-symmetric operators of axisymmetric meshes), Jacobi
+// preconditioned on the right: p^ = D^-1 p, s^ = D^-1 s.
+
+// Initial residual r = b - L x on free rows, shadow residual r^ = r, p = v =
+// 0; partial sums of r^.r, r.r and |b - L_fD x_D|^2.
+__global__ void __launch_bounds__(kThreads) k_bi_init2(PoissonDev P, CgVec X) {
+  double bmean = 0.0;
+  if (P.singular) bmean = sum_partials(X.part + P_B * P.nc, P.nc) / sum_partials(X.part + P_V * P.nc, P.nc);
+  int i0, i1;
+  agg_rows(P, i0, i1);
+  double rr = 0.0, bb = 0.0;
+  for (int i = i0 + threadIdx.x; i < i1; i += kThreads) {
+    double r = 0.0;
+    if (P.dinv[i] != 0.0) {
+      double b = X.b[i];
+      if (P.singular) {
+        b -= P.vn[i] * bmean;
+        X.b[i] = b;
+      }
+      double ax = 0.0, ad = 0.0;
+      for (int e = P.rp[i]; e < P.rp[i + 1]; ++e) {
+        const int k = P.col[e];
+        const double t = P.val[e] * X.x[k];
+        ax += t;
+        if (P.dinv[k] == 0.0) ad += t;
+      }
+      r = b - ax;
+      const double bt = b - ad;
+      bb += bt * bt;
+    }
+    X.r[i] = r;
+    X.rh[i] = r;
+    X.p0[i] = X.p1[i] = 0.0;
+    X.v0[i] = X.v1[i] = 0.0;
+    rr += r * r;
+  }
+  put_partial(X.part + P_RHO0 * P.nc, rr);
+  put_partial(X.part + P_RR0 * P.nc, rr);
+  put_partial(X.part + P_RRI * P.nc, rr);
+  put_partial(X.part + P_BB * P.nc, bb);
+}
+
+// Iteration k, part 1: stop test on r_k; beta = (rho_k/rho_(k-1))
+// (alpha/omega); p_k = r + beta (p_(k-1) - omega v_(k-1)); v_k = L p^_k
+// (neighbours' p^ formed in the same arithmetic as their own rows);
+// partial sums of r^.v_k.
+__global__ void __launch_bounds__(kThreads) k_bi_a(PoissonDev P, CgVec X, int k, double tol2) {
+  if (block_done(X.ctl)) return;
+  const int cur = k & 1;
+  const double rr = sum_partials(X.part + (P_RR0 + cur) * P.nc, P.nc);
+  const double bb = sum_partials(X.part + P_BB * P.nc, P.nc);
+  const double ref2 = bb > 0.0 ? bb : sum_partials(X.part + P_RRI * P.nc, P.nc);
+  const double rho = sum_partials(X.part + (P_RHO0 + cur) * P.nc, P.nc);
+  // converged, or a breakdown (r^.r = 0, or omega = 0 with r != 0)
+  const bool conv = !(rr > tol2 * ref2) || rho == 0.0 || (k > 0 && X.ctl->omega == 0.0);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    X.ctl->last = k;
+    X.ctl->rr = rr;
+    X.ctl->ref2 = ref2;
+    X.ctl->rz[cur] = rho;
+    if (conv) {
+      X.ctl->iters = k;
+      __hip_atomic_store(&X.ctl->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  if (conv) return;
+  double beta = 0.0, om = 0.0;
+  if (k > 0) {
+    om = X.ctl->omega;
+    beta = (rho / X.ctl->rz[cur ^ 1]) * (X.ctl->alpha / om);
+  }
+  const double* po = cur ? X.p1 : X.p0;  // p_(k-1)
+  const double* vo = cur ? X.v1 : X.v0;  // v_(k-1)
+  double* pn = cur ? X.p0 : X.p1;
+  double* vn = cur ? X.v0 : X.v1;
+  int i0, i1;
+  agg_rows(P, i0, i1);
+  double rv = 0.0;
+  for (int i = i0 + threadIdx.x; i < i1; i += kThreads) {
+    double p = 0.0, v = 0.0;
+    if (P.dinv[i] != 0.0) {
+      p = X.r[i] + beta * (po[i] - om * vo[i]);
+      for (int e = P.rp[i]; e < P.rp[i + 1]; ++e) {
+        const int j = P.col[e];
+        const double pj = X.r[j] + beta * (po[j] - om * vo[j]);
+        v += P.val[e] * (P.dinv[j] * pj);
+      }
+    }
+    pn[i] = p;
+    vn[i] = v;
+    rv += X.rh[i] * v;
+  }
+  put_partial(X.part + P_RV * P.nc, rv);
+}
+
+// Iteration k, part 2: alpha = rho_k / r^.v_k; s = r - alpha v_k;
+// t = L s^ (neighbours' s^ formed the same way); partial sums of t.s, t.t.
+__global__ void __launch_bounds__(kThreads) k_bi_b(PoissonDev P, CgVec X, int k) {
+  if (block_done(X.ctl)) return;
+  const int cur = k & 1;
+  const double rv = sum_partials(X.part + P_RV * P.nc, P.nc);
+  if (rv == 0.0) {  // breakdown: stop at the current iterate
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      X.ctl->iters = k;
+      __hip_atomic_store(&X.ctl->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return;
+  }
+  const double alpha = X.ctl->rz[cur] / rv;
+  if (blockIdx.x == 0 && threadIdx.x == 0) X.ctl->alpha = alpha;
+  const double* vn = cur ? X.v0 : X.v1;
+  int i0, i1;
+  agg_rows(P, i0, i1);
+  double ts = 0.0, tt = 0.0;
+  for (int i = i0 + threadIdx.x; i < i1; i += kThreads) {
+    double t = 0.0, sv = 0.0;
+    if (P.dinv[i] != 0.0) {
+      sv = X.r[i] - alpha * vn[i];
+      for (int e = P.rp[i]; e < P.rp[i + 1]; ++e) {
+        const int j = P.col[e];
+        t += P.val[e] * (P.dinv[j] * (X.r[j] - alpha * vn[j]));
+      }
+    }
+    X.t[i] = t;
+    ts += t * sv;
+    tt += t * t;
+  }
+  put_partial(X.part + P_TS * P.nc, ts);
+  put_partial(X.part + P_TT * P.nc, tt);
+}
+
+// Iteration k, part 3: omega = t.s / t.t; x += alpha p^ + omega s^;
+// r = s - omega t; partial sums of r^.r and r.r of iterate k+1.
+__global__ void __launch_bounds__(kThreads) k_bi_c(PoissonDev P, CgVec X, int k) {
+  if (block_done(X.ctl)) return;
+  const int cur = k & 1, nxt = cur ^ 1;
+  const double tt = sum_partials(X.part + P_TT * P.nc, P.nc);
+  const double om = tt > 0.0 ? sum_partials(X.part + P_TS * P.nc, P.nc) / tt : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) X.ctl->omega = om;
+  const double alpha = X.ctl->alpha;
+  const double* pn = cur ? X.p0 : X.p1;
+  const double* vn = cur ? X.v0 : X.v1;
+  int i0, i1;
+  agg_rows(P, i0, i1);
+  double rho = 0.0, rr = 0.0;
+  for (int i = i0 + threadIdx.x; i < i1; i += kThreads) {
+    const double di = P.dinv[i];
+    if (di == 0.0) continue;
+    const double sv = X.r[i] - alpha * vn[i];
+    X.x[i] += alpha * (di * pn[i]) + om * (di * sv);
+    const double r = sv - om * X.t[i];
+    X.r[i] = r;
+    rho += X.rh[i] * r;
+    rr += r * r;
+  }
+  put_partial(X.part + (P_RHO0 + nxt) * P.nc, rho);
+  put_partial(X.part + (P_RR0 + nxt) * P.nc, rr);
+}
+
 // Singular systems: phi with zero volume mean.
 __global__ void __launch_bounds__(kThreads) k_cg_mean1(PoissonDev P, CgVec X) {
   int i0, i1;
@@ -437,6 +603,7 @@ struct vcx_poisson_s {
   double* fbuf = nullptr;   // [nd][n] field rows for host outputs
   CgCtl* ctl_host = nullptr;
   int n = 0, nd = 0;
+  bool bicg = false;  // non-symmetric operator (axisymmetric mesh): BiCGStab
 };
 
 static vcx_status dev_alloc(vcx_poisson p, size_t bytes, void** out) {
@@ -510,13 +677,31 @@ extern "C" vcx_status vcx_poisson_create(vcx_mesh mesh, const int32_t* dirichlet
         }
       }
       simplex_grads(nd, X, grad, vol);
+      // axisymmetric: int r n dl over node a's dual boundary in the cell is
+      // sum over its other vertices j of the segment normal (S_a - S_j)/6
+      // (S_k = -2 A grad lambda_k) times the segment's centroid radius
+      // (r_a + r_j + 2 r_c)/4; the row then takes -grad lambda_k . that
+      double wa[3] = {0, 0, 0};
+      if (h.axi) {
+        const double rc = (X[0][1] + X[1][1] + X[2][1]) / 3.0;
+        for (int j = 0; j < 3; ++j) {
+          if (j == a) continue;
+          const double rr = X[a][1] + X[j][1] + 2.0 * rc;
+          for (int d = 0; d < 2; ++d) wa[d] += -(vol / 12.0) * (grad[a][d] - grad[j][d]) * rr;
+        }
+      }
       for (int k = 0; k < nv; ++k) {
         Entry e{};
         e.col = h.cell[(size_t)k * nc + c];
         e.cell = (int)c;
         double dot = 0.0;
-        for (int d = 0; d < nd; ++d) dot += grad[a][d] * grad[k][d];
-        e.v = vol * dot;
+        if (h.axi) {
+          for (int d = 0; d < nd; ++d) dot -= grad[k][d] * wa[d];
+          e.v = dot;
+        } else {
+          for (int d = 0; d < nd; ++d) dot += grad[a][d] * grad[k][d];
+          e.v = vol * dot;
+        }
         // E_i = -(1/V_i) sum_tau (V_tau/n_v) grad phi_tau, grad phi_tau = sum_k phi_k grad lambda_k
         for (int d = 0; d < nd; ++d) e.g[d] = -(vol / nv) * grad[k][d];
         ent.push_back(e);
@@ -571,7 +756,7 @@ extern "C" vcx_status vcx_poisson_create(vcx_mesh mesh, const int32_t* dirichlet
   chk(upload(p, val, &P.val));
   chk(upload(p, gall, &P.gval));
   chk(upload(p, dinv, &P.dinv));
-  chk(upload(p, h.vnode, &P.vn));
+  chk(upload(p, h.vupd, &P.vn));  // revolved volumes on axisymmetric meshes
   chk(upload(p, sbm, &P.sbm));
   // aggregates: consecutive nodes of the space-filling curve, a multiple of
   // the block size each, at most kMaxCoarse of them; coarse operator
@@ -580,8 +765,11 @@ extern "C" vcx_status vcx_poisson_create(vcx_mesh mesh, const int32_t* dirichlet
   P.agg = (int)(((per + kThreads - 1) / kThreads) * kThreads);
   P.nc = (int)((n + P.agg - 1) / P.agg);
   const int ncg = P.nc;
-  std::vector<double> Ac((size_t)ncg * ncg, 0.0);
-  for (int64_t i = 0; i < n; ++i) {
+  p->bicg = h.axi;
+  // the coarse space serves the symmetric operator (conjugate gradients);
+  // axisymmetric operators go to BiCGStab with Jacobi alone
+  std::vector<double> Ac(h.axi ? 1 : (size_t)ncg * ncg, 0.0);
+  for (int64_t i = 0; i < n && !h.axi; ++i) {
     if (dir[(size_t)i]) continue;
     const int a = (int)(i / P.agg);
     for (int32_t e = rp[(size_t)i]; e < rp[(size_t)i + 1]; ++e) {
@@ -589,20 +777,22 @@ extern "C" vcx_status vcx_poisson_create(vcx_mesh mesh, const int32_t* dirichlet
       if (!dir[(size_t)j]) Ac[(size_t)a * ncg + j / P.agg] += val[(size_t)e];
     }
   }
-  double tr = 0.0;
-  for (int a = 0; a < ncg; ++a) tr += Ac[(size_t)a * ncg + a];
-  for (int a = 0; a < ncg; ++a)
-    if (Ac[(size_t)a * ncg + a] == 0.0) Ac[(size_t)a * ncg + a] = tr > 0.0 ? tr / ncg : 1.0;  // no free node
-  if (!any_dir) {
-    // constants are the null space: (A_c + mu 1 1^T)^-1 acts as the
-    // pseudo-inverse on restrictions of residuals, which sum to zero
-    const double mu = tr / ((double)ncg * ncg);
-    for (double& v : Ac) v += mu;
+  if (!h.axi) {
+    double tr = 0.0;
+    for (int a = 0; a < ncg; ++a) tr += Ac[(size_t)a * ncg + a];
+    for (int a = 0; a < ncg; ++a)
+      if (Ac[(size_t)a * ncg + a] == 0.0) Ac[(size_t)a * ncg + a] = tr > 0.0 ? tr / ncg : 1.0;  // no free node
+    if (!any_dir) {
+      // constants are the null space: (A_c + mu 1 1^T)^-1 acts as the
+      // pseudo-inverse on restrictions of residuals, which sum to zero
+      const double mu = tr / ((double)ncg * ncg);
+      for (double& v : Ac) v += mu;
+    }
+    if (!spd_inverse(Ac, ncg)) st = err(VCX_E_MESH, "coarse Poisson operator is not positive definite");
   }
-  if (!spd_inverse(Ac, ncg)) st = err(VCX_E_MESH, "coarse Poisson operator is not positive definite");
   chk(upload(p, Ac, &P.ainv));
   CgVec& X = p->X;
-  double** vecs[6] = {&X.x, &X.r, &X.p0, &X.p1, &X.q, &X.b};
+  double** vecs[10] = {&X.x, &X.r, &X.p0, &X.p1, &X.q, &X.b, &X.rh, &X.v0, &X.v1, &X.t};
   for (double** v : vecs) {
     void* d = nullptr;
     chk(dev_alloc(p, sizeof(double) * (size_t)n, &d));
@@ -667,31 +857,51 @@ extern "C" vcx_status vcx_poisson_solve(vcx_poisson p, const double* q, const do
   const dim3 grid(p->P.nc), block(kThreads);
   PS_HIP(hipMemsetAsync(p->X.ctl, 0, sizeof(CgCtl), p->stream));
   hipLaunchKernelGGL(k_cg_init1, grid, block, 0, p->stream, p->P, p->X, dq, dD, dE, d0);
-  hipLaunchKernelGGL(k_cg_init2, grid, block, 0, p->stream, p->P, p->X);
+  if (p->bicg)
+    hipLaunchKernelGGL(k_bi_init2, grid, block, 0, p->stream, p->P, p->X);
+  else
+    hipLaunchKernelGGL(k_cg_init2, grid, block, 0, p->stream, p->P, p->X);
   PS_HIP(hipGetLastError());
   const double tol2 = tol * tol;
+  // one iteration: conjugate gradients (coarse correction, direction and
+  // product, update) or BiCGStab (three parts); the first kernel of each
+  // holds the stop test
+  auto head = [&](int it) {
+    if (p->bicg) {
+      hipLaunchKernelGGL(k_bi_a, grid, block, 0, p->stream, p->P, p->X, it, tol2);
+    } else {
+      hipLaunchKernelGGL(k_cg_c, grid, block, 0, p->stream, p->P, p->X);
+      hipLaunchKernelGGL(k_cg_a, grid, block, 0, p->stream, p->P, p->X, it, tol2);
+    }
+  };
+  auto tail = [&](int it) {
+    if (p->bicg) {
+      hipLaunchKernelGGL(k_bi_b, grid, block, 0, p->stream, p->P, p->X, it);
+      hipLaunchKernelGGL(k_bi_c, grid, block, 0, p->stream, p->P, p->X, it);
+    } else {
+      hipLaunchKernelGGL(k_cg_b, grid, block, 0, p->stream, p->P, p->X, it);
+    }
+  };
   int k = 0, chunk = 8;
   bool done = false;
   while (!done) {
     // iterations k .. k+c-1, then the stop test of iterate k+c (which also
-    // does the first half of iteration k+c when it does not stop)
+    // does the first part of iteration k+c when it does not stop)
     const int c = std::min(chunk, max_iter - k);
     for (int j = 0; j < c; ++j) {
-      hipLaunchKernelGGL(k_cg_c, grid, block, 0, p->stream, p->P, p->X);
-      hipLaunchKernelGGL(k_cg_a, grid, block, 0, p->stream, p->P, p->X, k + j, tol2);
-      hipLaunchKernelGGL(k_cg_b, grid, block, 0, p->stream, p->P, p->X, k + j);
+      head(k + j);
+      tail(k + j);
     }
     k += c;
-    hipLaunchKernelGGL(k_cg_c, grid, block, 0, p->stream, p->P, p->X);
-    hipLaunchKernelGGL(k_cg_a, grid, block, 0, p->stream, p->P, p->X, k, tol2);
+    head(k);
     PS_HIP(hipGetLastError());
     PS_HIP(hipMemcpyAsync(p->ctl_host, p->X.ctl, sizeof(CgCtl), hipMemcpyDeviceToHost, p->stream));
     PS_HIP(hipStreamSynchronize(p->stream));
     done = p->ctl_host->done || k >= max_iter;
     chunk = std::min(chunk * 2, 256);
     if (!done) {
-      // the test launch above did iteration k's first half: finish it
-      hipLaunchKernelGGL(k_cg_b, grid, block, 0, p->stream, p->P, p->X, k);
+      // the test launch above did iteration k's first part: finish it
+      tail(k);
       k += 1;
     }
   }

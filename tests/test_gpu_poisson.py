@@ -181,3 +181,68 @@ def test_step_coupled_to_the_poisson_field_matches_the_oracle():
     err = (np.abs(U - U_o).max(axis=1) / np.abs(U_o).max(axis=1))
     print("coupled state err", err)
     assert err.max() <= 1e-8
+
+
+def _axi_strip(nx=40, nr=20, seed=2):
+    m = wl.tri_rect_mesh(nx, nr, 2.0, 1.0, jitter=0.15, seed=seed, origin=(-1.0, 0.0))
+    x, r = m.xyz
+    outer = (np.abs(np.abs(x) - 1) < 1e-12) | (np.abs(r - 1) < 1e-12)
+    return m, outer
+
+
+def test_axisymmetric_solve_matches_the_direct_solve():
+    """Sec. "Axisymmetric configuration": the non-symmetric operator, solved
+    by BiCGStab, against the oracle's direct solve; Dirichlet values on the
+    outer boundary, nothing imposed on the axis."""
+    m, outer = _axi_strip()
+    print(f"[case] poisson axisymmetric nn={m.nnodes}", flush=True)
+    om = oracle.OracleMesh(m, axisymmetric=True)
+    x, r = m.xyz
+    q = _charge(m, seed=4)
+    phiD = 0.2 * x + 0.1
+    ref = om.poisson_solve(q, dirichlet=outer, phi_D=phiD)
+    ps = vcx.Poisson(vcx.Mesh(m, axisymmetric=True), dirichlet=outer)
+    phi, it, rel = ps.solve(q, phiD=phiD, tol=TOL)
+    print("BiCGStab iterations", it, "relres", rel)
+    assert rel <= TOL
+    assert np.abs(phi - ref).max() <= PHI_BAR * np.abs(ref).max()
+    a, ia, _ = ps.solve(q, phiD=phiD, tol=TOL)
+    assert ia == it and np.array_equal(a, phi)
+    E = ps.field(phi)
+    Eo = om.electric_field(phi)
+    assert np.abs(E - Eo).max() <= FIELD_BAR * np.abs(Eo).max()
+
+
+def test_axisymmetric_step_coupled_to_the_poisson_field():
+    """The streamer setting: axisymmetric drift-diffusion of electrons and
+    ions with E = E_background - grad phi, phi from the space charge
+    (grounded outer boundary); Poisson solve, field, one step, both sides."""
+    m = wl.tri_rect_mesh(40, 20, 2e-3, 1e-3, jitter=0.15, seed=6, origin=(-1e-3, 0.0))
+    x, r = m.xyz
+    outer = (np.abs(np.abs(x) - 1e-3) < 1e-15) | (np.abs(r - 1e-3) < 1e-15)
+    ne = 1e18 * np.exp(-(x ** 2 + r ** 2) / (3e-4) ** 2)
+    n = np.vstack([ne, 1.2 * ne])
+    q = 1.602176634e-19 * (n[1] - n[0]) / 8.8541878128e-12
+    Ebg = np.vstack([np.full(m.nnodes, -1e6), np.zeros(m.nnodes)])
+    sp = dict(nspecies=2, z=[-1.0, 1.0], mu=[0.04, 0.0], D=[0.1, 0.0])
+    om = oracle.OracleMesh(m, axisymmetric=True)
+    phi_o = om.poisson_solve(q, dirichlet=outer, phi_D=np.zeros(m.nnodes))
+    E_o = Ebg + om.electric_field(phi_o)
+    ph = oracle.Phys(model=oracle.DRIFT_DIFFUSION, limiter=oracle.MINMOD, rk=1, cfl=0.5, fourier=0.25, **sp)
+    U_o, t_o, _, _ = om.step(ph, n, E_o, nsteps=1)
+
+    gm = vcx.Mesh(m, axisymmetric=True)
+    ps = vcx.Poisson(gm, dirichlet=outer)
+    s = vcx.Solver(gm, vcx.physics(model=vcx.MODEL_DRIFT_DIFFUSION, limiter=vcx.LIM_MINMOD,
+                                   rk_stages=1, cfl=0.5, fourier=0.25, **sp), Ebg)
+    s.upload(n)
+    phi, it, _ = ps.solve(q, phiD=np.zeros(m.nnodes), tol=TOL)
+    E = Ebg + ps.field(phi)
+    s.set_field(E)
+    t, _ = s.step(1)
+    print("axisymmetric coupled: iterations", it, "E err", np.abs(E - E_o).max() / np.abs(E_o).max())
+    assert np.abs(E - E_o).max() <= PHI_BAR * np.abs(E_o).max()
+    assert t == pytest.approx(t_o, rel=1e-9)
+    err = np.abs(s.download() - U_o).max(axis=1) / np.abs(U_o).max(axis=1)
+    print("axisymmetric coupled state err", err)
+    assert err.max() <= 1e-8
