@@ -24,8 +24,9 @@
  *                 eq. (virtual_node_reconstruction) and the co-reconstruction
  *                 of pressure
  *   closure       Sec. "Boundary conditions in AVIP", first option (node flux)
- *   axisymmetry   Sec. "Cylindrical frames" (Pappus-Guldinus theorems) and
- *                 eq. (vertex_centered_flux_axi), drift-diffusion only
+ *   axisymmetry   Sec. "Cylindrical frames" (Pappus-Guldinus theorems),
+ *                 eq. (vertex_centered_flux_axi), Sec. "Geometric source
+ *                 terms" (inviscid part); drift-diffusion and gas
  *   time step     Sec. "Time step computation", eqs. (dt_conv), (dt_diff) and
  *                 the dielectric time step
  *   RK            Sec. "Time integration of the HLLC MUSCL-Hancock solver",
@@ -78,6 +79,7 @@ struct om_mesh {
   double *Rf;    /* [nc][ne] centroid radius of each cell-edge piece of the dual surface */
   double *Vp;    /* [nn] int_{A_i} r dA */
   double *Sbr;   /* [nn][nd] boundary node normals weighted by the centroid radius */
+  double *Rn;    /* [nn] node radius */
 };
 
 /* local cell-edges, oriented from the lower to the higher local vertex */
@@ -288,7 +290,7 @@ static void sort_small(int64_t *v, int n) {
 void om_mesh_destroy(om_mesh *m) {
   if (!m) return;
   free(m->cell); free(m->X); free(m->S); free(m->Vc); free(m->Vn); free(m->Sb); free(m->bnd);
-  free(m->Rf); free(m->Vp); free(m->Sbr);
+  free(m->Rf); free(m->Vp); free(m->Sbr); free(m->Rn);
   free(m);
 }
 
@@ -348,7 +350,9 @@ om_mesh *om_mesh_create_axi(int nd, int64_t nn, const double *xyz, int64_t nc, i
     m->Rf = malloc(sizeof(double) * nc * 3);
     m->Vp = calloc(nn, sizeof(double));
     m->Sbr = calloc(nn * nd, sizeof(double));
-    if (!m->Rf || !m->Vp || !m->Sbr) { om_mesh_destroy(m); *status = -3; return NULL; }
+    m->Rn = malloc(sizeof(double) * nn);
+    if (!m->Rf || !m->Vp || !m->Sbr || !m->Rn) { om_mesh_destroy(m); *status = -3; return NULL; }
+    for (int64_t i = 0; i < nn; i++) m->Rn[i] = xyz[nn + i];
     for (int64_t c = 0; c < nc; c++) {
       const double *X = m->X + c * 3 * 2;
       const double r[3] = {X[1], X[3], X[5]};
@@ -745,6 +749,8 @@ static int residual_gas(const om_mesh *m, const om_phys *ph, const double *U, do
       } else {
         om_roe(nd, nsp, ph->gamma, ph->entropy_fix, WL, WR, Sij, F);
       }
+      if (m->axi)
+        for (int v = 0; v < nvar; v++) F[v] *= m->Rf[c * 3 + e]; /* revolved face, over 2 pi */
       for (int v = 0; v < nvar; v++) {
         r[(int64_t)v * nn + i] += absmode ? fabs(F[v]) : F[v];
         r[(int64_t)v * nn + j] -= absmode ? -fabs(F[v]) : F[v];
@@ -758,8 +764,16 @@ static int residual_gas(const om_mesh *m, const om_phys *ph, const double *U, do
     for (int64_t i = 0; i < nn; i++) {
       if (!m->bnd[i]) continue;
       for (int v = 0; v < nr; v++) Wi[v] = W[(int64_t)v * nn + i];
-      om_euler_flux(nd, nsp, Wi, m->Sb + i * nd, F);
+      om_euler_flux(nd, nsp, Wi, m->axi ? m->Sbr + i * nd : m->Sb + i * nd, F);
       for (int v = 0; v < nvar; v++) r[(int64_t)v * nn + i] += absmode ? fabs(F[v]) : F[v];
+    }
+  }
+  if (m->axi) {
+    /* geometric source of the radial momentum (Sec. "Geometric source
+     * terms"): + p over the plane dual area, i.e. - p_i A_i in the residual */
+    for (int64_t i = 0; i < nn; i++) {
+      const double src = W[(int64_t)nvar * nn + i] * m->Vn[i];
+      r[(int64_t)2 * nn + i] += absmode ? fabs(src) : -src;
     }
   }
   free(W);
@@ -844,7 +858,7 @@ static int residual_any(const om_mesh *m, const om_phys *ph, const double *U, co
   if (!m || !ph || !U || !r) return -1;
   if (ph->nspecies < 0 || ph->nspecies > OM_MAXSP) return -1;
   if (ph->model == 0 || ph->model == 2) {
-    if (m->axi) return -1; /* axisymmetric gas needs the geometric source terms: not built */
+    if (m->axi && ph->model == 2) return -1; /* viscous geometric source terms: not built */
     return residual_gas(m, ph, U, r, absmode);
   }
   if (ph->model == 1) {
@@ -1042,6 +1056,11 @@ int om_step(const om_mesh *m, const om_phys *ph, double *U, const double *E, int
       for (int v = 0; v < nvar; v++)
         for (int64_t i = 0; i < nn; i++)
           Uk[(int64_t)v * nn + i] = U0[(int64_t)v * nn + i] - a * dt * r[(int64_t)v * nn + i] / vol[i];
+      /* axisymmetric gas: the radial velocity is set to zero on the axis
+       * after the geometric source terms */
+      if (m->axi && ph->model == 0)
+        for (int64_t i = 0; i < nn; i++)
+          if (m->Rn[i] == 0.0) Uk[(int64_t)2 * nn + i] = 0.0;
     }
     if (st) break;
     if (!state_ok(m, ph, Uk)) { st = -5; break; }

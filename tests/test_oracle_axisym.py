@@ -136,3 +136,45 @@ def test_axisymmetric_poisson_converges_to_a_3d_solution():
     rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
     print("axisymmetric Poisson errors", errs, rates)
     assert min(rates) > 1.7 and errs[-1] < 2e-3
+
+
+def _gas(flux=oracle.HLLC, **kw):
+    return oracle.Phys(model=oracle.GAS, flux=flux, limiter=oracle.VANLEER, rk=2, cfl=0.5, **kw)
+
+
+@pytest.mark.parametrize("flux", [oracle.HLLC, oracle.ROE])
+def test_axisymmetric_gas_preserves_a_uniform_axial_stream(flux):
+    """Sec. "Geometric source terms": with the pressure source p A_i in the
+    radial momentum, a uniform stream along the axis is an exact discrete
+    steady state on every node, boundary and axis included (the revolved
+    dual surface gives int r n dl = (0, A_i), which the source balances)."""
+    m = wl.tri_rect_mesh(10, 6, 2.0, 1.0, jitter=0.25, seed=8, origin=(-1.0, 0.0))
+    om = oracle.OracleMesh(m, axisymmetric=True)
+    U = wl.conserved_from_primitive(np.ones(m.nnodes), np.vstack([np.full(m.nnodes, 0.7), np.zeros(m.nnodes)]),
+                                    np.full(m.nnodes, 1.3), 1.4)
+    r = om.residual(_gas(flux), U)
+    scale = np.abs(om.flux_scale(_gas(flux), U)).max(axis=1)
+    assert np.all(np.abs(r).max(axis=1) <= 1e-14 * scale)
+
+
+def test_axisymmetric_gas_conserves_mass_axial_momentum_and_energy():
+    """Periodic in x, no boundary closure: the revolved totals of mass,
+    axial momentum and energy are conserved (the geometric source acts on
+    the radial momentum only); the radial velocity stays zero on the axis."""
+    m = wl.tri_rect_mesh(24, 10, 2.0, 1.0, jitter=0.2, seed=9, periodic=(True, False), origin=(-1.0, 0.0))
+    om = oracle.OracleMesh(m, axisymmetric=True)
+    x, r = m.xyz
+    rho = 1.0 + 0.3 * np.exp(-(x * x + r * r) / 0.1)
+    p = 1.0 + 0.5 * np.exp(-(x * x + r * r) / 0.1)
+    U = wl.conserved_from_primitive(rho, np.vstack([0.3 + 0 * x, 0 * x]), p, 1.4)
+    ph = _gas()
+    ph.closure = False
+    Vp, _ = om.axi_geometry()
+    s0 = Vp @ U.T
+    Un, _, _, n = om.step(ph, U, nsteps=10)
+    assert n == 10
+    s1 = Vp @ Un.T
+    for v in (0, 1, 3):
+        assert abs(s1[v] - s0[v]) <= 1e-13 * abs(Vp @ np.abs(U[v]))
+    assert np.all(Un[2][r == 0.0] == 0.0)
+    assert abs(s1[2]) > 1e-6 * Vp @ np.abs(U[1])    # the radial momentum has a source
