@@ -296,6 +296,14 @@ struct Impl {
     hipStream_t st = s->mesh->stream;
     if constexpr (MODEL == 0) {
       GasParams gp{s->ph.gamma, s->ph.beta, s->ph.entropy_fix, s->ph.limiter};
+      if constexpr (ND == 2) {
+        if (m.axi)
+          return launch(s, "flux", [&](hipEvent_t ea, hipEvent_t eb) {
+            hipExtLaunchKernelGGL((k_flux_gas<ND, NSP, FLUX, CT, true>), dim3(xcd_grid(m.ntiles)),
+                               dim3(s->tile_block), s->lds_flux, st, ea, eb, 0, m, Win, (const double*)s->G,
+                               s->PR, gp, f);
+          });
+      }
       return launch(s, "flux", [&](hipEvent_t ea, hipEvent_t eb) {
         hipExtLaunchKernelGGL((k_flux_gas<ND, NSP, FLUX, CT>), dim3(xcd_grid(m.ntiles)),
                            dim3(s->tile_block), s->lds_flux, st, ea, eb, 0, m, Win, (const double*)s->G,
@@ -361,10 +369,13 @@ struct Impl {
     }
     VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_grad_tile<ND, NGF>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)grad_bytes));
-    if constexpr (MODEL == 0)
+    if constexpr (MODEL == 0) {
       VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_gas<ND, NSP, FLUX, CT>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)flux_bytes));
-    else if constexpr (MODEL == 2)
+      if constexpr (ND == 2)
+        VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_gas<ND, NSP, FLUX, CT, true>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)flux_bytes));
+    } else if constexpr (MODEL == 2)
       VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_ns<ND, NSP, CT>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)flux_bytes));
     else {
@@ -871,8 +882,9 @@ extern "C" vcx_status vcx_solver_create(vcx_mesh mesh, const vcx_physics* phys, 
     if (!(ph.mu_ref >= 0.0) || !(ph.T_ref > 0.0) || !(ph.Pr > 0.0))
       return fail(VCX_E_ARG, "Navier-Stokes needs mu_ref >= 0, T_ref > 0, Pr > 0");
   }
-  if (mesh->h.axi && ph.model != VCX_MODEL_DRIFT_DIFFUSION)
-    return fail(VCX_E_ARG, "axisymmetric meshes support the drift-diffusion model only");
+  if (mesh->h.axi && ph.model == VCX_MODEL_NAVIER_STOKES)
+    return fail(VCX_E_ARG, "axisymmetric meshes support the drift-diffusion and gas models (the viscous "
+                           "geometric source terms are not built)");
   if (ph.rk_stages < 1 || ph.rk_stages > 4) return fail(VCX_E_ARG, "rk_stages must be 1..4");
   if (ph.limiter < 0 || ph.limiter > 4) return fail(VCX_E_ARG, "unknown limiter");
   if (ph.precision != VCX_PREC_FP64 && ph.precision != VCX_PREC_MIXED)

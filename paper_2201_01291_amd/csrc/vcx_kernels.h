@@ -811,6 +811,16 @@ __device__ inline double finish_node(const DevMesh& m, const Finish& f, int i, b
       }
     }
   }
+  bool on_axis = false;
+  if constexpr (MODEL == 0 && ND == 2) {
+    if (m.axi) {
+      // axisymmetric gas: geometric source + p of the radial momentum over
+      // the plane dual area (in the residual: - p_i A_i); the radial
+      // velocity is set to zero on the axis after it
+      r[2] -= f.Win[(size_t)NVAR * m.nn + i] * m.vnode[i];
+      on_axis = m.x[(size_t)m.nn + i] == 0.0;
+    }
+  }
   if (f.residual_only) {
 #pragma unroll
     for (int v = 0; v < NVAR; ++v) f.rout[(size_t)v * m.nn + i] = r[v];
@@ -818,10 +828,10 @@ __device__ inline double finish_node(const DevMesh& m, const Finish& f, int i, b
   }
   double u[NVAR];
 #pragma unroll
-  for (int v = 0; v < NVAR; ++v) {
-    u[v] = ni.Un[v] - ni.fac * r[v];
-    f.Wout[(size_t)v * m.nn + i] = u[v];
-  }
+  for (int v = 0; v < NVAR; ++v) u[v] = ni.Un[v] - ni.fac * r[v];
+  if (on_axis) u[2] = 0.0;
+#pragma unroll
+  for (int v = 0; v < NVAR; ++v) f.Wout[(size_t)v * m.nn + i] = u[v];
   bool ok = true;
   double p = 0.0;
   if constexpr (MODEL == 0) {
@@ -884,7 +894,7 @@ struct CellLd {
 
 // Gas fluxes of the tile's cells: MUSCL with virtual upwind nodes, slope
 // limiter, HLLC or Roe; accumulated per cell vertex into sR.
-template <int ND, int NSP, int FLUX, typename CT, int NV>
+template <int ND, int NSP, int FLUX, typename CT, int NV, bool AXI = false>
 __device__ inline void gas_cell_fluxes(const DevMesh& m, const TilePre<NV>& tp, const double* sX,
                                        const CT* sW, const CT* sG, double* sR, CellLd L,
                                        const GasParams& gp) {
@@ -933,10 +943,20 @@ __device__ inline void gas_cell_fluxes(const DevMesh& m, const TilePre<NV>& tp, 
         hllc_flux<ND, NSP, CT>(WL, WR, S, gamma, gamma, F);
       else
         roe_flux<ND, NSP, CT>(WL, WR, S, gamma, fix, F);
+      // axisymmetric (x, r): centroid radius of the edge's dual face piece
+      double rw = 1.0;
+      if constexpr (AXI) {
+        static_assert(ND == 2, "axisymmetric meshes are (x, r) planes");
+        double rr[NV];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) rr[k] = sX[L.ldx + l[k]];
+        const double rc = (rr[0] + rr[1] + rr[2]) / 3.0;
+        rw = 0.5 * (0.5 * (rr[a] + rr[b]) + rc);
+      }
 #pragma unroll
       for (int v = 0; v < NVAR; ++v) {
-        acc[a][v] += double(F[v]);
-        acc[b][v] -= double(F[v]);
+        acc[a][v] += double(F[v]) * rw;
+        acc[b][v] -= double(F[v]) * rw;
       }
     }
 #pragma unroll
@@ -1059,7 +1079,7 @@ __device__ inline double tile_node_pass(const DevMesh& m, const Finish& f, doubl
   return cand;
 }
 
-template <int ND, int NSP, int FLUX, typename CT>
+template <int ND, int NSP, int FLUX, typename CT, bool AXI = false>
 __device__ inline void flux_gas_body(DevMesh m, const double* __restrict__ W,
                                                   const double* __restrict__ G,
                                                   double* __restrict__ PR, GasParams gp, Finish f,
@@ -1094,7 +1114,7 @@ __device__ inline void flux_gas_body(DevMesh m, const double* __restrict__ W,
   }
   tile_store_inc<NV>(m, tp, sInc);
   __syncthreads();
-  gas_cell_fluxes<ND, NSP, FLUX, CT, NV>(m, tp, sX, sW, sG, sR, CellLd{maxn, maxn, maxn, maxc}, gp);
+  gas_cell_fluxes<ND, NSP, FLUX, CT, NV, AXI>(m, tp, sX, sW, sG, sR, CellLd{maxn, maxn, maxn, maxc}, gp);
   __syncthreads();
   const double dt = f.sc ? f.sc->dt : 0.0;
   const double cand = tile_node_pass<ND, NSP, 0, NVAR>(m, f, dt, PR, ns, sSl, maxn, sInc, sR, maxc);
@@ -1104,14 +1124,14 @@ __device__ inline void flux_gas_body(DevMesh m, const double* __restrict__ W,
   }
 }
 
-template <int ND, int NSP, int FLUX, typename CT>
+template <int ND, int NSP, int FLUX, typename CT, bool AXI = false>
 __global__ void VCX_FLUX_BOUNDS k_flux_gas(DevMesh m, const double* __restrict__ W,
                                                   const double* __restrict__ G,
                                                   double* __restrict__ PR, GasParams gp, Finish f) {
   extern __shared__ double lds[];
   const int t = xcd_tile(m.ntiles);
   if (t >= m.ntiles) return;
-  flux_gas_body<ND, NSP, FLUX, CT>(m, W, G, PR, gp, f, t, lds);
+  flux_gas_body<ND, NSP, FLUX, CT, AXI>(m, W, G, PR, gp, f, t, lds);
 }
 
 // ---------------------------------------------------------------------------
