@@ -147,7 +147,7 @@ def workload(name):
                           + N * 8 * (nv + nr + 1 + nr)) + N * 8 * (nr + nd) + M * 16
         return m, U, None, phys, ophys, cfg, dict(flux=bytes_flux, step=bytes_step,
                                                    traffic_record="traffic_flux_euler3d_2m.md",
-                                                   flux_kernel="k_flux_gas<3,0,1,double>")
+                                                   flux_kernel="k_flux_gas<3,0,1,double,false>")
     if name == "ns3d":
         mix = wl.synthetic_mixture(9, seed=3)
         m = wl.ns3d_mesh()
