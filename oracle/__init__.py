@@ -56,7 +56,7 @@ class Phys:
     limiter: int = MINMOD
     rk: int = 2
     nspecies: int = 0
-    closure: bool = True
+    closure: int = 1         # 0 none, 1 node flux, 2 interpolated (2D)
     beta: float = 1.0
     cfl: float = 0.5
     fourier: float = 0.25
@@ -71,7 +71,7 @@ class Phys:
     def to_c(self) -> _Phys:
         p = _Phys()
         p.model, p.flux, p.limiter, p.rk = self.model, self.flux, self.limiter, self.rk
-        p.nspecies, p.closure = self.nspecies, int(bool(self.closure))
+        p.nspecies, p.closure = self.nspecies, int(self.closure)
         p.beta, p.cfl, p.fourier = self.beta, self.cfl, self.fourier
         p.gamma, p.entropy_fix = self.gamma, self.entropy_fix
         p.diel = self.diel

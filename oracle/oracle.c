@@ -24,6 +24,7 @@
  *                 eq. (virtual_node_reconstruction) and the co-reconstruction
  *                 of pressure
  *   closure       Sec. "Boundary conditions in AVIP", first option (node flux)
+ *                 and, in 2D, the second (interpolated 0.75 / 0.25 fluxes)
  *   axisymmetry   Sec. "Cylindrical frames" (Pappus-Guldinus theorems),
  *                 eq. (vertex_centered_flux_axi), Sec. "Geometric source
  *                 terms" (inviscid part); drift-diffusion and gas
@@ -80,6 +81,11 @@ struct om_mesh {
   double *Vp;    /* [nn] int_{A_i} r dA */
   double *Sbr;   /* [nn][nd] boundary node normals weighted by the centroid radius */
   double *Rn;    /* [nn] node radius */
+  /* 2D boundary edges (a, b) with their outward normal share S_f / 2 of
+   * each end (boundary-closure option 2) */
+  int64_t nbe;
+  int64_t *be;   /* [nbe][2] */
+  double *beS;   /* [nbe][2] */
 };
 
 /* local cell-edges, oriented from the lower to the higher local vertex */
@@ -290,7 +296,7 @@ static void sort_small(int64_t *v, int n) {
 void om_mesh_destroy(om_mesh *m) {
   if (!m) return;
   free(m->cell); free(m->X); free(m->S); free(m->Vc); free(m->Vn); free(m->Sb); free(m->bnd);
-  free(m->Rf); free(m->Vp); free(m->Sbr); free(m->Rn);
+  free(m->Rf); free(m->Vp); free(m->Sbr); free(m->Rn); free(m->be); free(m->beS);
   free(m);
 }
 
@@ -390,6 +396,11 @@ om_mesh *om_mesh_create_axi(int nd, int64_t nn, const double *xyz, int64_t nc, i
       r->k = k;
     }
   qsort(f, nf, sizeof(face_rec), face_cmp);
+  if (nd == 2) {
+    m->be = malloc(sizeof(int64_t) * 2 * nf);
+    m->beS = malloc(sizeof(double) * 2 * nf);
+    if (!m->be || !m->beS) { free(f); om_mesh_destroy(m); *status = -3; return NULL; }
+  }
   for (int64_t a = 0; a < nf;) {
     int64_t b = a + 1;
     while (b < nf && memcmp(f[b].key, f[a].key, sizeof(f[a].key)) == 0) b++;
@@ -408,6 +419,13 @@ om_mesh *om_mesh_create_axi(int nd, int64_t nn, const double *xyz, int64_t nc, i
           const double rf = 0.75 * xyz[nn + i] + 0.25 * xyz[nn + j];
           for (int d = 0; d < nd; d++) m->Sbr[i * nd + d] += Sk[d] / nd * rf;
         }
+      }
+      if (nd == 2) {
+        m->be[m->nbe * 2] = f[a].key[0];
+        m->be[m->nbe * 2 + 1] = f[a].key[1];
+        m->beS[m->nbe * 2] = Sk[0] / 2;
+        m->beS[m->nbe * 2 + 1] = Sk[1] / 2;
+        m->nbe++;
       }
       m->nbfaces++;
     }
@@ -757,7 +775,26 @@ static int residual_gas(const om_mesh *m, const om_phys *ph, const double *U, do
       }
     }
   }
-  if (ph->closure) {
+  if (ph->closure == 2) {
+    /* boundary closure, second option (2D): the flux through each half of a
+     * boundary edge is interpolated, 0.75 F(U_i) + 0.25 F(U_j) */
+    double Wa[2 + 3 + OM_MAXSP + 1], Wb[2 + 3 + OM_MAXSP + 1];
+    double Fa[2 + 3 + OM_MAXSP], Fb[2 + 3 + OM_MAXSP];
+    for (int64_t e = 0; e < m->nbe; e++) {
+      const int64_t a = m->be[2 * e], b = m->be[2 * e + 1];
+      for (int v = 0; v < nr; v++) {
+        Wa[v] = W[(int64_t)v * nn + a];
+        Wb[v] = W[(int64_t)v * nn + b];
+      }
+      om_euler_flux(nd, nsp, Wa, m->beS + 2 * e, Fa);
+      om_euler_flux(nd, nsp, Wb, m->beS + 2 * e, Fb);
+      for (int v = 0; v < nvar; v++) {
+        const double fa = 0.75 * Fa[v] + 0.25 * Fb[v], fb = 0.75 * Fb[v] + 0.25 * Fa[v];
+        r[(int64_t)v * nn + a] += absmode ? fabs(fa) : fa;
+        r[(int64_t)v * nn + b] += absmode ? fabs(fb) : fb;
+      }
+    }
+  } else if (ph->closure) {
     /* boundary closure, first option: the flux through the boundary part of
      * the dual surface is the node flux F(U_i) . S_i^b */
     double Wi[2 + 3 + OM_MAXSP + 1], F[2 + 3 + OM_MAXSP];
@@ -833,7 +870,29 @@ static int residual_dd(const om_mesh *m, const om_phys *ph, const double *U, con
       }
     }
   }
-  if (ph->closure) {
+  if (ph->closure == 2) {
+    /* second option (2D): 0.75 F_i + 0.25 F_j on each half boundary edge,
+     * F_k = u_k V_k . S - D grad u_k . S */
+    for (int64_t e = 0; e < m->nbe; e++) {
+      const int64_t ab[2] = {m->be[2 * e], m->be[2 * e + 1]};
+      const double *S = m->beS + 2 * e;
+      for (int s = 0; s < ns; s++) {
+        double F[2];
+        for (int q = 0; q < 2; q++) {
+          const int64_t i = ab[q];
+          double zm = ph->z[s] * ph->mu[s], vb = 0.0, gb = 0.0;
+          for (int d = 0; d < nd; d++) {
+            vb += zm * E[(int64_t)d * nn + i] * S[d];
+            gb += G[((int64_t)s * nd + d) * nn + i] * S[d];
+          }
+          F[q] = U[(int64_t)s * nn + i] * vb - ph->D[s] * gb;
+        }
+        const double fa = 0.75 * F[0] + 0.25 * F[1], fb = 0.75 * F[1] + 0.25 * F[0];
+        r[(int64_t)s * nn + ab[0]] += absmode ? fabs(fa) : fa;
+        r[(int64_t)s * nn + ab[1]] += absmode ? fabs(fb) : fb;
+      }
+    }
+  } else if (ph->closure) {
     /* supersonic-type boundary: F = F_C + F_D with node values */
     for (int64_t i = 0; i < nn; i++) {
       if (!m->bnd[i]) continue;
@@ -856,6 +915,8 @@ static int residual_dd(const om_mesh *m, const om_phys *ph, const double *U, con
 static int residual_any(const om_mesh *m, const om_phys *ph, const double *U, const double *E,
                         double dt, double *r, int absmode) {
   if (!m || !ph || !U || !r) return -1;
+  /* the interpolated closure is given for planar 2D meshes */
+  if (ph->closure == 2 && (m->nd != 2 || m->axi || ph->model == 2)) return -1;
   if (ph->nspecies < 0 || ph->nspecies > OM_MAXSP) return -1;
   if (ph->model == 0 || ph->model == 2) {
     if (m->axi && ph->model == 2) return -1; /* viscous geometric source terms: not built */

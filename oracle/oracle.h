@@ -32,7 +32,8 @@ typedef struct {
   int32_t limiter;    /* 0 first order, 1 minmod, 2 van Leer, 3 Sweby(beta), 4 unlimited */
   int32_t rk;         /* 1..4, low-storage table */
   int32_t nspecies;   /* gas: passive species; drift-diffusion: charged species */
-  int32_t closure;    /* 1: add node-flux boundary closure on boundary nodes */
+  int32_t closure;    /* 1: node-flux boundary closure on boundary nodes; 2: interpolated
+                         fluxes 0.75 F_i + 0.25 F_j on each half boundary edge (2D) */
   double beta;        /* Sweby parameter */
   double cfl, fourier;
   double gamma;

@@ -64,7 +64,7 @@ def physics(model=MODEL_GAS, flux=FLUX_HLLC, limiter=LIM_MINMOD, rk_stages=2, ns
             entropy_fix=0.1, z=(), mu=(), D=(), mixture=None, diel=0.0) -> Physics:
     p = Physics()
     p.model, p.flux, p.limiter, p.rk_stages = model, flux, limiter, rk_stages
-    p.nspecies, p.closure, p.precision = nspecies, int(bool(closure)), precision
+    p.nspecies, p.closure, p.precision = nspecies, int(closure), precision
     p.beta, p.cfl, p.fourier, p.gamma, p.entropy_fix = beta, cfl, fourier, gamma, entropy_fix
     p.diel = diel
     for k, (a, b, c) in enumerate(zip(z, mu, D)):

@@ -30,7 +30,7 @@ class Case:
         s = self.scheme
         return oracle.Phys(model=self.model, flux=1 if s.get("flux") == "roe" else 0,
                            limiter=LIMNAMES[s["limiter"]], rk=s.get("rk", 2),
-                           nspecies=s.get("nspecies", 0), closure=s.get("closure", True),
+                           nspecies=s.get("nspecies", 0), closure=int(s.get("closure", 1)),
                            beta=s.get("beta", 1.0), cfl=s.get("cfl", 0.5),
                            fourier=s.get("fourier", 0.25), gamma=1.4,
                            entropy_fix=s.get("fix", 0.1), z=s.get("z", []), mu=s.get("mu", []),
@@ -41,7 +41,7 @@ class Case:
         s = self.scheme
         return vcx.physics(model=self.model, flux=1 if s.get("flux") == "roe" else 0,
                            limiter=LIMNAMES[s["limiter"]], rk_stages=s.get("rk", 2),
-                           nspecies=s.get("nspecies", 0), closure=s.get("closure", True),
+                           nspecies=s.get("nspecies", 0), closure=int(s.get("closure", 1)),
                            precision=precision, beta=s.get("beta", 1.0), cfl=s.get("cfl", 0.5),
                            fourier=s.get("fourier", 0.25), gamma=1.4,
                            entropy_fix=s.get("fix", 0.1), z=s.get("z", []), mu=s.get("mu", []),
