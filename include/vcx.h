@@ -94,7 +94,10 @@ typedef struct {
   int32_t nspecies;   /* gas: passive species (0, 2 or 9 supported);
                          drift-diffusion: charged species (1 or 2);
                          Navier-Stokes: species (2 or 9), HLLC only */
-  int32_t closure;    /* 1: node-flux closure on boundary nodes */
+  int32_t closure;    /* boundary closure (Sec. "Boundary conditions in AVIP"):
+                         0 none, 1 node flux F(U_i) . S_i^b, 2 (plane 2D meshes,
+                         gas and drift-diffusion) interpolated fluxes
+                         0.75 F_i + 0.25 F_j on each half boundary edge */
   int32_t precision;  /* VCX_PREC_* */
   int32_t reserved;
   double beta;        /* Sweby beta */

@@ -82,6 +82,7 @@ struct vcx_solver_s {
   size_t lds_grad = 0, lds_flux = 0, lds_fused = 0;
   bool fused = false;      // time loop and residual run the fused gradient + flux pass
   double* gout = nullptr;  // fused passes: node gradients for the boundary closure, or null
+  double* cbuf = nullptr;  // second closure option: [nb][nvar] closure fluxes of the stage input
   int tile_block = 256;
   size_t bytes = 0;  // device bytes held by the solver (mesh excluded)
   // profiling
@@ -162,6 +163,7 @@ struct KernelTable {
   vcx_status (*allow_lds)(size_t grad_bytes, size_t flux_bytes, size_t fused_bytes);
   vcx_status (*aux)(vcx_solver, double* W);
   vcx_status (*batch_stage)(const struct BatchRun& br, hipStream_t stream, const BatchStage& st, bool prof);
+  vcx_status (*closure2)(vcx_solver, const Finish& f);
   int nw, ngf;
 };
 
@@ -455,10 +457,23 @@ struct Impl {
                          stream, ea, eb, 0, (const BatchEntry*)br.tab, (const int2*)br.sh_map, st, fs);
     });
   }
+  // second closure option: boundary-node closure fluxes of the stage input
+  static vcx_status closure2(vcx_solver s, const Finish& f) {
+    const DevMesh& m = s->mesh->d;
+    if constexpr (ND == 2 && MODEL != 2) {
+      if (m.nb == 0) return VCX_OK;
+      hipLaunchKernelGGL((k_closure2<ND, NSP, MODEL>), dim3((m.nb + 255) / 256), dim3(256), 0, s->mesh->stream,
+                         m, f, s->cbuf);
+      VCX_HIP(hipGetLastError());
+      return VCX_OK;
+    } else {
+      return fail(VCX_E_ARG, "the interpolated closure is defined on plane 2D meshes");
+    }
+  }
   static const KernelTable* table() {
     static const KernelTable t{&grad,     &grad_complete, &flux,      &update_shared, &node_dt,
                                &lds_grad, &lds_flux,      &lds_fused, &fused,         &allow_lds,
-                               &aux,      &batch_stage,   NW,         NGF};
+                               &aux,      &batch_stage,   &closure2,  NW,             NGF};
     return &t;
   }
 };
@@ -691,6 +706,13 @@ static vcx_status create_mesh(int ndim, int64_t nnodes, const double* xyz, int64
   }
   chk(upload(m, bidx, &d.bnd_index));
   chk(upload(m, h.bnd_S, &d.bnd_S));
+  chk(upload(m, h.bnd_node, &d.bnd_node));
+  d.nbe = (int)h.bedge_nb.size();
+  if (h.nd == 2) {
+    chk(upload(m, h.bedge_ptr, &d.bedge_ptr));
+    chk(upload(m, h.bedge_nb, &d.bedge_nb));
+    chk(upload(m, h.bedge_S, &d.bedge_S));
+  }
   chk(upload(m, h.perm, &d.perm));
   if (st == VCX_OK) {
     // smallest inscribed diameter of the cells around each node (time step)
@@ -761,7 +783,7 @@ extern "C" vcx_status vcx_mesh_geometry(vcx_mesh m, double* Vn, double* Sb) {
 static void free_solver(vcx_solver s) {
   if (!s) return;
   for (double* p : {s->W[0], s->W[1], s->G, s->PG, s->PR, s->E, s->io, s->rbuf, s->part,
-                    s->sums_dev})
+                    s->sums_dev, s->cbuf})
     if (p) (void)hipFree(p);
   if (s->lp) (void)hipFree(s->lp);
   if (s->sc_host) (void)hipHostFree(s->sc_host);
@@ -885,6 +907,10 @@ extern "C" vcx_status vcx_solver_create(vcx_mesh mesh, const vcx_physics* phys, 
   if (mesh->h.axi && ph.model == VCX_MODEL_NAVIER_STOKES)
     return fail(VCX_E_ARG, "axisymmetric meshes support the drift-diffusion and gas models (the viscous "
                            "geometric source terms are not built)");
+  if (ph.closure < 0 || ph.closure > 2) return fail(VCX_E_ARG, "closure must be 0, 1 or 2");
+  if (ph.closure == 2 && (nd != 2 || mesh->h.axi || ph.model == VCX_MODEL_NAVIER_STOKES))
+    return fail(VCX_E_ARG, "the interpolated boundary closure is defined on plane 2D meshes (gas and "
+                           "drift-diffusion)");
   if (ph.rk_stages < 1 || ph.rk_stages > 4) return fail(VCX_E_ARG, "rk_stages must be 1..4");
   if (ph.limiter < 0 || ph.limiter > 4) return fail(VCX_E_ARG, "unknown limiter");
   if (ph.precision != VCX_PREC_FP64 && ph.precision != VCX_PREC_MIXED)
@@ -925,7 +951,9 @@ extern "C" vcx_status vcx_solver_create(vcx_mesh mesh, const vcx_physics* phys, 
   s->lds_fused = kt->lds_fused(d);
   // the fused pass is for plane meshes; axisymmetric ones take the
   // gradient + flux passes, whose flux carries the face radii
-  s->fused = !d.axi && s->lds_fused > 0 && s->lds_fused <= (size_t)mesh->lds_max;
+  // (and the interpolated closure reads neighbours' gradients, complete only
+  // after a separate gradient pass)
+  s->fused = !d.axi && ph.closure != 2 && s->lds_fused > 0 && s->lds_fused <= (size_t)mesh->lds_max;
   if (!s->fused) s->lds_fused = 0;
   if (std::max({s->lds_grad, s->lds_flux, s->lds_fused}) > 65536) {
     vcx_status st = kt->allow_lds(s->lds_grad, s->lds_flux, s->lds_fused);
@@ -951,6 +979,10 @@ extern "C" vcx_status vcx_solver_create(vcx_mesh mesh, const vcx_physics* phys, 
   chk(dmalloc(&s->rbuf, z.io));
   chk(dmalloc(&s->part, z.part));
   chk(dmalloc(&s->sums_dev, z.sums));
+  if (ph.closure == 2 && d.nb > 0) {
+    chk(dmalloc(&s->cbuf, (size_t)d.nb * s->nvar));
+    s->bytes += sizeof(double) * (size_t)d.nb * s->nvar;
+  }
   s->node_blocks = z.node_blocks;
   s->nsh_blocks = z.nsh_blocks;
   if (st == VCX_OK && hipMalloc(reinterpret_cast<void**>(&s->lp), sizeof(DevLoop)) != hipSuccess)
@@ -1040,6 +1072,7 @@ extern "C" vcx_status vcx_gradient(vcx_solver s, double* G, int is_device) {
 
 static Finish make_finish(vcx_solver s) {
   Finish f{};
+  f.cbuf = s->cbuf;
   f.G = s->G;
   f.PG = s->PG;
   f.E = s->E;
@@ -1064,6 +1097,7 @@ extern "C" vcx_status vcx_residual(vcx_solver s, double dt, double* r, int is_de
   } else {
     GradCtl gc{nullptr, 0, 0};
     VCX_TRY(s->kt->grad(s, Win, gc));
+    if (s->ph.closure == 2) VCX_TRY(s->kt->closure2(s, f));
     VCX_TRY(s->kt->flux(s, Win, f, dt));
   }
   VCX_TRY(s->kt->update_shared(s, f));
@@ -1137,6 +1171,7 @@ static vcx_status enqueue_step(vcx_solver s) {
     } else {
       GradCtl gc{s->lp, par, k == 1 ? 1 : 0};
       VCX_TRY(s->kt->grad(s, Win, gc));
+      if (s->ph.closure == 2) VCX_TRY(s->kt->closure2(s, f));
       VCX_TRY(s->kt->flux(s, Win, f, 0.0));
     }
     VCX_TRY(s->kt->update_shared(s, f));
@@ -1294,7 +1329,8 @@ vcx_status vcx::batch_set(BatchGroup* g, vcx_solver* ss, int n, const int* steps
     g->pair = nullptr;
   }
   for (int i = 0; i < n; ++i)
-    if (ss[i] && ss[i]->mesh->h.axi) return fail(VCX_E_ARG, "solvers on axisymmetric meshes are not batched");
+    if (ss[i] && (ss[i]->mesh->h.axi || ss[i]->ph.closure == 2))
+      return fail(VCX_E_ARG, "solvers on axisymmetric meshes or with the interpolated closure are not batched");
   g->mem.assign(ss, ss + n);
   g->q = 0;
   if (n == 0) return VCX_OK;
@@ -1462,6 +1498,7 @@ static vcx_status solve_batch(vcx_solver* ss, int n, const int* nsteps, const do
     if (ss[i]->host_flag) return fail(VCX_E_UNSTABLE, "batch member in a failed state");
     if (nsteps[i] < 0) return fail(VCX_E_ARG, "nsteps must be >= 0");
     if (ss[i]->mesh->h.axi) return fail(VCX_E_ARG, "solvers on axisymmetric meshes are not batched");
+    if (ss[i]->ph.closure == 2) return fail(VCX_E_ARG, "solvers with the interpolated closure are not batched");
     if (!batch_compatible(ss[i], ss[0]))
       return fail(VCX_E_ARG, "batch members must share the model and scheme parameters");
     for (int j = 0; j < i; ++j)

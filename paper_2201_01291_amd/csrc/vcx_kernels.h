@@ -79,6 +79,12 @@ struct DevMesh {
   const double* dxmin;       // [nn] smallest inscribed diameter of the cells around the node
   const int32_t* bnd_index;  // [nn] -1 or index into bnd_S
   const double* bnd_S;       // [nd][nb]
+  // 2D boundary edge shares by boundary index (second closure option)
+  const int32_t* bnd_node;   // [nb] internal ids of the boundary nodes
+  const int32_t* bedge_ptr;  // [nb+1]
+  const int32_t* bedge_nb;   // [nbe]
+  const double* bedge_S;     // [nd][nbe]
+  int nbe;
   const int32_t* perm;       // [nn] internal -> caller
 };
 
@@ -713,6 +719,7 @@ struct Finish {
   MixParams mix;        // Navier-Stokes species data
   double alpha;
   int closure, final_stage, residual_only;
+  const double* cbuf;   // second closure option: [nb][NVAR] closure fluxes of the stage input
 };
 
 // Node inputs of the stage update, loaded ahead of the residual sums where
@@ -764,50 +771,67 @@ __device__ inline void node_in_lds(const DevMesh& m, const Finish& f, double dt,
   }
 }
 
+// Node flux F(node k) . S of the boundary closure: the Euler flux of the
+// stage state (inviscid part for Navier-Stokes), or the drift plus diffusive
+// flux u_k V_k . S - D grad u_k . S for drift-diffusion.
+template <int ND, int NSP, int MODEL, int NVAR>
+__device__ inline void closure_flux(const DevMesh& m, const Finish& f, int k, bool shared, const double (&S)[ND],
+                                    double (&F)[NVAR]) {
+  if constexpr (MODEL != 1) {
+    double Wk[NVAR + 1];
+#pragma unroll
+    for (int v = 0; v <= NVAR; ++v) Wk[v] = f.Win[(size_t)v * m.nn + k];
+    double q = 0.0;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) q += Wk[1 + d] * S[d];
+    q /= Wk[0];
+    const double p = Wk[NVAR];
+    F[0] = Wk[0] * q;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) F[1 + d] = Wk[1 + d] * q + p * S[d];
+    F[1 + ND] = (Wk[1 + ND] + p) * q;
+#pragma unroll
+    for (int s = 0; s < NSP; ++s) F[2 + ND + s] = Wk[2 + ND + s] * q;
+  } else {
+    double gr[NSP * ND];
+    if (shared && !f.gfull) {
+      shared_gradient<NSP * ND, ND>(m, f.PG, k, make_int2(m.node_slot[k], m.node_slot[k + 1]), gr);
+    } else {
+#pragma unroll
+      for (int j = 0; j < NSP * ND; ++j) gr[j] = f.G[(size_t)j * m.nn + k];
+    }
+#pragma unroll
+    for (int s = 0; s < NVAR; ++s) {
+      double vb = 0.0, gb = 0.0;
+#pragma unroll
+      for (int d = 0; d < ND; ++d) {
+        vb += f.dc.zmu[s] * f.E[(size_t)d * m.nn + k] * S[d];
+        gb += gr[s * ND + d] * S[d];
+      }
+      F[s] = f.Win[(size_t)s * m.nn + k] * vb - f.dc.D[s] * gb;
+    }
+  }
+}
+
 template <int ND, int NSP, int MODEL, int NVAR>
 __device__ inline double finish_node(const DevMesh& m, const Finish& f, int i, bool shared,
                                      double (&r)[NVAR], const NodeIn<NVAR, ND>& ni) {
   if (f.closure && m.nb > 0) {
     const int bi = m.bnd_index[i];
     if (bi >= 0) {
-      double Sb[ND];
+      if (ND == 2 && f.closure == 2) {
+        // second option: computed from the stage input before the flux pass
+        // (it reads neighbours, which the pass may overwrite in place)
 #pragma unroll
-      for (int d = 0; d < ND; ++d) Sb[d] = m.bnd_S[(size_t)d * m.nb + bi];
-      if constexpr (MODEL != 1) {
-        // node flux F(W_i) . S_i^b (inviscid part for Navier-Stokes)
-        double Wi[NVAR + 1];
-#pragma unroll
-        for (int v = 0; v <= NVAR; ++v) Wi[v] = f.Win[(size_t)v * m.nn + i];
-        double q = 0.0;
-#pragma unroll
-        for (int d = 0; d < ND; ++d) q += Wi[1 + d] * Sb[d];
-        q /= Wi[0];
-        const double p = Wi[NVAR];
-        r[0] += Wi[0] * q;
-#pragma unroll
-        for (int d = 0; d < ND; ++d) r[1 + d] += Wi[1 + d] * q + p * Sb[d];
-        r[1 + ND] += (Wi[1 + ND] + p) * q;
-#pragma unroll
-        for (int k = 0; k < NSP; ++k) r[2 + ND + k] += Wi[2 + ND + k] * q;
+        for (int v = 0; v < NVAR; ++v) r[v] += f.cbuf[(size_t)bi * NVAR + v];
       } else {
-        // convective plus diffusive node flux
-        double gr[NSP * ND];
-        if (shared && !f.gfull) {
-          shared_gradient<NSP * ND, ND>(m, f.PG, i, make_int2(m.node_slot[i], m.node_slot[i + 1]), gr);
-        } else {
+        // first option: the node flux through S_i^b
+        double Sb[ND], F[NVAR];
 #pragma unroll
-          for (int j = 0; j < NSP * ND; ++j) gr[j] = f.G[(size_t)j * m.nn + i];
-        }
+        for (int d = 0; d < ND; ++d) Sb[d] = m.bnd_S[(size_t)d * m.nb + bi];
+        closure_flux<ND, NSP, MODEL, NVAR>(m, f, i, shared, Sb, F);
 #pragma unroll
-        for (int s = 0; s < NVAR; ++s) {
-          double vb = 0.0, gb = 0.0;
-#pragma unroll
-          for (int d = 0; d < ND; ++d) {
-            vb += f.dc.zmu[s] * f.E[(size_t)d * m.nn + i] * Sb[d];
-            gb += gr[s * ND + d] * Sb[d];
-          }
-          r[s] += f.Win[(size_t)s * m.nn + i] * vb - f.dc.D[s] * gb;
-        }
+        for (int v = 0; v < NVAR; ++v) r[v] += F[v];
       }
     }
   }
@@ -829,7 +853,9 @@ __device__ inline double finish_node(const DevMesh& m, const Finish& f, int i, b
   double u[NVAR];
 #pragma unroll
   for (int v = 0; v < NVAR; ++v) u[v] = ni.Un[v] - ni.fac * r[v];
-  if (on_axis) u[2] = 0.0;
+  if constexpr (MODEL == 0 && ND == 2) {
+    if (on_axis) u[2] = 0.0;
+  }
 #pragma unroll
   for (int v = 0; v < NVAR; ++v) f.Wout[(size_t)v * m.nn + i] = u[v];
   bool ok = true;
@@ -964,6 +990,36 @@ __device__ inline void gas_cell_fluxes(const DevMesh& m, const TilePre<NV>& tp, 
 #pragma unroll
       for (int v = 0; v < NVAR; ++v) sR[(k * NVAR + v) * L.ldc + lc] = acc[k][v];
   }
+}
+
+// Second boundary-closure option (Sec. "Boundary conditions in AVIP", 2D):
+// each half boundary edge carries the interpolated flux 0.75 F_i + 0.25 F_j;
+// per boundary node, the sum over its half edges, in ascending order of the
+// other end.  Runs after the gradient pass and before the flux pass of a
+// stage.
+template <int ND, int NSP, int MODEL>
+__global__ void __launch_bounds__(256) k_closure2(DevMesh m, Finish f, double* __restrict__ cbuf) {
+  constexpr int NVAR = MODEL == 1 ? NSP : 2 + ND + NSP;
+  if (step_inactive(f.sc)) return;
+  const int bi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (bi >= m.nb) return;
+  const int i = m.bnd_node[bi];
+  const bool shared_i = m.node_slot[i + 1] - m.node_slot[i] > 1;
+  double c[NVAR];
+#pragma unroll
+  for (int v = 0; v < NVAR; ++v) c[v] = 0.0;
+  for (int e = m.bedge_ptr[bi]; e < m.bedge_ptr[bi + 1]; ++e) {
+    const int j = m.bedge_nb[e];
+    double S[ND], Fi[NVAR], Fj[NVAR];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) S[d] = m.bedge_S[(size_t)d * m.nbe + e];
+    closure_flux<ND, NSP, MODEL, NVAR>(m, f, i, shared_i, S, Fi);
+    closure_flux<ND, NSP, MODEL, NVAR>(m, f, j, m.node_slot[j + 1] - m.node_slot[j] > 1, S, Fj);
+#pragma unroll
+    for (int v = 0; v < NVAR; ++v) c[v] += 0.75 * Fi[v] + 0.25 * Fj[v];
+  }
+#pragma unroll
+  for (int v = 0; v < NVAR; ++v) cbuf[(size_t)bi * NVAR + v] = c[v];
 }
 
 // Drift-diffusion fluxes of the tile's cells: limited Lax-Wendroff

@@ -261,6 +261,8 @@ std::string preprocess_mesh(int nd, int64_t nn, const double* xyz, int64_t nc, i
   });
   std::vector<double> Sb((size_t)nd * nn, 0.0);
   std::vector<char> isb(nn, 0);
+  struct EdgeShare { int32_t i, j; double S[2]; };
+  std::vector<EdgeShare> shares;
   for (size_t a = 0; a < faces.size();) {
     size_t b = a + 1;
     while (b < faces.size() && faces[b].n == faces[a].n) ++b;
@@ -281,6 +283,7 @@ std::string preprocess_mesh(int nd, int64_t nn, const double* xyz, int64_t nc, i
         // axisymmetric: node i's half of the edge revolves at radius (3 r_i + r_j)/4
         const double w = m.axi ? 0.75 * m.x[(size_t)nn + i] + 0.25 * m.x[(size_t)nn + faces[a].n[1 - q]] : 1.0;
         for (int d = 0; d < nd; ++d) Sb[(size_t)d * nn + i] += S[faces[a].k][d] / nd * w;
+        if (nd == 2) shares.push_back({i, faces[a].n[1 - q], {S[faces[a].k][0] / 2, S[faces[a].k][1] / 2}});
       }
     }
     a = b;
@@ -291,6 +294,23 @@ std::string preprocess_mesh(int nd, int64_t nn, const double* xyz, int64_t nc, i
   m.bnd_S.resize((size_t)nd * nb);
   for (size_t q = 0; q < nb; ++q)
     for (int d = 0; d < nd; ++d) m.bnd_S[(size_t)d * nb + q] = Sb[(size_t)d * nn + m.bnd_node[q]];
+  if (nd == 2) {
+    // bnd_node is ascending, so the boundary index orders like the node id
+    std::sort(shares.begin(), shares.end(), [](const EdgeShare& a, const EdgeShare& b) {
+      return a.i != b.i ? a.i < b.i : a.j < b.j;
+    });
+    m.bedge_ptr.assign(nb + 1, 0);
+    m.bedge_nb.resize(shares.size());
+    m.bedge_S.resize(2 * shares.size());
+    size_t q = 0;
+    for (size_t e = 0; e < shares.size(); ++e) {
+      while (m.bnd_node[q] != shares[e].i) m.bedge_ptr[++q] = (int32_t)e;
+      m.bedge_nb[e] = shares[e].j;
+      m.bedge_S[e] = shares[e].S[0];
+      m.bedge_S[shares.size() + e] = shares[e].S[1];
+    }
+    while (q < nb) m.bedge_ptr[++q] = (int32_t)shares.size();
+  }
 
   // ---- tiles: consecutive cells, closed at max_cells cells or max_nodes nodes
   std::vector<int64_t> stamp(nn, -1);

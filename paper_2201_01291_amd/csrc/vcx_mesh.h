@@ -38,6 +38,12 @@ struct HostMesh {
   // boundary closure
   std::vector<int32_t> bnd_node;  // [nb] internal ids (ascending)
   std::vector<double> bnd_S;      // [nd][nb] boundary node normals S_i^b
+  // 2D: each boundary node's shares of its boundary edges (the other end
+  // and the outward normal share S_f / 2), by boundary index, ascending
+  // other end (second boundary-closure option)
+  std::vector<int32_t> bedge_ptr;  // [nb+1]
+  std::vector<int32_t> bedge_nb;   // [nbe]
+  std::vector<double> bedge_S;     // [nd][nbe]
 
   // tiles
   TileLimits lim{};

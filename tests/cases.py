@@ -62,6 +62,15 @@ def make_case(name: str) -> Case:
         m = wl.dd_streamer_mesh(40, 25, seed=3)
         n, E = wl.dd_fields(m, sigma=2e-3, seed=8, peak=2e19)
         return Case(name, m, n, E, dict(DD2, diel=0.8))
+    if name == "dd2d-open-closure2":
+        # second boundary-closure option: interpolated half-edge fluxes
+        m = wl.tri_rect_mesh(23, 17, 0.02, 0.015, jitter=0.2, seed=12)
+        n, E = wl.dd_fields(m, sigma=3e-3, seed=6)
+        return Case(name, m, n, E, dict(DD2, limiter="vanleer", closure=2))
+    if name == "euler2d-open-closure2":
+        m = wl.tri_rect_mesh(18, 14, jitter=0.2, seed=13)
+        U = wl.euler_blob_state(m, nblobs=3, amp=0.3, sigma=0.2, mach=0.5)
+        return Case(name, m, U, None, dict(model="gas", flux="hllc", limiter="minmod", rk=2, closure=2))
     if name == "dd2d-open-vanleer":
         m = wl.tri_rect_mesh(23, 17, 0.02, 0.015, jitter=0.2, seed=9)
         n, E = wl.dd_fields(m, sigma=3e-3, seed=4)
@@ -110,7 +119,8 @@ def make_case(name: str) -> Case:
     raise KeyError(name)
 
 
-CASE_NAMES = ["dd2d-streamer", "dd2d-diel", "dd2d-open-vanleer", "dd3d-sweby", "sod-hllc", "euler2d-roe-sp2",
+CASE_NAMES = ["dd2d-streamer", "dd2d-diel", "dd2d-open-vanleer", "dd2d-open-closure2",
+              "euler2d-open-closure2", "dd3d-sweby", "sod-hllc", "euler2d-roe-sp2",
               "euler3d-roe", "euler3d-hllc-open-sp2", "euler3d-hllc-sp9", "ns3d-sp9",
               "ns2d-sp2-open"]
 
