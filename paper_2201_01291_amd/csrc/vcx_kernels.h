@@ -231,6 +231,40 @@ __device__ __attribute__((always_inline)) inline void edge_rolled(int ed, const 
   for (int k = 0; k < NV; ++k) g.coef[k] = k == g.a ? 1.0 : (k == g.b ? -1.0 : 0.0);
 }
 
+// The same for a compile-time edge.
+template <int ED, int ND, typename CT>
+__device__ __attribute__((always_inline)) inline void edge_static(const int (&l)[ND + 1], const double (&e)[ND][ND],
+                                                                  const double (&Sd)[ND + 1][ND],
+                                                                  EdgeRolled<ND, CT>& g) {
+  constexpr int NV = ND + 1, a = Edges<ND>::a(ED), b = Edges<ND>::b(ED);
+  g.a = a;
+  g.b = b;
+  g.la = l[a];
+  g.lb = l[b];
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    g.S[d] = CT((Sd[a][d] - Sd[b][d]) * (1.0 / double(ND * NV)));
+    g.dx[d] = CT((a == 0 ? 0.0 : -e[a == 0 ? 0 : a - 1][d]) + e[b - 1][d]);
+  }
+#pragma unroll
+  for (int k = 0; k < NV; ++k) g.coef[k] = k == a ? 1.0 : (k == b ? -1.0 : 0.0);
+}
+
+// Edge ed of a tetrahedron, ed the same in every lane: a scalar branch to the
+// compile-time form (no run-time indexing of register arrays).
+template <typename CT>
+__device__ __attribute__((always_inline)) inline void edge_uniform3(int ed, const int (&l)[4], const double (&e)[3][3],
+                                                                    const double (&Sd)[4][3], EdgeRolled<3, CT>& g) {
+  switch (__builtin_amdgcn_readfirstlane(ed)) {
+    case 0: edge_static<0, 3, CT>(l, e, Sd, g); break;
+    case 1: edge_static<1, 3, CT>(l, e, Sd, g); break;
+    case 2: edge_static<2, 3, CT>(l, e, Sd, g); break;
+    case 3: edge_static<3, 3, CT>(l, e, Sd, g); break;
+    case 4: edge_static<4, 3, CT>(l, e, Sd, g); break;
+    default: edge_static<5, 3, CT>(l, e, Sd, g); break;
+  }
+}
+
 // Tile topology read at the start of a tile pass, so that its loads are in
 // flight together with the staging of the node data: this thread's cell and
 // slot (the first iteration of the cell and slot loops) and up to NV of the
@@ -1624,7 +1658,10 @@ __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ W,
 #pragma unroll 1
     for (int ed = 0; ed < NE; ++ed) {
       EdgeRolled<ND, CT> g;
-      edge_rolled<ND, CT>(ed, l, e, Sd, g);
+      if constexpr (ND == 3)
+        edge_uniform3<CT>(ed, l, e, Sd, g);
+      else
+        edge_rolled<ND, CT>(ed, l, e, Sd, g);
       const int la = g.la, lb = g.lb;
       const CT(&S)[ND] = g.S;
       const CT(&dx)[ND] = g.dx;
