@@ -222,7 +222,8 @@ struct Impl {
   static constexpr int NW = NR + NP + NA;                    // rows of a state buffer
 
   static size_t lds_grad(int maxn, int maxc) {
-    return sizeof(double) * ((size_t)(NGF + ND) * maxn + (size_t)NGF * ND * maxc) + inc_lds_bytes(NV, maxc);
+    constexpr int FG = grad_group(NGF);  // fields staged per pass
+    return sizeof(double) * ((size_t)(FG + ND) * maxn + (size_t)FG * ND * maxc) + inc_lds_bytes(NV, maxc);
   }
   static size_t lds_flux(int maxn, int maxc) {
     size_t dbl = sizeof(double) * ((size_t)ND * maxn + (size_t)NV * NVAR * maxc);

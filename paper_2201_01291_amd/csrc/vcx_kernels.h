@@ -535,92 +535,105 @@ struct GradCtl {
   int first_stage; // first stage: an extra block decides the step
 };
 
+// Fields per pass of the gradient kernel: at most 8, in equal groups, so
+// that the staged fields and cell parts of many-field states (multi-species
+// Navier-Stokes) take a fraction of the LDS and more blocks fit on a CU.
+__host__ __device__ constexpr int grad_group(int nr) {
+  return (nr + (nr + 7) / 8 - 1) / ((nr + 7) / 8);
+}
+
 template <int ND, int NR>
 __device__ inline void grad_tile_body(const DevMesh& m, const double* __restrict__ W,
                                       double* __restrict__ G, double* __restrict__ PG,
                                       const GradCtl& ctl, int t, double* lds) {
-  constexpr int NV = ND + 1, NC = NR * ND;
+  constexpr int NV = ND + 1, NC = NR * ND, FG = grad_group(NR);
   // later stages of a step that does no work (set by an earlier launch)
   if (ctl.lp && !ctl.first_stage && ctl.lp->s[ctl.par].active == 0) return;
   TilePre<NV> tp;
   tile_prefetch<NV>(m, t, tp);
   const int maxn = m.max_tile_nodes, maxc = m.max_tile_cells;
-  double* sW = lds;                 // [NR][maxn]
-  double* sX = sW + NR * maxn;      // [ND][maxn]
-  double* sC = sX + ND * maxn;      // [NC][maxc]
-  uint16_t* sInc = reinterpret_cast<uint16_t*>(sC + NC * maxc);
+  double* sW = lds;                 // [FG][maxn] fields of this group
+  double* sX = sW + FG * maxn;      // [ND][maxn]
+  double* sC = sX + ND * maxn;      // [FG*ND][maxc]
+  uint16_t* sInc = reinterpret_cast<uint16_t*>(sC + FG * ND * maxc);
   const int nc = tp.nc, ns = tp.ns;
   double iv = 0.0;  // 1/V of this thread's slot node (tile-owned nodes)
-  for (int q = threadIdx.x; q < ns; q += blockDim.x) {
-    const int sv = q == (int)threadIdx.x ? tp.sv : m.slot_node[tp.s0 + q];
-    const int g = slot_node_id(sv);
-    if (q == (int)threadIdx.x && sv >= 0) iv = m.inv_vol[sv];
-    constexpr int WC = NR <= 16 ? NR : 16;
-    double xx[ND];
+  // the fields in groups of FG: stage, cell parts, node sums
+  for (int v0 = 0; v0 < NR; v0 += FG) {
+    if (v0 > 0) __syncthreads();  // the previous group's node sums have read sC
+    for (int q = threadIdx.x; q < ns; q += blockDim.x) {
+      const int sv = q == (int)threadIdx.x ? tp.sv : m.slot_node[tp.s0 + q];
+      const int g = slot_node_id(sv);
+      double w[FG];
 #pragma unroll
-    for (int d = 0; d < ND; ++d) xx[d] = m.x[(size_t)d * m.nn + g];
-    for (int v0 = 0; v0 < NR; v0 += WC) {
-      double w[WC];
-#pragma unroll
-      for (int vv = 0; vv < WC; ++vv)
+      for (int vv = 0; vv < FG; ++vv)
         if (v0 + vv < NR) w[vv] = W[(size_t)(v0 + vv) * m.nn + g];
+      if (v0 == 0) {
+        if (q == (int)threadIdx.x && sv >= 0) iv = m.inv_vol[sv];
+        double xx[ND];
 #pragma unroll
-      for (int vv = 0; vv < WC; ++vv)
-        if (v0 + vv < NR) sW[(v0 + vv) * maxn + q] = w[vv];
-    }
+        for (int d = 0; d < ND; ++d) xx[d] = m.x[(size_t)d * m.nn + g];
 #pragma unroll
-    for (int d = 0; d < ND; ++d) sX[d * maxn + q] = xx[d];
-  }
-  tile_store_inc<NV>(m, tp, sInc);
-  __syncthreads();
-  for (int lc = threadIdx.x; lc < nc; lc += blockDim.x) {
-    int l[NV];
-    uint32_t sh;
-    cell_topo<NV>(m, tp, lc, l, sh);
-    double e[ND][ND], S[NV][ND];
-    cell_rel_coords<ND>(m, sX, maxn, l, sh, e);
-    simplex_normals<ND>(e, S);
-#pragma unroll
-    for (int v = 0; v < NR; ++v) {
-      double acc[ND];
-#pragma unroll
-      for (int d = 0; d < ND; ++d) acc[d] = 0.0;
-#pragma unroll
-      for (int k = 0; k < NV; ++k) {
-        const double w = sW[v * maxn + l[k]];
-#pragma unroll
-        for (int d = 0; d < ND; ++d) acc[d] += w * S[k][d];
+        for (int d = 0; d < ND; ++d) sX[d * maxn + q] = xx[d];
       }
 #pragma unroll
-      for (int d = 0; d < ND; ++d) sC[(v * ND + d) * maxc + lc] = acc[d];
+      for (int vv = 0; vv < FG; ++vv)
+        if (v0 + vv < NR) sW[vv * maxn + q] = w[vv];
     }
-  }
-  __syncthreads();
-  // components in chunks of JC to bound register use for many fields
-  constexpr int JC = NC <= 24 ? NC : 12;
-  for (int q = threadIdx.x; q < ns; q += blockDim.x) {
-    const SlotTopo st = slot_topo<NV>(m, tp, q);
-    const int sv = st.sv;
-    double coef = 0.0;
-    if (sv >= 0) coef = -(q == (int)threadIdx.x ? iv : m.inv_vol[sv]) / double(ND * NV);
-    for (int j0 = 0; j0 < NC; j0 += JC) {
-      double acc[JC];
+    if (v0 == 0) tile_store_inc<NV>(m, tp, sInc);
+    __syncthreads();
+    for (int lc = threadIdx.x; lc < nc; lc += blockDim.x) {
+      int l[NV];
+      uint32_t sh;
+      cell_topo<NV>(m, tp, lc, l, sh);
+      double e[ND][ND], S[NV][ND];
+      cell_rel_coords<ND>(m, sX, maxn, l, sh, e);
+      simplex_normals<ND>(e, S);
 #pragma unroll
-      for (int jj = 0; jj < JC; ++jj) acc[jj] = 0.0;
-      for (int p = st.p0; p < st.p1; ++p) {
-        const int lc = sInc[p] >> 2;
+      for (int vv = 0; vv < FG; ++vv) {
+        if (v0 + vv >= NR) break;
+        double acc[ND];
 #pragma unroll
-        for (int jj = 0; jj < JC; ++jj)
-          if (j0 + jj < NC) acc[jj] += sC[(j0 + jj) * maxc + lc];
+        for (int d = 0; d < ND; ++d) acc[d] = 0.0;
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+          const double w = sW[vv * maxn + l[k]];
+#pragma unroll
+          for (int d = 0; d < ND; ++d) acc[d] += w * S[k][d];
+        }
+#pragma unroll
+        for (int d = 0; d < ND; ++d) sC[(vv * ND + d) * maxc + lc] = acc[d];
       }
-      if (sv >= 0) {
+    }
+    __syncthreads();
+    // this group's components, in chunks of JC to bound register use
+    constexpr int NCG = FG * ND;
+    constexpr int JC = NCG <= 24 ? NCG : 12;
+    const int ncg = min(NR - v0, FG) * ND, j00 = v0 * ND;
+    for (int q = threadIdx.x; q < ns; q += blockDim.x) {
+      const SlotTopo st = slot_topo<NV>(m, tp, q);
+      const int sv = st.sv;
+      double coef = 0.0;
+      if (sv >= 0) coef = -(q == (int)threadIdx.x ? iv : m.inv_vol[sv]) / double(ND * NV);
+      for (int j0 = 0; j0 < ncg; j0 += JC) {
+        double acc[JC];
 #pragma unroll
-        for (int jj = 0; jj < JC; ++jj)
-          if (j0 + jj < NC) G[(size_t)(j0 + jj) * m.nn + sv] = coef * acc[jj];
-      } else {
+        for (int jj = 0; jj < JC; ++jj) acc[jj] = 0.0;
+        for (int p = st.p0; p < st.p1; ++p) {
+          const int lc = sInc[p] >> 2;
 #pragma unroll
-        for (int jj = 0; jj < JC; ++jj)
-          if (j0 + jj < NC) PG[(size_t)st.pos * NC + j0 + jj] = acc[jj];
+          for (int jj = 0; jj < JC; ++jj)
+            if (j0 + jj < ncg) acc[jj] += sC[(j0 + jj) * maxc + lc];
+        }
+        if (sv >= 0) {
+#pragma unroll
+          for (int jj = 0; jj < JC; ++jj)
+            if (j0 + jj < ncg) G[(size_t)(j00 + j0 + jj) * m.nn + sv] = coef * acc[jj];
+        } else {
+#pragma unroll
+          for (int jj = 0; jj < JC; ++jj)
+            if (j0 + jj < ncg) PG[(size_t)st.pos * NC + j00 + j0 + jj] = acc[jj];
+        }
       }
     }
   }
