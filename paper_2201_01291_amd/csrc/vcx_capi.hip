@@ -226,6 +226,14 @@ struct Impl {
     return sizeof(double) * ((size_t)(FG + ND) * maxn + (size_t)FG * ND * maxc) + inc_lds_bytes(NV, maxc);
   }
   static size_t lds_flux(int maxn, int maxc) {
+    if constexpr (MODEL == 2) {
+      // the vertex parts overlay the staged fields when the block has a
+      // thread per cell (tile_block covers up to 256 cells)
+      const size_t wg = ns_field_bytes(sizeof(CT) * (size_t)(NW + NGF * ND) * maxn);
+      const size_t r = sizeof(double) * (size_t)NV * NVAR * maxc;
+      return sizeof(double) * (size_t)ND * maxn + ns_area_bytes(wg, r, maxc <= 256) + slot_lds_bytes(maxn) +
+             inc_lds_bytes(NV, maxc);
+    }
     size_t dbl = sizeof(double) * ((size_t)ND * maxn + (size_t)NV * NVAR * maxc);
     size_t ct = MODEL == 0   ? (size_t)(NR + NR * ND) * maxn
                 : MODEL == 1 ? (size_t)(NSP + NSP * ND + ND) * maxn

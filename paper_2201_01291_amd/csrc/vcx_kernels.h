@@ -365,6 +365,14 @@ __host__ __device__ inline size_t inc_lds_bytes(int nv, int maxc) {
   return ((size_t)nv * maxc * sizeof(uint16_t) + 7) / 8 * 8;
 }
 
+// Multi-species flux pass: bytes of the staged fields and gradients
+// (rounded to doubles), and of that area together with the cells' vertex
+// parts, which overlay it when each thread holds one cell.
+__host__ __device__ inline size_t ns_field_bytes(size_t b) { return (b + 7) / 8 * 8; }
+__host__ __device__ inline size_t ns_area_bytes(size_t field_bytes, size_t part_bytes, bool overlay) {
+  return overlay ? (field_bytes > part_bytes ? field_bytes : part_bytes) : field_bytes + part_bytes;
+}
+
 // bytes of a tile's slot table in LDS
 __host__ __device__ inline size_t slot_lds_bytes(int maxn) { return (size_t)4 * maxn * sizeof(int); }
 
@@ -1622,11 +1630,17 @@ __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ W,
   TilePre<NV> tp;
   tile_prefetch<NV>(m, t, tp);
   const int maxn = m.max_tile_nodes, maxc = m.max_tile_cells;
+  // with one cell per thread, the cells' vertex parts overlay the staged
+  // fields and gradients once every edge flux is done
+  const bool overlay = maxc <= (int)blockDim.x;
   double* sX = lds;                                        // [ND][maxn]
-  double* sR = sX + ND * maxn;                             // [NV*NVAR][maxc]
-  CT* sW = reinterpret_cast<CT*>(sR + NV * NVAR * maxc);   // [NR + NP + NA][maxn]
+  char* area = reinterpret_cast<char*>(sX + ND * maxn);
+  CT* sW = reinterpret_cast<CT*>(area);                    // [NR + NP + NA][maxn]
   CT* sG = sW + (NR + NP + NA) * maxn;                     // [NG*ND][maxn]
-  int* sSl = reinterpret_cast<int*>(sG + NG * ND * maxn);
+  const size_t wgb = ns_field_bytes(sizeof(CT) * (size_t)(NR + NP + NA + NG * ND) * maxn);
+  const size_t rb = sizeof(double) * (size_t)NV * NVAR * maxc;
+  double* sR = reinterpret_cast<double*>(overlay ? area : area + wgb);  // [NV*NVAR][maxc]
+  int* sSl = reinterpret_cast<int*>(area + ns_area_bytes(wgb, rb, overlay));
   uint16_t* sInc = reinterpret_cast<uint16_t*>(sSl + 4 * maxn);
   const int nc = tp.nc, ns = tp.ns;
   for (int q = threadIdx.x; q < ns; q += blockDim.x) {
@@ -1654,6 +1668,7 @@ __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ W,
   tile_store_inc<NV>(m, tp, sInc);
   __syncthreads();
   const CT beta = CT(gp.beta);
+  double acc[NV][NVAR];
   for (int lc = threadIdx.x; lc < nc; lc += blockDim.x) {
     int l[NV];
     uint32_t sh;
@@ -1661,7 +1676,6 @@ __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ W,
     double e[ND][ND], Sd[NV][ND];
     cell_rel_coords<ND>(m, sX, maxn, l, sh, e);
     simplex_normals<ND>(e, Sd);
-    double acc[NV][NVAR];
 #pragma unroll
     for (int k = 0; k < NV; ++k)
 #pragma unroll
@@ -1721,10 +1735,22 @@ __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ W,
         for (int k = 0; k < NV; ++k) acc[k][v] = fma(fv, g.coef[k], acc[k][v]);
       }
     }
+    if (!overlay) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k)
+      for (int k = 0; k < NV; ++k)
 #pragma unroll
-      for (int v = 0; v < NVAR; ++v) sR[(k * NVAR + v) * maxc + lc] = acc[k][v];
+        for (int v = 0; v < NVAR; ++v) sR[(k * NVAR + v) * maxc + lc] = acc[k][v];
+    }
+  }
+  if (overlay) {
+    __syncthreads();  // every edge flux has read the staged fields
+    const int lc = threadIdx.x;
+    if (lc < nc) {
+#pragma unroll
+      for (int k = 0; k < NV; ++k)
+#pragma unroll
+        for (int v = 0; v < NVAR; ++v) sR[(k * NVAR + v) * maxc + lc] = acc[k][v];
+    }
   }
   __syncthreads();
   double cand = INFINITY;
