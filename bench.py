@@ -114,9 +114,9 @@ def workload(name):
                             "2 charged species, LLW-minmod + central diffusion, RK1",
                    cells=m.ncells, nodes=m.nnodes, faces=m.nfaces, species=2,
                    residuals_per_step=1)
-        # algorithmic bytes of the fused gradient + flux pass, every array once
-        # ("Roofline"): reads U, x, E, 1/V, dx_min per node and the
-        # cell topology (3 x u16 local vertices + u32 periodic code), writes U
+        # algorithmic bytes of the fused gradient + flux pass, every array
+        # once: reads U, x, E, 1/V, dx_min per node and the cell topology
+        # (3 x u16 local vertices + u32 periodic code), writes U
         N, M = m.nnodes, m.ncells
         ns, nd = 2, 2
         bytes_flux = N * 8 * (ns + nd + nd + 1 + 1 + ns) + M * (3 * 2 + 4)
@@ -416,8 +416,8 @@ def size_sweep(a, stream):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not "
-                                   "supported (see DESIGN.md, 'Sharding')", "n_gpus": a.gpus}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only; runs on several GPUs are "
+                                   "not supported (the library has no multi-GPU path)", "n_gpus": a.gpus}))
         sys.exit(2)
     import torch
     from paper_2201_01291_amd import vcx
