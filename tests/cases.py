@@ -116,13 +116,22 @@ def make_case(name: str) -> Case:
         U = wl.ns_state(m, mix, lattice=3, seed=9, vel=(30.0, -10.0))
         return Case(name, m, U, None, dict(model="ns", flux="hllc", limiter="minmod", rk=3,
                                            nspecies=2, mixture=mix))
+    if name == "ns2d-sp2-bigtile":
+        # tiles of more cells than a block has threads: the multi-species
+        # flux pass keeps the cells' vertex parts apart from the staged fields
+        mix = wl.synthetic_mixture(2, seed=6)
+        mix.mu_ref = 2e-3
+        m = wl.tri_rect_mesh(24, 17, 0.012, 0.009, jitter=0.2, seed=21)
+        U = wl.ns_state(m, mix, lattice=3, seed=10, vel=(20.0, 15.0))
+        return Case(name, m, U, None, dict(model="ns", flux="hllc", limiter="vanleer", rk=2,
+                                           nspecies=2, mixture=mix), tiles=(320, 200))
     raise KeyError(name)
 
 
 CASE_NAMES = ["dd2d-streamer", "dd2d-diel", "dd2d-open-vanleer", "dd2d-open-closure2",
               "euler2d-open-closure2", "dd3d-sweby", "sod-hllc", "euler2d-roe-sp2",
               "euler3d-roe", "euler3d-hllc-open-sp2", "euler3d-hllc-sp9", "ns3d-sp9",
-              "ns2d-sp2-open"]
+              "ns2d-sp2-open", "ns2d-sp2-bigtile"]
 
 
 def reconstructed(case: Case) -> np.ndarray:
