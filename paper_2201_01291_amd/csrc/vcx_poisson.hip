@@ -52,8 +52,10 @@ vcx_status err(vcx_status s, const std::string& m) { return vcx::set_error(s, m.
 
 struct PoissonDev {
   int n, nd, nnz, singular;
-  int agg;              // nodes per aggregate (a multiple of kThreads); block b owns aggregate b
-  int nc;               // aggregates = blocks of the CG kernels
+  int agg;              // nodes per aggregate: 64, 128 or a multiple of kThreads
+  int nc;               // aggregates
+  int rpb;              // rows per block, max(agg, kThreads): whole aggregates
+  int nb;               // blocks of the solver kernels (one partial sum each)
   const int* rp;        // [n+1]
   const int* col;       // [nnz]
   const double* val;    // [nnz] matrix of -lap phi over the nodal volumes
@@ -134,10 +136,30 @@ __device__ void put_partial(double* row, double v) {
   if (threadIdx.x == 0) row[blockIdx.x] = s;
 }
 
-// Rows of this block's aggregate: [i0, i1)
+// Rows of this block: [i0, i1), whole aggregates
 __device__ inline void agg_rows(const PoissonDev& P, int& i0, int& i1) {
-  i0 = blockIdx.x * P.agg;
-  i1 = min(P.n, i0 + P.agg);
+  i0 = blockIdx.x * P.rpb;
+  i1 = min(P.n, i0 + P.rpb);
+}
+
+// Restriction g = R r of this block's aggregates from each thread's sum v
+// of r over its rows: one block sum (an aggregate of kThreads rows or more),
+// or a fixed-order tree per aggregate of agg consecutive threads (each
+// thread then holds one row).
+__device__ void put_restriction(const PoissonDev& P, double* g, double v) {
+  __shared__ double red[kThreads];
+  const int seg = min(P.agg, kThreads), t = threadIdx.x;
+  red[t] = v;
+  __syncthreads();
+  for (int s = seg / 2; s > 0; s >>= 1) {
+    if (t % seg < s) red[t] += red[t + s];
+    __syncthreads();
+  }
+  if (t % seg == 0) {
+    const int a = P.agg >= kThreads ? (int)blockIdx.x : (int)((blockIdx.x * kThreads + t) / P.agg);
+    if (a < P.nc) g[a] = red[t];
+  }
+  __syncthreads();
 }
 
 // Preconditioned residual of node j: z = D^-1 r + c_(aggregate of j) on free
@@ -171,8 +193,8 @@ __global__ void __launch_bounds__(kThreads) k_cg_init1(PoissonDev P, CgVec X, co
     sb += b;
     sv += P.vn[i];
   }
-  put_partial(X.part + P_B * P.nc, sb);
-  put_partial(X.part + P_V * P.nc, sv);
+  put_partial(X.part + P_B * P.nb, sb);
+  put_partial(X.part + P_V * P.nb, sv);
 }
 
 // Singular systems: the uniform background that makes b sum to zero.
@@ -180,7 +202,7 @@ __global__ void __launch_bounds__(kThreads) k_cg_init1(PoissonDev P, CgVec X, co
 // r.r and |b - L_fD x_D|^2 (the norm the tolerance refers to), and g = R r.
 __global__ void __launch_bounds__(kThreads) k_cg_init2(PoissonDev P, CgVec X) {
   double bmean = 0.0;
-  if (P.singular) bmean = sum_partials(X.part + P_B * P.nc, P.nc) / sum_partials(X.part + P_V * P.nc, P.nc);
+  if (P.singular) bmean = sum_partials(X.part + P_B * P.nb, P.nb) / sum_partials(X.part + P_V * P.nb, P.nb);
   int i0, i1;
   agg_rows(P, i0, i1);
   double drr = 0.0, rr = 0.0, bb = 0.0, gs = 0.0;
@@ -211,25 +233,48 @@ __global__ void __launch_bounds__(kThreads) k_cg_init2(PoissonDev P, CgVec X) {
     rr += r * r;
     gs += r;
   }
-  put_partial(X.part + P_DRR0 * P.nc, drr);
-  put_partial(X.part + P_RR0 * P.nc, rr);
-  put_partial(X.part + P_RRI * P.nc, rr);
-  put_partial(X.part + P_BB * P.nc, bb);
-  const double g = block_sum(gs);
-  if (threadIdx.x == 0) X.g[blockIdx.x] = g;
+  put_partial(X.part + P_DRR0 * P.nb, drr);
+  put_partial(X.part + P_RR0 * P.nb, rr);
+  put_partial(X.part + P_RRI * P.nb, rr);
+  put_partial(X.part + P_BB * P.nb, bb);
+  put_restriction(P, X.g, gs);
 }
 
-// Coarse correction of iterate k: c_b = (A_c^-1 g)_b for this block's
-// aggregate, and the coarse part g_b c_b of r.z.
+// Coarse correction of iterate k: c_a = (A_c^-1 g)_a for this block's
+// aggregates, and their coarse part sum g_a c_a of r.z.
 __global__ void __launch_bounds__(kThreads) k_cg_c(PoissonDev P, CgVec X) {
   if (block_done(X.ctl)) return;
-  const double* row = P.ainv + (size_t)blockIdx.x * P.nc;
-  double s = 0.0;
-  for (int a = threadIdx.x; a < P.nc; a += kThreads) s += row[a] * X.g[a];
-  const double cb = block_sum(s);
+  const int per = P.rpb / P.agg, a0 = blockIdx.x * per, a1 = min(P.nc, a0 + per);
+  if (per == 1) {
+    const double* row = P.ainv + (size_t)a0 * P.nc;
+    double s = 0.0;
+    for (int j = threadIdx.x; j < P.nc; j += kThreads) s += row[j] * X.g[j];
+    const double ca = block_sum(s);
+    if (threadIdx.x == 0) {
+      X.c[a0] = ca;
+      X.part[P_GC * P.nb + blockIdx.x] = X.g[a0] * ca;
+    }
+    return;
+  }
+  // several aggregates per block (at most one per wavefront): one wavefront
+  // each, lanes over the row, a fixed butterfly of shuffles
+  __shared__ double cw[kThreads / 64];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, a = a0 + w;
+  if (a < a1) {
+    const double* row = P.ainv + (size_t)a * P.nc;
+    double v = 0.0;
+    for (int j = lane; j < P.nc; j += 64) v += row[j] * X.g[j];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) {
+      X.c[a] = v;
+      cw[w] = v;
+    }
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
-    X.c[blockIdx.x] = cb;
-    X.part[P_GC * P.nc + blockIdx.x] = X.g[blockIdx.x] * cb;
+    double gc = 0.0;
+    for (int b = a0; b < a1; ++b) gc += X.g[b] * cw[b - a0];
+    X.part[P_GC * P.nb + blockIdx.x] = gc;
   }
 }
 
@@ -240,13 +285,13 @@ __global__ void __launch_bounds__(kThreads) k_cg_c(PoissonDev P, CgVec X) {
 __global__ void __launch_bounds__(kThreads) k_cg_a(PoissonDev P, CgVec X, int k, double tol2) {
   if (block_done(X.ctl)) return;
   const int cur = k & 1;
-  const double rr = sum_partials(X.part + (P_RR0 + cur) * P.nc, P.nc);
+  const double rr = sum_partials(X.part + (P_RR0 + cur) * P.nb, P.nb);
   // relative to |b - L_fD x_D| (the free system's right-hand side), or to
   // the initial residual when that is zero
-  const double bb = sum_partials(X.part + P_BB * P.nc, P.nc);
-  const double ref2 = bb > 0.0 ? bb : sum_partials(X.part + P_RRI * P.nc, P.nc);
+  const double bb = sum_partials(X.part + P_BB * P.nb, P.nb);
+  const double ref2 = bb > 0.0 ? bb : sum_partials(X.part + P_RRI * P.nb, P.nb);
   const bool conv = !(rr > tol2 * ref2);  // also stops on rr = 0
-  const double rz = sum_partials(X.part + (P_DRR0 + cur) * P.nc, P.nc) + sum_partials(X.part + P_GC * P.nc, P.nc);
+  const double rz = sum_partials(X.part + (P_DRR0 + cur) * P.nb, P.nb) + sum_partials(X.part + P_GC * P.nb, P.nb);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     X.ctl->last = k;
     X.ctl->rr = rr;
@@ -277,7 +322,7 @@ __global__ void __launch_bounds__(kThreads) k_cg_a(PoissonDev P, CgVec X, int k,
     X.q[i] = qv;
     pq += p * qv;
   }
-  put_partial(X.part + P_PQ * P.nc, pq);
+  put_partial(X.part + P_PQ * P.nb, pq);
 }
 
 // Iteration k, second half: alpha = (r.z)_k / (p.q); x += alpha p,
@@ -286,7 +331,7 @@ __global__ void __launch_bounds__(kThreads) k_cg_a(PoissonDev P, CgVec X, int k,
 __global__ void __launch_bounds__(kThreads) k_cg_b(PoissonDev P, CgVec X, int k) {
   if (block_done(X.ctl)) return;
   const int cur = k & 1, nxt = cur ^ 1;
-  const double alpha = X.ctl->rz[cur] / sum_partials(X.part + P_PQ * P.nc, P.nc);
+  const double alpha = X.ctl->rz[cur] / sum_partials(X.part + P_PQ * P.nb, P.nb);
   const double* pn = cur ? X.p0 : X.p1;
   int i0, i1;
   agg_rows(P, i0, i1);
@@ -301,10 +346,9 @@ __global__ void __launch_bounds__(kThreads) k_cg_b(PoissonDev P, CgVec X, int k)
     rr += r * r;
     gs += r;
   }
-  put_partial(X.part + (P_DRR0 + nxt) * P.nc, drr);
-  put_partial(X.part + (P_RR0 + nxt) * P.nc, rr);
-  const double g = block_sum(gs);
-  if (threadIdx.x == 0) X.g[blockIdx.x] = g;
+  put_partial(X.part + (P_DRR0 + nxt) * P.nb, drr);
+  put_partial(X.part + (P_RR0 + nxt) * P.nb, rr);
+  put_restriction(P, X.g, gs);
 }
 
 // ---- BiCGStab (non-symmetric operators of axisymmetric meshes), Jacobi
@@ -314,7 +358,7 @@ __global__ void __launch_bounds__(kThreads) k_cg_b(PoissonDev P, CgVec X, int k)
 // 0; partial sums of r^.r, r.r and |b - L_fD x_D|^2.
 __global__ void __launch_bounds__(kThreads) k_bi_init2(PoissonDev P, CgVec X) {
   double bmean = 0.0;
-  if (P.singular) bmean = sum_partials(X.part + P_B * P.nc, P.nc) / sum_partials(X.part + P_V * P.nc, P.nc);
+  if (P.singular) bmean = sum_partials(X.part + P_B * P.nb, P.nb) / sum_partials(X.part + P_V * P.nb, P.nb);
   int i0, i1;
   agg_rows(P, i0, i1);
   double rr = 0.0, bb = 0.0;
@@ -343,10 +387,10 @@ __global__ void __launch_bounds__(kThreads) k_bi_init2(PoissonDev P, CgVec X) {
     X.v0[i] = X.v1[i] = 0.0;
     rr += r * r;
   }
-  put_partial(X.part + P_RHO0 * P.nc, rr);
-  put_partial(X.part + P_RR0 * P.nc, rr);
-  put_partial(X.part + P_RRI * P.nc, rr);
-  put_partial(X.part + P_BB * P.nc, bb);
+  put_partial(X.part + P_RHO0 * P.nb, rr);
+  put_partial(X.part + P_RR0 * P.nb, rr);
+  put_partial(X.part + P_RRI * P.nb, rr);
+  put_partial(X.part + P_BB * P.nb, bb);
 }
 
 // Iteration k, part 1: stop test on r_k; beta = (rho_k/rho_(k-1))
@@ -356,10 +400,10 @@ __global__ void __launch_bounds__(kThreads) k_bi_init2(PoissonDev P, CgVec X) {
 __global__ void __launch_bounds__(kThreads) k_bi_a(PoissonDev P, CgVec X, int k, double tol2) {
   if (block_done(X.ctl)) return;
   const int cur = k & 1;
-  const double rr = sum_partials(X.part + (P_RR0 + cur) * P.nc, P.nc);
-  const double bb = sum_partials(X.part + P_BB * P.nc, P.nc);
-  const double ref2 = bb > 0.0 ? bb : sum_partials(X.part + P_RRI * P.nc, P.nc);
-  const double rho = sum_partials(X.part + (P_RHO0 + cur) * P.nc, P.nc);
+  const double rr = sum_partials(X.part + (P_RR0 + cur) * P.nb, P.nb);
+  const double bb = sum_partials(X.part + P_BB * P.nb, P.nb);
+  const double ref2 = bb > 0.0 ? bb : sum_partials(X.part + P_RRI * P.nb, P.nb);
+  const double rho = sum_partials(X.part + (P_RHO0 + cur) * P.nb, P.nb);
   // converged, or a breakdown (r^.r = 0, or omega = 0 with r != 0)
   const bool conv = !(rr > tol2 * ref2) || rho == 0.0 || (k > 0 && X.ctl->omega == 0.0);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -399,7 +443,7 @@ __global__ void __launch_bounds__(kThreads) k_bi_a(PoissonDev P, CgVec X, int k,
     vn[i] = v;
     rv += X.rh[i] * v;
   }
-  put_partial(X.part + P_RV * P.nc, rv);
+  put_partial(X.part + P_RV * P.nb, rv);
 }
 
 // Iteration k, part 2: alpha = rho_k / r^.v_k; s = r - alpha v_k;
@@ -407,7 +451,7 @@ __global__ void __launch_bounds__(kThreads) k_bi_a(PoissonDev P, CgVec X, int k,
 __global__ void __launch_bounds__(kThreads) k_bi_b(PoissonDev P, CgVec X, int k) {
   if (block_done(X.ctl)) return;
   const int cur = k & 1;
-  const double rv = sum_partials(X.part + P_RV * P.nc, P.nc);
+  const double rv = sum_partials(X.part + P_RV * P.nb, P.nb);
   if (rv == 0.0) {  // breakdown: stop at the current iterate
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       X.ctl->iters = k;
@@ -434,8 +478,8 @@ __global__ void __launch_bounds__(kThreads) k_bi_b(PoissonDev P, CgVec X, int k)
     ts += t * sv;
     tt += t * t;
   }
-  put_partial(X.part + P_TS * P.nc, ts);
-  put_partial(X.part + P_TT * P.nc, tt);
+  put_partial(X.part + P_TS * P.nb, ts);
+  put_partial(X.part + P_TT * P.nb, tt);
 }
 
 // Iteration k, part 3: omega = t.s / t.t; x += alpha p^ + omega s^;
@@ -443,8 +487,8 @@ __global__ void __launch_bounds__(kThreads) k_bi_b(PoissonDev P, CgVec X, int k)
 __global__ void __launch_bounds__(kThreads) k_bi_c(PoissonDev P, CgVec X, int k) {
   if (block_done(X.ctl)) return;
   const int cur = k & 1, nxt = cur ^ 1;
-  const double tt = sum_partials(X.part + P_TT * P.nc, P.nc);
-  const double om = tt > 0.0 ? sum_partials(X.part + P_TS * P.nc, P.nc) / tt : 0.0;
+  const double tt = sum_partials(X.part + P_TT * P.nb, P.nb);
+  const double om = tt > 0.0 ? sum_partials(X.part + P_TS * P.nb, P.nb) / tt : 0.0;
   if (blockIdx.x == 0 && threadIdx.x == 0) X.ctl->omega = om;
   const double alpha = X.ctl->alpha;
   const double* pn = cur ? X.p0 : X.p1;
@@ -462,8 +506,8 @@ __global__ void __launch_bounds__(kThreads) k_bi_c(PoissonDev P, CgVec X, int k)
     rho += X.rh[i] * r;
     rr += r * r;
   }
-  put_partial(X.part + (P_RHO0 + nxt) * P.nc, rho);
-  put_partial(X.part + (P_RR0 + nxt) * P.nc, rr);
+  put_partial(X.part + (P_RHO0 + nxt) * P.nb, rho);
+  put_partial(X.part + (P_RR0 + nxt) * P.nb, rr);
 }
 
 // Singular systems: phi with zero volume mean.
@@ -472,11 +516,11 @@ __global__ void __launch_bounds__(kThreads) k_cg_mean1(PoissonDev P, CgVec X) {
   agg_rows(P, i0, i1);
   double s = 0.0;
   for (int i = i0 + threadIdx.x; i < i1; i += kThreads) s += P.vn[i] * X.x[i];
-  put_partial(X.part + P_VX * P.nc, s);
+  put_partial(X.part + P_VX * P.nb, s);
 }
 
 __global__ void __launch_bounds__(kThreads) k_cg_mean2(PoissonDev P, CgVec X) {
-  const double m = sum_partials(X.part + P_VX * P.nc, P.nc) / sum_partials(X.part + P_V * P.nc, P.nc);
+  const double m = sum_partials(X.part + P_VX * P.nb, P.nb) / sum_partials(X.part + P_V * P.nb, P.nb);
   int i0, i1;
   agg_rows(P, i0, i1);
   for (int i = i0 + threadIdx.x; i < i1; i += kThreads) X.x[i] -= m;
@@ -568,28 +612,33 @@ bool spd_inverse(std::vector<double>& A, int n) {
       L[(size_t)i * n + j] = v / ljj;
     }
   }
-  // M = L^-1 (lower triangular), column by column
-  std::vector<double> M((size_t)n * n, 0.0);
+  // M = L^-1 (lower triangular), column by column; stored transposed,
+  // Mt[c][i] = M[i][c], so that every inner loop runs over contiguous memory
+  std::vector<double> Mt((size_t)n * n, 0.0);
   for (int c = 0; c < n; ++c) {
-    M[(size_t)c * n + c] = 1.0 / L[(size_t)c * n + c];
+    double* mc = &Mt[(size_t)c * n];
+    mc[c] = 1.0 / L[(size_t)c * n + c];
     for (int i = c + 1; i < n; ++i) {
+      const double* li = &L[(size_t)i * n];
       double v = 0.0;
-      for (int k = c; k < i; ++k) v -= L[(size_t)i * n + k] * M[(size_t)k * n + c];
-      M[(size_t)i * n + c] = v / L[(size_t)i * n + i];
+      for (int k = c; k < i; ++k) v -= li[k] * mc[k];
+      mc[i] = v / li[i];
     }
   }
-  // A^-1 = M^T M
+  // A^-1 = M^T M: (i, j) is the product of columns i and j of M
   for (int i = 0; i < n; ++i)
     for (int j = 0; j <= i; ++j) {
+      const double* mi = &Mt[(size_t)i * n];
+      const double* mj = &Mt[(size_t)j * n];
       double v = 0.0;
-      for (int k = i; k < n; ++k) v += M[(size_t)k * n + i] * M[(size_t)k * n + j];
+      for (int k = i; k < n; ++k) v += mi[k] * mj[k];
       A[(size_t)i * n + j] = v;
       A[(size_t)j * n + i] = v;
     }
   return true;
 }
 
-constexpr int kMaxCoarse = 1024;
+constexpr int kMaxCoarse = 2048;
 
 }  // namespace
 
@@ -758,12 +807,15 @@ extern "C" vcx_status vcx_poisson_create(vcx_mesh mesh, const int32_t* dirichlet
   chk(upload(p, dinv, &P.dinv));
   chk(upload(p, h.vupd, &P.vn));  // revolved volumes on axisymmetric meshes
   chk(upload(p, sbm, &P.sbm));
-  // aggregates: consecutive nodes of the space-filling curve, a multiple of
-  // the block size each, at most kMaxCoarse of them; coarse operator
-  // A_c = R L R^T over free nodes, inverted densely on the host
+  // aggregates: runs of 64, 128 or a multiple of kThreads consecutive nodes
+  // of the space-filling curve, at most kMaxCoarse of them (a block holds
+  // whole aggregates); coarse operator A_c = R L R^T over free nodes,
+  // inverted densely on the host
   const int64_t per = (n + kMaxCoarse - 1) / kMaxCoarse;
-  P.agg = (int)(((per + kThreads - 1) / kThreads) * kThreads);
+  P.agg = per <= 64 ? 64 : per <= 128 ? 128 : (int)(((per + kThreads - 1) / kThreads) * kThreads);
   P.nc = (int)((n + P.agg - 1) / P.agg);
+  P.rpb = std::max(P.agg, kThreads);
+  P.nb = (int)((n + P.rpb - 1) / P.rpb);
   const int ncg = P.nc;
   p->bicg = h.axi;
   // the coarse space serves the symmetric operator (conjugate gradients);
@@ -803,7 +855,7 @@ extern "C" vcx_status vcx_poisson_create(vcx_mesh mesh, const int32_t* dirichlet
   X.g = static_cast<double*>(d);
   chk(dev_alloc(p, sizeof(double) * ncg, &d));
   X.c = static_cast<double*>(d);
-  chk(dev_alloc(p, sizeof(double) * P_NROWS * (size_t)ncg, &d));
+  chk(dev_alloc(p, sizeof(double) * P_NROWS * (size_t)P.nb, &d));
   X.part = static_cast<double*>(d);
   chk(dev_alloc(p, sizeof(CgCtl), &d));
   X.ctl = static_cast<CgCtl*>(d);
@@ -854,7 +906,7 @@ extern "C" vcx_status vcx_poisson_solve(vcx_poisson p, const double* q, const do
   if (st == VCX_OK) st = stage_in(p, En, 2, is_device, &dE);
   if (st == VCX_OK) st = stage_in(p, phi, 3, is_device, &d0);
   if (st != VCX_OK) return st;
-  const dim3 grid(p->P.nc), block(kThreads);
+  const dim3 grid(p->P.nb), block(kThreads);
   PS_HIP(hipMemsetAsync(p->X.ctl, 0, sizeof(CgCtl), p->stream));
   hipLaunchKernelGGL(k_cg_init1, grid, block, 0, p->stream, p->P, p->X, dq, dD, dE, d0);
   if (p->bicg)
