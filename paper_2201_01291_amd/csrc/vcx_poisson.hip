@@ -100,15 +100,22 @@ struct CgVec {
   CgCtl* ctl;
 };
 
+// Sum over a wavefront: a fixed butterfly of shuffles (every lane ends with
+// the same value).
+__device__ inline double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum over the block: wavefront sums, then the wavefronts in order.  The
+// same arithmetic in every block and every thread.
 __device__ double block_sum(double v) {
-  __shared__ double red[kThreads];
-  red[threadIdx.x] = v;
+  __shared__ double wsum[kThreads / 64];
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int s = kThreads / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
-  }
-  const double out = red[0];
+  double out = wsum[0];
+  for (int w = 1; w < kThreads / 64; ++w) out += wsum[w];
   __syncthreads();
   return out;
 }
@@ -144,20 +151,22 @@ __device__ inline void agg_rows(const PoissonDev& P, int& i0, int& i1) {
 
 // Restriction g = R r of this block's aggregates from each thread's sum v
 // of r over its rows: one block sum (an aggregate of kThreads rows or more),
-// or a fixed-order tree per aggregate of agg consecutive threads (each
-// thread then holds one row).
+// or the sum over the agg consecutive threads of each aggregate (each
+// thread then holds one row), from the wavefront sums in order.
 __device__ void put_restriction(const PoissonDev& P, double* g, double v) {
-  __shared__ double red[kThreads];
-  const int seg = min(P.agg, kThreads), t = threadIdx.x;
-  red[t] = v;
+  __shared__ double wsum[kThreads / 64];
+  constexpr int NW = kThreads / 64;
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int s = seg / 2; s > 0; s >>= 1) {
-    if (t % seg < s) red[t] += red[t + s];
-    __syncthreads();
-  }
-  if (t % seg == 0) {
-    const int a = P.agg >= kThreads ? (int)blockIdx.x : (int)((blockIdx.x * kThreads + t) / P.agg);
-    if (a < P.nc) g[a] = red[t];
+  // wavefronts per aggregate: 1 (64 nodes), 2 (128) or all of the block
+  const int wpa = min(P.agg, kThreads) / 64;
+  const int t = threadIdx.x;
+  if (t < NW / wpa) {
+    double s = wsum[t * wpa];
+    for (int w = 1; w < wpa; ++w) s += wsum[t * wpa + w];
+    const int a = P.agg >= kThreads ? (int)blockIdx.x : (int)(blockIdx.x * (kThreads / P.agg) + t);
+    if (a < P.nc) g[a] = s;
   }
   __syncthreads();
 }
@@ -264,7 +273,7 @@ __global__ void __launch_bounds__(kThreads) k_cg_c(PoissonDev P, CgVec X) {
     const double* row = P.ainv + (size_t)a * P.nc;
     double v = 0.0;
     for (int j = lane; j < P.nc; j += 64) v += row[j] * X.g[j];
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    v = wave_sum(v);
     if (lane == 0) {
       X.c[a] = v;
       cw[w] = v;
