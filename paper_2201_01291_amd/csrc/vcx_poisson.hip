@@ -120,6 +120,31 @@ __device__ double block_sum(double v) {
   return out;
 }
 
+// Sums of N rows of block partials at once (the loads of all rows in
+// flight together), each in the order of sum_partials.
+template <int N>
+__device__ void sum_partials_n(const double* const (&rows)[N], int nb, double (&out)[N]) {
+  __shared__ double wsum[N][kThreads / 64];
+  double v[N];
+#pragma unroll
+  for (int q = 0; q < N; ++q) v[q] = 0.0;
+  for (int k = threadIdx.x; k < nb; k += kThreads)
+#pragma unroll
+    for (int q = 0; q < N; ++q) v[q] += rows[q][k];
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    v[q] = wave_sum(v[q]);
+    if ((threadIdx.x & 63) == 0) wsum[q][threadIdx.x >> 6] = v[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    out[q] = wsum[q][0];
+    for (int w = 1; w < kThreads / 64; ++w) out[q] += wsum[q][w];
+  }
+  __syncthreads();
+}
+
 // Sum of one row of block partials in a fixed order (same in every block).
 __device__ double sum_partials(const double* row, int nb) {
   double s = 0.0;
@@ -294,13 +319,17 @@ __global__ void __launch_bounds__(kThreads) k_cg_c(PoissonDev P, CgVec X) {
 __global__ void __launch_bounds__(kThreads) k_cg_a(PoissonDev P, CgVec X, int k, double tol2) {
   if (block_done(X.ctl)) return;
   const int cur = k & 1;
-  const double rr = sum_partials(X.part + (P_RR0 + cur) * P.nb, P.nb);
+  const double* const rows[5] = {X.part + (P_RR0 + cur) * P.nb, X.part + P_BB * P.nb, X.part + P_RRI * P.nb,
+                                  X.part + (P_DRR0 + cur) * P.nb, X.part + P_GC * P.nb};
+  double sums[5];
+  sum_partials_n<5>(rows, P.nb, sums);
+  const double rr = sums[0];
   // relative to |b - L_fD x_D| (the free system's right-hand side), or to
   // the initial residual when that is zero
-  const double bb = sum_partials(X.part + P_BB * P.nb, P.nb);
-  const double ref2 = bb > 0.0 ? bb : sum_partials(X.part + P_RRI * P.nb, P.nb);
+  const double bb = sums[1];
+  const double ref2 = bb > 0.0 ? bb : sums[2];
   const bool conv = !(rr > tol2 * ref2);  // also stops on rr = 0
-  const double rz = sum_partials(X.part + (P_DRR0 + cur) * P.nb, P.nb) + sum_partials(X.part + P_GC * P.nb, P.nb);
+  const double rz = sums[3] + sums[4];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     X.ctl->last = k;
     X.ctl->rr = rr;
