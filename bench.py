@@ -87,6 +87,8 @@ def parse():
                          "timed after the main run, e.g. 1200x750,2400x1500")
     ap.add_argument("--sweep-only", action="store_true", help="run the size sweep only")
     ap.add_argument("--no-poisson", action="store_true", help="skip the Poisson leg")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time the candidate tile sizes when the tuning cache has no entry")
     ap.add_argument("--serve-load", type=float, default=0.8,
                     help="arrival rate as a fraction of the measured batched capacity")
     return ap.parse_args()
@@ -432,7 +434,20 @@ def main():
     print(f"[bench] building workload {a.workload}", file=sys.stderr, flush=True)
     m, U0, E, phys, ophys, cfg, alg = workload(a.workload)
     primary = cfg.pop("primary", "fp64")    # precision of the reported value
-    tiles = tuple(int(v) for v in a.tiles.split(",")) if a.tiles else cfg.get("tiles", (0, 0))
+    # tile size: the command line, else the autotuner's cached choice for the
+    # primary precision (tuned now with --autotune when none is cached), else
+    # the workload's default
+    if a.tiles:
+        tiles, tile_src = tuple(int(v) for v in a.tiles.split(",")), "command line"
+    else:
+        from paper_2201_01291_amd import autotune
+        prim = phys(vcx.PREC_MIXED if primary == "mixed" else vcx.PREC_FP64)
+        tc, tn, tile_src = autotune.pick_tiles(m, prim, U0, E, tune_if_missing=a.autotune)
+        tiles = (tc, tn) if tile_src != "default" else tuple(cfg.get("tiles", (0, 0)))
+        if tile_src == "default":
+            tile_src = "workload default"
+    cfg["tiles"] = list(tiles)
+    cfg["tiles_from"] = tile_src
     stream = torch.cuda.current_stream()
     gm = vcx.Mesh(m, stream=stream.cuda_stream, tile_cells=tiles[0], tile_nodes=tiles[1])
     info = gm.info()
