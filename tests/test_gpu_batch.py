@@ -146,3 +146,33 @@ def test_batch_argument_errors():
         assert e.value.code == vcx.E_ARG
     with pytest.raises(vcx.VcxError):
         vcx.solve_batch([], [])
+
+
+def test_batch_members_with_different_tile_sizes_match_alone():
+    """Meshes partitioned with different tile sizes (as the autotuner may pick
+    per mesh) in one batch: the launch takes the largest block and LDS, and
+    each member still gets the bits of its own solve."""
+    import cases
+    tiles = [(128, 96), (256, 192), (384, 288)]
+    cs = [_dd_case(40, 25, 11), _dd_case(33, 21, 12), _dd_case(52, 37, 13)]
+    g3 = make_case("euler3d-roe")
+    print("[batch] dd members with tiles", tiles, flush=True)
+    runs = []
+    for c, t in zip(cs, tiles):
+        c = cases.Case(c.name, c.mesh, c.U, c.E, c.scheme, tiles=t)
+        runs.append((c, _alone(c, 5)))
+    keep = [_solver(c) for c, _ in runs]
+    ss = [s for _, s in keep]
+    vcx.solve_batch(ss, [5] * len(ss))
+    for s, (_, (U, tt, n)) in zip(ss, runs):
+        assert s.steps_done() == n == 5 and s.time() == tt
+        assert np.array_equal(s.download(), U)
+    print("[batch] euler3d members with tiles (64, 48) and (128, 96)", flush=True)
+    gs = [cases.Case(g3.name, g3.mesh, g3.U, g3.E, g3.scheme, tiles=t) for t in ((64, 48), (128, 96))]
+    ref = [_alone(c, 3) for c in gs]
+    keep = [_solver(c) for c in gs]
+    ss = [s for _, s in keep]
+    vcx.solve_batch(ss, [3, 3])
+    for s, (U, tt, n) in zip(ss, ref):
+        assert s.steps_done() == n == 3 and s.time() == tt
+        assert np.array_equal(s.download(), U)
