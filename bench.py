@@ -12,6 +12,11 @@ One step = CFL time step + nodal gradients + cell-edge fluxes with the
 deterministic gather + update, all on the GPU.  Metric: Mfaces/s = cell-edge
 fluxes per residual evaluation x residual evaluations per second / 1e6.
 
+The tile size of the mesh is the autotuner's cached choice for the
+workload and primary precision (paper_2201_01291_amd/tune_cache.json;
+--autotune times the candidates when the cache has no entry, --tiles
+overrides it); config.tiles and config.tiles_from say which was used.
+
 Prints ONE JSON line.  Extra fields: algorithmic GB/s of the whole step,
 p50/p99 single-step latency of the FP64 path and of the mixed path (FP32
 fluxes, FP64 accumulation), the mixed path's drift from FP64 after the timed
