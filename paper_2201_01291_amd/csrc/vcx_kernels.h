@@ -973,6 +973,13 @@ struct CellLd {
   int ldx, ldw, ldg, ldc;
 };
 
+// Threads per cell of the gas flux pass: 2 for FP64 tetrahedra (each takes
+// three of the six edges), else 1.
+template <int ND, typename CT>
+__host__ __device__ constexpr int gas_halves() {
+  return ND == 3 && sizeof(CT) == sizeof(double) ? 2 : 1;
+}
+
 // Gas fluxes of the tile's cells: MUSCL with virtual upwind nodes, slope
 // limiter, HLLC or Roe; accumulated per cell vertex into sR.
 template <int ND, int NSP, int FLUX, typename CT, int NV, bool AXI = false>
@@ -981,10 +988,24 @@ __device__ inline void gas_cell_fluxes(const DevMesh& m, const TilePre<NV>& tp, 
                                        const GasParams& gp) {
   constexpr int NVAR = 2 + ND + NSP, NR = NVAR + 1, NE = Edges<ND>::NE;
   const CT gamma = CT(gp.gamma), beta = CT(gp.beta), fix = CT(gp.entropy_fix);
-  for (int lc = threadIdx.x; lc < tp.nc; lc += blockDim.x) {
+  // FP64 tetrahedra: two threads per cell, edges 0-2 and 3-5, each into its
+  // own plane of vertex parts (sR and sR + NV*NVAR*ldc), which the node pass
+  // adds: half the registers of a cell's six Riemann problems, so two
+  // wavefronts per SIMD instead of one
+  constexpr int NH = gas_halves<ND, CT>(), EH = NE / NH;
+  const int ncp = NH == 1 ? tp.nc : (tp.nc + 63) / 64 * 64;
+  for (int task = threadIdx.x; task < NH * ncp; task += blockDim.x) {
+    const int h = __builtin_amdgcn_readfirstlane(task / ncp), lc = task - h * ncp;
+    if (lc >= tp.nc) continue;
     int l[NV];
     uint32_t sh;
-    cell_topo<NV>(m, tp, lc, l, sh);
+    if constexpr (NH == 1) {
+      cell_topo<NV>(m, tp, lc, l, sh);
+    } else {
+#pragma unroll
+      for (int k = 0; k < NV; ++k) l[k] = m.lconn[(size_t)k * m.nc + tp.c0 + lc];
+      sh = m.shift[tp.c0 + lc];
+    }
     double e[ND][ND], Sd[NV][ND];
     cell_rel_coords<ND>(m, sX, L.ldx, l, sh, e);
     simplex_normals<ND>(e, Sd);
@@ -994,7 +1015,9 @@ __device__ inline void gas_cell_fluxes(const DevMesh& m, const TilePre<NV>& tp, 
 #pragma unroll
       for (int v = 0; v < NVAR; ++v) acc[k][v] = 0.0;
 #pragma unroll
-    for (int ed = 0; ed < NE; ++ed) {
+    for (int ed0 = 0; ed0 < NE; ++ed0) {
+      if (NH == 2 && (ed0 / EH) != h) continue;
+      const int ed = ed0;
       const int a = Edges<ND>::a(ed), b = Edges<ND>::b(ed);
       const int la = l[a], lb = l[b];
       CT S[ND], dx[ND];
@@ -1040,10 +1063,11 @@ __device__ inline void gas_cell_fluxes(const DevMesh& m, const TilePre<NV>& tp, 
         acc[b][v] -= double(F[v]) * rw;
       }
     }
+    double* sRh = sR + (size_t)h * NV * NVAR * L.ldc;
 #pragma unroll
     for (int k = 0; k < NV; ++k)
 #pragma unroll
-      for (int v = 0; v < NVAR; ++v) sR[(k * NVAR + v) * L.ldc + lc] = acc[k][v];
+      for (int v = 0; v < NVAR; ++v) sRh[(k * NVAR + v) * L.ldc + lc] = acc[k][v];
   }
 }
 
@@ -1161,7 +1185,7 @@ __device__ inline void dd_cell_fluxes(const DevMesh& m, const TilePre<NV>& tp, c
 // fixed order; a tile-owned node is finished (stage update, time-step
 // candidate), a shared node's partial is stored at its partial index.
 // Returns this thread's smallest candidate.
-template <int ND, int NSP, int MODEL, int NVAR>
+template <int ND, int NSP, int MODEL, int NVAR, bool HALVES = false>
 __device__ inline double tile_node_pass(const DevMesh& m, const Finish& f, double dt, double* PR, int ns,
                                         const int* sSl, int ldsl, const uint16_t* sInc, const double* sR,
                                         int ldc, const NodeLds& nl = NodeLds{}) {
@@ -1177,8 +1201,14 @@ __device__ inline double tile_node_pass(const DevMesh& m, const Finish& f, doubl
     for (int p = st.p0; p < st.p1; ++p) {
       const int code = sInc[p];
       const int lc = code >> 2, k = code & 3;
+      if constexpr (HALVES) {
+        const double* sR1 = sR + (size_t)(ND + 1) * NVAR * ldc;
 #pragma unroll
-      for (int v = 0; v < NVAR; ++v) r[v] += sR[(k * NVAR + v) * ldc + lc];
+        for (int v = 0; v < NVAR; ++v) r[v] += sR[(k * NVAR + v) * ldc + lc] + sR1[(k * NVAR + v) * ldc + lc];
+      } else {
+#pragma unroll
+        for (int v = 0; v < NVAR; ++v) r[v] += sR[(k * NVAR + v) * ldc + lc];
+      }
     }
     if (st.sv >= 0) {
       cand = fmin(cand, finish_node<ND, NSP, MODEL, NVAR>(m, f, st.sv, false, r, nq));
@@ -1200,9 +1230,10 @@ __device__ inline void flux_gas_body(DevMesh m, const double* __restrict__ W,
   TilePre<NV> tp;
   tile_prefetch<NV>(m, t, tp);
   const int maxn = m.max_tile_nodes, maxc = m.max_tile_cells;
+  constexpr int NH = gas_halves<ND, CT>();
   double* sX = lds;                       // [ND][maxn]
-  double* sR = sX + ND * maxn;            // [NV*NVAR][maxc]
-  CT* sW = reinterpret_cast<CT*>(sR + NV * NVAR * maxc);  // [NR][maxn]
+  double* sR = sX + ND * maxn;            // [NH][NV*NVAR][maxc]
+  CT* sW = reinterpret_cast<CT*>(sR + NH * NV * NVAR * maxc);  // [NR][maxn]
   CT* sG = sW + NR * maxn;                // [NR*ND][maxn]
   int* sSl = reinterpret_cast<int*>(sG + NR * ND * maxn);
   uint16_t* sInc = reinterpret_cast<uint16_t*>(sSl + 4 * maxn);
@@ -1228,7 +1259,7 @@ __device__ inline void flux_gas_body(DevMesh m, const double* __restrict__ W,
   gas_cell_fluxes<ND, NSP, FLUX, CT, NV, AXI>(m, tp, sX, sW, sG, sR, CellLd{maxn, maxn, maxn, maxc}, gp);
   __syncthreads();
   const double dt = f.sc ? f.sc->dt : 0.0;
-  const double cand = tile_node_pass<ND, NSP, 0, NVAR>(m, f, dt, PR, ns, sSl, maxn, sInc, sR, maxc);
+  const double cand = tile_node_pass<ND, NSP, 0, NVAR, (NH == 2)>(m, f, dt, PR, ns, sSl, maxn, sInc, sR, maxc);
   if (f.final_stage && f.sc) {
     const double b = block_min(cand);
     if (threadIdx.x == 0) post_candidate(f.cand, t, b);
