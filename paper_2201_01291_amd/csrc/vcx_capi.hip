@@ -226,9 +226,12 @@ struct Impl {
     return sizeof(double) * ((size_t)(FG + ND) * maxn + (size_t)FG * ND * maxc) + inc_lds_bytes(NV, maxc);
   }
   static size_t lds_flux(int maxn, int maxc) {
-    if constexpr (MODEL == 0 && gas_halves<ND, CT>() == 2)  // two planes of vertex parts
+    if constexpr (MODEL == 0 && cell_halves<ND, CT>() == 2)  // two planes of vertex parts
       return sizeof(double) * ((size_t)ND * maxn + (size_t)2 * NV * NVAR * maxc) +
              sizeof(CT) * (size_t)(NR + NR * ND) * maxn + slot_lds_bytes(maxn) + inc_lds_bytes(NV, maxc);
+    if constexpr (MODEL == 1 && cell_halves<ND, CT>() == 2)
+      return sizeof(double) * ((size_t)ND * maxn + (size_t)2 * NV * NVAR * maxc) +
+             sizeof(CT) * (size_t)(NSP + NSP * ND + ND) * maxn + slot_lds_bytes(maxn) + inc_lds_bytes(NV, maxc);
     if constexpr (MODEL == 2) {
       // the vertex parts overlay the staged fields when the block has a
       // thread per cell (tile_block covers up to 256 cells)
@@ -320,7 +323,7 @@ struct Impl {
       }
       return launch(s, "flux", [&](hipEvent_t ea, hipEvent_t eb) {
         // a thread per cell and half: the cells rounded to wavefronts, per half
-        const int fb = gas_halves<ND, CT>() == 2 ? std::min(256, 2 * ((m.max_tile_cells + 63) / 64) * 64)
+        const int fb = cell_halves<ND, CT>() == 2 ? std::min(256, 2 * ((m.max_tile_cells + 63) / 64) * 64)
                                                   : s->tile_block;
         hipExtLaunchKernelGGL((k_flux_gas<ND, NSP, FLUX, CT>), dim3(xcd_grid(m.ntiles)),
                            dim3(fb), s->lds_flux, st, ea, eb, 0, m, Win, (const double*)s->G,
@@ -350,8 +353,10 @@ struct Impl {
           });
       }
       return launch(s, "flux", [&](hipEvent_t ea, hipEvent_t eb) {
+        const int fb = cell_halves<ND, CT>() == 2 ? std::min(256, 2 * ((m.max_tile_cells + 63) / 64) * 64)
+                                                  : s->tile_block;
         hipExtLaunchKernelGGL((k_flux_dd<ND, NSP, CT>), dim3(xcd_grid(m.ntiles)),
-                           dim3(s->tile_block), s->lds_flux, st, ea, eb, 0, m, Win, (const double*)s->G,
+                           dim3(fb), s->lds_flux, st, ea, eb, 0, m, Win, (const double*)s->G,
                            s->PR, pp, f);
       });
     }

@@ -973,10 +973,10 @@ struct CellLd {
   int ldx, ldw, ldg, ldc;
 };
 
-// Threads per cell of the gas flux pass: 2 for FP64 tetrahedra (each takes
-// three of the six edges), else 1.
+// Threads per cell of the gas and drift-diffusion flux passes: 2 for FP64
+// tetrahedra (each takes three of the six edges), else 1.
 template <int ND, typename CT>
-__host__ __device__ constexpr int gas_halves() {
+__host__ __device__ constexpr int cell_halves() {
   return ND == 3 && sizeof(CT) == sizeof(double) ? 2 : 1;
 }
 
@@ -992,11 +992,15 @@ __device__ inline void gas_cell_fluxes(const DevMesh& m, const TilePre<NV>& tp, 
   // own plane of vertex parts (sR and sR + NV*NVAR*ldc), which the node pass
   // adds: half the registers of a cell's six Riemann problems, so two
   // wavefronts per SIMD instead of one
-  constexpr int NH = gas_halves<ND, CT>(), EH = NE / NH;
+  constexpr int NH = cell_halves<ND, CT>(), EH = NE / NH;
   const int ncp = NH == 1 ? tp.nc : (tp.nc + 63) / 64 * 64;
   for (int task = threadIdx.x; task < NH * ncp; task += blockDim.x) {
-    const int h = __builtin_amdgcn_readfirstlane(task / ncp), lc = task - h * ncp;
-    if (lc >= tp.nc) continue;
+    int h = 0, lc = task;
+    if constexpr (NH == 2) {
+      h = __builtin_amdgcn_readfirstlane(task / ncp);
+      lc = task - h * ncp;
+      if (lc >= tp.nc) continue;
+    }
     int l[NV];
     uint32_t sh;
     if constexpr (NH == 1) {
@@ -1111,10 +1115,26 @@ __device__ inline void dd_cell_fluxes(const DevMesh& m, const TilePre<NV>& tp, c
   constexpr int NE = Edges<ND>::NE;
   static_assert(!AXI || ND == 2, "axisymmetric meshes are (x, r) planes");
   const CT beta = CT(pp.beta);
-  for (int lc = threadIdx.x; lc < tp.nc; lc += blockDim.x) {
+  // FP64 tetrahedra: two threads per cell, three edges each, into two
+  // planes of vertex parts (as the gas pass)
+  constexpr int NH = cell_halves<ND, CT>(), EH = NE / NH;
+  const int ncp = NH == 1 ? tp.nc : (tp.nc + 63) / 64 * 64;
+  for (int task = threadIdx.x; task < NH * ncp; task += blockDim.x) {
+    int h = 0, lc = task;
+    if constexpr (NH == 2) {
+      h = __builtin_amdgcn_readfirstlane(task / ncp);
+      lc = task - h * ncp;
+      if (lc >= tp.nc) continue;
+    }
     int l[NV];
     uint32_t sh;
-    cell_topo<NV>(m, tp, lc, l, sh);
+    if constexpr (NH == 1) {
+      cell_topo<NV>(m, tp, lc, l, sh);
+    } else {
+#pragma unroll
+      for (int k = 0; k < NV; ++k) l[k] = m.lconn[(size_t)k * m.nc + tp.c0 + lc];
+      sh = m.shift[tp.c0 + lc];
+    }
     double e[ND][ND], Sd[NV][ND];
     cell_rel_coords<ND>(m, sX, L.ldx, l, sh, e);
     simplex_normals<ND>(e, Sd);
@@ -1125,6 +1145,7 @@ __device__ inline void dd_cell_fluxes(const DevMesh& m, const TilePre<NV>& tp, c
       for (int s = 0; s < NS; ++s) acc[k][s] = 0.0;
 #pragma unroll
     for (int ed = 0; ed < NE; ++ed) {
+      if (NH == 2 && ed / EH != h) continue;
       const int a = Edges<ND>::a(ed), b = Edges<ND>::b(ed);
       const int la = l[a], lb = l[b];
       CT S[ND], dx[ND], Ebar[ND];
@@ -1174,10 +1195,11 @@ __device__ inline void dd_cell_fluxes(const DevMesh& m, const TilePre<NV>& tp, c
         acc[b][s] -= double(F) * rw;
       }
     }
+    double* sRh = sR + (size_t)h * NV * NS * L.ldc;
 #pragma unroll
     for (int k = 0; k < NV; ++k)
 #pragma unroll
-      for (int s = 0; s < NS; ++s) sR[(k * NS + s) * L.ldc + lc] = acc[k][s];
+      for (int s = 0; s < NS; ++s) sRh[(k * NS + s) * L.ldc + lc] = acc[k][s];
   }
 }
 
@@ -1230,7 +1252,7 @@ __device__ inline void flux_gas_body(DevMesh m, const double* __restrict__ W,
   TilePre<NV> tp;
   tile_prefetch<NV>(m, t, tp);
   const int maxn = m.max_tile_nodes, maxc = m.max_tile_cells;
-  constexpr int NH = gas_halves<ND, CT>();
+  constexpr int NH = cell_halves<ND, CT>();
   double* sX = lds;                       // [ND][maxn]
   double* sR = sX + ND * maxn;            // [NH][NV*NVAR][maxc]
   CT* sW = reinterpret_cast<CT*>(sR + NH * NV * NVAR * maxc);  // [NR][maxn]
@@ -1290,9 +1312,10 @@ __device__ inline void flux_dd_body(DevMesh m, const double* __restrict__ U,
   TilePre<NV> tp;
   tile_prefetch<NV>(m, t, tp);
   const int maxn = m.max_tile_nodes, maxc = m.max_tile_cells;
+  constexpr int NH = cell_halves<ND, CT>();
   double* sX = lds;                      // [ND][maxn]
-  double* sR = sX + ND * maxn;           // [NV*NS][maxc]
-  CT* sU = reinterpret_cast<CT*>(sR + NV * NS * maxc);  // [NS][maxn]
+  double* sR = sX + ND * maxn;           // [NH][NV*NS][maxc]
+  CT* sU = reinterpret_cast<CT*>(sR + NH * NV * NS * maxc);  // [NS][maxn]
   CT* sG = sU + NS * maxn;               // [NS*ND][maxn]
   CT* sE = sG + NS * ND * maxn;          // [ND][maxn]
   int* sSl = reinterpret_cast<int*>(sE + ND * maxn);
@@ -1326,7 +1349,7 @@ __device__ inline void flux_dd_body(DevMesh m, const double* __restrict__ U,
   const double dt = f.sc ? f.sc->dt : pp.dt_host;
   dd_cell_fluxes<ND, NS, CT, NV, AXI>(m, tp, sX, sU, sG, sE, sR, CellLd{maxn, maxn, maxn, maxc}, CT(dt), pp);
   __syncthreads();
-  const double cand = tile_node_pass<ND, NS, 1, NS>(m, f, dt, PR, ns, sSl, maxn, sInc, sR, maxc);
+  const double cand = tile_node_pass<ND, NS, 1, NS, (NH == 2)>(m, f, dt, PR, ns, sSl, maxn, sInc, sR, maxc);
   if (f.final_stage && f.sc) {
     const double b = block_min(cand);
     if (threadIdx.x == 0) post_candidate(f.cand, t, b);
