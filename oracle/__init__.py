@@ -118,6 +118,7 @@ def lib():
         L.om_euler_flux.argtypes = [C.c_int, C.c_int, dp, dp, dp]
         L.om_hllc.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, dp, dp, dp, dp]
         L.om_roe.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, dp, dp, dp, dp]
+        L.om_flux_branches.argtypes = [ip, C.c_int]
         pp = C.POINTER(_Phys)
         L.om_residual.argtypes = [C.c_void_p, pp, dp, dp, C.c_double, dp]
         L.om_flux_scale.argtypes = [C.c_void_p, pp, dp, dp, C.c_double, dp]
@@ -341,6 +342,16 @@ def hllc(nd, nsp, WL, WR, S, gL=1.4, gR=None):
     F = np.zeros(2 + nd + nsp)
     lib().om_hllc(nd, nsp, float(gL), float(gL if gR is None else gR), _d(WL), _d(WR), _d(S), _d(F))
     return F
+
+
+def flux_branches(reset: bool = True) -> dict:
+    """Counts of the Riemann-flux branches taken since the last reset (test
+    instrumentation of the oracle), and reset them."""
+    out = np.zeros(6, dtype=np.int64)
+    lib().om_flux_branches(out.ctypes.data_as(C.POINTER(C.c_int64)), int(reset))
+    keys = ("hllc_left_supersonic", "hllc_right_supersonic", "hllc_star_left",
+            "hllc_star_right", "roe_calls", "roe_entropy_fix")
+    return dict(zip(keys, (int(v) for v in out)))
 
 
 def roe(nd, nsp, WL, WR, S, gamma=1.4, fix=0.1):

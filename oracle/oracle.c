@@ -562,6 +562,19 @@ void om_euler_flux(int nd, int nsp, const double *W, const double *S, double *F)
   for (int k = 0; k < nsp; k++) F[2 + nd + k] = W[2 + nd + k] * q;
 }
 
+/* Branch counters of the two Riemann fluxes, for tests that must show an
+ * input reaches a given branch: [0] HLLC 0 <= S_L, [1] HLLC S_R < 0, [2] HLLC
+ * left star state, [3] HLLC right star state, [4] Roe calls, [5] Roe calls
+ * with Harten's fix active on an acoustic wave. */
+static int64_t om_branch_count[6];
+
+void om_flux_branches(int64_t *out, int reset) {
+  for (int k = 0; k < 6; k++) {
+    if (out) out[k] = om_branch_count[k];
+    if (reset) om_branch_count[k] = 0;
+  }
+}
+
 /* HLLC flux through the area vector S (|S| times the unit-normal flux).
  * The rotation to the edge frame of the paper is written without forming the
  * rotation matrix: normal velocity q = u.n, tangential velocity kept as is.
@@ -584,10 +597,13 @@ void om_hllc(int nd, int nsp, double gL, double gR, const double *WL, const doub
               (rL * (SL - qL) - rR * (SR - qR));
   double FK[2 + 3 + OM_MAXSP];
   if (0.0 <= SL) {
+    om_branch_count[0]++;
     om_euler_flux(nd, nsp, WL, n, FK);
   } else if (SR < 0.0) {
+    om_branch_count[1]++;
     om_euler_flux(nd, nsp, WR, n, FK);
   } else {
+    om_branch_count[(0.0 <= Ss) ? 2 : 3]++;
     const double *WK = (0.0 <= Ss) ? WL : WR;
     double SK = (0.0 <= Ss) ? SL : SR;
     double rK = WK[0], pK = WK[nvar];
@@ -638,7 +654,9 @@ void om_roe(int nd, int nsp, double gamma, double fix, const double *WL, const d
   double a2 = dr - dp / (a * a);
   double l1 = fabs(q - a), l2 = fabs(q), l5 = fabs(q + a);
   double delta = fix * a;
+  om_branch_count[4]++;
   if (delta > 0.0) {
+    if (l1 < delta || l5 < delta) om_branch_count[5]++;
     if (l1 < delta) l1 = (l1 * l1 + delta * delta) / (2.0 * delta);
     if (l5 < delta) l5 = (l5 * l5 + delta * delta) / (2.0 * delta);
   }

@@ -74,6 +74,11 @@ void om_hllc(int nd, int nsp, double gL, double gR, const double *WL, const doub
              const double *S, double *F);
 void om_roe(int nd, int nsp, double gamma, double fix, const double *WL, const double *WR,
             const double *S, double *F);
+/* branch counters of om_hllc / om_roe since the last reset (test
+ * instrumentation): [0] HLLC 0 <= S_L, [1] HLLC S_R < 0, [2] HLLC left star,
+ * [3] HLLC right star, [4] Roe calls, [5] Roe calls with the entropy fix
+ * active; out may be NULL, reset != 0 clears them */
+void om_flux_branches(int64_t *out, int reset);
 
 /* multi-species node state from conserved U_i [nvar]: out = T, p, gamma, mu,
  * lambda, D_1..D_N, hs_1..hs_N */
