@@ -373,8 +373,12 @@ vcx_status vcx_poisson_destroy(vcx_poisson p);
  * Stops when |r| <= tol |b - L_fD phi_D| (or tol |r_0| when that is zero),
  * or after max_iter iterations.  iters and relres (may be NULL) receive
  * the iteration count and |r| over that reference.  Returns VCX_E_STATE,
- * with phi holding the last iterate, when max_iter is reached first;
- * VCX_E_ARG for NULL q or phi, tol <= 0 or max_iter < 0; VCX_E_HIP. */
+ * with phi holding the last iterate, when max_iter is reached first or
+ * when BiCGStab breaks down (r^.r = 0, r^.v = 0 or omega = 0) above the
+ * tolerance; VCX_E_UNSTABLE when the residual becomes non-finite (a NaN or
+ * infinity in q, phiD, En or the initial phi); VCX_E_ARG for NULL q or phi,
+ * tol <= 0 or max_iter < 0; VCX_E_HIP.  VCX_OK means |r| <= tol times the
+ * reference. */
 vcx_status vcx_poisson_solve(vcx_poisson p, const double *q, const double *phiD, const double *En,
                              double *phi, int is_device, double tol, int max_iter, int *iters,
                              double *relres);

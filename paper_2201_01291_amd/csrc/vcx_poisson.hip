@@ -81,10 +81,10 @@ enum {
 };
 
 struct CgCtl {
-  int done;       // converged (iterations stop)
+  int done;       // iterations stop (converged, or a fault below)
   int iters;      // iterations taken when done
   int last;       // last iteration started
-  int pad;
+  int fault;      // 0 none, 1 non-finite residual, 2 BiCGStab breakdown above the tolerance
   double rr;      // squared residual norm of the last iterate
   double ref2;    // squared norm the tolerance is relative to
   double rz[2];   // r.z of the iterates, by parity (BiCGStab: r^.r)
@@ -328,8 +328,10 @@ __global__ void __launch_bounds__(kThreads) k_cg_a(PoissonDev P, CgVec X, int k,
   // the initial residual when that is zero
   const double bb = sums[1];
   const double ref2 = bb > 0.0 ? bb : sums[2];
-  const bool conv = !(rr > tol2 * ref2);  // also stops on rr = 0
   const double rz = sums[3] + sums[4];
+  // a non-finite residual (e.g. a NaN in q) stops the iteration as a fault
+  const bool bad = !isfinite(rr) || !isfinite(ref2) || !isfinite(rz);
+  const bool conv = bad || !(rr > tol2 * ref2);  // also stops on rr = 0
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     X.ctl->last = k;
     X.ctl->rr = rr;
@@ -337,6 +339,7 @@ __global__ void __launch_bounds__(kThreads) k_cg_a(PoissonDev P, CgVec X, int k,
     X.ctl->rz[cur] = rz;
     if (conv) {
       X.ctl->iters = k;
+      if (bad) X.ctl->fault = 1;
       __hip_atomic_store(&X.ctl->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
@@ -442,8 +445,12 @@ __global__ void __launch_bounds__(kThreads) k_bi_a(PoissonDev P, CgVec X, int k,
   const double bb = sum_partials(X.part + P_BB * P.nb, P.nb);
   const double ref2 = bb > 0.0 ? bb : sum_partials(X.part + P_RRI * P.nb, P.nb);
   const double rho = sum_partials(X.part + (P_RHO0 + cur) * P.nb, P.nb);
-  // converged, or a breakdown (r^.r = 0, or omega = 0 with r != 0)
-  const bool conv = !(rr > tol2 * ref2) || rho == 0.0 || (k > 0 && X.ctl->omega == 0.0);
+  // converged; or a fault: a non-finite residual, or a breakdown (r^.r = 0,
+  // or omega = 0 with r != 0) above the tolerance
+  const bool bad = !isfinite(rr) || !isfinite(ref2) || !isfinite(rho);
+  const bool ok = !bad && !(rr > tol2 * ref2);
+  const bool brk = !bad && !ok && (rho == 0.0 || (k > 0 && X.ctl->omega == 0.0));
+  const bool conv = ok || bad || brk;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     X.ctl->last = k;
     X.ctl->rr = rr;
@@ -451,6 +458,8 @@ __global__ void __launch_bounds__(kThreads) k_bi_a(PoissonDev P, CgVec X, int k,
     X.ctl->rz[cur] = rho;
     if (conv) {
       X.ctl->iters = k;
+      if (bad) X.ctl->fault = 1;
+      if (brk) X.ctl->fault = 2;
       __hip_atomic_store(&X.ctl->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
@@ -490,9 +499,10 @@ __global__ void __launch_bounds__(kThreads) k_bi_b(PoissonDev P, CgVec X, int k)
   if (block_done(X.ctl)) return;
   const int cur = k & 1;
   const double rv = sum_partials(X.part + P_RV * P.nb, P.nb);
-  if (rv == 0.0) {  // breakdown: stop at the current iterate
+  if (!(rv != 0.0) || !isfinite(rv)) {  // breakdown: stop at the current iterate
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       X.ctl->iters = k;
+      X.ctl->fault = isfinite(rv) ? 2 : 1;
       __hip_atomic_store(&X.ctl->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     return;
@@ -1010,7 +1020,12 @@ extern "C" vcx_status vcx_poisson_solve(vcx_poisson p, const double* q, const do
   const double rel = c.ref2 > 0.0 ? std::sqrt(c.rr / c.ref2) : std::sqrt(c.rr);
   if (iters) *iters = it;
   if (relres) *relres = rel;
+  if (c.fault == 1 || !std::isfinite(rel))
+    return err(VCX_E_UNSTABLE, "non-finite residual in the Poisson solve (non-finite q, phiD or En)");
+  if (c.fault == 2)
+    return err(VCX_E_STATE, "BiCGStab breakdown before the tolerance was reached");
   if (!c.done) return err(VCX_E_STATE, "conjugate gradients did not reach the tolerance within max_iter");
+  if (!(rel <= tol)) return err(VCX_E_STATE, "the Poisson solve stopped above the tolerance");
   return VCX_OK;
 }
 

@@ -269,6 +269,51 @@ def euler_blob_state(mesh: Mesh, *, nblobs: int = 8, amp: float = 0.1, sigma: fl
     return conserved_from_primitive(rho, vel, p, gamma, Y)
 
 
+def explosion_state(mesh: Mesh, *, centre=(1.0, 1.0), radius: float = 0.4,
+                    inside=(1.0, 1.0), outside=(0.125, 0.1), width: float | None = None,
+                    gamma: float = 1.4) -> np.ndarray:
+    """Cylindrical (2D) or spherical (3D) explosion at rest (Sec.
+    "Explosions", after Toro Ch. 17.1): density and pressure ``inside`` =
+    (rho, p) within ``radius`` of ``centre`` and ``outside`` beyond it, blended
+    by 0.5 (1 - tanh((r - radius)/width)) so the interface has no staircase;
+    ``width`` defaults to one mean mesh spacing."""
+    nd = mesh.ndim
+    if width is None:
+        ext = mesh.xyz.max(1) - mesh.xyz.min(1)
+        width = float(np.prod(ext) / max(mesh.ncells, 1) * math.factorial(nd)) ** (1.0 / nd)
+    r = np.sqrt(sum((mesh.xyz[a] - centre[a]) ** 2 for a in range(nd)))
+    w = 0.5 * (1.0 - np.tanh((r - radius) / width))
+    rho = outside[0] + (inside[0] - outside[0]) * w
+    p = outside[1] + (inside[1] - outside[1]) * w
+    return conserved_from_primitive(rho, np.zeros((nd, mesh.nnodes)), p, gamma)
+
+
+# Velocity directions of the four quadrant states of the paper's 2D Riemann
+# problems (figure of the four cases; quadrants 1..4 = top-left, top-right,
+# bottom-right, bottom-left), as signs of (u_x, u_y).
+QUADRANT_SIGNS = {
+    1: ((+1, +1), (+1, -1), (-1, -1), (-1, +1)),   # clockwise turn (mixing interfaces)
+    2: ((-1, +1), (-1, -1), (+1, -1), (+1, +1)),   # shock / expansion diagonals
+    3: ((-1, +1), (+1, +1), (+1, -1), (-1, -1)),   # every state moving outward
+    4: ((+1, -1), (-1, -1), (-1, +1), (+1, +1)),   # every state moving inward
+}
+
+
+def quadrant_state(mesh: Mesh, case: int, *, centre=(0.0, 0.0), rho=(2.0, 1.0, 3.0, 1.0),
+                   p: float = 1.0, speeds=(0.75, 0.5), gamma: float = 1.4) -> np.ndarray:
+    """Initial data of the paper's 2D Riemann problems (Sec. "2D Riemann
+    problems"): four constant states in the quadrants around ``centre``,
+    densities 2, 1, 3, 1 (quadrants 1..4), pressure 1 everywhere, velocity
+    components of magnitude 0.75 (x) and 0.5 (y) with the signs of
+    ``QUADRANT_SIGNS[case]``."""
+    x, y = mesh.xyz[0] - centre[0], mesh.xyz[1] - centre[1]
+    q = np.where(y >= 0, np.where(x < 0, 0, 1), np.where(x >= 0, 2, 3))
+    sg = np.array(QUADRANT_SIGNS[case], dtype=np.float64)
+    r = np.asarray(rho, dtype=np.float64)[q]
+    vel = np.stack([speeds[0] * sg[q, 0], speeds[1] * sg[q, 1]])
+    return conserved_from_primitive(r, vel, np.full(mesh.nnodes, p), gamma)
+
+
 @dataclass
 class DDSpecies:
     z: float      # charge sign (-1 electrons, +1 positive ions)

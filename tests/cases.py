@@ -125,13 +125,77 @@ def make_case(name: str) -> Case:
         U = wl.ns_state(m, mix, lattice=3, seed=10, vel=(20.0, 15.0))
         return Case(name, m, U, None, dict(model="ns", flux="hllc", limiter="vanleer", rk=2,
                                            nspecies=2, mixture=mix), tiles=(320, 200))
+    # -- cases that drive faces transonic or supersonic ------------------
+    if name == "shock1d-roe-vanleer":
+        # the paper's modified shock tube (table shock_1d): its left
+        # rarefaction is transonic, where Roe's entropy fix acts
+        m = wl.sod_tube(100, 10)
+        U = wl.sod_state(m, left=(1.0, 0.75, 1.0), right=(0.125, 0.0, 0.1))
+        return Case(name, m, U, None, dict(model="gas", flux="roe", limiter="vanleer", rk=2))
+    if name == "euler2d-mach2.5-hllc":
+        # supersonic stream: both fully upwind HLLC branches (0 <= S_L, S_R < 0)
+        m = wl.tri_rect_mesh(20, 16, jitter=0.2, seed=14, periodic=True)
+        U = wl.euler_blob_state(m, nblobs=4, amp=0.4, sigma=0.15, mach=2.5, seed=3)
+        return Case(name, m, U, None, dict(model="gas", flux="hllc", limiter="minmod", rk=2))
+    if name == "euler2d-mach2.5-roe-sp2":
+        m = wl.tri_rect_mesh(18, 17, jitter=0.2, seed=15, periodic=True)
+        U = wl.euler_blob_state(m, nblobs=4, amp=0.4, sigma=0.15, mach=2.5, seed=4, nspecies=2)
+        return Case(name, m, U, None, dict(model="gas", flux="roe", limiter="vanleer", rk=3,
+                                           nspecies=2))
+    if name == "explosion2d":
+        # cylindrical explosion (Sec. "Explosions"): [0,2]^2, circle of radius
+        # 0.4, HLLC-MUSCL RK2 with the Sweby limiter at beta = 1.7
+        m = wl.tri_rect_mesh(40, 40, 2.0, 2.0)
+        U = wl.explosion_state(m)
+        return Case(name, m, U, None, dict(model="gas", flux="hllc", limiter="sweby", beta=1.7,
+                                           rk=2))
+    if name == "riemann2d-c3-hllc":
+        # 2D Riemann problem, every quadrant moving outward (the rho = 3
+        # quadrant is supersonic, Mach 1.3)
+        m = wl.tri_rect_mesh(30, 30, 1.0, 1.0, origin=(-0.5, -0.5))
+        U = wl.quadrant_state(m, 3)
+        return Case(name, m, U, None, dict(model="gas", flux="hllc", limiter="minmod", rk=2))
+    if name == "riemann2d-c4-roe":
+        # every quadrant moving inward: colliding shocks
+        m = wl.tri_rect_mesh(30, 30, 1.0, 1.0, origin=(-0.5, -0.5))
+        U = wl.quadrant_state(m, 4)
+        return Case(name, m, U, None, dict(model="gas", flux="roe", limiter="vanleer", rk=2))
+    if name == "euler3d-mach2-roe":
+        m = wl.kuhn_tet_mesh(6, 6, 6, jitter=0.1, seed=16)
+        U = wl.euler_blob_state(m, nblobs=6, amp=0.4, sigma=0.2, mach=2.0, seed=5)
+        return Case(name, m, U, None, dict(model="gas", flux="roe", limiter="vanleer", rk=2))
+    if name == "euler3d-mach2-hllc-sp2":
+        m = wl.kuhn_tet_mesh(5, 6, 5, jitter=0.1, seed=17)
+        U = wl.euler_blob_state(m, nblobs=6, amp=0.4, sigma=0.2, mach=2.0, seed=6, nspecies=2)
+        return Case(name, m, U, None, dict(model="gas", flux="hllc", limiter="minmod", rk=2,
+                                           nspecies=2))
+    if name == "explosion3d-hllc":
+        # spherical explosion (Sec. "Explosions"), open cube
+        m = wl.kuhn_tet_mesh(8, 8, 8, 2.0, 2.0, 2.0, periodic=False)
+        U = wl.explosion_state(m, centre=(1.0, 1.0, 1.0), radius=0.5)
+        return Case(name, m, U, None, dict(model="gas", flux="hllc", limiter="sweby", beta=1.7,
+                                           rk=2))
     raise KeyError(name)
 
+
+# Gas cases built to reach the transonic and supersonic branches of the
+# Riemann fluxes, with the branches each must reach (oracle branch counters)
+BRANCH_CASES = {
+    "shock1d-roe-vanleer": ("roe_entropy_fix",),
+    "euler2d-mach2.5-hllc": ("hllc_left_supersonic", "hllc_right_supersonic"),
+    "euler2d-mach2.5-roe-sp2": ("roe_entropy_fix",),
+    "explosion2d": ("hllc_star_left", "hllc_star_right"),
+    "riemann2d-c3-hllc": ("hllc_left_supersonic", "hllc_right_supersonic"),
+    "riemann2d-c4-roe": ("roe_entropy_fix",),
+    "euler3d-mach2-roe": ("roe_entropy_fix",),
+    "euler3d-mach2-hllc-sp2": ("hllc_left_supersonic", "hllc_right_supersonic"),
+    "explosion3d-hllc": ("hllc_star_left", "hllc_star_right"),
+}
 
 CASE_NAMES = ["dd2d-streamer", "dd2d-diel", "dd2d-open-vanleer", "dd2d-open-closure2",
               "euler2d-open-closure2", "dd3d-sweby", "sod-hllc", "euler2d-roe-sp2",
               "euler3d-roe", "euler3d-hllc-open-sp2", "euler3d-hllc-sp9", "ns3d-sp9",
-              "ns2d-sp2-open", "ns2d-sp2-bigtile"]
+              "ns2d-sp2-open", "ns2d-sp2-bigtile", *BRANCH_CASES]
 
 
 def reconstructed(case: Case) -> np.ndarray:

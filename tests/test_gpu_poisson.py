@@ -149,6 +149,27 @@ def test_iteration_cap_is_reported():
     assert e.value.code == vcx.E_STATE
 
 
+@pytest.mark.parametrize("axisymmetric", [False, True])
+def test_non_finite_charge_is_not_reported_as_converged(axisymmetric):
+    """A NaN in the space charge makes the residual non-finite: conjugate
+    gradients and BiCGStab must stop with VCX_E_UNSTABLE, not VCX_OK; the same
+    operator then solves a finite charge normally."""
+    if axisymmetric:
+        m, bnd = _axi_strip(20, 10)
+    else:
+        m, bnd = _open_square(20, seed=3)
+    print(f"[case] poisson NaN charge axisymmetric={axisymmetric} nn={m.nnodes}", flush=True)
+    ps = vcx.Poisson(vcx.Mesh(m, axisymmetric=axisymmetric), dirichlet=bnd)
+    q = _charge(m, seed=7)
+    bad = q.copy()
+    bad[m.nnodes // 2] = np.nan
+    with pytest.raises(vcx.VcxError) as e:
+        ps.solve(bad, tol=TOL, max_iter=2000)
+    assert e.value.code == vcx.E_UNSTABLE
+    phi, it, rel = ps.solve(q, tol=TOL)
+    assert rel <= TOL and np.all(np.isfinite(phi))
+
+
 def test_step_coupled_to_the_poisson_field_matches_the_oracle():
     """Drift-diffusion of electrons and ions with E = E_background - grad phi,
     phi from the space charge e (n_i - n_e) / eps0 (periodic box, neutralising

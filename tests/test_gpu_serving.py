@@ -32,8 +32,8 @@ def _request(kind, side, seed):
     return cases.Case(f"dd-{side}", m, n, E, dict(cases.DD2, fourier=0.25))
 
 
-def _alone(case, gm, nsteps, t_end=0.0):
-    s = vcx.Solver(gm, case.vcx_phys(), case.E)
+def _alone(case, gm, nsteps, t_end=0.0, precision=0):
+    s = vcx.Solver(gm, case.vcx_phys(precision), case.E)
     s.upload(case.U)
     s.step(nsteps, t_end=t_end)
     return s.download(), s.time()[0]
@@ -48,26 +48,37 @@ def _mix(n, seed=0):
     return out
 
 
-def test_requests_in_a_mix_match_alone():
+@pytest.mark.parametrize("precision,graphs", [(0, True), (1, True), (1, False)])
+def test_requests_in_a_mix_match_alone(precision, graphs):
+    """Each served result equals the same solve alone, bit for bit, in the
+    FP64 path and in the mixed path the benchmark serves (with graph
+    replays and with direct launches); mixed results also stay within the
+    stated 1e-4 of the FP64 oracle."""
+    import oracle
     reqs = _mix(10)
     meshes = [vcx.Mesh(c.mesh) for c in reqs]
     budgets = [int(b) for b in np.random.default_rng(1).integers(5, 40, size=len(reqs))]
-    print("[serve] mix", [c.name for c in reqs], budgets, flush=True)
-    ref = [_alone(c, gm, k) for c, gm, k in zip(reqs, meshes, budgets)]
-    sv = vcx.Server(hbm_budget=1 << 34, max_slots=16, chunk_steps=4)
+    print(f"[serve] mix prec={precision} graphs={graphs}", [c.name for c in reqs], budgets, flush=True)
+    ref = [_alone(c, gm, k, precision=precision) for c, gm, k in zip(reqs, meshes, budgets)]
+    sv = vcx.Server(hbm_budget=1 << 34, max_slots=16, chunk_steps=4, graphs=graphs)
     ids = []
     for c, gm, k in zip(reqs[:4], meshes[:4], budgets[:4]):
-        ids.append(sv.submit(gm, c.vcx_phys(), c.U, c.E, nsteps=k))
+        ids.append(sv.submit(gm, c.vcx_phys(precision), c.U, c.E, nsteps=k))
     assert sv.wait(ids[0], timeout=60)
     # later arrivals join the running batch
     for c, gm, k in zip(reqs[4:], meshes[4:], budgets[4:]):
-        ids.append(sv.submit(gm, c.vcx_phys(), c.U, c.E, nsteps=k))
-    for rid, (U, t) in zip(ids, ref):
+        ids.append(sv.submit(gm, c.vcx_phys(precision), c.U, c.E, nsteps=k))
+    for rid, (U, t), c, k in zip(ids, ref, reqs, budgets):
         assert sv.wait(rid, timeout=120)
         done, st, Us, ts = sv.poll(rid)
         assert done and st == vcx.OK
         assert ts == t
         assert np.array_equal(Us, U)
+        if precision and c.mesh.nnodes <= 1200:
+            Uo, *_ = oracle.OracleMesh(c.mesh).step(c.oracle_phys(), c.U, c.E, nsteps=k)
+            err = cases.state_err(c, Us, Uo)
+            print(f"MIXED served {c.name} after {k} steps vs FP64 oracle: {err}")
+            assert err.max() <= 1e-4
     st = sv.stats()
     print("[serve] stats", st, flush=True)
     assert st["completed"] == len(reqs) and st["failed"] == 0
