@@ -29,6 +29,12 @@ HIP_FLAGS = [
 ]
 
 
+# HIP translation units: the C ABI, one kernel-table unit per model (compiled
+# in parallel), and the Poisson solve
+HIP_SOURCES = ["vcx_capi.hip", "vcx_tab_gas2.hip", "vcx_tab_gas3.hip", "vcx_tab_dd.hip",
+               "vcx_tab_ns.hip", "vcx_poisson.hip"]
+
+
 def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
@@ -40,8 +46,6 @@ def build(verbose: bool = False) -> str:
     with tempfile.TemporaryDirectory(prefix="vcx_build_") as tmp:
         host_o = os.path.join(tmp, "vcx_mesh.o")
         serv_o = os.path.join(tmp, "vcx_server.o")
-        dev_o = os.path.join(tmp, "vcx_capi.o")
-        poi_o = os.path.join(tmp, "vcx_poisson.o")
         rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
         procs = [
             subprocess.Popen(["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", *inc, "-c",
@@ -49,20 +53,21 @@ def build(verbose: bool = False) -> str:
             subprocess.Popen(["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-pthread",
                               "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(rocm, "include"), *inc,
                               "-c", os.path.join(CSRC, "vcx_server.cpp"), "-o", serv_o]),
-            subprocess.Popen(["hipcc", *HIP_FLAGS, *inc, "-c",
-                              os.path.join(CSRC, "vcx_capi.hip"), "-o", dev_o]),
-            subprocess.Popen(["hipcc", *HIP_FLAGS, *inc, "-c",
-                              os.path.join(CSRC, "vcx_poisson.hip"), "-o", poi_o]),
         ]
+        objs = [host_o, serv_o]
+        for src in HIP_SOURCES:
+            obj = os.path.join(tmp, src.replace(".hip", ".o"))
+            objs.append(obj)
+            procs.append(subprocess.Popen(["hipcc", *HIP_FLAGS, *inc, "-c", os.path.join(CSRC, src),
+                                           "-o", obj]))
         if verbose:
-            print("compiling vcx_mesh.cpp, vcx_server.cpp (g++), vcx_capi.hip and vcx_poisson.hip (hipcc)",
-                  flush=True)
+            print("compiling vcx_mesh.cpp, vcx_server.cpp (g++) and " + ", ".join(HIP_SOURCES) +
+                  " (hipcc)", flush=True)
         rcs = [p.wait() for p in procs]
         if any(rcs):
             raise RuntimeError(f"compilation failed (exit codes {rcs})")
         tmp_lib = LIB + ".tmp"
-        _run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", tmp_lib, host_o,
-              serv_o, dev_o, poi_o],
+        _run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", tmp_lib, *objs],
              verbose)
         os.replace(tmp_lib, LIB)
     return LIB

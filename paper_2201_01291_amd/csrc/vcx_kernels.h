@@ -1943,18 +1943,18 @@ __global__ void __launch_bounds__(256) k_node_dt(DevMesh m, const double* __rest
 }
 
 // empty the node-pass slots (before a node pass)
-__global__ void k_node_slots_clear(DevLoop* lp) {
+static __global__ void k_node_slots_clear(DevLoop* lp) {
   if (threadIdx.x < kCandSlots) lp->cnode[threadIdx.x] = cand_empty();
 }
 
-__global__ void __launch_bounds__(256) k_dt_query(DevLoop* lp) {
+static __global__ void __launch_bounds__(256) k_dt_query(DevLoop* lp) {
   const double v = threadIdx.x < kCandSlots ? key_cand(lp->cnode[threadIdx.x]) : INFINITY;
   const double d = block_min(v);
   if (threadIdx.x == 0) lp->s[0].dt_query = lp->s[1].dt_query = (d > 0.0 && isfinite(d)) ? d : -1.0;
 }
 
 // end of a host call: commit the last step (of parity par)
-__global__ void k_commit(DevLoop* lp, int par) {
+static __global__ void k_commit(DevLoop* lp, int par) {
   if (threadIdx.x == 0 && blockIdx.x == 0) step_finish(lp, par);
 }
 
@@ -2151,7 +2151,7 @@ __global__ void __launch_bounds__(256) k_update_shared_batch(const BatchEntry* _
 }
 
 // per-solve control of a batch call: end time and step budget
-__global__ void k_batch_control(const BatchEntry* __restrict__ tab, int n,
+static __global__ void k_batch_control(const BatchEntry* __restrict__ tab, int n,
                                 const double* __restrict__ t_end, const int* __restrict__ steps) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -2163,7 +2163,7 @@ __global__ void k_batch_control(const BatchEntry* __restrict__ tab, int n,
 
 // after nq batch steps: commit every solve's last step and copy the
 // scalars to one array
-__global__ void k_batch_commit(const BatchEntry* __restrict__ tab, int n, int nq,
+static __global__ void k_batch_commit(const BatchEntry* __restrict__ tab, int n, int nq,
                                DevScalars* __restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -2176,7 +2176,7 @@ __global__ void k_batch_commit(const BatchEntry* __restrict__ tab, int n, int nq
 // permutations between the caller's node order and the internal order
 // ---------------------------------------------------------------------------
 
-__global__ void k_gather_rows(const int32_t* __restrict__ perm, const double* __restrict__ src,
+static __global__ void k_gather_rows(const int32_t* __restrict__ perm, const double* __restrict__ src,
                               double* __restrict__ dst, int nn, int nrows) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nn) return;
@@ -2184,7 +2184,7 @@ __global__ void k_gather_rows(const int32_t* __restrict__ perm, const double* __
   for (int v = 0; v < nrows; ++v) dst[(size_t)v * nn + i] = src[(size_t)v * nn + o];
 }
 
-__global__ void k_scatter_rows(const int32_t* __restrict__ perm, const double* __restrict__ src,
+static __global__ void k_scatter_rows(const int32_t* __restrict__ perm, const double* __restrict__ src,
                                double* __restrict__ dst, int nn, int nrows) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nn) return;
@@ -2193,7 +2193,7 @@ __global__ void k_scatter_rows(const int32_t* __restrict__ perm, const double* _
 }
 
 // pressure row of the gas reconstructed variables from the conserved rows
-__global__ void k_pressure(double* W, int nn, int nd, int nsp, double gamma) {
+static __global__ void k_pressure(double* W, int nn, int nd, int nsp, double gamma) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nn) return;
   const double rho = W[i];
@@ -2209,7 +2209,7 @@ __global__ void k_pressure(double* W, int nn, int nd, int nsp, double gamma) {
 // conservation sums: fixed assignment of nodes to blocks, fixed tree
 // ---------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(256) k_sums_partial(const double* __restrict__ W,
+static __global__ void __launch_bounds__(256) k_sums_partial(const double* __restrict__ W,
                                                       const double* __restrict__ vnode, int nn,
                                                       int nrows, double* __restrict__ part) {
   __shared__ double red[256];
@@ -2228,7 +2228,7 @@ __global__ void __launch_bounds__(256) k_sums_partial(const double* __restrict__
   }
 }
 
-__global__ void __launch_bounds__(256) k_sums_final(const double* __restrict__ part, int nparts,
+static __global__ void __launch_bounds__(256) k_sums_final(const double* __restrict__ part, int nparts,
                                                     int nrows, double* __restrict__ out) {
   __shared__ double red[256];
   for (int v = 0; v < nrows; ++v) {
