@@ -206,6 +206,16 @@ vcx_status vcx_solver_destroy(vcx_solver s);
  * field), VCX_E_HIP. */
 vcx_status vcx_solver_set_field(vcx_solver s, const double *E, int is_device);
 
+/* Space charge of a drift-diffusion solver's current state, the right-hand
+ * side of the Poisson equation (Sec. "Integrating the Poisson equation"):
+ * q_i = (e / eps0) sum_s z_s n_s,i at the nodes, with z_s the species'
+ * charge numbers of its physics (at most 4 species), e = 1.602176634e-19 C
+ * and eps0 = 8.8541878128e-12 F/m.  q: [nnodes] in caller order, host or
+ * device (is_device), written on the mesh's stream; synchronises it.
+ * Errors: VCX_E_ARG (NULL, not drift-diffusion), VCX_E_STATE (no state),
+ * VCX_E_HIP. */
+vcx_status vcx_solver_charge(vcx_solver s, double *q, int is_device);
+
 /* Number of conserved variables (gas 2 + ndim + nspecies; DD nspecies). */
 int vcx_solver_nvar(vcx_solver s);
 
@@ -215,6 +225,14 @@ int vcx_solver_nvar(vcx_solver s);
 vcx_status vcx_state_upload(vcx_solver s, const double *U, int is_device);
 vcx_status vcx_state_download(vcx_solver s, double *U, int is_device);
 vcx_status vcx_state_set_time(vcx_solver s, double t);
+/* Upload a state given in primitive variables P [nvar][nnodes] (caller
+ * order, host or device per is_device), converted on the device with the
+ * solver's own equation of state: gas rows (rho, u_1..u_nd, p, Y_1..Y_N) ->
+ * rho E = p / (gamma - 1) + rho |u|^2 / 2; Navier-Stokes rows (rho, u, T,
+ * Y) -> rho E = rho (e_s(T) + |u|^2 / 2) with the mixture's sensible energy
+ * (the total non-chemical energy of eq. ns_reactive); drift-diffusion rows
+ * are the densities themselves.  Otherwise as vcx_state_upload. */
+vcx_status vcx_state_upload_primitive(vcx_solver s, const double *P, int is_device);
 
 /* Nodal gradients of the reconstructed variables of the current state,
  * [nr][ndim][nnodes] (gas nr = nvar + 1 with pressure last; DD nr = nvar),
@@ -389,6 +407,17 @@ vcx_status vcx_poisson_solve(vcx_poisson p, const double *q, const double *phiD,
  * drift-diffusion solver takes the result through vcx_solver_create or, for
  * a coupled step, vcx_solver_set_field. */
 vcx_status vcx_poisson_field(vcx_poisson p, const double *phi, double *E, int is_device);
+/* As vcx_poisson_field plus a background field: E = E_bg - grad phi, with
+ * Ebg [ndim][nnodes] in caller order on the same side (host or device) as
+ * phi and E; Ebg may be the same array as E.  The field of a step coupled to
+ * the Poisson equation under an applied field (Sec. "Bagheri benchmark").
+ * Errors: VCX_E_ARG (NULL argument), VCX_E_HIP. */
+vcx_status vcx_poisson_field_add(vcx_poisson p, const double *phi, const double *Ebg, double *E,
+                                 int is_device);
+/* Operator and preconditioner sizes: out[0] rows, [1] nonzeros, [2] coarse
+ * unknowns of the aggregation level (0 for BiCGStab), [3] 0 conjugate
+ * gradients, 1 BiCGStab. */
+vcx_status vcx_poisson_info(vcx_poisson p, int64_t out[4]);
 
 
 /* sum_i V_i U_i per variable [nvar] (FP64, fixed-order tree). */

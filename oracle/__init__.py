@@ -119,6 +119,7 @@ def lib():
         L.om_hllc.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, dp, dp, dp, dp]
         L.om_roe.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, dp, dp, dp, dp]
         L.om_flux_branches.argtypes = [ip, C.c_int]
+        L.om_ns_conserved.argtypes = [C.c_int, C.POINTER(_Phys), dp, dp]
         pp = C.POINTER(_Phys)
         L.om_residual.argtypes = [C.c_void_p, pp, dp, dp, C.c_double, dp]
         L.om_flux_scale.argtypes = [C.c_void_p, pp, dp, dp, C.c_double, dp]
@@ -368,6 +369,30 @@ def ns_node(nd, phys: Phys, Ui):
     p = phys.to_c()
     lib().om_ns_node(nd, C.byref(p), _d(Ui), _d(out))
     return out
+
+
+def ns_conserved(nd, phys: Phys, prim):
+    """Conserved multi-species state from (rho, u, T, Y) at one node."""
+    prim = np.ascontiguousarray(prim, dtype=np.float64)
+    U = np.zeros(2 + nd + phys.nspecies)
+    p = phys.to_c()
+    lib().om_ns_conserved(nd, C.byref(p), _d(prim), _d(U))
+    return U
+
+
+def conserved_from_primitive(nd, phys: Phys, P):
+    """Conserved state [nvar][nn] from primitive rows [nvar][nn]: gas (rho, u,
+    p, Y) with the constant-gamma ideal gas, multi-species (rho, u, T, Y) with
+    the mixture's sensible energy, drift-diffusion densities unchanged."""
+    P = np.asarray(P, dtype=np.float64)
+    if phys.model == DRIFT_DIFFUSION:
+        return P.copy()
+    if phys.model == NAVIER_STOKES:
+        return np.stack([ns_conserved(nd, phys, P[:, i]) for i in range(P.shape[1])], axis=1)
+    rho, u, p = P[0], P[1:1 + nd], P[1 + nd]
+    rows = [rho] + [rho * v for v in u] + [p / (phys.gamma - 1.0) + 0.5 * rho * np.sum(u * u, axis=0)]
+    rows += [rho * y for y in P[2 + nd:]]
+    return np.stack(rows)
 
 
 def viscous_flux(nd, nsp, prim_i, prim_j, rho_i, rho_j, aux_i, aux_j, gprim_i, gprim_j, S):

@@ -135,6 +135,20 @@ static void mixture_es_cv(const om_phys *ph, const double *Y, double T, double *
   *cv = c;
 }
 
+/* Conserved multi-species state from primitives prim = (rho, u_1..u_nd, T,
+ * Y_1..Y_N): U = (rho, rho u, rho (e_s(T) + |u|^2/2), rho Y) with the total
+ * non-chemical energy of eq. (ns_reactive). */
+void om_ns_conserved(int nd, const om_phys *ph, const double *prim, double *U) {
+  int ns = ph->nspecies;
+  double rho = prim[0], T = prim[1 + nd], uu = 0.0, es, cv;
+  for (int d = 0; d < nd; d++) uu += prim[1 + d] * prim[1 + d];
+  mixture_es_cv(ph, prim + 2 + nd, T, &es, &cv);
+  U[0] = rho;
+  for (int d = 0; d < nd; d++) U[1 + d] = rho * prim[1 + d];
+  U[1 + nd] = rho * (es + 0.5 * uu);
+  for (int k = 0; k < ns; k++) U[2 + nd + k] = rho * prim[2 + nd + k];
+}
+
 /* Node state of the multi-species model: out = T, p, gamma, mu, lambda,
  * D_1..D_N, hs_1..hs_N (the temperature solves e_s(T) = E - |u|^2/2). */
 void om_ns_node(int nd, const om_phys *ph, const double *Ui, double *out) {

@@ -83,6 +83,9 @@ void om_flux_branches(int64_t *out, int reset);
 /* multi-species node state from conserved U_i [nvar]: out = T, p, gamma, mu,
  * lambda, D_1..D_N, hs_1..hs_N */
 void om_ns_node(int nd, const om_phys *ph, const double *Ui, double *out);
+/* conserved multi-species state U [nvar] from prim = (rho, u_1..u_nd, T,
+ * Y_1..Y_N) */
+void om_ns_conserved(int nd, const om_phys *ph, const double *prim, double *U);
 /* central viscous + heat + species-diffusion flux through S (sign: to be
  * subtracted from the convective flux) from face-end primitive data */
 void om_viscous_flux(int nd, int nsp, const double *prim_i, const double *prim_j,

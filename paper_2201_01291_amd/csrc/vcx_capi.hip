@@ -402,15 +402,30 @@ extern "C" vcx_status vcx_solver_set_field(vcx_solver s, const double* E, int is
   return VCX_OK;
 }
 
+extern "C" vcx_status vcx_solver_charge(vcx_solver s, double* q, int is_device) {
+  if (!s || !q) return fail(VCX_E_ARG, "NULL argument");
+  if (s->ph.model != VCX_MODEL_DRIFT_DIFFUSION) return fail(VCX_E_ARG, "space charge needs a drift-diffusion solver");
+  if (!s->has_state) return fail(VCX_E_STATE, "no state uploaded");
+  const DevMesh& d = s->mesh->d;
+  double* dst = is_device ? q : s->io;
+  const double e_eps0 = 1.602176634e-19 / 8.8541878128e-12;  // elementary charge / vacuum permittivity
+  hipLaunchKernelGGL(k_space_charge, dim3((d.nn + 255) / 256), dim3(256), 0, s->mesh->stream,
+                     (const double*)s->W[s->cur], d.nn, s->nvar, s->ph.z[0], s->ph.z[1], s->ph.z[2],
+                     s->ph.z[3], e_eps0, d.perm, dst);
+  VCX_HIP(hipGetLastError());
+  if (!is_device)
+    VCX_HIP(hipMemcpyAsync(q, s->io, sizeof(double) * d.nn, hipMemcpyDeviceToHost, s->mesh->stream));
+  VCX_HIP(hipStreamSynchronize(s->mesh->stream));
+  return VCX_OK;
+}
+
 bool vcx::solver_matches(vcx_solver s, vcx_mesh mesh, const vcx_physics* ph) {
   return s && s->mesh == mesh && same_scheme(s->ph, *ph);
 }
 
-extern "C" vcx_status vcx_solver_create(vcx_mesh mesh, const vcx_physics* phys, const double* E,
-                                        vcx_solver* out) {
-  if (!mesh || !phys || !out) return fail(VCX_E_ARG, "NULL argument");
-  *out = nullptr;
-  const vcx_physics& ph = *phys;
+// Check a physics struct against a mesh and pick its kernel table.
+vcx_status vcx::check_physics(vcx_mesh mesh, const vcx_physics& ph, const double* E,
+                              const KernelTable** kt_out) {
   const int nd = mesh->h.nd;
   if (ph.model != VCX_MODEL_GAS && ph.model != VCX_MODEL_DRIFT_DIFFUSION &&
       ph.model != VCX_MODEL_NAVIER_STOKES)
@@ -444,8 +459,14 @@ extern "C" vcx_status vcx_solver_create(vcx_mesh mesh, const vcx_physics* phys, 
   }
   const KernelTable* kt = pick_table(nd, ph);
   if (!kt) return fail(VCX_E_ARG, "unsupported species count for this model");
-  vcx_solver s = new (std::nothrow) vcx_solver_s();
-  if (!s) return fail(VCX_E_OOM, "host allocation failed");
+  *kt_out = kt;
+  return VCX_OK;
+}
+
+// Sizes, LDS footprints, fused-pass choice and launch shapes of a solver
+// (host fields only; no device memory is touched).
+vcx_status vcx::configure_solver(vcx_solver s, vcx_mesh mesh, const vcx_physics& ph, const KernelTable* kt) {
+  const int nd = mesh->h.nd;
   s->mesh = mesh;
   s->ph = ph;
   s->nd = nd;
@@ -459,7 +480,6 @@ extern "C" vcx_status vcx_solver_create(vcx_mesh mesh, const vcx_physics* phys, 
   s->lds_flux = kt->lds_flux(d.max_tile_nodes, d.max_tile_cells);
   if (s->lds_grad > (size_t)mesh->lds_max || s->lds_flux > (size_t)mesh->lds_max) {
     const size_t need = std::max(s->lds_grad, s->lds_flux);
-    delete s;
     return fail(VCX_E_ARG, "tile LDS footprint " + std::to_string(need) + " B exceeds the device limit " +
                                std::to_string(mesh->lds_max) +
                                " B for this model; create the mesh with smaller tiles");
@@ -473,14 +493,32 @@ extern "C" vcx_status vcx_solver_create(vcx_mesh mesh, const vcx_physics* phys, 
   // after a separate gradient pass)
   s->fused = !d.axi && ph.closure != 2 && s->lds_fused > 0 && s->lds_fused <= (size_t)mesh->lds_max;
   if (!s->fused) s->lds_fused = 0;
-  if (std::max({s->lds_grad, s->lds_flux, s->lds_fused}) > 65536) {
-    vcx_status st = kt->allow_lds(s->lds_grad, s->lds_flux, s->lds_fused);
-    if (st != VCX_OK) {
+  if (std::max({s->lds_grad, s->lds_flux, s->lds_fused}) > 65536)
+    VCX_TRY(kt->allow_lds(s->lds_grad, s->lds_flux, s->lds_fused));
+  s->tile_block = std::min(256, ((d.max_tile_cells + 63) / 64) * 64);
+  s->node_blocks = (int)((d.nn + kNodeBlock - 1) / kNodeBlock);
+  s->nsh_blocks = std::max(1, (d.nshared + kNodeBlock - 1) / kNodeBlock);
+  return VCX_OK;
+}
+
+extern "C" vcx_status vcx_solver_create(vcx_mesh mesh, const vcx_physics* phys, const double* E,
+                                        vcx_solver* out) {
+  if (!mesh || !phys || !out) return fail(VCX_E_ARG, "NULL argument");
+  *out = nullptr;
+  const vcx_physics& ph = *phys;
+  const int nd = mesh->h.nd;
+  const KernelTable* kt = nullptr;
+  VCX_TRY(check_physics(mesh, ph, E, &kt));
+  vcx_solver s = new (std::nothrow) vcx_solver_s();
+  if (!s) return fail(VCX_E_OOM, "host allocation failed");
+  {
+    vcx_status cs = configure_solver(s, mesh, ph, kt);
+    if (cs != VCX_OK) {
       delete s;
-      return st;
+      return cs;
     }
   }
-  s->tile_block = std::min(256, ((d.max_tile_cells + 63) / 64) * 64);
+  const DevMesh& d = mesh->d;
   const SolverSizes z = solver_sizes(d, nd, s->nvar, s->nr, s->nw, s->ngf, ph.model);
   s->bytes = z.bytes();
   vcx_status st = VCX_OK;
@@ -567,6 +605,19 @@ extern "C" vcx_status vcx_state_upload(vcx_solver s, const double* U, int is_dev
   return reset_scalars(s, 0.0, true);
 }
 
+extern "C" vcx_status vcx_state_upload_primitive(vcx_solver s, const double* P, int is_device) {
+  if (!s || !P) return fail(VCX_E_ARG, "NULL argument");
+  const DevMesh& d = s->mesh->d;
+  VCX_TRY(copy_in(s, P, s->nvar, is_device));
+  hipLaunchKernelGGL(k_gather_rows, dim3((d.nn + 255) / 256), dim3(256), 0, s->mesh->stream,
+                     d.perm, (const double*)s->io, s->W[s->cur], d.nn, s->nvar);
+  VCX_HIP(hipGetLastError());
+  VCX_TRY(s->kt->prim_to_cons(s, s->W[s->cur]));
+  VCX_TRY(s->kt->aux(s, s->W[s->cur]));
+  s->has_state = true;
+  return reset_scalars(s, 0.0, true);
+}
+
 extern "C" vcx_status vcx_state_set_time(vcx_solver s, double t) {
   if (!s) return fail(VCX_E_ARG, "NULL solver");
   if (!s->has_state) return fail(VCX_E_STATE, "no state uploaded");
@@ -586,19 +637,6 @@ extern "C" vcx_status vcx_gradient(vcx_solver s, double* G, int is_device) {
   VCX_TRY(s->kt->grad(s, s->W[s->cur], gc));
   VCX_TRY(s->kt->grad_complete(s));
   return copy_out(s, s->G, (size_t)s->nr * s->nd, G, is_device);
-}
-
-static Finish make_finish(vcx_solver s) {
-  Finish f{};
-  f.cbuf = s->cbuf;
-  f.G = s->G;
-  f.PG = s->PG;
-  f.E = s->E;
-  f.dc = dt_coef(s->ph);
-  f.mix = mix_params(s->ph);
-  f.closure = s->ph.closure;
-  f.gfull = s->fused && s->gout != nullptr;
-  return f;
 }
 
 extern "C" vcx_status vcx_residual(vcx_solver s, double dt, double* r, int is_device) {

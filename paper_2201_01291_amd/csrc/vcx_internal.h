@@ -145,6 +145,7 @@ struct KernelTable {
   vcx_status (*aux)(vcx_solver, double* W);
   vcx_status (*batch_stage)(const struct BatchRun& br, hipStream_t stream, const BatchStage& st, bool prof);
   vcx_status (*closure2)(vcx_solver, const Finish& f);
+  vcx_status (*prim_to_cons)(vcx_solver, double* W);
   int nw, ngf;
 };
 
@@ -471,13 +472,34 @@ struct Impl {
       return vcx::fail(VCX_E_ARG, "the interpolated closure is defined on plane 2D meshes");
     }
   }
+  static vcx_status prim_to_cons(vcx_solver s, double* W) {
+    const DevMesh& m = s->mesh->d;
+    hipLaunchKernelGGL((k_prim_to_cons<ND, NSP, MODEL>), dim3((m.nn + 255) / 256), dim3(256), 0,
+                       s->mesh->stream, W, m.nn, s->ph.gamma, mix_params(s->ph));
+    VCX_HIP(hipGetLastError());
+    return VCX_OK;
+  }
   static const KernelTable* table() {
     static const KernelTable t{&grad,     &grad_complete, &flux,      &update_shared, &node_dt,
                                &lds_grad, &lds_flux,      &lds_fused, &fused,         &allow_lds,
-                               &aux,      &batch_stage,   &closure2,  NW,             NGF};
+                               &aux,      &batch_stage,   &closure2,  &prim_to_cons,  NW,
+                               NGF};
     return &t;
   }
 };
+
+inline Finish make_finish(vcx_solver s) {
+  Finish f{};
+  f.cbuf = s->cbuf;
+  f.G = s->G;
+  f.PG = s->PG;
+  f.E = s->E;
+  f.dc = dt_coef(s->ph);
+  f.mix = mix_params(s->ph);
+  f.closure = s->ph.closure;
+  f.gfull = s->fused && s->gout != nullptr;
+  return f;
+}
 
 // Kernel tables by model (one translation unit each); nullptr for an
 // unsupported species count or flux.
@@ -486,6 +508,10 @@ const KernelTable* pick_table_gas2(const vcx_physics& ph);
 const KernelTable* pick_table_gas3(const vcx_physics& ph);
 const KernelTable* pick_table_dd(int nd, const vcx_physics& ph);
 const KernelTable* pick_table_ns(int nd, const vcx_physics& ph);
+// validate physics against a mesh and pick its table (vcx_capi.hip)
+vcx_status check_physics(vcx_mesh mesh, const vcx_physics& ph, const double* E, const KernelTable** kt);
+// host-side configuration of a solver: sizes, LDS, fused pass, launch shapes
+vcx_status configure_solver(vcx_solver s, vcx_mesh mesh, const vcx_physics& ph, const KernelTable* kt);
 }  // namespace vcx
 
 template <int MODEL, int ND, int NSP>

@@ -1844,6 +1844,41 @@ __global__ void VCX_FLUX_BOUNDS k_flux_ns(DevMesh m, const double* __restrict__ 
   flux_ns_body<ND, NSP, CT>(m, W, G, PR, gp, f, t, lds);
 }
 
+// Primitive rows -> conserved rows, in place on the first nvar rows of W:
+// gas (rho, u, p, Y) with the constant-gamma ideal gas; multi-species
+// (rho, u, T, Y) with the mixture's sensible energy e_s(T); drift-diffusion
+// densities are left as they are.
+template <int ND, int NSP, int MODEL>
+__global__ void __launch_bounds__(256) k_prim_to_cons(double* __restrict__ W, int nn, double gamma,
+                                                      MixParams mp) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (MODEL == 1 || i >= nn) return;
+  const double rho = W[i];
+  double ke = 0.0;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    const double u = W[(size_t)(1 + d) * nn + i];
+    ke += u * u;
+    W[(size_t)(1 + d) * nn + i] = rho * u;
+  }
+  double Y[NSP > 0 ? NSP : 1];
+#pragma unroll
+  for (int k = 0; k < NSP; ++k) {
+    Y[k] = W[(size_t)(2 + ND + k) * nn + i];
+    W[(size_t)(2 + ND + k) * nn + i] = rho * Y[k];
+  }
+  const double q = W[(size_t)(1 + ND) * nn + i];  // p (gas) or T (multi-species)
+  double e;
+  if constexpr (MODEL == 2) {
+    double es, cv;
+    mix_es_cv<NSP>(mp, Y, q, es, cv);
+    e = rho * (es + 0.5 * ke);
+  } else {
+    e = q / (gamma - 1.0) + 0.5 * rho * ke;
+  }
+  W[(size_t)(1 + ND) * nn + i] = e;
+}
+
 // multi-species node rows (p, primitives, aux) of an uploaded state
 template <int ND, int NSP>
 __global__ void __launch_bounds__(256) k_ns_aux(double* __restrict__ W, int nn, MixParams mp) {
@@ -2193,6 +2228,20 @@ static __global__ void k_scatter_rows(const int32_t* __restrict__ perm, const do
 }
 
 // pressure row of the gas reconstructed variables from the conserved rows
+// Space charge rho / eps0 = (e / eps0) sum_s z_s n_s of a drift-diffusion
+// state (internal order) into q (caller order).
+static __global__ void __launch_bounds__(256) k_space_charge(const double* __restrict__ W, int nn, int nsp,
+                                                             double z0, double z1, double z2, double z3,
+                                                             double e_eps0, const int32_t* __restrict__ perm,
+                                                             double* __restrict__ q) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nn) return;
+  const double z[4] = {z0, z1, z2, z3};
+  double c = 0.0;
+  for (int k = 0; k < nsp && k < 4; ++k) c += z[k] * W[(size_t)k * nn + i];
+  q[perm[i]] = e_eps0 * c;
+}
+
 static __global__ void k_pressure(double* W, int nn, int nd, int nsp, double gamma) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nn) return;

@@ -588,7 +588,7 @@ __global__ void __launch_bounds__(kThreads) k_gather(PoissonDev P, const double*
 
 // E = -grad phi at the nodes (phi in internal order), out in caller order.
 __global__ void __launch_bounds__(kThreads) k_field(PoissonDev P, const double* __restrict__ phi,
-                                                     double* __restrict__ E) {
+                                                     const double* bg, double* E) {
   const int i = blockIdx.x * kThreads + threadIdx.x;
   if (i >= P.n) return;
   double e[3] = {0.0, 0.0, 0.0};
@@ -596,8 +596,12 @@ __global__ void __launch_bounds__(kThreads) k_field(PoissonDev P, const double* 
     const double f = phi[P.col[q]];
     for (int d = 0; d < P.nd; ++d) e[d] += P.gval[(size_t)d * P.nnz + q] * f;
   }
+  // caller order; a background field (caller order, may alias E) is added
   const int o = P.perm[i];
-  for (int d = 0; d < P.nd; ++d) E[(size_t)d * P.n + o] = e[d];
+  for (int d = 0; d < P.nd; ++d) {
+    const size_t k = (size_t)d * P.n + o;
+    E[k] = bg ? bg[k] + e[d] : e[d];
+  }
 }
 
 // Host assembly: per node, the (column, value, gradient weights) entries of
@@ -1029,7 +1033,7 @@ extern "C" vcx_status vcx_poisson_solve(vcx_poisson p, const double* q, const do
   return VCX_OK;
 }
 
-extern "C" vcx_status vcx_poisson_field(vcx_poisson p, const double* phi, double* E, int is_device) {
+static vcx_status field(vcx_poisson p, const double* phi, const double* Ebg, double* E, int is_device) {
   if (!p || !phi || !E) return err(VCX_E_ARG, "NULL argument");
   const double* dphi;
   vcx_status st = stage_in(p, phi, 0, is_device, &dphi);
@@ -1038,10 +1042,35 @@ extern "C" vcx_status vcx_poisson_field(vcx_poisson p, const double* phi, double
   double* tmp = p->stage + (size_t)p->n;  // phi in the internal order
   hipLaunchKernelGGL(k_gather, g1, block, 0, p->stream, p->P, dphi, tmp);
   double* rows = is_device ? E : p->fbuf;
-  hipLaunchKernelGGL(k_field, g1, block, 0, p->stream, p->P, (const double*)tmp, rows);
+  const double* bg = Ebg;
+  if (Ebg && !is_device) {  // host background: staged in the output rows
+    PS_HIP(hipMemcpyAsync(p->fbuf, Ebg, sizeof(double) * (size_t)p->nd * p->n, hipMemcpyHostToDevice,
+                          p->stream));
+    bg = p->fbuf;
+  }
+  hipLaunchKernelGGL(k_field, g1, block, 0, p->stream, p->P, (const double*)tmp, bg, rows);
   PS_HIP(hipGetLastError());
   if (!is_device)
     PS_HIP(hipMemcpyAsync(E, p->fbuf, sizeof(double) * (size_t)p->nd * p->n, hipMemcpyDeviceToHost, p->stream));
   PS_HIP(hipStreamSynchronize(p->stream));
+  return VCX_OK;
+}
+
+extern "C" vcx_status vcx_poisson_field(vcx_poisson p, const double* phi, double* E, int is_device) {
+  return field(p, phi, nullptr, E, is_device);
+}
+
+extern "C" vcx_status vcx_poisson_field_add(vcx_poisson p, const double* phi, const double* Ebg, double* E,
+                                            int is_device) {
+  if (!Ebg) return err(VCX_E_ARG, "NULL background field");
+  return field(p, phi, Ebg, E, is_device);
+}
+
+extern "C" vcx_status vcx_poisson_info(vcx_poisson p, int64_t out[4]) {
+  if (!p || !out) return err(VCX_E_ARG, "NULL argument");
+  out[0] = p->n;
+  out[1] = p->P.nnz;
+  out[2] = p->bicg ? 0 : p->P.nc;
+  out[3] = p->bicg ? 1 : 0;
   return VCX_OK;
 }

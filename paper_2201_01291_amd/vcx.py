@@ -29,13 +29,14 @@ MAX_SPECIES = 16
 EXPORTS = (
     "vcx_mesh_create", "vcx_mesh_create_tiled", "vcx_mesh_destroy", "vcx_mesh_info", "vcx_mesh_geometry",
     "vcx_mesh_preprocess", "vcx_solver_create", "vcx_solver_destroy", "vcx_solver_nvar",
-    "vcx_state_upload", "vcx_state_download", "vcx_state_set_time", "vcx_gradient",
+    "vcx_state_upload", "vcx_state_upload_primitive", "vcx_state_download", "vcx_state_set_time", "vcx_gradient",
     "vcx_residual", "vcx_timestep", "vcx_step", "vcx_steps_done", "vcx_state_time", "vcx_solve_batch",
     "vcx_solve_batch_eager", "vcx_solver_footprint", "vcx_server_create", "vcx_server_submit",
     "vcx_server_poll", "vcx_server_wait", "vcx_server_stats", "vcx_server_destroy",
     "vcx_conservation_sums", "vcx_profile_enable", "vcx_profile_query", "vcx_last_error",
     "vcx_solver_set_field", "vcx_poisson_create", "vcx_poisson_destroy", "vcx_poisson_solve",
-    "vcx_poisson_field", "vcx_mesh_create_axisymmetric",
+    "vcx_poisson_field", "vcx_poisson_field_add", "vcx_poisson_info", "vcx_solver_charge",
+    "vcx_mesh_create_axisymmetric",
 )
 
 
@@ -103,6 +104,7 @@ def lib():
         L.vcx_solver_nvar.argtypes = [vp]
         L.vcx_solver_nvar.restype = C.c_int
         L.vcx_state_upload.argtypes = [vp, vp, C.c_int]
+        L.vcx_state_upload_primitive.argtypes = [vp, vp, C.c_int]
         L.vcx_state_download.argtypes = [vp, vp, C.c_int]
         L.vcx_state_set_time.argtypes = [vp, C.c_double]
         L.vcx_gradient.argtypes = [vp, vp, C.c_int]
@@ -134,6 +136,9 @@ def lib():
         L.vcx_poisson_solve.argtypes = [vp, vp, vp, vp, vp, C.c_int, C.c_double, C.c_int,
                                         C.POINTER(C.c_int), dp]
         L.vcx_poisson_field.argtypes = [vp, vp, vp, C.c_int]
+        L.vcx_poisson_field_add.argtypes = [vp, vp, vp, vp, C.c_int]
+        L.vcx_poisson_info.argtypes = [vp, i64p]
+        L.vcx_solver_charge.argtypes = [vp, vp, C.c_int]
         for name in EXPORTS:
             if name not in ("vcx_solver_nvar", "vcx_steps_done", "vcx_last_error"):
                 getattr(L, name).restype = C.c_int
@@ -264,6 +269,23 @@ class Solver:
             U = _f64(U)
         p, dev = _ptr(U)
         _check(lib().vcx_state_upload(self.h, p, dev), "vcx_state_upload")
+
+    def charge(self, out=None):
+        """Space charge (e/eps0) sum_s z_s n_s of a drift-diffusion state
+        (vcx_solver_charge), host array or into a device tensor."""
+        if out is None:
+            out = np.zeros(self.mesh.nnodes)
+        p, dev = _ptr(out)
+        _check(lib().vcx_solver_charge(self.h, p, dev), "vcx_solver_charge")
+        return out
+
+    def upload_primitive(self, P):
+        """State from primitive rows (gas: rho, u, p, Y; Navier-Stokes: rho,
+        u, T, Y), converted by the library's equation of state."""
+        if not _is_device_tensor(P):
+            P = _f64(P)
+        p, dev = _ptr(P)
+        _check(lib().vcx_state_upload_primitive(self.h, p, dev), "vcx_state_upload_primitive")
 
     def set_field(self, E):
         """Replace the drift-diffusion field E [ndim][nnodes] (host or device)."""
@@ -461,7 +483,8 @@ class Poisson:
                                        C.byref(it), C.byref(rel)), "vcx_poisson_solve")
         return out, it.value, rel.value
 
-    def field(self, phi, out=None):
+    def field(self, phi, out=None, background=None):
+        """E = -grad phi, or E = background - grad phi (vcx_poisson_field_add)."""
         dev = _is_device_tensor(phi)
         n, nd = self.mesh.nnodes, self.mesh.ndim
         if out is None:
@@ -472,11 +495,24 @@ class Poisson:
                 out = np.zeros((nd, n))
         if dev:
             pp, op = C.c_void_p(phi.data_ptr()), C.c_void_p(out.data_ptr())
+            bp = C.c_void_p(background.data_ptr()) if background is not None else None
         else:
             phi = _f64(phi)
             pp, op = C.c_void_p(phi.ctypes.data), C.c_void_p(out.ctypes.data)
-        _check(lib().vcx_poisson_field(self.h, pp, op, int(dev)), "vcx_poisson_field")
+            if background is not None:
+                background = _f64(background)
+            bp = C.c_void_p(background.ctypes.data) if background is not None else None
+        if background is None:
+            _check(lib().vcx_poisson_field(self.h, pp, op, int(dev)), "vcx_poisson_field")
+        else:
+            _check(lib().vcx_poisson_field_add(self.h, pp, bp, op, int(dev)), "vcx_poisson_field_add")
         return out
+
+    def info(self) -> dict:
+        out = np.zeros(4, dtype=np.int64)
+        _check(lib().vcx_poisson_info(self.h, out.ctypes.data_as(C.POINTER(C.c_int64))), "vcx_poisson_info")
+        return dict(rows=int(out[0]), nnz=int(out[1]), coarse=int(out[2]),
+                    solver="BiCGStab" if out[3] else "CG")
 
     def close(self):
         if getattr(self, "h", None):

@@ -455,6 +455,51 @@ def synthetic_mixture(nspecies: int = 9, seed: int = 3) -> Mixture:
                    Sc=rng.uniform(0.4, 1.2, size=nspecies))
 
 
+def _lattice_fields(mesh: Mesh, nfields_y: int, lattice: int, rng, ranges):
+    """Dirichlet(1) fractions and uniform scalar fields drawn on a periodic
+    lattice^nd lattice and interpolated (multi)linearly to the nodes."""
+    nd = mesh.ndim
+    shape = (lattice,) * nd
+    Yl = rng.dirichlet(np.ones(nfields_y), size=shape)
+    Sl = [rng.uniform(lo, hi, size=shape) for lo, hi in ranges]
+    lengths = mesh.period if mesh.period is not None else (mesh.xyz.max(1) - mesh.xyz.min(1))
+    lo = mesh.xyz.min(1)
+    t = [(mesh.xyz[a] - lo[a]) / lengths[a] * lattice for a in range(nd)]
+    i0 = [np.floor(ta).astype(np.int64) for ta in t]
+    fr = [ta - ia for ta, ia in zip(t, i0)]
+    Y = np.zeros((nfields_y, mesh.nnodes))
+    S = [np.zeros(mesh.nnodes) for _ in ranges]
+    for corner in np.ndindex(*(2,) * nd):
+        w = np.ones(mesh.nnodes)
+        idx = []
+        for a in range(nd):
+            w = w * (fr[a] if corner[a] else 1.0 - fr[a])
+            idx.append((i0[a] + corner[a]) % lattice)
+        Y += w[None, :] * Yl[tuple(idx)].T
+        for f, fl in zip(S, Sl):
+            f += w * fl[tuple(idx)]
+    return Y / Y.sum(axis=0, keepdims=True), S
+
+
+def ns_primitive_state(mesh: Mesh, mix: Mixture, *, seed: int = 4, lattice: int = 8,
+                       T_range=(300.0, 2000.0), p: float = 101325.0,
+                       vel=(100.0, 50.0, 25.0)) -> np.ndarray:
+    """Primitive multi-species state [rho, u_1..u_nd, T, Y_1..Y_n] of the 3D
+    multi-species workload: Dirichlet(1) mass fractions and T ~ U(300, 2000)
+    K drawn on a periodic lattice^nd lattice and interpolated to the nodes
+    (Y stays on the simplex, T inside the range), pressure 101325 Pa, so
+    rho = p W_mix / (R T) with the mixture molar mass of the drawn Y, and a
+    uniform velocity.  The library or the oracle turns it into conserved
+    variables with its own equation of state."""
+    rng = np.random.default_rng(seed)
+    Y, (T,) = _lattice_fields(mesh, mix.n, lattice, rng, [T_range])
+    r_mix = R_GAS * np.sum(Y / mix.W[:, None], axis=0)   # specific gas constant of the draw
+    rho = p / (r_mix * T)
+    nd = mesh.ndim
+    velv = np.tile(np.asarray(vel[:nd], dtype=np.float64)[:, None], (1, mesh.nnodes))
+    return np.stack([rho, *velv, T, *Y])
+
+
 def ns_state(mesh: Mesh, mix: Mixture, *, seed: int = 4, lattice: int = 8,
              theta_range=(300.0, 2000.0), rho_range=(0.2, 1.2),
              vel=(100.0, 50.0, 25.0), cv_scale: float = 718.0) -> np.ndarray:

@@ -276,3 +276,43 @@ def test_full_size_ns3d_properties():
     dev = np.abs(U32 - U64).max(axis=1) / np.abs(U64).max(axis=1)
     print("ns3d full: mixed state vs FP64 after 2 steps", dev)
     assert dev.max() <= 1e-5
+
+
+@pytest.mark.parametrize("kind", ["ns3d", "gas2d-sp2"])
+def test_primitive_upload_matches_the_oracle_conversion(kind):
+    """vcx_state_upload_primitive converts (rho, u, T, Y) or (rho, u, p, Y)
+    with the library's equation of state: the conserved state equals the
+    oracle's conversion of the same primitives to 1e-14, and the residual of
+    that state matches the oracle's within the FP64 bar."""
+    from paper_2201_01291_amd import workloads as wl
+    import cases
+    if kind == "ns3d":
+        mix = wl.synthetic_mixture(9, seed=3)
+        m = wl.kuhn_tet_mesh(5, 5, 4, 0.01, 0.01, 0.008, jitter=0.1, seed=9)
+        P = wl.ns_primitive_state(m, mix, lattice=3, seed=2)
+        scheme = dict(model="ns", flux="hllc", limiter="vanleer", rk=2, nspecies=9, mixture=mix)
+    else:
+        m = wl.tri_rect_mesh(16, 12, jitter=0.2, seed=3, periodic=True)
+        rng = np.random.default_rng(4)
+        Y = rng.dirichlet(np.ones(2), size=m.nnodes).T
+        P = np.stack([rng.uniform(0.5, 1.5, m.nnodes), rng.uniform(-0.3, 0.3, m.nnodes),
+                      rng.uniform(-0.3, 0.3, m.nnodes), rng.uniform(0.5, 1.0, m.nnodes), *Y])
+        scheme = dict(model="gas", flux="hllc", limiter="minmod", rk=2, nspecies=2)
+    case = cases.Case(f"prim-{kind}", m, None, None, scheme)
+    ph = case.oracle_phys()
+    Uo = oracle.conserved_from_primitive(m.ndim, ph, P)
+    case.U = Uo
+    print(f"[case] {case.name} nn={m.nnodes} T range "
+          f"{P[1 + m.ndim].min():.1f}..{P[1 + m.ndim].max():.1f}", flush=True)
+    gm = vcx.Mesh(m)
+    s = vcx.Solver(gm, case.vcx_phys(), None)
+    s.upload_primitive(P)
+    Ug = s.download()
+    rel = np.abs(Ug - Uo).max(axis=1) / np.abs(Uo).max(axis=1)
+    print("conversion rel err", rel)
+    assert rel.max() <= 1e-14
+    om = oracle.OracleMesh(m)
+    dt = om.timestep(ph, Uo)
+    err = normwise(s.residual(dt), om.residual(ph, Uo, None, dt), om.flux_scale(ph, Uo, None, dt))
+    print("residual err", err)
+    assert err.max() <= FP64_TOL

@@ -191,8 +191,13 @@ def test_step_coupled_to_the_poisson_field_matches_the_oracle():
     ps = vcx.Poisson(gm)
     s = vcx.Solver(gm, case.vcx_phys(), Ebg)
     s.upload(n)
-    phi, it, _ = ps.solve(q, tol=TOL)
-    E = Ebg + ps.field(phi)
+    # the whole coupled step through the library: charge from the solver's
+    # state, solve, field with the background, step
+    qg = s.charge()
+    assert np.abs(qg - q).max() <= 1e-14 * np.abs(q).max()
+    phi, it, _ = ps.solve(qg, tol=TOL)
+    E = ps.field(phi, background=Ebg)
+    assert np.array_equal(E, Ebg + ps.field(phi))
     s.set_field(E)
     t, _ = s.step(1)
     print("coupled: iterations", it, "max |E - E_o| / max |E_o|", np.abs(E - E_o).max() / np.abs(E_o).max())
@@ -202,6 +207,29 @@ def test_step_coupled_to_the_poisson_field_matches_the_oracle():
     err = (np.abs(U - U_o).max(axis=1) / np.abs(U_o).max(axis=1))
     print("coupled state err", err)
     assert err.max() <= 1e-8
+
+
+def test_device_charge_and_field_with_background_in_place():
+    """Device-side coupled step: vcx_solver_charge into a device tensor, and
+    vcx_poisson_field_add writing E over its own background (aliased)."""
+    import cases
+    m = wl.dd_streamer_mesh(30, 20)
+    n, E0 = wl.dd_fields(m, sigma=2e-3)
+    case = cases.Case("dd-charge", m, n, E0, dict(cases.DD2))
+    gm = vcx.Mesh(m)
+    s = vcx.Solver(gm, case.vcx_phys(), E0)
+    s.upload(n)
+    qd = torch.empty(m.nnodes, dtype=torch.float64, device="cuda")
+    s.charge(out=qd)
+    torch.cuda.synchronize()
+    assert np.array_equal(qd.cpu().numpy(), s.charge())
+    ps = vcx.Poisson(gm)
+    phi, _, _ = ps.solve(qd, tol=TOL)
+    E = torch.tensor(E0, device="cuda")
+    ps.field(phi, out=E, background=E)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(E.cpu().numpy(), ps.field(phi.cpu().numpy(), background=E0))
+    assert ps.info()["coarse"] > 0 and ps.info()["rows"] == m.nnodes
 
 
 def _axi_strip(nx=40, nr=20, seed=2):

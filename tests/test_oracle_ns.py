@@ -75,6 +75,38 @@ def test_temperature_inverts_the_integrated_heat_capacity():
         assert out[1] == pytest.approx(rho * T_true * R * np.sum(Y / mix.W), rel=1e-11)
 
 
+def test_conserved_from_primitive_matches_the_quadrature_energy():
+    """(rho, u, T, Y) -> conserved state: the energy is rho (e_s + |u|^2/2)
+    with e_s the quadrature of c_p - R/W from 298.15 K (independent of the
+    oracle's closed-form enthalpies), and the node state of that conserved
+    vector returns the same T (300-2000 K, the multi-species workload's
+    range)."""
+    mix = wl.synthetic_mixture(9, seed=3)
+    ph = _phys(mix)
+    rng = np.random.default_rng(5)
+    for T in (300.0, 777.0, 1400.0, 2000.0):
+        Y = rng.dirichlet(np.ones(9))
+        rho, u = 0.6, np.array([100.0, 50.0, 25.0])
+        es = 0.0
+        for k in range(9):
+            Rk = R / mix.W[k]
+            cp = lambda t: Rk * (mix.cp_a[k] + mix.cp_b[k] * t / 1000 + mix.cp_c[k] * (t / 1000) ** 2)
+            es += Y[k] * (integrate.quad(cp, 298.15, T, epsabs=0, epsrel=1e-13)[0] - Rk * T)
+        U = oracle.ns_conserved(3, ph, np.concatenate([[rho], u, [T], Y]))
+        np.testing.assert_allclose(U[:4], [rho, *(rho * u)], rtol=1e-15)
+        assert U[4] == pytest.approx(rho * (es + 0.5 * u @ u), rel=1e-12)
+        np.testing.assert_allclose(U[5:], rho * Y, rtol=1e-15)
+        assert oracle.ns_node(3, ph, U)[0] == pytest.approx(T, rel=1e-12)
+
+
+def test_gas_conserved_from_primitive_by_hand():
+    """Constant-gamma gas: rho E = p / (gamma - 1) + rho |u|^2 / 2."""
+    ph = oracle.Phys(gamma=1.4, nspecies=1)
+    P = np.array([[2.0], [3.0], [-1.0], [0.8], [0.25]])
+    U = oracle.conserved_from_primitive(2, ph, P)
+    np.testing.assert_allclose(U[:, 0], [2.0, 6.0, -2.0, 0.8 / 0.4 + 0.5 * 2.0 * 10.0, 0.5])
+
+
 def _aux(mu, lam, D, hs):
     return np.concatenate([[1.4, mu, lam], D, hs])
 
