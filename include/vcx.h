@@ -244,6 +244,30 @@ vcx_status vcx_gradient(vcx_solver s, double *G, int is_device);
  * only used by the limited Lax-Wendroff flux. */
 vcx_status vcx_residual(vcx_solver s, double dt, double *r, int is_device);
 
+/* Allocation-free variant of vcx_residual, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the residual of the state U on this mesh with this
+ * physics, without a solver.
+ *   U    device [nvar][nnodes], caller's node order (read)
+ *   E    drift-diffusion: device [ndim][nnodes] field, caller order; else NULL
+ *   dt   used by the limited Lax-Wendroff flux only
+ *   r    device [nvar][nnodes], caller order (written)
+ * Result: bit for bit that of vcx_residual on a solver of the same mesh and
+ * physics holding U.  The call allocates nothing: every intermediate array
+ * (reconstructed rows, nodal gradients, tile partials, the field in internal
+ * order) lives in one static device array of vcx_noalloc_scratch_bytes()
+ * (64 MiB) per device, which the library holds until the process ends.
+ * Meshes and physics that need more return VCX_E_ARG (e.g. 2D
+ * drift-diffusion up to about 300k nodes).  All calls on one device share
+ * that array and the work runs on the mesh's stream; the call returns once
+ * it is complete, so calls must not overlap on one GPU (several threads or
+ * streams at once race).  Errors: VCX_E_ARG (NULL argument, unsupported
+ * physics, too large), VCX_E_HIP. */
+vcx_status vcx_residual_noalloc(vcx_mesh mesh, const vcx_physics *phys, const double *U,
+                                const double *E, double dt, double *r);
+/* Bytes of the per-device scratch array of vcx_residual_noalloc. */
+size_t vcx_noalloc_scratch_bytes(void);
+
 /* CFL / Fourier time step of the current state (minimum over cells and
  * species). */
 vcx_status vcx_timestep(vcx_solver s, double *dt);

@@ -36,7 +36,8 @@ EXPORTS = (
     "vcx_conservation_sums", "vcx_profile_enable", "vcx_profile_query", "vcx_last_error",
     "vcx_solver_set_field", "vcx_poisson_create", "vcx_poisson_destroy", "vcx_poisson_solve",
     "vcx_poisson_field", "vcx_poisson_field_add", "vcx_poisson_info", "vcx_solver_charge",
-    "vcx_mesh_create_axisymmetric",
+    "vcx_mesh_create_axisymmetric", "vcx_residual_noalloc",
+    "vcx_noalloc_scratch_bytes",
 )
 
 
@@ -139,8 +140,12 @@ def lib():
         L.vcx_poisson_field_add.argtypes = [vp, vp, vp, vp, C.c_int]
         L.vcx_poisson_info.argtypes = [vp, i64p]
         L.vcx_solver_charge.argtypes = [vp, vp, C.c_int]
+        L.vcx_residual_noalloc.argtypes = [vp, C.POINTER(Physics), vp, vp, C.c_double, vp]
+        L.vcx_noalloc_scratch_bytes.argtypes = []
+        L.vcx_noalloc_scratch_bytes.restype = C.c_size_t
         for name in EXPORTS:
-            if name not in ("vcx_solver_nvar", "vcx_steps_done", "vcx_last_error"):
+            if name not in ("vcx_solver_nvar", "vcx_steps_done", "vcx_last_error",
+                            "vcx_noalloc_scratch_bytes"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -524,6 +529,24 @@ class Poisson:
             self.close()
         except Exception:
             pass
+
+
+def residual_noalloc(mesh: "Mesh", phys: Physics, U, E=None, dt: float = 0.0, out=None):
+    """vcx_residual_noalloc: residual of the device state U (torch tensor,
+    [nvar][nnodes]) without a solver and without device allocation in the
+    library; E a device [ndim][nnodes] field for drift-diffusion; out a
+    device tensor like U (allocated here by torch when None)."""
+    import torch
+    if out is None:
+        out = torch.empty_like(U)
+    ep = C.c_void_p(E.data_ptr()) if E is not None else None
+    _check(lib().vcx_residual_noalloc(mesh.h, C.byref(phys), C.c_void_p(U.data_ptr()), ep, float(dt),
+                                      C.c_void_p(out.data_ptr())), "vcx_residual_noalloc")
+    return out
+
+
+def noalloc_scratch_bytes() -> int:
+    return int(lib().vcx_noalloc_scratch_bytes())
 
 
 def solve_batch(solvers, nsteps, t_end=None, graphs=True):
