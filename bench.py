@@ -299,7 +299,7 @@ def pick_tiles(w, prec, a, override=""):
     from paper_2201_01291_amd import autotune
     if override:
         return tuple(int(v) for v in override.split(",")), "command line"
-    tc, tn, src = autotune.pick_tiles(w.mesh, w.vphys(prec), w.U0, w.E, tune_if_missing=a.autotune)
+    tc, tn, src = autotune.pick_tiles(w.mesh, w.vphys(prec), w.upload, w.E, tune_if_missing=a.autotune)
     if src == "default":
         return (0, 0), "library default"
     return (tc, tn), src

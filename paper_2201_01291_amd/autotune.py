@@ -67,7 +67,8 @@ def device_arch() -> str:
 def time_candidate(mesh, physes, U, E, tiles, steps: int, repeats: int):
     """Seconds per step of vcx_step on mesh with the given tiles, best of
     repeats, for each physics in physes (None where the library rejects the
-    tile size); the mesh is built once for all of them."""
+    tile size); the mesh is built once for all of them.  U is the conserved
+    state, or a callable that uploads the state into a solver."""
     import torch
     from . import vcx
     try:
@@ -83,12 +84,13 @@ def time_candidate(mesh, physes, U, E, tiles, steps: int, repeats: int):
                 out.append(None)
                 continue
             try:
-                s.upload(U)
+                put = U if callable(U) else (lambda sv: sv.upload(U))   # state upload
+                put(s)
                 s.step(max(2, steps // 5))
                 torch.cuda.synchronize()
                 best = math.inf
                 for _ in range(repeats):
-                    s.upload(U)
+                    put(s)
                     torch.cuda.synchronize()
                     t0 = time.perf_counter()
                     s.step(steps)
@@ -159,9 +161,10 @@ def _main():
     arch = device_arch()
     for name in names:
         print(f"[tune] building {name}", flush=True)
-        m, U, E, phys = bench.workload(name)[:4]
-        physes = [phys(0), phys(1)]
-        entries = tune_many(m, physes, U, E, steps=10 if name == "ns3d" else 50,
+        w = bench.Workload(name)
+        m = w.mesh
+        physes = [w.vphys(0), w.vphys(1)]
+        entries = tune_many(m, physes, w.upload, w.E, steps=10 if name == "ns3d" else 50,
                             log=lambda line: print(f"[tune] {name} {line}", flush=True))
         for ph, entry in zip(physes, entries):
             store(path, tune_key(arch, m.ndim, ph, m.ncells), entry)

@@ -109,6 +109,33 @@ extern "C" vcx_status vcx_mesh_create_axisymmetric(int64_t nnodes, const double*
                      out);
 }
 
+// Build (host) and upload (device) the tile-edge tables of a mesh, once.
+vcx_status vcx::ensure_tile_edges(vcx_mesh m) {
+  if (m->d.has_edges) return VCX_OK;
+  std::string err = build_tile_edges(m->h);
+  if (!err.empty()) return fail(VCX_E_MESH, err);
+  const HostMesh& h = m->h;
+  DevMesh& d = m->d;
+  const int32_t *te = nullptr, *ece = nullptr, *sei = nullptr;
+  const uint32_t* ed = nullptr;
+  const uint16_t *ce = nullptr, *ei = nullptr;
+  VCX_TRY(upload(m, h.tile_edge, &te));
+  VCX_TRY(upload(m, h.edge, &ed));
+  VCX_TRY(upload(m, h.edge_ce, &ece));
+  VCX_TRY(upload(m, h.ce, &ce));
+  VCX_TRY(upload(m, h.slot_einc, &sei));
+  VCX_TRY(upload(m, h.einc, &ei));
+  d.tile_edge = te;
+  d.edge = ed;
+  d.edge_ce = ece;
+  d.ce = ce;
+  d.slot_einc = sei;
+  d.einc = ei;
+  d.max_tile_edges = h.max_tile_edges;
+  d.has_edges = 1;
+  return VCX_OK;
+}
+
 static vcx_status create_mesh(int ndim, int64_t nnodes, const double* xyz, int64_t ncells, int nv,
                               const int64_t* cells, const double* period, int max_tile_cells,
                               int max_tile_nodes, void* stream, bool axi, vcx_mesh* out) {
@@ -232,6 +259,9 @@ static vcx_status create_mesh(int ndim, int64_t nnodes, const double* xyz, int64
     chk(upload(m, h.bedge_S, &d.bedge_S));
   }
   chk(upload(m, h.perm, &d.perm));
+  // tile-edge tables of the multi-species flux pass: 3D meshes at creation,
+  // 2D meshes when their first Navier-Stokes solver is created
+  if (st == VCX_OK && h.nd == 3) st = ensure_tile_edges(m);
   if (st == VCX_OK) {
     // smallest inscribed diameter of the cells around each node (time step)
     void* p = nullptr;
@@ -477,7 +507,9 @@ vcx_status vcx::configure_solver(vcx_solver s, vcx_mesh mesh, const vcx_physics&
   s->kt = kt;
   const DevMesh& d = mesh->d;
   s->lds_grad = kt->lds_grad(d.max_tile_nodes, d.max_tile_cells);
-  s->lds_flux = kt->lds_flux(d.max_tile_nodes, d.max_tile_cells);
+  if (ph.model == VCX_MODEL_NAVIER_STOKES && !d.has_edges)
+    return fail(VCX_E_ARG, "the mesh has no tile-edge tables (created by the first Navier-Stokes solver)");
+  s->lds_flux = kt->lds_flux(d);
   if (s->lds_grad > (size_t)mesh->lds_max || s->lds_flux > (size_t)mesh->lds_max) {
     const size_t need = std::max(s->lds_grad, s->lds_flux);
     return fail(VCX_E_ARG, "tile LDS footprint " + std::to_string(need) + " B exceeds the device limit " +
@@ -496,6 +528,9 @@ vcx_status vcx::configure_solver(vcx_solver s, vcx_mesh mesh, const vcx_physics&
   if (std::max({s->lds_grad, s->lds_flux, s->lds_fused}) > 65536)
     VCX_TRY(kt->allow_lds(s->lds_grad, s->lds_flux, s->lds_fused));
   s->tile_block = std::min(256, ((d.max_tile_cells + 63) / 64) * 64);
+  s->flux_block = ph.model == VCX_MODEL_NAVIER_STOKES
+                      ? std::min(256, ((std::max(d.max_tile_cells, d.max_tile_edges) + 63) / 64) * 64)
+                      : s->tile_block;
   s->node_blocks = (int)((d.nn + kNodeBlock - 1) / kNodeBlock);
   s->nsh_blocks = std::max(1, (d.nshared + kNodeBlock - 1) / kNodeBlock);
   return VCX_OK;
@@ -509,6 +544,7 @@ extern "C" vcx_status vcx_solver_create(vcx_mesh mesh, const vcx_physics* phys, 
   const int nd = mesh->h.nd;
   const KernelTable* kt = nullptr;
   VCX_TRY(check_physics(mesh, ph, E, &kt));
+  if (ph.model == VCX_MODEL_NAVIER_STOKES) VCX_TRY(ensure_tile_edges(mesh));
   vcx_solver s = new (std::nothrow) vcx_solver_s();
   if (!s) return fail(VCX_E_OOM, "host allocation failed");
   {
@@ -894,7 +930,7 @@ vcx_status vcx::batch_set(BatchGroup* g, vcx_solver* ss, int n, const int* steps
   std::vector<BatchEntry> tab(n);
   std::vector<int2> tmap, smap;
   size_t lg = 0, lf = 0, lfu = 0;
-  int block = 64;
+  int block = 64, fblock = 64;
   g->steps0.resize(n);
   g->phase0.resize(n);
   g->spar0.resize(n);
@@ -912,6 +948,7 @@ vcx_status vcx::batch_set(BatchGroup* g, vcx_solver* ss, int n, const int* steps
     lf = std::max(lf, s->lds_flux);
     lfu = std::max(lfu, s->lds_fused);
     block = std::max(block, s->tile_block);
+    fblock = std::max(fblock, s->flux_block);
   }
   const bool fused = lead->fused;
   const int lds_max = lead->mesh->lds_max;
@@ -956,6 +993,7 @@ vcx_status vcx::batch_set(BatchGroup* g, vcx_solver* ss, int n, const int* steps
   br.fused = fused;
   br.lds_flux = fused ? lfu : lf;
   br.tile_block = std::min(256, block);
+  br.flux_block = std::min(256, fblock);
   if (g->graphs && !lead->prof) {
     hipGraph_t graph = nullptr;
     VCX_HIP(hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal));

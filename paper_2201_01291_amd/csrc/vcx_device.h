@@ -89,9 +89,19 @@ __device__ inline void normal_flux(const T* W, const T* n, T* F, T& q) {
   for (int k = 0; k < NSP; ++k) F[2 + ND + k] = W[2 + ND + k] * q;
 }
 
+// Normal velocity q = (rho u . n) / rho of a reconstructed state, as
+// normal_flux forms it.
+template <int ND, typename T>
+__device__ inline T normal_velocity(const T* W, const T* n) {
+  T q = T(0);
+  for (int d = 0; d < ND; ++d) q += W[1 + d] * n[d];
+  return q * (T(1) / W[0]);
+}
+
 // HLLC flux through the area vector S (result scaled by |S|), Davis wave
 // speeds, star states of the paper's multicomponent HLLC; gL, gR: ratio of
-// specific heats of the left and right states.
+// specific heats of the left and right states.  Only the physical flux of
+// the side a branch needs is formed.
 template <int ND, int NSP, typename T>
 __device__ inline void hllc_flux(const T* WL, const T* WR, const T* S, T gL, T gR, T* F) {
   constexpr int NV = 2 + ND + NSP;
@@ -100,23 +110,22 @@ __device__ inline void hllc_flux(const T* WL, const T* WR, const T* S, T gL, T g
   const T A = sqrt(A2), iA = T(1) / A;
   T n[ND];
   for (int d = 0; d < ND; ++d) n[d] = S[d] * iA;
-  T FL[NV], FR[NV], qL, qR;
-  normal_flux<ND, NSP>(WL, n, FL, qL);
-  normal_flux<ND, NSP>(WR, n, FR, qR);
+  const T qL = normal_velocity<ND>(WL, n), qR = normal_velocity<ND>(WR, n);
   const T rL = WL[0], rR = WR[0], pL = WL[NV], pR = WR[NV];
   const T aL = sqrt(gL * pL / rL), aR = sqrt(gR * pR / rR);
   const T SL = fmin(qL - aL, qR - aR), SR = fmax(qL + aL, qR + aR);
   const T mL = rL * (SL - qL), mR = rR * (SR - qR);
   const T Ss = (pR - pL + mL * qL - mR * qR) / (mL - mR);
-  if (T(0) <= SL) {
-    for (int v = 0; v < NV; ++v) F[v] = A * FL[v];
-  } else if (SR < T(0)) {
-    for (int v = 0; v < NV; ++v) F[v] = A * FR[v];
+  // the side whose flux the branch starts from
+  const bool left = (T(0) <= SL) || (!(SR < T(0)) && T(0) <= Ss);
+  T W[NV + 1];
+  for (int v = 0; v <= NV; ++v) W[v] = left ? WL[v] : WR[v];
+  T FK[NV], qK;
+  normal_flux<ND, NSP>(W, n, FK, qK);
+  if (T(0) <= SL || SR < T(0)) {
+    for (int v = 0; v < NV; ++v) F[v] = A * FK[v];
   } else {
-    const bool left = T(0) <= Ss;
-    const T* W = left ? WL : WR;
-    const T* FK = left ? FL : FR;
-    const T SK = left ? SL : SR, qK = left ? qL : qR, rK = W[0], pK = W[NV];
+    const T SK = left ? SL : SR, rK = W[0], pK = W[NV];
     const T irK = T(1) / rK;
     const T fac = rK * (SK - qK) / (SK - Ss);
     const T dq = Ss - qK;
@@ -267,60 +276,58 @@ __device__ inline bool ns_node_state(const MixParams& mp, const double* u, doubl
   return rho > 0.0 && T > 0.0 && isfinite(T) && isfinite(p);
 }
 
-// Central diffusive flux through S of the multi-species Navier-Stokes
-// equations: Newtonian stress with Stokes' hypothesis, Fourier heat flux plus
-// species enthalpy transport, Fick species fluxes with the correction velocity
-// V_c = sum_k D_k grad Y_k.  Face values are means of the two nodes (pi, pj:
-// prim rows; ai, aj: aux rows; gi, gj: prim gradients [NP][ND]).  Writes Fv =
-// (0, tau S, u.(tau S) - q.S, -J_k.S), to be subtracted from the convective
-// flux.
+// Face averages of the diffusive flux's node data: h (x_i + x_j) with h = 1/2.
 template <int ND, int NSP, typename T>
-__device__ inline void viscous_flux(const T* pi, const T* pj, T rhoi, T rhoj, const T* ai,
-                                    const T* aj, const T* gi, const T* gj, const T* S, T* Fv) {
-  const T h = T(0.5);
-  const T rho = h * (rhoi + rhoj), mu = h * (ai[1] + aj[1]), lam = h * (ai[2] + aj[2]);
-  T Gu[ND][ND], div = T(0);
+struct ViscousFace {
+  static constexpr int NP = ND + 1 + NSP;
+  T rho, mu, lam;
+  T p[NP];             // primitives (u, T, Y)
+  T D[NSP], hs[NSP];   // species diffusivities and sensible enthalpies
+  T g[NP * ND];        // gradients of the primitives, component q * ND + d
+};
+
+// Central diffusive flux through S of the multi-species Navier-Stokes
+// equations from face averages of the two nodes: Newtonian stress with
+// Stokes' hypothesis, Fourier heat flux plus species enthalpy transport, Fick
+// species fluxes with the correction velocity V_c = sum_k D_k grad Y_k.
+// Linear in S.  Writes Fv = (0, tau S, u.(tau S) - q.S, -J_k.S), to be
+// subtracted from the convective flux.
+template <int ND, int NSP, typename T>
+__device__ inline void viscous_flux_face(const ViscousFace<ND, NSP, T>& a, const T* S, T* Fv) {
+  T div = T(0);
 #pragma unroll
-  for (int a = 0; a < ND; ++a) {
-#pragma unroll
-    for (int b = 0; b < ND; ++b) Gu[a][b] = h * (gi[a * ND + b] + gj[a * ND + b]);
-    div += Gu[a][a];
-  }
+  for (int d = 0; d < ND; ++d) div += a.g[d * ND + d];
   T utS = T(0);
 #pragma unroll
-  for (int a = 0; a < ND; ++a) {
+  for (int i = 0; i < ND; ++i) {
     T ts = T(0);
 #pragma unroll
-    for (int b = 0; b < ND; ++b) ts += (Gu[a][b] + Gu[b][a]) * S[b];
-    ts = mu * (ts - T(2.0 / 3.0) * div * S[a]);
-    Fv[1 + a] = ts;
-    utS += h * (pi[a] + pj[a]) * ts;
+    for (int j = 0; j < ND; ++j) ts += (a.g[i * ND + j] + a.g[j * ND + i]) * S[j];
+    ts = a.mu * (ts - T(2.0 / 3.0) * div * S[i]);
+    Fv[1 + i] = ts;
+    utS += a.p[i] * ts;
   }
   T Vc[ND];
 #pragma unroll
   for (int d = 0; d < ND; ++d) Vc[d] = T(0);
 #pragma unroll
-  for (int k = 0; k < NSP; ++k) {
-    const T Dk = h * (ai[3 + k] + aj[3 + k]);
+  for (int k = 0; k < NSP; ++k)
 #pragma unroll
-    for (int d = 0; d < ND; ++d) Vc[d] += Dk * h * (gi[(ND + 1 + k) * ND + d] + gj[(ND + 1 + k) * ND + d]);
-  }
+    for (int d = 0; d < ND; ++d) Vc[d] += a.D[k] * a.g[(ND + 1 + k) * ND + d];
   T VcS = T(0), gTS = T(0);
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
     VcS += Vc[d] * S[d];
-    gTS += h * (gi[ND * ND + d] + gj[ND * ND + d]) * S[d];
+    gTS += a.g[ND * ND + d] * S[d];
   }
-  T qS = -lam * gTS;
+  T qS = -a.lam * gTS;
 #pragma unroll
   for (int k = 0; k < NSP; ++k) {
-    const T Dk = h * (ai[3 + k] + aj[3 + k]);
-    const T Yk = h * (pi[ND + 1 + k] + pj[ND + 1 + k]);
     T gYS = T(0);
 #pragma unroll
-    for (int d = 0; d < ND; ++d) gYS += h * (gi[(ND + 1 + k) * ND + d] + gj[(ND + 1 + k) * ND + d]) * S[d];
-    const T JS = -rho * (Dk * gYS - Yk * VcS);
-    qS += h * (ai[3 + NSP + k] + aj[3 + NSP + k]) * JS;
+    for (int d = 0; d < ND; ++d) gYS += a.g[(ND + 1 + k) * ND + d] * S[d];
+    const T JS = -a.rho * (a.D[k] * gYS - a.p[ND + 1 + k] * VcS);
+    qS += a.hs[k] * JS;
     Fv[2 + ND + k] = -JS;
   }
   Fv[0] = T(0);

@@ -83,6 +83,7 @@ struct vcx_solver_s {
   double* gout = nullptr;  // fused passes: node gradients for the boundary closure, or null
   double* cbuf = nullptr;  // second closure option: [nb][nvar] closure fluxes of the stage input
   int tile_block = 256;
+  int flux_block = 256;  // block of the flux tile pass (multi-species: covers the tile's edges)
   size_t bytes = 0;  // device bytes held by the solver (mesh excluded)
   // profiling
   bool prof = false;
@@ -138,7 +139,7 @@ struct KernelTable {
   vcx_status (*update_shared)(vcx_solver, const Finish& f);
   vcx_status (*node_dt)(vcx_solver, const double* W);
   size_t (*lds_grad)(int maxn, int maxc);
-  size_t (*lds_flux)(int maxn, int maxc);
+  size_t (*lds_flux)(const DevMesh& d);
   size_t (*lds_fused)(const DevMesh& d);  // 0: no fused pass for this model
   vcx_status (*fused)(vcx_solver, const double* Win, const Finish& f, const FusedCtl& fc, double dt_host);
   vcx_status (*allow_lds)(size_t grad_bytes, size_t flux_bytes, size_t fused_bytes);
@@ -158,7 +159,7 @@ struct BatchRun {
   int2* sh_map;
   int nsh_blocks;
   size_t lds_grad, lds_flux;
-  int tile_block;
+  int tile_block, flux_block;
   bool fused;
 };
 
@@ -207,21 +208,15 @@ struct Impl {
     constexpr int FG = grad_group(NGF);  // fields staged per pass
     return sizeof(double) * ((size_t)(FG + ND) * maxn + (size_t)FG * ND * maxc) + inc_lds_bytes(NV, maxc);
   }
-  static size_t lds_flux(int maxn, int maxc) {
+  static size_t lds_flux(const DevMesh& d) {
+    const int maxn = d.max_tile_nodes, maxc = d.max_tile_cells;
     if constexpr (MODEL == 0 && cell_halves<ND, CT>() == 2)  // two planes of vertex parts
       return sizeof(double) * ((size_t)ND * maxn + (size_t)2 * NV * NVAR * maxc) +
              sizeof(CT) * (size_t)(NR + NR * ND) * maxn + slot_lds_bytes(maxn) + inc_lds_bytes(NV, maxc);
     if constexpr (MODEL == 1 && cell_halves<ND, CT>() == 2)
       return sizeof(double) * ((size_t)ND * maxn + (size_t)2 * NV * NVAR * maxc) +
              sizeof(CT) * (size_t)(NSP + NSP * ND + ND) * maxn + slot_lds_bytes(maxn) + inc_lds_bytes(NV, maxc);
-    if constexpr (MODEL == 2) {
-      // the vertex parts overlay the staged fields when the block has a
-      // thread per cell (tile_block covers up to 256 cells)
-      const size_t wg = ns_field_bytes(sizeof(CT) * (size_t)(NW + NGF * ND) * maxn);
-      const size_t r = sizeof(double) * (size_t)NV * NVAR * maxc;
-      return sizeof(double) * (size_t)ND * maxn + ns_area_bytes(wg, r, maxc <= 256) + slot_lds_bytes(maxn) +
-             inc_lds_bytes(NV, maxc);
-    }
+    if constexpr (MODEL == 2) return NsEdgeLds<ND, NSP, CT>::lds_bytes(maxn, maxc, d.max_tile_edges);
     size_t dbl = sizeof(double) * ((size_t)ND * maxn + (size_t)NV * NVAR * maxc);
     size_t ct = MODEL == 0   ? (size_t)(NR + NR * ND) * maxn
                 : MODEL == 1 ? (size_t)(NSP + NSP * ND + ND) * maxn
@@ -314,7 +309,7 @@ struct Impl {
     } else if constexpr (MODEL == 2) {
       GasParams gp{s->ph.gamma, s->ph.beta, s->ph.entropy_fix, s->ph.limiter};
       return launch(s, "flux", [&](hipEvent_t ea, hipEvent_t eb) {
-        hipExtLaunchKernelGGL((k_flux_ns<ND, NSP, CT>), dim3(xcd_grid(m.ntiles)), dim3(s->tile_block),
+        hipExtLaunchKernelGGL((k_flux_ns<ND, NSP, CT>), dim3(xcd_grid(m.ntiles)), dim3(s->flux_block),
                            s->lds_flux, st, ea, eb, 0, m, Win, (const double*)s->G, s->PR, gp, f);
       });
     } else {
@@ -437,7 +432,7 @@ struct Impl {
       GasParams gp{s->ph.gamma, s->ph.beta, s->ph.entropy_fix, s->ph.limiter};
       VCX_TRY(launch_on(s, stream, prof, "flux", [&](hipEvent_t ea, hipEvent_t eb) {
         hipExtLaunchKernelGGL((k_flux_ns_batch<ND, NSP, CT>), dim3(xcd_grid(br.ntile_blocks)),
-                           dim3(br.tile_block), br.lds_flux, stream, ea, eb, 0, (const BatchEntry*)br.tab,
+                           dim3(br.flux_block), br.lds_flux, stream, ea, eb, 0, (const BatchEntry*)br.tab,
                            (const int2*)br.tile_map, br.ntile_blocks, st, gp, fs);
       }));
     } else {
@@ -510,6 +505,8 @@ const KernelTable* pick_table_dd(int nd, const vcx_physics& ph);
 const KernelTable* pick_table_ns(int nd, const vcx_physics& ph);
 // validate physics against a mesh and pick its table (vcx_capi.hip)
 vcx_status check_physics(vcx_mesh mesh, const vcx_physics& ph, const double* E, const KernelTable** kt);
+// tile-edge tables of a mesh (host build and device upload, once)
+vcx_status ensure_tile_edges(vcx_mesh m);
 // host-side configuration of a solver: sizes, LDS, fused pass, launch shapes
 vcx_status configure_solver(vcx_solver s, vcx_mesh mesh, const vcx_physics& ph, const KernelTable* kt);
 }  // namespace vcx

@@ -86,6 +86,15 @@ struct DevMesh {
   const double* bedge_S;     // [nd][nbe]
   int nbe;
   const int32_t* perm;       // [nn] internal -> caller
+  // tile edges (the multi-species flux pass): distinct edges of each tile's
+  // cells, their cell-edges, and each slot's incident edges
+  int has_edges, max_tile_edges;
+  const int32_t* tile_edge;  // [T+1]
+  const uint32_t* edge;      // [E] la | lb << 12 | image << 24
+  const int32_t* edge_ce;    // [E+1] CSR into ce
+  const uint16_t* ce;        // [nc*ne] (local cell << 4) | (cell-local edge << 1) | reversed
+  const int32_t* slot_einc;  // [P+1] CSR into einc
+  const uint16_t* einc;      // [2E] (tile edge << 1) | (slot's node is end b)
 };
 
 // Per-solve device scalars of the time loop: the state of one step.
@@ -365,16 +374,35 @@ __host__ __device__ inline size_t inc_lds_bytes(int nv, int maxc) {
   return ((size_t)nv * maxc * sizeof(uint16_t) + 7) / 8 * 8;
 }
 
-// Multi-species flux pass: bytes of the staged fields and gradients
-// (rounded to doubles), and of that area together with the cells' vertex
-// parts, which overlay it when each thread holds one cell.
-__host__ __device__ inline size_t ns_field_bytes(size_t b) { return (b + 7) / 8 * 8; }
-__host__ __device__ inline size_t ns_area_bytes(size_t field_bytes, size_t part_bytes, bool overlay) {
-  return overlay ? (field_bytes > part_bytes ? field_bytes : part_bytes) : field_bytes + part_bytes;
-}
-
 // bytes of a tile's slot table in LDS
 __host__ __device__ inline size_t slot_lds_bytes(int maxn) { return (size_t)4 * maxn * sizeof(int); }
+
+// LDS of the edge-based multi-species flux pass, in order: node coordinates
+// (double), the tile edges' net fluxes (double [NVAR][maxe]), the cell-edge
+// dual-face vectors (CT [ND][maxc * ne]), the node staging area of the two
+// phases (CT rows: A = reconstructed rows, gamma and their gradients; B =
+// rho, primitives, transport rows and the gradients of the primitives), the
+// slot table and the slots' edge incidences.
+template <int ND, int NSP, typename CT>
+struct NsEdgeLds {
+  static constexpr int NVAR = 2 + ND + NSP, NR = NVAR + 1, NP = ND + 1 + NSP, NA = 3 + 2 * NSP;
+  static constexpr int NCE = ND == 2 ? 3 : 6;  // cell-edges per cell
+  // FP64 forms D_k and h_s,k at the edge ends from mu, rho and T; FP32 stages them
+  static constexpr bool RECOMPUTE = sizeof(CT) == 8;
+  static constexpr int RA = NR + 1, CA = NR * ND;
+  static constexpr int RB = 1 + NP + (RECOMPUTE ? 2 : NA - 1), CB = NP * ND;
+  __host__ __device__ static size_t r8(size_t b) { return (b + 7) / 8 * 8; }
+  __host__ __device__ static size_t x_bytes(int maxn) { return sizeof(double) * (size_t)ND * maxn; }
+  __host__ __device__ static size_t f_bytes(int maxe) { return sizeof(double) * (size_t)NVAR * maxe; }
+  __host__ __device__ static size_t s_bytes(int maxc) { return r8(sizeof(CT) * (size_t)ND * maxc * NCE); }
+  __host__ __device__ static size_t area_bytes(int maxn) {
+    return r8(sizeof(CT) * (size_t)(RA + CA > RB + CB ? RA + CA : RB + CB) * maxn);
+  }
+  __host__ __device__ static size_t lds_bytes(int maxn, int maxc, int maxe) {
+    return x_bytes(maxn) + f_bytes(maxe) + s_bytes(maxc) + area_bytes(maxn) + slot_lds_bytes(maxn) +
+           r8(sizeof(uint16_t) * 2 * (size_t)maxe);
+  }
+};
 
 // Decision of a step from the state it starts from: commit the previous
 // step unless it failed, then start this one (or stop at the end time, the
@@ -1674,139 +1702,264 @@ __global__ void VCX_FUSED_BOUNDS k_fused(DevMesh m, const double* __restrict__ W
 // first NR + NP rows.
 // ---------------------------------------------------------------------------
 
+// Stage gradient components [C0, C0 + NCS) of the NC components of a node
+// into LDS (sG [NCS][maxn]): from G for a tile-owned node, or the sum of the
+// slot partials of a shared node in ascending partial order (the same for
+// every reader).
+template <int NC, int C0, int NCS, int ND, typename CT>
+__device__ inline void stage_gradient_part(const DevMesh& m, const double* __restrict__ G,
+                                           const double* __restrict__ PG, int sv, int2 run, CT* sG,
+                                           int maxn, int q) {
+  if (sv >= 0) {
+    constexpr int JC = NCS <= 32 ? NCS : 16;
+    for (int j0 = 0; j0 < NCS; j0 += JC) {
+      double v[JC];
+#pragma unroll
+      for (int jj = 0; jj < JC; ++jj)
+        if (j0 + jj < NCS) v[jj] = G[(size_t)(C0 + j0 + jj) * m.nn + sv];
+#pragma unroll
+      for (int jj = 0; jj < JC; ++jj)
+        if (j0 + jj < NCS) sG[(j0 + jj) * maxn + q] = CT(v[jj]);
+    }
+    return;
+  }
+  const int g = ~sv;
+  const double coef = -m.inv_vol[g] / double(ND * (ND + 1));
+  constexpr int JC = NCS <= 24 ? NCS : 12;
+  for (int j0 = 0; j0 < NCS; j0 += JC) {
+    double acc[JC];
+#pragma unroll
+    for (int jj = 0; jj < JC; ++jj) acc[jj] = 0.0;
+    int p = run.x;
+    for (; p + 1 < run.y; p += 2) {
+      const double* s0 = PG + (size_t)p * NC + C0 + j0;
+      const double* s1 = s0 + NC;
+      double a[JC], b[JC];
+#pragma unroll
+      for (int jj = 0; jj < JC; ++jj)
+        if (j0 + jj < NCS) {
+          a[jj] = s0[jj];
+          b[jj] = s1[jj];
+        }
+#pragma unroll
+      for (int jj = 0; jj < JC; ++jj)
+        if (j0 + jj < NCS) acc[jj] = (acc[jj] + a[jj]) + b[jj];
+    }
+    if (p < run.y) {
+      const double* s0 = PG + (size_t)p * NC + C0 + j0;
+#pragma unroll
+      for (int jj = 0; jj < JC; ++jj)
+        if (j0 + jj < NCS) acc[jj] += s0[jj];
+    }
+#pragma unroll
+    for (int jj = 0; jj < JC; ++jj)
+      if (j0 + jj < NCS) sG[(j0 + jj) * maxn + q] = CT(coef * acc[jj]);
+  }
+}
+
+// Rows [r0, r0 + N) of node g into LDS rows [d0, d0 + N) (loads first).
+template <int N, typename CT>
+__device__ inline void stage_rows(const double* __restrict__ W, size_t nn, int g, int r0, CT* s, int d0,
+                                  int maxn, int q) {
+  double w[N];
+#pragma unroll
+  for (int v = 0; v < N; ++v) w[v] = W[(size_t)(r0 + v) * nn + g];
+#pragma unroll
+  for (int v = 0; v < N; ++v) s[(d0 + v) * maxn + q] = CT(w[v]);
+}
+
+// Multi-species flux tile pass over the tile's distinct edges.  For an edge
+// (a, b) the MUSCL face states (virtual-node reconstruction with the nodal
+// gradients) depend on its two nodes only, so they are formed once per edge;
+// the HLLC flux is taken for each of the edge's cell-edges with that cell's
+// dual-face vector (the flux is not linear in it); the central diffusive
+// flux is linear in the dual-face vector, so it is taken once with their
+// sum.  The edge's net flux F goes to node a as +F and to node b as -F; each
+// node sums its edges in a fixed order (node pass), then the update.
 template <int ND, int NSP, typename CT>
 __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ W,
-                                          const double* __restrict__ G,
-                                          double* __restrict__ PR, GasParams gp, Finish f, int t, double* lds) {
-  constexpr int NV = ND + 1, NVAR = 2 + ND + NSP, NR = NVAR + 1, NE = Edges<ND>::NE;
-  constexpr int NP = ND + 1 + NSP, NA = 3 + 2 * NSP, NG = NR + NP;
+                                    const double* __restrict__ G,
+                                    double* __restrict__ PR, GasParams gp, Finish f, int t, double* lds) {
+  using L = NsEdgeLds<ND, NSP, CT>;
+  constexpr int NV = ND + 1, NVAR = 2 + ND + NSP, NR = NVAR + 1, NCE = L::NCE;
+  constexpr int NP = ND + 1 + NSP, NA = 3 + 2 * NSP, NC = (NR + NP) * ND;
+  constexpr int RA = L::RA, CA = L::CA, RB = L::RB, CB = L::CB;
   if (step_inactive(f.sc)) return;
-  TilePre<NV> tp;
-  tile_prefetch<NV>(m, t, tp);
-  const int maxn = m.max_tile_nodes, maxc = m.max_tile_cells;
-  // with one cell per thread, the cells' vertex parts overlay the staged
-  // fields and gradients once every edge flux is done
-  const bool overlay = maxc <= (int)blockDim.x;
-  double* sX = lds;                                        // [ND][maxn]
-  char* area = reinterpret_cast<char*>(sX + ND * maxn);
-  CT* sW = reinterpret_cast<CT*>(area);                    // [NR + NP + NA][maxn]
-  CT* sG = sW + (NR + NP + NA) * maxn;                     // [NG*ND][maxn]
-  const size_t wgb = ns_field_bytes(sizeof(CT) * (size_t)(NR + NP + NA + NG * ND) * maxn);
-  const size_t rb = sizeof(double) * (size_t)NV * NVAR * maxc;
-  double* sR = reinterpret_cast<double*>(overlay ? area : area + wgb);  // [NV*NVAR][maxc]
-  int* sSl = reinterpret_cast<int*>(area + ns_area_bytes(wgb, rb, overlay));
-  uint16_t* sInc = reinterpret_cast<uint16_t*>(sSl + 4 * maxn);
-  const int nc = tp.nc, ns = tp.ns;
-  for (int q = threadIdx.x; q < ns; q += blockDim.x) {
-    const SlotTopo st = slot_topo<NV>(m, tp, q);
-    slot_table_put(sSl, maxn, q, st.sv, st.pos, st.p0, st.p1);
-    const int sv = st.sv;
-    const int g = slot_node_id(sv);
-    double xx[ND];
-#pragma unroll
-    for (int d = 0; d < ND; ++d) xx[d] = m.x[(size_t)d * m.nn + g];
-    constexpr int NWR = NR + NP + NA, WC = 16;
-    for (int v0 = 0; v0 < NWR; v0 += WC) {
-      double w[WC];
-#pragma unroll
-      for (int vv = 0; vv < WC; ++vv)
-        if (v0 + vv < NWR) w[vv] = W[(size_t)(v0 + vv) * m.nn + g];
-#pragma unroll
-      for (int vv = 0; vv < WC; ++vv)
-        if (v0 + vv < NWR) sW[(v0 + vv) * maxn + q] = CT(w[vv]);
-    }
-    stage_gradient<NG * ND, ND, CT>(m, G, f.PG, sv, st.run, sG, maxn, q);
-#pragma unroll
-    for (int d = 0; d < ND; ++d) sX[d * maxn + q] = xx[d];
-  }
-  tile_store_inc<NV>(m, tp, sInc);
-  __syncthreads();
+  const int c0 = m.tile_cell[t], nc = m.tile_cell[t + 1] - c0;
+  const int s0 = m.tile_slot[t], ns = m.tile_slot[t + 1] - s0;
+  const int e0 = m.tile_edge[t], ne = m.tile_edge[t + 1] - e0;
+  const int pb = m.slot_einc[s0], ninc = m.slot_einc[s0 + ns] - pb;
+  const int maxn = m.max_tile_nodes, maxc = m.max_tile_cells, maxe = m.max_tile_edges;
+  const int mce = maxc * NCE;
+  char* base = reinterpret_cast<char*>(lds);
+  double* sX = reinterpret_cast<double*>(base);                      // [ND][maxn]
+  double* sF = reinterpret_cast<double*>(base + L::x_bytes(maxn));   // [NVAR][maxe]
+  CT* sS = reinterpret_cast<CT*>(base + L::x_bytes(maxn) + L::f_bytes(maxe));  // [ND][maxc*NCE]
+  CT* sW = reinterpret_cast<CT*>(base + L::x_bytes(maxn) + L::f_bytes(maxe) + L::s_bytes(maxc));
+  int* sSl = reinterpret_cast<int*>(reinterpret_cast<char*>(sW) + L::area_bytes(maxn));
+  uint16_t* sEi = reinterpret_cast<uint16_t*>(sSl + 4 * maxn);
   const CT beta = CT(gp.beta);
-  double acc[NV][NVAR];
+
+  // ---- phase A staging: coordinates, reconstructed rows, gamma, gradients
+  {
+    CT* sG = sW + RA * maxn;
+    for (int q = threadIdx.x; q < ns; q += blockDim.x) {
+      const int sl = s0 + q;
+      const int sv = m.slot_node[sl];
+      slot_table_put(sSl, maxn, q, sv, m.slot_pos[sl], m.slot_einc[sl] - pb, m.slot_einc[sl + 1] - pb);
+      const int g = slot_node_id(sv);
+      double xx[ND];
+#pragma unroll
+      for (int d = 0; d < ND; ++d) xx[d] = m.x[(size_t)d * m.nn + g];
+      stage_rows<NR, CT>(W, m.nn, g, 0, sW, 0, maxn, q);
+      stage_rows<1, CT>(W, m.nn, g, NR + NP, sW, NR, maxn, q);
+      stage_gradient_part<NC, 0, CA, ND, CT>(m, G, f.PG, sv, m.slot_run[sl], sG, maxn, q);
+#pragma unroll
+      for (int d = 0; d < ND; ++d) sX[d * maxn + q] = xx[d];
+    }
+    for (int p = threadIdx.x; p < ninc; p += blockDim.x) sEi[p] = m.einc[pb + p];
+  }
+  __syncthreads();
+  // ---- dual-face vectors of every cell-edge: S_ab = (S_a - S_b) / (n_d n_v)
   for (int lc = threadIdx.x; lc < nc; lc += blockDim.x) {
     int l[NV];
-    uint32_t sh;
-    cell_topo<NV>(m, tp, lc, l, sh);
+#pragma unroll
+    for (int k = 0; k < NV; ++k) l[k] = m.lconn[(size_t)k * m.nc + c0 + lc];
     double e[ND][ND], Sd[NV][ND];
-    cell_rel_coords<ND>(m, sX, maxn, l, sh, e);
+    cell_rel_coords<ND>(m, sX, maxn, l, m.shift[c0 + lc], e);
     simplex_normals<ND>(e, Sd);
 #pragma unroll
-    for (int k = 0; k < NV; ++k)
+    for (int ed = 0; ed < NCE; ++ed) {
+      const int a = Edges<ND>::a(ed), b = Edges<ND>::b(ed);
 #pragma unroll
-      for (int v = 0; v < NVAR; ++v) acc[k][v] = 0.0;
-    // one edge at a time: the multi-species fluxes have many temporaries,
-    // and the cell vertex sums stay in registers (static indices)
-#pragma unroll 1
-    for (int ed = 0; ed < NE; ++ed) {
-      EdgeRolled<ND, CT> g;
-      if constexpr (ND == 3)
-        edge_uniform3<CT>(ed, l, e, Sd, g);
-      else
-        edge_rolled<ND, CT>(ed, l, e, Sd, g);
-      const int la = g.la, lb = g.lb;
-      const CT(&S)[ND] = g.S;
-      const CT(&dx)[ND] = g.dx;
-      CT WL[NR], WR[NR];
-#pragma unroll
-      for (int v = 0; v < NR; ++v) {
-        const CT wi = sW[v * maxn + la], wj = sW[v * maxn + lb];
-        CT gi = CT(0), gj = CT(0);
-#pragma unroll
-        for (int d = 0; d < ND; ++d) {
-          gi += sG[(v * ND + d) * maxn + la] * dx[d];
-          gj += sG[(v * ND + d) * maxn + lb] * dx[d];
-        }
-        const CT delta = wj - wi;
-        const CT dli = CT(2) * gi - delta, djk = CT(2) * gj - delta;
-        WL[v] = wi + CT(0.5) * slope_limit<CT>(gp.limiter, beta, dli, delta);
-        WR[v] = wj - CT(0.5) * slope_limit<CT>(gp.limiter, beta, delta, djk);
-      }
-      CT F[NVAR];
-      // each side's ratio of specific heats: first aux row of its node
-      hllc_flux<ND, NSP, CT>(WL, WR, S, sW[(NR + NP) * maxn + la], sW[(NR + NP) * maxn + lb], F);
-      // diffusive part from the primitive fields, their gradients and aux
-      CT pi[NP], pj[NP], ai[NA], aj[NA], gi[NP * ND], gj[NP * ND], Fv[NVAR];
-#pragma unroll
-      for (int q = 0; q < NP; ++q) {
-        pi[q] = sW[(NR + q) * maxn + la];
-        pj[q] = sW[(NR + q) * maxn + lb];
-      }
-#pragma unroll
-      for (int q = 0; q < NA; ++q) {
-        ai[q] = sW[(NR + NP + q) * maxn + la];
-        aj[q] = sW[(NR + NP + q) * maxn + lb];
-      }
-#pragma unroll
-      for (int q = 0; q < NP * ND; ++q) {
-        gi[q] = sG[(NR * ND + q) * maxn + la];
-        gj[q] = sG[(NR * ND + q) * maxn + lb];
-      }
-      viscous_flux<ND, NSP, CT>(pi, pj, sW[la], sW[lb], ai, aj, gi, gj, S, Fv);
-#pragma unroll
-      for (int v = 0; v < NVAR; ++v) {
-        const double fv = double(F[v]) - double(Fv[v]);
-#pragma unroll
-        for (int k = 0; k < NV; ++k) acc[k][v] = fma(fv, g.coef[k], acc[k][v]);
-      }
-    }
-    if (!overlay) {
-#pragma unroll
-      for (int k = 0; k < NV; ++k)
-#pragma unroll
-        for (int v = 0; v < NVAR; ++v) sR[(k * NVAR + v) * maxc + lc] = acc[k][v];
-    }
-  }
-  if (overlay) {
-    __syncthreads();  // every edge flux has read the staged fields
-    const int lc = threadIdx.x;
-    if (lc < nc) {
-#pragma unroll
-      for (int k = 0; k < NV; ++k)
-#pragma unroll
-        for (int v = 0; v < NVAR; ++v) sR[(k * NVAR + v) * maxc + lc] = acc[k][v];
+      for (int d = 0; d < ND; ++d)
+        sS[d * mce + lc * NCE + ed] = CT((Sd[a][d] - Sd[b][d]) * (1.0 / double(ND * NV)));
     }
   }
   __syncthreads();
+  // ---- convective flux of each edge: face states once, HLLC per cell-edge
+  for (int le = threadIdx.x; le < ne; le += blockDim.x) {
+    const CT* sG = sW + RA * maxn;
+    const uint32_t desc = m.edge[e0 + le];
+    const int la = desc & 4095u, lb = (desc >> 12) & 4095u;
+    CT dx[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      const uint32_t im = (desc >> (24 + 2 * d)) & 3u;
+      const double sh = im == 1u ? m.period[d] : (im == 2u ? -m.period[d] : 0.0);
+      dx[d] = CT(sX[d * maxn + lb] + sh - sX[d * maxn + la]);
+    }
+    CT WL[NR], WR[NR];
+#pragma unroll
+    for (int v = 0; v < NR; ++v) {
+      const CT wi = sW[v * maxn + la], wj = sW[v * maxn + lb];
+      CT gi = CT(0), gj = CT(0);
+#pragma unroll
+      for (int d = 0; d < ND; ++d) {
+        gi += sG[(v * ND + d) * maxn + la] * dx[d];
+        gj += sG[(v * ND + d) * maxn + lb] * dx[d];
+      }
+      const CT delta = wj - wi;
+      const CT dli = CT(2) * gi - delta, djk = CT(2) * gj - delta;
+      WL[v] = wi + CT(0.5) * slope_limit<CT>(gp.limiter, beta, dli, delta);
+      WR[v] = wj - CT(0.5) * slope_limit<CT>(gp.limiter, beta, delta, djk);
+    }
+    const CT gL = sW[NR * maxn + la], gR = sW[NR * maxn + lb];
+    double Fs[NVAR];
+#pragma unroll
+    for (int v = 0; v < NVAR; ++v) Fs[v] = 0.0;
+    const int q0 = m.edge_ce[e0 + le], q1 = m.edge_ce[e0 + le + 1];
+    for (int q = q0; q < q1; ++q) {
+      const int code = m.ce[q];
+      const int k = (code >> 4) * NCE + ((code >> 1) & 7);
+      const CT sg = (code & 1) ? CT(-1) : CT(1);
+      CT S[ND], F[NVAR];
+#pragma unroll
+      for (int d = 0; d < ND; ++d) S[d] = sg * sS[d * mce + k];
+      hllc_flux<ND, NSP, CT>(WL, WR, S, gL, gR, F);
+#pragma unroll
+      for (int v = 0; v < NVAR; ++v) Fs[v] += double(F[v]);
+    }
+#pragma unroll
+    for (int v = 0; v < NVAR; ++v) sF[v * maxe + le] = Fs[v];
+  }
+  __syncthreads();  // every convective flux has read phase A
+
+  // ---- phase B staging: rho, primitives, transport rows, primitive gradients
+  {
+    CT* sG = sW + RB * maxn;
+    for (int q = threadIdx.x; q < ns; q += blockDim.x) {
+      const int sl = s0 + q;
+      const int sv = m.slot_node[sl];
+      const int g = slot_node_id(sv);
+      stage_rows<1, CT>(W, m.nn, g, 0, sW, 0, maxn, q);
+      stage_rows<NP, CT>(W, m.nn, g, NR, sW, 1, maxn, q);
+      if constexpr (L::RECOMPUTE)
+        stage_rows<2, CT>(W, m.nn, g, NR + NP + 1, sW, 1 + NP, maxn, q);
+      else
+        stage_rows<NA - 1, CT>(W, m.nn, g, NR + NP + 1, sW, 1 + NP, maxn, q);
+      stage_gradient_part<NC, CA, CB, ND, CT>(m, G, f.PG, sv, m.slot_run[sl], sG, maxn, q);
+    }
+  }
+  __syncthreads();
+  // ---- diffusive flux of each edge, with the sum of its dual-face vectors
+  for (int le = threadIdx.x; le < ne; le += blockDim.x) {
+    const CT* sG = sW + RB * maxn;
+    const uint32_t desc = m.edge[e0 + le];
+    const int la = desc & 4095u, lb = (desc >> 12) & 4095u;
+    CT S[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) S[d] = CT(0);
+    const int q0 = m.edge_ce[e0 + le], q1 = m.edge_ce[e0 + le + 1];
+    for (int q = q0; q < q1; ++q) {
+      const int code = m.ce[q];
+      const int k = (code >> 4) * NCE + ((code >> 1) & 7);
+#pragma unroll
+      for (int d = 0; d < ND; ++d) S[d] = (code & 1) ? S[d] - sS[d * mce + k] : S[d] + sS[d * mce + k];
+    }
+    // face averages h (x_a + x_b) of the diffusive flux's node data
+    const CT h = CT(0.5);
+    ViscousFace<ND, NSP, CT> fa;
+    fa.rho = h * (sW[la] + sW[lb]);
+#pragma unroll
+    for (int q = 0; q < NP; ++q) fa.p[q] = h * (sW[(1 + q) * maxn + la] + sW[(1 + q) * maxn + lb]);
+    if constexpr (L::RECOMPUTE) {
+      const CT mui = sW[(1 + NP) * maxn + la], muj = sW[(1 + NP) * maxn + lb];
+      const CT rhoi = sW[la], rhoj = sW[lb];
+      fa.mu = h * (mui + muj);
+      fa.lam = h * (sW[(2 + NP) * maxn + la] + sW[(2 + NP) * maxn + lb]);
+      // D_k = mu / (rho Sc_k) and h_s,k(T) of each end, as the node state forms them
+      const double Ti = sW[(1 + ND) * maxn + la], Tj = sW[(1 + ND) * maxn + lb];
+      const double dTi = Ti - kT0, sTi = Ti + kT0, qTi = Ti * Ti + Ti * kT0 + kT0 * kT0;
+      const double dTj = Tj - kT0, sTj = Tj + kT0, qTj = Tj * Tj + Tj * kT0 + kT0 * kT0;
+#pragma unroll
+      for (int k = 0; k < NSP; ++k) {
+        fa.D[k] = h * (mui / (rhoi * f.mix.Sc[k]) + muj / (rhoj * f.mix.Sc[k]));
+        const double hi = kRgas / f.mix.W[k] * dTi *
+                          (f.mix.a[k] + f.mix.b[k] * sTi * (1.0 / 2000.0) + f.mix.c[k] * qTi * (1.0 / 3.0e6));
+        const double hj = kRgas / f.mix.W[k] * dTj *
+                          (f.mix.a[k] + f.mix.b[k] * sTj * (1.0 / 2000.0) + f.mix.c[k] * qTj * (1.0 / 3.0e6));
+        fa.hs[k] = h * (hi + hj);
+      }
+    } else {
+      fa.mu = h * (sW[(1 + NP) * maxn + la] + sW[(1 + NP) * maxn + lb]);
+      fa.lam = h * (sW[(2 + NP) * maxn + la] + sW[(2 + NP) * maxn + lb]);
+#pragma unroll
+      for (int k = 0; k < NSP; ++k) {
+        fa.D[k] = h * (sW[(3 + NP + k) * maxn + la] + sW[(3 + NP + k) * maxn + lb]);
+        fa.hs[k] = h * (sW[(3 + NP + NSP + k) * maxn + la] + sW[(3 + NP + NSP + k) * maxn + lb]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NP * ND; ++q) fa.g[q] = h * (sG[q * maxn + la] + sG[q * maxn + lb]);
+    CT Fv[NVAR];
+    viscous_flux_face<ND, NSP, CT>(fa, S, Fv);
+#pragma unroll
+    for (int v = 0; v < NVAR; ++v) sF[v * maxe + le] -= double(Fv[v]);
+  }
+  __syncthreads();
+
+  // ---- node pass: each slot sums its edges' fluxes in ascending edge order
   double cand = INFINITY;
   for (int q = threadIdx.x; q < ns; q += blockDim.x) {
     const SlotTopo st = slot_table_get(sSl, maxn, q);
@@ -1814,10 +1967,15 @@ __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ W,
 #pragma unroll
     for (int v = 0; v < NVAR; ++v) r[v] = 0.0;
     for (int p = st.p0; p < st.p1; ++p) {
-      const int code = sInc[p];
-      const int lc = code >> 2, k = code & 3;
+      const int code = sEi[p];
+      const int le = code >> 1;
+      if (code & 1) {
 #pragma unroll
-      for (int v = 0; v < NVAR; ++v) r[v] += sR[(k * NVAR + v) * maxc + lc];
+        for (int v = 0; v < NVAR; ++v) r[v] -= sF[v * maxe + le];
+      } else {
+#pragma unroll
+        for (int v = 0; v < NVAR; ++v) r[v] += sF[v * maxe + le];
+      }
     }
     if (st.sv >= 0) {
       NodeIn<NVAR, ND> nq;

@@ -482,4 +482,102 @@ void build_halos(HostMesh& m) {
   m.has_halo = m.max_ext_cells < 65536 && m.max_ext_nodes < 65536;
 }
 
+
+std::string build_tile_edges(HostMesh& m) {
+  if (m.has_edges) return "";
+  const int nd = m.nd, NE = m.ne;
+  const int64_t nc = m.nc, T = m.ntiles();
+  // local cell-edges (a, b), a < b, in the kernels' order
+  static const int E2[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+  static const int E3[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+  const int(*EE)[2] = nd == 2 ? E2 : E3;
+  m.tile_edge.assign(1, 0);
+  m.edge.clear();
+  m.edge_ce.assign(1, 0);
+  m.ce.clear();
+  m.ce.reserve((size_t)nc * NE);
+  m.slot_einc.assign(1, 0);
+  m.einc.clear();
+  m.max_tile_edges = 0;
+  // one record per cell-edge of a tile: its unordered end pair, its position
+  // in cell order, and its code
+  struct CE {
+    uint32_t key;  // min end << 16 | max end
+    int pos;
+    uint16_t code;
+    int la, lb;    // ends in the cell-edge's own orientation
+    uint32_t image;
+  };
+  struct Grp {
+    int begin, end, first;
+  };
+  std::vector<CE> rec;
+  std::vector<Grp> grp;
+  std::vector<int> cnt, fill;
+  std::vector<uint16_t> sinc;
+  for (int64_t t = 0; t < T; ++t) {
+    const int32_t c0 = m.tile_cell[t], c1 = m.tile_cell[t + 1];
+    const int ns = m.tile_slot[t + 1] - m.tile_slot[t];
+    if (ns > 4095 || (c1 - c0) > 2047) return "tile too large for the tile-edge tables";
+    rec.clear();
+    for (int32_t c = c0; c < c1; ++c) {
+      const int lc = c - c0;
+      for (int e = 0; e < NE; ++e) {
+        const int a = EE[e][0], b = EE[e][1];
+        const int la = m.lconn[(size_t)a * nc + c], lb = m.lconn[(size_t)b * nc + c];
+        uint32_t image = 0;
+        for (int d = 0; d < nd; ++d) {
+          const int sa = a == 0 ? 0 : shift_of(m.shift[c], a, d, nd);
+          const int sb = shift_of(m.shift[c], b, d, nd);
+          const int ds = sb - sa;
+          if (ds < -1 || ds > 1) return "cell edge spans more than one periodic image";
+          image |= (uint32_t)(ds == 1 ? 1u : (ds == -1 ? 2u : 0u)) << (2 * d);
+        }
+        const uint32_t key = la < lb ? ((uint32_t)la << 16 | (uint32_t)lb) : ((uint32_t)lb << 16 | (uint32_t)la);
+        rec.push_back(CE{key, (int)rec.size(), (uint16_t)((lc << 4) | (e << 1)), la, lb, image});
+      }
+    }
+    std::stable_sort(rec.begin(), rec.end(), [](const CE& x, const CE& y) { return x.key < y.key; });
+    grp.clear();
+    for (int i = 0; i < (int)rec.size();) {
+      int j = i;
+      while (j < (int)rec.size() && rec[j].key == rec[i].key) ++j;
+      grp.push_back(Grp{i, j, rec[i].pos});  // stable: rec[i] is the first appearance
+      i = j;
+    }
+    // descending cell-edge count, then first appearance
+    std::sort(grp.begin(), grp.end(), [](const Grp& x, const Grp& y) {
+      return (x.end - x.begin) != (y.end - y.begin) ? (x.end - x.begin) > (y.end - y.begin) : x.first < y.first;
+    });
+    if (grp.size() > 32767) return "tile too large for the tile-edge tables";
+    cnt.assign(ns + 1, 0);
+    for (const Grp& g : grp) {
+      ++cnt[rec[g.begin].la + 1];
+      ++cnt[rec[g.begin].lb + 1];
+    }
+    for (int q = 0; q < ns; ++q) cnt[q + 1] += cnt[q];
+    fill.assign(cnt.begin(), cnt.end() - 1);
+    sinc.assign(2 * grp.size(), 0);
+    for (size_t k = 0; k < grp.size(); ++k) {
+      const CE& f = rec[grp[k].begin];  // orientation and image of the first appearance
+      m.edge.push_back((uint32_t)f.la | ((uint32_t)f.lb << 12) | (f.image << 24));
+      for (int i = grp[k].begin; i < grp[k].end; ++i)
+        m.ce.push_back((uint16_t)(rec[i].code | (rec[i].la == f.la ? 0 : 1)));
+      m.edge_ce.push_back((int32_t)m.ce.size());
+      // each slot's incident edges, in ascending tile-edge order
+      sinc[fill[f.la]++] = (uint16_t)(k << 1);
+      sinc[fill[f.lb]++] = (uint16_t)((k << 1) | 1);
+    }
+    for (int q = 0; q < ns; ++q) {
+      for (int p = cnt[q]; p < cnt[q + 1]; ++p) m.einc.push_back(sinc[p]);
+      m.slot_einc.push_back((int32_t)m.einc.size());
+    }
+    m.tile_edge.push_back((int32_t)m.edge.size());
+    m.max_tile_edges = std::max(m.max_tile_edges, (int)grp.size());
+  }
+  if ((int64_t)m.ce.size() != nc * NE) return "tile-edge tables do not cover every cell-edge";
+  m.has_edges = true;
+  return "";
+}
+
 }  // namespace vcx

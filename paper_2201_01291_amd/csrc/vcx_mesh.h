@@ -74,6 +74,20 @@ struct HostMesh {
   std::vector<uint16_t> ginc;       // extended-local cells around each slot's node, ascending cell id
   int max_ext_cells = 0, max_ext_nodes = 0, max_tile_ginc = 0;
 
+  // tile edges: the distinct edges of each tile's cells (built on demand by
+  // build_tile_edges for the edge-based flux pass).  Within a tile, edges are
+  // ordered by descending number of cell-edges (ties: first appearance), so
+  // that the threads of a wavefront take edges with similar work.
+  bool has_edges = false;
+  std::vector<int32_t> tile_edge;  // [T+1] first tile edge of each tile
+  std::vector<uint32_t> edge;      // [E] la | lb << 12 | image << 24: tile-local ends a -> b and the
+                                   // periodic image of b relative to a (2 bits per axis: 1 -> +1, 2 -> -1)
+  std::vector<int32_t> edge_ce;    // [E+1] CSR into ce
+  std::vector<uint16_t> ce;        // [nc * ne] (local cell << 4) | (cell-local edge << 1) | reversed
+  std::vector<int32_t> slot_einc;  // [P+1] CSR into einc
+  std::vector<uint16_t> einc;      // [2E] per slot: (tile edge << 1) | (1 if the slot's node is end b)
+  int max_tile_edges = 0;
+
   int64_t ntiles() const { return (int64_t)tile_cell.size() - 1; }
   int64_t nslots() const { return (int64_t)slot_node.size(); }
 };
@@ -86,6 +100,10 @@ std::string preprocess_mesh(int nd, int64_t nn, const double* xyz, int64_t nc, i
 
 // Build the extended-tile tables of a preprocessed mesh (any dimension).
 void build_halos(HostMesh& m);
+
+// Build the tile-edge tables of a preprocessed mesh (any dimension);
+// returns "" or an error message.
+std::string build_tile_edges(HostMesh& m);
 
 // Decode the periodic image of vertex k (1..nv-1) along axis d: -1, 0, +1.
 inline int shift_of(uint32_t code, int k, int d, int nd) {
