@@ -152,7 +152,7 @@ class Workload:
             # fused gradient + flux pass: reads U, x, E, 1/V, dx_min per node
             # and the cell topology (3 x u16 local vertices + u32 periodic
             # code), writes U
-            self.bytes_flux = N * 8 * (2 + 2 + 2 + 1 + 1 + 2) + M * (3 * 2 + 4)
+            self.bytes_flux = {p: N * 8 * (2 + 2 + 2 + 1 + 1 + 2) + M * (3 * 2 + 4) for p in (0, 1)}
             self.flops_face_est = 120
             self.flux_kernel = {0: "k_fused<2,2,1,0,double>", 1: "k_fused<2,2,1,0,float>"}
             self.record = "dd2d_streamer_200k"
@@ -171,7 +171,7 @@ class Workload:
             # flux pass: reads W, G, x, U^n, 1/V, dx_min per node and the
             # cell topology (4 x u16 local vertices + u32 periodic code),
             # writes W
-            self.bytes_flux = N * 8 * (nr + nr * nd + nd + nv + 2 + nr) + M * (4 * 2 + 4)
+            self.bytes_flux = {p: N * 8 * (nr + nr * nd + nd + nv + 2 + nr) + M * (4 * 2 + 4) for p in (0, 1)}
             self.flops_face_est = 400
             self.flux_kernel = {0: "k_flux_gas<3,0,1,double,false>", 1: "k_flux_gas<3,0,1,float,false>"}
             self.record = "euler3d_2m"
@@ -195,7 +195,12 @@ class Workload:
             N, M = m.nnodes, m.ncells
             nrow = 15 + 13 + 21       # conserved + p, primitives, transport/thermo aux
             ng = (15 + 13) * 3        # gradients of the reconstructed rows and primitives
-            self.bytes_flux = N * 8 * (nrow + ng + 3 + 14 + 2 + nrow) + M * (4 * 2 + 4)
+            # rows the flux pass reads: conserved + p, gamma, primitives and
+            # mu, lambda (FP64, which forms D_k and h_s,k from them) or every
+            # transport/thermo row (mixed); it writes every row of the new state
+            rows_read = {0: 15 + 1 + 13 + 2, 1: 15 + 1 + 13 + 20}
+            self.bytes_flux = {p: N * 8 * (rows_read[p] + ng + 3 + 14 + 2 + nrow) + M * (4 * 2 + 4)
+                               for p in (0, 1)}
             self.flops_face_est = 900
             self.flux_kernel = {0: "k_flux_ns<3,9,double>", 1: "k_flux_ns<3,9,float>"}
             self.record = "ns3d_8m"
@@ -325,10 +330,11 @@ def roofline(w, prec, kern):
     fpf = float(fl["flops_per_face"]) if fl else float(w.flops_face_est)
     flops = fpf * w.mesh.nfaces
     tr = profile_record(f"traffic_flux_{w.record}.md", "traffic", kname)
-    hbm = w.bytes_flux / (us * 1e-6) / 1e9
+    nbytes = w.bytes_flux[prec]
+    hbm = nbytes / (us * 1e-6) / 1e9
     valu = flops / (us * 1e-6) / 1e12
     ridge = VALU_PEAK_TFLOPS[dt] * 1e12 / (HBM_PEAK_GBS * 1e9)
-    alu = flops / w.bytes_flux > ridge
+    alu = flops / nbytes > ridge
     hbm_frac = hbm / HBM_PEAK_GBS
     valu_frac = valu / VALU_PEAK_TFLOPS[dt]
     out = dict(kernel=kname, bound="alu" if alu else "hbm",
@@ -337,7 +343,7 @@ def roofline(w, prec, kern):
                unit="TFLOP/s" if alu else "GB/s",
                frac=round(valu_frac if alu else hbm_frac, 4),
                traffic=int(tr["bytes"]) if tr else None,
-               avg_us=round(us, 2), alg_bytes_per_launch=int(w.bytes_flux),
+               avg_us=round(us, 2), alg_bytes_per_launch=int(nbytes),
                alg_flops_per_launch=int(flops), flops_per_face=round(fpf, 1),
                flops_per_face_from="VALU instruction counters" if fl else "estimate",
                hbm=dict(achieved_gbs=round(hbm, 1), peak=HBM_PEAK_GBS, frac=round(hbm_frac, 4)),
