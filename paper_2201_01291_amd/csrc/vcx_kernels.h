@@ -1800,6 +1800,14 @@ __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ W,
   uint16_t* sEi = reinterpret_cast<uint16_t*>(sSl + 4 * maxn);
   const CT beta = CT(gp.beta);
 
+  constexpr int PCE = 6;
+  uint32_t pdesc = 0, pce[PCE / 2] = {0, 0, 0};
+  int pq0 = 0, pq1 = 0;
+  if ((int)threadIdx.x < ne) {
+    pdesc = m.edge[e0 + threadIdx.x];
+    pq0 = m.edge_ce[e0 + threadIdx.x];
+    pq1 = m.edge_ce[e0 + threadIdx.x + 1];
+  }
   // ---- phase A staging: coordinates, reconstructed rows, gamma, gradients
   {
     CT* sG = sW + RA * maxn;
@@ -1840,7 +1848,8 @@ __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ W,
   // ---- convective flux of each edge: face states once, HLLC per cell-edge
   for (int le = threadIdx.x; le < ne; le += blockDim.x) {
     const CT* sG = sW + RA * maxn;
-    const uint32_t desc = m.edge[e0 + le];
+    const bool first = le == (int)threadIdx.x;
+    const uint32_t desc = first ? pdesc : m.edge[e0 + le];
     const int la = desc & 4095u, lb = (desc >> 12) & 4095u;
     CT dx[ND];
 #pragma unroll
@@ -1868,8 +1877,9 @@ __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ W,
     double Fs[NVAR];
 #pragma unroll
     for (int v = 0; v < NVAR; ++v) Fs[v] = 0.0;
-    const int q0 = m.edge_ce[e0 + le], q1 = m.edge_ce[e0 + le + 1];
+    const int q0 = first ? pq0 : m.edge_ce[e0 + le], q1 = first ? pq1 : m.edge_ce[e0 + le + 1];
     for (int q = q0; q < q1; ++q) {
+      const int j = q - q0;
       const int code = m.ce[q];
       const int k = (code >> 4) * NCE + ((code >> 1) & 7);
       const CT sg = (code & 1) ? CT(-1) : CT(1);
@@ -1905,13 +1915,15 @@ __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ W,
   // ---- diffusive flux of each edge, with the sum of its dual-face vectors
   for (int le = threadIdx.x; le < ne; le += blockDim.x) {
     const CT* sG = sW + RB * maxn;
-    const uint32_t desc = m.edge[e0 + le];
+    const bool first = le == (int)threadIdx.x;
+    const uint32_t desc = first ? pdesc : m.edge[e0 + le];
     const int la = desc & 4095u, lb = (desc >> 12) & 4095u;
     CT S[ND];
 #pragma unroll
     for (int d = 0; d < ND; ++d) S[d] = CT(0);
-    const int q0 = m.edge_ce[e0 + le], q1 = m.edge_ce[e0 + le + 1];
+    const int q0 = first ? pq0 : m.edge_ce[e0 + le], q1 = first ? pq1 : m.edge_ce[e0 + le + 1];
     for (int q = q0; q < q1; ++q) {
+      const int j = q - q0;
       const int code = m.ce[q];
       const int k = (code >> 4) * NCE + ((code >> 1) & 7);
 #pragma unroll
