@@ -39,7 +39,7 @@ def build(verbose: bool = False) -> str:
 class _Phys(C.Structure):
     _fields_ = [("model", C.c_int32), ("flux", C.c_int32), ("limiter", C.c_int32),
                 ("rk", C.c_int32), ("nspecies", C.c_int32), ("closure", C.c_int32),
-                ("beta", C.c_double), ("cfl", C.c_double), ("fourier", C.c_double),
+                ("predictor", C.c_int32), ("beta", C.c_double), ("cfl", C.c_double), ("fourier", C.c_double),
                 ("gamma", C.c_double), ("entropy_fix", C.c_double),
                 ("z", C.c_double * MAXSP), ("mu", C.c_double * MAXSP),
                 ("D", C.c_double * MAXSP),
@@ -57,6 +57,7 @@ class Phys:
     rk: int = 2
     nspecies: int = 0
     closure: int = 1         # 0 none, 1 node flux, 2 interpolated (2D)
+    predictor: int = 0       # gas, plane meshes, rk 1: MUSCL-Hancock half-step predictor
     beta: float = 1.0
     cfl: float = 0.5
     fourier: float = 0.25
@@ -72,6 +73,7 @@ class Phys:
         p = _Phys()
         p.model, p.flux, p.limiter, p.rk = self.model, self.flux, self.limiter, self.rk
         p.nspecies, p.closure = self.nspecies, int(self.closure)
+        p.predictor = int(self.predictor)
         p.beta, p.cfl, p.fourier = self.beta, self.cfl, self.fourier
         p.gamma, p.entropy_fix = self.gamma, self.entropy_fix
         p.diel = self.diel
@@ -119,6 +121,7 @@ def lib():
         L.om_hllc.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, dp, dp, dp, dp]
         L.om_roe.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, dp, dp, dp, dp]
         L.om_flux_branches.argtypes = [ip, C.c_int]
+        L.om_hancock_rate.argtypes = [C.c_int, C.c_int, C.c_double, dp, dp, dp]
         L.om_ns_conserved.argtypes = [C.c_int, C.POINTER(_Phys), dp, dp]
         pp = C.POINTER(_Phys)
         L.om_residual.argtypes = [C.c_void_p, pp, dp, dp, C.c_double, dp]
@@ -353,6 +356,16 @@ def flux_branches(reset: bool = True) -> dict:
     keys = ("hllc_left_supersonic", "hllc_right_supersonic", "hllc_star_left",
             "hllc_star_right", "roe_calls", "roe_entropy_fix")
     return dict(zip(keys, (int(v) for v in out)))
+
+
+def hancock_rate(nd, nsp, w, g, gamma=1.4):
+    """MUSCL-Hancock half-step rate of one node: the time derivative of
+    (rho, rho u, rho E, rho Y, p) from the node state w [nr] and its gradients
+    g [nr][nd]."""
+    w, g = _c64(w), _c64(g)
+    out = np.zeros(3 + nd + nsp)
+    lib().om_hancock_rate(nd, nsp, float(gamma), _d(w), _d(g), _d(out))
+    return out
 
 
 def roe(nd, nsp, WL, WR, S, gamma=1.4, fix=0.1):

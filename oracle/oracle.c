@@ -32,6 +32,12 @@
  *                 the dielectric time step
  *   RK            Sec. "Time integration of the HLLC MUSCL-Hancock solver",
  *                 table (rk_coeffs)
+ *   predictor     the MUSCL-Hancock half-step evolution the paper names (Sec.
+ *                 "The HLLC solver" and "Effect of multicomponent mixture",
+ *                 after Toro, Chap. 14) without writing it out: here the face
+ *                 states gain dt/2 times the node's time derivative of the
+ *                 reconstructed variables from the quasi-linear Euler
+ *                 equations and the nodal gradients (gas, plane meshes, RK1)
  *   multi-species eq. (ns_reactive) without sources (transport only), total
  *                 non-chemical energy; temperature from the sensible energy by
  *                 iteration and pressure co-reconstructed (Sec. "Effect of
@@ -582,6 +588,37 @@ void om_euler_flux(int nd, int nsp, const double *W, const double *S, double *F)
  * with Harten's fix active on an acoustic wave. */
 static int64_t om_branch_count[6];
 
+/* MUSCL-Hancock half-step rate at one node.  The reconstructed variables
+ * are w = (rho, m = rho u, rho E, rho Y_s, p) with gradients g.  The velocity
+ * gradient follows from the momentum and density gradients,
+ * du_k/dx_d = (dm_k/dx_d - u_k drho/dx_d) / rho, and the Euler equations give
+ *   d rho/dt    = -div m
+ *   d m_k/dt    = -(u . grad m_k + m_k div u) - dp/dx_k
+ *   d rho E/dt  = -(u . grad (rho E) + u . grad p + (rho E + p) div u)
+ *   d rho Y/dt  = -(u . grad (rho Y) + rho Y div u)
+ *   d p/dt      = -(u . grad p + gamma p div u)   (constant-gamma ideal gas) */
+void om_hancock_rate(int nd, int nsp, double gamma, const double *w, const double *g, double *out) {
+  const int nvar = 2 + nd + nsp, nr = nvar + 1;
+  const double rho = w[0], rhoE = w[1 + nd], p = w[nr - 1];
+  double u[3], du[3][3], divu = 0.0;
+  for (int k = 0; k < nd; k++) u[k] = w[1 + k] / rho;
+  for (int k = 0; k < nd; k++)
+    for (int d = 0; d < nd; d++) du[k][d] = (g[(1 + k) * nd + d] - u[k] * g[d]) / rho;
+  for (int d = 0; d < nd; d++) divu += du[d][d];
+  /* u . grad of row v */
+  double adv[2 + 3 + OM_MAXSP + 1];
+  for (int v = 0; v < nr; v++) {
+    adv[v] = 0.0;
+    for (int d = 0; d < nd; d++) adv[v] += u[d] * g[v * nd + d];
+  }
+  out[0] = 0.0;
+  for (int d = 0; d < nd; d++) out[0] -= g[(1 + d) * nd + d];
+  for (int k = 0; k < nd; k++) out[1 + k] = -(adv[1 + k] + w[1 + k] * divu) - g[(nr - 1) * nd + k];
+  out[1 + nd] = -(adv[1 + nd] + adv[nr - 1] + (rhoE + p) * divu);
+  for (int s = 0; s < nsp; s++) out[2 + nd + s] = -(adv[2 + nd + s] + w[2 + nd + s] * divu);
+  out[nr - 1] = -(adv[nr - 1] + gamma * p * divu);
+}
+
 void om_flux_branches(int64_t *out, int reset) {
   for (int k = 0; k < 6; k++) {
     if (out) out[k] = om_branch_count[k];
@@ -713,7 +750,8 @@ static double pressure_of(int nd, const double *U, int64_t nn, int64_t i, double
   return (gamma - 1.0) * (U[(int64_t)(1 + nd) * nn + i] - 0.5 * ke / rho);
 }
 
-static int residual_gas(const om_mesh *m, const om_phys *ph, const double *U, double *r, int absmode) {
+static int residual_gas(const om_mesh *m, const om_phys *ph, const double *U, double dt, double *r,
+                        int absmode) {
   int nd = m->nd, nv = m->nv, nsp = ph->nspecies;
   int nvar = 2 + nd + nsp, nr = nvar + 1;
   int ns_model = ph->model == 2;
@@ -748,6 +786,24 @@ static int residual_gas(const om_mesh *m, const om_phys *ph, const double *U, do
     om_gradient(m, np, P, GP);
   }
   om_gradient(m, nr, W, G);
+  /* MUSCL-Hancock predictor: dt/2 times each node's half-step rate */
+  double *H = NULL;
+  if (ph->predictor) {
+    H = malloc(sizeof(double) * nr * nn);
+    if (!H) {
+      free(W); free(G); free(P); free(GP); free(A);
+      return -3;
+    }
+    double wi[2 + 3 + OM_MAXSP + 1], gi[(2 + 3 + OM_MAXSP + 1) * 3], hi[2 + 3 + OM_MAXSP + 1];
+    for (int64_t i = 0; i < nn; i++) {
+      for (int v = 0; v < nr; v++) {
+        wi[v] = W[(int64_t)v * nn + i];
+        for (int d = 0; d < nd; d++) gi[v * nd + d] = G[((int64_t)v * nd + d) * nn + i];
+      }
+      om_hancock_rate(nd, nsp, ph->gamma, wi, gi, hi);
+      for (int v = 0; v < nr; v++) H[(int64_t)v * nn + i] = 0.5 * dt * hi[v];
+    }
+  }
   memset(r, 0, sizeof(double) * nvar * nn);
   for (int64_t c = 0; c < m->nc; c++) {
     const double *X = m->X + c * nv * nd;
@@ -773,6 +829,10 @@ static int residual_gas(const om_mesh *m, const om_phys *ph, const double *U, do
         double bar_j = om_slope_limiter(ph->limiter, ph->beta, delta, d_jk);
         WL[v] = wi + 0.5 * bar_i;
         WR[v] = wj - 0.5 * bar_j;
+        if (H) {
+          WL[v] += H[(int64_t)v * nn + i];
+          WR[v] += H[(int64_t)v * nn + j];
+        }
       }
       double F[2 + 3 + OM_MAXSP];
       if (ns_model) {
@@ -850,6 +910,7 @@ static int residual_gas(const om_mesh *m, const om_phys *ph, const double *U, do
   free(P);
   free(GP);
   free(A);
+  free(H);
   return 0;
 }
 
@@ -950,9 +1011,11 @@ static int residual_any(const om_mesh *m, const om_phys *ph, const double *U, co
   /* the interpolated closure is given for planar 2D meshes */
   if (ph->closure == 2 && (m->nd != 2 || m->axi || ph->model == 2)) return -1;
   if (ph->nspecies < 0 || ph->nspecies > OM_MAXSP) return -1;
+  /* the predictor: constant-gamma gas on plane meshes, one-stage time step */
+  if (ph->predictor && (ph->model != 0 || m->axi || ph->rk != 1)) return -1;
   if (ph->model == 0 || ph->model == 2) {
     if (m->axi && ph->model == 2) return -1; /* viscous geometric source terms: not built */
-    return residual_gas(m, ph, U, r, absmode);
+    return residual_gas(m, ph, U, dt, r, absmode);
   }
   if (ph->model == 1) {
     if (!E || ph->nspecies < 1) return -1;

@@ -34,6 +34,8 @@ typedef struct {
   int32_t nspecies;   /* gas: passive species; drift-diffusion: charged species */
   int32_t closure;    /* 1: node-flux boundary closure on boundary nodes; 2: interpolated
                          fluxes 0.75 F_i + 0.25 F_j on each half boundary edge (2D) */
+  int32_t predictor;  /* gas, plane meshes, rk = 1: 1 adds the MUSCL-Hancock half-step
+                         evolution to the reconstructed face states, 0 none */
   double beta;        /* Sweby parameter */
   double cfl, fourier;
   double gamma;
@@ -74,6 +76,11 @@ void om_hllc(int nd, int nsp, double gL, double gR, const double *WL, const doub
              const double *S, double *F);
 void om_roe(int nd, int nsp, double gamma, double fix, const double *WL, const double *WR,
             const double *S, double *F);
+/* MUSCL-Hancock half-step rate at one node: the time derivative of the
+ * reconstructed gas variables w = (rho, rho u, rho E, rho Y, p) [nr] from the
+ * Euler equations in quasi-linear form, with the node's state and nodal
+ * gradients g [nr][nd] (row-major); out [nr] */
+void om_hancock_rate(int nd, int nsp, double gamma, const double *w, const double *g, double *out);
 /* branch counters of om_hllc / om_roe since the last reset (test
  * instrumentation): [0] HLLC 0 <= S_L, [1] HLLC S_R < 0, [2] HLLC left star,
  * [3] HLLC right star, [4] Roe calls, [5] Roe calls with the entropy fix
