@@ -99,7 +99,14 @@ typedef struct {
                          gas and drift-diffusion) interpolated fluxes
                          0.75 F_i + 0.25 F_j on each half boundary edge */
   int32_t precision;  /* VCX_PREC_* */
-  int32_t reserved;
+  int32_t predictor;  /* gas model on plane meshes with rk_stages = 1: 1 adds the
+                         MUSCL-Hancock half-step evolution (after Toro, Chap. 14,
+                         which Sec. "The HLLC solver" names) to the face states:
+                         each end's reconstructed (rho, rho u, rho E, rho Y, p)
+                         gains dt/2 times its time derivative from the
+                         quasi-linear Euler equations with the nodal state and
+                         gradients; 0 none.  Other combinations: VCX_E_ARG.
+                         Not batched (vcx_solve_batch, the server). */
   double beta;        /* Sweby beta */
   double cfl;         /* convective CFL number */
   double fourier;     /* diffusive Fourier number */
@@ -241,7 +248,8 @@ vcx_status vcx_state_upload_primitive(vcx_solver s, const double *P, int is_devi
 vcx_status vcx_gradient(vcx_solver s, double *G, int is_device);
 
 /* Residual of the current state, FP64 [nvar][nnodes], caller order.  dt is
- * only used by the limited Lax-Wendroff flux. */
+ * used by the limited Lax-Wendroff flux and the gas predictor's half step
+ * (vcx_physics.predictor); other physics ignore it. */
 vcx_status vcx_residual(vcx_solver s, double dt, double *r, int is_device);
 
 /* Allocation-free variant of vcx_residual, for callers that cannot allocate
@@ -250,7 +258,7 @@ vcx_status vcx_residual(vcx_solver s, double dt, double *r, int is_device);
  * physics, without a solver.
  *   U    device [nvar][nnodes], caller's node order (read)
  *   E    drift-diffusion: device [ndim][nnodes] field, caller order; else NULL
- *   dt   used by the limited Lax-Wendroff flux only
+ *   dt   used by the limited Lax-Wendroff flux and the gas predictor only
  *   r    device [nvar][nnodes], caller order (written)
  * Result: bit for bit that of vcx_residual on a solver of the same mesh and
  * physics holding U.  The call allocates nothing: every intermediate array

@@ -475,6 +475,10 @@ vcx_status vcx::check_physics(vcx_mesh mesh, const vcx_physics& ph, const double
     return fail(VCX_E_ARG, "the interpolated boundary closure is defined on plane 2D meshes (gas and "
                            "drift-diffusion)");
   if (ph.rk_stages < 1 || ph.rk_stages > 4) return fail(VCX_E_ARG, "rk_stages must be 1..4");
+  if (ph.predictor != 0 && ph.predictor != 1) return fail(VCX_E_ARG, "predictor must be 0 or 1");
+  if (ph.predictor && (ph.model != VCX_MODEL_GAS || mesh->h.axi || ph.rk_stages != 1))
+    return fail(VCX_E_ARG, "the MUSCL-Hancock predictor is defined for the gas model on plane meshes with "
+                           "rk_stages = 1");
   if (ph.limiter < 0 || ph.limiter > 4) return fail(VCX_E_ARG, "unknown limiter");
   if (ph.precision != VCX_PREC_FP64 && ph.precision != VCX_PREC_MIXED)
     return fail(VCX_E_ARG, "unknown precision");
@@ -509,7 +513,7 @@ vcx_status vcx::configure_solver(vcx_solver s, vcx_mesh mesh, const vcx_physics&
   s->lds_grad = kt->lds_grad(d.max_tile_nodes, d.max_tile_cells);
   if (ph.model == VCX_MODEL_NAVIER_STOKES && !d.has_edges)
     return fail(VCX_E_ARG, "the mesh has no tile-edge tables (created by the first Navier-Stokes solver)");
-  s->lds_flux = kt->lds_flux(d);
+  s->lds_flux = kt->lds_flux(d, ph.predictor);
   if (s->lds_grad > (size_t)mesh->lds_max || s->lds_flux > (size_t)mesh->lds_max) {
     const size_t need = std::max(s->lds_grad, s->lds_flux);
     return fail(VCX_E_ARG, "tile LDS footprint " + std::to_string(need) + " B exceeds the device limit " +
@@ -523,7 +527,9 @@ vcx_status vcx::configure_solver(vcx_solver s, vcx_mesh mesh, const vcx_physics&
   // gradient + flux passes, whose flux carries the face radii
   // (and the interpolated closure reads neighbours' gradients, complete only
   // after a separate gradient pass)
-  s->fused = !d.axi && ph.closure != 2 && s->lds_fused > 0 && s->lds_fused <= (size_t)mesh->lds_max;
+  // (the predictor takes the separate passes too)
+  s->fused = !d.axi && ph.closure != 2 && !ph.predictor && s->lds_fused > 0 &&
+             s->lds_fused <= (size_t)mesh->lds_max;
   if (!s->fused) s->lds_fused = 0;
   if (std::max({s->lds_grad, s->lds_flux, s->lds_fused}) > 65536)
     VCX_TRY(kt->allow_lds(s->lds_grad, s->lds_flux, s->lds_fused));
@@ -921,8 +927,9 @@ vcx_status vcx::batch_set(BatchGroup* g, vcx_solver* ss, int n, const int* steps
     g->pair = nullptr;
   }
   for (int i = 0; i < n; ++i)
-    if (ss[i] && (ss[i]->mesh->h.axi || ss[i]->ph.closure == 2))
-      return fail(VCX_E_ARG, "solvers on axisymmetric meshes or with the interpolated closure are not batched");
+    if (ss[i] && (ss[i]->mesh->h.axi || ss[i]->ph.closure == 2 || ss[i]->ph.predictor))
+      return fail(VCX_E_ARG, "solvers on axisymmetric meshes, with the interpolated closure or the "
+                             "predictor are not batched");
   g->mem.assign(ss, ss + n);
   g->q = 0;
   if (n == 0) return VCX_OK;
@@ -1093,6 +1100,7 @@ static vcx_status solve_batch(vcx_solver* ss, int n, const int* nsteps, const do
     if (nsteps[i] < 0) return fail(VCX_E_ARG, "nsteps must be >= 0");
     if (ss[i]->mesh->h.axi) return fail(VCX_E_ARG, "solvers on axisymmetric meshes are not batched");
     if (ss[i]->ph.closure == 2) return fail(VCX_E_ARG, "solvers with the interpolated closure are not batched");
+    if (ss[i]->ph.predictor) return fail(VCX_E_ARG, "solvers with the MUSCL-Hancock predictor are not batched");
     if (!batch_compatible(ss[i], ss[0]))
       return fail(VCX_E_ARG, "batch members must share the model and scheme parameters");
     for (int j = 0; j < i; ++j)

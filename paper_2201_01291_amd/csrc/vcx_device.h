@@ -195,6 +195,44 @@ __device__ inline void roe_flux(const T* WL, const T* WR, const T* S, T gamma, T
   for (int v = 0; v < NV; ++v) F[v] = A * (T(0.5) * (FL[v] + FR[v]) - T(0.5) * Dv[v]);
 }
 
+// MUSCL-Hancock half step of one node's reconstructed gas variables
+// w = (rho, m = rho u, rho E, rho Y, p), staged as rows of stride ld with
+// gradient rows g[(v*ND + d)*ld]: writes h * dw/dt per row to out, where
+// the rate comes from the quasi-linear Euler equations with the node's own
+// state and gradients.  With du_k/dx_d = (dm_k/dx_d - u_k drho/dx_d)/rho,
+//   rho: -div m            m_k: -(u.grad m_k + m_k div u) - dp/dx_k
+//   rho E: -(u.grad(rho E + p) + (rho E + p) div u)
+//   rho Y: -(u.grad(rho Y) + rho Y div u)     p: -(u.grad p + gamma p div u)
+template <int ND, int NSP, typename T>
+__device__ inline void hancock_half_step(const T* w, const T* g, int ld, int q, T gamma, T h, T* out) {
+  constexpr int NVAR = 2 + ND + NSP, NR = NVAR + 1;
+  const T rho = w[q], rinv = T(1) / rho;
+  T u[ND], divu = T(0);
+#pragma unroll
+  for (int d = 0; d < ND; ++d) u[d] = w[(1 + d) * ld + q] * rinv;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) divu += (g[((1 + d) * ND + d) * ld + q] - u[d] * g[d * ld + q]) * rinv;
+  auto adv = [&](int v) {
+    T a = T(0);
+#pragma unroll
+    for (int d = 0; d < ND; ++d) a += u[d] * g[(v * ND + d) * ld + q];
+    return a;
+  };
+  const T p = w[(NR - 1) * ld + q], rhoE = w[(1 + ND) * ld + q], ap = adv(NR - 1);
+  T dm = T(0);
+#pragma unroll
+  for (int d = 0; d < ND; ++d) dm += g[((1 + d) * ND + d) * ld + q];
+  out[q] = -h * dm;
+#pragma unroll
+  for (int k = 0; k < ND; ++k)
+    out[(1 + k) * ld + q] = -h * (adv(1 + k) + w[(1 + k) * ld + q] * divu + g[((NR - 1) * ND + k) * ld + q]);
+  out[(1 + ND) * ld + q] = -h * (adv(1 + ND) + ap + (rhoE + p) * divu);
+#pragma unroll
+  for (int s = 0; s < NSP; ++s)
+    out[(2 + ND + s) * ld + q] = -h * (adv(2 + ND + s) + w[(2 + ND + s) * ld + q] * divu);
+  out[(NR - 1) * ld + q] = -h * (ap + gamma * p * divu);
+}
+
 // ---------------------------------------------------------------------------
 // multi-species mixture (species data supplied by the caller)
 // ---------------------------------------------------------------------------

@@ -139,7 +139,7 @@ struct KernelTable {
   vcx_status (*update_shared)(vcx_solver, const Finish& f);
   vcx_status (*node_dt)(vcx_solver, const double* W);
   size_t (*lds_grad)(int maxn, int maxc);
-  size_t (*lds_flux)(const DevMesh& d);
+  size_t (*lds_flux)(const DevMesh& d, int predictor);
   size_t (*lds_fused)(const DevMesh& d);  // 0: no fused pass for this model
   vcx_status (*fused)(vcx_solver, const double* Win, const Finish& f, const FusedCtl& fc, double dt_host);
   vcx_status (*allow_lds)(size_t grad_bytes, size_t flux_bytes, size_t fused_bytes);
@@ -208,11 +208,13 @@ struct Impl {
     constexpr int FG = grad_group(NGF);  // fields staged per pass
     return sizeof(double) * ((size_t)(FG + ND) * maxn + (size_t)FG * ND * maxc) + inc_lds_bytes(NV, maxc);
   }
-  static size_t lds_flux(const DevMesh& d) {
+  static size_t lds_flux(const DevMesh& d, int predictor) {
     const int maxn = d.max_tile_nodes, maxc = d.max_tile_cells;
+    // the gas predictor stages one more row set: the half-step increments
+    const size_t pred = MODEL == 0 && predictor ? sizeof(CT) * (size_t)NR * maxn : 0;
     if constexpr (MODEL == 0 && cell_halves<ND, CT>() == 2)  // two planes of vertex parts
       return sizeof(double) * ((size_t)ND * maxn + (size_t)2 * NV * NVAR * maxc) +
-             sizeof(CT) * (size_t)(NR + NR * ND) * maxn + slot_lds_bytes(maxn) + inc_lds_bytes(NV, maxc);
+             sizeof(CT) * (size_t)(NR + NR * ND) * maxn + pred + slot_lds_bytes(maxn) + inc_lds_bytes(NV, maxc);
     if constexpr (MODEL == 1 && cell_halves<ND, CT>() == 2)
       return sizeof(double) * ((size_t)ND * maxn + (size_t)2 * NV * NVAR * maxc) +
              sizeof(CT) * (size_t)(NSP + NSP * ND + ND) * maxn + slot_lds_bytes(maxn) + inc_lds_bytes(NV, maxc);
@@ -221,7 +223,7 @@ struct Impl {
     size_t ct = MODEL == 0   ? (size_t)(NR + NR * ND) * maxn
                 : MODEL == 1 ? (size_t)(NSP + NSP * ND + ND) * maxn
                              : (size_t)(NW + NGF * ND) * maxn;
-    return dbl + sizeof(CT) * ct + slot_lds_bytes(maxn) + inc_lds_bytes(NV, maxc);
+    return dbl + sizeof(CT) * ct + pred + slot_lds_bytes(maxn) + inc_lds_bytes(NV, maxc);
   }
   static constexpr bool FUSABLE = ND == 2 && MODEL != 2;
   static size_t lds_fused(const DevMesh& d) {
@@ -289,7 +291,16 @@ struct Impl {
     const DevMesh& m = s->mesh->d;
     hipStream_t st = s->mesh->stream;
     if constexpr (MODEL == 0) {
-      GasParams gp{s->ph.gamma, s->ph.beta, s->ph.entropy_fix, s->ph.limiter};
+      GasParams gp{s->ph.gamma, s->ph.beta, s->ph.entropy_fix, s->ph.limiter, dt_host};
+      // a thread per cell and half: the cells rounded to wavefronts, per half
+      const int fb = cell_halves<ND, CT>() == 2 ? std::min(256, 2 * ((m.max_tile_cells + 63) / 64) * 64)
+                                                : s->tile_block;
+      if (s->ph.predictor)
+        return launch(s, "flux", [&](hipEvent_t ea, hipEvent_t eb) {
+          hipExtLaunchKernelGGL((k_flux_gas<ND, NSP, FLUX, CT, false, true>), dim3(xcd_grid(m.ntiles)),
+                                dim3(fb), s->lds_flux, st, ea, eb, 0, m, Win, (const double*)s->G, s->PR, gp,
+                                f);
+        });
       if constexpr (ND == 2) {
         if (m.axi)
           return launch(s, "flux", [&](hipEvent_t ea, hipEvent_t eb) {
@@ -299,9 +310,6 @@ struct Impl {
           });
       }
       return launch(s, "flux", [&](hipEvent_t ea, hipEvent_t eb) {
-        // a thread per cell and half: the cells rounded to wavefronts, per half
-        const int fb = cell_halves<ND, CT>() == 2 ? std::min(256, 2 * ((m.max_tile_cells + 63) / 64) * 64)
-                                                  : s->tile_block;
         hipExtLaunchKernelGGL((k_flux_gas<ND, NSP, FLUX, CT>), dim3(xcd_grid(m.ntiles)),
                            dim3(fb), s->lds_flux, st, ea, eb, 0, m, Win, (const double*)s->G,
                            s->PR, gp, f);
@@ -370,6 +378,8 @@ struct Impl {
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)grad_bytes));
     if constexpr (MODEL == 0) {
       VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_gas<ND, NSP, FLUX, CT>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)flux_bytes));
+      VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_gas<ND, NSP, FLUX, CT, false, true>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)flux_bytes));
       if constexpr (ND == 2)
         VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_gas<ND, NSP, FLUX, CT, true>),

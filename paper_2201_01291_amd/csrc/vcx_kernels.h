@@ -981,6 +981,7 @@ __device__ inline double finish_node(const DevMesh& m, const Finish& f, int i, b
 struct GasParams {
   double gamma, beta, entropy_fix;
   int limiter;
+  double dt_host;  // time step of the MUSCL-Hancock predictor outside the time loop
 };
 
 // ---------------------------------------------------------------------------
@@ -1010,10 +1011,12 @@ __host__ __device__ constexpr int cell_halves() {
 
 // Gas fluxes of the tile's cells: MUSCL with virtual upwind nodes, slope
 // limiter, HLLC or Roe; accumulated per cell vertex into sR.
-template <int ND, int NSP, int FLUX, typename CT, int NV, bool AXI = false>
+// With HANCOCK, sH holds each slot's MUSCL-Hancock half-step increments
+// (rows like sW), added to the face states of both ends.
+template <int ND, int NSP, int FLUX, typename CT, int NV, bool AXI = false, bool HANCOCK = false>
 __device__ inline void gas_cell_fluxes(const DevMesh& m, const TilePre<NV>& tp, const double* sX,
                                        const CT* sW, const CT* sG, double* sR, CellLd L,
-                                       const GasParams& gp) {
+                                       const GasParams& gp, const CT* sH = nullptr) {
   constexpr int NVAR = 2 + ND + NSP, NR = NVAR + 1, NE = Edges<ND>::NE;
   const CT gamma = CT(gp.gamma), beta = CT(gp.beta), fix = CT(gp.entropy_fix);
   // FP64 tetrahedra: two threads per cell, edges 0-2 and 3-5, each into its
@@ -1073,6 +1076,10 @@ __device__ inline void gas_cell_fluxes(const DevMesh& m, const TilePre<NV>& tp, 
         const CT dli = CT(2) * gi - delta, djk = CT(2) * gj - delta;
         WL[v] = wi + CT(0.5) * slope_limit<CT>(gp.limiter, beta, dli, delta);
         WR[v] = wj - CT(0.5) * slope_limit<CT>(gp.limiter, beta, delta, djk);
+        if constexpr (HANCOCK) {
+          WL[v] += sH[v * L.ldw + la];
+          WR[v] += sH[v * L.ldw + lb];
+        }
       }
       CT F[NVAR];
       if constexpr (FLUX == 0)
@@ -1270,7 +1277,7 @@ __device__ inline double tile_node_pass(const DevMesh& m, const Finish& f, doubl
   return cand;
 }
 
-template <int ND, int NSP, int FLUX, typename CT, bool AXI = false>
+template <int ND, int NSP, int FLUX, typename CT, bool AXI = false, bool HANCOCK = false>
 __device__ inline void flux_gas_body(DevMesh m, const double* __restrict__ W,
                                                   const double* __restrict__ G,
                                                   double* __restrict__ PR, GasParams gp, Finish f,
@@ -1285,7 +1292,8 @@ __device__ inline void flux_gas_body(DevMesh m, const double* __restrict__ W,
   double* sR = sX + ND * maxn;            // [NH][NV*NVAR][maxc]
   CT* sW = reinterpret_cast<CT*>(sR + NH * NV * NVAR * maxc);  // [NR][maxn]
   CT* sG = sW + NR * maxn;                // [NR*ND][maxn]
-  int* sSl = reinterpret_cast<int*>(sG + NR * ND * maxn);
+  CT* sH = sG + NR * ND * maxn;           // predictor: [NR][maxn] half-step increments
+  int* sSl = reinterpret_cast<int*>(sH + (HANCOCK ? NR * maxn : 0));
   uint16_t* sInc = reinterpret_cast<uint16_t*>(sSl + 4 * maxn);
   const int ns = tp.ns;
   for (int q = threadIdx.x; q < ns; q += blockDim.x) {
@@ -1306,9 +1314,16 @@ __device__ inline void flux_gas_body(DevMesh m, const double* __restrict__ W,
   }
   tile_store_inc<NV>(m, tp, sInc);
   __syncthreads();
-  gas_cell_fluxes<ND, NSP, FLUX, CT, NV, AXI>(m, tp, sX, sW, sG, sR, CellLd{maxn, maxn, maxn, maxc}, gp);
+  const double dt = f.sc ? f.sc->dt : gp.dt_host;
+  if constexpr (HANCOCK) {
+    // each slot's half-step increments from its staged state and gradients
+    for (int q = threadIdx.x; q < ns; q += blockDim.x)
+      hancock_half_step<ND, NSP, CT>(sW, sG, maxn, q, CT(gp.gamma), CT(0.5 * dt), sH);
+    __syncthreads();
+  }
+  gas_cell_fluxes<ND, NSP, FLUX, CT, NV, AXI, HANCOCK>(m, tp, sX, sW, sG, sR, CellLd{maxn, maxn, maxn, maxc},
+                                                       gp, sH);
   __syncthreads();
-  const double dt = f.sc ? f.sc->dt : 0.0;
   const double cand = tile_node_pass<ND, NSP, 0, NVAR, (NH == 2)>(m, f, dt, PR, ns, sSl, maxn, sInc, sR, maxc);
   if (f.final_stage && f.sc) {
     const double b = block_min(cand);
@@ -1316,14 +1331,14 @@ __device__ inline void flux_gas_body(DevMesh m, const double* __restrict__ W,
   }
 }
 
-template <int ND, int NSP, int FLUX, typename CT, bool AXI = false>
+template <int ND, int NSP, int FLUX, typename CT, bool AXI = false, bool HANCOCK = false>
 __global__ void VCX_FLUX_BOUNDS k_flux_gas(DevMesh m, const double* __restrict__ W,
                                                   const double* __restrict__ G,
                                                   double* __restrict__ PR, GasParams gp, Finish f) {
   extern __shared__ double lds[];
   const int t = xcd_tile(m.ntiles);
   if (t >= m.ntiles) return;
-  flux_gas_body<ND, NSP, FLUX, CT, AXI>(m, W, G, PR, gp, f, t, lds);
+  flux_gas_body<ND, NSP, FLUX, CT, AXI, HANCOCK>(m, W, G, PR, gp, f, t, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1800,8 +1815,7 @@ __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ W,
   uint16_t* sEi = reinterpret_cast<uint16_t*>(sSl + 4 * maxn);
   const CT beta = CT(gp.beta);
 
-  constexpr int PCE = 6;
-  uint32_t pdesc = 0, pce[PCE / 2] = {0, 0, 0};
+  uint32_t pdesc = 0;
   int pq0 = 0, pq1 = 0;
   if ((int)threadIdx.x < ne) {
     pdesc = m.edge[e0 + threadIdx.x];
@@ -1879,7 +1893,6 @@ __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ W,
     for (int v = 0; v < NVAR; ++v) Fs[v] = 0.0;
     const int q0 = first ? pq0 : m.edge_ce[e0 + le], q1 = first ? pq1 : m.edge_ce[e0 + le + 1];
     for (int q = q0; q < q1; ++q) {
-      const int j = q - q0;
       const int code = m.ce[q];
       const int k = (code >> 4) * NCE + ((code >> 1) & 7);
       const CT sg = (code & 1) ? CT(-1) : CT(1);
@@ -1923,7 +1936,6 @@ __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ W,
     for (int d = 0; d < ND; ++d) S[d] = CT(0);
     const int q0 = first ? pq0 : m.edge_ce[e0 + le], q1 = first ? pq1 : m.edge_ce[e0 + le + 1];
     for (int q = q0; q < q1; ++q) {
-      const int j = q - q0;
       const int code = m.ce[q];
       const int k = (code >> 4) * NCE + ((code >> 1) & 7);
 #pragma unroll

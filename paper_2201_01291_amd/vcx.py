@@ -50,7 +50,7 @@ class VcxError(RuntimeError):
 class Physics(C.Structure):
     _fields_ = [("model", C.c_int32), ("flux", C.c_int32), ("limiter", C.c_int32),
                 ("rk_stages", C.c_int32), ("nspecies", C.c_int32), ("closure", C.c_int32),
-                ("precision", C.c_int32), ("reserved", C.c_int32),
+                ("precision", C.c_int32), ("predictor", C.c_int32),
                 ("beta", C.c_double), ("cfl", C.c_double), ("fourier", C.c_double),
                 ("gamma", C.c_double), ("entropy_fix", C.c_double),
                 ("z", C.c_double * MAX_SPECIES), ("mu", C.c_double * MAX_SPECIES),
@@ -63,10 +63,11 @@ class Physics(C.Structure):
 
 def physics(model=MODEL_GAS, flux=FLUX_HLLC, limiter=LIM_MINMOD, rk_stages=2, nspecies=0,
             closure=True, precision=PREC_FP64, beta=1.0, cfl=0.5, fourier=0.25, gamma=1.4,
-            entropy_fix=0.1, z=(), mu=(), D=(), mixture=None, diel=0.0) -> Physics:
+            entropy_fix=0.1, z=(), mu=(), D=(), mixture=None, diel=0.0, predictor=0) -> Physics:
     p = Physics()
     p.model, p.flux, p.limiter, p.rk_stages = model, flux, limiter, rk_stages
     p.nspecies, p.closure, p.precision = nspecies, int(closure), precision
+    p.predictor = int(predictor)
     p.beta, p.cfl, p.fourier, p.gamma, p.entropy_fix = beta, cfl, fourier, gamma, entropy_fix
     p.diel = diel
     for k, (a, b, c) in enumerate(zip(z, mu, D)):

@@ -34,7 +34,8 @@ class Case:
                            beta=s.get("beta", 1.0), cfl=s.get("cfl", 0.5),
                            fourier=s.get("fourier", 0.25), gamma=1.4,
                            entropy_fix=s.get("fix", 0.1), z=s.get("z", []), mu=s.get("mu", []),
-                           D=s.get("D", []), mixture=s.get("mixture"), diel=s.get("diel", 0.0))
+                           D=s.get("D", []), mixture=s.get("mixture"), diel=s.get("diel", 0.0),
+                           predictor=s.get("predictor", 0))
 
     def vcx_phys(self, precision=0):
         from paper_2201_01291_amd import vcx
@@ -45,7 +46,8 @@ class Case:
                            precision=precision, beta=s.get("beta", 1.0), cfl=s.get("cfl", 0.5),
                            fourier=s.get("fourier", 0.25), gamma=1.4,
                            entropy_fix=s.get("fix", 0.1), z=s.get("z", []), mu=s.get("mu", []),
-                           D=s.get("D", []), mixture=s.get("mixture"), diel=s.get("diel", 0.0))
+                           D=s.get("D", []), mixture=s.get("mixture"), diel=s.get("diel", 0.0),
+                           predictor=s.get("predictor", 0))
 
 
 DD2 = dict(model="dd", limiter="minmod", rk=1, nspecies=2, z=[-1.0, 1.0], mu=[0.04, 0.04],
@@ -175,8 +177,39 @@ def make_case(name: str) -> Case:
         U = wl.explosion_state(m, centre=(1.0, 1.0, 1.0), radius=0.5)
         return Case(name, m, U, None, dict(model="gas", flux="hllc", limiter="sweby", beta=1.7,
                                            rk=2))
+    # -- MUSCL-Hancock predictor (one forward-Euler stage) ---------------
+    if name == "euler2d-hancock-hllc":
+        m = wl.tri_rect_mesh(20, 16, jitter=0.2, seed=23, periodic=True)
+        U = wl.euler_blob_state(m, nblobs=4, amp=0.3, sigma=0.15, mach=0.8, seed=7)
+        return Case(name, m, U, None, dict(model="gas", flux="hllc", limiter="vanleer", rk=1,
+                                           predictor=1))
+    if name == "sod-hancock-roe":
+        m = wl.sod_tube(100, 10)
+        return Case(name, m, wl.sod_state(m), None,
+                    dict(model="gas", flux="roe", limiter="minmod", rk=1, predictor=1))
+    if name == "euler2d-open-closure2-hancock":
+        m = wl.tri_rect_mesh(18, 14, jitter=0.2, seed=24)
+        U = wl.euler_blob_state(m, nblobs=3, amp=0.3, sigma=0.2, mach=0.5, seed=8, nspecies=2)
+        return Case(name, m, U, None, dict(model="gas", flux="hllc", limiter="sweby", beta=1.5,
+                                           rk=1, closure=2, nspecies=2, predictor=1))
+    if name == "euler3d-hancock-roe-sp2":
+        m = wl.kuhn_tet_mesh(6, 5, 6, jitter=0.1, seed=25, periodic=False)
+        U = wl.euler_blob_state(m, nblobs=5, amp=0.3, sigma=0.25, mach=0.7, seed=9, nspecies=2)
+        return Case(name, m, U, None, dict(model="gas", flux="roe", limiter="vanleer", rk=1,
+                                           nspecies=2, predictor=1))
+    if name == "euler3d-hancock-hllc-sp9":
+        m = wl.kuhn_tet_mesh(5, 5, 5, jitter=0.1, seed=26)
+        U = wl.euler_blob_state(m, nblobs=4, amp=0.2, sigma=0.25, nspecies=9, mach=1.2, seed=10)
+        # the predictor's increments take more LDS than the default 3D tile
+        # leaves with nine species in FP64
+        return Case(name, m, U, None, dict(model="gas", flux="hllc", limiter="minmod", rk=1,
+                                           nspecies=9, predictor=1), tiles=(96, 72))
     raise KeyError(name)
 
+
+# Gas cases with the MUSCL-Hancock predictor (plane meshes, one stage)
+HANCOCK_CASES = ["euler2d-hancock-hllc", "sod-hancock-roe", "euler2d-open-closure2-hancock",
+                 "euler3d-hancock-roe-sp2", "euler3d-hancock-hllc-sp9"]
 
 # Gas cases built to reach the transonic and supersonic branches of the
 # Riemann fluxes, with the branches each must reach (oracle branch counters)
@@ -195,7 +228,7 @@ BRANCH_CASES = {
 CASE_NAMES = ["dd2d-streamer", "dd2d-diel", "dd2d-open-vanleer", "dd2d-open-closure2",
               "euler2d-open-closure2", "dd3d-sweby", "sod-hllc", "euler2d-roe-sp2",
               "euler3d-roe", "euler3d-hllc-open-sp2", "euler3d-hllc-sp9", "ns3d-sp9",
-              "ns2d-sp2-open", "ns2d-sp2-bigtile", *BRANCH_CASES]
+              "ns2d-sp2-open", "ns2d-sp2-bigtile", *BRANCH_CASES, *HANCOCK_CASES]
 
 
 def reconstructed(case: Case) -> np.ndarray:

@@ -17,9 +17,11 @@ if not torch.cuda.is_available():
 from paper_2201_01291_amd import vcx, workloads as wl  # noqa: E402
 
 # (larger, smaller) pairs in nodes, each on the fused 2D pass, the
-# three-kernel 3D path, the second closure option and the multi-species model
+# three-kernel 3D path, the second closure option, the multi-species model
+# and the MUSCL-Hancock predictor (whose half step takes dt)
 PAIRS = [("dd2d-streamer", "dd2d-open-vanleer"), ("euler3d-roe", "euler3d-mach2-hllc-sp2"),
-         ("explosion2d", "dd2d-open-closure2"), ("ns2d-sp2-open", "ns3d-sp9")]
+         ("explosion2d", "dd2d-open-closure2"), ("ns2d-sp2-open", "ns3d-sp9"),
+         ("euler2d-hancock-hllc", "euler3d-hancock-roe-sp2")]
 
 
 def _reference(case, precision):
