@@ -27,7 +27,10 @@
  *                 and, in 2D, the second (interpolated 0.75 / 0.25 fluxes)
  *   axisymmetry   Sec. "Cylindrical frames" (Pappus-Guldinus theorems),
  *                 eq. (vertex_centered_flux_axi), Sec. "Geometric source
- *                 terms" (inviscid part); drift-diffusion and gas
+ *                 terms", eq. (ns_cyl_source_terms): the convective p and,
+ *                 for the multi-species model, the diffusive hoop-stress
+ *                 source, with the cylindrical velocity divergence in the
+ *                 diffusive fluxes; drift-diffusion, gas and multi-species
  *   time step     Sec. "Time step computation", eqs. (dt_conv), (dt_diff) and
  *                 the dielectric time step
  *   RK            Sec. "Time integration of the HLLC MUSCL-Hancock solver",
@@ -191,9 +194,12 @@ void om_ns_node(int nd, const om_phys *ph, const double *Ui, double *out) {
  * gradients.  prim = (u_1..u_nd, T, Y_1..Y_N), aux = (gamma, mu, lambda,
  * D_k, hs_k), gprim [np][nd].  Returns Fv = (0, tau.S, u.(tau.S) - q.S,
  * -J_k.S), to be subtracted from the convective flux. */
-void om_viscous_flux(int nd, int nsp, const double *prim_i, const double *prim_j,
-                     double rho_i, double rho_j, const double *aux_i, const double *aux_j,
-                     const double *gprim_i, const double *gprim_j, const double *S, double *Fv) {
+/* hoop: on axisymmetric (x, r) meshes the face value of u_r / r, the third
+ * term of the velocity divergence in cylindrical coordinates (0 otherwise) */
+static void viscous_flux_div(int nd, int nsp, const double *prim_i, const double *prim_j,
+                             double rho_i, double rho_j, const double *aux_i, const double *aux_j,
+                             const double *gprim_i, const double *gprim_j, const double *S,
+                             double hoop, double *Fv) {
   double rho = 0.5 * (rho_i + rho_j);
   double mu = 0.5 * (aux_i[1] + aux_j[1]), lam = 0.5 * (aux_i[2] + aux_j[2]);
   double u[3], Gu[3][3], div = 0.0;
@@ -202,6 +208,7 @@ void om_viscous_flux(int nd, int nsp, const double *prim_i, const double *prim_j
     for (int b = 0; b < nd; b++) Gu[a][b] = 0.5 * (gprim_i[a * nd + b] + gprim_j[a * nd + b]);
     div += Gu[a][a];
   }
+  div += hoop;
   double tauS[3];
   for (int a = 0; a < nd; a++) {
     tauS[a] = 0.0;
@@ -236,6 +243,12 @@ void om_viscous_flux(int nd, int nsp, const double *prim_i, const double *prim_j
     Fv[2 + nd + k] = -JS;
   }
   Fv[1 + nd] = utauS - qS;
+}
+
+void om_viscous_flux(int nd, int nsp, const double *prim_i, const double *prim_j,
+                     double rho_i, double rho_j, const double *aux_i, const double *aux_j,
+                     const double *gprim_i, const double *gprim_j, const double *S, double *Fv) {
+  viscous_flux_div(nd, nsp, prim_i, prim_j, rho_i, rho_j, aux_i, aux_j, gprim_i, gprim_j, S, 0.0, Fv);
 }
 
 /* ------------------------------------------------------------------ */
@@ -852,7 +865,14 @@ static int residual_gas(const om_mesh *m, const om_phys *ph, const double *U, do
           ai[q] = A[(int64_t)q * nn + i];
           aj[q] = A[(int64_t)q * nn + j];
         }
-        om_viscous_flux(nd, nsp, pi, pj, U[i], U[j], ai, aj, gi, gj, Sij, Fv);
+        double hoop = 0.0;
+        if (m->axi) {
+          /* u_r / r at the edge midpoint; on an edge along the axis (u_r = 0
+           * at both ends) its limit, the mean of the ends' d u_r / d r */
+          const double rbar = 0.5 * (X[ab[0] * nd + 1] + X[ab[1] * nd + 1]);
+          hoop = rbar > 0.0 ? 0.5 * (pi[1] + pj[1]) / rbar : 0.5 * (gi[1 * nd + 1] + gj[1 * nd + 1]);
+        }
+        viscous_flux_div(nd, nsp, pi, pj, U[i], U[j], ai, aj, gi, gj, Sij, hoop, Fv);
         for (int v = 0; v < nvar; v++) F[v] -= Fv[v];
       } else if (ph->flux == 0) {
         om_hllc(nd, nsp, ph->gamma, ph->gamma, WL, WR, Sij, F);
@@ -903,6 +923,20 @@ static int residual_gas(const om_mesh *m, const om_phys *ph, const double *U, do
     for (int64_t i = 0; i < nn; i++) {
       const double src = W[(int64_t)nvar * nn + i] * m->Vn[i];
       r[(int64_t)2 * nn + i] += absmode ? fabs(src) : -src;
+    }
+    if (ns_model) {
+      /* its diffusive part, eq. (ns_cyl_source_terms): - 2 eta u_r/r
+       * - lambda (u_r/r + d u_r/d r + d u_x/d x) with the second viscosity
+       * lambda = -2/3 eta (Stokes), i.e. minus the hoop stress tau_theta_theta;
+       * at a node on the axis u_r/r takes its limit d u_r/d r */
+      for (int64_t i = 0; i < nn; i++) {
+        const double eta = A[(int64_t)1 * nn + i], ur = P[(int64_t)1 * nn + i], rr = m->Rn[i];
+        const double durdr = GP[((int64_t)1 * nd + 1) * nn + i], duxdx = GP[((int64_t)0 * nd + 0) * nn + i];
+        const double hoop = rr > 0.0 ? ur / rr : durdr;
+        const double tth = 2.0 * eta * hoop - 2.0 / 3.0 * eta * (hoop + durdr + duxdx);
+        const double src = -tth * m->Vn[i];
+        r[(int64_t)2 * nn + i] += absmode ? fabs(src) : -src;
+      }
     }
   }
   free(W);
@@ -1014,7 +1048,6 @@ static int residual_any(const om_mesh *m, const om_phys *ph, const double *U, co
   /* the predictor: constant-gamma gas on plane meshes, one-stage time step */
   if (ph->predictor && (ph->model != 0 || m->axi || ph->rk != 1)) return -1;
   if (ph->model == 0 || ph->model == 2) {
-    if (m->axi && ph->model == 2) return -1; /* viscous geometric source terms: not built */
     return residual_gas(m, ph, U, dt, r, absmode);
   }
   if (ph->model == 1) {
@@ -1214,7 +1247,7 @@ int om_step(const om_mesh *m, const om_phys *ph, double *U, const double *E, int
           Uk[(int64_t)v * nn + i] = U0[(int64_t)v * nn + i] - a * dt * r[(int64_t)v * nn + i] / vol[i];
       /* axisymmetric gas: the radial velocity is set to zero on the axis
        * after the geometric source terms */
-      if (m->axi && ph->model == 0)
+      if (m->axi && (ph->model == 0 || ph->model == 2))
         for (int64_t i = 0; i < nn; i++)
           if (m->Rn[i] == 0.0) Uk[(int64_t)2 * nn + i] = 0.0;
     }
