@@ -165,10 +165,14 @@ vcx_status vcx_mesh_create_tiled(int ndim, int64_t nnodes, const double *xyz, in
  * of vcx_conservation_sums are int r dA over each node's dual region (second
  * theorem; exact, and non-zero on the axis), and boundary closures use the
  * radius-weighted boundary normals; all over 2 pi.  Nodal gradients stay
- * planar.  Gas solvers add the geometric source p A_i (plane dual area) to
- * the radial momentum (Sec. "Geometric source terms") and set the radial
- * velocity to zero on the axis after each stage.  Drift-diffusion and gas
- * models (Navier-Stokes: VCX_E_ARG); such solvers are not batched or served
+ * planar.  Gas and multi-species solvers add the geometric source p A_i
+ * (plane dual area) to the radial momentum (Sec. "Geometric source terms")
+ * and set the radial velocity to zero on the axis after each stage.  The
+ * multi-species model also takes the diffusive source of eq.
+ * ns_cyl_source_terms, -(2 eta u_r/r + lambda (u_r/r + du_r/dr + du_x/dx)) A_i
+ * with lambda = -2/3 eta and u_r/r -> du_r/dr on the axis, and the
+ * cylindrical div u (with u_r/r at the edge midpoint) in its diffusive
+ * fluxes.  All three models; such solvers are not batched or served
  * (VCX_E_ARG).  vcx_mesh_geometry returns the planar V_i and the
  * radius-weighted S_i^b.  Errors as vcx_mesh_create_tiled, and VCX_E_ARG
  * for r < 0. */

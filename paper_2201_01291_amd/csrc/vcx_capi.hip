@@ -467,9 +467,6 @@ vcx_status vcx::check_physics(vcx_mesh mesh, const vcx_physics& ph, const double
     if (!(ph.mu_ref >= 0.0) || !(ph.T_ref > 0.0) || !(ph.Pr > 0.0))
       return fail(VCX_E_ARG, "Navier-Stokes needs mu_ref >= 0, T_ref > 0, Pr > 0");
   }
-  if (mesh->h.axi && ph.model == VCX_MODEL_NAVIER_STOKES)
-    return fail(VCX_E_ARG, "axisymmetric meshes support the drift-diffusion and gas models (the viscous "
-                           "geometric source terms are not built)");
   if (ph.closure < 0 || ph.closure > 2) return fail(VCX_E_ARG, "closure must be 0, 1 or 2");
   if (ph.closure == 2 && (nd != 2 || mesh->h.axi || ph.model == VCX_MODEL_NAVIER_STOKES))
     return fail(VCX_E_ARG, "the interpolated boundary closure is defined on plane 2D meshes (gas and "

@@ -329,12 +329,14 @@ struct ViscousFace {
 // Stokes' hypothesis, Fourier heat flux plus species enthalpy transport, Fick
 // species fluxes with the correction velocity V_c = sum_k D_k grad Y_k.
 // Linear in S.  Writes Fv = (0, tau S, u.(tau S) - q.S, -J_k.S), to be
-// subtracted from the convective flux.
+// subtracted from the convective flux.  hoop: on axisymmetric (x, r) meshes
+// the face value of u_r / r, the cylindrical third term of div u.
 template <int ND, int NSP, typename T>
-__device__ inline void viscous_flux_face(const ViscousFace<ND, NSP, T>& a, const T* S, T* Fv) {
+__device__ inline void viscous_flux_face(const ViscousFace<ND, NSP, T>& a, const T* S, T* Fv, T hoop = T(0)) {
   T div = T(0);
 #pragma unroll
   for (int d = 0; d < ND; ++d) div += a.g[d * ND + d];
+  div += hoop;
   T utS = T(0);
 #pragma unroll
   for (int i = 0; i < ND; ++i) {

@@ -316,6 +316,13 @@ struct Impl {
       });
     } else if constexpr (MODEL == 2) {
       GasParams gp{s->ph.gamma, s->ph.beta, s->ph.entropy_fix, s->ph.limiter};
+      if constexpr (ND == 2) {
+        if (m.axi)
+          return launch(s, "flux", [&](hipEvent_t ea, hipEvent_t eb) {
+            hipExtLaunchKernelGGL((k_flux_ns<ND, NSP, CT, true>), dim3(xcd_grid(m.ntiles)), dim3(s->flux_block),
+                                  s->lds_flux, st, ea, eb, 0, m, Win, (const double*)s->G, s->PR, gp, f);
+          });
+      }
       return launch(s, "flux", [&](hipEvent_t ea, hipEvent_t eb) {
         hipExtLaunchKernelGGL((k_flux_ns<ND, NSP, CT>), dim3(xcd_grid(m.ntiles)), dim3(s->flux_block),
                            s->lds_flux, st, ea, eb, 0, m, Win, (const double*)s->G, s->PR, gp, f);
@@ -384,10 +391,13 @@ struct Impl {
       if constexpr (ND == 2)
         VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_gas<ND, NSP, FLUX, CT, true>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)flux_bytes));
-    } else if constexpr (MODEL == 2)
+    } else if constexpr (MODEL == 2) {
       VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_ns<ND, NSP, CT>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)flux_bytes));
-    else {
+      if constexpr (ND == 2)
+        VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_ns<ND, NSP, CT, true>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)flux_bytes));
+    } else {
       VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_dd<ND, NSP, CT>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)flux_bytes));
       if constexpr (ND == 2)

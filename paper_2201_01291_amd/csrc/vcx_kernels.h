@@ -896,9 +896,42 @@ __device__ inline void closure_flux(const DevMesh& m, const Finish& f, int k, bo
   }
 }
 
+// Axisymmetric multi-species: the hoop stress tau_theta_theta of node i,
+// 2 eta u_r/r + lambda (u_r/r + du_r/dr + du_x/dx) with lambda = -2/3 eta
+// (Stokes), u_r/r taking its limit du_r/dr on the axis.  The two velocity
+// derivatives come from the node's gradient: G for a node inside one tile,
+// else the sum of its tile partials (run of PG), as the gradient pass
+// leaves them.
+template <int ND, int NSP>
+__device__ inline double ns_hoop_stress(const DevMesh& m, const Finish& f, int i, bool shared, int2 run) {
+  constexpr int NVAR = 2 + ND + NSP, NR = NVAR + 1, NP = ND + 1 + NSP, NC = (NR + NP) * ND;
+  constexpr int CR = (NR + 1) * ND + 1, CX = NR * ND;  // du_r/dr, du_x/dx
+  double durdr, duxdx;
+  if (!shared) {
+    durdr = f.G[(size_t)CR * m.nn + i];
+    duxdx = f.G[(size_t)CX * m.nn + i];
+  } else {
+    double a = 0.0, b = 0.0;
+    for (int p = run.x; p < run.y; ++p) {
+      a += f.PG[(size_t)p * NC + CR];
+      b += f.PG[(size_t)p * NC + CX];
+    }
+    const double coef = -m.inv_vol[i] / double(ND * (ND + 1));
+    durdr = coef * a;
+    duxdx = coef * b;
+  }
+  const double eta = f.Win[(size_t)(NR + NP + 1) * m.nn + i], ur = f.Win[(size_t)(NR + 1) * m.nn + i];
+  const double rr = m.x[(size_t)m.nn + i];
+  const double hoop = rr > 0.0 ? ur / rr : durdr;
+  return 2.0 * eta * hoop - 2.0 / 3.0 * eta * (hoop + durdr + duxdx);
+}
+
+// run: for a node split over tiles, its run of gradient partials (used by
+// the axisymmetric multi-species source)
 template <int ND, int NSP, int MODEL, int NVAR>
 __device__ inline double finish_node(const DevMesh& m, const Finish& f, int i, bool shared,
-                                     double (&r)[NVAR], const NodeIn<NVAR, ND>& ni) {
+                                     double (&r)[NVAR], const NodeIn<NVAR, ND>& ni,
+                                     int2 run = make_int2(0, 0)) {
   if (f.closure && m.nb > 0) {
     const int bi = m.bnd_index[i];
     if (bi >= 0) {
@@ -919,12 +952,14 @@ __device__ inline double finish_node(const DevMesh& m, const Finish& f, int i, b
     }
   }
   bool on_axis = false;
-  if constexpr (MODEL == 0 && ND == 2) {
+  if constexpr ((MODEL == 0 || MODEL == 2) && ND == 2) {
     if (m.axi) {
       // axisymmetric gas: geometric source + p of the radial momentum over
       // the plane dual area (in the residual: - p_i A_i); the radial
       // velocity is set to zero on the axis after it
       r[2] -= f.Win[(size_t)NVAR * m.nn + i] * m.vnode[i];
+      // multi-species: its diffusive part, minus the hoop stress
+      if constexpr (MODEL == 2) r[2] += ns_hoop_stress<ND, NSP>(m, f, i, shared, run) * m.vnode[i];
       on_axis = m.x[(size_t)m.nn + i] == 0.0;
     }
   }
@@ -936,7 +971,7 @@ __device__ inline double finish_node(const DevMesh& m, const Finish& f, int i, b
   double u[NVAR];
 #pragma unroll
   for (int v = 0; v < NVAR; ++v) u[v] = ni.Un[v] - ni.fac * r[v];
-  if constexpr (MODEL == 0 && ND == 2) {
+  if constexpr ((MODEL == 0 || MODEL == 2) && ND == 2) {
     if (on_axis) u[2] = 0.0;
   }
 #pragma unroll
@@ -1791,10 +1826,14 @@ __device__ inline void stage_rows(const double* __restrict__ W, size_t nn, int g
 // flux is linear in the dual-face vector, so it is taken once with their
 // sum.  The edge's net flux F goes to node a as +F and to node b as -F; each
 // node sums its edges in a fixed order (node pass), then the update.
-template <int ND, int NSP, typename CT>
+// AXI: axisymmetric (x, r) meshes; every cell-edge's dual-face vector is
+// weighted by the centroid radius of its face piece (revolved face over
+// 2 pi) and the diffusive flux takes the cylindrical div u.
+template <int ND, int NSP, typename CT, bool AXI = false>
 __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ W,
                                     const double* __restrict__ G,
                                     double* __restrict__ PR, GasParams gp, Finish f, int t, double* lds) {
+  static_assert(!AXI || ND == 2, "axisymmetric meshes are (x, r) planes");
   using L = NsEdgeLds<ND, NSP, CT>;
   constexpr int NV = ND + 1, NVAR = 2 + ND + NSP, NR = NVAR + 1, NCE = L::NCE;
   constexpr int NP = ND + 1 + NSP, NA = 3 + 2 * NSP, NC = (NR + NP) * ND;
@@ -1850,12 +1889,21 @@ __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ W,
     double e[ND][ND], Sd[NV][ND];
     cell_rel_coords<ND>(m, sX, maxn, l, m.shift[c0 + lc], e);
     simplex_normals<ND>(e, Sd);
+    double rr[NV], rc = 0.0;
+    if constexpr (AXI) {
+#pragma unroll
+      for (int k = 0; k < NV; ++k) rr[k] = sX[maxn + l[k]];
+      rc = (rr[0] + rr[1] + rr[2]) / 3.0;
+    }
 #pragma unroll
     for (int ed = 0; ed < NCE; ++ed) {
       const int a = Edges<ND>::a(ed), b = Edges<ND>::b(ed);
+      // axisymmetric: the face piece from the edge midpoint to the centroid,
+      // revolved, carries its mean radius
+      const double rw = AXI ? 0.5 * (0.5 * (rr[a] + rr[b]) + rc) : 1.0;
 #pragma unroll
       for (int d = 0; d < ND; ++d)
-        sS[d * mce + lc * NCE + ed] = CT((Sd[a][d] - Sd[b][d]) * (1.0 / double(ND * NV)));
+        sS[d * mce + lc * NCE + ed] = CT((Sd[a][d] - Sd[b][d]) * (1.0 / double(ND * NV)) * rw);
     }
   }
   __syncthreads();
@@ -1976,8 +2024,14 @@ __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ W,
     }
 #pragma unroll
     for (int q = 0; q < NP * ND; ++q) fa.g[q] = h * (sG[q * maxn + la] + sG[q * maxn + lb]);
-    CT Fv[NVAR];
-    viscous_flux_face<ND, NSP, CT>(fa, S, Fv);
+    CT Fv[NVAR], hoop = CT(0);
+    if constexpr (AXI) {
+      // u_r / r at the edge midpoint; on an edge along the axis its limit,
+      // the mean of the ends' d u_r / d r
+      const CT rbar = h * CT(sX[maxn + la] + sX[maxn + lb]);
+      hoop = rbar > CT(0) ? fa.p[1] / rbar : fa.g[1 * ND + 1];
+    }
+    viscous_flux_face<ND, NSP, CT>(fa, S, Fv, hoop);
 #pragma unroll
     for (int v = 0; v < NVAR; ++v) sF[v * maxe + le] -= double(Fv[v]);
   }
@@ -2016,14 +2070,14 @@ __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ W,
   }
 }
 
-template <int ND, int NSP, typename CT>
+template <int ND, int NSP, typename CT, bool AXI = false>
 __global__ void VCX_FLUX_BOUNDS k_flux_ns(DevMesh m, const double* __restrict__ W,
                                           const double* __restrict__ G,
                                           double* __restrict__ PR, GasParams gp, Finish f) {
   extern __shared__ double lds[];
   const int t = xcd_tile(m.ntiles);
   if (t >= m.ntiles) return;
-  flux_ns_body<ND, NSP, CT>(m, W, G, PR, gp, f, t, lds);
+  flux_ns_body<ND, NSP, CT, AXI>(m, W, G, PR, gp, f, t, lds);
 }
 
 // Primitive rows -> conserved rows, in place on the first nvar rows of W:
@@ -2105,7 +2159,7 @@ __device__ inline void update_shared_body(const DevMesh& m, const double* __rest
 #pragma unroll
       for (int v = 0; v < NVAR; ++v) r[v] += src[v];
     }
-    cand = finish_node<ND, NSP, MODEL, NVAR>(m, f, i, true, r, ni);
+    cand = finish_node<ND, NSP, MODEL, NVAR>(m, f, i, true, r, ni, run);
   }
   if (f.final_stage && f.sc) {
     const double bm = block_min(cand);

@@ -113,10 +113,6 @@ def test_axisymmetric_diffusion_follows_the_3d_heat_kernel():
 def test_axisymmetric_restrictions():
     m, U, E = _case(12, 6)
     gm = vcx.Mesh(m, axisymmetric=True)
-    with pytest.raises(vcx.VcxError) as e:
-        vcx.Solver(gm, vcx.physics(model=vcx.MODEL_NAVIER_STOKES, nspecies=2,
-                                   mixture=wl.synthetic_mixture(2, seed=1)), None)
-    assert e.value.code == vcx.E_ARG
     s = vcx.Solver(gm, _phys_v(), E)
     s.upload(U)
     with pytest.raises(vcx.VcxError) as e:
@@ -162,4 +158,59 @@ def test_axisymmetric_gas_matches_the_oracle(flux):
     s32.upload(U)
     err32 = normwise(s32.residual(dt), om.residual(ph, U, None, dt), om.flux_scale(ph, U, None, dt))
     print("axisymmetric gas MIXED residual err", err32)
+    assert err32.max() <= 1e-4
+
+
+def _axi_ns_case(nsp):
+    """Multi-species flow on an open (x, r) mesh [0, 12 mm] x [0, 6 mm]: an
+    axial stream with a hot, fast core on the axis and a radial outflow
+    vanishing on it."""
+    import cases
+    mix = wl.synthetic_mixture(nsp, seed=4)
+    mix.mu_ref = 2e-3     # visible diffusive fluxes at this resolution
+    m = wl.tri_rect_mesh(24, 12, 0.012, 0.006, jitter=0.2, seed=9 + nsp)
+    x, r = m.xyz
+    bump = np.exp(-((x - 0.005) ** 2 + r ** 2) / 0.003 ** 2)
+    Y = np.vstack([0.3 + 0.2 * np.sin(400.0 * x + k) * bump for k in range(nsp)])
+    Y = Y / Y.sum(axis=0)
+    P = np.vstack([1.1 * (1.0 + 0.1 * bump), 30.0 + 40.0 * bump, 2.0e3 * r * bump,
+                   600.0 + 500.0 * bump, Y])
+    scheme = dict(model="ns", flux="hllc", limiter="vanleer", rk=2, nspecies=nsp, mixture=mix)
+    case = cases.Case(f"axi-ns-sp{nsp}", m, None, None, scheme, tiles=(64, 48))
+    ph = case.oracle_phys()
+    U = oracle.conserved_from_primitive(2, ph, P)
+    return cases.Case(case.name, m, U, None, scheme, tiles=(64, 48))
+
+
+@pytest.mark.parametrize("nsp", [2, 9])
+def test_axisymmetric_navier_stokes_matches_the_oracle(nsp):
+    """Multi-species Navier-Stokes on an (x, r) mesh (eq. ns_cyl_source_terms):
+    radius-weighted convective and diffusive fluxes with the cylindrical
+    div u, the pressure and hoop-stress sources of the radial momentum and
+    u_r = 0 on the axis; small tiles so that many nodes gather partials."""
+    case = _axi_ns_case(nsp)
+    m, U = case.mesh, case.U
+    print(f"[case] {case.name} nn={m.nnodes} tiles={case.tiles}", flush=True)
+    om = oracle.OracleMesh(m, axisymmetric=True)
+    gm = vcx.Mesh(m, axisymmetric=True, tile_cells=case.tiles[0], tile_nodes=case.tiles[1])
+    s = vcx.Solver(gm, case.vcx_phys(), None)
+    s.upload(U)
+    ph = case.oracle_phys()
+    dt = om.timestep(ph, U)
+    assert s.timestep() == pytest.approx(dt, rel=1e-13)
+    err = normwise(s.residual(dt), om.residual(ph, U, None, dt), om.flux_scale(ph, U, None, dt))
+    print("axisymmetric NS residual err", err)
+    assert err.max() <= TOL
+    Uo, to, _, no = om.step(ph, U, None, nsteps=5)
+    tg, _ = s.step(5)
+    assert s.steps_done() == no == 5 and tg == pytest.approx(to, rel=1e-12)
+    Ug = s.download()
+    serr = np.abs(Ug - Uo).max(axis=1) / np.abs(Uo).max(axis=1)
+    print("axisymmetric NS state err", serr)
+    assert serr.max() <= TOL
+    assert np.all(Ug[2][m.xyz[1] == 0.0] == 0.0)
+    s32 = vcx.Solver(gm, case.vcx_phys(1), None)
+    s32.upload(U)
+    err32 = normwise(s32.residual(dt), om.residual(ph, U, None, dt), om.flux_scale(ph, U, None, dt))
+    print(f"axisymmetric NS MIXED residual err {case.name}: {err32}")
     assert err32.max() <= 1e-4
