@@ -23,6 +23,7 @@ MAXSP = 16
 # model / flux / limiter codes of the oracle
 GAS, DRIFT_DIFFUSION, NAVIER_STOKES = 0, 1, 2
 HLLC, ROE = 0, 1
+LLW, SG = 0, 2   # drift-diffusion schemes
 FIRST_ORDER, MINMOD, VANLEER, SWEBY, UNLIMITED = 0, 1, 2, 3, 4
 
 
@@ -122,6 +123,8 @@ def lib():
         L.om_roe.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double, dp, dp, dp, dp]
         L.om_flux_branches.argtypes = [ip, C.c_int]
         L.om_hancock_rate.argtypes = [C.c_int, C.c_int, C.c_double, dp, dp, dp]
+        L.om_sg_flux.restype = C.c_double
+        L.om_sg_flux.argtypes = [C.c_int, C.c_double, C.c_double, dp, dp, dp, C.c_double, dp]
         L.om_ns_conserved.argtypes = [C.c_int, C.POINTER(_Phys), dp, dp]
         pp = C.POINTER(_Phys)
         L.om_residual.argtypes = [C.c_void_p, pp, dp, dp, C.c_double, dp]
@@ -366,6 +369,12 @@ def hancock_rate(nd, nsp, w, g, gamma=1.4):
     out = np.zeros(3 + nd + nsp)
     lib().om_hancock_rate(nd, nsp, float(gamma), _d(w), _d(g), _d(out))
     return out
+
+
+def sg_flux(ui, uj, V, S, dx, D, gbar):
+    """Scharfetter-Gummel flux of one species through S on the edge i -> j."""
+    V, S, dx, gbar = _c64(V), _c64(S), _c64(dx), _c64(gbar)
+    return lib().om_sg_flux(len(S), float(ui), float(uj), _d(V), _d(S), _d(dx), float(D), _d(gbar))
 
 
 def roe(nd, nsp, WL, WR, S, gamma=1.4, fix=0.1):

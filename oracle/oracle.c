@@ -18,7 +18,9 @@
  *                 node of the flux through each cell-edge piece of the dual
  *                 surface
  *   drift-diff.   Sec. "Limited Lax-Wendroff scheme" and "Central difference
- *                 diffusive flux integration"
+ *                 diffusive flux integration"; Sec. "Scharfetter Gummel
+ *                 scheme" (exponential fitting along the edge, central
+ *                 across it)
  *   Euler         Sec. "The HLLC solver", eq. (hllc_formulation_mutlicomponent);
  *                 Sec. "The MUSCL procedure implementation in AVIP",
  *                 eq. (virtual_node_reconstruction) and the co-reconstruction
@@ -950,6 +952,55 @@ static int residual_gas(const om_mesh *m, const om_phys *ph, const double *U, do
 
 /* Limited Lax-Wendroff convective flux plus central diffusive flux for every
  * charged species, per cell-edge (Sec. "Limited Lax-Wendroff scheme"). */
+/* Bernoulli function B(x) = x / (e^x - 1), B(0) = 1 */
+static double bernoulli(double x) { return x == 0.0 ? 1.0 : x / expm1(x); }
+
+/* face gradient (grad u_i + grad u_j) / 2 of one species, into a static
+ * buffer of nd values */
+static const double *gbar_of(int nd, const double *g, int64_t nn, int64_t i, int64_t j) {
+  static double gb[3];
+  for (int d = 0; d < nd; d++) gb[d] = 0.5 * (g[(int64_t)d * nn + i] + g[(int64_t)d * nn + j]);
+  return gb;
+}
+
+/* Scharfetter-Gummel flux through the cell-edge vector S of edge i -> j
+ * (dx = x_j - x_i, h = |dx|), face drift V, diffusion D, face gradient gbar.
+ * S is split into S_par = (S . dx / h^2) dx along the edge and
+ * S_perp = S - S_par.  Along the edge the flux of the 1D steady
+ * advection-diffusion solution between u_i and u_j:
+ *   F . S_par = V . S_par (u_j - e^a u_i) / (1 - e^a),  a = h V . dx/h / D,
+ * written with the Bernoulli function as (S . dx / h^2) D (B(-a) u_i - B(a) u_j)
+ * (the same function, without the cancellation at a -> 0); D = 0 gives its
+ * limit, upwinding.  Across the edge the central flux
+ *   F . S_perp = V (u_i + u_j)/2 . S_perp - D gbar . S_perp. */
+double om_sg_flux(int nd, double ui, double uj, const double *V, const double *S, const double *dx,
+                  double D, const double *gbar) {
+  double h2 = 0.0, sdx = 0.0, vdx = 0.0, vS = 0.0, gS = 0.0, gdx = 0.0;
+  for (int d = 0; d < nd; d++) {
+    h2 += dx[d] * dx[d];
+    sdx += S[d] * dx[d];
+    vdx += V[d] * dx[d];
+    vS += V[d] * S[d];
+    gS += gbar[d] * S[d];
+    gdx += gbar[d] * dx[d];
+  }
+  const double c = sdx / h2;  /* S_par = c dx */
+  double Fpar;
+  if (D > 0.0) {
+    const double a = vdx / D;
+    Fpar = c * D * (bernoulli(-a) * ui - bernoulli(a) * uj);
+  } else {
+    Fpar = c * vdx * (vdx >= 0.0 ? ui : uj);
+  }
+  const double vperp = vS - c * vdx, gperp = gS - c * gdx;
+  return Fpar + 0.5 * (ui + uj) * vperp - D * gperp;
+}
+
+static double sg_flux(int nd, double ui, double uj, const double *V, const double *S, const double *dx,
+                      double D, const double *gbar) {
+  return om_sg_flux(nd, ui, uj, V, S, dx, D, gbar);
+}
+
 static int residual_dd(const om_mesh *m, const om_phys *ph, const double *U, const double *E,
                        double dt, double *r, int absmode) {
   int nd = m->nd, nv = m->nv, ns = ph->nspecies;
@@ -979,6 +1030,16 @@ static int residual_dd(const om_mesh *m, const om_phys *ph, const double *U, con
           double gbar = 0.5 * (g[(int64_t)d * nn + i] + g[(int64_t)d * nn + j]);
           gV += gbar * Vij[d];
           gS += gbar * Sij[d];
+        }
+        if (ph->flux == 2) {
+          /* Scharfetter-Gummel (Sec. "Scharfetter Gummel scheme"): S_ij =
+           * S_par + S_perp along / across the edge; exponential fitting
+           * along it, central across it */
+          double F = sg_flux(nd, u[i], u[j], Vij, Sij, dx, ph->D[s], gbar_of(nd, g, nn, i, j));
+          if (m->axi) F *= m->Rf[c * 3 + e];
+          r[(int64_t)s * nn + i] += absmode ? fabs(F) : F;
+          r[(int64_t)s * nn + j] -= absmode ? -fabs(F) : F;
+          continue;
         }
         /* upwind node w and downwind node m of the edge, virtual node k
          * upwind of w: u_w - u_k = grad u_w . (2 w->m) - (u_m - u_w) */
@@ -1052,6 +1113,7 @@ static int residual_any(const om_mesh *m, const om_phys *ph, const double *U, co
   }
   if (ph->model == 1) {
     if (!E || ph->nspecies < 1) return -1;
+    if (ph->flux != 0 && ph->flux != 2) return -1; /* 0 limited Lax-Wendroff, 2 Scharfetter-Gummel */
     return residual_dd(m, ph, U, E, dt, r, absmode);
   }
   return -1;

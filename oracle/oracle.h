@@ -28,7 +28,8 @@
 typedef struct {
   int32_t model;      /* 0 gas (Euler + passive species), 1 drift-diffusion,
                          2 multi-species Navier-Stokes transport */
-  int32_t flux;       /* gas: 0 HLLC, 1 Roe */
+  int32_t flux;       /* gas: 0 HLLC, 1 Roe; drift-diffusion: 0 limited Lax-Wendroff,
+                         2 Scharfetter-Gummel */
   int32_t limiter;    /* 0 first order, 1 minmod, 2 van Leer, 3 Sweby(beta), 4 unlimited */
   int32_t rk;         /* 1..4, low-storage table */
   int32_t nspecies;   /* gas: passive species; drift-diffusion: charged species */
@@ -81,6 +82,11 @@ void om_roe(int nd, int nsp, double gamma, double fix, const double *WL, const d
  * Euler equations in quasi-linear form, with the node's state and nodal
  * gradients g [nr][nd] (row-major); out [nr] */
 void om_hancock_rate(int nd, int nsp, double gamma, const double *w, const double *g, double *out);
+/* Scharfetter-Gummel flux of one species through the cell-edge vector S of
+ * edge i -> j (dx = x_j - x_i), face drift V [nd], diffusion D and face
+ * gradient gbar [nd] */
+double om_sg_flux(int nd, double ui, double uj, const double *V, const double *S, const double *dx,
+                  double D, const double *gbar);
 /* branch counters of om_hllc / om_roe since the last reset (test
  * instrumentation): [0] HLLC 0 <= S_L, [1] HLLC S_R < 0, [2] HLLC left star,
  * [3] HLLC right star, [4] Roe calls, [5] Roe calls with the entropy fix

@@ -28,7 +28,7 @@ class Case:
 
     def oracle_phys(self):
         s = self.scheme
-        return oracle.Phys(model=self.model, flux=1 if s.get("flux") == "roe" else 0,
+        return oracle.Phys(model=self.model, flux={"roe": 1, "sg": 2}.get(s.get("flux"), 0),
                            limiter=LIMNAMES[s["limiter"]], rk=s.get("rk", 2),
                            nspecies=s.get("nspecies", 0), closure=int(s.get("closure", 1)),
                            beta=s.get("beta", 1.0), cfl=s.get("cfl", 0.5),
@@ -40,7 +40,7 @@ class Case:
     def vcx_phys(self, precision=0):
         from paper_2201_01291_amd import vcx
         s = self.scheme
-        return vcx.physics(model=self.model, flux=1 if s.get("flux") == "roe" else 0,
+        return vcx.physics(model=self.model, flux={"roe": 1, "sg": 2}.get(s.get("flux"), 0),
                            limiter=LIMNAMES[s["limiter"]], rk_stages=s.get("rk", 2),
                            nspecies=s.get("nspecies", 0), closure=int(s.get("closure", 1)),
                            precision=precision, beta=s.get("beta", 1.0), cfl=s.get("cfl", 0.5),
