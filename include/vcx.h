@@ -69,7 +69,20 @@ enum {
                                      without sources): HLLC + viscous, heat and species
                                      diffusion; temperature from the sensible energy */
 };
-enum { VCX_FLUX_HLLC = 0, VCX_FLUX_ROE = 1 };
+enum {
+  VCX_FLUX_HLLC = 0, /* gas */
+  VCX_FLUX_ROE = 1,  /* gas */
+  VCX_FLUX_LLW = 0,  /* drift-diffusion: limited Lax-Wendroff + central diffusion */
+  VCX_FLUX_SG = 2    /* drift-diffusion: Scharfetter-Gummel (Sec. "Scharfetter Gummel
+                        scheme"): along each edge the flux of the 1D steady
+                        advection-diffusion solution through its two nodal values,
+                        c D (B(-a) u_i - B(a) u_j) with S_par = c (x_j - x_i),
+                        a = V . (x_j - x_i) / D, B(x) = x / (e^x - 1) (upwinding
+                        when D = 0); across the edge the central flux
+                        (V u_bar - D grad u_bar) . (S - S_par); V the mean drift of
+                        the two nodes.  Separate gradient and flux passes (not
+                        fused); not batched or served (VCX_E_ARG). */
+};
 enum {
   VCX_LIM_FIRST_ORDER = 0, /* zero slope / Psi = 0 (first-order upwind) */
   VCX_LIM_MINMOD = 1,
@@ -88,7 +101,9 @@ enum {
 /* Physical model and scheme parameters. */
 typedef struct {
   int32_t model;      /* VCX_MODEL_* */
-  int32_t flux;       /* gas: VCX_FLUX_*; ignored for drift-diffusion */
+  int32_t flux;       /* gas: VCX_FLUX_HLLC or VCX_FLUX_ROE; drift-diffusion:
+                         VCX_FLUX_LLW or VCX_FLUX_SG (else VCX_E_ARG);
+                         multi-species: ignored (HLLC) */
   int32_t limiter;    /* VCX_LIM_* */
   int32_t rk_stages;  /* 1..4 (table rk_coeffs) */
   int32_t nspecies;   /* gas: passive species (0, 2 or 9 supported);

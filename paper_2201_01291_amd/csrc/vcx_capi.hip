@@ -481,6 +481,8 @@ vcx_status vcx::check_physics(vcx_mesh mesh, const vcx_physics& ph, const double
     return fail(VCX_E_ARG, "unknown precision");
   if (ph.model == VCX_MODEL_GAS && ph.flux != VCX_FLUX_HLLC && ph.flux != VCX_FLUX_ROE)
     return fail(VCX_E_ARG, "unknown flux");
+  if (ph.model == VCX_MODEL_DRIFT_DIFFUSION && ph.flux != VCX_FLUX_LLW && ph.flux != VCX_FLUX_SG)
+    return fail(VCX_E_ARG, "drift-diffusion flux must be VCX_FLUX_LLW or VCX_FLUX_SG");
   if (!(ph.cfl > 0.0)) return fail(VCX_E_ARG, "cfl must be > 0");
   if (ph.model == VCX_MODEL_GAS && !(ph.gamma > 1.0)) return fail(VCX_E_ARG, "gamma must be > 1");
   if (ph.model == VCX_MODEL_DRIFT_DIFFUSION) {
@@ -524,8 +526,9 @@ vcx_status vcx::configure_solver(vcx_solver s, vcx_mesh mesh, const vcx_physics&
   // gradient + flux passes, whose flux carries the face radii
   // (and the interpolated closure reads neighbours' gradients, complete only
   // after a separate gradient pass)
-  // (the predictor takes the separate passes too)
-  s->fused = !d.axi && ph.closure != 2 && !ph.predictor && s->lds_fused > 0 &&
+  // (the predictor and the Scharfetter-Gummel flux take the separate passes too)
+  const bool sg = ph.model == VCX_MODEL_DRIFT_DIFFUSION && ph.flux == VCX_FLUX_SG;
+  s->fused = !d.axi && ph.closure != 2 && !ph.predictor && !sg && s->lds_fused > 0 &&
              s->lds_fused <= (size_t)mesh->lds_max;
   if (!s->fused) s->lds_fused = 0;
   if (std::max({s->lds_grad, s->lds_flux, s->lds_fused}) > 65536)
@@ -924,9 +927,10 @@ vcx_status vcx::batch_set(BatchGroup* g, vcx_solver* ss, int n, const int* steps
     g->pair = nullptr;
   }
   for (int i = 0; i < n; ++i)
-    if (ss[i] && (ss[i]->mesh->h.axi || ss[i]->ph.closure == 2 || ss[i]->ph.predictor))
-      return fail(VCX_E_ARG, "solvers on axisymmetric meshes, with the interpolated closure or the "
-                             "predictor are not batched");
+    if (ss[i] && (ss[i]->mesh->h.axi || ss[i]->ph.closure == 2 || ss[i]->ph.predictor ||
+                  (ss[i]->ph.model == VCX_MODEL_DRIFT_DIFFUSION && ss[i]->ph.flux == VCX_FLUX_SG)))
+      return fail(VCX_E_ARG, "solvers on axisymmetric meshes, with the interpolated closure, the "
+                             "predictor or the Scharfetter-Gummel flux are not batched");
   g->mem.assign(ss, ss + n);
   g->q = 0;
   if (n == 0) return VCX_OK;
@@ -1098,6 +1102,8 @@ static vcx_status solve_batch(vcx_solver* ss, int n, const int* nsteps, const do
     if (ss[i]->mesh->h.axi) return fail(VCX_E_ARG, "solvers on axisymmetric meshes are not batched");
     if (ss[i]->ph.closure == 2) return fail(VCX_E_ARG, "solvers with the interpolated closure are not batched");
     if (ss[i]->ph.predictor) return fail(VCX_E_ARG, "solvers with the MUSCL-Hancock predictor are not batched");
+    if (ss[i]->ph.model == VCX_MODEL_DRIFT_DIFFUSION && ss[i]->ph.flux == VCX_FLUX_SG)
+      return fail(VCX_E_ARG, "solvers with the Scharfetter-Gummel flux are not batched");
     if (!batch_compatible(ss[i], ss[0]))
       return fail(VCX_E_ARG, "batch members must share the model and scheme parameters");
     for (int j = 0; j < i; ++j)

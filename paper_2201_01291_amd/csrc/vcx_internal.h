@@ -336,20 +336,29 @@ struct Impl {
       pp.beta = s->ph.beta;
       pp.dt_host = dt_host;
       pp.limiter = s->ph.limiter;
+      const bool sg = s->ph.flux == VCX_FLUX_SG;
       if constexpr (ND == 2) {
         if (m.axi)
           return launch(s, "flux", [&](hipEvent_t ea, hipEvent_t eb) {
-            hipExtLaunchKernelGGL((k_flux_dd<ND, NSP, CT, true>), dim3(xcd_grid(m.ntiles)),
-                               dim3(s->tile_block), s->lds_flux, st, ea, eb, 0, m, Win, (const double*)s->G,
-                               s->PR, pp, f);
+            if (sg)
+              hipExtLaunchKernelGGL((k_flux_dd<ND, NSP, CT, true, true>), dim3(xcd_grid(m.ntiles)),
+                                    dim3(s->tile_block), s->lds_flux, st, ea, eb, 0, m, Win,
+                                    (const double*)s->G, s->PR, pp, f);
+            else
+              hipExtLaunchKernelGGL((k_flux_dd<ND, NSP, CT, true>), dim3(xcd_grid(m.ntiles)),
+                                    dim3(s->tile_block), s->lds_flux, st, ea, eb, 0, m, Win,
+                                    (const double*)s->G, s->PR, pp, f);
           });
       }
+      const int fb = cell_halves<ND, CT>() == 2 ? std::min(256, 2 * ((m.max_tile_cells + 63) / 64) * 64)
+                                                : s->tile_block;
       return launch(s, "flux", [&](hipEvent_t ea, hipEvent_t eb) {
-        const int fb = cell_halves<ND, CT>() == 2 ? std::min(256, 2 * ((m.max_tile_cells + 63) / 64) * 64)
-                                                  : s->tile_block;
-        hipExtLaunchKernelGGL((k_flux_dd<ND, NSP, CT>), dim3(xcd_grid(m.ntiles)),
-                           dim3(fb), s->lds_flux, st, ea, eb, 0, m, Win, (const double*)s->G,
-                           s->PR, pp, f);
+        if (sg)
+          hipExtLaunchKernelGGL((k_flux_dd<ND, NSP, CT, false, true>), dim3(xcd_grid(m.ntiles)), dim3(fb),
+                                s->lds_flux, st, ea, eb, 0, m, Win, (const double*)s->G, s->PR, pp, f);
+        else
+          hipExtLaunchKernelGGL((k_flux_dd<ND, NSP, CT>), dim3(xcd_grid(m.ntiles)), dim3(fb), s->lds_flux,
+                                st, ea, eb, 0, m, Win, (const double*)s->G, s->PR, pp, f);
       });
     }
   }
@@ -400,9 +409,14 @@ struct Impl {
     } else {
       VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_dd<ND, NSP, CT>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)flux_bytes));
-      if constexpr (ND == 2)
+      VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_dd<ND, NSP, CT, false, true>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)flux_bytes));
+      if constexpr (ND == 2) {
         VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_dd<ND, NSP, CT, true>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)flux_bytes));
+        VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_dd<ND, NSP, CT, true, true>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)flux_bytes));
+      }
     }
     VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_grad_tile_batch<ND, NGF>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)grad_bytes));

@@ -1178,7 +1178,45 @@ __global__ void __launch_bounds__(256) k_closure2(DevMesh m, Finish f, double* _
 // Drift-diffusion fluxes of the tile's cells: limited Lax-Wendroff
 // convective flux (upwind node w, downwind node m, virtual node upwind of w)
 // plus central diffusion; accumulated per cell vertex into sR.
-template <int ND, int NS, typename CT, int NV, bool AXI = false>
+// Bernoulli function B(x) = x / (e^x - 1), B(0) = 1
+template <typename T>
+__device__ inline T bernoulli(T x) {
+  if constexpr (sizeof(T) == sizeof(double))
+    return x == T(0) ? T(1) : x / expm1(x);
+  else
+    return x == T(0) ? T(1) : x / expm1f(x);
+}
+
+// Scharfetter-Gummel flux of one species through the cell-edge vector S of
+// the edge a -> b (dx = x_b - x_a): with S_par = c dx, c = S.dx / |dx|^2,
+// exponential fitting along the edge, c D (B(-al) u_a - B(al) u_b) with
+// al = V.dx / D (upwinding when D = 0), and the central flux
+// (V u_bar - D g_bar) . (S - S_par) across it.  vS = V.S, gS = g_bar.S.
+template <int ND, typename CT>
+__device__ inline CT sg_edge_flux(CT ua, CT ub, const CT (&V)[ND], const CT (&S)[ND], const CT (&dx)[ND],
+                                  CT D, const CT (&gbar)[ND], CT vS, CT gS) {
+  CT h2 = CT(0), sdx = CT(0), vdx = CT(0), gdx = CT(0);
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    h2 += dx[d] * dx[d];
+    sdx += S[d] * dx[d];
+    vdx += V[d] * dx[d];
+    gdx += gbar[d] * dx[d];
+  }
+  const CT c = sdx / h2;
+  CT fpar;
+  if (D > CT(0)) {
+    const CT al = vdx / D;
+    fpar = c * D * (bernoulli<CT>(-al) * ua - bernoulli<CT>(al) * ub);
+  } else {
+    fpar = c * vdx * (vdx >= CT(0) ? ua : ub);
+  }
+  return fpar + CT(0.5) * (ua + ub) * (vS - c * vdx) - D * (gS - c * gdx);
+}
+
+// SG: the Scharfetter-Gummel flux instead of limited Lax-Wendroff with the
+// central diffusive flux.
+template <int ND, int NS, typename CT, int NV, bool AXI = false, bool SG = false>
 __device__ inline void dd_cell_fluxes(const DevMesh& m, const TilePre<NV>& tp, const double* sX,
                                       const CT* sU, const CT* sG, const CT* sE, double* sR, CellLd L,
                                       CT dt, const DDParams& pp) {
@@ -1252,6 +1290,18 @@ __device__ inline void dd_cell_fluxes(const DevMesh& m, const TilePre<NV>& tp, c
           gB += gb * dx[d];
         }
         const CT ua = sU[s * L.ldw + la], ub = sU[s * L.ldw + lb];
+        if constexpr (SG) {
+          CT V[ND], gbar[ND];
+#pragma unroll
+          for (int d = 0; d < ND; ++d) {
+            V[d] = zm * Ebar[d];
+            gbar[d] = CT(0.5) * (sG[(s * ND + d) * L.ldg + la] + sG[(s * ND + d) * L.ldg + lb]);
+          }
+          const CT F = sg_edge_flux<ND, CT>(ua, ub, V, S, dx, CT(pp.D[s]), gbar, v, gS);
+          acc[a][s] += double(F) * rw;
+          acc[b][s] -= double(F) * rw;
+          continue;
+        }
         // upwind node w, downwind node m; the virtual node upwind of w
         const bool fwd = v >= CT(0);
         const CT uw = fwd ? ua : ub;
@@ -1380,7 +1430,7 @@ __global__ void VCX_FLUX_BOUNDS k_flux_gas(DevMesh m, const double* __restrict__
 // drift-diffusion flux pass
 // ---------------------------------------------------------------------------
 
-template <int ND, int NS, typename CT, bool AXI = false>
+template <int ND, int NS, typename CT, bool AXI = false, bool SG = false>
 __device__ inline void flux_dd_body(DevMesh m, const double* __restrict__ U,
                                                  const double* __restrict__ G,
                                                  double* __restrict__ PR, DDParams pp, Finish f,
@@ -1425,7 +1475,7 @@ __device__ inline void flux_dd_body(DevMesh m, const double* __restrict__ U,
   tile_store_inc<NV>(m, tp, sInc);
   __syncthreads();
   const double dt = f.sc ? f.sc->dt : pp.dt_host;
-  dd_cell_fluxes<ND, NS, CT, NV, AXI>(m, tp, sX, sU, sG, sE, sR, CellLd{maxn, maxn, maxn, maxc}, CT(dt), pp);
+  dd_cell_fluxes<ND, NS, CT, NV, AXI, SG>(m, tp, sX, sU, sG, sE, sR, CellLd{maxn, maxn, maxn, maxc}, CT(dt), pp);
   __syncthreads();
   const double cand = tile_node_pass<ND, NS, 1, NS, (NH == 2)>(m, f, dt, PR, ns, sSl, maxn, sInc, sR, maxc);
   if (f.final_stage && f.sc) {
@@ -1434,14 +1484,14 @@ __device__ inline void flux_dd_body(DevMesh m, const double* __restrict__ U,
   }
 }
 
-template <int ND, int NS, typename CT, bool AXI = false>
+template <int ND, int NS, typename CT, bool AXI = false, bool SG = false>
 __global__ void VCX_FLUX_BOUNDS k_flux_dd(DevMesh m, const double* __restrict__ U,
                                                  const double* __restrict__ G,
                                                  double* __restrict__ PR, DDParams pp, Finish f) {
   extern __shared__ double lds[];
   const int t = xcd_tile(m.ntiles);
   if (t >= m.ntiles) return;
-  flux_dd_body<ND, NS, CT, AXI>(m, U, G, PR, pp, f, t, lds);
+  flux_dd_body<ND, NS, CT, AXI, SG>(m, U, G, PR, pp, f, t, lds);
 }
 
 // ---------------------------------------------------------------------------

@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(PKG, "libvcx.so")
 OK, E_ARG, E_MESH, E_OOM, E_HIP, E_UNSTABLE, E_BUSY, E_STATE = 0, -1, -2, -3, -4, -5, -6, -7
 MODEL_GAS, MODEL_DRIFT_DIFFUSION, MODEL_NAVIER_STOKES = 0, 1, 2
 FLUX_HLLC, FLUX_ROE = 0, 1
+FLUX_LLW, FLUX_SG = 0, 2   # drift-diffusion schemes
 LIM_FIRST_ORDER, LIM_MINMOD, LIM_VANLEER, LIM_SWEBY, LIM_NONE = 0, 1, 2, 3, 4
 PREC_FP64, PREC_MIXED = 0, 1
 MAX_SPECIES = 16

@@ -204,8 +204,25 @@ def make_case(name: str) -> Case:
         # leaves with nine species in FP64
         return Case(name, m, U, None, dict(model="gas", flux="hllc", limiter="minmod", rk=1,
                                            nspecies=9, predictor=1), tiles=(96, 72))
+    # -- Scharfetter-Gummel drift-diffusion flux --------------------------
+    if name == "dd2d-sg":
+        m = wl.dd_streamer_mesh(40, 25, seed=4)
+        n, E = wl.dd_fields(m, sigma=2e-3, seed=11)
+        return Case(name, m, n, E, dict(DD2, flux="sg", rk=2))
+    if name == "dd2d-open-sg":
+        m = wl.tri_rect_mesh(23, 17, 0.02, 0.015, jitter=0.2, seed=27)
+        n, E = wl.dd_fields(m, sigma=3e-3, seed=12)
+        return Case(name, m, n, E, dict(DD2, flux="sg"))
+    if name == "dd3d-sg":
+        m = wl.kuhn_tet_mesh(5, 5, 6, 1e-3, 1e-3, 1.2e-3, jitter=0.1, seed=28)
+        n, E = wl.dd_fields(m, sigma=3e-4, bump_sigma=2e-4, bump_amp=50.0, nspecies=1, seed=13)
+        return Case(name, m, n, E, dict(model="dd", flux="sg", limiter="minmod", rk=2, nspecies=1,
+                                        z=[-1.0], mu=[0.04], D=[0.1]))
     raise KeyError(name)
 
+
+# Drift-diffusion cases with the Scharfetter-Gummel flux
+SG_CASES = ["dd2d-sg", "dd2d-open-sg", "dd3d-sg"]
 
 # Gas cases with the MUSCL-Hancock predictor (plane meshes, one stage)
 HANCOCK_CASES = ["euler2d-hancock-hllc", "sod-hancock-roe", "euler2d-open-closure2-hancock",
@@ -228,7 +245,7 @@ BRANCH_CASES = {
 CASE_NAMES = ["dd2d-streamer", "dd2d-diel", "dd2d-open-vanleer", "dd2d-open-closure2",
               "euler2d-open-closure2", "dd3d-sweby", "sod-hllc", "euler2d-roe-sp2",
               "euler3d-roe", "euler3d-hllc-open-sp2", "euler3d-hllc-sp9", "ns3d-sp9",
-              "ns2d-sp2-open", "ns2d-sp2-bigtile", *BRANCH_CASES, *HANCOCK_CASES]
+              "ns2d-sp2-open", "ns2d-sp2-bigtile", *BRANCH_CASES, *HANCOCK_CASES, *SG_CASES]
 
 
 def reconstructed(case: Case) -> np.ndarray:

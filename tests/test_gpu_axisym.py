@@ -57,9 +57,11 @@ def _setup(prec=0, **kw):
     return m, U, E, om, gm, s
 
 
-def test_axisymmetric_residual_timestep_and_steps_match_the_oracle():
-    m, U, E, om, gm, s = _setup()
-    ph = _phys_o()
+@pytest.mark.parametrize("flux", [0, 2])
+def test_axisymmetric_residual_timestep_and_steps_match_the_oracle(flux):
+    """Limited Lax-Wendroff (0) and Scharfetter-Gummel (2) fluxes."""
+    m, U, E, om, gm, s = _setup(flux=flux)
+    ph = _phys_o(flux=flux)
     dt = om.timestep(ph, U, E)
     assert s.timestep() == pytest.approx(dt, rel=1e-13)
     err = normwise(s.residual(dt), om.residual(ph, U, E, dt), om.flux_scale(ph, U, E, dt))
