@@ -164,7 +164,7 @@ class OracleMesh:
         self.axi = bool(axisymmetric)
         self.nd, self.nn = mesh.ndim, mesh.nnodes
         self.nc, self.nv = mesh.ncells, mesh.nv
-        self.ne = 3 if self.nv == 3 else 6
+        self.ne = 3 if self.nv == 3 else (4 if self.nd == 2 else 6)
         xyz = _c64(mesh.xyz)
         cells = np.ascontiguousarray(mesh.cells, dtype=np.int64)
         per = None if mesh.period is None else _c64(mesh.period)

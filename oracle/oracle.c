@@ -77,7 +77,9 @@ struct om_mesh {
   int64_t nn, nc;
   int64_t *cell; /* [nc][nv] */
   double *X;     /* [nc][nv][nd] unwrapped vertex coordinates */
-  double *S;     /* [nc][nv][nd] node normals S_k (outward normal of the opposite face) */
+  double *S;     /* [nc][nv][nd] node normals S_k (simplex: outward normal of the opposite
+                    face; quadrilateral: minus the sum of its two sides' outward normals) */
+  double *orient; /* [nc] quadrilaterals: +1 counter-clockwise vertex order, -1 clockwise */
   double *Vc;    /* [nc] */
   double *Vn;    /* [nn] */
   double *Sb;    /* [nn][nd] boundary node normals */
@@ -99,12 +101,18 @@ struct om_mesh {
   double *beS;   /* [nbe][2] */
 };
 
-/* local cell-edges, oriented from the lower to the higher local vertex */
+/* local cell-edges: of a simplex every vertex pair, oriented from the lower
+ * to the higher local vertex; of a quadrilateral its four sides in cyclic
+ * order (its diagonals are not edges) */
 static const int TRI_EDGES[3][2] = {{0, 1}, {0, 2}, {1, 2}};
 static const int TET_EDGES[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+static const int QUAD_EDGES[4][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 0}};
 
-static const int *edge_of(int nv, int e) {
-  return nv == 3 ? TRI_EDGES[e] : TET_EDGES[e];
+static int is_quad(const om_mesh *m) { return m->nd == 2 && m->nv == 4; }
+
+static const int *edge_of(const om_mesh *m, int e) {
+  if (m->nv == 3) return TRI_EDGES[e];
+  return is_quad(m) ? QUAD_EDGES[e] : TET_EDGES[e];
 }
 
 int om_nvar(int nd, const om_phys *ph) {
@@ -304,6 +312,48 @@ static void simplex_normals(int nd, const double *X, double *S, double *V) {
   }
 }
 
+/* Node normals of a convex quadrilateral (2D, vertices in cyclic order)
+ * from eq. (node_normal): in 2D every face is a side with two vertices, so
+ * S_k = -(S_f + S_g) over the two sides f, g through k, S_f the outward side
+ * normals of side length; V the area.  Returns 0 for a non-convex or
+ * degenerate cell.  *orient: +1 counter-clockwise, -1 clockwise. */
+static int quad_normals(const double *X, double *S, double *V, double *orient) {
+  double A2 = 0.0; /* twice the signed area (shoelace) */
+  for (int k = 0; k < 4; k++) {
+    const int l = (k + 1) % 4;
+    A2 += X[2 * k] * X[2 * l + 1] - X[2 * l] * X[2 * k + 1];
+  }
+  const double o = A2 > 0.0 ? 1.0 : -1.0;
+  for (int k = 0; k < 4; k++) {
+    const int l = (k + 1) % 4, q = (k + 2) % 4;
+    const double ax = X[2 * l] - X[2 * k], ay = X[2 * l + 1] - X[2 * k + 1];
+    const double bx = X[2 * q] - X[2 * l], by = X[2 * q + 1] - X[2 * l + 1];
+    if ((ax * by - ay * bx) * o <= 0.0) return 0; /* every corner turns the same way */
+  }
+  double N[4][2];
+  for (int k = 0; k < 4; k++) {
+    const int l = (k + 1) % 4;
+    const double tx = X[2 * l] - X[2 * k], ty = X[2 * l + 1] - X[2 * k + 1];
+    N[k][0] = o * ty;
+    N[k][1] = -o * tx;
+  }
+  for (int k = 0; k < 4; k++) {
+    const int p = (k + 3) % 4;
+    S[2 * k] = -(N[k][0] + N[p][0]);
+    S[2 * k + 1] = -(N[k][1] + N[p][1]);
+  }
+  *V = 0.5 * fabs(A2);
+  *orient = o;
+  return 1;
+}
+
+/* Outward normal (of side length) of side k -> k+1 of a quadrilateral */
+static void quad_side_normal(const double *X, int k, double orient, double *n) {
+  const int l = (k + 1) % 4;
+  n[0] = orient * (X[2 * l + 1] - X[2 * k + 1]);
+  n[1] = -orient * (X[2 * l] - X[2 * k]);
+}
+
 typedef struct {
   int64_t key[3];
   int64_t cell;
@@ -331,7 +381,7 @@ static void sort_small(int64_t *v, int n) {
 void om_mesh_destroy(om_mesh *m) {
   if (!m) return;
   free(m->cell); free(m->X); free(m->S); free(m->Vc); free(m->Vn); free(m->Sb); free(m->bnd);
-  free(m->Rf); free(m->Vp); free(m->Sbr); free(m->Rn); free(m->be); free(m->beS);
+  free(m->Rf); free(m->Vp); free(m->Sbr); free(m->Rn); free(m->be); free(m->beS); free(m->orient);
   free(m);
 }
 
@@ -343,14 +393,18 @@ om_mesh *om_mesh_create(int nd, int64_t nn, const double *xyz, int64_t nc, int n
 om_mesh *om_mesh_create_axi(int nd, int64_t nn, const double *xyz, int64_t nc, int nv,
                             const int64_t *cells, const double *period, int axi, int *status) {
   *status = -1;
-  if (!(nd == 2 || nd == 3) || nv != nd + 1 || nn <= 0 || nc <= 0 || !xyz || !cells) return NULL;
+  if (!(nd == 2 || nd == 3) || !(nv == nd + 1 || (nd == 2 && nv == 4)) || nn <= 0 || nc <= 0 || !xyz ||
+      !cells)
+    return NULL;
   if (axi && (nd != 2 || (period && period[1] > 0.0))) return NULL;  /* (x, r) plane, r not periodic */
   if (axi)
     for (int64_t i = 0; i < nn; i++)
       if (xyz[nn + i] < 0.0) return NULL;
   om_mesh *m = calloc(1, sizeof(*m));
   if (!m) { *status = -3; return NULL; }
-  m->nd = nd; m->nv = nv; m->ne = nd == 2 ? 3 : 6; m->nn = nn; m->nc = nc;
+  m->nd = nd; m->nv = nv; m->ne = nv == 3 ? 3 : (nd == 2 ? 4 : 6); m->nn = nn; m->nc = nc;
+  m->orient = calloc(nc, sizeof(double));
+  if (!m->orient) { om_mesh_destroy(m); *status = -3; return NULL; }
   m->cell = malloc(sizeof(int64_t) * nc * nv);
   m->X = malloc(sizeof(double) * nc * nv * nd);
   m->S = malloc(sizeof(double) * nc * nv * nd);
@@ -379,7 +433,13 @@ om_mesh *om_mesh_create_axi(int nd, int64_t nn, const double *xyz, int64_t nc, i
         }
         X[k * nd + d] = x;
       }
-    simplex_normals(nd, X, m->S + c * nv * nd, &m->Vc[c]);
+    if (is_quad(m)) {
+      if (!quad_normals(X, m->S + c * nv * nd, &m->Vc[c], &m->orient[c])) {
+        om_mesh_destroy(m); *status = -2; return NULL;
+      }
+    } else {
+      simplex_normals(nd, X, m->S + c * nv * nd, &m->Vc[c]);
+    }
     if (m->Vc[c] > vmax) vmax = m->Vc[c];
   }
   for (int64_t c = 0; c < nc; c++)
@@ -388,21 +448,48 @@ om_mesh *om_mesh_create_axi(int nd, int64_t nn, const double *xyz, int64_t nc, i
     for (int k = 0; k < nv; k++) m->Vn[m->cell[c * nv + k]] += m->Vc[c] / nv;
   if (axi) {
     m->axi = 1;
-    m->Rf = malloc(sizeof(double) * nc * 3);
+    m->Rf = malloc(sizeof(double) * nc * m->ne);
     m->Vp = calloc(nn, sizeof(double));
     m->Sbr = calloc(nn * nd, sizeof(double));
     m->Rn = malloc(sizeof(double) * nn);
     if (!m->Rf || !m->Vp || !m->Sbr || !m->Rn) { om_mesh_destroy(m); *status = -3; return NULL; }
     for (int64_t i = 0; i < nn; i++) m->Rn[i] = xyz[nn + i];
     for (int64_t c = 0; c < nc; c++) {
+      if (is_quad(m)) {
+        /* quadrilateral: the dual piece of side (a, b) runs from its
+         * midpoint to the centre C (mean of the vertices); node k's dual
+         * region is the quadrilateral (X_k, M_k, C, M_p) with M_k, M_p the
+         * midpoints of its two sides, split into triangles (X_k, M_k, C) and
+         * (X_k, C, M_p) whose first moments are area times mean radius */
+        const double *X = m->X + c * 8;
+        double C[2] = {0.0, 0.0};
+        for (int k = 0; k < 4; k++) {
+          C[0] += 0.25 * X[2 * k];
+          C[1] += 0.25 * X[2 * k + 1];
+        }
+        for (int e = 0; e < 4; e++) {
+          const int *ab = edge_of(m, e);
+          m->Rf[c * m->ne + e] = 0.5 * (0.5 * (X[2 * ab[0] + 1] + X[2 * ab[1] + 1]) + C[1]);
+        }
+        for (int k = 0; k < 4; k++) {
+          const int l = (k + 1) % 4, p = (k + 3) % 4;
+          const double Mk[2] = {0.5 * (X[2 * k] + X[2 * l]), 0.5 * (X[2 * k + 1] + X[2 * l + 1])};
+          const double Mp[2] = {0.5 * (X[2 * k] + X[2 * p]), 0.5 * (X[2 * k + 1] + X[2 * p + 1])};
+          const double *P0 = X + 2 * k;
+          const double a1 = 0.5 * fabs((Mk[0] - P0[0]) * (C[1] - P0[1]) - (Mk[1] - P0[1]) * (C[0] - P0[0]));
+          const double a2 = 0.5 * fabs((C[0] - P0[0]) * (Mp[1] - P0[1]) - (C[1] - P0[1]) * (Mp[0] - P0[0]));
+          m->Vp[m->cell[c * 4 + k]] += a1 * (P0[1] + Mk[1] + C[1]) / 3.0 + a2 * (P0[1] + C[1] + Mp[1]) / 3.0;
+        }
+        continue;
+      }
       const double *X = m->X + c * 3 * 2;
       const double r[3] = {X[1], X[3], X[5]};
       const double rc = (r[0] + r[1] + r[2]) / 3.0;
       /* dual piece of edge (a, b): from the edge midpoint to the centroid */
       for (int e = 0; e < 3; e++) {
-        const int *ab = edge_of(3, e);
+        const int *ab = edge_of(m, e);
         const double rm = 0.5 * (r[ab[0]] + r[ab[1]]);
-        m->Rf[c * 3 + e] = 0.5 * (rm + rc);
+        m->Rf[c * m->ne + e] = 0.5 * (rm + rc);
       }
       /* node k's dual region in the triangle: the quadrilateral (X_k,
        * midpoint k-l, centroid, midpoint k-m), two triangles of area A/6 */
@@ -424,8 +511,15 @@ om_mesh *om_mesh_create_axi(int nd, int64_t nn, const double *xyz, int64_t nc, i
       face_rec *r = &f[c * nv + k];
       int q = 0;
       r->key[0] = r->key[1] = r->key[2] = -1;
-      for (int v = 0; v < nv; v++)
-        if (v != k) r->key[q++] = m->cell[c * nv + v];
+      if (is_quad(m)) {
+        /* face k of a quadrilateral: its side k -> k+1 */
+        r->key[0] = m->cell[c * nv + k];
+        r->key[1] = m->cell[c * nv + (k + 1) % 4];
+      } else {
+        /* face k of a simplex: the one opposite vertex k */
+        for (int v = 0; v < nv; v++)
+          if (v != k) r->key[q++] = m->cell[c * nv + v];
+      }
       sort_small(r->key, nd);
       r->cell = c;
       r->k = k;
@@ -441,9 +535,15 @@ om_mesh *om_mesh_create_axi(int nd, int64_t nn, const double *xyz, int64_t nc, i
     while (b < nf && memcmp(f[b].key, f[a].key, sizeof(f[a].key)) == 0) b++;
     if (b - a > 2) { free(f); om_mesh_destroy(m); *status = -2; return NULL; }
     if (b - a == 1) {
-      /* the face opposite vertex k: its outward area vector is S_k; each of its
-       * n_d nodes receives an equal share (boundary node normal S_i^b) */
+      /* its outward area vector: of the face opposite vertex k of a simplex,
+       * S_k; of side k of a quadrilateral, that side's outward normal.  Each
+       * of its n_d nodes receives an equal share (boundary node normal S_i^b) */
+      double Sq[2];
       const double *Sk = m->S + (f[a].cell * nv + f[a].k) * nd;
+      if (is_quad(m)) {
+        quad_side_normal(m->X + f[a].cell * 8, f[a].k, m->orient[f[a].cell], Sq);
+        Sk = Sq;
+      }
       for (int q = 0; q < nd; q++) {
         int64_t i = f[a].key[q];
         m->bnd[i] = 1;
@@ -498,6 +598,25 @@ void om_geometry(const om_mesh *m, double *S, double *Vc, double *Vn, double *Sb
 
 /* dual-surface normal of cell-edge (a,b): S_ab = (S_a - S_b) / (n_d n_v) */
 static void edge_normal(const om_mesh *m, int64_t c, int a, int b, double *Sab) {
+  if (is_quad(m)) {
+    /* the dual face in a quadrilateral: the segment from the side's midpoint
+     * to the cell centre (mean of the vertices), oriented from a to b */
+    const double *X = m->X + c * 8;
+    double cx = 0.0, cy = 0.0;
+    for (int k = 0; k < 4; k++) {
+      cx += 0.25 * X[2 * k];
+      cy += 0.25 * X[2 * k + 1];
+    }
+    const double tx = cx - 0.5 * (X[2 * a] + X[2 * b]), ty = cy - 0.5 * (X[2 * a + 1] + X[2 * b + 1]);
+    double nx = ty, ny = -tx;
+    if (nx * (X[2 * b] - X[2 * a]) + ny * (X[2 * b + 1] - X[2 * a + 1]) < 0.0) {
+      nx = -nx;
+      ny = -ny;
+    }
+    Sab[0] = nx;
+    Sab[1] = ny;
+    return;
+  }
   const double *S = m->S + c * m->nv * m->nd;
   for (int d = 0; d < m->nd; d++)
     Sab[d] = (S[a * m->nd + d] - S[b * m->nd + d]) / (double)(m->nd * m->nv);
@@ -506,7 +625,7 @@ static void edge_normal(const om_mesh *m, int64_t c, int a, int b, double *Sab) 
 void om_edge_normals(const om_mesh *m, double *Sij, int64_t *ends) {
   for (int64_t c = 0; c < m->nc; c++)
     for (int e = 0; e < m->ne; e++) {
-      const int *ab = edge_of(m->nv, e);
+      const int *ab = edge_of(m, e);
       edge_normal(m, c, ab[0], ab[1], Sij + (c * m->ne + e) * m->nd);
       ends[(c * m->ne + e) * 2] = m->cell[c * m->nv + ab[0]];
       ends[(c * m->ne + e) * 2 + 1] = m->cell[c * m->nv + ab[1]];
@@ -823,7 +942,7 @@ static int residual_gas(const om_mesh *m, const om_phys *ph, const double *U, do
   for (int64_t c = 0; c < m->nc; c++) {
     const double *X = m->X + c * nv * nd;
     for (int e = 0; e < m->ne; e++) {
-      const int *ab = edge_of(nv, e);
+      const int *ab = edge_of(m, e);
       int64_t i = m->cell[c * nv + ab[0]], j = m->cell[c * nv + ab[1]];
       double Sij[3], dx[3];
       edge_normal(m, c, ab[0], ab[1], Sij);
@@ -882,7 +1001,7 @@ static int residual_gas(const om_mesh *m, const om_phys *ph, const double *U, do
         om_roe(nd, nsp, ph->gamma, ph->entropy_fix, WL, WR, Sij, F);
       }
       if (m->axi)
-        for (int v = 0; v < nvar; v++) F[v] *= m->Rf[c * 3 + e]; /* revolved face, over 2 pi */
+        for (int v = 0; v < nvar; v++) F[v] *= m->Rf[c * m->ne + e]; /* revolved face, over 2 pi */
       for (int v = 0; v < nvar; v++) {
         r[(int64_t)v * nn + i] += absmode ? fabs(F[v]) : F[v];
         r[(int64_t)v * nn + j] -= absmode ? -fabs(F[v]) : F[v];
@@ -1012,7 +1131,7 @@ static int residual_dd(const om_mesh *m, const om_phys *ph, const double *U, con
   for (int64_t c = 0; c < m->nc; c++) {
     const double *X = m->X + c * nv * nd;
     for (int e = 0; e < m->ne; e++) {
-      const int *ab = edge_of(nv, e);
+      const int *ab = edge_of(m, e);
       int64_t i = m->cell[c * nv + ab[0]], j = m->cell[c * nv + ab[1]];
       double Sij[3], dx[3];
       edge_normal(m, c, ab[0], ab[1], Sij);
@@ -1036,7 +1155,7 @@ static int residual_dd(const om_mesh *m, const om_phys *ph, const double *U, con
            * S_par + S_perp along / across the edge; exponential fitting
            * along it, central across it */
           double F = sg_flux(nd, u[i], u[j], Vij, Sij, dx, ph->D[s], gbar_of(nd, g, nn, i, j));
-          if (m->axi) F *= m->Rf[c * 3 + e];
+          if (m->axi) F *= m->Rf[c * m->ne + e];
           r[(int64_t)s * nn + i] += absmode ? fabs(F) : F;
           r[(int64_t)s * nn + j] -= absmode ? -fabs(F) : F;
           continue;
@@ -1052,7 +1171,7 @@ static int residual_dd(const om_mesh *m, const om_phys *ph, const double *U, con
         double psi = om_psi_limiter(ph->limiter, ph->beta, a, b);
         double uf = u[w] + (0.5 * b - 0.5 * dt * gV) * psi;
         double F = uf * v - ph->D[s] * gS;
-        if (m->axi) F *= m->Rf[c * 3 + e]; /* flux through the revolved face, over 2 pi */
+        if (m->axi) F *= m->Rf[c * m->ne + e]; /* flux through the revolved face, over 2 pi */
         r[(int64_t)s * nn + i] += absmode ? fabs(F) : F;
         r[(int64_t)s * nn + j] -= absmode ? -fabs(F) : F;
       }

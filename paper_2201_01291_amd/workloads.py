@@ -55,8 +55,8 @@ class Mesh:
 
     @property
     def nfaces(self) -> int:
-        """Cell-edges: 3 per triangle, 6 per tetrahedron."""
-        return self.ncells * (3 if self.nv == 3 else 6)
+        """Cell-edges: 3 per triangle, 4 per quadrilateral, 6 per tetrahedron."""
+        return self.ncells * {3: 3, 4: 4 if self.ndim == 2 else 6}[self.nv]
 
 
 # ---------------------------------------------------------------------------
@@ -117,6 +117,26 @@ def tri_rect_mesh(nx: int, ny: int, lx: float = 1.0, ly: float = 1.0, *,
     period = np.array([lx if perx else 0.0, ly if pery else 0.0]) if (perx or pery) else None
     return Mesh(xyz, cells, period, name=f"tri{nx}x{ny}",
                 meta=dict(nx=nx, ny=ny, lx=lx, ly=ly, jitter=jitter, seed=seed))
+
+
+def quad_rect_mesh(nx: int, ny: int, lx: float = 1.0, ly: float = 1.0, *,
+                   jitter: float = 0.0, seed: int = 0, periodic=False,
+                   origin=(0.0, 0.0)) -> Mesh:
+    """``nx`` x ``ny`` quadrilaterals on ``[0,lx]x[0,ly]``, vertices in
+    counter-clockwise order; node layout, ``periodic`` and ``jitter`` as
+    :func:`tri_rect_mesh` (the same seed moves the nodes the same way)."""
+    t = tri_rect_mesh(nx, ny, lx, ly, jitter=jitter, seed=seed, periodic=periodic, origin=origin)
+    perx, pery = (periodic, periodic) if isinstance(periodic, bool) else tuple(periodic)
+    px = nx if perx else nx + 1
+    py = ny if pery else ny + 1
+
+    def nid(i, j):
+        return (i % px) * py + (j % py)
+
+    qi, qj = np.meshgrid(np.arange(nx), np.arange(ny), indexing="ij")
+    qi, qj = qi.ravel(), qj.ravel()
+    cells = np.stack([nid(qi, qj), nid(qi + 1, qj), nid(qi + 1, qj + 1), nid(qi, qj + 1)]).astype(np.int64)
+    return Mesh(t.xyz, cells, t.period, name=f"quad{nx}x{ny}", meta=dict(t.meta))
 
 
 _KUHN_PERMS = ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0))
