@@ -150,7 +150,16 @@ typedef struct vcx_solver_s *vcx_solver;
 typedef struct vcx_server_s *vcx_server;
 
 /* Build a device mesh (Sec. "Nomenclature and notations").
- *   ndim      2 (triangles) or 3 (tetrahedra); nv must be ndim + 1
+ *   ndim      2 or 3
+ *   nv        vertices per cell: ndim + 1 (triangles, tetrahedra) or, in 2D,
+ *             4 (convex quadrilaterals, vertices in cyclic order: node
+ *             normals from eq. node_normal, S_k = -(sum of the outward
+ *             normals of the two sides through k), the four sides as the
+ *             cell-edges, dual faces from the side midpoints to the mean of
+ *             the vertices).  Quadrilateral meshes run the gas and
+ *             drift-diffusion models, with separate gradient and flux passes;
+ *             they are not batched, served or taken by the Poisson solver
+ *             (VCX_E_ARG)
  *   xyz       host [ndim][nnodes] coordinates
  *   cells     host [nv][ncells] node indices (any vertex orientation)
  *   period    host [ndim] box length of each periodic axis, 0 for an open
@@ -194,6 +203,14 @@ vcx_status vcx_mesh_create_tiled(int ndim, int64_t nnodes, const double *xyz, in
 vcx_status vcx_mesh_create_axisymmetric(int64_t nnodes, const double *xr, int64_t ncells,
                                         const int64_t *cells, double period_x, int max_tile_cells,
                                         int max_tile_nodes, void *stream, vcx_mesh *out);
+/* As vcx_mesh_create_axisymmetric with nv vertices per cell: 3 (triangles)
+ * or 4 (convex quadrilaterals in cyclic order, see vcx_mesh_create_tiled);
+ * cells host [nv][ncells].  A quadrilateral's dual piece of a side runs from
+ * the side's midpoint to the mean of the vertices and carries its mean
+ * radius; node volumes are int r dA over the exact dual regions. */
+vcx_status vcx_mesh_create_axisymmetric_nv(int64_t nnodes, const double *xr, int64_t ncells, int nv,
+                                           const int64_t *cells, double period_x, int max_tile_cells,
+                                           int max_tile_nodes, void *stream, vcx_mesh *out);
 vcx_status vcx_mesh_destroy(vcx_mesh mesh);
 
 /* Mesh counters: out[0] nnodes, [1] ncells, [2] cell-edges (faces),

@@ -32,7 +32,7 @@ HIP_FLAGS = [
 # HIP translation units: the C ABI, one kernel-table unit per model (compiled
 # in parallel), and the Poisson solve
 HIP_SOURCES = ["vcx_capi.hip", "vcx_tab_gas2.hip", "vcx_tab_gas3.hip", "vcx_tab_dd.hip",
-               "vcx_tab_ns.hip", "vcx_poisson.hip", "vcx_static.hip"]
+               "vcx_tab_ns.hip", "vcx_tab_quad.hip", "vcx_poisson.hip", "vcx_static.hip"]
 
 
 def _run(cmd, verbose):

@@ -53,6 +53,8 @@ int mesh_ndim(vcx_mesh m);
 int64_t mesh_nnodes(vcx_mesh m);
 const HostMesh* mesh_host(vcx_mesh m);        // preprocessed mesh, internal order
 bool mesh_axisymmetric(vcx_mesh m);
+// cells are simplices (not 2D quadrilaterals)
+bool mesh_simplex(vcx_mesh m);
 hipStream_t mesh_stream(vcx_mesh m);          // stream of the mesh and its solvers
 const int32_t* mesh_perm_device(vcx_mesh m);  // [nn] internal node -> caller node (device)
 int solver_failed(vcx_solver s);

@@ -30,7 +30,8 @@ static vcx_status harvest(vcx_solver s) {
   return VCX_OK;
 }
 
-static const KernelTable* pick_table(int nd, const vcx_physics& ph) {
+static const KernelTable* pick_table(int nd, int nv, const vcx_physics& ph) {
+  if (nv != nd + 1) return pick_table_quad(ph);
   if (ph.model == VCX_MODEL_GAS) return nd == 2 ? pick_table_gas2(ph) : pick_table_gas3(ph);
   if (ph.model == VCX_MODEL_NAVIER_STOKES) return pick_table_ns(nd, ph);
   return pick_table_dd(nd, ph);
@@ -106,6 +107,15 @@ extern "C" vcx_status vcx_mesh_create_axisymmetric(int64_t nnodes, const double*
                                                    int max_tile_nodes, void* stream, vcx_mesh* out) {
   const double period[2] = {period_x, 0.0};
   return create_mesh(2, nnodes, xr, ncells, 3, cells, period, max_tile_cells, max_tile_nodes, stream, true,
+                     out);
+}
+
+extern "C" vcx_status vcx_mesh_create_axisymmetric_nv(int64_t nnodes, const double* xr, int64_t ncells, int nv,
+                                                      const int64_t* cells, double period_x, int max_tile_cells,
+                                                      int max_tile_nodes, void* stream, vcx_mesh* out) {
+  if (nv != 3 && nv != 4) return fail(VCX_E_ARG, "axisymmetric cells are triangles (nv 3) or quadrilaterals (nv 4)");
+  const double period[2] = {period_x, 0.0};
+  return create_mesh(2, nnodes, xr, ncells, nv, cells, period, max_tile_cells, max_tile_nodes, stream, true,
                      out);
 }
 
@@ -273,6 +283,8 @@ static vcx_status create_mesh(int ndim, int64_t nnodes, const double* xyz, int64
       auto* bits = static_cast<unsigned long long*>(p);
       if (hipMemsetAsync(p, 0xFF, sizeof(double) * h.nn, m->stream) != hipSuccess)
         st = fail(VCX_E_HIP, "hipMemsetAsync failed");
+      else if (d.nd == 2 && h.nv == 4)
+        hipLaunchKernelGGL((k_cell_dx<2, 4>), dim3((d.nc + 255) / 256), dim3(256), 0, m->stream, d, bits);
       else if (d.nd == 2)
         hipLaunchKernelGGL(k_cell_dx<2>, dim3((d.nc + 255) / 256), dim3(256), 0, m->stream, d, bits);
       else
@@ -467,6 +479,8 @@ vcx_status vcx::check_physics(vcx_mesh mesh, const vcx_physics& ph, const double
     if (!(ph.mu_ref >= 0.0) || !(ph.T_ref > 0.0) || !(ph.Pr > 0.0))
       return fail(VCX_E_ARG, "Navier-Stokes needs mu_ref >= 0, T_ref > 0, Pr > 0");
   }
+  if (mesh->h.nv != nd + 1 && ph.model == VCX_MODEL_NAVIER_STOKES)
+    return fail(VCX_E_ARG, "quadrilateral meshes support the gas and drift-diffusion models");
   if (ph.closure < 0 || ph.closure > 2) return fail(VCX_E_ARG, "closure must be 0, 1 or 2");
   if (ph.closure == 2 && (nd != 2 || mesh->h.axi || ph.model == VCX_MODEL_NAVIER_STOKES))
     return fail(VCX_E_ARG, "the interpolated boundary closure is defined on plane 2D meshes (gas and "
@@ -490,7 +504,7 @@ vcx_status vcx::check_physics(vcx_mesh mesh, const vcx_physics& ph, const double
     for (int k = 0; k < ph.nspecies && k < VCX_MAX_SPECIES; ++k)
       if (ph.D[k] < 0.0) return fail(VCX_E_ARG, "negative diffusion coefficient");
   }
-  const KernelTable* kt = pick_table(nd, ph);
+  const KernelTable* kt = pick_table(nd, mesh->h.nv, ph);
   if (!kt) return fail(VCX_E_ARG, "unsupported species count for this model");
   *kt_out = kt;
   return VCX_OK;
@@ -927,7 +941,8 @@ vcx_status vcx::batch_set(BatchGroup* g, vcx_solver* ss, int n, const int* steps
     g->pair = nullptr;
   }
   for (int i = 0; i < n; ++i)
-    if (ss[i] && (ss[i]->mesh->h.axi || ss[i]->ph.closure == 2 || ss[i]->ph.predictor ||
+    if (ss[i] && (ss[i]->mesh->h.axi || ss[i]->mesh->h.nv != ss[i]->mesh->h.nd + 1 ||
+                  ss[i]->ph.closure == 2 || ss[i]->ph.predictor ||
                   (ss[i]->ph.model == VCX_MODEL_DRIFT_DIFFUSION && ss[i]->ph.flux == VCX_FLUX_SG)))
       return fail(VCX_E_ARG, "solvers on axisymmetric meshes, with the interpolated closure, the "
                              "predictor or the Scharfetter-Gummel flux are not batched");
@@ -1066,7 +1081,7 @@ vcx_status vcx::batch_sync(BatchGroup* g, std::vector<int>* ended) {
 
 vcx_status vcx::solver_footprint(vcx_mesh mesh, const vcx_physics* ph, size_t* bytes) {
   if (!mesh || !ph || !bytes) return fail(VCX_E_ARG, "NULL argument");
-  const KernelTable* kt = pick_table(mesh->h.nd, *ph);
+  const KernelTable* kt = pick_table(mesh->h.nd, mesh->h.nv, *ph);
   if (!kt) return fail(VCX_E_ARG, "unsupported model / species count");
   const int nd = mesh->h.nd;
   const int nvar = ph->model == VCX_MODEL_DRIFT_DIFFUSION ? ph->nspecies : 2 + nd + ph->nspecies;
@@ -1084,6 +1099,7 @@ int vcx::mesh_ndim(vcx_mesh m) { return m ? m->h.nd : 0; }
 int64_t vcx::mesh_nnodes(vcx_mesh m) { return m ? m->d.nn : 0; }
 const vcx::HostMesh* vcx::mesh_host(vcx_mesh m) { return m ? &m->h : nullptr; }
 bool vcx::mesh_axisymmetric(vcx_mesh m) { return m && m->h.axi; }
+bool vcx::mesh_simplex(vcx_mesh m) { return m && m->h.nv == m->h.nd + 1; }
 hipStream_t vcx::mesh_stream(vcx_mesh m) { return m ? m->stream : nullptr; }
 const int32_t* vcx::mesh_perm_device(vcx_mesh m) { return m ? m->d.perm : nullptr; }
 int vcx::solver_failed(vcx_solver s) { return s ? s->host_flag : 0; }
@@ -1100,6 +1116,8 @@ static vcx_status solve_batch(vcx_solver* ss, int n, const int* nsteps, const do
     if (ss[i]->host_flag) return fail(VCX_E_UNSTABLE, "batch member in a failed state");
     if (nsteps[i] < 0) return fail(VCX_E_ARG, "nsteps must be >= 0");
     if (ss[i]->mesh->h.axi) return fail(VCX_E_ARG, "solvers on axisymmetric meshes are not batched");
+    if (ss[i]->mesh->h.nv != ss[i]->mesh->h.nd + 1)
+      return fail(VCX_E_ARG, "solvers on quadrilateral meshes are not batched");
     if (ss[i]->ph.closure == 2) return fail(VCX_E_ARG, "solvers with the interpolated closure are not batched");
     if (ss[i]->ph.predictor) return fail(VCX_E_ARG, "solvers with the MUSCL-Hancock predictor are not batched");
     if (ss[i]->ph.model == VCX_MODEL_DRIFT_DIFFUSION && ss[i]->ph.flux == VCX_FLUX_SG)

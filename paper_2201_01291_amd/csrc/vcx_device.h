@@ -49,6 +49,61 @@ __device__ inline T simplex_normals(const T (&e)[ND][ND], T (&S)[ND + 1][ND]) {
   }
 }
 
+// Sides of a 2D quadrilateral (vertices in counter-clockwise cyclic order):
+// its cell-edges (its diagonals are not edges)
+struct QuadEdges {
+  static constexpr int NE = 4;
+  __device__ static constexpr int a(int e) { return e; }
+  __device__ static constexpr int b(int e) { return e == 3 ? 0 : e + 1; }
+};
+
+// Node normals of a counter-clockwise quadrilateral from its relative vertex
+// coordinates e[k-1] = X_k - X_0 (eq. node_normal: in 2D each face is a side
+// of two vertices, so S_k = -(S_f + S_g) over the two sides through k, which
+// is the vector X_{k+1} - X_{k-1} turned a quarter counter-clockwise).
+// Returns twice the area.
+template <typename T>
+__device__ inline T quad_normals(const T (&e)[3][2], T (&S)[4][2]) {
+  // P_0 = 0, P_k = e[k-1]
+  S[0][0] = -(e[0][1] - e[2][1]);
+  S[0][1] = e[0][0] - e[2][0];
+  S[1][0] = -e[1][1];
+  S[1][1] = e[1][0];
+  S[2][0] = -(e[2][1] - e[0][1]);
+  S[2][1] = e[2][0] - e[0][0];
+  S[3][0] = e[1][1];
+  S[3][1] = -e[1][0];
+  return (e[0][0] * e[1][1] - e[0][1] * e[1][0]) + (e[1][0] * e[2][1] - e[1][1] * e[2][0]);
+}
+
+// Cell shapes: the simplex of dimension ND (NV = ND + 1) and the 2D
+// quadrilateral (NV = 4).  E: its cell-edges; normals(e, S): node normals,
+// returning the measure that kvol turns into the volume; kdual: the dual-face
+// vector of cell-edge (a, b) is (S_a - S_b) kdual (1/(n_d n_v) for simplices;
+// for a quadrilateral 1/4, the segment from the side's midpoint to the mean
+// of the vertices).
+template <int ND, int NV>
+struct Shape {
+  static_assert(NV == ND + 1, "simplices");
+  using E = Edges<ND>;
+  static constexpr double kdual = 1.0 / double(ND * NV);
+  static constexpr double kvol = ND == 2 ? 0.5 : 1.0 / 6.0;
+  template <typename T>
+  __device__ static T normals(const T (&e)[ND][ND], T (&S)[NV][ND]) {
+    return simplex_normals<ND>(e, S);
+  }
+};
+template <>
+struct Shape<2, 4> {
+  using E = QuadEdges;
+  static constexpr double kdual = 0.25;
+  static constexpr double kvol = 0.5;
+  template <typename T>
+  __device__ static T normals(const T (&e)[3][2], T (&S)[4][2]) {
+    return quad_normals(e, S);
+  }
+};
+
 // Slope limiter L(a, b) (kinds as vcx.h VCX_LIM_*).
 template <typename T>
 __device__ inline T slope_limit(int kind, T beta, T a, T b) {

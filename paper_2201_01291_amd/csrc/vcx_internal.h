@@ -194,11 +194,13 @@ inline DtCoef dt_coef(const vcx_physics& ph) {
   return c;
 }
 
-template <int MODEL, int ND, int NSP, int FLUX, typename CT>
+// NV: vertices per cell, ND + 1 (simplices) or 4 (2D quadrilaterals; gas
+// and drift-diffusion, separate gradient and flux passes, not batched)
+template <int MODEL, int ND, int NSP, int FLUX, typename CT, int NV = ND + 1>
 struct Impl {
   static constexpr int NVAR = MODEL == 1 ? NSP : 2 + ND + NSP;
   static constexpr int NR = MODEL == 1 ? NVAR : NVAR + 1;
-  static constexpr int NV = ND + 1;
+  static constexpr bool SIMPLEX = NV == ND + 1;
   static constexpr int NP = MODEL == 2 ? ND + 1 + NSP : 0;   // primitives (u, T, Y)
   static constexpr int NA = MODEL == 2 ? 3 + 2 * NSP : 0;    // gamma, mu, lambda, D_k, hs_k
   static constexpr int NGF = NR + NP;                        // fields with gradients
@@ -225,7 +227,7 @@ struct Impl {
                              : (size_t)(NW + NGF * ND) * maxn;
     return dbl + sizeof(CT) * ct + pred + slot_lds_bytes(maxn) + inc_lds_bytes(NV, maxc);
   }
-  static constexpr bool FUSABLE = ND == 2 && MODEL != 2;
+  static constexpr bool FUSABLE = ND == 2 && MODEL != 2 && SIMPLEX;
   static size_t lds_fused(const DevMesh& d) {
     if constexpr (FUSABLE) {
       if (!d.has_halo) return 0;
@@ -263,7 +265,7 @@ struct Impl {
     const DevMesh& m = s->mesh->d;
     return launch(s, "gradient", [&](hipEvent_t ea, hipEvent_t eb) {
       const int lead = gc.lp && gc.first_stage ? 1 : 0;
-      hipExtLaunchKernelGGL((k_grad_tile<ND, NGF>), dim3(xcd_grid(m.ntiles) + lead), dim3(s->tile_block),
+      hipExtLaunchKernelGGL((k_grad_tile<ND, NGF, NV>), dim3(xcd_grid(m.ntiles) + lead), dim3(s->tile_block),
                          s->lds_grad, s->mesh->stream, ea, eb, 0, m, Win, s->G, s->PG, gc);
     });
   }
@@ -297,20 +299,20 @@ struct Impl {
                                                 : s->tile_block;
       if (s->ph.predictor)
         return launch(s, "flux", [&](hipEvent_t ea, hipEvent_t eb) {
-          hipExtLaunchKernelGGL((k_flux_gas<ND, NSP, FLUX, CT, false, true>), dim3(xcd_grid(m.ntiles)),
+          hipExtLaunchKernelGGL((k_flux_gas<ND, NSP, FLUX, CT, false, true, NV>), dim3(xcd_grid(m.ntiles)),
                                 dim3(fb), s->lds_flux, st, ea, eb, 0, m, Win, (const double*)s->G, s->PR, gp,
                                 f);
         });
       if constexpr (ND == 2) {
         if (m.axi)
           return launch(s, "flux", [&](hipEvent_t ea, hipEvent_t eb) {
-            hipExtLaunchKernelGGL((k_flux_gas<ND, NSP, FLUX, CT, true>), dim3(xcd_grid(m.ntiles)),
+            hipExtLaunchKernelGGL((k_flux_gas<ND, NSP, FLUX, CT, true, false, NV>), dim3(xcd_grid(m.ntiles)),
                                dim3(s->tile_block), s->lds_flux, st, ea, eb, 0, m, Win, (const double*)s->G,
                                s->PR, gp, f);
           });
       }
       return launch(s, "flux", [&](hipEvent_t ea, hipEvent_t eb) {
-        hipExtLaunchKernelGGL((k_flux_gas<ND, NSP, FLUX, CT>), dim3(xcd_grid(m.ntiles)),
+        hipExtLaunchKernelGGL((k_flux_gas<ND, NSP, FLUX, CT, false, false, NV>), dim3(xcd_grid(m.ntiles)),
                            dim3(fb), s->lds_flux, st, ea, eb, 0, m, Win, (const double*)s->G,
                            s->PR, gp, f);
       });
@@ -341,11 +343,11 @@ struct Impl {
         if (m.axi)
           return launch(s, "flux", [&](hipEvent_t ea, hipEvent_t eb) {
             if (sg)
-              hipExtLaunchKernelGGL((k_flux_dd<ND, NSP, CT, true, true>), dim3(xcd_grid(m.ntiles)),
+              hipExtLaunchKernelGGL((k_flux_dd<ND, NSP, CT, true, true, NV>), dim3(xcd_grid(m.ntiles)),
                                     dim3(s->tile_block), s->lds_flux, st, ea, eb, 0, m, Win,
                                     (const double*)s->G, s->PR, pp, f);
             else
-              hipExtLaunchKernelGGL((k_flux_dd<ND, NSP, CT, true>), dim3(xcd_grid(m.ntiles)),
+              hipExtLaunchKernelGGL((k_flux_dd<ND, NSP, CT, true, false, NV>), dim3(xcd_grid(m.ntiles)),
                                     dim3(s->tile_block), s->lds_flux, st, ea, eb, 0, m, Win,
                                     (const double*)s->G, s->PR, pp, f);
           });
@@ -354,10 +356,10 @@ struct Impl {
                                                 : s->tile_block;
       return launch(s, "flux", [&](hipEvent_t ea, hipEvent_t eb) {
         if (sg)
-          hipExtLaunchKernelGGL((k_flux_dd<ND, NSP, CT, false, true>), dim3(xcd_grid(m.ntiles)), dim3(fb),
+          hipExtLaunchKernelGGL((k_flux_dd<ND, NSP, CT, false, true, NV>), dim3(xcd_grid(m.ntiles)), dim3(fb),
                                 s->lds_flux, st, ea, eb, 0, m, Win, (const double*)s->G, s->PR, pp, f);
         else
-          hipExtLaunchKernelGGL((k_flux_dd<ND, NSP, CT>), dim3(xcd_grid(m.ntiles)), dim3(fb), s->lds_flux,
+          hipExtLaunchKernelGGL((k_flux_dd<ND, NSP, CT, false, false, NV>), dim3(xcd_grid(m.ntiles)), dim3(fb), s->lds_flux,
                                 st, ea, eb, 0, m, Win, (const double*)s->G, s->PR, pp, f);
       });
     }
@@ -390,15 +392,15 @@ struct Impl {
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)fused_bytes));
       }
     }
-    VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_grad_tile<ND, NGF>),
+    VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_grad_tile<ND, NGF, NV>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)grad_bytes));
     if constexpr (MODEL == 0) {
-      VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_gas<ND, NSP, FLUX, CT>),
+      VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_gas<ND, NSP, FLUX, CT, false, false, NV>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)flux_bytes));
-      VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_gas<ND, NSP, FLUX, CT, false, true>),
+      VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_gas<ND, NSP, FLUX, CT, false, true, NV>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)flux_bytes));
       if constexpr (ND == 2)
-        VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_gas<ND, NSP, FLUX, CT, true>),
+        VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_gas<ND, NSP, FLUX, CT, true, false, NV>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)flux_bytes));
     } else if constexpr (MODEL == 2) {
       VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_ns<ND, NSP, CT>),
@@ -407,32 +409,41 @@ struct Impl {
         VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_ns<ND, NSP, CT, true>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)flux_bytes));
     } else {
-      VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_dd<ND, NSP, CT>),
+      VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_dd<ND, NSP, CT, false, false, NV>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)flux_bytes));
-      VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_dd<ND, NSP, CT, false, true>),
+      VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_dd<ND, NSP, CT, false, true, NV>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)flux_bytes));
       if constexpr (ND == 2) {
-        VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_dd<ND, NSP, CT, true>),
+        VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_dd<ND, NSP, CT, true, false, NV>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)flux_bytes));
-        VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_dd<ND, NSP, CT, true, true>),
+        VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_dd<ND, NSP, CT, true, true, NV>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)flux_bytes));
       }
     }
-    VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_grad_tile_batch<ND, NGF>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)grad_bytes));
-    if constexpr (MODEL == 0)
-      VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_gas_batch<ND, NSP, FLUX, CT>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)flux_bytes));
-    else if constexpr (MODEL == 2)
-      VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_ns_batch<ND, NSP, CT>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)flux_bytes));
-    else
-      VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_dd_batch<ND, NSP, CT>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)flux_bytes));
+    if constexpr (SIMPLEX) {  // (quadrilaterals have no batch kernels)
+      VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_grad_tile_batch<ND, NGF>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)grad_bytes));
+      if constexpr (MODEL == 0)
+        VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_gas_batch<ND, NSP, FLUX, CT>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)flux_bytes));
+      else if constexpr (MODEL == 2)
+        VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_ns_batch<ND, NSP, CT>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)flux_bytes));
+      else
+        VCX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_flux_dd_batch<ND, NSP, CT>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)flux_bytes));
+    }
     return VCX_OK;
   }
   // one RK stage of every solve of a batch: gradient, flux, shared-node update
   static vcx_status batch_stage(const BatchRun& br, hipStream_t stream, const BatchStage& st, bool prof) {
+    if constexpr (!SIMPLEX) {
+      return vcx::fail(VCX_E_ARG, "solvers on quadrilateral meshes are not batched");
+    } else {
+      return batch_stage_simplex(br, stream, st, prof);
+    }
+  }
+  static vcx_status batch_stage_simplex(const BatchRun& br, hipStream_t stream, const BatchStage& st, bool prof) {
     vcx_solver s = br.lead;
     FinishShared fs{dt_coef(s->ph), mix_params(s->ph), s->ph.closure, br.fused ? 1 : 0};
     if constexpr (FUSABLE) {
@@ -537,6 +548,8 @@ const KernelTable* pick_table_gas2(const vcx_physics& ph);
 const KernelTable* pick_table_gas3(const vcx_physics& ph);
 const KernelTable* pick_table_dd(int nd, const vcx_physics& ph);
 const KernelTable* pick_table_ns(int nd, const vcx_physics& ph);
+// 2D quadrilateral meshes (gas and drift-diffusion)
+const KernelTable* pick_table_quad(const vcx_physics& ph);
 // validate physics against a mesh and pick its table (vcx_capi.hip)
 vcx_status check_physics(vcx_mesh mesh, const vcx_physics& ph, const double* E, const KernelTable** kt);
 // tile-edge tables of a mesh (host build and device upload, once)
@@ -545,13 +558,13 @@ vcx_status ensure_tile_edges(vcx_mesh m);
 vcx_status configure_solver(vcx_solver s, vcx_mesh mesh, const vcx_physics& ph, const KernelTable* kt);
 }  // namespace vcx
 
-template <int MODEL, int ND, int NSP>
+template <int MODEL, int ND, int NSP, int NV = ND + 1>
 inline const KernelTable* pick_flux_prec(int flux, int prec) {
-  if (MODEL != 0) return prec == VCX_PREC_MIXED ? Impl<MODEL, ND, NSP, 0, float>::table()
-                                                : Impl<MODEL, ND, NSP, 0, double>::table();
+  if (MODEL != 0) return prec == VCX_PREC_MIXED ? Impl<MODEL, ND, NSP, 0, float, NV>::table()
+                                                : Impl<MODEL, ND, NSP, 0, double, NV>::table();
   if (flux == VCX_FLUX_HLLC)
-    return prec == VCX_PREC_MIXED ? Impl<MODEL, ND, NSP, 0, float>::table()
-                                  : Impl<MODEL, ND, NSP, 0, double>::table();
-  return prec == VCX_PREC_MIXED ? Impl<MODEL, ND, NSP, 1, float>::table()
-                                : Impl<MODEL, ND, NSP, 1, double>::table();
+    return prec == VCX_PREC_MIXED ? Impl<MODEL, ND, NSP, 0, float, NV>::table()
+                                  : Impl<MODEL, ND, NSP, 0, double, NV>::table();
+  return prec == VCX_PREC_MIXED ? Impl<MODEL, ND, NSP, 1, float, NV>::table()
+                                : Impl<MODEL, ND, NSP, 1, double, NV>::table();
 }

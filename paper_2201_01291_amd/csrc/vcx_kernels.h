@@ -179,10 +179,10 @@ __device__ inline double block_min(double v) {
   return b;
 }
 
-template <int ND>
-__device__ inline void cell_rel_coords(const DevMesh& m, const double* sX, int maxn, const int (&l)[ND + 1],
-                                       uint32_t code, double (&e)[ND][ND]) {
-  for (int k = 1; k <= ND; ++k)
+template <int ND, int NV = ND + 1>
+__device__ inline void cell_rel_coords(const DevMesh& m, const double* sX, int maxn, const int (&l)[NV],
+                                       uint32_t code, double (&e)[NV - 1][ND]) {
+  for (int k = 1; k < NV; ++k)
     for (int d = 0; d < ND; ++d) {
       const uint32_t b = (code >> (2 * ((k - 1) * ND + d))) & 3u;
       const double s = b == 1u ? m.period[d] : (b == 2u ? -m.period[d] : 0.0);
@@ -578,11 +578,11 @@ __host__ __device__ constexpr int grad_group(int nr) {
   return (nr + (nr + 7) / 8 - 1) / ((nr + 7) / 8);
 }
 
-template <int ND, int NR>
+template <int ND, int NR, int NV = ND + 1>
 __device__ inline void grad_tile_body(const DevMesh& m, const double* __restrict__ W,
                                       double* __restrict__ G, double* __restrict__ PG,
                                       const GradCtl& ctl, int t, double* lds) {
-  constexpr int NV = ND + 1, NC = NR * ND, FG = grad_group(NR);
+  constexpr int NC = NR * ND, FG = grad_group(NR);
   // later stages of a step that does no work (set by an earlier launch)
   if (ctl.lp && !ctl.first_stage && ctl.lp->s[ctl.par].active == 0) return;
   TilePre<NV> tp;
@@ -622,9 +622,9 @@ __device__ inline void grad_tile_body(const DevMesh& m, const double* __restrict
       int l[NV];
       uint32_t sh;
       cell_topo<NV>(m, tp, lc, l, sh);
-      double e[ND][ND], S[NV][ND];
-      cell_rel_coords<ND>(m, sX, maxn, l, sh, e);
-      simplex_normals<ND>(e, S);
+      double e[NV - 1][ND], S[NV][ND];
+      cell_rel_coords<ND, NV>(m, sX, maxn, l, sh, e);
+      Shape<ND, NV>::normals(e, S);
 #pragma unroll
       for (int vv = 0; vv < FG; ++vv) {
         if (v0 + vv >= NR) break;
@@ -675,7 +675,7 @@ __device__ inline void grad_tile_body(const DevMesh& m, const double* __restrict
   }
 }
 
-template <int ND, int NR>
+template <int ND, int NR, int NV = ND + 1>
 __global__ void __launch_bounds__(256) k_grad_tile(DevMesh m, const double* __restrict__ W,
                                                    double* __restrict__ G, double* __restrict__ PG,
                                                    GradCtl ctl) {
@@ -689,7 +689,7 @@ __global__ void __launch_bounds__(256) k_grad_tile(DevMesh m, const double* __re
   }
   const int t = xcd_tile_of((int)blockIdx.x - lead, m.ntiles);
   if (t >= m.ntiles) return;
-  grad_tile_body<ND, NR>(m, W, G, PG, ctl, t, lds);
+  grad_tile_body<ND, NR, NV>(m, W, G, PG, ctl, t, lds);
 }
 
 // gradient of a shared node g from its per-tile partial sums, taken over the
@@ -697,7 +697,7 @@ __global__ void __launch_bounds__(256) k_grad_tile(DevMesh m, const double* __re
 template <int NC, int ND>
 __device__ inline void shared_gradient(const DevMesh& m, const double* __restrict__ PG, int g,
                                        int2 run, double (&out)[NC]) {
-  const double coef = -m.inv_vol[g] / double(ND * (ND + 1));
+  const double coef = -m.inv_vol[g] / double(ND * m.nv);
 #pragma unroll
   for (int j = 0; j < NC; ++j) out[j] = 0.0;
   for (int p = run.x; p < run.y; ++p) {
@@ -731,7 +731,7 @@ __device__ inline void stage_gradient(const DevMesh& m, const double* __restrict
     return;
   }
   const int g = ~sv;
-  const double coef = -m.inv_vol[g] / double(ND * (ND + 1));
+  const double coef = -m.inv_vol[g] / double(ND * m.nv);
   constexpr int JC = NC <= 24 ? NC : 12;
   for (int j0 = 0; j0 < NC; j0 += JC) {
     double acc[JC];
@@ -916,7 +916,7 @@ __device__ inline double ns_hoop_stress(const DevMesh& m, const Finish& f, int i
       a += f.PG[(size_t)p * NC + CR];
       b += f.PG[(size_t)p * NC + CX];
     }
-    const double coef = -m.inv_vol[i] / double(ND * (ND + 1));
+    const double coef = -m.inv_vol[i] / double(ND * m.nv);
     durdr = coef * a;
     duxdx = coef * b;
   }
@@ -1052,7 +1052,8 @@ template <int ND, int NSP, int FLUX, typename CT, int NV, bool AXI = false, bool
 __device__ inline void gas_cell_fluxes(const DevMesh& m, const TilePre<NV>& tp, const double* sX,
                                        const CT* sW, const CT* sG, double* sR, CellLd L,
                                        const GasParams& gp, const CT* sH = nullptr) {
-  constexpr int NVAR = 2 + ND + NSP, NR = NVAR + 1, NE = Edges<ND>::NE;
+  using SH = Shape<ND, NV>;
+  constexpr int NVAR = 2 + ND + NSP, NR = NVAR + 1, NE = SH::E::NE;
   const CT gamma = CT(gp.gamma), beta = CT(gp.beta), fix = CT(gp.entropy_fix);
   // FP64 tetrahedra: two threads per cell, edges 0-2 and 3-5, each into its
   // own plane of vertex parts (sR and sR + NV*NVAR*ldc), which the node pass
@@ -1076,9 +1077,9 @@ __device__ inline void gas_cell_fluxes(const DevMesh& m, const TilePre<NV>& tp, 
       for (int k = 0; k < NV; ++k) l[k] = m.lconn[(size_t)k * m.nc + tp.c0 + lc];
       sh = m.shift[tp.c0 + lc];
     }
-    double e[ND][ND], Sd[NV][ND];
-    cell_rel_coords<ND>(m, sX, L.ldx, l, sh, e);
-    simplex_normals<ND>(e, Sd);
+    double e[NV - 1][ND], Sd[NV][ND];
+    cell_rel_coords<ND, NV>(m, sX, L.ldx, l, sh, e);
+    SH::normals(e, Sd);
     double acc[NV][NVAR];
 #pragma unroll
     for (int k = 0; k < NV; ++k)
@@ -1088,13 +1089,13 @@ __device__ inline void gas_cell_fluxes(const DevMesh& m, const TilePre<NV>& tp, 
     for (int ed0 = 0; ed0 < NE; ++ed0) {
       if (NH == 2 && (ed0 / EH) != h) continue;
       const int ed = ed0;
-      const int a = Edges<ND>::a(ed), b = Edges<ND>::b(ed);
+      const int a = SH::E::a(ed), b = SH::E::b(ed);
       const int la = l[a], lb = l[b];
       CT S[ND], dx[ND];
 #pragma unroll
       for (int d = 0; d < ND; ++d) {
-        S[d] = CT((Sd[a][d] - Sd[b][d]) * (1.0 / double(ND * NV)));
-        dx[d] = CT((a == 0 ? 0.0 : -e[a - 1][d]) + e[b - 1][d]);
+        S[d] = CT((Sd[a][d] - Sd[b][d]) * SH::kdual);
+        dx[d] = CT((a == 0 ? 0.0 : -e[a - 1][d]) + (b == 0 ? 0.0 : e[b - 1][d]));
       }
       CT WL[NR], WR[NR];
 #pragma unroll
@@ -1125,10 +1126,12 @@ __device__ inline void gas_cell_fluxes(const DevMesh& m, const TilePre<NV>& tp, 
       double rw = 1.0;
       if constexpr (AXI) {
         static_assert(ND == 2, "axisymmetric meshes are (x, r) planes");
-        double rr[NV];
+        double rr[NV], rc = 0.0;
 #pragma unroll
         for (int k = 0; k < NV; ++k) rr[k] = sX[L.ldx + l[k]];
-        const double rc = (rr[0] + rr[1] + rr[2]) / 3.0;
+#pragma unroll
+        for (int k = 0; k < NV; ++k) rc += rr[k];
+        rc /= double(NV);
         rw = 0.5 * (0.5 * (rr[a] + rr[b]) + rc);
       }
 #pragma unroll
@@ -1220,7 +1223,8 @@ template <int ND, int NS, typename CT, int NV, bool AXI = false, bool SG = false
 __device__ inline void dd_cell_fluxes(const DevMesh& m, const TilePre<NV>& tp, const double* sX,
                                       const CT* sU, const CT* sG, const CT* sE, double* sR, CellLd L,
                                       CT dt, const DDParams& pp) {
-  constexpr int NE = Edges<ND>::NE;
+  using SH = Shape<ND, NV>;
+  constexpr int NE = SH::E::NE;
   static_assert(!AXI || ND == 2, "axisymmetric meshes are (x, r) planes");
   const CT beta = CT(pp.beta);
   // FP64 tetrahedra: two threads per cell, three edges each, into two
@@ -1243,9 +1247,9 @@ __device__ inline void dd_cell_fluxes(const DevMesh& m, const TilePre<NV>& tp, c
       for (int k = 0; k < NV; ++k) l[k] = m.lconn[(size_t)k * m.nc + tp.c0 + lc];
       sh = m.shift[tp.c0 + lc];
     }
-    double e[ND][ND], Sd[NV][ND];
-    cell_rel_coords<ND>(m, sX, L.ldx, l, sh, e);
-    simplex_normals<ND>(e, Sd);
+    double e[NV - 1][ND], Sd[NV][ND];
+    cell_rel_coords<ND, NV>(m, sX, L.ldx, l, sh, e);
+    SH::normals(e, Sd);
     double acc[NV][NS];
 #pragma unroll
     for (int k = 0; k < NV; ++k)
@@ -1254,13 +1258,13 @@ __device__ inline void dd_cell_fluxes(const DevMesh& m, const TilePre<NV>& tp, c
 #pragma unroll
     for (int ed = 0; ed < NE; ++ed) {
       if (NH == 2 && ed / EH != h) continue;
-      const int a = Edges<ND>::a(ed), b = Edges<ND>::b(ed);
+      const int a = SH::E::a(ed), b = SH::E::b(ed);
       const int la = l[a], lb = l[b];
       CT S[ND], dx[ND], Ebar[ND];
 #pragma unroll
       for (int d = 0; d < ND; ++d) {
-        S[d] = CT((Sd[a][d] - Sd[b][d]) * (1.0 / double(ND * NV)));
-        dx[d] = CT((a == 0 ? 0.0 : -e[a - 1][d]) + e[b - 1][d]);
+        S[d] = CT((Sd[a][d] - Sd[b][d]) * SH::kdual);
+        dx[d] = CT((a == 0 ? 0.0 : -e[a - 1][d]) + (b == 0 ? 0.0 : e[b - 1][d]));
         Ebar[d] = CT(0.5) * (sE[d * L.ldg + la] + sE[d * L.ldg + lb]);
       }
       // axisymmetric (x, r): the dual face piece of the edge, from its
@@ -1268,10 +1272,12 @@ __device__ inline void dd_cell_fluxes(const DevMesh& m, const TilePre<NV>& tp, c
       // Pappus-Guldinus theorem; the radius is never periodic)
       double rw = 1.0;
       if constexpr (AXI) {
-        double r[NV];
+        double r[NV], rc = 0.0;
 #pragma unroll
         for (int k = 0; k < NV; ++k) r[k] = sX[L.ldx + l[k]];
-        const double rc = (r[0] + r[1] + r[2]) / 3.0;
+#pragma unroll
+        for (int k = 0; k < NV; ++k) rc += r[k];
+        rc /= double(NV);
         rw = 0.5 * (0.5 * (r[a] + r[b]) + rc);
       }
 #pragma unroll
@@ -1362,12 +1368,12 @@ __device__ inline double tile_node_pass(const DevMesh& m, const Finish& f, doubl
   return cand;
 }
 
-template <int ND, int NSP, int FLUX, typename CT, bool AXI = false, bool HANCOCK = false>
+template <int ND, int NSP, int FLUX, typename CT, bool AXI = false, bool HANCOCK = false, int NV = ND + 1>
 __device__ inline void flux_gas_body(DevMesh m, const double* __restrict__ W,
                                                   const double* __restrict__ G,
                                                   double* __restrict__ PR, GasParams gp, Finish f,
                                                   int t, double* lds) {
-  constexpr int NV = ND + 1, NVAR = 2 + ND + NSP, NR = NVAR + 1;
+  constexpr int NVAR = 2 + ND + NSP, NR = NVAR + 1;
   if (step_inactive(f.sc)) return;
   TilePre<NV> tp;
   tile_prefetch<NV>(m, t, tp);
@@ -1416,26 +1422,25 @@ __device__ inline void flux_gas_body(DevMesh m, const double* __restrict__ W,
   }
 }
 
-template <int ND, int NSP, int FLUX, typename CT, bool AXI = false, bool HANCOCK = false>
+template <int ND, int NSP, int FLUX, typename CT, bool AXI = false, bool HANCOCK = false, int NV = ND + 1>
 __global__ void VCX_FLUX_BOUNDS k_flux_gas(DevMesh m, const double* __restrict__ W,
                                                   const double* __restrict__ G,
                                                   double* __restrict__ PR, GasParams gp, Finish f) {
   extern __shared__ double lds[];
   const int t = xcd_tile(m.ntiles);
   if (t >= m.ntiles) return;
-  flux_gas_body<ND, NSP, FLUX, CT, AXI, HANCOCK>(m, W, G, PR, gp, f, t, lds);
+  flux_gas_body<ND, NSP, FLUX, CT, AXI, HANCOCK, NV>(m, W, G, PR, gp, f, t, lds);
 }
 
 // ---------------------------------------------------------------------------
 // drift-diffusion flux pass
 // ---------------------------------------------------------------------------
 
-template <int ND, int NS, typename CT, bool AXI = false, bool SG = false>
+template <int ND, int NS, typename CT, bool AXI = false, bool SG = false, int NV = ND + 1>
 __device__ inline void flux_dd_body(DevMesh m, const double* __restrict__ U,
                                                  const double* __restrict__ G,
                                                  double* __restrict__ PR, DDParams pp, Finish f,
                                                  int t, double* lds) {
-  constexpr int NV = ND + 1;
   if (step_inactive(f.sc)) return;
   TilePre<NV> tp;
   tile_prefetch<NV>(m, t, tp);
@@ -1484,14 +1489,14 @@ __device__ inline void flux_dd_body(DevMesh m, const double* __restrict__ U,
   }
 }
 
-template <int ND, int NS, typename CT, bool AXI = false, bool SG = false>
+template <int ND, int NS, typename CT, bool AXI = false, bool SG = false, int NV = ND + 1>
 __global__ void VCX_FLUX_BOUNDS k_flux_dd(DevMesh m, const double* __restrict__ U,
                                                  const double* __restrict__ G,
                                                  double* __restrict__ PR, DDParams pp, Finish f) {
   extern __shared__ double lds[];
   const int t = xcd_tile(m.ntiles);
   if (t >= m.ntiles) return;
-  flux_dd_body<ND, NS, CT, AXI, SG>(m, U, G, PR, pp, f, t, lds);
+  flux_dd_body<ND, NS, CT, AXI, SG, NV>(m, U, G, PR, pp, f, t, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1824,7 +1829,7 @@ __device__ inline void stage_gradient_part(const DevMesh& m, const double* __res
     return;
   }
   const int g = ~sv;
-  const double coef = -m.inv_vol[g] / double(ND * (ND + 1));
+  const double coef = -m.inv_vol[g] / double(ND * m.nv);
   constexpr int JC = NCS <= 24 ? NCS : 12;
   for (int j0 = 0; j0 < NCS; j0 += JC) {
     double acc[JC];
@@ -2280,25 +2285,24 @@ static __global__ void k_commit(DevLoop* lp, int par) {
 }
 
 // smallest inscribed diameter 2 nd V / sum_k |S_k| over the cells of each node
-template <int ND>
+template <int ND, int NV = ND + 1>
 __global__ void __launch_bounds__(256) k_cell_dx(DevMesh m, unsigned long long* __restrict__ dxbits) {
-  constexpr int NV = ND + 1;
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= m.nc) return;
   int v[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) v[k] = m.cell[(size_t)k * m.nc + c];
   const uint32_t code = m.shift[c];
-  double e[ND][ND], S[NV][ND];
+  double e[NV - 1][ND], S[NV][ND];
 #pragma unroll
-  for (int k = 1; k <= ND; ++k)
+  for (int k = 1; k < NV; ++k)
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
       const uint32_t b = (code >> (2 * ((k - 1) * ND + d))) & 3u;
       const double s = b == 1u ? m.period[d] : (b == 2u ? -m.period[d] : 0.0);
       e[k - 1][d] = m.x[(size_t)d * m.nn + v[k]] + s - m.x[(size_t)d * m.nn + v[0]];
     }
-  const double det = simplex_normals<ND>(e, S);
+  const double det = Shape<ND, NV>::normals(e, S);
   double area = 0.0;
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
@@ -2307,7 +2311,7 @@ __global__ void __launch_bounds__(256) k_cell_dx(DevMesh m, unsigned long long* 
     for (int d = 0; d < ND; ++d) s2 += S[k][d] * S[k][d];
     area += sqrt(s2);
   }
-  const double dx = 2.0 * ND * (det / (ND == 2 ? 2.0 : 6.0)) / area;
+  const double dx = 2.0 * ND * (NV == ND + 1 ? det / (ND == 2 ? 2.0 : 6.0) : det * Shape<ND, NV>::kvol) / area;
   const unsigned long long bits = (unsigned long long)__double_as_longlong(dx);
 #pragma unroll
   for (int k = 0; k < NV; ++k) atomicMin(&dxbits[v[k]], bits);

@@ -89,13 +89,15 @@ std::string preprocess_mesh(int nd, int64_t nn, const double* xyz, int64_t nc, i
                             HostMesh& m, int* code, bool axisymmetric) {
   *code = -1;
   if (nd != 2 && nd != 3) return "ndim must be 2 or 3";
-  if (nv != nd + 1) return "only simplices are supported: nv must be ndim + 1";
+  if (nv != nd + 1 && !(nd == 2 && nv == 4))
+    return "cells must be simplices (nv = ndim + 1) or, in 2D, quadrilaterals (nv = 4)";
   if (nn <= 0 || nc <= 0 || !xyz || !cells) return "empty mesh or NULL array";
   if (nn >= (int64_t)INT32_MAX || nc * nv >= (int64_t)INT32_MAX) return "mesh too large for 32-bit indices";
   if (lim.max_cells < 1 || lim.max_cells > 1024 || lim.max_nodes < nv || lim.max_nodes > 4096)
     return "tile limits out of range";
   m = HostMesh();
-  m.nd = nd; m.nv = nv; m.ne = nd == 2 ? 3 : 6; m.nn = nn; m.nc = nc; m.lim = lim;
+  const bool quad = nv == 4 && nd == 2;
+  m.nd = nd; m.nv = nv; m.ne = quad ? 4 : (nd == 2 ? 3 : 6); m.nn = nn; m.nc = nc; m.lim = lim;
   for (int d = 0; d < nd; ++d) {
     double L = period ? period[d] : 0.0;
     if (!(L >= 0.0) || !std::isfinite(L)) return "period entries must be finite and >= 0";
@@ -138,6 +140,34 @@ std::string preprocess_mesh(int nd, int64_t nn, const double* xyz, int64_t nc, i
       }
     double e[3][3];
     relative_coords(m, xyz, v, s, e);
+    if (quad) {
+      // twice the signed area (shoelace from vertex 0); a clockwise cell is
+      // reversed (vertices 1 and 3 swap, with their periodic images)
+      auto area2 = [](const double (&q)[3][3]) {
+        return (q[0][0] * q[1][1] - q[0][1] * q[1][0]) + (q[1][0] * q[2][1] - q[1][1] * q[2][0]);
+      };
+      double a2 = area2(e);
+      if (a2 < 0.0) {
+        std::swap(v[1], v[3]);
+        const uint32_t f1 = s & 0xFu, f3 = (s >> 8) & 0xFu;
+        s = (s & ~0xF0Fu) | f3 | (f1 << 8);
+        relative_coords(m, xyz, v, s, e);
+        a2 = area2(e);
+      }
+      // convex: every corner turns counter-clockwise
+      const double P[4][2] = {{0.0, 0.0}, {e[0][0], e[0][1]}, {e[1][0], e[1][1]}, {e[2][0], e[2][1]}};
+      for (int k = 0; k < 4; ++k) {
+        const double* p0 = P[k];
+        const double* p1 = P[(k + 1) % 4];
+        const double* p2 = P[(k + 2) % 4];
+        const double cr = (p1[0] - p0[0]) * (p2[1] - p1[1]) - (p1[1] - p0[1]) * (p2[0] - p1[0]);
+        if (!(cr > 0.0)) return "non-convex or degenerate quadrilateral";
+      }
+      sh[c] = s;
+      vol[c] = 0.5 * a2;
+      vmax = std::max(vmax, vol[c]);
+      continue;
+    }
     double det = signed_measure(nd, e);
     if (det < 0.0) {
       // reorient: swap vertices 1 and 2 together with their periodic images
@@ -223,7 +253,43 @@ std::string preprocess_mesh(int nd, int64_t nn, const double* xyz, int64_t nc, i
   m.vol_nodes = 0.0;
   for (int64_t i = 0; i < nn; ++i) m.vol_nodes += m.vnode[i];
   m.vupd = m.vnode;
-  if (m.axi) {
+  if (m.axi && quad) {
+    // int r dA over node k's dual region in each quadrilateral: (X_k, midpoint
+    // of side k, centre C = mean of the vertices, midpoint of side k-1), as the
+    // triangles (X_k, M_k, C) and (X_k, C, M_p), each of first moment area
+    // times mean vertex radius; r is not periodic, x differences come from the
+    // unwrapped relative coordinates
+    std::fill(m.vupd.begin(), m.vupd.end(), 0.0);
+    for (int64_t c = 0; c < nc; ++c) {
+      int64_t v[4];
+      for (int k = 0; k < 4; ++k) v[k] = m.cell[(size_t)k * nc + c];
+      double e[3][3];
+      for (int k = 1; k < 4; ++k)
+        for (int d = 0; d < 2; ++d)
+          e[k - 1][d] = m.x[(size_t)d * nn + v[k]] + shift_of(m.shift[c], k, d, nd) * m.period[d] -
+                        m.x[(size_t)d * nn + v[0]];
+      const double P[4][2] = {{0.0, m.x[(size_t)nn + v[0]]},
+                              {e[0][0], m.x[(size_t)nn + v[1]]},
+                              {e[1][0], m.x[(size_t)nn + v[2]]},
+                              {e[2][0], m.x[(size_t)nn + v[3]]}};
+      const double C[2] = {0.25 * (P[0][0] + P[1][0] + P[2][0] + P[3][0]),
+                           0.25 * (P[0][1] + P[1][1] + P[2][1] + P[3][1])};
+      auto tri = [](const double* a, const double* b, const double* q) {
+        const double ar = 0.5 * std::fabs((b[0] - a[0]) * (q[1] - a[1]) - (b[1] - a[1]) * (q[0] - a[0]));
+        return ar * (a[1] + b[1] + q[1]) / 3.0;
+      };
+      for (int k = 0; k < 4; ++k) {
+        const double* X = P[k];
+        const double* Xn = P[(k + 1) % 4];
+        const double* Xp = P[(k + 3) % 4];
+        const double Mk[2] = {0.5 * (X[0] + Xn[0]), 0.5 * (X[1] + Xn[1])};
+        const double Mp[2] = {0.5 * (X[0] + Xp[0]), 0.5 * (X[1] + Xp[1])};
+        m.vupd[v[k]] += tri(X, Mk, C) + tri(X, C, Mp);
+      }
+    }
+    for (int64_t i = 0; i < nn; ++i)
+      if (!(m.vupd[i] > 0.0)) return "axisymmetric node with a zero revolved volume";
+  } else if (m.axi) {
     // int r dA over node k's dual region in each triangle: the quadrilateral
     // (X_k, midpoint k-l, centroid, midpoint k-m), two triangles of area A/6
     // whose first moments are area times the mean vertex radius (second
@@ -249,9 +315,16 @@ std::string preprocess_mesh(int nd, int64_t nn, const double* xyz, int64_t nc, i
     for (int k = 0; k < nv; ++k) {
       Face& f = faces[(size_t)c * nv + k];
       f.n = {-1, -1, -1};
-      int q = 0;
-      for (int v = 0; v < nv; ++v)
-        if (v != k) f.n[q++] = m.cell[(size_t)v * nc + c];
+      if (quad) {
+        // face k of a quadrilateral: its side k -> k+1
+        f.n[0] = m.cell[(size_t)k * nc + c];
+        f.n[1] = m.cell[(size_t)((k + 1) % 4) * nc + c];
+      } else {
+        // face k of a simplex: the one opposite vertex k
+        int q = 0;
+        for (int v = 0; v < nv; ++v)
+          if (v != k) f.n[q++] = m.cell[(size_t)v * nc + c];
+      }
       std::sort(f.n.begin(), f.n.begin() + nd);
       f.c = (int32_t)c;
       f.k = (int8_t)k;
@@ -276,7 +349,17 @@ std::string preprocess_mesh(int nd, int64_t nn, const double* xyz, int64_t nc, i
         for (int d = 0; d < nd; ++d)
           e[k - 1][d] = m.x[(size_t)d * nn + v[k]] + shift_of(m.shift[c], k, d, nd) * m.period[d] -
                         m.x[(size_t)d * nn + v[0]];
-      node_normals(nd, e, S);
+      if (quad) {
+        // outward normal of side k -> k+1 (counter-clockwise cell), in the
+        // slot the simplex path reads
+        const int k = faces[a].k, l = (k + 1) % 4;
+        const double xk = k == 0 ? 0.0 : e[k - 1][0], yk = k == 0 ? 0.0 : e[k - 1][1];
+        const double xl = l == 0 ? 0.0 : e[l - 1][0], yl = l == 0 ? 0.0 : e[l - 1][1];
+        S[k][0] = yl - yk;
+        S[k][1] = -(xl - xk);
+      } else {
+        node_normals(nd, e, S);
+      }
       for (int q = 0; q < nd; ++q) {
         int32_t i = faces[a].n[q];
         isb[i] = 1;
@@ -388,7 +471,7 @@ std::string preprocess_mesh(int nd, int64_t nn, const double* xyz, int64_t nc, i
     if (m.node_slot[g + 1] - m.node_slot[g] > 1) m.slot_node[s] = ~g;
   }
 
-  if (nd == 2) build_halos(m);
+  if (nd == 2 && !quad) build_halos(m);
   *code = 0;
   return "";
 }

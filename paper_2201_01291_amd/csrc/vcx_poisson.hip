@@ -736,6 +736,7 @@ extern "C" vcx_status vcx_poisson_create(vcx_mesh mesh, const int32_t* dirichlet
   const HostMesh& h = *vcx::mesh_host(mesh);
   const int nd = h.nd, nv = h.nv;
   const int64_t n = h.nn, nc = h.nc;
+  if (nv != nd + 1) return err(VCX_E_ARG, "the Poisson operator is assembled on simplex meshes");
   if (n >= (int64_t)1 << 31) return err(VCX_E_ARG, "mesh too large for 32-bit rows");
   // Dirichlet flags in the internal order
   std::vector<char> dir((size_t)n, 0);

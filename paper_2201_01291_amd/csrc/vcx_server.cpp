@@ -465,6 +465,7 @@ extern "C" vcx_status vcx_server_submit(vcx_server sv, vcx_mesh mesh, const vcx_
   if (phys->model == VCX_MODEL_DRIFT_DIFFUSION && !E)
     return set_err(VCX_E_ARG, "drift-diffusion needs the electric field E");
   if (vcx::mesh_axisymmetric(mesh)) return set_err(VCX_E_ARG, "axisymmetric meshes are not served (not batched)");
+  if (!vcx::mesh_simplex(mesh)) return set_err(VCX_E_ARG, "quadrilateral meshes are not served (not batched)");
   if (phys->closure == 2 || phys->predictor ||
       (phys->model == VCX_MODEL_DRIFT_DIFFUSION && phys->flux == VCX_FLUX_SG))
     return set_err(VCX_E_ARG, "the interpolated closure, the predictor and the Scharfetter-Gummel flux are "

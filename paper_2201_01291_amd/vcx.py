@@ -37,7 +37,7 @@ EXPORTS = (
     "vcx_conservation_sums", "vcx_profile_enable", "vcx_profile_query", "vcx_last_error",
     "vcx_solver_set_field", "vcx_poisson_create", "vcx_poisson_destroy", "vcx_poisson_solve",
     "vcx_poisson_field", "vcx_poisson_field_add", "vcx_poisson_info", "vcx_solver_charge",
-    "vcx_mesh_create_axisymmetric", "vcx_residual_noalloc",
+    "vcx_mesh_create_axisymmetric", "vcx_mesh_create_axisymmetric_nv", "vcx_residual_noalloc",
     "vcx_noalloc_scratch_bytes",
 )
 
@@ -134,6 +134,8 @@ def lib():
         L.vcx_solver_set_field.argtypes = [vp, vp, C.c_int]
         L.vcx_mesh_create_axisymmetric.argtypes = [C.c_int64, dp, C.c_int64, i64p, C.c_double, C.c_int,
                                                    C.c_int, vp, C.POINTER(vp)]
+        L.vcx_mesh_create_axisymmetric_nv.argtypes = [C.c_int64, dp, C.c_int64, C.c_int, i64p, C.c_double,
+                                                      C.c_int, C.c_int, vp, C.POINTER(vp)]
         L.vcx_poisson_create.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(vp)]
         L.vcx_poisson_destroy.argtypes = [vp]
         L.vcx_poisson_solve.argtypes = [vp, vp, vp, vp, vp, C.c_int, C.c_double, C.c_int,
@@ -225,10 +227,10 @@ class Mesh:
         cp = cells.ctypes.data_as(C.POINTER(C.c_int64))
         if axisymmetric:
             px = float(per[0]) if per is not None else 0.0
-            _check(L.vcx_mesh_create_axisymmetric(mesh.nnodes, _dptr(xyz), mesh.ncells, cp, px,
-                                                  int(tile_cells), int(tile_nodes),
-                                                  C.c_void_p(self.stream), C.byref(h)),
-                   "vcx_mesh_create_axisymmetric")
+            _check(L.vcx_mesh_create_axisymmetric_nv(mesh.nnodes, _dptr(xyz), mesh.ncells, mesh.nv, cp, px,
+                                                     int(tile_cells), int(tile_nodes),
+                                                     C.c_void_p(self.stream), C.byref(h)),
+                   "vcx_mesh_create_axisymmetric_nv")
         else:
             _check(L.vcx_mesh_create_tiled(mesh.ndim, mesh.nnodes, _dptr(xyz), mesh.ncells, mesh.nv, cp,
                                            _dptr(per) if per is not None else None, int(tile_cells),

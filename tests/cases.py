@@ -218,8 +218,35 @@ def make_case(name: str) -> Case:
         n, E = wl.dd_fields(m, sigma=3e-4, bump_sigma=2e-4, bump_amp=50.0, nspecies=1, seed=13)
         return Case(name, m, n, E, dict(model="dd", flux="sg", limiter="minmod", rk=2, nspecies=1,
                                         z=[-1.0], mu=[0.04], D=[0.1]))
+    # -- 2D quadrilateral meshes -----------------------------------------
+    if name == "quad-dd-llw":
+        m = wl.quad_rect_mesh(36, 22, 2e-3, 1.2e-3, jitter=0.2, seed=31, periodic=True)
+        n, E = wl.dd_fields(m, sigma=2e-4, seed=14)
+        return Case(name, m, n, E, dict(DD2, limiter="vanleer", rk=2), tiles=(96, 120))
+    if name == "quad-dd-sg-open":
+        m = wl.quad_rect_mesh(23, 17, 0.02, 0.015, jitter=0.2, seed=32)
+        n, E = wl.dd_fields(m, sigma=3e-3, seed=15)
+        return Case(name, m, n, E, dict(DD2, flux="sg"))
+    if name == "quad-euler-hllc":
+        m = wl.quad_rect_mesh(24, 18, jitter=0.2, seed=33, periodic=True)
+        U = wl.euler_blob_state(m, nblobs=4, amp=0.3, sigma=0.15, mach=0.8, seed=11)
+        return Case(name, m, U, None, dict(model="gas", flux="hllc", limiter="vanleer", rk=2))
+    if name == "quad-euler-roe-sp2-closure2":
+        m = wl.quad_rect_mesh(18, 14, jitter=0.2, seed=34)
+        U = wl.euler_blob_state(m, nblobs=3, amp=0.4, sigma=0.2, mach=1.5, seed=12, nspecies=2)
+        return Case(name, m, U, None, dict(model="gas", flux="roe", limiter="minmod", rk=3, nspecies=2,
+                                           closure=2))
+    if name == "quad-explosion-hancock":
+        m = wl.quad_rect_mesh(40, 40, 2.0, 2.0)
+        U = wl.explosion_state(m)
+        return Case(name, m, U, None, dict(model="gas", flux="hllc", limiter="sweby", beta=1.5, rk=1,
+                                           predictor=1))
     raise KeyError(name)
 
+
+# Cases on 2D quadrilateral meshes (gas and drift-diffusion)
+QUAD_CASES = ["quad-dd-llw", "quad-dd-sg-open", "quad-euler-hllc", "quad-euler-roe-sp2-closure2",
+              "quad-explosion-hancock"]
 
 # Drift-diffusion cases with the Scharfetter-Gummel flux
 SG_CASES = ["dd2d-sg", "dd2d-open-sg", "dd3d-sg"]
@@ -245,7 +272,8 @@ BRANCH_CASES = {
 CASE_NAMES = ["dd2d-streamer", "dd2d-diel", "dd2d-open-vanleer", "dd2d-open-closure2",
               "euler2d-open-closure2", "dd3d-sweby", "sod-hllc", "euler2d-roe-sp2",
               "euler3d-roe", "euler3d-hllc-open-sp2", "euler3d-hllc-sp9", "ns3d-sp9",
-              "ns2d-sp2-open", "ns2d-sp2-bigtile", *BRANCH_CASES, *HANCOCK_CASES, *SG_CASES]
+              "ns2d-sp2-open", "ns2d-sp2-bigtile", *BRANCH_CASES, *HANCOCK_CASES, *SG_CASES,
+              *QUAD_CASES]
 
 
 def reconstructed(case: Case) -> np.ndarray:
