@@ -173,7 +173,8 @@ class Workload:
             # writes W
             self.bytes_flux = {p: N * 8 * (nr + nr * nd + nd + nv + 2 + nr) + M * (4 * 2 + 4) for p in (0, 1)}
             self.flops_face_est = 400
-            self.flux_kernel = {0: "k_flux_gas<3,0,1,double,false>", 1: "k_flux_gas<3,0,1,float,false>"}
+            self.flux_kernel = {0: "k_flux_gas<3,0,1,double,false,false,4>",
+                                1: "k_flux_gas<3,0,1,float,false,false,4>"}
             self.record = "euler3d_2m"
         elif name == "ns3d":
             n = scale or 110
@@ -202,7 +203,7 @@ class Workload:
             self.bytes_flux = {p: N * 8 * (rows_read[p] + ng + 3 + 14 + 2 + nrow) + M * (4 * 2 + 4)
                                for p in (0, 1)}
             self.flops_face_est = 900
-            self.flux_kernel = {0: "k_flux_ns<3,9,double>", 1: "k_flux_ns<3,9,float>"}
+            self.flux_kernel = {0: "k_flux_ns<3,9,double,false>", 1: "k_flux_ns<3,9,float,false>"}
             self.record = "ns3d_8m"
         else:
             raise ValueError(name)
