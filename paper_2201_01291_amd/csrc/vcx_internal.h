@@ -273,8 +273,8 @@ struct Impl {
     const DevMesh& m = s->mesh->d;
     if (m.nshared == 0) return VCX_OK;
     return launch(s, "gradient_shared", [&](hipEvent_t ea, hipEvent_t eb) {
-      hipExtLaunchKernelGGL((k_grad_shared<ND, NGF>), dim3((m.nshared + kNodeBlock - 1) / kNodeBlock),
-                         dim3(kNodeBlock), 0, s->mesh->stream, ea, eb, 0, m, (const double*)s->PG, s->G);
+      hipExtLaunchKernelGGL((k_grad_shared<ND, NGF>), dim3((m.nshared + kGradSharedNodes - 1) / kGradSharedNodes),
+                            dim3(256), 0, s->mesh->stream, ea, eb, 0, m, (const double*)s->PG, s->G);
     });
   }
   static vcx_status aux(vcx_solver s, double* W) {
@@ -318,16 +318,21 @@ struct Impl {
       });
     } else if constexpr (MODEL == 2) {
       GasParams gp{s->ph.gamma, s->ph.beta, s->ph.entropy_fix, s->ph.limiter};
+      // complete G on the shared nodes once, so that every tile stages its
+      // slots' gradient rows from G instead of summing the partials per slot
+      VCX_TRY(grad_complete(s));
+      Finish fg = f;
+      fg.gfull = 1;
       if constexpr (ND == 2) {
         if (m.axi)
           return launch(s, "flux", [&](hipEvent_t ea, hipEvent_t eb) {
             hipExtLaunchKernelGGL((k_flux_ns<ND, NSP, CT, true>), dim3(xcd_grid(m.ntiles)), dim3(s->flux_block),
-                                  s->lds_flux, st, ea, eb, 0, m, Win, (const double*)s->G, s->PR, gp, f);
+                                  s->lds_flux, st, ea, eb, 0, m, Win, (const double*)s->G, s->PR, gp, fg);
           });
       }
       return launch(s, "flux", [&](hipEvent_t ea, hipEvent_t eb) {
         hipExtLaunchKernelGGL((k_flux_ns<ND, NSP, CT>), dim3(xcd_grid(m.ntiles)), dim3(s->flux_block),
-                           s->lds_flux, st, ea, eb, 0, m, Win, (const double*)s->G, s->PR, gp, f);
+                           s->lds_flux, st, ea, eb, 0, m, Win, (const double*)s->G, s->PR, gp, fg);
       });
     } else {
       DDParams pp{};

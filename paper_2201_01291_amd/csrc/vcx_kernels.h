@@ -766,17 +766,46 @@ __device__ inline void stage_gradient(const DevMesh& m, const double* __restrict
 
 // complete G on the shared nodes (gradient output only; the time loop reads
 // the partials directly)
+// A block takes kGradSharedNodes shared nodes: its threads walk the (node,
+// component) pairs component-fastest, so the reads of a partial row are
+// contiguous, sum each component over the node's partials in run order
+// (the order of shared_gradient), and the block then writes G node-fastest
+// from LDS.
+constexpr int kGradSharedNodes = 32;
 template <int ND, int NR>
 __global__ void __launch_bounds__(256) k_grad_shared(DevMesh m, const double* __restrict__ PG,
                                                      double* __restrict__ G) {
-  constexpr int NC = NR * ND;
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= m.nshared) return;
-  const int g = m.shared[k];
-  double out[NC];
-  shared_gradient<NC, ND>(m, PG, g, m.shared_run[k], out);
-#pragma unroll
-  for (int j = 0; j < NC; ++j) G[(size_t)j * m.nn + g] = out[j];
+  constexpr int NC = NR * ND, NB = kGradSharedNodes;
+  __shared__ double sg[NC * NB];
+  __shared__ int snode[NB];
+  const int k0 = blockIdx.x * NB;
+  const int nb = min(NB, m.nshared - k0);
+  if (nb <= 0) return;
+  if ((int)threadIdx.x < nb) snode[threadIdx.x] = m.shared[k0 + threadIdx.x];
+  for (int idx = threadIdx.x; idx < nb * NC; idx += blockDim.x) {
+    const int i = idx / NC, j = idx - i * NC;
+    const int2 run = m.shared_run[k0 + i];
+    double acc = 0.0;
+    // four partials in flight at a time, added in run order
+    int p = run.x;
+    for (; p + 4 <= run.y; p += 4) {
+      const double* src = PG + (size_t)p * NC + j;
+      const double a = src[0], b = src[NC], c = src[2 * NC], d = src[3 * NC];
+      acc += a;
+      acc += b;
+      acc += c;
+      acc += d;
+    }
+    for (; p < run.y; ++p) acc += PG[(size_t)p * NC + j];
+    sg[j * NB + i] = acc;
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < nb * NC; idx += blockDim.x) {
+    const int j = idx / nb, i = idx - j * nb;
+    const int g = snode[i];
+    const double coef = -m.inv_vol[g] / double(ND * m.nv);
+    G[(size_t)j * m.nn + g] = coef * sg[j * NB + i];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -797,7 +826,8 @@ struct Finish {
   long long* cand;      // candidate slots of this step's new state
   DevLoop* roll;        // fused passes: the shared-node pass of the first stage rolls the
   int roll_par;         //   candidate slots over (step_rollover) for this parity
-  int gfull;            // G holds the gradients of shared nodes too (fused passes)
+  int gfull;            // G holds the gradients of shared nodes too (fused passes; the
+                        // multi-species pass after the shared-node gradient completion)
   DtCoef dc;
   MixParams mix;        // Navier-Stokes species data
   double alpha;
@@ -1929,7 +1959,8 @@ __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ W,
       for (int d = 0; d < ND; ++d) xx[d] = m.x[(size_t)d * m.nn + g];
       stage_rows<NR, CT>(W, m.nn, g, 0, sW, 0, maxn, q);
       stage_rows<1, CT>(W, m.nn, g, NR + NP, sW, NR, maxn, q);
-      stage_gradient_part<NC, 0, CA, ND, CT>(m, G, f.PG, sv, m.slot_run[sl], sG, maxn, q);
+      // (with G complete on shared nodes too, every slot reads its node's row)
+      stage_gradient_part<NC, 0, CA, ND, CT>(m, G, f.PG, f.gfull ? g : sv, m.slot_run[sl], sG, maxn, q);
 #pragma unroll
       for (int d = 0; d < ND; ++d) sX[d * maxn + q] = xx[d];
     }
@@ -2024,7 +2055,7 @@ __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ W,
         stage_rows<2, CT>(W, m.nn, g, NR + NP + 1, sW, 1 + NP, maxn, q);
       else
         stage_rows<NA - 1, CT>(W, m.nn, g, NR + NP + 1, sW, 1 + NP, maxn, q);
-      stage_gradient_part<NC, CA, CB, ND, CT>(m, G, f.PG, sv, m.slot_run[sl], sG, maxn, q);
+      stage_gradient_part<NC, CA, CB, ND, CT>(m, G, f.PG, f.gfull ? g : sv, m.slot_run[sl], sG, maxn, q);
     }
   }
   __syncthreads();
