@@ -571,11 +571,12 @@ struct GradCtl {
   int first_stage; // first stage: an extra block decides the step
 };
 
-// Fields per pass of the gradient kernel: at most 8, in equal groups, so
-// that the staged fields and cell parts of many-field states (multi-species
-// Navier-Stokes) take a fraction of the LDS and more blocks fit on a CU.
+// Fields per pass of the gradient kernel: at most 8 (at most 4 for states
+// of more than 16 fields), in equal groups, so that the staged fields and
+// cell parts of many-field states (multi-species Navier-Stokes) take a
+// fraction of the LDS and more blocks fit on a CU.
 __host__ __device__ constexpr int grad_group(int nr) {
-  return (nr + (nr + 7) / 8 - 1) / ((nr + 7) / 8);
+  return nr > 16 ? (nr + (nr + 3) / 4 - 1) / ((nr + 3) / 4) : (nr + (nr + 7) / 8 - 1) / ((nr + 7) / 8);
 }
 
 template <int ND, int NR, int NV = ND + 1>
