@@ -542,7 +542,14 @@ vcx_status vcx::configure_solver(vcx_solver s, vcx_mesh mesh, const vcx_physics&
   // after a separate gradient pass)
   // (the predictor and the Scharfetter-Gummel flux take the separate passes too)
   const bool sg = ph.model == VCX_MODEL_DRIFT_DIFFUSION && ph.flux == VCX_FLUX_SG;
-  s->fused = !d.axi && ph.closure != 2 && !ph.predictor && !sg && s->lds_fused > 0 &&
+  // Drift-diffusion meshes above kFusedMaxCells take the separate passes:
+  // gradient, shared-node completion and flux outrun the fused pass once the
+  // launches are long (1.8M cells: 120 vs 158 us per step; 28.8M: 2.27 vs
+  // 2.59 ms), while the fused pass's two launches win on small meshes
+  // (200k cells: 26 vs 33 us).
+  constexpr int64_t kFusedMaxCells = int64_t(1) << 20;
+  const bool big_dd = ph.model == VCX_MODEL_DRIFT_DIFFUSION && d.nc > kFusedMaxCells;
+  s->fused = !d.axi && ph.closure != 2 && !ph.predictor && !sg && !big_dd && s->lds_fused > 0 &&
              s->lds_fused <= (size_t)mesh->lds_max;
   if (!s->fused) s->lds_fused = 0;
   if (std::max({s->lds_grad, s->lds_flux, s->lds_fused}) > 65536)

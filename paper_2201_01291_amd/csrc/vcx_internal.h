@@ -344,17 +344,20 @@ struct Impl {
       pp.dt_host = dt_host;
       pp.limiter = s->ph.limiter;
       const bool sg = s->ph.flux == VCX_FLUX_SG;
+      VCX_TRY(grad_complete(s));
+      Finish fg = f;
+      fg.gfull = 1;
       if constexpr (ND == 2) {
         if (m.axi)
           return launch(s, "flux", [&](hipEvent_t ea, hipEvent_t eb) {
             if (sg)
               hipExtLaunchKernelGGL((k_flux_dd<ND, NSP, CT, true, true, NV>), dim3(xcd_grid(m.ntiles)),
                                     dim3(s->tile_block), s->lds_flux, st, ea, eb, 0, m, Win,
-                                    (const double*)s->G, s->PR, pp, f);
+                                    (const double*)s->G, s->PR, pp, fg);
             else
               hipExtLaunchKernelGGL((k_flux_dd<ND, NSP, CT, true, false, NV>), dim3(xcd_grid(m.ntiles)),
                                     dim3(s->tile_block), s->lds_flux, st, ea, eb, 0, m, Win,
-                                    (const double*)s->G, s->PR, pp, f);
+                                    (const double*)s->G, s->PR, pp, fg);
           });
       }
       const int fb = cell_halves<ND, CT>() == 2 ? std::min(256, 2 * ((m.max_tile_cells + 63) / 64) * 64)
@@ -362,10 +365,10 @@ struct Impl {
       return launch(s, "flux", [&](hipEvent_t ea, hipEvent_t eb) {
         if (sg)
           hipExtLaunchKernelGGL((k_flux_dd<ND, NSP, CT, false, true, NV>), dim3(xcd_grid(m.ntiles)), dim3(fb),
-                                s->lds_flux, st, ea, eb, 0, m, Win, (const double*)s->G, s->PR, pp, f);
+                                s->lds_flux, st, ea, eb, 0, m, Win, (const double*)s->G, s->PR, pp, fg);
         else
           hipExtLaunchKernelGGL((k_flux_dd<ND, NSP, CT, false, false, NV>), dim3(xcd_grid(m.ntiles)), dim3(fb), s->lds_flux,
-                                st, ea, eb, 0, m, Win, (const double*)s->G, s->PR, pp, f);
+                                st, ea, eb, 0, m, Win, (const double*)s->G, s->PR, pp, fg);
       });
     }
   }

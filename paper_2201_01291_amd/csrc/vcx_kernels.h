@@ -1499,7 +1499,7 @@ __device__ inline void flux_dd_body(DevMesh m, const double* __restrict__ U,
       xe[d] = m.x[(size_t)d * m.nn + g];
       xe[ND + d] = E[(size_t)d * m.nn + g];
     }
-    stage_gradient<NS * ND, ND, CT>(m, G, f.PG, sv, st.run, sG, maxn, q);
+    stage_gradient<NS * ND, ND, CT>(m, G, f.PG, f.gfull ? g : sv, st.run, sG, maxn, q);
 #pragma unroll
     for (int s = 0; s < NS; ++s) sU[s * maxn + q] = CT(u[s]);
 #pragma unroll
