@@ -774,12 +774,11 @@ __device__ inline void stage_gradient(const DevMesh& m, const double* __restrict
 // from LDS.
 constexpr int kGradSharedNodes = 32;
 template <int ND, int NR>
-__global__ void __launch_bounds__(256) k_grad_shared(DevMesh m, const double* __restrict__ PG,
-                                                     double* __restrict__ G) {
+__device__ inline void grad_shared_body(const DevMesh& m, const double* __restrict__ PG,
+                                        double* __restrict__ G, int k0) {
   constexpr int NC = NR * ND, NB = kGradSharedNodes;
   __shared__ double sg[NC * NB];
   __shared__ int snode[NB];
-  const int k0 = blockIdx.x * NB;
   const int nb = min(NB, m.nshared - k0);
   if (nb <= 0) return;
   if ((int)threadIdx.x < nb) snode[threadIdx.x] = m.shared[k0 + threadIdx.x];
@@ -807,6 +806,12 @@ __global__ void __launch_bounds__(256) k_grad_shared(DevMesh m, const double* __
     const double coef = -m.inv_vol[g] / double(ND * m.nv);
     G[(size_t)j * m.nn + g] = coef * sg[j * NB + i];
   }
+}
+
+template <int ND, int NR>
+__global__ void __launch_bounds__(256) k_grad_shared(DevMesh m, const double* __restrict__ PG,
+                                                     double* __restrict__ G) {
+  grad_shared_body<ND, NR>(m, PG, G, (int)blockIdx.x * kGradSharedNodes);
 }
 
 // ---------------------------------------------------------------------------
@@ -930,15 +935,15 @@ __device__ inline void closure_flux(const DevMesh& m, const Finish& f, int k, bo
 // Axisymmetric multi-species: the hoop stress tau_theta_theta of node i,
 // 2 eta u_r/r + lambda (u_r/r + du_r/dr + du_x/dx) with lambda = -2/3 eta
 // (Stokes), u_r/r taking its limit du_r/dr on the axis.  The two velocity
-// derivatives come from the node's gradient: G for a node inside one tile,
-// else the sum of its tile partials (run of PG), as the gradient pass
-// leaves them.
+// derivatives come from the node's gradient: G for a node inside one tile or
+// once G is complete, else the sum of its tile partials (run of PG), as the
+// gradient pass leaves them.
 template <int ND, int NSP>
 __device__ inline double ns_hoop_stress(const DevMesh& m, const Finish& f, int i, bool shared, int2 run) {
   constexpr int NVAR = 2 + ND + NSP, NR = NVAR + 1, NP = ND + 1 + NSP, NC = (NR + NP) * ND;
   constexpr int CR = (NR + 1) * ND + 1, CX = NR * ND;  // du_r/dr, du_x/dx
   double durdr, duxdx;
-  if (!shared) {
+  if (!shared || f.gfull) {
     durdr = f.G[(size_t)CR * m.nn + i];
     duxdx = f.G[(size_t)CX * m.nn + i];
   } else {
@@ -2359,6 +2364,7 @@ __global__ void __launch_bounds__(256) k_cell_dx(DevMesh m, unsigned long long* 
 
 struct BatchEntry {
   DevMesh m;
+  DevMesh mg;       // tiling of the gradient pass and its completion (m, or coarser tiles)
   double* W[2];     // state buffers; the current one is W[(step + phase) & 1]
   double* G;
   double* PG;
@@ -2382,6 +2388,7 @@ struct FinishShared {
   MixParams mix;
   int closure;
   int fused;        // the stage runs the fused gradient + flux pass
+  int gcomplete;    // G is complete on shared nodes before the flux pass (multi-species)
 };
 
 __device__ inline Finish batch_finish(const BatchEntry& e, const BatchStage& st,
@@ -2402,7 +2409,7 @@ __device__ inline Finish batch_finish(const BatchEntry& e, const BatchStage& st,
     f.roll = e.lp;
     f.roll_par = par;
   }
-  f.gfull = fs.fused && e.gout != nullptr;
+  f.gfull = (fs.fused && e.gout != nullptr) || fs.gcomplete;
   f.dc = fs.dc;
   f.mix = fs.mix;
   f.alpha = st.alpha;
@@ -2431,7 +2438,17 @@ __global__ void __launch_bounds__(256) k_grad_tile_batch(const BatchEntry* __res
   const int cur = (st.step + e.phase) & 1;
   const double* Win = st.stage == 1 ? e.W[cur] : e.W[cur ^ 1];
   GradCtl ctl{e.lp, par, st.stage == 1 ? 1 : 0};
-  grad_tile_body<ND, NR>(e.m, Win, e.G, e.PG, ctl, ml.y, lds);
+  grad_tile_body<ND, NR>(e.mg, Win, e.G, e.PG, ctl, ml.y, lds);
+}
+
+// shared-node gradient completion of every solve of a batch (block map:
+// solve, block of kGradSharedNodes shared nodes of its gradient tiling)
+template <int ND, int NR>
+__global__ void __launch_bounds__(256) k_grad_shared_batch(const BatchEntry* __restrict__ tab,
+                                                           const int2* __restrict__ map) {
+  const int2 ml = map[blockIdx.x];
+  const BatchEntry& e = tab[ml.x];
+  grad_shared_body<ND, NR>(e.mg, e.PG, e.G, ml.y * kGradSharedNodes);
 }
 
 template <int ND, int NSP, int FLUX, typename CT>

@@ -21,6 +21,15 @@ TileLimits default_tile_limits(int nd) {
   return {128, 96};
 }
 
+#ifndef VCX_GRAD_TILE_CELLS
+#define VCX_GRAD_TILE_CELLS 384
+#endif
+
+TileLimits gradient_tile_limits(TileLimits mesh) {
+  const int c = std::min(VCX_GRAD_TILE_CELLS, 4 * mesh.max_cells);
+  return {c, std::max(c * 3 / 4, mesh.max_nodes)};
+}
+
 namespace {
 
 uint64_t spread_bits(uint64_t v, int nd) {
@@ -83,6 +92,90 @@ void node_normals(int nd, const double e[3][3], double S[4][3]) {
 }
 
 }  // namespace
+
+// Tiles of consecutive cells, each closed at lim.max_cells cells or
+// lim.max_nodes distinct nodes, with their slot, incidence and run tables.
+std::string build_tiling(const HostMesh& m, TileLimits lim, Tiling& out) {
+  const int nv = m.nv;
+  const int64_t nn = m.nn, nc = m.nc;
+  out = Tiling();
+  std::vector<int64_t> stamp(nn, -1);
+  out.tile_cell.push_back(0);
+  int64_t tcount = 0, ncount = 0;
+  for (int64_t c = 0; c < nc; ++c) {
+    int fresh = 0;
+    for (int k = 0; k < nv; ++k)
+      if (stamp[m.cell[(size_t)k * nc + c]] != (int64_t)out.tile_cell.size() - 1) ++fresh;
+    if (tcount > 0 && (tcount + 1 > lim.max_cells || ncount + fresh > lim.max_nodes)) {
+      out.tile_cell.push_back((int32_t)c);
+      tcount = 0;
+      ncount = 0;
+      fresh = nv;
+    }
+    int64_t t = (int64_t)out.tile_cell.size() - 1;
+    for (int k = 0; k < nv; ++k) {
+      int32_t i = m.cell[(size_t)k * nc + c];
+      if (stamp[i] != t) { stamp[i] = t; ++ncount; }
+    }
+    ++tcount;
+  }
+  out.tile_cell.push_back((int32_t)nc);
+  int64_t T = out.ntiles();
+
+  out.lconn.resize((size_t)nv * nc);
+  out.tile_slot.assign(1, 0);
+  std::vector<int32_t> local(nn, -1);
+  std::vector<int32_t> tnodes;
+  std::vector<std::vector<uint16_t>> tinc;
+  out.slot_inc.assign(1, 0);
+  for (int64_t t = 0; t < T; ++t) {
+    int32_t c0 = out.tile_cell[t], c1 = out.tile_cell[t + 1];
+    tnodes.clear();
+    for (int32_t c = c0; c < c1; ++c)
+      for (int k = 0; k < nv; ++k) tnodes.push_back(m.cell[(size_t)k * nc + c]);
+    std::sort(tnodes.begin(), tnodes.end());
+    tnodes.erase(std::unique(tnodes.begin(), tnodes.end()), tnodes.end());
+    for (size_t q = 0; q < tnodes.size(); ++q) local[tnodes[q]] = (int32_t)q;
+    tinc.assign(tnodes.size(), {});
+    for (int32_t c = c0; c < c1; ++c)
+      for (int k = 0; k < nv; ++k) {
+        int32_t l = local[m.cell[(size_t)k * nc + c]];
+        out.lconn[(size_t)k * nc + c] = (uint16_t)l;
+        tinc[l].push_back((uint16_t)(((c - c0) << 2) | k));
+      }
+    for (size_t q = 0; q < tnodes.size(); ++q) {
+      out.slot_node.push_back(tnodes[q]);
+      for (uint16_t code : tinc[q]) out.inc.push_back(code);
+      out.slot_inc.push_back((int32_t)out.inc.size());
+    }
+    out.tile_slot.push_back((int32_t)out.slot_node.size());
+    out.max_tile_cells = std::max(out.max_tile_cells, (int)(c1 - c0));
+    out.max_tile_nodes = std::max(out.max_tile_nodes, (int)tnodes.size());
+  }
+
+  // ---- node -> slots (ascending tile order)
+  int64_t P = out.nslots();
+  out.node_slot.assign(nn + 1, 0);
+  for (int64_t s = 0; s < P; ++s) out.node_slot[out.slot_node[s] + 1]++;
+  for (int64_t i = 0; i < nn; ++i) out.node_slot[i + 1] += out.node_slot[i];
+  out.slots_of.resize(P);
+  std::vector<int32_t> fill(out.node_slot.begin(), out.node_slot.end() - 1);
+  for (int64_t s = 0; s < P; ++s) out.slots_of[fill[out.slot_node[s]]++] = (int32_t)s;
+  for (int64_t i = 0; i < nn; ++i)
+    if (out.node_slot[i + 1] == out.node_slot[i]) return "node not referenced by any cell";
+  // nodes split over several tiles: gathered through partial sums
+  for (int64_t i = 0; i < nn; ++i)
+    if (out.node_slot[i + 1] - out.node_slot[i] > 1) out.shared.push_back((int32_t)i);
+  out.slot_run.resize(2 * P);
+  for (int64_t s = 0; s < P; ++s) {
+    int32_t g = out.slot_node[s];
+    out.slot_run[2 * s] = out.node_slot[g];
+    out.slot_run[2 * s + 1] = out.node_slot[g + 1];
+    if (out.node_slot[g + 1] - out.node_slot[g] > 1) out.slot_node[s] = ~g;
+  }
+
+  return "";
+}
 
 std::string preprocess_mesh(int nd, int64_t nn, const double* xyz, int64_t nc, int nv,
                             const int64_t* cells, const double* period, TileLimits lim,
@@ -395,80 +488,23 @@ std::string preprocess_mesh(int nd, int64_t nn, const double* xyz, int64_t nc, i
     while (q < nb) m.bedge_ptr[++q] = (int32_t)shares.size();
   }
 
-  // ---- tiles: consecutive cells, closed at max_cells cells or max_nodes nodes
-  std::vector<int64_t> stamp(nn, -1);
-  m.tile_cell.push_back(0);
-  int64_t tcount = 0, ncount = 0;
-  for (int64_t c = 0; c < nc; ++c) {
-    int fresh = 0;
-    for (int k = 0; k < nv; ++k)
-      if (stamp[m.cell[(size_t)k * nc + c]] != (int64_t)m.tile_cell.size() - 1) ++fresh;
-    if (tcount > 0 && (tcount + 1 > lim.max_cells || ncount + fresh > lim.max_nodes)) {
-      m.tile_cell.push_back((int32_t)c);
-      tcount = 0;
-      ncount = 0;
-      fresh = nv;
-    }
-    int64_t t = (int64_t)m.tile_cell.size() - 1;
-    for (int k = 0; k < nv; ++k) {
-      int32_t i = m.cell[(size_t)k * nc + c];
-      if (stamp[i] != t) { stamp[i] = t; ++ncount; }
-    }
-    ++tcount;
-  }
-  m.tile_cell.push_back((int32_t)nc);
-  int64_t T = m.ntiles();
-
-  m.lconn.resize((size_t)nv * nc);
-  m.tile_slot.assign(1, 0);
-  std::vector<int32_t> local(nn, -1);
-  std::vector<int32_t> tnodes;
-  std::vector<std::vector<uint16_t>> tinc;
-  m.slot_inc.assign(1, 0);
-  for (int64_t t = 0; t < T; ++t) {
-    int32_t c0 = m.tile_cell[t], c1 = m.tile_cell[t + 1];
-    tnodes.clear();
-    for (int32_t c = c0; c < c1; ++c)
-      for (int k = 0; k < nv; ++k) tnodes.push_back(m.cell[(size_t)k * nc + c]);
-    std::sort(tnodes.begin(), tnodes.end());
-    tnodes.erase(std::unique(tnodes.begin(), tnodes.end()), tnodes.end());
-    for (size_t q = 0; q < tnodes.size(); ++q) local[tnodes[q]] = (int32_t)q;
-    tinc.assign(tnodes.size(), {});
-    for (int32_t c = c0; c < c1; ++c)
-      for (int k = 0; k < nv; ++k) {
-        int32_t l = local[m.cell[(size_t)k * nc + c]];
-        m.lconn[(size_t)k * nc + c] = (uint16_t)l;
-        tinc[l].push_back((uint16_t)(((c - c0) << 2) | k));
-      }
-    for (size_t q = 0; q < tnodes.size(); ++q) {
-      m.slot_node.push_back(tnodes[q]);
-      for (uint16_t code : tinc[q]) m.inc.push_back(code);
-      m.slot_inc.push_back((int32_t)m.inc.size());
-    }
-    m.tile_slot.push_back((int32_t)m.slot_node.size());
-    m.max_tile_cells = std::max(m.max_tile_cells, (int)(c1 - c0));
-    m.max_tile_nodes = std::max(m.max_tile_nodes, (int)tnodes.size());
-  }
-
-  // ---- node -> slots (ascending tile order)
-  int64_t P = m.nslots();
-  m.node_slot.assign(nn + 1, 0);
-  for (int64_t s = 0; s < P; ++s) m.node_slot[m.slot_node[s] + 1]++;
-  for (int64_t i = 0; i < nn; ++i) m.node_slot[i + 1] += m.node_slot[i];
-  m.slots_of.resize(P);
-  std::vector<int32_t> fill(m.node_slot.begin(), m.node_slot.end() - 1);
-  for (int64_t s = 0; s < P; ++s) m.slots_of[fill[m.slot_node[s]]++] = (int32_t)s;
-  for (int64_t i = 0; i < nn; ++i)
-    if (m.node_slot[i + 1] == m.node_slot[i]) return "node not referenced by any cell";
-  // nodes split over several tiles: gathered through partial sums
-  for (int64_t i = 0; i < nn; ++i)
-    if (m.node_slot[i + 1] - m.node_slot[i] > 1) m.shared.push_back((int32_t)i);
-  m.slot_run.resize(2 * P);
-  for (int64_t s = 0; s < P; ++s) {
-    int32_t g = m.slot_node[s];
-    m.slot_run[2 * s] = m.node_slot[g];
-    m.slot_run[2 * s + 1] = m.node_slot[g + 1];
-    if (m.node_slot[g + 1] - m.node_slot[g] > 1) m.slot_node[s] = ~g;
+  // ---- tiles
+  {
+    Tiling t;
+    std::string e = build_tiling(m, lim, t);
+    if (!e.empty()) return e;
+    m.tile_cell = std::move(t.tile_cell);
+    m.tile_slot = std::move(t.tile_slot);
+    m.slot_node = std::move(t.slot_node);
+    m.lconn = std::move(t.lconn);
+    m.slot_inc = std::move(t.slot_inc);
+    m.inc = std::move(t.inc);
+    m.node_slot = std::move(t.node_slot);
+    m.slots_of = std::move(t.slots_of);
+    m.shared = std::move(t.shared);
+    m.slot_run = std::move(t.slot_run);
+    m.max_tile_cells = t.max_tile_cells;
+    m.max_tile_nodes = t.max_tile_nodes;
   }
 
   if (nd == 2 && !quad) build_halos(m);

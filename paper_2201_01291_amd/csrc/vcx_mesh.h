@@ -14,6 +14,32 @@ struct TileLimits {
 };
 
 TileLimits default_tile_limits(int nd);
+// Tiles of the multi-species gradient pass, given the mesh's: up to four
+// times larger (at most 384 cells), so that a node has fewer slots (partial
+// sums to write and to gather) while the pass, which stages a few fields at
+// a time, still fits three blocks' LDS on a CU.
+TileLimits gradient_tile_limits(TileLimits mesh);
+
+// A tiling of the cells (consecutive cells in the internal order, each tile
+// closed at max_cells cells or max_nodes distinct nodes) with its slot tables:
+// a tile's nodes are its slots; a node with slots in several tiles is shared
+// and gathered through per-slot partial sums in ascending tile order.
+struct Tiling {
+  std::vector<int32_t> tile_cell;  // [T+1] first cell of each tile
+  std::vector<int32_t> tile_slot;  // [T+1] first slot of each tile
+  std::vector<int32_t> slot_node;  // [P] node of each slot (ascending inside a tile); ~node
+                                   // when the node also has slots in other tiles
+  std::vector<uint16_t> lconn;     // [nv][nc] tile-local node of each cell vertex
+  std::vector<int32_t> slot_inc;   // [P+1] CSR into inc
+  std::vector<uint16_t> inc;       // [nc*nv] (local cell << 2) | vertex, ascending cell
+  std::vector<int32_t> node_slot;  // [nn+1] CSR into slots_of
+  std::vector<int32_t> slots_of;   // [P] slots of each node, ascending tile
+  std::vector<int32_t> shared;     // nodes with more than one slot, ascending
+  std::vector<int32_t> slot_run;   // [2P] per slot: [begin, end) of its node's run in slots_of
+  int max_tile_cells = 0, max_tile_nodes = 0;
+  int64_t ntiles() const { return (int64_t)tile_cell.size() - 1; }
+  int64_t nslots() const { return (int64_t)slot_node.size(); }
+};
 
 // Mesh after preprocessing, in the internal (space-filling-curve) order.
 struct HostMesh {
@@ -88,9 +114,18 @@ struct HostMesh {
   std::vector<uint16_t> einc;      // [2E] per slot: (tile edge << 1) | (1 if the slot's node is end b)
   int max_tile_edges = 0;
 
+  // a coarser tiling for the gradient pass of the multi-species model (built
+  // on demand): fewer tiles per node, so fewer partial sums to write and
+  // gather, while its LDS per tile stays small
+  bool has_gtiles = false;
+  Tiling gt;
+
   int64_t ntiles() const { return (int64_t)tile_cell.size() - 1; }
   int64_t nslots() const { return (int64_t)slot_node.size(); }
 };
+
+// Tile the cells of a preprocessed mesh; returns "" or an error message.
+std::string build_tiling(const HostMesh& m, TileLimits lim, Tiling& t);
 
 // Returns "" on success, else an error message; *code receives the status
 // (-1 argument, -2 mesh).

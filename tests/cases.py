@@ -111,6 +111,15 @@ def make_case(name: str) -> Case:
         U = wl.ns_state(m, mix, lattice=4, seed=6)
         return Case(name, m, U, None, dict(model="ns", flux="hllc", limiter="vanleer", rk=2,
                                            nspecies=9, mixture=mix), tiles=(64, 48))
+    if name == "ns3d-sp2-smalltile":
+        # small flux tiles: the gradient pass's tiles (four times larger)
+        # still split the mesh, so its shared-node completion runs
+        mix = wl.synthetic_mixture(2, seed=7)
+        mix.mu_ref = 2e-3
+        m = wl.kuhn_tet_mesh(4, 4, 3, 0.008, 0.008, 0.006, jitter=0.15, seed=12)
+        U = wl.ns_state(m, mix, lattice=3, seed=13, vel=(25.0, -10.0, 5.0))
+        return Case(name, m, U, None, dict(model="ns", flux="hllc", limiter="minmod", rk=3,
+                                           nspecies=2, mixture=mix), tiles=(24, 20))
     if name == "ns2d-sp2-open":
         mix = wl.synthetic_mixture(2, seed=5)
         mix.mu_ref = 2e-3    # visible diffusive fluxes at this resolution
@@ -271,7 +280,7 @@ BRANCH_CASES = {
 
 CASE_NAMES = ["dd2d-streamer", "dd2d-diel", "dd2d-open-vanleer", "dd2d-open-closure2",
               "euler2d-open-closure2", "dd3d-sweby", "sod-hllc", "euler2d-roe-sp2",
-              "euler3d-roe", "euler3d-hllc-open-sp2", "euler3d-hllc-sp9", "ns3d-sp9",
+              "euler3d-roe", "euler3d-hllc-open-sp2", "euler3d-hllc-sp9", "ns3d-sp9", "ns3d-sp2-smalltile",
               "ns2d-sp2-open", "ns2d-sp2-bigtile", *BRANCH_CASES, *HANCOCK_CASES, *SG_CASES,
               *QUAD_CASES]
 
