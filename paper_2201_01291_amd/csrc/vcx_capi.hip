@@ -90,52 +90,31 @@ extern "C" vcx_status vcx_mesh_create(int ndim, int64_t nnodes, const double* xy
   return vcx_mesh_create_tiled(ndim, nnodes, xyz, ncells, nv, cells, period, 0, 0, stream, out);
 }
 
-// Build (host) and upload (device) the gradient tiling of a mesh, once:
-// tiles larger than the mesh's, for the multi-species gradient pass and its
-// shared-node completion (nothing when the mesh's tiles are as large).
-vcx_status vcx::ensure_grad_tiles(vcx_mesh m) {
-  if (m->has_dg) return VCX_OK;
+// Build (host) and upload (device) the node-gradient tables of a simplex
+// mesh, once (the host copies are released after the upload).
+vcx_status vcx::ensure_node_gradient(vcx_mesh m) {
+  if (m->d.has_ngrad) return VCX_OK;
   HostMesh& h = m->h;
-  const TileLimits lim = gradient_tile_limits(h.lim);
-  if (lim.max_cells <= h.lim.max_cells) return VCX_OK;
-  std::string err = build_tiling(h, lim, h.gt);
+  if (h.nv != h.nd + 1) return VCX_OK;
+  std::string err = build_node_gradient(h);
   if (!err.empty()) return fail(VCX_E_MESH, err);
-  const Tiling& t = h.gt;
-  std::vector<int32_t> tile_inc(t.tile_slot.size()), slot_pos(t.slot_node.size());
-  for (size_t q = 0; q < t.tile_slot.size(); ++q) tile_inc[q] = t.slot_inc[t.tile_slot[q]];
-  for (size_t p = 0; p < t.slots_of.size(); ++p) slot_pos[t.slots_of[p]] = (int32_t)p;
-  std::vector<int32_t> srun(2 * t.shared.size());
-  for (size_t k = 0; k < t.shared.size(); ++k) {
-    srun[2 * k] = t.node_slot[t.shared[k]];
-    srun[2 * k + 1] = t.node_slot[t.shared[k] + 1];
-  }
-  DevMesh g = m->d;
-  const int32_t *sr = nullptr, *run = nullptr;
-  VCX_TRY(upload(m, t.lconn, &g.lconn));
-  VCX_TRY(upload(m, t.tile_cell, &g.tile_cell));
-  VCX_TRY(upload(m, t.tile_slot, &g.tile_slot));
-  VCX_TRY(upload(m, t.slot_node, &g.slot_node));
-  VCX_TRY(upload(m, t.slot_inc, &g.slot_inc));
-  VCX_TRY(upload(m, t.inc, &g.inc));
-  VCX_TRY(upload(m, tile_inc, &g.tile_inc));
-  VCX_TRY(upload(m, slot_pos, &g.slot_pos));
-  VCX_TRY(upload(m, t.node_slot, &g.node_slot));
-  VCX_TRY(upload(m, t.slots_of, &g.slots_of));
-  VCX_TRY(upload(m, t.shared, &g.shared));
-  VCX_TRY(upload(m, srun, &sr));
-  VCX_TRY(upload(m, t.slot_run, &run));
-  g.shared_run = reinterpret_cast<const int2*>(sr);
-  g.slot_run = reinterpret_cast<const int2*>(run);
-  g.ntiles = (int)t.ntiles();
-  g.nslots = (int)t.nslots();
-  g.nshared = (int)t.shared.size();
-  g.max_tile_cells = t.max_tile_cells;
-  g.max_tile_nodes = t.max_tile_nodes;
-  // no extended tiles or tile edges: the gradient pass reads neither
-  g.has_halo = 0;
-  g.has_edges = 0;
-  m->dg = g;
-  m->has_dg = true;
+  DevMesh& d = m->d;
+  const int64_t* off = nullptr;
+  const int32_t* nbr = nullptr;
+  const double* c = nullptr;
+  VCX_TRY(upload(m, h.ng_off, &off));
+  VCX_TRY(upload(m, h.ng_nbr, &nbr));
+  VCX_TRY(upload(m, h.ng_c, &c));
+  VCX_HIP(hipStreamSynchronize(m->stream));
+  d.ng_off = reinterpret_cast<const long long*>(off);
+  d.ng_nbr = nbr;
+  d.ng_c = c;
+  d.ng_nslices = (int)(h.ng_off.size() - 1);
+  d.ng_total = (long long)h.ng_off.back();
+  d.has_ngrad = 1;
+  std::vector<int64_t>().swap(h.ng_off);
+  std::vector<int32_t>().swap(h.ng_nbr);
+  std::vector<double>().swap(h.ng_c);
   return VCX_OK;
 }
 
@@ -422,13 +401,14 @@ struct SolverSizes {
   }
 };
 
-static SolverSizes solver_sizes(const DevMesh& d, int nd, int nvar, int nr, int nw, int ngf, int model,
-                                int grad_slots) {
+static SolverSizes solver_sizes(const DevMesh& d, int nd, int nvar, int nr, int nw, int ngf, int model) {
   SolverSizes z;
   const size_t nn = (size_t)d.nn, P = (size_t)d.nslots;
   z.W = (size_t)nw * nn;
   z.G = (size_t)ngf * nd * nn;
-  z.PG = (size_t)ngf * nd * std::max<size_t>(P, (size_t)grad_slots);
+  // (the node-gradient pass has no partial sums; a solver may still take
+  // the tile gradient, so the partials keep their size)
+  z.PG = (size_t)ngf * nd * P;
   z.PR = (size_t)nvar * P;
   z.io = std::max<size_t>((size_t)ngf * nd, (size_t)nw) * nn;
   z.part = (size_t)nr * 256;
@@ -573,9 +553,11 @@ vcx_status vcx::configure_solver(vcx_solver s, vcx_mesh mesh, const vcx_physics&
   s->ngf = kt->ngf;
   s->kt = kt;
   const DevMesh& d = mesh->d;
-  s->gtiles = ph.model == VCX_MODEL_NAVIER_STOKES && mesh->has_dg;
-  const DevMesh& dgr = grad_mesh(s);
-  s->lds_grad = kt->lds_grad(dgr.max_tile_nodes, dgr.max_tile_cells);
+  // multi-species: the node-gradient pass where the mesh has its tables
+  // (built by the first solver of that model), else gradient tiles and the
+  // shared-node completion
+  s->ngrad = ph.model == VCX_MODEL_NAVIER_STOKES && d.has_ngrad;
+  s->lds_grad = s->ngrad ? 0 : kt->lds_grad(d.max_tile_nodes, d.max_tile_cells);
   if (ph.model == VCX_MODEL_NAVIER_STOKES && !d.has_edges)
     return fail(VCX_E_ARG, "the mesh has no tile-edge tables (created by the first Navier-Stokes solver)");
   s->lds_flux = kt->lds_flux(d, ph.predictor);
@@ -607,7 +589,6 @@ vcx_status vcx::configure_solver(vcx_solver s, vcx_mesh mesh, const vcx_physics&
   if (std::max({s->lds_grad, s->lds_flux, s->lds_fused}) > 65536)
     VCX_TRY(kt->allow_lds(s->lds_grad, s->lds_flux, s->lds_fused));
   s->tile_block = std::min(256, ((d.max_tile_cells + 63) / 64) * 64);
-  s->grad_block = std::min(256, ((dgr.max_tile_cells + 63) / 64) * 64);
   s->flux_block = ph.model == VCX_MODEL_NAVIER_STOKES
                       ? std::min(256, ((std::max(d.max_tile_cells, d.max_tile_edges) + 63) / 64) * 64)
                       : s->tile_block;
@@ -626,7 +607,7 @@ extern "C" vcx_status vcx_solver_create(vcx_mesh mesh, const vcx_physics* phys, 
   VCX_TRY(check_physics(mesh, ph, E, &kt));
   if (ph.model == VCX_MODEL_NAVIER_STOKES) {
     VCX_TRY(ensure_tile_edges(mesh));
-    VCX_TRY(ensure_grad_tiles(mesh));
+    VCX_TRY(ensure_node_gradient(mesh));
   }
   vcx_solver s = new (std::nothrow) vcx_solver_s();
   if (!s) return fail(VCX_E_OOM, "host allocation failed");
@@ -638,7 +619,7 @@ extern "C" vcx_status vcx_solver_create(vcx_mesh mesh, const vcx_physics* phys, 
     }
   }
   const DevMesh& d = mesh->d;
-  const SolverSizes z = solver_sizes(d, nd, s->nvar, s->nr, s->nw, s->ngf, ph.model, grad_mesh(s).nslots);
+  const SolverSizes z = solver_sizes(d, nd, s->nvar, s->nr, s->nw, s->ngf, ph.model);
   s->bytes = z.bytes();
   vcx_status st = VCX_OK;
   auto chk = [&](vcx_status x) {
@@ -934,18 +915,17 @@ struct vcx::BatchGroup {
   BatchEntry* tab = nullptr;
   int2* tile_map = nullptr;
   int2* grad_map = nullptr;
-  int2* gsh_map = nullptr;
   int2* sh_map = nullptr;
   double* tend = nullptr;
   int* steps = nullptr;
   DevScalars* out = nullptr;
   DevScalars* out_host = nullptr;  // pinned
-  int cap_tab = 0, cap_tiles = 0, cap_grad = 0, cap_gsh = 0, cap_sh = 0, cap_tend = 0, cap_steps = 0, cap_out = 0, cap_host = 0;
+  int cap_tab = 0, cap_tiles = 0, cap_grad = 0, cap_sh = 0, cap_tend = 0, cap_steps = 0, cap_out = 0, cap_host = 0;
   hipGraphExec_t pair = nullptr;   // two batch steps (parities 0 and 1), captured once per table
   ~BatchGroup() {
     if (pair) (void)hipGraphExecDestroy(pair);
-    for (void* p : {(void*)tab, (void*)tile_map, (void*)grad_map, (void*)gsh_map, (void*)sh_map, (void*)tend,
-                    (void*)steps, (void*)out})
+    for (void* p : {(void*)tab, (void*)tile_map, (void*)grad_map, (void*)sh_map, (void*)tend, (void*)steps,
+                    (void*)out})
       if (p) (void)hipFree(p);
     if (out_host) (void)hipHostFree(out_host);
     if (cap) (void)hipStreamDestroy(cap);
@@ -955,7 +935,6 @@ struct vcx::BatchGroup {
 static BatchEntry entry_of(vcx_solver s) {
   BatchEntry e{};
   e.m = s->mesh->d;
-  e.mg = grad_mesh(s);
   e.W[0] = s->W[0];
   e.W[1] = s->W[1];
   e.G = s->G;
@@ -1013,14 +992,17 @@ vcx_status vcx::batch_set(BatchGroup* g, vcx_solver* ss, int n, const int* steps
                   (ss[i]->ph.model == VCX_MODEL_DRIFT_DIFFUSION && ss[i]->ph.flux == VCX_FLUX_SG)))
       return fail(VCX_E_ARG, "solvers on axisymmetric meshes, with the interpolated closure, the "
                              "predictor or the Scharfetter-Gummel flux are not batched");
+  for (int i = 0; i < n; ++i)
+    if (ss[i] && ss[i]->ph.model == VCX_MODEL_NAVIER_STOKES && !ss[i]->ngrad)
+      return fail(VCX_E_ARG, "multi-species solvers are batched with the node-gradient pass");
   g->mem.assign(ss, ss + n);
   g->q = 0;
   if (n == 0) return VCX_OK;
   vcx_solver lead = ss[0];
   std::vector<BatchEntry> tab(n);
-  std::vector<int2> tmap, gmap, gsmap, smap;
+  std::vector<int2> tmap, gmap, smap;
   size_t lg = 0, lf = 0, lfu = 0;
-  int block = 64, fblock = 64, gblock = 64;
+  int block = 64, fblock = 64;
   g->steps0.resize(n);
   g->phase0.resize(n);
   g->spar0.resize(n);
@@ -1034,18 +1016,14 @@ vcx_status vcx::batch_set(BatchGroup* g, vcx_solver* ss, int n, const int* steps
     g->phase0[i] = s->cur;
     g->spar0[i] = s->spar;
     for (int t = 0; t < s->mesh->d.ntiles; ++t) tmap.push_back(make_int2(i, t));
-    const DevMesh& mg = grad_mesh(s);
-    for (int t = 0; t < mg.ntiles; ++t) gmap.push_back(make_int2(i, t));
-    if (s->ph.model == VCX_MODEL_NAVIER_STOKES)
-      for (int b = 0; b < (mg.nshared + kGradSharedNodes - 1) / kGradSharedNodes; ++b)
-        gsmap.push_back(make_int2(i, b));
+    if (s->ngrad)
+      for (int b = 0; b < s->mesh->d.ng_nslices; ++b) gmap.push_back(make_int2(i, b));
     for (int b = 0; b < s->nsh_blocks; ++b) smap.push_back(make_int2(i, b));
     lg = std::max(lg, s->lds_grad);
     lf = std::max(lf, s->lds_flux);
     lfu = std::max(lfu, s->lds_fused);
     block = std::max(block, s->tile_block);
     fblock = std::max(fblock, s->flux_block);
-    gblock = std::max(gblock, s->grad_block);
   }
   const bool fused = lead->fused;
   const int lds_max = lead->mesh->lds_max;
@@ -1058,7 +1036,6 @@ vcx_status vcx::batch_set(BatchGroup* g, vcx_solver* ss, int n, const int* steps
   VCX_TRY(dev_array(&g->out, &g->cap_out, n));
   VCX_TRY(dev_array(&g->tile_map, &g->cap_tiles, (int)tmap.size()));
   VCX_TRY(dev_array(&g->grad_map, &g->cap_grad, (int)gmap.size()));
-  VCX_TRY(dev_array(&g->gsh_map, &g->cap_gsh, (int)gsmap.size()));
   VCX_TRY(dev_array(&g->sh_map, &g->cap_sh, (int)smap.size()));
   if (g->cap_host < n) {
     if (g->out_host) (void)hipHostFree(g->out_host);
@@ -1074,8 +1051,6 @@ vcx_status vcx::batch_set(BatchGroup* g, vcx_solver* ss, int n, const int* steps
   VCX_HIP(hipMemcpyAsync(g->tab, tab.data(), sizeof(BatchEntry) * n, hipMemcpyHostToDevice, st));
   VCX_HIP(hipMemcpyAsync(g->tile_map, tmap.data(), sizeof(int2) * tmap.size(), hipMemcpyHostToDevice, st));
   VCX_HIP(hipMemcpyAsync(g->grad_map, gmap.data(), sizeof(int2) * gmap.size(), hipMemcpyHostToDevice, st));
-  if (!gsmap.empty())
-    VCX_HIP(hipMemcpyAsync(g->gsh_map, gsmap.data(), sizeof(int2) * gsmap.size(), hipMemcpyHostToDevice, st));
   VCX_HIP(hipMemcpyAsync(g->sh_map, smap.data(), sizeof(int2) * smap.size(), hipMemcpyHostToDevice, st));
   VCX_HIP(hipMemcpyAsync(g->tend, t_end, sizeof(double) * n, hipMemcpyHostToDevice, st));
   VCX_HIP(hipMemcpyAsync(g->steps, steps_left, sizeof(int) * n, hipMemcpyHostToDevice, st));
@@ -1091,9 +1066,6 @@ vcx_status vcx::batch_set(BatchGroup* g, vcx_solver* ss, int n, const int* steps
   br.ntile_blocks = (int)tmap.size();
   br.grad_map = g->grad_map;
   br.ngrad_blocks = (int)gmap.size();
-  br.gsh_map = g->gsh_map;
-  br.ngsh_blocks = (int)gsmap.size();
-  br.grad_block = std::min(256, gblock);
   br.sh_map = g->sh_map;
   br.nsh_blocks = (int)smap.size();
   br.lds_grad = lg;
@@ -1170,8 +1142,7 @@ vcx_status vcx::solver_footprint(vcx_mesh mesh, const vcx_physics* ph, size_t* b
   const int nd = mesh->h.nd;
   const int nvar = ph->model == VCX_MODEL_DRIFT_DIFFUSION ? ph->nspecies : 2 + nd + ph->nspecies;
   const int nr = ph->model == VCX_MODEL_DRIFT_DIFFUSION ? nvar : nvar + 1;
-  const int gslots = ph->model == VCX_MODEL_NAVIER_STOKES && mesh->has_dg ? mesh->dg.nslots : 0;
-  *bytes = solver_sizes(mesh->d, nd, nvar, nr, kt->nw, kt->ngf, ph->model, gslots).bytes();
+  *bytes = solver_sizes(mesh->d, nd, nvar, nr, kt->nw, kt->ngf, ph->model).bytes();
   return VCX_OK;
 }
 

@@ -44,11 +44,6 @@ constexpr int kNodeBlock = 256;
 struct vcx_mesh_s {
   HostMesh h;
   DevMesh d{};
-  // the gradient pass of the multi-species model on coarser tiles (built by
-  // its first solver): a copy of d whose tile, slot and shared-node tables
-  // are those of h.gt
-  DevMesh dg{};
-  bool has_dg = false;
   std::vector<void*> allocs;
   hipStream_t stream = nullptr;
   int device = 0;
@@ -88,8 +83,7 @@ struct vcx_solver_s {
   double* gout = nullptr;  // fused passes: node gradients for the boundary closure, or null
   double* cbuf = nullptr;  // second closure option: [nb][nvar] closure fluxes of the stage input
   int tile_block = 256;
-  bool gtiles = false;   // the gradient pass and its completion use the mesh's gradient tiling
-  int grad_block = 256;  // block of the gradient pass
+  bool ngrad = false;    // multi-species: the node-gradient pass (complete G, no partial sums)
   int flux_block = 256;  // block of the flux tile pass (multi-species: covers the tile's edges)
   size_t bytes = 0;  // device bytes held by the solver (mesh excluded)
   // profiling
@@ -102,9 +96,6 @@ struct vcx_solver_s {
 // ---------------------------------------------------------------------------
 // launch helper with optional event timing
 // ---------------------------------------------------------------------------
-
-// the tiling of a solver's gradient pass and of its shared-node completion
-inline const DevMesh& grad_mesh(vcx_solver s) { return s->gtiles ? s->mesh->dg : s->mesh->d; }
 
 inline hipEvent_t take_event(vcx_solver s) {
   if (!s->spare.empty()) {
@@ -166,14 +157,12 @@ struct BatchRun {
   BatchEntry* tab;
   int2* tile_map;
   int ntile_blocks;
-  int2* grad_map;                  // blocks of the gradient pass (the solves' gradient tilings)
+  int2* grad_map;                  // blocks of the node-gradient pass (multi-species): solve, slice
   int ngrad_blocks;
-  int2* gsh_map;                   // blocks of the shared-node gradient completion (multi-species)
-  int ngsh_blocks;
   int2* sh_map;
   int nsh_blocks;
   size_t lds_grad, lds_flux;
-  int tile_block, flux_block, grad_block;
+  int tile_block, flux_block;
   bool fused;
 };
 
@@ -276,16 +265,23 @@ struct Impl {
     }
   }
   static vcx_status grad(vcx_solver s, const double* Win, const GradCtl& gc) {
-    const DevMesh& m = grad_mesh(s);
+    const DevMesh& m = s->mesh->d;
+    const int lead = gc.lp && gc.first_stage ? 1 : 0;
+    if constexpr (MODEL == 2 && SIMPLEX) {
+      if (s->ngrad)
+        return launch(s, "gradient", [&](hipEvent_t ea, hipEvent_t eb) {
+          hipExtLaunchKernelGGL((k_grad_node<ND, NGF>), dim3(xcd_grid(m.ng_nslices) + lead), dim3(256), 0,
+                                s->mesh->stream, ea, eb, 0, m, Win, s->G, gc);
+        });
+    }
     return launch(s, "gradient", [&](hipEvent_t ea, hipEvent_t eb) {
-      const int lead = gc.lp && gc.first_stage ? 1 : 0;
-      hipExtLaunchKernelGGL((k_grad_tile<ND, NGF, NV>), dim3(xcd_grid(m.ntiles) + lead), dim3(s->grad_block),
+      hipExtLaunchKernelGGL((k_grad_tile<ND, NGF, NV>), dim3(xcd_grid(m.ntiles) + lead), dim3(s->tile_block),
                          s->lds_grad, s->mesh->stream, ea, eb, 0, m, Win, s->G, s->PG, gc);
     });
   }
   static vcx_status grad_complete(vcx_solver s) {
-    const DevMesh& m = grad_mesh(s);
-    if (m.nshared == 0) return VCX_OK;
+    const DevMesh& m = s->mesh->d;
+    if (m.nshared == 0 || s->ngrad) return VCX_OK;
     return launch(s, "gradient_shared", [&](hipEvent_t ea, hipEvent_t eb) {
       hipExtLaunchKernelGGL((k_grad_shared<ND, NGF>), dim3((m.nshared + kGradSharedNodes - 1) / kGradSharedNodes),
                             dim3(256), 0, s->mesh->stream, ea, eb, 0, m, (const double*)s->PG, s->G);
@@ -467,8 +463,8 @@ struct Impl {
   }
   static vcx_status batch_stage_simplex(const BatchRun& br, hipStream_t stream, const BatchStage& st, bool prof) {
     vcx_solver s = br.lead;
-    // multi-species: G is completed on the shared nodes before the flux pass,
-    // as in the single solve
+    // multi-species: the node-gradient pass leaves G complete, as in the
+    // single solve
     FinishShared fs{dt_coef(s->ph), mix_params(s->ph), s->ph.closure, br.fused ? 1 : 0, MODEL == 2 ? 1 : 0};
     if constexpr (FUSABLE) {
       if (br.fused) {
@@ -485,17 +481,18 @@ struct Impl {
         });
       }
     }
-    VCX_TRY(launch_on(s, stream, prof, "gradient", [&](hipEvent_t ea, hipEvent_t eb) {
-      hipExtLaunchKernelGGL((k_grad_tile_batch<ND, NGF>), dim3(xcd_grid(br.ngrad_blocks)),
-                         dim3(br.grad_block), br.lds_grad, stream, ea, eb, 0, (const BatchEntry*)br.tab,
-                         (const int2*)br.grad_map, br.ngrad_blocks, st);
-    }));
     if constexpr (MODEL == 2) {
-      if (br.ngsh_blocks > 0)
-        VCX_TRY(launch_on(s, stream, prof, "gradient_shared", [&](hipEvent_t ea, hipEvent_t eb) {
-          hipExtLaunchKernelGGL((k_grad_shared_batch<ND, NGF>), dim3(br.ngsh_blocks), dim3(256), 0, stream, ea,
-                                eb, 0, (const BatchEntry*)br.tab, (const int2*)br.gsh_map);
-        }));
+      VCX_TRY(launch_on(s, stream, prof, "gradient", [&](hipEvent_t ea, hipEvent_t eb) {
+        hipExtLaunchKernelGGL((k_grad_node_batch<ND, NGF>), dim3(xcd_grid(br.ngrad_blocks)), dim3(256), 0,
+                              stream, ea, eb, 0, (const BatchEntry*)br.tab, (const int2*)br.grad_map,
+                              br.ngrad_blocks, st);
+      }));
+    } else {
+      VCX_TRY(launch_on(s, stream, prof, "gradient", [&](hipEvent_t ea, hipEvent_t eb) {
+        hipExtLaunchKernelGGL((k_grad_tile_batch<ND, NGF>), dim3(xcd_grid(br.ntile_blocks)),
+                           dim3(br.tile_block), br.lds_grad, stream, ea, eb, 0, (const BatchEntry*)br.tab,
+                           (const int2*)br.tile_map, br.ntile_blocks, st);
+      }));
     }
     if constexpr (MODEL == 0) {
       GasParams gp{s->ph.gamma, s->ph.beta, s->ph.entropy_fix, s->ph.limiter};
@@ -569,8 +566,9 @@ inline Finish make_finish(vcx_solver s) {
   f.mix = mix_params(s->ph);
   f.closure = s->ph.closure;
   // fused passes with a closure that reads gradients complete G on every
-  // node; the multi-species flux launcher completes it before its pass, so
-  // its flux pass and shared-node update read G
+  // node; so does the multi-species gradient (the node-gradient pass, or the
+  // flux launcher's completion before its pass), so that its flux pass and
+  // shared-node update read G
   f.gfull = (s->fused && s->gout != nullptr) || s->ph.model == VCX_MODEL_NAVIER_STOKES;
   return f;
 }
@@ -588,8 +586,8 @@ const KernelTable* pick_table_quad(const vcx_physics& ph);
 vcx_status check_physics(vcx_mesh mesh, const vcx_physics& ph, const double* E, const KernelTable** kt);
 // tile-edge tables of a mesh (host build and device upload, once)
 vcx_status ensure_tile_edges(vcx_mesh m);
-// Build (host) and upload (device) the gradient tiling of a mesh, once.
-vcx_status ensure_grad_tiles(vcx_mesh m);
+// Build (host) and upload (device) the node-gradient tables of a mesh, once.
+vcx_status ensure_node_gradient(vcx_mesh m);
 // host-side configuration of a solver: sizes, LDS, fused pass, launch shapes
 vcx_status configure_solver(vcx_solver s, vcx_mesh mesh, const vcx_physics& ph, const KernelTable* kt);
 }  // namespace vcx

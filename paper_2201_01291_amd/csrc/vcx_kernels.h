@@ -95,6 +95,14 @@ struct DevMesh {
   const uint16_t* ce;        // [nc*ne] (local cell << 4) | (cell-local edge << 1) | reversed
   const int32_t* slot_einc;  // [P+1] CSR into einc
   const uint16_t* einc;      // [2E] (tile edge << 1) | (slot's node is end b)
+  // node gradient (the multi-species gradient pass): per 64-node slice, the
+  // neighbours of each node and their coefficients C_ij, entry k of the
+  // slice's node l at ng_off[slice] + 64 k + l
+  int has_ngrad, ng_nslices;
+  long long ng_total;
+  const long long* ng_off;   // [nslices+1]
+  const int32_t* ng_nbr;     // [total]
+  const double* ng_c;        // [nd][total]
 };
 
 // Per-solve device scalars of the time loop: the state of one step.
@@ -812,6 +820,68 @@ template <int ND, int NR>
 __global__ void __launch_bounds__(256) k_grad_shared(DevMesh m, const double* __restrict__ PG,
                                                      double* __restrict__ G) {
   grad_shared_body<ND, NR>(m, PG, G, (int)blockIdx.x * kGradSharedNodes);
+}
+
+// Node gradient: G_i = -1/(nd nv V_i) sum_j W_j C_ij over the node's
+// neighbours j in ascending order (the cell sum regrouped by neighbour; no
+// partial sums).  A block takes one 64-node slice: each of its four
+// wavefronts takes a quarter of the fields for the slice's 64 nodes (lane =
+// node), so the loads of a neighbour index, its coefficients and a field row
+// are coalesced across the wavefront.
+constexpr int kGradNodeGroups = 4;
+template <int ND, int NR>
+__device__ inline void grad_node_body(const DevMesh& m, const double* __restrict__ W,
+                                      double* __restrict__ G, const GradCtl& ctl, int sl) {
+  constexpr int FG = (NR + kGradNodeGroups - 1) / kGradNodeGroups;
+  if (ctl.lp && !ctl.first_stage && ctl.lp->s[ctl.par].active == 0) return;
+  const int lane = threadIdx.x & 63;
+  const int v0 = (int)(threadIdx.x >> 6) * FG;
+  const int i = sl * 64 + lane;
+  if (i >= m.nn || v0 >= NR) return;
+  const long long o0 = m.ng_off[sl];
+  const int w = (int)((m.ng_off[sl + 1] - o0) >> 6);
+  double acc[FG][ND];
+#pragma unroll
+  for (int f = 0; f < FG; ++f)
+#pragma unroll
+    for (int d = 0; d < ND; ++d) acc[f][d] = 0.0;
+#pragma unroll 2
+  for (int k = 0; k < w; ++k) {
+    const long long q = o0 + (long long)k * 64 + lane;
+    const int j = m.ng_nbr[q];
+    double c[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) c[d] = m.ng_c[(size_t)d * m.ng_total + q];
+#pragma unroll
+    for (int f = 0; f < FG; ++f) {
+      if (v0 + f < NR) {
+        const double wv = W[(size_t)(v0 + f) * m.nn + j];
+#pragma unroll
+        for (int d = 0; d < ND; ++d) acc[f][d] += wv * c[d];
+      }
+    }
+  }
+  const double coef = -m.inv_vol[i] / double(ND * m.nv);
+#pragma unroll
+  for (int f = 0; f < FG; ++f)
+    if (v0 + f < NR)
+#pragma unroll
+      for (int d = 0; d < ND; ++d) G[(size_t)((v0 + f) * ND + d) * m.nn + i] = coef * acc[f][d];
+}
+
+template <int ND, int NR>
+__global__ void __launch_bounds__(256) k_grad_node(DevMesh m, const double* __restrict__ W,
+                                                   double* __restrict__ G, GradCtl ctl) {
+  // in the first stage of a step, block 0 reduces the time-step candidates
+  // and commits (the slices take the other blocks)
+  const int lead = ctl.lp && ctl.first_stage ? 1 : 0;
+  if (lead && blockIdx.x == 0) {
+    step_start(ctl.lp, ctl.par);
+    return;
+  }
+  const int sl = xcd_tile_of((int)blockIdx.x - lead, m.ng_nslices);
+  if (sl >= m.ng_nslices) return;
+  grad_node_body<ND, NR>(m, W, G, ctl, sl);
 }
 
 // ---------------------------------------------------------------------------
@@ -2364,7 +2434,6 @@ __global__ void __launch_bounds__(256) k_cell_dx(DevMesh m, unsigned long long* 
 
 struct BatchEntry {
   DevMesh m;
-  DevMesh mg;       // tiling of the gradient pass and its completion (m, or coarser tiles)
   double* W[2];     // state buffers; the current one is W[(step + phase) & 1]
   double* G;
   double* PG;
@@ -2438,17 +2507,28 @@ __global__ void __launch_bounds__(256) k_grad_tile_batch(const BatchEntry* __res
   const int cur = (st.step + e.phase) & 1;
   const double* Win = st.stage == 1 ? e.W[cur] : e.W[cur ^ 1];
   GradCtl ctl{e.lp, par, st.stage == 1 ? 1 : 0};
-  grad_tile_body<ND, NR>(e.mg, Win, e.G, e.PG, ctl, ml.y, lds);
+  grad_tile_body<ND, NR>(e.m, Win, e.G, e.PG, ctl, ml.y, lds);
 }
 
-// shared-node gradient completion of every solve of a batch (block map:
-// solve, block of kGradSharedNodes shared nodes of its gradient tiling)
+// node gradient of every solve of a batch (block map: solve, node slice;
+// slice -1 is the solve's decision entry)
 template <int ND, int NR>
-__global__ void __launch_bounds__(256) k_grad_shared_batch(const BatchEntry* __restrict__ tab,
-                                                           const int2* __restrict__ map) {
-  const int2 ml = map[blockIdx.x];
+__global__ void __launch_bounds__(256) k_grad_node_batch(const BatchEntry* __restrict__ tab,
+                                                         const int2* __restrict__ map, int nblocks,
+                                                         BatchStage st) {
+  const int g = xcd_tile(nblocks);
+  if (g >= nblocks) return;
+  const int2 ml = map[g];
   const BatchEntry& e = tab[ml.x];
-  grad_shared_body<ND, NR>(e.mg, e.PG, e.G, ml.y * kGradSharedNodes);
+  const int par = (st.step + e.spar) & 1;
+  if (ml.y < 0) {
+    if (st.stage == 1) step_start(e.lp, par);
+    return;
+  }
+  const int cur = (st.step + e.phase) & 1;
+  const double* Win = st.stage == 1 ? e.W[cur] : e.W[cur ^ 1];
+  GradCtl ctl{e.lp, par, st.stage == 1 ? 1 : 0};
+  grad_node_body<ND, NR>(e.m, Win, e.G, ctl, ml.y);
 }
 
 template <int ND, int NSP, int FLUX, typename CT>

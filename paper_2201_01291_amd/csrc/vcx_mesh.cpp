@@ -21,14 +21,6 @@ TileLimits default_tile_limits(int nd) {
   return {128, 96};
 }
 
-#ifndef VCX_GRAD_TILE_CELLS
-#define VCX_GRAD_TILE_CELLS 384
-#endif
-
-TileLimits gradient_tile_limits(TileLimits mesh) {
-  const int c = std::min(VCX_GRAD_TILE_CELLS, 4 * mesh.max_cells);
-  return {c, std::max(c * 3 / 4, mesh.max_nodes)};
-}
 
 namespace {
 
@@ -174,6 +166,85 @@ std::string build_tiling(const HostMesh& m, TileLimits lim, Tiling& out) {
     if (out.node_slot[g + 1] - out.node_slot[g] > 1) out.slot_node[s] = ~g;
   }
 
+  return "";
+}
+
+// Node-gradient tables: neighbours of each node (itself included) in
+// ascending order and C_ij = sum over the cells c holding i and j of S_j^c,
+// accumulated in ascending cell order; then the 64-node slices.
+std::string build_node_gradient(HostMesh& m) {
+  const int nd = m.nd, nv = m.nv;
+  const int64_t nn = m.nn, nc = m.nc;
+  if (nv != nd + 1) return "node-gradient tables are built for simplices";
+  // cells around each node, ascending
+  std::vector<int64_t> cs(nn + 1, 0);
+  for (int64_t c = 0; c < nc; ++c)
+    for (int k = 0; k < nv; ++k) cs[m.cell[(size_t)k * nc + c] + 1]++;
+  for (int64_t i = 0; i < nn; ++i) cs[i + 1] += cs[i];
+  std::vector<int32_t> cells_of((size_t)cs[nn]);
+  {
+    std::vector<int64_t> fill(cs.begin(), cs.end() - 1);
+    for (int64_t c = 0; c < nc; ++c)
+      for (int k = 0; k < nv; ++k) cells_of[fill[m.cell[(size_t)k * nc + c]]++] = (int32_t)c;
+  }
+  // neighbour lists (CSR) and their coefficients
+  std::vector<int64_t> np(nn + 1, 0);
+  std::vector<int32_t> nb;
+  std::vector<int32_t> tmp;
+  for (int64_t i = 0; i < nn; ++i) {
+    tmp.clear();
+    for (int64_t q = cs[i]; q < cs[i + 1]; ++q)
+      for (int k = 0; k < nv; ++k) tmp.push_back(m.cell[(size_t)k * nc + cells_of[q]]);
+    std::sort(tmp.begin(), tmp.end());
+    tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
+    nb.insert(nb.end(), tmp.begin(), tmp.end());
+    np[i + 1] = (int64_t)nb.size();
+  }
+  std::vector<double> cv((size_t)nd * nb.size(), 0.0);  // [entry][nd]
+  for (int64_t i = 0; i < nn; ++i) {
+    const int32_t* row = nb.data() + np[i];
+    const int64_t deg = np[i + 1] - np[i];
+    for (int64_t q = cs[i]; q < cs[i + 1]; ++q) {
+      const int32_t c = cells_of[q];
+      int64_t v[4];
+      for (int k = 0; k < nv; ++k) v[k] = m.cell[(size_t)k * nc + c];
+      double e[3][3], S[4][3];
+      relative_coords(m, m.x.data(), v, m.shift[c], e);
+      node_normals(nd, e, S);
+      for (int k = 0; k < nv; ++k) {
+        const int64_t at = std::lower_bound(row, row + deg, (int32_t)v[k]) - row;
+        for (int d = 0; d < nd; ++d) cv[(size_t)(np[i] + at) * nd + d] += S[k][d];
+      }
+    }
+  }
+  // slices of kNgSlice nodes, padded to the slice's largest count
+  const int W = HostMesh::kNgSlice;
+  const int64_t ns = (nn + W - 1) / W;
+  m.ng_off.assign(ns + 1, 0);
+  for (int64_t sl = 0; sl < ns; ++sl) {
+    int64_t w = 0;
+    for (int64_t i = sl * W; i < std::min(nn, (sl + 1) * W); ++i) w = std::max(w, np[i + 1] - np[i]);
+    m.ng_off[sl + 1] = m.ng_off[sl] + w * W;
+  }
+  const int64_t tot = m.ng_off[ns];
+  m.ng_nbr.assign(tot, 0);
+  m.ng_c.assign((size_t)nd * tot, 0.0);
+  for (int64_t sl = 0; sl < ns; ++sl) {
+    const int64_t w = (m.ng_off[sl + 1] - m.ng_off[sl]) / W;
+    for (int l = 0; l < W; ++l) {
+      const int64_t i = sl * W + l;
+      for (int64_t k = 0; k < w; ++k) {
+        const int64_t at = m.ng_off[sl] + k * W + l;
+        if (i < nn && k < np[i + 1] - np[i]) {
+          m.ng_nbr[at] = nb[np[i] + k];
+          for (int d = 0; d < nd; ++d) m.ng_c[(size_t)d * tot + at] = cv[(size_t)(np[i] + k) * nd + d];
+        } else {
+          m.ng_nbr[at] = (int32_t)std::min(i, nn - 1);  // C = 0
+        }
+      }
+    }
+  }
+  m.has_ngrad = true;
   return "";
 }
 

@@ -14,11 +14,6 @@ struct TileLimits {
 };
 
 TileLimits default_tile_limits(int nd);
-// Tiles of the multi-species gradient pass, given the mesh's: up to four
-// times larger (at most 384 cells), so that a node has fewer slots (partial
-// sums to write and to gather) while the pass, which stages a few fields at
-// a time, still fits three blocks' LDS on a CU.
-TileLimits gradient_tile_limits(TileLimits mesh);
 
 // A tiling of the cells (consecutive cells in the internal order, each tile
 // closed at max_cells cells or max_nodes distinct nodes) with its slot tables:
@@ -114,11 +109,18 @@ struct HostMesh {
   std::vector<uint16_t> einc;      // [2E] per slot: (tile edge << 1) | (1 if the slot's node is end b)
   int max_tile_edges = 0;
 
-  // a coarser tiling for the gradient pass of the multi-species model (built
-  // on demand): fewer tiles per node, so fewer partial sums to write and
-  // gather, while its LDS per tile stays small
-  bool has_gtiles = false;
-  Tiling gt;
+  // node gradient (the multi-species gradient pass; built on demand by
+  // build_node_gradient): for each node i its neighbours j, the nodes of its
+  // cells with i itself, ascending, and C_ij, the sum of the node normals
+  // S_j of the cells holding both i and j, so that the cell-sum gradient is
+  // G_i = -1/(nd nv V_i) sum_j W_j C_ij.  Nodes in slices of 64 (one per
+  // wavefront), each slice padded to its largest neighbour count (pad
+  // entries: j = i, C = 0); entry k of the slice's node l at off + 64 k + l.
+  static constexpr int kNgSlice = 64;
+  bool has_ngrad = false;
+  std::vector<int64_t> ng_off;  // [nslices + 1]
+  std::vector<int32_t> ng_nbr;  // [total]
+  std::vector<double> ng_c;     // [nd][total]
 
   int64_t ntiles() const { return (int64_t)tile_cell.size() - 1; }
   int64_t nslots() const { return (int64_t)slot_node.size(); }
@@ -126,6 +128,9 @@ struct HostMesh {
 
 // Tile the cells of a preprocessed mesh; returns "" or an error message.
 std::string build_tiling(const HostMesh& m, TileLimits lim, Tiling& t);
+
+// Node-gradient tables of a preprocessed simplex mesh (HostMesh::ng_*).
+std::string build_node_gradient(HostMesh& m);
 
 // Returns "" on success, else an error message; *code receives the status
 // (-1 argument, -2 mesh).

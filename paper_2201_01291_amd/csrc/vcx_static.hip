@@ -63,12 +63,11 @@ extern "C" vcx_status vcx_residual_noalloc(vcx_mesh mesh, const vcx_physics* phy
   VCX_TRY(configure_solver(&s, mesh, ph, kt));
   const DevMesh& d = mesh->d;
   const size_t nn = (size_t)d.nn, P = (size_t)d.nslots;
-  const size_t PGS = std::max<size_t>(P, (size_t)grad_mesh(&s).nslots);  // slots of the gradient partials
   const bool dd = ph.model == VCX_MODEL_DRIFT_DIFFUSION;
   // required doubles, each array rounded up to 256 bytes
   auto rnd = [](size_t n) { return (std::max<size_t>(n, 1) + 31) / 32 * 32; };
   const size_t need = rnd((size_t)s.nw * nn) + rnd((size_t)s.ngf * s.nd * nn) +
-                      rnd((size_t)s.ngf * s.nd * PGS) + rnd((size_t)s.nvar * P) + rnd((size_t)s.nvar * nn) +
+                      rnd((size_t)s.ngf * s.nd * P) + rnd((size_t)s.nvar * P) + rnd((size_t)s.nvar * nn) +
                       (dd ? rnd((size_t)s.nd * nn) : 0) +
                       (ph.closure == 2 && d.nb > 0 ? rnd((size_t)d.nb * s.nvar) : 0);
   if (need > kScratchDoubles)
@@ -81,7 +80,7 @@ extern "C" vcx_status vcx_residual_noalloc(vcx_mesh mesh, const vcx_physics* phy
   s.W[0] = carve(base, off, (size_t)s.nw * nn);
   s.cur = 0;
   s.G = carve(base, off, (size_t)s.ngf * s.nd * nn);
-  s.PG = carve(base, off, (size_t)s.ngf * s.nd * PGS);
+  s.PG = carve(base, off, (size_t)s.ngf * s.nd * P);
   s.PR = carve(base, off, (size_t)s.nvar * P);
   s.rbuf = carve(base, off, (size_t)s.nvar * nn);
   if (dd) s.E = carve(base, off, (size_t)s.nd * nn);
