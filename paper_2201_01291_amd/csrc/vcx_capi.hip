@@ -90,34 +90,6 @@ extern "C" vcx_status vcx_mesh_create(int ndim, int64_t nnodes, const double* xy
   return vcx_mesh_create_tiled(ndim, nnodes, xyz, ncells, nv, cells, period, 0, 0, stream, out);
 }
 
-// Build (host) and upload (device) the node-gradient tables of a simplex
-// mesh, once (the host copies are released after the upload).
-vcx_status vcx::ensure_node_gradient(vcx_mesh m) {
-  if (m->d.has_ngrad) return VCX_OK;
-  HostMesh& h = m->h;
-  if (h.nv != h.nd + 1) return VCX_OK;
-  std::string err = build_node_gradient(h);
-  if (!err.empty()) return fail(VCX_E_MESH, err);
-  DevMesh& d = m->d;
-  const int64_t* off = nullptr;
-  const int32_t* nbr = nullptr;
-  const double* c = nullptr;
-  VCX_TRY(upload(m, h.ng_off, &off));
-  VCX_TRY(upload(m, h.ng_nbr, &nbr));
-  VCX_TRY(upload(m, h.ng_c, &c));
-  VCX_HIP(hipStreamSynchronize(m->stream));
-  d.ng_off = reinterpret_cast<const long long*>(off);
-  d.ng_nbr = nbr;
-  d.ng_c = c;
-  d.ng_nslices = (int)(h.ng_off.size() - 1);
-  d.ng_total = (long long)h.ng_off.back();
-  d.has_ngrad = 1;
-  std::vector<int64_t>().swap(h.ng_off);
-  std::vector<int32_t>().swap(h.ng_nbr);
-  std::vector<double>().swap(h.ng_c);
-  return VCX_OK;
-}
-
 static vcx_status create_mesh(int ndim, int64_t nnodes, const double* xyz, int64_t ncells, int nv,
                               const int64_t* cells, const double* period, int max_tile_cells,
                               int max_tile_nodes, void* stream, bool axi, vcx_mesh* out);
@@ -147,9 +119,39 @@ extern "C" vcx_status vcx_mesh_create_axisymmetric_nv(int64_t nnodes, const doub
                      out);
 }
 
-// Build (host) and upload (device) the tile-edge tables of a mesh, once.
+// Build (host) and upload (device) the node-gradient tables of a simplex
+// mesh, once (the host copies are released after the upload).
+static vcx_status ensure_node_gradient(vcx_mesh m) {
+  if (m->d.has_ngrad) return VCX_OK;
+  HostMesh& h = m->h;
+  std::string err = build_node_gradient(h);
+  if (!err.empty()) return fail(VCX_E_MESH, err);
+  DevMesh& d = m->d;
+  const int64_t* off = nullptr;
+  const int32_t* nbr = nullptr;
+  const double* c = nullptr;
+  VCX_TRY(upload(m, h.ng_off, &off));
+  VCX_TRY(upload(m, h.ng_nbr, &nbr));
+  VCX_TRY(upload(m, h.ng_c, &c));
+  VCX_HIP(hipStreamSynchronize(m->stream));
+  d.ng_off = reinterpret_cast<const long long*>(off);
+  d.ng_nbr = nbr;
+  d.ng_c = c;
+  d.ng_nslices = (int)(h.ng_off.size() - 1);
+  d.ng_total = (long long)h.ng_off.back();
+  d.has_ngrad = 1;
+  std::vector<int64_t>().swap(h.ng_off);
+  std::vector<int32_t>().swap(h.ng_nbr);
+  std::vector<double>().swap(h.ng_c);
+  return VCX_OK;
+}
+
+// Build (host) and upload (device) the tables of the multi-species passes
+// of a simplex mesh, once: tile edges (flux pass) and node gradient.
 vcx_status vcx::ensure_tile_edges(vcx_mesh m) {
   if (m->d.has_edges) return VCX_OK;
+  if (m->h.nv != m->h.nd + 1) return fail(VCX_E_ARG, "the multi-species model runs on simplex meshes");
+  VCX_TRY(ensure_node_gradient(m));
   std::string err = build_tile_edges(m->h);
   if (!err.empty()) return fail(VCX_E_MESH, err);
   const HostMesh& h = m->h;
@@ -553,13 +555,11 @@ vcx_status vcx::configure_solver(vcx_solver s, vcx_mesh mesh, const vcx_physics&
   s->ngf = kt->ngf;
   s->kt = kt;
   const DevMesh& d = mesh->d;
-  // multi-species: the node-gradient pass where the mesh has its tables
-  // (built by the first solver of that model), else gradient tiles and the
-  // shared-node completion
-  s->ngrad = ph.model == VCX_MODEL_NAVIER_STOKES && d.has_ngrad;
-  s->lds_grad = s->ngrad ? 0 : kt->lds_grad(d.max_tile_nodes, d.max_tile_cells);
-  if (ph.model == VCX_MODEL_NAVIER_STOKES && !d.has_edges)
-    return fail(VCX_E_ARG, "the mesh has no tile-edge tables (created by the first Navier-Stokes solver)");
+  // (the multi-species node-gradient pass takes no dynamic LDS)
+  s->lds_grad = ph.model == VCX_MODEL_NAVIER_STOKES ? 0 : kt->lds_grad(d.max_tile_nodes, d.max_tile_cells);
+  if (ph.model == VCX_MODEL_NAVIER_STOKES && !(d.has_edges && d.has_ngrad))
+    return fail(VCX_E_ARG, "the mesh has no tile-edge and node-gradient tables (created by the first "
+                           "Navier-Stokes solver)");
   s->lds_flux = kt->lds_flux(d, ph.predictor);
   if (s->lds_grad > (size_t)mesh->lds_max || s->lds_flux > (size_t)mesh->lds_max) {
     const size_t need = std::max(s->lds_grad, s->lds_flux);
@@ -605,10 +605,7 @@ extern "C" vcx_status vcx_solver_create(vcx_mesh mesh, const vcx_physics* phys, 
   const int nd = mesh->h.nd;
   const KernelTable* kt = nullptr;
   VCX_TRY(check_physics(mesh, ph, E, &kt));
-  if (ph.model == VCX_MODEL_NAVIER_STOKES) {
-    VCX_TRY(ensure_tile_edges(mesh));
-    VCX_TRY(ensure_node_gradient(mesh));
-  }
+  if (ph.model == VCX_MODEL_NAVIER_STOKES) VCX_TRY(ensure_tile_edges(mesh));
   vcx_solver s = new (std::nothrow) vcx_solver_s();
   if (!s) return fail(VCX_E_OOM, "host allocation failed");
   {
@@ -736,6 +733,19 @@ extern "C" vcx_status vcx_gradient(vcx_solver s, double* G, int is_device) {
   GradCtl gc{nullptr, 0, 0};
   VCX_TRY(s->kt->grad(s, s->W[s->cur], gc));
   VCX_TRY(s->kt->grad_complete(s));
+  if (s->ph.model == VCX_MODEL_NAVIER_STOKES) {
+    // node-major gradient rows: their first nr * nd components
+    const int nn = s->mesh->d.nn;
+    double* target = is_device ? G : s->io;
+    hipLaunchKernelGGL(k_scatter_node_rows, dim3((nn + 255) / 256), dim3(256), 0, s->mesh->stream,
+                       s->mesh->d.perm, (const double*)s->G, target, nn, s->nr * s->nd, s->ngf * s->nd);
+    VCX_HIP(hipGetLastError());
+    if (!is_device)
+      VCX_HIP(hipMemcpyAsync(G, s->io, sizeof(double) * (size_t)s->nr * s->nd * nn, hipMemcpyDeviceToHost,
+                             s->mesh->stream));
+    VCX_HIP(hipStreamSynchronize(s->mesh->stream));
+    return VCX_OK;
+  }
   return copy_out(s, s->G, (size_t)s->nr * s->nd, G, is_device);
 }
 
@@ -992,9 +1002,6 @@ vcx_status vcx::batch_set(BatchGroup* g, vcx_solver* ss, int n, const int* steps
                   (ss[i]->ph.model == VCX_MODEL_DRIFT_DIFFUSION && ss[i]->ph.flux == VCX_FLUX_SG)))
       return fail(VCX_E_ARG, "solvers on axisymmetric meshes, with the interpolated closure, the "
                              "predictor or the Scharfetter-Gummel flux are not batched");
-  for (int i = 0; i < n; ++i)
-    if (ss[i] && ss[i]->ph.model == VCX_MODEL_NAVIER_STOKES && !ss[i]->ngrad)
-      return fail(VCX_E_ARG, "multi-species solvers are batched with the node-gradient pass");
   g->mem.assign(ss, ss + n);
   g->q = 0;
   if (n == 0) return VCX_OK;
@@ -1016,7 +1023,7 @@ vcx_status vcx::batch_set(BatchGroup* g, vcx_solver* ss, int n, const int* steps
     g->phase0[i] = s->cur;
     g->spar0[i] = s->spar;
     for (int t = 0; t < s->mesh->d.ntiles; ++t) tmap.push_back(make_int2(i, t));
-    if (s->ngrad)
+    if (s->ph.model == VCX_MODEL_NAVIER_STOKES)
       for (int b = 0; b < s->mesh->d.ng_nslices; ++b) gmap.push_back(make_int2(i, b));
     for (int b = 0; b < s->nsh_blocks; ++b) smap.push_back(make_int2(i, b));
     lg = std::max(lg, s->lds_grad);

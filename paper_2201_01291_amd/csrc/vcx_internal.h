@@ -83,7 +83,6 @@ struct vcx_solver_s {
   double* gout = nullptr;  // fused passes: node gradients for the boundary closure, or null
   double* cbuf = nullptr;  // second closure option: [nb][nvar] closure fluxes of the stage input
   int tile_block = 256;
-  bool ngrad = false;    // multi-species: the node-gradient pass (complete G, no partial sums)
   int flux_block = 256;  // block of the flux tile pass (multi-species: covers the tile's edges)
   size_t bytes = 0;  // device bytes held by the solver (mesh excluded)
   // profiling
@@ -267,21 +266,25 @@ struct Impl {
   static vcx_status grad(vcx_solver s, const double* Win, const GradCtl& gc) {
     const DevMesh& m = s->mesh->d;
     const int lead = gc.lp && gc.first_stage ? 1 : 0;
-    if constexpr (MODEL == 2 && SIMPLEX) {
-      if (s->ngrad)
+    if constexpr (MODEL == 2) {
+      // multi-species: the node-gradient pass (node-major G, complete)
+      if constexpr (SIMPLEX)
         return launch(s, "gradient", [&](hipEvent_t ea, hipEvent_t eb) {
           hipExtLaunchKernelGGL((k_grad_node<ND, NGF>), dim3(xcd_grid(m.ng_nslices) + lead), dim3(256), 0,
                                 s->mesh->stream, ea, eb, 0, m, Win, s->G, gc);
         });
+      else
+        return vcx::fail(VCX_E_ARG, "the multi-species model runs on simplex meshes");
+    } else {
+      return launch(s, "gradient", [&](hipEvent_t ea, hipEvent_t eb) {
+        hipExtLaunchKernelGGL((k_grad_tile<ND, NGF, NV>), dim3(xcd_grid(m.ntiles) + lead), dim3(s->tile_block),
+                              s->lds_grad, s->mesh->stream, ea, eb, 0, m, Win, s->G, s->PG, gc);
+      });
     }
-    return launch(s, "gradient", [&](hipEvent_t ea, hipEvent_t eb) {
-      hipExtLaunchKernelGGL((k_grad_tile<ND, NGF, NV>), dim3(xcd_grid(m.ntiles) + lead), dim3(s->tile_block),
-                         s->lds_grad, s->mesh->stream, ea, eb, 0, m, Win, s->G, s->PG, gc);
-    });
   }
   static vcx_status grad_complete(vcx_solver s) {
     const DevMesh& m = s->mesh->d;
-    if (m.nshared == 0 || s->ngrad) return VCX_OK;
+    if (m.nshared == 0 || MODEL == 2) return VCX_OK;
     return launch(s, "gradient_shared", [&](hipEvent_t ea, hipEvent_t eb) {
       hipExtLaunchKernelGGL((k_grad_shared<ND, NGF>), dim3((m.nshared + kGradSharedNodes - 1) / kGradSharedNodes),
                             dim3(256), 0, s->mesh->stream, ea, eb, 0, m, (const double*)s->PG, s->G);
@@ -328,21 +331,17 @@ struct Impl {
       });
     } else if constexpr (MODEL == 2) {
       GasParams gp{s->ph.gamma, s->ph.beta, s->ph.entropy_fix, s->ph.limiter};
-      // complete G on the shared nodes once, so that every tile stages its
-      // slots' gradient rows from G instead of summing the partials per slot
-      VCX_TRY(grad_complete(s));
-      Finish fg = f;
-      fg.gfull = 1;
+      // (the node-gradient pass has left G complete and node-major)
       if constexpr (ND == 2) {
         if (m.axi)
           return launch(s, "flux", [&](hipEvent_t ea, hipEvent_t eb) {
             hipExtLaunchKernelGGL((k_flux_ns<ND, NSP, CT, true>), dim3(xcd_grid(m.ntiles)), dim3(s->flux_block),
-                                  s->lds_flux, st, ea, eb, 0, m, Win, (const double*)s->G, s->PR, gp, fg);
+                                  s->lds_flux, st, ea, eb, 0, m, Win, (const double*)s->G, s->PR, gp, f);
           });
       }
       return launch(s, "flux", [&](hipEvent_t ea, hipEvent_t eb) {
         hipExtLaunchKernelGGL((k_flux_ns<ND, NSP, CT>), dim3(xcd_grid(m.ntiles)), dim3(s->flux_block),
-                           s->lds_flux, st, ea, eb, 0, m, Win, (const double*)s->G, s->PR, gp, fg);
+                           s->lds_flux, st, ea, eb, 0, m, Win, (const double*)s->G, s->PR, gp, f);
       });
     } else {
       DDParams pp{};
@@ -566,9 +565,7 @@ inline Finish make_finish(vcx_solver s) {
   f.mix = mix_params(s->ph);
   f.closure = s->ph.closure;
   // fused passes with a closure that reads gradients complete G on every
-  // node; so does the multi-species gradient (the node-gradient pass, or the
-  // flux launcher's completion before its pass), so that its flux pass and
-  // shared-node update read G
+  // node; so does the multi-species node-gradient pass
   f.gfull = (s->fused && s->gout != nullptr) || s->ph.model == VCX_MODEL_NAVIER_STOKES;
   return f;
 }
@@ -585,9 +582,10 @@ const KernelTable* pick_table_quad(const vcx_physics& ph);
 // validate physics against a mesh and pick its table (vcx_capi.hip)
 vcx_status check_physics(vcx_mesh mesh, const vcx_physics& ph, const double* E, const KernelTable** kt);
 // tile-edge tables of a mesh (host build and device upload, once)
+// Build (host) and upload (device) the tables of the multi-species passes
+// (tile edges, node gradient) of a mesh, once.
 vcx_status ensure_tile_edges(vcx_mesh m);
-// Build (host) and upload (device) the node-gradient tables of a mesh, once.
-vcx_status ensure_node_gradient(vcx_mesh m);
+
 // host-side configuration of a solver: sizes, LDS, fused pass, launch shapes
 vcx_status configure_solver(vcx_solver s, vcx_mesh mesh, const vcx_physics& ph, const KernelTable* kt);
 }  // namespace vcx

@@ -827,46 +827,57 @@ __global__ void __launch_bounds__(256) k_grad_shared(DevMesh m, const double* __
 // partial sums).  A block takes one 64-node slice: each of its four
 // wavefronts takes a quarter of the fields for the slice's 64 nodes (lane =
 // node), so the loads of a neighbour index, its coefficients and a field row
-// are coalesced across the wavefront.
+// are coalesced across the wavefront.  G is node-major (the NR * ND
+// components of a node contiguous, component v * ND + d): the block gathers
+// the slice's rows in LDS and writes them as one contiguous run.
 constexpr int kGradNodeGroups = 4;
 template <int ND, int NR>
 __device__ inline void grad_node_body(const DevMesh& m, const double* __restrict__ W,
                                       double* __restrict__ G, const GradCtl& ctl, int sl) {
-  constexpr int FG = (NR + kGradNodeGroups - 1) / kGradNodeGroups;
+  constexpr int FG = (NR + kGradNodeGroups - 1) / kGradNodeGroups, NC = NR * ND, LD = NC + 1;
+  __shared__ double sg[64 * LD];
   if (ctl.lp && !ctl.first_stage && ctl.lp->s[ctl.par].active == 0) return;
   const int lane = threadIdx.x & 63;
   const int v0 = (int)(threadIdx.x >> 6) * FG;
   const int i = sl * 64 + lane;
-  if (i >= m.nn || v0 >= NR) return;
-  const long long o0 = m.ng_off[sl];
-  const int w = (int)((m.ng_off[sl + 1] - o0) >> 6);
-  double acc[FG][ND];
+  const int nb = min(64, m.nn - sl * 64);  // nodes of this slice
+  if (lane < nb && v0 < NR) {
+    const long long o0 = m.ng_off[sl];
+    const int w = (int)((m.ng_off[sl + 1] - o0) >> 6);
+    double acc[FG][ND];
 #pragma unroll
-  for (int f = 0; f < FG; ++f)
+    for (int f = 0; f < FG; ++f)
 #pragma unroll
-    for (int d = 0; d < ND; ++d) acc[f][d] = 0.0;
+      for (int d = 0; d < ND; ++d) acc[f][d] = 0.0;
 #pragma unroll 2
-  for (int k = 0; k < w; ++k) {
-    const long long q = o0 + (long long)k * 64 + lane;
-    const int j = m.ng_nbr[q];
-    double c[ND];
+    for (int k = 0; k < w; ++k) {
+      const long long q = o0 + (long long)k * 64 + lane;
+      const int j = m.ng_nbr[q];
+      double c[ND];
 #pragma unroll
-    for (int d = 0; d < ND; ++d) c[d] = m.ng_c[(size_t)d * m.ng_total + q];
+      for (int d = 0; d < ND; ++d) c[d] = m.ng_c[(size_t)d * m.ng_total + q];
 #pragma unroll
-    for (int f = 0; f < FG; ++f) {
-      if (v0 + f < NR) {
-        const double wv = W[(size_t)(v0 + f) * m.nn + j];
+      for (int f = 0; f < FG; ++f) {
+        if (v0 + f < NR) {
+          const double wv = W[(size_t)(v0 + f) * m.nn + j];
 #pragma unroll
-        for (int d = 0; d < ND; ++d) acc[f][d] += wv * c[d];
+          for (int d = 0; d < ND; ++d) acc[f][d] += wv * c[d];
+        }
       }
     }
+    const double coef = -m.inv_vol[i] / double(ND * m.nv);
+#pragma unroll
+    for (int f = 0; f < FG; ++f)
+      if (v0 + f < NR)
+#pragma unroll
+        for (int d = 0; d < ND; ++d) sg[lane * LD + (v0 + f) * ND + d] = coef * acc[f][d];
   }
-  const double coef = -m.inv_vol[i] / double(ND * m.nv);
-#pragma unroll
-  for (int f = 0; f < FG; ++f)
-    if (v0 + f < NR)
-#pragma unroll
-      for (int d = 0; d < ND; ++d) G[(size_t)((v0 + f) * ND + d) * m.nn + i] = coef * acc[f][d];
+  __syncthreads();
+  double* out = G + (size_t)sl * 64 * NC;
+  for (int idx = threadIdx.x; idx < nb * NC; idx += blockDim.x) {
+    const int l = idx / NC;
+    out[idx] = sg[l * LD + (idx - l * NC)];
+  }
 }
 
 template <int ND, int NR>
@@ -1005,39 +1016,22 @@ __device__ inline void closure_flux(const DevMesh& m, const Finish& f, int k, bo
 // Axisymmetric multi-species: the hoop stress tau_theta_theta of node i,
 // 2 eta u_r/r + lambda (u_r/r + du_r/dr + du_x/dx) with lambda = -2/3 eta
 // (Stokes), u_r/r taking its limit du_r/dr on the axis.  The two velocity
-// derivatives come from the node's gradient: G for a node inside one tile or
-// once G is complete, else the sum of its tile partials (run of PG), as the
-// gradient pass leaves them.
+// derivatives come from the node's (node-major) gradient row.
 template <int ND, int NSP>
-__device__ inline double ns_hoop_stress(const DevMesh& m, const Finish& f, int i, bool shared, int2 run) {
+__device__ inline double ns_hoop_stress(const DevMesh& m, const Finish& f, int i) {
   constexpr int NVAR = 2 + ND + NSP, NR = NVAR + 1, NP = ND + 1 + NSP, NC = (NR + NP) * ND;
   constexpr int CR = (NR + 1) * ND + 1, CX = NR * ND;  // du_r/dr, du_x/dx
-  double durdr, duxdx;
-  if (!shared || f.gfull) {
-    durdr = f.G[(size_t)CR * m.nn + i];
-    duxdx = f.G[(size_t)CX * m.nn + i];
-  } else {
-    double a = 0.0, b = 0.0;
-    for (int p = run.x; p < run.y; ++p) {
-      a += f.PG[(size_t)p * NC + CR];
-      b += f.PG[(size_t)p * NC + CX];
-    }
-    const double coef = -m.inv_vol[i] / double(ND * m.nv);
-    durdr = coef * a;
-    duxdx = coef * b;
-  }
+  const double durdr = f.G[(size_t)i * NC + CR];
+  const double duxdx = f.G[(size_t)i * NC + CX];
   const double eta = f.Win[(size_t)(NR + NP + 1) * m.nn + i], ur = f.Win[(size_t)(NR + 1) * m.nn + i];
   const double rr = m.x[(size_t)m.nn + i];
   const double hoop = rr > 0.0 ? ur / rr : durdr;
   return 2.0 * eta * hoop - 2.0 / 3.0 * eta * (hoop + durdr + duxdx);
 }
 
-// run: for a node split over tiles, its run of gradient partials (used by
-// the axisymmetric multi-species source)
 template <int ND, int NSP, int MODEL, int NVAR>
 __device__ inline double finish_node(const DevMesh& m, const Finish& f, int i, bool shared,
-                                     double (&r)[NVAR], const NodeIn<NVAR, ND>& ni,
-                                     int2 run = make_int2(0, 0)) {
+                                     double (&r)[NVAR], const NodeIn<NVAR, ND>& ni) {
   if (f.closure && m.nb > 0) {
     const int bi = m.bnd_index[i];
     if (bi >= 0) {
@@ -1065,7 +1059,7 @@ __device__ inline double finish_node(const DevMesh& m, const Finish& f, int i, b
       // velocity is set to zero on the axis after it
       r[2] -= f.Win[(size_t)NVAR * m.nn + i] * m.vnode[i];
       // multi-species: its diffusive part, minus the hoop stress
-      if constexpr (MODEL == 2) r[2] += ns_hoop_stress<ND, NSP>(m, f, i, shared, run) * m.vnode[i];
+      if constexpr (MODEL == 2) r[2] += ns_hoop_stress<ND, NSP>(m, f, i) * m.vnode[i];
       on_axis = m.x[(size_t)m.nn + i] == 0.0;
     }
   }
@@ -1913,58 +1907,20 @@ __global__ void VCX_FUSED_BOUNDS k_fused(DevMesh m, const double* __restrict__ W
 // first NR + NP rows.
 // ---------------------------------------------------------------------------
 
-// Stage gradient components [C0, C0 + NCS) of the NC components of a node
-// into LDS (sG [NCS][maxn]): from G for a tile-owned node, or the sum of the
-// slot partials of a shared node in ascending partial order (the same for
-// every reader).
-template <int NC, int C0, int NCS, int ND, typename CT>
-__device__ inline void stage_gradient_part(const DevMesh& m, const double* __restrict__ G,
-                                           const double* __restrict__ PG, int sv, int2 run, CT* sG,
-                                           int maxn, int q) {
-  if (sv >= 0) {
-    constexpr int JC = NCS <= 32 ? NCS : 16;
-    for (int j0 = 0; j0 < NCS; j0 += JC) {
-      double v[JC];
-#pragma unroll
-      for (int jj = 0; jj < JC; ++jj)
-        if (j0 + jj < NCS) v[jj] = G[(size_t)(C0 + j0 + jj) * m.nn + sv];
-#pragma unroll
-      for (int jj = 0; jj < JC; ++jj)
-        if (j0 + jj < NCS) sG[(j0 + jj) * maxn + q] = CT(v[jj]);
-    }
-    return;
-  }
-  const int g = ~sv;
-  const double coef = -m.inv_vol[g] / double(ND * m.nv);
-  constexpr int JC = NCS <= 24 ? NCS : 12;
+// Gradient components [C0, C0 + NCS) of node g from the node-major G (NC
+// components per node, contiguous) into LDS (sG [NCS][maxn]).
+template <int NC, int C0, int NCS, typename CT>
+__device__ inline void stage_gradient_row(const double* __restrict__ G, int g, CT* sG, int maxn, int q) {
+  const double* src = G + (size_t)g * NC + C0;
+  constexpr int JC = NCS <= 32 ? NCS : 16;
   for (int j0 = 0; j0 < NCS; j0 += JC) {
-    double acc[JC];
-#pragma unroll
-    for (int jj = 0; jj < JC; ++jj) acc[jj] = 0.0;
-    int p = run.x;
-    for (; p + 1 < run.y; p += 2) {
-      const double* s0 = PG + (size_t)p * NC + C0 + j0;
-      const double* s1 = s0 + NC;
-      double a[JC], b[JC];
-#pragma unroll
-      for (int jj = 0; jj < JC; ++jj)
-        if (j0 + jj < NCS) {
-          a[jj] = s0[jj];
-          b[jj] = s1[jj];
-        }
-#pragma unroll
-      for (int jj = 0; jj < JC; ++jj)
-        if (j0 + jj < NCS) acc[jj] = (acc[jj] + a[jj]) + b[jj];
-    }
-    if (p < run.y) {
-      const double* s0 = PG + (size_t)p * NC + C0 + j0;
-#pragma unroll
-      for (int jj = 0; jj < JC; ++jj)
-        if (j0 + jj < NCS) acc[jj] += s0[jj];
-    }
+    double v[JC];
 #pragma unroll
     for (int jj = 0; jj < JC; ++jj)
-      if (j0 + jj < NCS) sG[(j0 + jj) * maxn + q] = CT(coef * acc[jj]);
+      if (j0 + jj < NCS) v[jj] = src[j0 + jj];
+#pragma unroll
+    for (int jj = 0; jj < JC; ++jj)
+      if (j0 + jj < NCS) sG[(j0 + jj) * maxn + q] = CT(v[jj]);
   }
 }
 
@@ -2035,8 +1991,7 @@ __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ W,
       for (int d = 0; d < ND; ++d) xx[d] = m.x[(size_t)d * m.nn + g];
       stage_rows<NR, CT>(W, m.nn, g, 0, sW, 0, maxn, q);
       stage_rows<1, CT>(W, m.nn, g, NR + NP, sW, NR, maxn, q);
-      // (with G complete on shared nodes too, every slot reads its node's row)
-      stage_gradient_part<NC, 0, CA, ND, CT>(m, G, f.PG, f.gfull ? g : sv, m.slot_run[sl], sG, maxn, q);
+      stage_gradient_row<NC, 0, CA, CT>(G, g, sG, maxn, q);
 #pragma unroll
       for (int d = 0; d < ND; ++d) sX[d * maxn + q] = xx[d];
     }
@@ -2131,7 +2086,7 @@ __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ W,
         stage_rows<2, CT>(W, m.nn, g, NR + NP + 1, sW, 1 + NP, maxn, q);
       else
         stage_rows<NA - 1, CT>(W, m.nn, g, NR + NP + 1, sW, 1 + NP, maxn, q);
-      stage_gradient_part<NC, CA, CB, ND, CT>(m, G, f.PG, f.gfull ? g : sv, m.slot_run[sl], sG, maxn, q);
+      stage_gradient_row<NC, CA, CB, CT>(G, g, sG, maxn, q);
     }
   }
   __syncthreads();
@@ -2321,7 +2276,7 @@ __device__ inline void update_shared_body(const DevMesh& m, const double* __rest
 #pragma unroll
       for (int v = 0; v < NVAR; ++v) r[v] += src[v];
     }
-    cand = finish_node<ND, NSP, MODEL, NVAR>(m, f, i, true, r, ni, run);
+    cand = finish_node<ND, NSP, MODEL, NVAR>(m, f, i, true, r, ni);
   }
   if (f.final_stage && f.sc) {
     const double bm = block_min(cand);
@@ -2636,6 +2591,16 @@ static __global__ void k_gather_rows(const int32_t* __restrict__ perm, const dou
   if (i >= nn) return;
   const int o = perm[i];
   for (int v = 0; v < nrows; ++v) dst[(size_t)v * nn + i] = src[(size_t)v * nn + o];
+}
+
+// the first nrows components of node-major rows (stride per node) into
+// caller-order rows
+static __global__ void k_scatter_node_rows(const int32_t* __restrict__ perm, const double* __restrict__ src,
+                                           double* __restrict__ dst, int nn, int nrows, int stride) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nn) return;
+  const int o = perm[i];
+  for (int v = 0; v < nrows; ++v) dst[(size_t)v * nn + o] = src[(size_t)i * stride + v];
 }
 
 static __global__ void k_scatter_rows(const int32_t* __restrict__ perm, const double* __restrict__ src,
