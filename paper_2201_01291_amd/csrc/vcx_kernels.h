@@ -1909,19 +1909,31 @@ __global__ void VCX_FUSED_BOUNDS k_fused(DevMesh m, const double* __restrict__ W
 
 // Gradient components [C0, C0 + NCS) of node g from the node-major G (NC
 // components per node, contiguous) into LDS (sG [NCS][maxn]).
+// The row is read in 16-byte pairs from its first even component (NC even:
+// every node's row starts 16-byte aligned).
 template <int NC, int C0, int NCS, typename CT>
 __device__ inline void stage_gradient_row(const double* __restrict__ G, int g, CT* sG, int maxn, int q) {
+  static_assert(NC % 2 == 0, "node rows of an even number of components");
+  constexpr int H = C0 % 2;                // a leading odd component, read alone
+  constexpr int NPAIR = (NCS - H) / 2;     // then pairs
+  constexpr int T = NCS - H - 2 * NPAIR;   // and a trailing single
   const double* src = G + (size_t)g * NC + C0;
-  constexpr int JC = NCS <= 32 ? NCS : 16;
-  for (int j0 = 0; j0 < NCS; j0 += JC) {
-    double v[JC];
+  if constexpr (H) sG[q] = CT(src[0]);
+  const double2* p2 = reinterpret_cast<const double2*>(src + H);
+  constexpr int PC = NPAIR <= 16 ? NPAIR : 8;
+  for (int k0 = 0; k0 < NPAIR; k0 += PC) {
+    double2 v[PC];
 #pragma unroll
-    for (int jj = 0; jj < JC; ++jj)
-      if (j0 + jj < NCS) v[jj] = src[j0 + jj];
+    for (int kk = 0; kk < PC; ++kk)
+      if (k0 + kk < NPAIR) v[kk] = p2[k0 + kk];
 #pragma unroll
-    for (int jj = 0; jj < JC; ++jj)
-      if (j0 + jj < NCS) sG[(j0 + jj) * maxn + q] = CT(v[jj]);
+    for (int kk = 0; kk < PC; ++kk)
+      if (k0 + kk < NPAIR) {
+        sG[(H + 2 * (k0 + kk)) * maxn + q] = CT(v[kk].x);
+        sG[(H + 2 * (k0 + kk) + 1) * maxn + q] = CT(v[kk].y);
+      }
   }
+  if constexpr (T) sG[(NCS - 1) * maxn + q] = CT(src[NCS - 1]);
 }
 
 // Rows [r0, r0 + N) of node g into LDS rows [d0, d0 + N) (loads first).
