@@ -407,9 +407,7 @@ static SolverSizes solver_sizes(const DevMesh& d, int nd, int nvar, int nr, int 
   SolverSizes z;
   const size_t nn = (size_t)d.nn, P = (size_t)d.nslots;
   z.W = (size_t)nw * nn;
-  z.G = (size_t)ngf * nd * nn;
-  // (the node-gradient pass has no partial sums; a solver may still take
-  // the tile gradient, so the partials keep their size)
+  z.G = (size_t)node_row(ngf * nd) * nn;  // (node-major rows are padded to an even stride)
   z.PG = (size_t)ngf * nd * P;
   z.PR = (size_t)nvar * P;
   z.io = std::max<size_t>((size_t)ngf * nd, (size_t)nw) * nn;
@@ -555,8 +553,10 @@ vcx_status vcx::configure_solver(vcx_solver s, vcx_mesh mesh, const vcx_physics&
   s->ngf = kt->ngf;
   s->kt = kt;
   const DevMesh& d = mesh->d;
-  // (the multi-species node-gradient pass takes no dynamic LDS)
-  s->lds_grad = ph.model == VCX_MODEL_NAVIER_STOKES ? 0 : kt->lds_grad(d.max_tile_nodes, d.max_tile_cells);
+  // (the node-gradient pass takes no dynamic LDS)
+  const bool nodeg = node_gradient(ph.model, nd, mesh->h.nv);
+  if (nodeg && !d.has_ngrad) return fail(VCX_E_ARG, "the mesh has no node-gradient tables");
+  s->lds_grad = nodeg ? 0 : kt->lds_grad(d.max_tile_nodes, d.max_tile_cells);
   if (ph.model == VCX_MODEL_NAVIER_STOKES && !(d.has_edges && d.has_ngrad))
     return fail(VCX_E_ARG, "the mesh has no tile-edge and node-gradient tables (created by the first "
                            "Navier-Stokes solver)");
@@ -733,12 +733,12 @@ extern "C" vcx_status vcx_gradient(vcx_solver s, double* G, int is_device) {
   GradCtl gc{nullptr, 0, 0};
   VCX_TRY(s->kt->grad(s, s->W[s->cur], gc));
   VCX_TRY(s->kt->grad_complete(s));
-  if (s->ph.model == VCX_MODEL_NAVIER_STOKES) {
+  if (node_gradient(s->ph.model, s->nd, s->mesh->h.nv)) {
     // node-major gradient rows: their first nr * nd components
     const int nn = s->mesh->d.nn;
     double* target = is_device ? G : s->io;
     hipLaunchKernelGGL(k_scatter_node_rows, dim3((nn + 255) / 256), dim3(256), 0, s->mesh->stream,
-                       s->mesh->d.perm, (const double*)s->G, target, nn, s->nr * s->nd, s->ngf * s->nd);
+                       s->mesh->d.perm, (const double*)s->G, target, nn, s->nr * s->nd, node_row(s->ngf * s->nd));
     VCX_HIP(hipGetLastError());
     if (!is_device)
       VCX_HIP(hipMemcpyAsync(G, s->io, sizeof(double) * (size_t)s->nr * s->nd * nn, hipMemcpyDeviceToHost,
@@ -1023,7 +1023,7 @@ vcx_status vcx::batch_set(BatchGroup* g, vcx_solver* ss, int n, const int* steps
     g->phase0[i] = s->cur;
     g->spar0[i] = s->spar;
     for (int t = 0; t < s->mesh->d.ntiles; ++t) tmap.push_back(make_int2(i, t));
-    if (s->ph.model == VCX_MODEL_NAVIER_STOKES)
+    if (node_gradient(s->ph.model, s->nd, s->mesh->h.nv))
       for (int b = 0; b < s->mesh->d.ng_nslices; ++b) gmap.push_back(make_int2(i, b));
     for (int b = 0; b < s->nsh_blocks; ++b) smap.push_back(make_int2(i, b));
     lg = std::max(lg, s->lds_grad);

@@ -266,15 +266,12 @@ struct Impl {
   static vcx_status grad(vcx_solver s, const double* Win, const GradCtl& gc) {
     const DevMesh& m = s->mesh->d;
     const int lead = gc.lp && gc.first_stage ? 1 : 0;
-    if constexpr (MODEL == 2) {
-      // multi-species: the node-gradient pass (node-major G, complete)
-      if constexpr (SIMPLEX)
-        return launch(s, "gradient", [&](hipEvent_t ea, hipEvent_t eb) {
-          hipExtLaunchKernelGGL((k_grad_node<ND, NGF>), dim3(xcd_grid(m.ng_nslices) + lead), dim3(256), 0,
-                                s->mesh->stream, ea, eb, 0, m, Win, s->G, gc);
-        });
-      else
-        return vcx::fail(VCX_E_ARG, "the multi-species model runs on simplex meshes");
+    if constexpr (node_gradient(MODEL, ND, NV)) {
+      // the node-gradient pass (node-major G, complete)
+      return launch(s, "gradient", [&](hipEvent_t ea, hipEvent_t eb) {
+        hipExtLaunchKernelGGL((k_grad_node<ND, NGF>), dim3(xcd_grid(m.ng_nslices) + lead), dim3(256), 0,
+                              s->mesh->stream, ea, eb, 0, m, Win, s->G, gc);
+      });
     } else {
       return launch(s, "gradient", [&](hipEvent_t ea, hipEvent_t eb) {
         hipExtLaunchKernelGGL((k_grad_tile<ND, NGF, NV>), dim3(xcd_grid(m.ntiles) + lead), dim3(s->tile_block),
@@ -284,7 +281,7 @@ struct Impl {
   }
   static vcx_status grad_complete(vcx_solver s) {
     const DevMesh& m = s->mesh->d;
-    if (m.nshared == 0 || MODEL == 2) return VCX_OK;
+    if (m.nshared == 0 || node_gradient(MODEL, ND, NV)) return VCX_OK;
     return launch(s, "gradient_shared", [&](hipEvent_t ea, hipEvent_t eb) {
       hipExtLaunchKernelGGL((k_grad_shared<ND, NGF>), dim3((m.nshared + kGradSharedNodes - 1) / kGradSharedNodes),
                             dim3(256), 0, s->mesh->stream, ea, eb, 0, m, (const double*)s->PG, s->G);
@@ -480,7 +477,7 @@ struct Impl {
         });
       }
     }
-    if constexpr (MODEL == 2) {
+    if constexpr (node_gradient(MODEL, ND, NV)) {
       VCX_TRY(launch_on(s, stream, prof, "gradient", [&](hipEvent_t ea, hipEvent_t eb) {
         hipExtLaunchKernelGGL((k_grad_node_batch<ND, NGF>), dim3(xcd_grid(br.ngrad_blocks)), dim3(256), 0,
                               stream, ea, eb, 0, (const BatchEntry*)br.tab, (const int2*)br.grad_map,

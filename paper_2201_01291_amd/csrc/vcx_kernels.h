@@ -169,6 +169,15 @@ __device__ inline int xcd_tile(int ntiles) { return xcd_tile_of(blockIdx.x, ntil
 
 inline int xcd_grid(int ntiles) { return ((ntiles + NXCD - 1) / NXCD) * NXCD; }
 
+// Models whose gradient pass is the node pass (node-major G, complete on
+// every node): the multi-species model, and the gas model on tetrahedra.
+__host__ __device__ constexpr bool node_gradient(int model, int nd, int nv) {
+  return nv == nd + 1 && (model == 2 || (model == 0 && nd == 3));
+}
+// Stride of a node's row of node-major G: its components rounded up to an
+// even count, so that every row starts 16-byte aligned.
+__host__ __device__ constexpr int node_row(int nc) { return nc + (nc & 1); }
+
 __device__ inline bool step_inactive(const DevScalars* sc) {
   return sc != nullptr && sc->active == 0;
 }
@@ -718,6 +727,35 @@ __device__ inline void shared_gradient(const DevMesh& m, const double* __restric
   for (int j = 0; j < NC; ++j) out[j] *= coef;
 }
 
+// Gradient components [C0, C0 + NCS) of node g from the node-major G (NC
+// components per node, contiguous) into LDS (sG [NCS][maxn]).
+// The row is read in 16-byte pairs from its first even component (NC is
+// the row stride, even: every node's row starts 16-byte aligned).
+template <int NC, int C0, int NCS, typename CT>
+__device__ inline void stage_gradient_row(const double* __restrict__ G, int g, CT* sG, int maxn, int q) {
+  static_assert(NC % 2 == 0, "node rows of an even stride");
+  constexpr int H = C0 % 2;                // a leading odd component, read alone
+  constexpr int NPAIR = (NCS - H) / 2;     // then pairs
+  constexpr int T = NCS - H - 2 * NPAIR;   // and a trailing single
+  const double* src = G + (size_t)g * NC + C0;
+  if constexpr (H) sG[q] = CT(src[0]);
+  const double2* p2 = reinterpret_cast<const double2*>(src + H);
+  constexpr int PC = NPAIR <= 16 ? NPAIR : 8;
+  for (int k0 = 0; k0 < NPAIR; k0 += PC) {
+    double2 v[PC];
+#pragma unroll
+    for (int kk = 0; kk < PC; ++kk)
+      if (k0 + kk < NPAIR) v[kk] = p2[k0 + kk];
+#pragma unroll
+    for (int kk = 0; kk < PC; ++kk)
+      if (k0 + kk < NPAIR) {
+        sG[(H + 2 * (k0 + kk)) * maxn + q] = CT(v[kk].x);
+        sG[(H + 2 * (k0 + kk) + 1) * maxn + q] = CT(v[kk].y);
+      }
+  }
+  if constexpr (T) sG[(NCS - 1) * maxn + q] = CT(src[NCS - 1]);
+}
+
 // Stage the NC gradient components of the tile's q-th node into LDS: read G
 // for a tile-owned node, gather the slot partials of a shared node (in
 // ascending partial order, the same for every reader).  Loads of a chunk of
@@ -828,13 +866,15 @@ __global__ void __launch_bounds__(256) k_grad_shared(DevMesh m, const double* __
 // wavefronts takes a quarter of the fields for the slice's 64 nodes (lane =
 // node), so the loads of a neighbour index, its coefficients and a field row
 // are coalesced across the wavefront.  G is node-major (the NR * ND
-// components of a node contiguous, component v * ND + d): the block gathers
-// the slice's rows in LDS and writes them as one contiguous run.
+// components of a node contiguous, component v * ND + d, rows of
+// node_row(NR * ND)): the block gathers the slice's rows in LDS and writes
+// them as one contiguous run.
 constexpr int kGradNodeGroups = 4;
 template <int ND, int NR>
 __device__ inline void grad_node_body(const DevMesh& m, const double* __restrict__ W,
                                       double* __restrict__ G, const GradCtl& ctl, int sl) {
-  constexpr int FG = (NR + kGradNodeGroups - 1) / kGradNodeGroups, NC = NR * ND, LD = NC + 1;
+  constexpr int FG = (NR + kGradNodeGroups - 1) / kGradNodeGroups, NC = NR * ND, NCP = node_row(NC);
+  constexpr int LD = NCP + 1;
   __shared__ double sg[64 * LD];
   if (ctl.lp && !ctl.first_stage && ctl.lp->s[ctl.par].active == 0) return;
   const int lane = threadIdx.x & 63;
@@ -873,10 +913,10 @@ __device__ inline void grad_node_body(const DevMesh& m, const double* __restrict
         for (int d = 0; d < ND; ++d) sg[lane * LD + (v0 + f) * ND + d] = coef * acc[f][d];
   }
   __syncthreads();
-  double* out = G + (size_t)sl * 64 * NC;
-  for (int idx = threadIdx.x; idx < nb * NC; idx += blockDim.x) {
-    const int l = idx / NC;
-    out[idx] = sg[l * LD + (idx - l * NC)];
+  double* out = G + (size_t)sl * 64 * NCP;
+  for (int idx = threadIdx.x; idx < nb * NCP; idx += blockDim.x) {
+    const int l = idx / NCP, c = idx - l * NCP;
+    out[idx] = c < NC ? sg[l * LD + c] : 0.0;  // (the padding component of an odd row: 0)
   }
 }
 
@@ -1019,10 +1059,10 @@ __device__ inline void closure_flux(const DevMesh& m, const Finish& f, int k, bo
 // derivatives come from the node's (node-major) gradient row.
 template <int ND, int NSP>
 __device__ inline double ns_hoop_stress(const DevMesh& m, const Finish& f, int i) {
-  constexpr int NVAR = 2 + ND + NSP, NR = NVAR + 1, NP = ND + 1 + NSP, NC = (NR + NP) * ND;
+  constexpr int NVAR = 2 + ND + NSP, NR = NVAR + 1, NP = ND + 1 + NSP, NCP = node_row((NR + NP) * ND);
   constexpr int CR = (NR + 1) * ND + 1, CX = NR * ND;  // du_r/dr, du_x/dx
-  const double durdr = f.G[(size_t)i * NC + CR];
-  const double duxdx = f.G[(size_t)i * NC + CX];
+  const double durdr = f.G[(size_t)i * NCP + CR];
+  const double duxdx = f.G[(size_t)i * NCP + CX];
   const double eta = f.Win[(size_t)(NR + NP + 1) * m.nn + i], ur = f.Win[(size_t)(NR + 1) * m.nn + i];
   const double rr = m.x[(size_t)m.nn + i];
   const double hoop = rr > 0.0 ? ur / rr : durdr;
@@ -1497,7 +1537,10 @@ __device__ inline void flux_gas_body(DevMesh m, const double* __restrict__ W,
     for (int v = 0; v < NR; ++v) w[v] = W[(size_t)v * m.nn + g];
 #pragma unroll
     for (int d = 0; d < ND; ++d) xx[d] = m.x[(size_t)d * m.nn + g];
-    stage_gradient<NR * ND, ND, CT>(m, G, f.PG, sv, st.run, sG, maxn, q);
+    if constexpr (node_gradient(0, ND, NV))
+      stage_gradient_row<node_row(NR * ND), 0, NR * ND, CT>(G, g, sG, maxn, q);
+    else
+      stage_gradient<NR * ND, ND, CT>(m, G, f.PG, sv, st.run, sG, maxn, q);
 #pragma unroll
     for (int v = 0; v < NR; ++v) sW[v * maxn + q] = CT(w[v]);
 #pragma unroll
@@ -1907,35 +1950,6 @@ __global__ void VCX_FUSED_BOUNDS k_fused(DevMesh m, const double* __restrict__ W
 // first NR + NP rows.
 // ---------------------------------------------------------------------------
 
-// Gradient components [C0, C0 + NCS) of node g from the node-major G (NC
-// components per node, contiguous) into LDS (sG [NCS][maxn]).
-// The row is read in 16-byte pairs from its first even component (NC even:
-// every node's row starts 16-byte aligned).
-template <int NC, int C0, int NCS, typename CT>
-__device__ inline void stage_gradient_row(const double* __restrict__ G, int g, CT* sG, int maxn, int q) {
-  static_assert(NC % 2 == 0, "node rows of an even number of components");
-  constexpr int H = C0 % 2;                // a leading odd component, read alone
-  constexpr int NPAIR = (NCS - H) / 2;     // then pairs
-  constexpr int T = NCS - H - 2 * NPAIR;   // and a trailing single
-  const double* src = G + (size_t)g * NC + C0;
-  if constexpr (H) sG[q] = CT(src[0]);
-  const double2* p2 = reinterpret_cast<const double2*>(src + H);
-  constexpr int PC = NPAIR <= 16 ? NPAIR : 8;
-  for (int k0 = 0; k0 < NPAIR; k0 += PC) {
-    double2 v[PC];
-#pragma unroll
-    for (int kk = 0; kk < PC; ++kk)
-      if (k0 + kk < NPAIR) v[kk] = p2[k0 + kk];
-#pragma unroll
-    for (int kk = 0; kk < PC; ++kk)
-      if (k0 + kk < NPAIR) {
-        sG[(H + 2 * (k0 + kk)) * maxn + q] = CT(v[kk].x);
-        sG[(H + 2 * (k0 + kk) + 1) * maxn + q] = CT(v[kk].y);
-      }
-  }
-  if constexpr (T) sG[(NCS - 1) * maxn + q] = CT(src[NCS - 1]);
-}
-
 // Rows [r0, r0 + N) of node g into LDS rows [d0, d0 + N) (loads first).
 template <int N, typename CT>
 __device__ inline void stage_rows(const double* __restrict__ W, size_t nn, int g, int r0, CT* s, int d0,
@@ -2003,7 +2017,7 @@ __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ W,
       for (int d = 0; d < ND; ++d) xx[d] = m.x[(size_t)d * m.nn + g];
       stage_rows<NR, CT>(W, m.nn, g, 0, sW, 0, maxn, q);
       stage_rows<1, CT>(W, m.nn, g, NR + NP, sW, NR, maxn, q);
-      stage_gradient_row<NC, 0, CA, CT>(G, g, sG, maxn, q);
+      stage_gradient_row<node_row(NC), 0, CA, CT>(G, g, sG, maxn, q);
 #pragma unroll
       for (int d = 0; d < ND; ++d) sX[d * maxn + q] = xx[d];
     }
@@ -2098,7 +2112,7 @@ __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ W,
         stage_rows<2, CT>(W, m.nn, g, NR + NP + 1, sW, 1 + NP, maxn, q);
       else
         stage_rows<NA - 1, CT>(W, m.nn, g, NR + NP + 1, sW, 1 + NP, maxn, q);
-      stage_gradient_row<NC, CA, CB, CT>(G, g, sG, maxn, q);
+      stage_gradient_row<node_row(NC), CA, CB, CT>(G, g, sG, maxn, q);
     }
   }
   __syncthreads();
