@@ -2181,7 +2181,9 @@ __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ W,
   __syncthreads();
 
   // ---- node pass: each slot sums its edges' fluxes in ascending edge order
-  double cand = INFINITY;
+  // into its partial; the update pass finishes every node.  (Most nodes of
+  // a tetrahedral tile are shared anyway, and finishing the few owned ones
+  // here set the pass's register peak.)
   for (int q = threadIdx.x; q < ns; q += blockDim.x) {
     const SlotTopo st = slot_table_get(sSl, maxn, q);
     double r[NVAR];
@@ -2198,18 +2200,8 @@ __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ W,
         for (int v = 0; v < NVAR; ++v) r[v] += sF[v * maxe + le];
       }
     }
-    if (st.sv >= 0) {
-      NodeIn<NVAR, ND> nq;
-      node_in_load<ND, 2, NVAR>(m, f, f.sc ? f.sc->dt : 0.0, st.sv, nq);
-      cand = fmin(cand, finish_node<ND, NSP, 2, NVAR>(m, f, st.sv, false, r, nq));
-    } else {
 #pragma unroll
-      for (int v = 0; v < NVAR; ++v) PR[(size_t)st.pos * NVAR + v] = r[v];
-    }
-  }
-  if (f.final_stage && f.sc) {
-    const double b = block_min(cand);
-    if (threadIdx.x == 0) post_candidate(f.cand, t, b);
+    for (int v = 0; v < NVAR; ++v) PR[(size_t)st.pos * NVAR + v] = r[v];
   }
 }
 
@@ -2289,9 +2281,12 @@ __device__ inline void update_shared_body(const DevMesh& m, const double* __rest
   if (f.final_stage && f.sc && b == 0 && threadIdx.x == 0) f.sc->dt_src = 1;  // cand[par] from now on
   const int k = b * blockDim.x + threadIdx.x;
   double cand = INFINITY;
-  if (k < m.nshared) {
-    const int i = m.shared[k];
-    const int2 run = m.shared_run[k];
+  // the multi-species flux pass leaves every node to this pass (each node's
+  // run of partials, one for an owned node); the other passes the shared ones
+  constexpr bool ALL = MODEL == 2;
+  if (k < (ALL ? m.nn : m.nshared)) {
+    const int i = ALL ? k : m.shared[k];
+    const int2 run = ALL ? make_int2(m.node_slot[k], m.node_slot[k + 1]) : m.shared_run[k];
     NodeIn<NVAR, ND> ni;
     node_in_load<ND, MODEL, NVAR>(m, f, f.sc ? f.sc->dt : 0.0, i, ni);
     double r[NVAR];
