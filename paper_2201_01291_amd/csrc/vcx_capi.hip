@@ -415,8 +415,8 @@ static SolverSizes solver_sizes(const DevMesh& d, int nd, int nvar, int nr, int 
   z.sums = (size_t)nr;
   z.E = model == VCX_MODEL_DRIFT_DIFFUSION ? (size_t)nd * nn : 0;
   z.node_blocks = (int)((nn + kNodeBlock - 1) / kNodeBlock);
-  // (the multi-species update pass finishes every node)
-  const int nupd = model == VCX_MODEL_NAVIER_STOKES ? d.nn : d.nshared;
+  // (update_all models finish every node in the update pass)
+  const int nupd = update_all(model, nd) ? d.nn : d.nshared;
   z.nsh_blocks = std::max(1, (nupd + kNodeBlock - 1) / kNodeBlock);
   return z;
 }
@@ -595,7 +595,7 @@ vcx_status vcx::configure_solver(vcx_solver s, vcx_mesh mesh, const vcx_physics&
                       ? std::min(256, ((std::max(d.max_tile_cells, d.max_tile_edges) + 63) / 64) * 64)
                       : s->tile_block;
   s->node_blocks = (int)((d.nn + kNodeBlock - 1) / kNodeBlock);
-  const int nupd = ph.model == VCX_MODEL_NAVIER_STOKES ? d.nn : d.nshared;
+  const int nupd = update_all(ph.model, nd) ? d.nn : d.nshared;
   s->nsh_blocks = std::max(1, (nupd + kNodeBlock - 1) / kNodeBlock);
   return VCX_OK;
 }

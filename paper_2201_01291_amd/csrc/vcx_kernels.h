@@ -174,6 +174,11 @@ inline int xcd_grid(int ntiles) { return ((ntiles + NXCD - 1) / NXCD) * NXCD; }
 __host__ __device__ constexpr bool node_gradient(int model, int nd, int nv) {
   return nv == nd + 1 && (model == 2 || (model == 0 && nd == 3));
 }
+// Models whose flux pass leaves every node to the update pass (each slot
+// writes its partial): the tetrahedral ones, where nearly every node of a
+// tile is shared anyway, and finishing the few owned nodes inside the flux
+// pass set its register peak.
+__host__ __device__ constexpr bool update_all(int model, int nd) { return model == 2 || (model == 0 && nd == 3); }
 // Stride of a node's row of node-major G: its components rounded up to an
 // even count, so that every row starts 16-byte aligned.
 __host__ __device__ constexpr int node_row(int nc) { return nc + (nc & 1); }
@@ -1473,7 +1478,8 @@ __device__ inline void dd_cell_fluxes(const DevMesh& m, const TilePre<NV>& tp, c
 // fixed order; a tile-owned node is finished (stage update, time-step
 // candidate), a shared node's partial is stored at its partial index.
 // Returns this thread's smallest candidate.
-template <int ND, int NSP, int MODEL, int NVAR, bool HALVES = false>
+// ALLPR: every slot writes its partial (update_all models)
+template <int ND, int NSP, int MODEL, int NVAR, bool HALVES = false, bool ALLPR = false>
 __device__ inline double tile_node_pass(const DevMesh& m, const Finish& f, double dt, double* PR, int ns,
                                         const int* sSl, int ldsl, const uint16_t* sInc, const double* sR,
                                         int ldc, const NodeLds& nl = NodeLds{}) {
@@ -1482,7 +1488,7 @@ __device__ inline double tile_node_pass(const DevMesh& m, const Finish& f, doubl
     const SlotTopo st = slot_table_get(sSl, ldsl, q);
     // update inputs first: their loads overlap the sums
     NodeIn<NVAR, ND> nq;
-    if (st.sv >= 0) node_in_lds<ND, MODEL, NVAR>(m, f, dt, st.sv, q, nl, nq);
+    if (!ALLPR && st.sv >= 0) node_in_lds<ND, MODEL, NVAR>(m, f, dt, st.sv, q, nl, nq);
     double r[NVAR];
 #pragma unroll
     for (int v = 0; v < NVAR; ++v) r[v] = 0.0;
@@ -1498,7 +1504,7 @@ __device__ inline double tile_node_pass(const DevMesh& m, const Finish& f, doubl
         for (int v = 0; v < NVAR; ++v) r[v] += sR[(k * NVAR + v) * ldc + lc];
       }
     }
-    if (st.sv >= 0) {
+    if (!ALLPR && st.sv >= 0) {
       cand = fmin(cand, finish_node<ND, NSP, MODEL, NVAR>(m, f, st.sv, false, r, nq));
     } else {
 #pragma unroll
@@ -1558,7 +1564,9 @@ __device__ inline void flux_gas_body(DevMesh m, const double* __restrict__ W,
   gas_cell_fluxes<ND, NSP, FLUX, CT, NV, AXI, HANCOCK>(m, tp, sX, sW, sG, sR, CellLd{maxn, maxn, maxn, maxc},
                                                        gp, sH);
   __syncthreads();
-  const double cand = tile_node_pass<ND, NSP, 0, NVAR, (NH == 2)>(m, f, dt, PR, ns, sSl, maxn, sInc, sR, maxc);
+  constexpr bool ALLPR = update_all(0, ND) && NV == ND + 1;
+  const double cand =
+      tile_node_pass<ND, NSP, 0, NVAR, (NH == 2), ALLPR>(m, f, dt, PR, ns, sSl, maxn, sInc, sR, maxc);
   if (f.final_stage && f.sc) {
     const double b = block_min(cand);
     if (threadIdx.x == 0) post_candidate(f.cand, t, b);
@@ -2281,9 +2289,9 @@ __device__ inline void update_shared_body(const DevMesh& m, const double* __rest
   if (f.final_stage && f.sc && b == 0 && threadIdx.x == 0) f.sc->dt_src = 1;  // cand[par] from now on
   const int k = b * blockDim.x + threadIdx.x;
   double cand = INFINITY;
-  // the multi-species flux pass leaves every node to this pass (each node's
-  // run of partials, one for an owned node); the other passes the shared ones
-  constexpr bool ALL = MODEL == 2;
+  // update_all models leave every node to this pass (each node's run of
+  // partials, one for an owned node); the others the shared ones
+  constexpr bool ALL = update_all(MODEL, ND);
   if (k < (ALL ? m.nn : m.nshared)) {
     const int i = ALL ? k : m.shared[k];
     const int2 run = ALL ? make_int2(m.node_slot[k], m.node_slot[k + 1]) : m.shared_run[k];
