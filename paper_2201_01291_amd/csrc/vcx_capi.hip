@@ -372,7 +372,7 @@ extern "C" vcx_status vcx_mesh_geometry(vcx_mesh m, double* Vn, double* Sb) {
 
 static void free_solver(vcx_solver s) {
   if (!s) return;
-  for (double* p : {s->W[0], s->W[1], s->G, s->PG, s->PR, s->E, s->io, s->rbuf, s->part,
+  for (double* p : {s->W[0], s->W[1], s->WS[0], s->WS[1], s->G, s->PG, s->PR, s->E, s->io, s->rbuf, s->part,
                     s->sums_dev, s->cbuf})
     if (p) (void)hipFree(p);
   if (s->lp) (void)hipFree(s->lp);
@@ -394,19 +394,27 @@ static bool same_scheme(const vcx_physics& a, const vcx_physics& b) {
 // Device buffers of a solver, in doubles (one definition for creation and
 // for the footprint query used by admission control).
 struct SolverSizes {
-  size_t W = 0, G = 0, PG = 0, PR = 0, io = 0, part = 0, sums = 0, E = 0;
+  size_t W = 0, WS = 0, G = 0, PG = 0, PR = 0, io = 0, part = 0, sums = 0, E = 0;
   int node_blocks = 0, nsh_blocks = 1;
   size_t bytes() const {
     auto r = [](size_t n) { return sizeof(double) * std::max<size_t>(n, 1); };
-    return 2 * r(W) + r(G) + r(PG) + r(PR) + 2 * r(io) + r(part) + r(sums) + (E ? r(E) : 0) +
-           sizeof(DevLoop);
+    return 2 * r(W) + (WS ? 2 * r(WS) : 0) + r(G) + r(PG) + r(PR) + 2 * r(io) + r(part) + r(sums) +
+           (E ? r(E) : 0) + sizeof(DevLoop);
   }
 };
 
-static SolverSizes solver_sizes(const DevMesh& d, int nd, int nvar, int nr, int nw, int ngf, int model) {
+// Row stride of the multi-species node-major staged rows (0: other models).
+static int staged_row_stride(int nd, const vcx_physics& ph) {
+  if (ph.model != VCX_MODEL_NAVIER_STOKES) return 0;
+  return node_row(ns_staged_rows(nd, ph.nspecies, ph.precision != VCX_PREC_MIXED));
+}
+
+static SolverSizes solver_sizes(const DevMesh& d, int nd, int nvar, int nr, int nw, int ngf, int model,
+                                int ldws) {
   SolverSizes z;
   const size_t nn = (size_t)d.nn, P = (size_t)d.nslots;
   z.W = (size_t)nw * nn;
+  z.WS = (size_t)ldws * nn;
   z.G = (size_t)node_row(ngf * nd) * nn;  // (node-major rows are padded to an even stride)
   z.PG = (size_t)ngf * nd * P;
   z.PR = (size_t)nvar * P;
@@ -553,6 +561,8 @@ vcx_status vcx::configure_solver(vcx_solver s, vcx_mesh mesh, const vcx_physics&
   s->nr = ph.model == VCX_MODEL_DRIFT_DIFFUSION ? s->nvar : s->nvar + 1;
   s->nw = kt->nw;
   s->ngf = kt->ngf;
+  s->ldws = staged_row_stride(nd, ph);
+  s->nws = s->ldws ? ns_staged_rows(nd, ph.nspecies, ph.precision != VCX_PREC_MIXED) : 0;
   s->kt = kt;
   const DevMesh& d = mesh->d;
   // (the node-gradient pass takes no dynamic LDS)
@@ -619,7 +629,7 @@ extern "C" vcx_status vcx_solver_create(vcx_mesh mesh, const vcx_physics* phys, 
     }
   }
   const DevMesh& d = mesh->d;
-  const SolverSizes z = solver_sizes(d, nd, s->nvar, s->nr, s->nw, s->ngf, ph.model);
+  const SolverSizes z = solver_sizes(d, nd, s->nvar, s->nr, s->nw, s->ngf, ph.model, s->ldws);
   s->bytes = z.bytes();
   vcx_status st = VCX_OK;
   auto chk = [&](vcx_status x) {
@@ -627,6 +637,10 @@ extern "C" vcx_status vcx_solver_create(vcx_mesh mesh, const vcx_physics* phys, 
   };
   chk(dmalloc(&s->W[0], z.W));
   chk(dmalloc(&s->W[1], z.W));
+  if (z.WS) {
+    chk(dmalloc(&s->WS[0], z.WS));
+    chk(dmalloc(&s->WS[1], z.WS));
+  }
   chk(dmalloc(&s->G, z.G));
   if (s->fused && ph.model == VCX_MODEL_DRIFT_DIFFUSION && ph.closure && d.nb > 0) s->gout = s->G;
   chk(dmalloc(&s->PG, z.PG));
@@ -824,6 +838,7 @@ static vcx_status enqueue_step(vcx_solver s) {
   f.cand = s->lp->cand[par];
   f.Un = Wn;
   f.Wout = Wk;
+  f.WSout = s->WS[1 - s->cur];
   for (int k = 1; k <= K; ++k) {
     const double* Win = k == 1 ? Wn : Wk;
     // stage k of K uses alpha_{k+1}; the last one is the full update
@@ -950,6 +965,10 @@ static BatchEntry entry_of(vcx_solver s) {
   e.m = s->mesh->d;
   e.W[0] = s->W[0];
   e.W[1] = s->W[1];
+  e.WS[0] = s->WS[0];
+  e.WS[1] = s->WS[1];
+  e.nws = s->nws;
+  e.ldws = s->ldws;
   e.G = s->G;
   e.PG = s->PG;
   e.PR = s->PR;
@@ -1152,7 +1171,7 @@ vcx_status vcx::solver_footprint(vcx_mesh mesh, const vcx_physics* ph, size_t* b
   const int nd = mesh->h.nd;
   const int nvar = ph->model == VCX_MODEL_DRIFT_DIFFUSION ? ph->nspecies : 2 + nd + ph->nspecies;
   const int nr = ph->model == VCX_MODEL_DRIFT_DIFFUSION ? nvar : nvar + 1;
-  *bytes = solver_sizes(mesh->d, nd, nvar, nr, kt->nw, kt->ngf, ph->model).bytes();
+  *bytes = solver_sizes(mesh->d, nd, nvar, nr, kt->nw, kt->ngf, ph->model, staged_row_stride(nd, *ph)).bytes();
   return VCX_OK;
 }
 

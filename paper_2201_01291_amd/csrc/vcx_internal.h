@@ -59,6 +59,11 @@ struct vcx_solver_s {
   int nw = 0;   // rows of a state buffer (conserved, pressure, Navier-Stokes primitives and aux)
   int ngf = 0;  // fields whose nodal gradients are computed
   double* W[2] = {nullptr, nullptr};
+  // multi-species: node-major copies [nn][ldws] of the first nws rows of each
+  // state buffer (staged by the gradient and flux passes), kept beside W by
+  // every kernel that writes a state
+  double* WS[2] = {nullptr, nullptr};
+  int nws = 0, ldws = 0;
   int cur = 0;
   double* G = nullptr;
   double* PG = nullptr;
@@ -95,6 +100,11 @@ struct vcx_solver_s {
 // ---------------------------------------------------------------------------
 // launch helper with optional event timing
 // ---------------------------------------------------------------------------
+
+// node-major staged rows of the state buffer W (multi-species), or null
+inline const double* ws_of(vcx_solver s, const double* W) {
+  return W == s->W[0] ? s->WS[0] : (W == s->W[1] ? s->WS[1] : nullptr);
+}
 
 inline hipEvent_t take_event(vcx_solver s) {
   if (!s->spare.empty()) {
@@ -267,10 +277,13 @@ struct Impl {
     const DevMesh& m = s->mesh->d;
     const int lead = gc.lp && gc.first_stage ? 1 : 0;
     if constexpr (node_gradient(MODEL, ND, NV)) {
-      // the node-gradient pass (node-major G, complete)
+      // the node-gradient pass (node-major G, complete); the multi-species
+      // fields from the node-major staged rows
+      const double* WS = ws_of(s, Win);
       return launch(s, "gradient", [&](hipEvent_t ea, hipEvent_t eb) {
-        hipExtLaunchKernelGGL((k_grad_node<ND, NGF>), dim3(xcd_grid(m.ng_nslices) + lead), dim3(256), 0,
-                              s->mesh->stream, ea, eb, 0, m, Win, s->G, gc);
+        hipExtLaunchKernelGGL((k_grad_node<ND, NGF, MODEL == 2>), dim3(xcd_grid(m.ng_nslices) + lead),
+                              dim3(64 * kGradNodeGroups), 0, s->mesh->stream, ea, eb, 0, m, Win, WS, s->ldws, s->G,
+                              gc);
       });
     } else {
       return launch(s, "gradient", [&](hipEvent_t ea, hipEvent_t eb) {
@@ -294,7 +307,7 @@ struct Impl {
                          m.nd, NSP, s->ph.gamma);
     } else if constexpr (MODEL == 2) {
       hipLaunchKernelGGL((k_ns_aux<ND, NSP>), dim3((m.nn + 255) / 256), dim3(256), 0, s->mesh->stream,
-                         W, m.nn, mix_params(s->ph));
+                         W, m.nn, mix_params(s->ph), const_cast<double*>(ws_of(s, W)), s->nws, s->ldws);
     }
     VCX_HIP(hipGetLastError());
     return VCX_OK;
@@ -328,17 +341,19 @@ struct Impl {
       });
     } else if constexpr (MODEL == 2) {
       GasParams gp{s->ph.gamma, s->ph.beta, s->ph.entropy_fix, s->ph.limiter};
-      // (the node-gradient pass has left G complete and node-major)
+      // (the node-gradient pass has left G complete and node-major; the
+      // state rows are staged from their node-major copy)
+      const double* WS = ws_of(s, Win);
       if constexpr (ND == 2) {
         if (m.axi)
           return launch(s, "flux", [&](hipEvent_t ea, hipEvent_t eb) {
             hipExtLaunchKernelGGL((k_flux_ns<ND, NSP, CT, true>), dim3(xcd_grid(m.ntiles)), dim3(s->flux_block),
-                                  s->lds_flux, st, ea, eb, 0, m, Win, (const double*)s->G, s->PR, gp, f);
+                                  s->lds_flux, st, ea, eb, 0, m, WS, (const double*)s->G, s->PR, gp, f);
           });
       }
       return launch(s, "flux", [&](hipEvent_t ea, hipEvent_t eb) {
         hipExtLaunchKernelGGL((k_flux_ns<ND, NSP, CT>), dim3(xcd_grid(m.ntiles)), dim3(s->flux_block),
-                           s->lds_flux, st, ea, eb, 0, m, Win, (const double*)s->G, s->PR, gp, f);
+                           s->lds_flux, st, ea, eb, 0, m, WS, (const double*)s->G, s->PR, gp, f);
       });
     } else {
       DDParams pp{};
@@ -479,7 +494,8 @@ struct Impl {
     }
     if constexpr (node_gradient(MODEL, ND, NV)) {
       VCX_TRY(launch_on(s, stream, prof, "gradient", [&](hipEvent_t ea, hipEvent_t eb) {
-        hipExtLaunchKernelGGL((k_grad_node_batch<ND, NGF>), dim3(xcd_grid(br.ngrad_blocks)), dim3(256), 0,
+        hipExtLaunchKernelGGL((k_grad_node_batch<ND, NGF, MODEL == 2>), dim3(xcd_grid(br.ngrad_blocks)),
+                              dim3(64 * kGradNodeGroups), 0,
                               stream, ea, eb, 0, (const BatchEntry*)br.tab, (const int2*)br.grad_map,
                               br.ngrad_blocks, st);
       }));
@@ -561,6 +577,8 @@ inline Finish make_finish(vcx_solver s) {
   f.dc = dt_coef(s->ph);
   f.mix = mix_params(s->ph);
   f.closure = s->ph.closure;
+  f.nws = s->nws;
+  f.ldws = s->ldws;
   // fused passes with a closure that reads gradients complete G on every
   // node; so does the multi-species node-gradient pass
   f.gfull = (s->fused && s->gout != nullptr) || s->ph.model == VCX_MODEL_NAVIER_STOKES;

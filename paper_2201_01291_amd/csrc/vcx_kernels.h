@@ -182,6 +182,12 @@ __host__ __device__ constexpr bool update_all(int model, int nd) { return model 
 // Stride of a node's row of node-major G: its components rounded up to an
 // even count, so that every row starts 16-byte aligned.
 __host__ __device__ constexpr int node_row(int nc) { return nc + (nc & 1); }
+// Rows of the multi-species node-major staged copy of the state: conserved,
+// p, primitives and gamma, mu, lambda, plus the species D and h_s rows where
+// the flux pass stages them (FP32) instead of forming them (FP64).
+__host__ __device__ constexpr int ns_staged_rows(int nd, int nsp, bool fp64) {
+  return (2 + nd + nsp) + 1 + (nd + 1 + nsp) + (fp64 ? 3 : 3 + 2 * nsp);
+}
 
 __device__ inline bool step_inactive(const DevScalars* sc) {
   return sc != nullptr && sc->active == 0;
@@ -745,7 +751,7 @@ __device__ inline void stage_gradient_row(const double* __restrict__ G, int g, C
   const double* src = G + (size_t)g * NC + C0;
   if constexpr (H) sG[q] = CT(src[0]);
   const double2* p2 = reinterpret_cast<const double2*>(src + H);
-  constexpr int PC = NPAIR <= 16 ? NPAIR : 8;
+  constexpr int PC = NPAIR == 0 ? 1 : (NPAIR <= 16 ? NPAIR : 8);
   for (int k0 = 0; k0 < NPAIR; k0 += PC) {
     double2 v[PC];
 #pragma unroll
@@ -874,9 +880,15 @@ __global__ void __launch_bounds__(256) k_grad_shared(DevMesh m, const double* __
 // components of a node contiguous, component v * ND + d, rows of
 // node_row(NR * ND)): the block gathers the slice's rows in LDS and writes
 // them as one contiguous run.
-constexpr int kGradNodeGroups = 4;
-template <int ND, int NR>
+#ifndef VCX_GRAD_NODE_GROUPS
+#define VCX_GRAD_NODE_GROUPS 2
+#endif
+constexpr int kGradNodeGroups = VCX_GRAD_NODE_GROUPS;
+// WSR: the fields come from the node-major staged rows WS ([nn][ldws]) of
+// the multi-species model instead of the component-major W.
+template <int ND, int NR, bool WSR = false>
 __device__ inline void grad_node_body(const DevMesh& m, const double* __restrict__ W,
+                                      const double* __restrict__ WS, int ldws,
                                       double* __restrict__ G, const GradCtl& ctl, int sl) {
   constexpr int FG = (NR + kGradNodeGroups - 1) / kGradNodeGroups, NC = NR * ND, NCP = node_row(NC);
   constexpr int LD = NCP + 1;
@@ -904,7 +916,7 @@ __device__ inline void grad_node_body(const DevMesh& m, const double* __restrict
 #pragma unroll
       for (int f = 0; f < FG; ++f) {
         if (v0 + f < NR) {
-          const double wv = W[(size_t)(v0 + f) * m.nn + j];
+          const double wv = WSR ? WS[(size_t)j * ldws + v0 + f] : W[(size_t)(v0 + f) * m.nn + j];
 #pragma unroll
           for (int d = 0; d < ND; ++d) acc[f][d] += wv * c[d];
         }
@@ -925,8 +937,9 @@ __device__ inline void grad_node_body(const DevMesh& m, const double* __restrict
   }
 }
 
-template <int ND, int NR>
-__global__ void __launch_bounds__(256) k_grad_node(DevMesh m, const double* __restrict__ W,
+template <int ND, int NR, bool WSR = false>
+__global__ void __launch_bounds__(64 * kGradNodeGroups) k_grad_node(DevMesh m, const double* __restrict__ W,
+                                                   const double* __restrict__ WS, int ldws,
                                                    double* __restrict__ G, GradCtl ctl) {
   // in the first stage of a step, block 0 reduces the time-step candidates
   // and commits (the slices take the other blocks)
@@ -937,7 +950,7 @@ __global__ void __launch_bounds__(256) k_grad_node(DevMesh m, const double* __re
   }
   const int sl = xcd_tile_of((int)blockIdx.x - lead, m.ng_nslices);
   if (sl >= m.ng_nslices) return;
-  grad_node_body<ND, NR>(m, W, G, ctl, sl);
+  grad_node_body<ND, NR, WSR>(m, W, WS, ldws, G, ctl, sl);
 }
 
 // ---------------------------------------------------------------------------
@@ -965,6 +978,10 @@ struct Finish {
   double alpha;
   int closure, final_stage, residual_only;
   const double* cbuf;   // second closure option: [nb][NVAR] closure fluxes of the stage input
+  // multi-species: node-major copy of the stage output's first nws rows
+  // ([nn][ldws]), written beside Wout, or null
+  double* WSout;
+  int nws, ldws;
 };
 
 // Node inputs of the stage update, loaded ahead of the residual sums where
@@ -1074,6 +1091,22 @@ __device__ inline double ns_hoop_stress(const DevMesh& m, const Finish& f, int i
   return 2.0 * eta * hoop - 2.0 / 3.0 * eta * (hoop + durdr + duxdx);
 }
 
+// Node-major staged row of a multi-species node: its first nws state rows
+// (conserved, p, primitives, then the transport/thermo rows) contiguous.
+template <int ND, int NSP>
+__device__ inline void ns_store_node_row(double* row, int nws, const double (&u)[2 + ND + NSP], double p,
+                                         const double (&prim)[ND + 1 + NSP], const double (&aux)[3 + 2 * NSP]) {
+  constexpr int NVAR = 2 + ND + NSP, NP = ND + 1 + NSP, NA = 3 + 2 * NSP;
+#pragma unroll
+  for (int v = 0; v < NVAR; ++v) row[v] = u[v];
+  row[NVAR] = p;
+#pragma unroll
+  for (int q = 0; q < NP; ++q) row[NVAR + 1 + q] = prim[q];
+#pragma unroll
+  for (int q = 0; q < NA; ++q)
+    if (NVAR + 1 + NP + q < nws) row[NVAR + 1 + NP + q] = aux[q];
+}
+
 template <int ND, int NSP, int MODEL, int NVAR>
 __device__ inline double finish_node(const DevMesh& m, const Finish& f, int i, bool shared,
                                      double (&r)[NVAR], const NodeIn<NVAR, ND>& ni) {
@@ -1141,6 +1174,7 @@ __device__ inline double finish_node(const DevMesh& m, const Finish& f, int i, b
     for (int q = 0; q < NP; ++q) f.Wout[(size_t)(NVAR + 1 + q) * m.nn + i] = prim[q];
 #pragma unroll
     for (int q = 0; q < NA; ++q) f.Wout[(size_t)(NVAR + 1 + NP + q) * m.nn + i] = aux[q];
+    if (f.WSout) ns_store_node_row<ND, NSP>(f.WSout + (size_t)i * f.ldws, f.nws, u, p, prim, aux);
 #pragma unroll
     for (int v = 0; v < NVAR; ++v) ok = ok && isfinite(u[v]);
     if (!f.final_stage) return INFINITY;
@@ -1981,14 +2015,18 @@ __device__ inline void stage_rows(const double* __restrict__ W, size_t nn, int g
 // weighted by the centroid radius of its face piece (revolved face over
 // 2 pi) and the diffusive flux takes the cylindrical div u.
 template <int ND, int NSP, typename CT, bool AXI = false>
-__device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ W,
+__device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ WS,
                                     const double* __restrict__ G,
                                     double* __restrict__ PR, GasParams gp, Finish f, int t, double* lds) {
   static_assert(!AXI || ND == 2, "axisymmetric meshes are (x, r) planes");
   using L = NsEdgeLds<ND, NSP, CT>;
   constexpr int NV = ND + 1, NVAR = 2 + ND + NSP, NR = NVAR + 1, NCE = L::NCE;
-  constexpr int NP = ND + 1 + NSP, NA = 3 + 2 * NSP, NC = (NR + NP) * ND;
+  // the node-major staged rows: all but the species D and h_s rows where
+  // FP64 forms them (ns_staged_rows)
+  constexpr int NWS = ns_staged_rows(ND, NSP, L::RECOMPUTE), LWS = node_row(NWS);
+  constexpr int NP = ND + 1 + NSP, NC = (NR + NP) * ND;
   constexpr int RA = L::RA, CA = L::CA, RB = L::RB, CB = L::CB;
+  static_assert(RB == 1 + NP + (NWS - NR - NP - 1), "phase B stages rho, the primitives and the staged tail");
   if (step_inactive(f.sc)) return;
   const int c0 = m.tile_cell[t], nc = m.tile_cell[t + 1] - c0;
   const int s0 = m.tile_slot[t], ns = m.tile_slot[t + 1] - s0;
@@ -2023,8 +2061,8 @@ __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ W,
       double xx[ND];
 #pragma unroll
       for (int d = 0; d < ND; ++d) xx[d] = m.x[(size_t)d * m.nn + g];
-      stage_rows<NR, CT>(W, m.nn, g, 0, sW, 0, maxn, q);
-      stage_rows<1, CT>(W, m.nn, g, NR + NP, sW, NR, maxn, q);
+      stage_gradient_row<LWS, 0, NR, CT>(WS, g, sW, maxn, q);
+      sW[NR * maxn + q] = CT(WS[(size_t)g * LWS + NR + NP]);
       stage_gradient_row<node_row(NC), 0, CA, CT>(G, g, sG, maxn, q);
 #pragma unroll
       for (int d = 0; d < ND; ++d) sX[d * maxn + q] = xx[d];
@@ -2114,12 +2152,9 @@ __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ W,
       const int sl = s0 + q;
       const int sv = m.slot_node[sl];
       const int g = slot_node_id(sv);
-      stage_rows<1, CT>(W, m.nn, g, 0, sW, 0, maxn, q);
-      stage_rows<NP, CT>(W, m.nn, g, NR, sW, 1, maxn, q);
-      if constexpr (L::RECOMPUTE)
-        stage_rows<2, CT>(W, m.nn, g, NR + NP + 1, sW, 1 + NP, maxn, q);
-      else
-        stage_rows<NA - 1, CT>(W, m.nn, g, NR + NP + 1, sW, 1 + NP, maxn, q);
+      sW[q] = CT(WS[(size_t)g * LWS]);
+      stage_gradient_row<LWS, NR, NP, CT>(WS, g, sW + maxn, maxn, q);
+      stage_gradient_row<LWS, NR + NP + 1, NWS - NR - NP - 1, CT>(WS, g, sW + (1 + NP) * maxn, maxn, q);
       stage_gradient_row<node_row(NC), CA, CB, CT>(G, g, sG, maxn, q);
     }
   }
@@ -2214,13 +2249,13 @@ __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ W,
 }
 
 template <int ND, int NSP, typename CT, bool AXI = false>
-__global__ void VCX_FLUX_BOUNDS k_flux_ns(DevMesh m, const double* __restrict__ W,
+__global__ void VCX_FLUX_BOUNDS k_flux_ns(DevMesh m, const double* __restrict__ WS,
                                           const double* __restrict__ G,
                                           double* __restrict__ PR, GasParams gp, Finish f) {
   extern __shared__ double lds[];
   const int t = xcd_tile(m.ntiles);
   if (t >= m.ntiles) return;
-  flux_ns_body<ND, NSP, CT, AXI>(m, W, G, PR, gp, f, t, lds);
+  flux_ns_body<ND, NSP, CT, AXI>(m, WS, G, PR, gp, f, t, lds);
 }
 
 // Primitive rows -> conserved rows, in place on the first nvar rows of W:
@@ -2260,7 +2295,8 @@ __global__ void __launch_bounds__(256) k_prim_to_cons(double* __restrict__ W, in
 
 // multi-species node rows (p, primitives, aux) of an uploaded state
 template <int ND, int NSP>
-__global__ void __launch_bounds__(256) k_ns_aux(double* __restrict__ W, int nn, MixParams mp) {
+__global__ void __launch_bounds__(256) k_ns_aux(double* __restrict__ W, int nn, MixParams mp,
+                                                double* __restrict__ WS, int nws, int ldws) {
   constexpr int NVAR = 2 + ND + NSP, NP = ND + 1 + NSP, NA = 3 + 2 * NSP;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nn) return;
@@ -2273,6 +2309,7 @@ __global__ void __launch_bounds__(256) k_ns_aux(double* __restrict__ W, int nn, 
   for (int q = 0; q < NP; ++q) W[(size_t)(NVAR + 1 + q) * nn + i] = prim[q];
 #pragma unroll
   for (int q = 0; q < NA; ++q) W[(size_t)(NVAR + 1 + NP + q) * nn + i] = aux[q];
+  if (WS) ns_store_node_row<ND, NSP>(WS + (size_t)i * ldws, nws, u, p, prim, aux);
 }
 
 // ---------------------------------------------------------------------------
@@ -2419,6 +2456,8 @@ __global__ void __launch_bounds__(256) k_cell_dx(DevMesh m, unsigned long long* 
 struct BatchEntry {
   DevMesh m;
   double* W[2];     // state buffers; the current one is W[(step + phase) & 1]
+  double* WS[2];    // multi-species: their node-major staged rows, or null
+  int nws, ldws;
   double* G;
   double* PG;
   double* PR;
@@ -2450,6 +2489,9 @@ __device__ inline Finish batch_finish(const BatchEntry& e, const BatchStage& st,
   Finish f{};
   f.Un = e.W[cur];
   f.Wout = e.W[cur ^ 1];
+  f.WSout = e.WS[cur ^ 1];
+  f.nws = e.nws;
+  f.ldws = e.ldws;
   f.Win = st.stage == 1 ? e.W[cur] : e.W[cur ^ 1];
   f.G = e.G;
   f.PG = e.PG;
@@ -2496,8 +2538,8 @@ __global__ void __launch_bounds__(256) k_grad_tile_batch(const BatchEntry* __res
 
 // node gradient of every solve of a batch (block map: solve, node slice;
 // slice -1 is the solve's decision entry)
-template <int ND, int NR>
-__global__ void __launch_bounds__(256) k_grad_node_batch(const BatchEntry* __restrict__ tab,
+template <int ND, int NR, bool WSR = false>
+__global__ void __launch_bounds__(64 * kGradNodeGroups) k_grad_node_batch(const BatchEntry* __restrict__ tab,
                                                          const int2* __restrict__ map, int nblocks,
                                                          BatchStage st) {
   const int g = xcd_tile(nblocks);
@@ -2512,7 +2554,8 @@ __global__ void __launch_bounds__(256) k_grad_node_batch(const BatchEntry* __res
   const int cur = (st.step + e.phase) & 1;
   const double* Win = st.stage == 1 ? e.W[cur] : e.W[cur ^ 1];
   GradCtl ctl{e.lp, par, st.stage == 1 ? 1 : 0};
-  grad_node_body<ND, NR>(e.m, Win, e.G, ctl, ml.y);
+  const double* WSin = st.stage == 1 ? e.WS[cur] : e.WS[cur ^ 1];
+  grad_node_body<ND, NR, WSR>(e.m, Win, WSin, e.ldws, e.G, ctl, ml.y);
 }
 
 template <int ND, int NSP, int FLUX, typename CT>
@@ -2557,7 +2600,8 @@ __global__ void VCX_FLUX_BOUNDS k_flux_ns_batch(const BatchEntry* __restrict__ t
   const BatchEntry& e = tab[ml.x];
   const double* Win;
   const Finish f = batch_finish(e, st, fs, &Win);
-  flux_ns_body<ND, NSP, CT>(e.m, Win, e.G, e.PR, gp, f, ml.y, lds);
+  const int cur = (st.step + e.phase) & 1;
+  flux_ns_body<ND, NSP, CT>(e.m, st.stage == 1 ? e.WS[cur] : e.WS[cur ^ 1], e.G, e.PR, gp, f, ml.y, lds);
 }
 
 template <int ND, int NSP, int MODEL, int FLUX, typename CT>
