@@ -453,15 +453,17 @@ def size_sweep(a, stream):
                      steps=k, mfaces=round(w.faces_per_step * k / el / 1e6, 1),
                      ms_per_step=round(el / k * 1e3, 4), tiles=list(tiles), kernels=kern)
         if name == "dd2d" and "gradient" in kern:
-            # large drift-diffusion meshes take the separate passes: the
-            # flux pass's own bytes (its gradients read from G), and the
-            # whole stage (gradient, completion, flux) against the stage's
-            # minimal bytes (those of the fused pass)
+            # large drift-diffusion meshes take the separate passes (the
+            # node gradient on simplices): the flux pass's own bytes (its
+            # gradients read from G), and the whole stage (gradient, any
+            # completion, flux) against the stage's minimal bytes (those of
+            # the fused pass)
             N, M = w.mesh.nnodes, w.mesh.ncells
             fb = N * 8 * (2 + 2 + 2 + 4 + 2 + 1 + 1 + 2) + M * (3 * 2 + 4)
             us = kern["flux"]["avg_us"]
             st_us = sum(kern[k_]["avg_us"] for k_ in ("gradient", "gradient_shared", "flux") if k_ in kern)
-            entry.update(path="gradient + shared-node completion + flux",
+            entry.update(path=("gradient + shared-node completion + flux" if "gradient_shared" in kern
+                               else "node gradient + flux"),
                          flux_alg_gbs=round(fb / (us * 1e-6) / 1e9, 1),
                          flux_hbm_frac=round(fb / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
                          stage_hbm_frac=round(w.bytes_flux[0] / (st_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4))

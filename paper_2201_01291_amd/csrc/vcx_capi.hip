@@ -550,6 +550,11 @@ vcx_status vcx::check_physics(vcx_mesh mesh, const vcx_physics& ph, const double
   return VCX_OK;
 }
 
+// Drift-diffusion meshes above this many cells take the separate passes
+// (1.8M cells: 120 against 158 us per step with the tile gradient; 200k
+// cells: the fused pass 26 against 33 us).
+constexpr int64_t kFusedMaxCells = int64_t(1) << 20;
+
 // Sizes, LDS footprints, fused-pass choice and launch shapes of a solver
 // (host fields only; no device memory is touched).
 vcx_status vcx::configure_solver(vcx_solver s, vcx_mesh mesh, const vcx_physics& ph, const KernelTable* kt) {
@@ -588,16 +593,17 @@ vcx_status vcx::configure_solver(vcx_solver s, vcx_mesh mesh, const vcx_physics&
   // after a separate gradient pass)
   // (the predictor and the Scharfetter-Gummel flux take the separate passes too)
   const bool sg = ph.model == VCX_MODEL_DRIFT_DIFFUSION && ph.flux == VCX_FLUX_SG;
-  // Drift-diffusion meshes above kFusedMaxCells take the separate passes:
-  // gradient, shared-node completion and flux outrun the fused pass once the
-  // launches are long (1.8M cells: 120 vs 158 us per step; 28.8M: 2.27 vs
-  // 2.59 ms), while the fused pass's two launches win on small meshes
-  // (200k cells: 26 vs 33 us).
-  constexpr int64_t kFusedMaxCells = int64_t(1) << 20;
+  // Drift-diffusion meshes above kFusedMaxCells take the separate passes
+  // (on simplices the node gradient, whose tables the solver builds, else the
+  // tile gradient and the shared-node completion), which outrun the fused
+  // pass once the launches are long, while the fused pass's two launches win
+  // on small meshes.
   const bool big_dd = ph.model == VCX_MODEL_DRIFT_DIFFUSION && d.nc > kFusedMaxCells;
   s->fused = !d.axi && ph.closure != 2 && !ph.predictor && !sg && !big_dd && s->lds_fused > 0 &&
              s->lds_fused <= (size_t)mesh->lds_max;
   if (!s->fused) s->lds_fused = 0;
+  s->dd_ngrad = ph.model == VCX_MODEL_DRIFT_DIFFUSION && !s->fused && d.has_ngrad;
+  if (s->dd_ngrad) s->lds_grad = 0;
   if (std::max({s->lds_grad, s->lds_flux, s->lds_fused}) > 65536)
     VCX_TRY(kt->allow_lds(s->lds_grad, s->lds_flux, s->lds_fused));
   s->tile_block = std::min(256, ((d.max_tile_cells + 63) / 64) * 64);
@@ -619,6 +625,8 @@ extern "C" vcx_status vcx_solver_create(vcx_mesh mesh, const vcx_physics* phys, 
   const KernelTable* kt = nullptr;
   VCX_TRY(check_physics(mesh, ph, E, &kt));
   if (ph.model == VCX_MODEL_NAVIER_STOKES) VCX_TRY(ensure_tile_edges(mesh));
+  if (ph.model == VCX_MODEL_DRIFT_DIFFUSION && mesh->h.nc > kFusedMaxCells && mesh->h.nv == nd + 1)
+    VCX_TRY(ensure_node_gradient(mesh));
   vcx_solver s = new (std::nothrow) vcx_solver_s();
   if (!s) return fail(VCX_E_OOM, "host allocation failed");
   {
@@ -1045,7 +1053,7 @@ vcx_status vcx::batch_set(BatchGroup* g, vcx_solver* ss, int n, const int* steps
     g->phase0[i] = s->cur;
     g->spar0[i] = s->spar;
     for (int t = 0; t < s->mesh->d.ntiles; ++t) tmap.push_back(make_int2(i, t));
-    if (node_gradient(s->ph.model, s->nd, s->mesh->h.nv))
+    if (node_gradient(s->ph.model, s->nd, s->mesh->h.nv) || s->dd_ngrad)
       for (int b = 0; b < s->mesh->d.ng_nslices; ++b) gmap.push_back(make_int2(i, b));
     for (int b = 0; b < s->nsh_blocks; ++b) smap.push_back(make_int2(i, b));
     lg = std::max(lg, s->lds_grad);
@@ -1095,6 +1103,7 @@ vcx_status vcx::batch_set(BatchGroup* g, vcx_solver* ss, int n, const int* steps
   br.ntile_blocks = (int)tmap.size();
   br.grad_map = g->grad_map;
   br.ngrad_blocks = (int)gmap.size();
+  br.dd_ngrad = lead->dd_ngrad;
   br.sh_map = g->sh_map;
   br.nsh_blocks = (int)smap.size();
   br.lds_grad = lg;
@@ -1176,7 +1185,7 @@ vcx_status vcx::solver_footprint(vcx_mesh mesh, const vcx_physics* ph, size_t* b
 }
 
 bool vcx::batch_compatible(vcx_solver a, vcx_solver b) {
-  return a->kt == b->kt && a->fused == b->fused && same_scheme(a->ph, b->ph);
+  return a->kt == b->kt && a->fused == b->fused && a->dd_ngrad == b->dd_ngrad && same_scheme(a->ph, b->ph);
 }
 
 vcx_status vcx::set_error(vcx_status s, const char* msg) { return fail(s, msg ? msg : ""); }

@@ -64,6 +64,9 @@ struct vcx_solver_s {
   // every kernel that writes a state
   double* WS[2] = {nullptr, nullptr};
   int nws = 0, ldws = 0;
+  // drift-diffusion on large simplex meshes: the node-gradient pass with a
+  // component-major G (no partial sums, no completion)
+  bool dd_ngrad = false;
   int cur = 0;
   double* G = nullptr;
   double* PG = nullptr;
@@ -166,8 +169,9 @@ struct BatchRun {
   BatchEntry* tab;
   int2* tile_map;
   int ntile_blocks;
-  int2* grad_map;                  // blocks of the node-gradient pass (multi-species): solve, slice
+  int2* grad_map;                  // blocks of the node-gradient pass: solve, slice
   int ngrad_blocks;
+  bool dd_ngrad;                   // drift-diffusion solves on the node-gradient pass
   int2* sh_map;
   int nsh_blocks;
   size_t lds_grad, lds_flux;
@@ -286,6 +290,14 @@ struct Impl {
                               gc);
       });
     } else {
+      if constexpr (MODEL == 1 && SIMPLEX) {
+        if (s->dd_ngrad)
+          return launch(s, "gradient", [&](hipEvent_t ea, hipEvent_t eb) {
+            hipExtLaunchKernelGGL((k_grad_node<ND, NGF, false, true>), dim3(xcd_grid(m.ng_nslices) + lead),
+                                  dim3(64 * kGradNodeGroups), 0, s->mesh->stream, ea, eb, 0, m, Win,
+                                  (const double*)nullptr, 0, s->G, gc);
+          });
+      }
       return launch(s, "gradient", [&](hipEvent_t ea, hipEvent_t eb) {
         hipExtLaunchKernelGGL((k_grad_tile<ND, NGF, NV>), dim3(xcd_grid(m.ntiles) + lead), dim3(s->tile_block),
                               s->lds_grad, s->mesh->stream, ea, eb, 0, m, Win, s->G, s->PG, gc);
@@ -294,7 +306,7 @@ struct Impl {
   }
   static vcx_status grad_complete(vcx_solver s) {
     const DevMesh& m = s->mesh->d;
-    if (m.nshared == 0 || node_gradient(MODEL, ND, NV)) return VCX_OK;
+    if (m.nshared == 0 || node_gradient(MODEL, ND, NV) || s->dd_ngrad) return VCX_OK;
     return launch(s, "gradient_shared", [&](hipEvent_t ea, hipEvent_t eb) {
       hipExtLaunchKernelGGL((k_grad_shared<ND, NGF>), dim3((m.nshared + kGradSharedNodes - 1) / kGradSharedNodes),
                             dim3(256), 0, s->mesh->stream, ea, eb, 0, m, (const double*)s->PG, s->G);
@@ -476,7 +488,8 @@ struct Impl {
     vcx_solver s = br.lead;
     // multi-species: the node-gradient pass leaves G complete, as in the
     // single solve
-    FinishShared fs{dt_coef(s->ph), mix_params(s->ph), s->ph.closure, br.fused ? 1 : 0, MODEL == 2 ? 1 : 0};
+    FinishShared fs{dt_coef(s->ph), mix_params(s->ph), s->ph.closure, br.fused ? 1 : 0,
+                    MODEL == 2 || br.dd_ngrad ? 1 : 0};
     if constexpr (FUSABLE) {
       if (br.fused) {
         GasParams gp{s->ph.gamma, s->ph.beta, s->ph.entropy_fix, s->ph.limiter};
@@ -498,6 +511,12 @@ struct Impl {
                               dim3(64 * kGradNodeGroups), 0,
                               stream, ea, eb, 0, (const BatchEntry*)br.tab, (const int2*)br.grad_map,
                               br.ngrad_blocks, st);
+      }));
+    } else if (MODEL == 1 && br.dd_ngrad) {
+      VCX_TRY(launch_on(s, stream, prof, "gradient", [&](hipEvent_t ea, hipEvent_t eb) {
+        hipExtLaunchKernelGGL((k_grad_node_batch<ND, NGF, false, true>), dim3(xcd_grid(br.ngrad_blocks)),
+                              dim3(64 * kGradNodeGroups), 0, stream, ea, eb, 0, (const BatchEntry*)br.tab,
+                              (const int2*)br.grad_map, br.ngrad_blocks, st);
       }));
     } else {
       VCX_TRY(launch_on(s, stream, prof, "gradient", [&](hipEvent_t ea, hipEvent_t eb) {
@@ -580,8 +599,8 @@ inline Finish make_finish(vcx_solver s) {
   f.nws = s->nws;
   f.ldws = s->ldws;
   // fused passes with a closure that reads gradients complete G on every
-  // node; so does the multi-species node-gradient pass
-  f.gfull = (s->fused && s->gout != nullptr) || s->ph.model == VCX_MODEL_NAVIER_STOKES;
+  // node; so do the node-gradient passes
+  f.gfull = (s->fused && s->gout != nullptr) || s->ph.model == VCX_MODEL_NAVIER_STOKES || s->dd_ngrad;
   return f;
 }
 

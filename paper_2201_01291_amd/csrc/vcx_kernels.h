@@ -885,8 +885,10 @@ __global__ void __launch_bounds__(256) k_grad_shared(DevMesh m, const double* __
 #endif
 constexpr int kGradNodeGroups = VCX_GRAD_NODE_GROUPS;
 // WSR: the fields come from the node-major staged rows WS ([nn][ldws]) of
-// the multi-species model instead of the component-major W.
-template <int ND, int NR, bool WSR = false>
+// the multi-species model instead of the component-major W.  CMAJ: G is
+// written component-major ([NR * ND][nn], the layout of the tile-gradient
+// models) straight from the lanes, coalesced.
+template <int ND, int NR, bool WSR = false, bool CMAJ = false>
 __device__ inline void grad_node_body(const DevMesh& m, const double* __restrict__ W,
                                       const double* __restrict__ WS, int ldws,
                                       double* __restrict__ G, const GradCtl& ctl, int sl) {
@@ -927,17 +929,24 @@ __device__ inline void grad_node_body(const DevMesh& m, const double* __restrict
     for (int f = 0; f < FG; ++f)
       if (v0 + f < NR)
 #pragma unroll
-        for (int d = 0; d < ND; ++d) sg[lane * LD + (v0 + f) * ND + d] = coef * acc[f][d];
+        for (int d = 0; d < ND; ++d) {
+          if constexpr (CMAJ)
+            G[(size_t)((v0 + f) * ND + d) * m.nn + i] = coef * acc[f][d];
+          else
+            sg[lane * LD + (v0 + f) * ND + d] = coef * acc[f][d];
+        }
   }
-  __syncthreads();
-  double* out = G + (size_t)sl * 64 * NCP;
-  for (int idx = threadIdx.x; idx < nb * NCP; idx += blockDim.x) {
-    const int l = idx / NCP, c = idx - l * NCP;
-    out[idx] = c < NC ? sg[l * LD + c] : 0.0;  // (the padding component of an odd row: 0)
+  if constexpr (!CMAJ) {
+    __syncthreads();
+    double* out = G + (size_t)sl * 64 * NCP;
+    for (int idx = threadIdx.x; idx < nb * NCP; idx += blockDim.x) {
+      const int l = idx / NCP, c = idx - l * NCP;
+      out[idx] = c < NC ? sg[l * LD + c] : 0.0;  // (the padding component of an odd row: 0)
+    }
   }
 }
 
-template <int ND, int NR, bool WSR = false>
+template <int ND, int NR, bool WSR = false, bool CMAJ = false>
 __global__ void __launch_bounds__(64 * kGradNodeGroups) k_grad_node(DevMesh m, const double* __restrict__ W,
                                                    const double* __restrict__ WS, int ldws,
                                                    double* __restrict__ G, GradCtl ctl) {
@@ -950,7 +959,7 @@ __global__ void __launch_bounds__(64 * kGradNodeGroups) k_grad_node(DevMesh m, c
   }
   const int sl = xcd_tile_of((int)blockIdx.x - lead, m.ng_nslices);
   if (sl >= m.ng_nslices) return;
-  grad_node_body<ND, NR, WSR>(m, W, WS, ldws, G, ctl, sl);
+  grad_node_body<ND, NR, WSR, CMAJ>(m, W, WS, ldws, G, ctl, sl);
 }
 
 // ---------------------------------------------------------------------------
@@ -1093,18 +1102,24 @@ __device__ inline double ns_hoop_stress(const DevMesh& m, const Finish& f, int i
 
 // Node-major staged row of a multi-species node: its first nws state rows
 // (conserved, p, primitives, then the transport/thermo rows) contiguous.
+// The row starts 16-byte aligned (an even stride): it is written in pairs.
 template <int ND, int NSP>
 __device__ inline void ns_store_node_row(double* row, int nws, const double (&u)[2 + ND + NSP], double p,
                                          const double (&prim)[ND + 1 + NSP], const double (&aux)[3 + 2 * NSP]) {
-  constexpr int NVAR = 2 + ND + NSP, NP = ND + 1 + NSP, NA = 3 + 2 * NSP;
+  constexpr int NVAR = 2 + ND + NSP, NP = ND + 1 + NSP, NA = 3 + 2 * NSP, NT = NVAR + 1 + NP + NA;
+  double r[NT + 1];
 #pragma unroll
-  for (int v = 0; v < NVAR; ++v) row[v] = u[v];
-  row[NVAR] = p;
+  for (int v = 0; v < NVAR; ++v) r[v] = u[v];
+  r[NVAR] = p;
 #pragma unroll
-  for (int q = 0; q < NP; ++q) row[NVAR + 1 + q] = prim[q];
+  for (int q = 0; q < NP; ++q) r[NVAR + 1 + q] = prim[q];
 #pragma unroll
-  for (int q = 0; q < NA; ++q)
-    if (NVAR + 1 + NP + q < nws) row[NVAR + 1 + NP + q] = aux[q];
+  for (int q = 0; q < NA; ++q) r[NVAR + 1 + NP + q] = aux[q];
+  r[NT] = 0.0;
+  double2* r2 = reinterpret_cast<double2*>(row);
+#pragma unroll
+  for (int c = 0; c < NT; c += 2)
+    if (c < nws) r2[c / 2] = make_double2(r[c], r[c + 1]);  // (an odd nws also fills the row's padding)
 }
 
 template <int ND, int NSP, int MODEL, int NVAR>
@@ -2538,7 +2553,7 @@ __global__ void __launch_bounds__(256) k_grad_tile_batch(const BatchEntry* __res
 
 // node gradient of every solve of a batch (block map: solve, node slice;
 // slice -1 is the solve's decision entry)
-template <int ND, int NR, bool WSR = false>
+template <int ND, int NR, bool WSR = false, bool CMAJ = false>
 __global__ void __launch_bounds__(64 * kGradNodeGroups) k_grad_node_batch(const BatchEntry* __restrict__ tab,
                                                          const int2* __restrict__ map, int nblocks,
                                                          BatchStage st) {
@@ -2555,7 +2570,7 @@ __global__ void __launch_bounds__(64 * kGradNodeGroups) k_grad_node_batch(const 
   const double* Win = st.stage == 1 ? e.W[cur] : e.W[cur ^ 1];
   GradCtl ctl{e.lp, par, st.stage == 1 ? 1 : 0};
   const double* WSin = st.stage == 1 ? e.WS[cur] : e.WS[cur ^ 1];
-  grad_node_body<ND, NR, WSR>(e.m, Win, WSin, e.ldws, e.G, ctl, ml.y);
+  grad_node_body<ND, NR, WSR, CMAJ>(e.m, Win, WSin, e.ldws, e.G, ctl, ml.y);
 }
 
 template <int ND, int NSP, int FLUX, typename CT>

@@ -211,6 +211,36 @@ def test_full_size_drift_diffusion_residual_and_steps():
     assert state_err(case, s.download(), Uo).max() <= FP64_TOL
 
 
+def test_large_drift_diffusion_mesh_on_the_separate_passes():
+    """A drift-diffusion mesh above 2^20 cells (the size family of the
+    workload, 1.2M cells) takes the separate gradient and flux passes, its
+    gradient from the node-gradient tables: time step, residual and 2 steps
+    against the oracle, and the gradient against the oracle's."""
+    from paper_2201_01291_amd import workloads as wl
+    import cases
+    m = wl.dd_streamer_mesh(800, 750)
+    assert m.ncells > 1 << 20
+    n, E = wl.dd_fields(m)
+    case = cases.Case("dd2d-large", m, n, E, dict(cases.DD2))
+    print(f"[case] {case.name} nc={m.ncells}", flush=True)
+    om, gm, s = _setup(case)
+    s.profile(True)
+    ph = case.oracle_phys()
+    dt = om.timestep(ph, n, E)
+    assert s.timestep() == pytest.approx(dt, rel=1e-13)
+    err = normwise(s.residual(dt), om.residual(ph, n, E, dt), om.flux_scale(ph, n, E, dt))
+    assert err.max() <= FP64_TOL
+    assert s.profile_query("gradient")[0] >= 1     # the separate passes ran
+    assert s.profile_query("gradient_shared")[0] == 0   # with no completion pass
+    W = reconstructed(case)
+    h = (m.ncells / om.geometry()["Vc"].sum()) ** 0.5
+    gerr = np.abs(s.gradient() - om.gradient(W)).max(axis=(1, 2)) / (np.abs(W).max(axis=1) * h)
+    assert gerr.max() <= FP64_TOL
+    Uo, *_ = om.step(ph, n, E, nsteps=2)
+    s.step(2)
+    assert state_err(case, s.download(), Uo).max() <= FP64_TOL
+
+
 def test_full_size_euler3d_residual_and_steps():
     """The 2M-tet periodic 3D Euler workload (Roe + van Leer, RK2) at full
     size and in the benchmark's tiling: time step, FP64 residual and two
