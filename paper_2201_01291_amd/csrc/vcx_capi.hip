@@ -119,6 +119,11 @@ extern "C" vcx_status vcx_mesh_create_axisymmetric_nv(int64_t nnodes, const doub
                      out);
 }
 
+// Drift-diffusion meshes above this many cells take the separate passes
+// (1.8M cells: 120 against 158 us per step with the tile gradient; 200k
+// cells: the fused pass 26 against 33 us).
+constexpr int64_t kFusedMaxCells = int64_t(1) << 20;
+
 // Build (host) and upload (device) the node-gradient tables of a simplex
 // mesh, once (the host copies are released after the upload).
 static vcx_status ensure_node_gradient(vcx_mesh m) {
@@ -302,6 +307,9 @@ static vcx_status create_mesh(int ndim, int64_t nnodes, const double* xyz, int64
   // tile-edge tables of the multi-species flux pass: 3D meshes at creation,
   // 2D meshes when their first Navier-Stokes solver is created
   if (st == VCX_OK && h.nd == 3) st = ensure_tile_edges(m);
+  // node-gradient tables of large 2D simplex meshes (the separate
+  // drift-diffusion passes) at creation too, not in a solver's first call
+  if (st == VCX_OK && h.nd == 2 && h.nv == 3 && h.nc > kFusedMaxCells) st = ensure_node_gradient(m);
   if (st == VCX_OK) {
     // smallest inscribed diameter of the cells around each node (time step)
     void* p = nullptr;
@@ -549,11 +557,6 @@ vcx_status vcx::check_physics(vcx_mesh mesh, const vcx_physics& ph, const double
   *kt_out = kt;
   return VCX_OK;
 }
-
-// Drift-diffusion meshes above this many cells take the separate passes
-// (1.8M cells: 120 against 158 us per step with the tile gradient; 200k
-// cells: the fused pass 26 against 33 us).
-constexpr int64_t kFusedMaxCells = int64_t(1) << 20;
 
 // Sizes, LDS footprints, fused-pass choice and launch shapes of a solver
 // (host fields only; no device memory is touched).
