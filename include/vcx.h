@@ -167,8 +167,12 @@ typedef struct vcx_server_s *vcx_server;
  *   stream    hipStream_t for the uploads and for every later use
  * Computes node normals, median-dual volumes V_i = sum V_tau / n_v, boundary
  * node normals, a space-filling-curve node/cell order and the fixed cell
- * tiles used by the deterministic scatter.  Errors: VCX_E_ARG, VCX_E_MESH,
- * VCX_E_OOM, VCX_E_HIP. */
+ * tiles used by the deterministic scatter.  Tetrahedral meshes, and triangle
+ * meshes above 2^20 cells, also get the node-gradient tables (each node's
+ * neighbours and their coefficients, about 15 entries of 28 B per node in
+ * 3D) and, in 3D, the tile-edge tables of the multi-species flux pass; a 2D
+ * mesh gets the latter two when its first multi-species solver is created.
+ * Errors: VCX_E_ARG, VCX_E_MESH, VCX_E_OOM, VCX_E_HIP. */
 vcx_status vcx_mesh_create(int ndim, int64_t nnodes, const double *xyz, int64_t ncells, int nv,
                            const int64_t *cells, const double *period, void *stream,
                            vcx_mesh *out);
@@ -302,7 +306,9 @@ vcx_status vcx_residual(vcx_solver s, double dt, double *r, int is_device);
  * order) lives in one static device array of vcx_noalloc_scratch_bytes()
  * (64 MiB) per device, which the library holds until the process ends.
  * Meshes and physics that need more return VCX_E_ARG (e.g. 2D
- * drift-diffusion up to about 300k nodes).  All calls on one device share
+ * drift-diffusion up to about 300k nodes), as does the multi-species model
+ * on a 2D mesh that has no multi-species solver yet (its tables are built
+ * by the first one).  All calls on one device share
  * that array and the work runs on the mesh's stream; the call returns once
  * it is complete, so calls must not overlap on one GPU (several threads or
  * streams at once race).  Errors: VCX_E_ARG (NULL argument, unsupported
@@ -357,8 +363,9 @@ vcx_status vcx_solve_batch(vcx_solver *s, int n, const int *nsteps, const double
 vcx_status vcx_solve_batch_eager(vcx_solver *s, int n, const int *nsteps, const double *t_end);
 
 /* Device bytes a solver with this physics on this mesh would allocate
- * (state buffers, gradients, tile partials, staging, time-step scalars; the
- * mesh's own arrays are not included).  Used for admission by device-memory
+ * (state buffers and, for the multi-species model, their node-major staged
+ * copies, gradients, tile partials, staging, time-step scalars; the mesh's
+ * own arrays are not included).  Used for admission by device-memory
  * footprint. */
 vcx_status vcx_solver_footprint(vcx_mesh mesh, const vcx_physics *phys, size_t *bytes);
 
