@@ -2065,22 +2065,39 @@ __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ WS,
     pq0 = m.edge_ce[e0 + threadIdx.x];
     pq1 = m.edge_ce[e0 + threadIdx.x + 1];
   }
+  // The node pass, and the FP32 path's staging, take two threads per slot
+  // where the block has them (half h of slot q at thread h * ns + q, so that
+  // a wavefront's lanes mostly take the same half).  Staging halves: the
+  // first the state rows, coordinates and slot table with the first part of
+  // the gradient row, the second the rest of the gradient row.  (Split
+  // staging was slower for the FP64 pass: 4.43 -> 4.58 ms on C4.)
+  const int tpn = (int)blockDim.x >= 2 * ns ? 2 : 1;
+  const int tps = sizeof(CT) == 4 ? tpn : 1;
+  constexpr int CA0 = CA / 3, CB0 = CB / 3;  // gradient components the first half stages
   // ---- phase A staging: coordinates, reconstructed rows, gamma, gradients
   {
     CT* sG = sW + RA * maxn;
-    for (int q = threadIdx.x; q < ns; q += blockDim.x) {
+    for (int t = threadIdx.x; t < tps * ns; t += blockDim.x) {
+      const int h = t >= ns ? 1 : 0, q = t - h * ns;
       const int sl = s0 + q;
       const int sv = m.slot_node[sl];
-      slot_table_put(sSl, maxn, q, sv, m.slot_pos[sl], m.slot_einc[sl] - pb, m.slot_einc[sl + 1] - pb);
       const int g = slot_node_id(sv);
-      double xx[ND];
+      if (h == 0) {
+        slot_table_put(sSl, maxn, q, sv, m.slot_pos[sl], m.slot_einc[sl] - pb, m.slot_einc[sl + 1] - pb);
+        double xx[ND];
 #pragma unroll
-      for (int d = 0; d < ND; ++d) xx[d] = m.x[(size_t)d * m.nn + g];
-      stage_gradient_row<LWS, 0, NR, CT>(WS, g, sW, maxn, q);
-      sW[NR * maxn + q] = CT(WS[(size_t)g * LWS + NR + NP]);
-      stage_gradient_row<node_row(NC), 0, CA, CT>(G, g, sG, maxn, q);
+        for (int d = 0; d < ND; ++d) xx[d] = m.x[(size_t)d * m.nn + g];
+        stage_gradient_row<LWS, 0, NR, CT>(WS, g, sW, maxn, q);
+        sW[NR * maxn + q] = CT(WS[(size_t)g * LWS + NR + NP]);
+        if (tps == 2)
+          stage_gradient_row<node_row(NC), 0, CA0, CT>(G, g, sG, maxn, q);
+        else
+          stage_gradient_row<node_row(NC), 0, CA, CT>(G, g, sG, maxn, q);
 #pragma unroll
-      for (int d = 0; d < ND; ++d) sX[d * maxn + q] = xx[d];
+        for (int d = 0; d < ND; ++d) sX[d * maxn + q] = xx[d];
+      } else {
+        stage_gradient_row<node_row(NC), CA0, CA - CA0, CT>(G, g, sG + CA0 * maxn, maxn, q);
+      }
     }
     for (int p = threadIdx.x; p < ninc; p += blockDim.x) sEi[p] = m.einc[pb + p];
   }
@@ -2163,14 +2180,20 @@ __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ WS,
   // ---- phase B staging: rho, primitives, transport rows, primitive gradients
   {
     CT* sG = sW + RB * maxn;
-    for (int q = threadIdx.x; q < ns; q += blockDim.x) {
-      const int sl = s0 + q;
-      const int sv = m.slot_node[sl];
-      const int g = slot_node_id(sv);
-      sW[q] = CT(WS[(size_t)g * LWS]);
-      stage_gradient_row<LWS, NR, NP, CT>(WS, g, sW + maxn, maxn, q);
-      stage_gradient_row<LWS, NR + NP + 1, NWS - NR - NP - 1, CT>(WS, g, sW + (1 + NP) * maxn, maxn, q);
-      stage_gradient_row<node_row(NC), CA, CB, CT>(G, g, sG, maxn, q);
+    for (int t = threadIdx.x; t < tps * ns; t += blockDim.x) {
+      const int h = t >= ns ? 1 : 0, q = t - h * ns;
+      const int g = slot_node_id(sSl[q]);
+      if (h == 0) {
+        sW[q] = CT(WS[(size_t)g * LWS]);
+        stage_gradient_row<LWS, NR, NP, CT>(WS, g, sW + maxn, maxn, q);
+        stage_gradient_row<LWS, NR + NP + 1, NWS - NR - NP - 1, CT>(WS, g, sW + (1 + NP) * maxn, maxn, q);
+        if (tps == 2)
+          stage_gradient_row<node_row(NC), CA, CB0, CT>(G, g, sG, maxn, q);
+        else
+          stage_gradient_row<node_row(NC), CA, CB, CT>(G, g, sG, maxn, q);
+      } else {
+        stage_gradient_row<node_row(NC), CA + CB0, CB - CB0, CT>(G, g, sG + CB0 * maxn, maxn, q);
+      }
     }
   }
   __syncthreads();
@@ -2242,24 +2265,26 @@ __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ WS,
   // into its partial; the update pass finishes every node.  (Most nodes of
   // a tetrahedral tile are shared anyway, and finishing the few owned ones
   // here set the pass's register peak.)
-  for (int q = threadIdx.x; q < ns; q += blockDim.x) {
+  // (two threads per slot: each sums half of the variables)
+  constexpr int NH = (NVAR + 1) / 2;
+  for (int t = threadIdx.x; t < tpn * ns; t += blockDim.x) {
+    const int h = t >= ns ? 1 : 0, q = t - h * ns;
     const SlotTopo st = slot_table_get(sSl, maxn, q);
+    const int v0 = tpn == 2 && h == 1 ? NH : 0, nv = tpn == 2 ? (h == 0 ? NH : NVAR - NH) : NVAR;
     double r[NVAR];
 #pragma unroll
     for (int v = 0; v < NVAR; ++v) r[v] = 0.0;
     for (int p = st.p0; p < st.p1; ++p) {
       const int code = sEi[p];
       const int le = code >> 1;
-      if (code & 1) {
+      const double sgn = (code & 1) ? -1.0 : 1.0;
 #pragma unroll
-        for (int v = 0; v < NVAR; ++v) r[v] -= sF[v * maxe + le];
-      } else {
-#pragma unroll
-        for (int v = 0; v < NVAR; ++v) r[v] += sF[v * maxe + le];
-      }
+      for (int v = 0; v < NVAR; ++v)
+        if (v < nv) r[v] += sgn * sF[(v0 + v) * maxe + le];
     }
 #pragma unroll
-    for (int v = 0; v < NVAR; ++v) PR[(size_t)st.pos * NVAR + v] = r[v];
+    for (int v = 0; v < NVAR; ++v)
+      if (v < nv) PR[(size_t)st.pos * NVAR + v0 + v] = r[v];
   }
 }
 
