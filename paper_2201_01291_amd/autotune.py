@@ -150,25 +150,39 @@ def pick_tiles(mesh, phys, U, E=None, cache: str = DEFAULT_CACHE, tune_if_missin
     return int(entry["tiles"][0]), int(entry["tiles"][1]), "tuned"
 
 
+# tile candidates for the size-sweep meshes (HBM-resident working sets,
+# long launches)
+LARGE_CANDIDATES = {
+    2: [(128, 96), (192, 144), (256, 192), (384, 288)],
+    3: [(96, 72), (128, 96), (192, 144)],
+}
+
+
 def _main():
     """Tune the benchmark workloads of bench.py (both precisions) into a
-    cache file: python -m paper_2201_01291_amd.autotune [cache] [workloads]."""
+    cache file: python -m paper_2201_01291_amd.autotune [cache] [workloads],
+    a workload as its name or name@size (the sizes of bench.py's sweep, e.g.
+    dd2d@4800x3000), the latter over LARGE_CANDIDATES."""
     import sys
     sys.path.insert(0, os.path.dirname(PKG))
     import bench
     path = sys.argv[1] if len(sys.argv) > 1 else DEFAULT_CACHE
     names = sys.argv[2].split(",") if len(sys.argv) > 2 else ["dd2d", "euler3d", "ns3d"]
     arch = device_arch()
-    for name in names:
-        print(f"[tune] building {name}", flush=True)
-        w = bench.Workload(name)
+    for item in names:
+        name, _, size = item.partition("@")
+        scale = tuple(int(v) for v in size.lower().split("x")) if size else None
+        print(f"[tune] building {item}", flush=True)
+        w = bench.Workload(name, scale)
         m = w.mesh
         physes = [w.vphys(0), w.vphys(1)]
-        entries = tune_many(m, physes, w.upload, w.E, steps=10 if name == "ns3d" else 50,
-                            log=lambda line: print(f"[tune] {name} {line}", flush=True))
+        cands = LARGE_CANDIDATES[m.ndim] if scale else None
+        entries = tune_many(m, physes, w.upload, w.E, candidates=cands,
+                            steps=10 if name == "ns3d" or scale else 50,
+                            log=lambda line: print(f"[tune] {item} {line}", flush=True))
         for ph, entry in zip(physes, entries):
             store(path, tune_key(arch, m.ndim, ph, m.ncells), entry)
-            print(f"[tune] {name} precision {ph.precision}: {entry['tiles']} {entry['table']}", flush=True)
+            print(f"[tune] {item} precision {ph.precision}: {entry['tiles']} {entry['table']}", flush=True)
 
 
 if __name__ == "__main__":
