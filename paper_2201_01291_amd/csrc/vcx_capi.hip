@@ -597,8 +597,8 @@ vcx_status vcx::configure_solver(vcx_solver s, vcx_mesh mesh, const vcx_physics&
   // (the predictor and the Scharfetter-Gummel flux take the separate passes too)
   const bool sg = ph.model == VCX_MODEL_DRIFT_DIFFUSION && ph.flux == VCX_FLUX_SG;
   // Drift-diffusion meshes above kFusedMaxCells take the separate passes
-  // (on simplices the node gradient, whose tables the solver builds, else the
-  // tile gradient and the shared-node completion), which outrun the fused
+  // (on simplices the node gradient with a node-major G, else the tile
+  // gradient and the shared-node completion), which outrun the fused
   // pass once the launches are long, while the fused pass's two launches win
   // on small meshes.
   const bool big_dd = ph.model == VCX_MODEL_DRIFT_DIFFUSION && d.nc > kFusedMaxCells;
@@ -761,7 +761,7 @@ extern "C" vcx_status vcx_gradient(vcx_solver s, double* G, int is_device) {
   GradCtl gc{nullptr, 0, 0};
   VCX_TRY(s->kt->grad(s, s->W[s->cur], gc));
   VCX_TRY(s->kt->grad_complete(s));
-  if (node_gradient(s->ph.model, s->nd, s->mesh->h.nv)) {
+  if (node_gradient(s->ph.model, s->nd, s->mesh->h.nv) || s->dd_ngrad) {
     // node-major gradient rows: their first nr * nd components
     const int nn = s->mesh->d.nn;
     double* target = is_device ? G : s->io;

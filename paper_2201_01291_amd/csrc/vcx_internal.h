@@ -65,7 +65,7 @@ struct vcx_solver_s {
   double* WS[2] = {nullptr, nullptr};
   int nws = 0, ldws = 0;
   // drift-diffusion on large simplex meshes: the node-gradient pass with a
-  // component-major G (no partial sums, no completion)
+  // node-major G (no partial sums, no completion)
   bool dd_ngrad = false;
   int cur = 0;
   double* G = nullptr;
@@ -293,7 +293,7 @@ struct Impl {
       if constexpr (MODEL == 1 && SIMPLEX) {
         if (s->dd_ngrad)
           return launch(s, "gradient", [&](hipEvent_t ea, hipEvent_t eb) {
-            hipExtLaunchKernelGGL((k_grad_node<ND, NGF, false, true>), dim3(xcd_grid(m.ng_nslices) + lead),
+            hipExtLaunchKernelGGL((k_grad_node<ND, NGF>), dim3(xcd_grid(m.ng_nslices) + lead),
                                   dim3(64 * kGradNodeGroups), 0, s->mesh->stream, ea, eb, 0, m, Win,
                                   (const double*)nullptr, 0, s->G, gc);
           });
@@ -489,7 +489,7 @@ struct Impl {
     // multi-species: the node-gradient pass leaves G complete, as in the
     // single solve
     FinishShared fs{dt_coef(s->ph), mix_params(s->ph), s->ph.closure, br.fused ? 1 : 0,
-                    MODEL == 2 || br.dd_ngrad ? 1 : 0};
+                    MODEL == 2 || br.dd_ngrad ? 1 : 0, br.dd_ngrad ? 1 : 0};
     if constexpr (FUSABLE) {
       if (br.fused) {
         GasParams gp{s->ph.gamma, s->ph.beta, s->ph.entropy_fix, s->ph.limiter};
@@ -514,7 +514,7 @@ struct Impl {
       }));
     } else if (MODEL == 1 && br.dd_ngrad) {
       VCX_TRY(launch_on(s, stream, prof, "gradient", [&](hipEvent_t ea, hipEvent_t eb) {
-        hipExtLaunchKernelGGL((k_grad_node_batch<ND, NGF, false, true>), dim3(xcd_grid(br.ngrad_blocks)),
+        hipExtLaunchKernelGGL((k_grad_node_batch<ND, NGF>), dim3(xcd_grid(br.ngrad_blocks)),
                               dim3(64 * kGradNodeGroups), 0, stream, ea, eb, 0, (const BatchEntry*)br.tab,
                               (const int2*)br.grad_map, br.ngrad_blocks, st);
       }));
@@ -601,6 +601,7 @@ inline Finish make_finish(vcx_solver s) {
   // fused passes with a closure that reads gradients complete G on every
   // node; so do the node-gradient passes
   f.gfull = (s->fused && s->gout != nullptr) || s->ph.model == VCX_MODEL_NAVIER_STOKES || s->dd_ngrad;
+  f.gnode = s->dd_ngrad ? 1 : 0;
   return f;
 }
 

@@ -885,10 +885,8 @@ __global__ void __launch_bounds__(256) k_grad_shared(DevMesh m, const double* __
 #endif
 constexpr int kGradNodeGroups = VCX_GRAD_NODE_GROUPS;
 // WSR: the fields come from the node-major staged rows WS ([nn][ldws]) of
-// the multi-species model instead of the component-major W.  CMAJ: G is
-// written component-major ([NR * ND][nn], the layout of the tile-gradient
-// models) straight from the lanes, coalesced.
-template <int ND, int NR, bool WSR = false, bool CMAJ = false>
+// the multi-species model instead of the component-major W.
+template <int ND, int NR, bool WSR = false>
 __device__ inline void grad_node_body(const DevMesh& m, const double* __restrict__ W,
                                       const double* __restrict__ WS, int ldws,
                                       double* __restrict__ G, const GradCtl& ctl, int sl) {
@@ -929,24 +927,17 @@ __device__ inline void grad_node_body(const DevMesh& m, const double* __restrict
     for (int f = 0; f < FG; ++f)
       if (v0 + f < NR)
 #pragma unroll
-        for (int d = 0; d < ND; ++d) {
-          if constexpr (CMAJ)
-            G[(size_t)((v0 + f) * ND + d) * m.nn + i] = coef * acc[f][d];
-          else
-            sg[lane * LD + (v0 + f) * ND + d] = coef * acc[f][d];
-        }
+        for (int d = 0; d < ND; ++d) sg[lane * LD + (v0 + f) * ND + d] = coef * acc[f][d];
   }
-  if constexpr (!CMAJ) {
-    __syncthreads();
-    double* out = G + (size_t)sl * 64 * NCP;
-    for (int idx = threadIdx.x; idx < nb * NCP; idx += blockDim.x) {
-      const int l = idx / NCP, c = idx - l * NCP;
-      out[idx] = c < NC ? sg[l * LD + c] : 0.0;  // (the padding component of an odd row: 0)
-    }
+  __syncthreads();
+  double* out = G + (size_t)sl * 64 * NCP;
+  for (int idx = threadIdx.x; idx < nb * NCP; idx += blockDim.x) {
+    const int l = idx / NCP, c = idx - l * NCP;
+    out[idx] = c < NC ? sg[l * LD + c] : 0.0;  // (the padding component of an odd row: 0)
   }
 }
 
-template <int ND, int NR, bool WSR = false, bool CMAJ = false>
+template <int ND, int NR, bool WSR = false>
 __global__ void __launch_bounds__(64 * kGradNodeGroups) k_grad_node(DevMesh m, const double* __restrict__ W,
                                                    const double* __restrict__ WS, int ldws,
                                                    double* __restrict__ G, GradCtl ctl) {
@@ -959,7 +950,7 @@ __global__ void __launch_bounds__(64 * kGradNodeGroups) k_grad_node(DevMesh m, c
   }
   const int sl = xcd_tile_of((int)blockIdx.x - lead, m.ng_nslices);
   if (sl >= m.ng_nslices) return;
-  grad_node_body<ND, NR, WSR, CMAJ>(m, W, WS, ldws, G, ctl, sl);
+  grad_node_body<ND, NR, WSR>(m, W, WS, ldws, G, ctl, sl);
 }
 
 // ---------------------------------------------------------------------------
@@ -982,6 +973,7 @@ struct Finish {
   int roll_par;         //   candidate slots over (step_rollover) for this parity
   int gfull;            // G holds the gradients of shared nodes too (fused passes; the
                         // multi-species pass after the shared-node gradient completion)
+  int gnode;            // drift-diffusion: G is node-major (rows of node_row(NSP * ND))
   DtCoef dc;
   MixParams mix;        // Navier-Stokes species data
   double alpha;
@@ -1065,7 +1057,10 @@ __device__ inline void closure_flux(const DevMesh& m, const Finish& f, int k, bo
     for (int s = 0; s < NSP; ++s) F[2 + ND + s] = Wk[2 + ND + s] * q;
   } else {
     double gr[NSP * ND];
-    if (shared && !f.gfull) {
+    if (f.gnode) {
+#pragma unroll
+      for (int j = 0; j < NSP * ND; ++j) gr[j] = f.G[(size_t)k * node_row(NSP * ND) + j];
+    } else if (shared && !f.gfull) {
       shared_gradient<NSP * ND, ND>(m, f.PG, k, make_int2(m.node_slot[k], m.node_slot[k + 1]), gr);
     } else {
 #pragma unroll
@@ -1668,7 +1663,10 @@ __device__ inline void flux_dd_body(DevMesh m, const double* __restrict__ U,
       xe[d] = m.x[(size_t)d * m.nn + g];
       xe[ND + d] = E[(size_t)d * m.nn + g];
     }
-    stage_gradient<NS * ND, ND, CT>(m, G, f.PG, f.gfull ? g : sv, st.run, sG, maxn, q);
+    if (f.gnode)
+      stage_gradient_row<node_row(NS * ND), 0, NS * ND, CT>(G, g, sG, maxn, q);
+    else
+      stage_gradient<NS * ND, ND, CT>(m, G, f.PG, f.gfull ? g : sv, st.run, sG, maxn, q);
 #pragma unroll
     for (int s = 0; s < NS; ++s) sU[s * maxn + q] = CT(u[s]);
 #pragma unroll
@@ -2521,6 +2519,7 @@ struct FinishShared {
   int closure;
   int fused;        // the stage runs the fused gradient + flux pass
   int gcomplete;    // G is complete on shared nodes before the flux pass (multi-species)
+  int gnode;        // drift-diffusion node-gradient pass: G node-major
 };
 
 __device__ inline Finish batch_finish(const BatchEntry& e, const BatchStage& st,
@@ -2545,6 +2544,7 @@ __device__ inline Finish batch_finish(const BatchEntry& e, const BatchStage& st,
     f.roll_par = par;
   }
   f.gfull = (fs.fused && e.gout != nullptr) || fs.gcomplete;
+  f.gnode = fs.gnode;
   f.dc = fs.dc;
   f.mix = fs.mix;
   f.alpha = st.alpha;
@@ -2578,7 +2578,7 @@ __global__ void __launch_bounds__(256) k_grad_tile_batch(const BatchEntry* __res
 
 // node gradient of every solve of a batch (block map: solve, node slice;
 // slice -1 is the solve's decision entry)
-template <int ND, int NR, bool WSR = false, bool CMAJ = false>
+template <int ND, int NR, bool WSR = false>
 __global__ void __launch_bounds__(64 * kGradNodeGroups) k_grad_node_batch(const BatchEntry* __restrict__ tab,
                                                          const int2* __restrict__ map, int nblocks,
                                                          BatchStage st) {
@@ -2595,7 +2595,7 @@ __global__ void __launch_bounds__(64 * kGradNodeGroups) k_grad_node_batch(const 
   const double* Win = st.stage == 1 ? e.W[cur] : e.W[cur ^ 1];
   GradCtl ctl{e.lp, par, st.stage == 1 ? 1 : 0};
   const double* WSin = st.stage == 1 ? e.WS[cur] : e.WS[cur ^ 1];
-  grad_node_body<ND, NR, WSR, CMAJ>(e.m, Win, WSin, e.ldws, e.G, ctl, ml.y);
+  grad_node_body<ND, NR, WSR>(e.m, Win, WSin, e.ldws, e.G, ctl, ml.y);
 }
 
 template <int ND, int NSP, int FLUX, typename CT>
