@@ -486,8 +486,8 @@ struct Impl {
   }
   static vcx_status batch_stage_simplex(const BatchRun& br, hipStream_t stream, const BatchStage& st, bool prof) {
     vcx_solver s = br.lead;
-    // multi-species: the node-gradient pass leaves G complete, as in the
-    // single solve
+    // the node-gradient passes (multi-species; drift-diffusion on large
+    // meshes) leave G complete, as in the single solve
     FinishShared fs{dt_coef(s->ph), mix_params(s->ph), s->ph.closure, br.fused ? 1 : 0,
                     MODEL == 2 || br.dd_ngrad ? 1 : 0, br.dd_ngrad ? 1 : 0};
     if constexpr (FUSABLE) {

@@ -822,8 +822,9 @@ __device__ inline void stage_gradient(const DevMesh& m, const double* __restrict
   }
 }
 
-// complete G on the shared nodes (gradient output only; the time loop reads
-// the partials directly)
+// Complete G on the shared nodes of a tile-gradient pass (the
+// drift-diffusion flux launcher runs it once per stage, so that its flux pass
+// and closure read complete rows; also the gradient output).
 // A block takes kGradSharedNodes shared nodes: its threads walk the (node,
 // component) pairs component-fastest, so the reads of a partial row are
 // contiguous, sum each component over the node's partials in run order
@@ -971,8 +972,9 @@ struct Finish {
   long long* cand;      // candidate slots of this step's new state
   DevLoop* roll;        // fused passes: the shared-node pass of the first stage rolls the
   int roll_par;         //   candidate slots over (step_rollover) for this parity
-  int gfull;            // G holds the gradients of shared nodes too (fused passes; the
-                        // multi-species pass after the shared-node gradient completion)
+  int gfull;            // G holds the gradients of shared nodes too (fused passes with a
+                        // closure, the node-gradient passes, the drift-diffusion flux
+                        // pass after the shared-node completion)
   int gnode;            // drift-diffusion: G is node-major (rows of node_row(NSP * ND))
   DtCoef dc;
   MixParams mix;        // Navier-Stokes species data
@@ -2005,17 +2007,6 @@ __global__ void VCX_FUSED_BOUNDS k_fused(DevMesh m, const double* __restrict__ W
 // first NR + NP rows.
 // ---------------------------------------------------------------------------
 
-// Rows [r0, r0 + N) of node g into LDS rows [d0, d0 + N) (loads first).
-template <int N, typename CT>
-__device__ inline void stage_rows(const double* __restrict__ W, size_t nn, int g, int r0, CT* s, int d0,
-                                  int maxn, int q) {
-  double w[N];
-#pragma unroll
-  for (int v = 0; v < N; ++v) w[v] = W[(size_t)(r0 + v) * nn + g];
-#pragma unroll
-  for (int v = 0; v < N; ++v) s[(d0 + v) * maxn + q] = CT(w[v]);
-}
-
 // Multi-species flux tile pass over the tile's distinct edges.  For an edge
 // (a, b) the MUSCL face states (virtual-node reconstruction with the nodal
 // gradients) depend on its two nodes only, so they are formed once per edge;
@@ -2023,7 +2014,9 @@ __device__ inline void stage_rows(const double* __restrict__ W, size_t nn, int g
 // dual-face vector (the flux is not linear in it); the central diffusive
 // flux is linear in the dual-face vector, so it is taken once with their
 // sum.  The edge's net flux F goes to node a as +F and to node b as -F; each
-// node sums its edges in a fixed order (node pass), then the update.
+// slot sums its edges in a fixed order into its partial (node pass), and the
+// update pass finishes every node.  The node data come from the node-major
+// staged rows WS and the node-major G.
 // AXI: axisymmetric (x, r) meshes; every cell-edge's dual-face vector is
 // weighted by the centroid radius of its face piece (revolved face over
 // 2 pi) and the diffusive flux takes the cylindrical div u.
@@ -2518,7 +2511,7 @@ struct FinishShared {
   MixParams mix;
   int closure;
   int fused;        // the stage runs the fused gradient + flux pass
-  int gcomplete;    // G is complete on shared nodes before the flux pass (multi-species)
+  int gcomplete;    // G is complete on shared nodes before the flux pass (node-gradient passes)
   int gnode;        // drift-diffusion node-gradient pass: G node-major
 };
 
