@@ -200,11 +200,17 @@ static vcx_status create_mesh(int ndim, int64_t nnodes, const double* xyz, int64
     return fail(code == -2 ? VCX_E_MESH : VCX_E_ARG, err);
   }
   m->stream = static_cast<hipStream_t>(stream);
-  if (hipGetDevice(&m->device) != hipSuccess ||
-      hipDeviceGetAttribute(&m->lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, m->device) !=
-          hipSuccess) {
+  // (the device count first: it initialises the runtime in a process whose
+  // first HIP call this is)
+  int ndev = 0;
+  hipError_t he = hipGetDeviceCount(&ndev);
+  if (he == hipSuccess && ndev <= 0) he = hipErrorNoDevice;
+  if (he == hipSuccess) he = hipGetDevice(&m->device);
+  if (he == hipSuccess)
+    he = hipDeviceGetAttribute(&m->lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, m->device);
+  if (he != hipSuccess) {
     delete m;
-    return fail(VCX_E_HIP, "no HIP device");
+    return fail(VCX_E_HIP, std::string("no usable HIP device: ") + hipGetErrorString(he));
   }
   const HostMesh& h = m->h;
   DevMesh& d = m->d;

@@ -434,7 +434,11 @@ extern "C" vcx_status vcx_server_create(size_t hbm_budget, int max_slots, int ch
   sv->max_slots = max_slots;
   sv->chunk = chunk_steps;
   sv->graphs = use_graphs != 0;
-  if (hipGetDevice(&sv->device) != hipSuccess || hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking) != hipSuccess) {
+  // (the device count first: it initialises the runtime in a process whose
+  // first HIP call this is)
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0 || hipGetDevice(&sv->device) != hipSuccess ||
+      hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking) != hipSuccess) {
     delete sv;
     return set_err(VCX_E_HIP, "no device or stream");
   }

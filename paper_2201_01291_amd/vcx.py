@@ -91,6 +91,14 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -m paper_2201_01291_amd.build`")
+        # PyTorch, where installed, loads its own copy of the HIP runtime by
+        # path; loaded first, it is the copy the library binds to (a second
+        # copy loaded after the library's would hold the device, and the
+        # library's first call would find none)
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         vp, dp, i64p = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)
         L.vcx_mesh_create.argtypes = [C.c_int, C.c_int64, dp, C.c_int64, C.c_int, i64p, dp, vp,
