@@ -8,6 +8,8 @@ not.  States after N steps: max |dU| / max |U| <= 1e-12 per variable.
 Mixed precision (FP32 flux) errors are measured and printed; the bound
 asserted for them is stated in each test.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -209,6 +211,27 @@ def test_full_size_drift_diffusion_residual_and_steps():
     Uo, *_ = om.step(ph, n, E, nsteps=3)
     s.step(3)
     assert state_err(case, s.download(), Uo).max() <= FP64_TOL
+
+
+def test_binding_first_in_a_fresh_process():
+    """A process whose first GPU work goes through the binding (PyTorch not
+    imported before it) creates a mesh and a solver and takes a step: the
+    library and PyTorch share one copy of the HIP runtime."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("from paper_2201_01291_amd import vcx, workloads as wl\n"
+            "m = wl.tri_rect_mesh(16, 12, periodic=True)\n"
+            "n, E = wl.dd_fields(m, sigma=2e-3)\n"
+            "gm = vcx.Mesh(m)\n"
+            "s = vcx.Solver(gm, vcx.physics(model=vcx.MODEL_DRIFT_DIFFUSION, nspecies=2, z=[1.0, -1.0],"
+            " mu=[0.03, 0.05], D=[0.1, 0.2]), E)\n"
+            "s.upload(n)\n"
+            "s.step(2)\n"
+            "print('ok', s.download().shape)\n")
+    out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=300)
+    print(out.stdout, out.stderr[-2000:])
+    assert out.returncode == 0 and "ok" in out.stdout
 
 
 def test_large_drift_diffusion_mesh_on_the_separate_passes():
