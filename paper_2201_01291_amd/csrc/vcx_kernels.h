@@ -2056,6 +2056,15 @@ __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ WS,
     pq0 = m.edge_ce[e0 + threadIdx.x];
     pq1 = m.edge_ce[e0 + threadIdx.x + 1];
   }
+  // the topology of this thread's first cell, loaded with the edge
+  // descriptors (both overlap the staging)
+  int pl[NV];
+  uint32_t pshift = 0;
+  if ((int)threadIdx.x < nc) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) pl[k] = m.lconn[(size_t)k * m.nc + c0 + threadIdx.x];
+    pshift = m.shift[c0 + threadIdx.x];
+  }
   // The node pass, and the FP32 path's staging, take two threads per slot
   // where the block has them (half h of slot q at thread h * ns + q, so that
   // a wavefront's lanes mostly take the same half).  Staging halves: the
@@ -2095,11 +2104,12 @@ __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ WS,
   __syncthreads();
   // ---- dual-face vectors of every cell-edge: S_ab = (S_a - S_b) / (n_d n_v)
   for (int lc = threadIdx.x; lc < nc; lc += blockDim.x) {
+    const bool first = lc == (int)threadIdx.x;
     int l[NV];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) l[k] = m.lconn[(size_t)k * m.nc + c0 + lc];
+    for (int k = 0; k < NV; ++k) l[k] = first ? pl[k] : (int)m.lconn[(size_t)k * m.nc + c0 + lc];
     double e[ND][ND], Sd[NV][ND];
-    cell_rel_coords<ND>(m, sX, maxn, l, m.shift[c0 + lc], e);
+    cell_rel_coords<ND>(m, sX, maxn, l, first ? pshift : m.shift[c0 + lc], e);
     simplex_normals<ND>(e, Sd);
     double rr[NV], rc = 0.0;
     if constexpr (AXI) {
