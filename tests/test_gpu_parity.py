@@ -2,9 +2,9 @@
 the same seeded inputs.
 
 Bar: FP64 path within 1e-12 norm-wise -- max_i |r_gpu - r_oracle| divided by
-max_i sum_f |F_f . S_f| (per variable), the survey's residual norm, since a
-residual is a difference of face fluxes and can vanish where the fluxes do
-not.  States after N steps: max |dU| / max |U| <= 1e-12 per variable.
+max_i sum_f |F_f . S_f| (per variable), a residual norm scaled by the face
+fluxes, since a residual is a difference of face fluxes and can vanish where
+the fluxes do not.  States after N steps: max |dU| / max |U| <= 1e-12 per variable.
 Mixed precision (FP32 flux) errors are measured and printed; the bound
 asserted for them is stated in each test.
 """
