@@ -95,9 +95,9 @@ struct DevMesh {
   const uint16_t* ce;        // [nc*ne] (local cell << 4) | (cell-local edge << 1) | reversed
   const int32_t* slot_einc;  // [P+1] CSR into einc
   const uint16_t* einc;      // [2E] (tile edge << 1) | (slot's node is end b)
-  // node gradient (the multi-species gradient pass): per 64-node slice, the
-  // neighbours of each node and their coefficients C_ij, entry k of the
-  // slice's node l at ng_off[slice] + 64 k + l
+  // node gradient: per 64-node slice, the neighbours j != i of each node and
+  // their coefficients C_ij, entry k of the slice's node l at
+  // ng_off[slice] + 64 k + l (pad entries: j = i, C = 0)
   int has_ngrad, ng_nslices;
   long long ng_total;
   const long long* ng_off;   // [nslices+1]
@@ -872,11 +872,12 @@ __global__ void __launch_bounds__(256) k_grad_shared(DevMesh m, const double* __
   grad_shared_body<ND, NR>(m, PG, G, (int)blockIdx.x * kGradSharedNodes);
 }
 
-// Node gradient: G_i = -1/(nd nv V_i) sum_j W_j C_ij over the node's
-// neighbours j in ascending order (the cell sum regrouped by neighbour; no
-// partial sums).  A block takes one 64-node slice: each of its four
-// wavefronts takes a quarter of the fields for the slice's 64 nodes (lane =
-// node), so the loads of a neighbour index, its coefficients and a field row
+// Node gradient: G_i = -1/(nd nv V_i) sum_{j != i} (W_j - W_i) C_ij over the
+// node's neighbours j in ascending order (the cell sum regrouped by
+// neighbour, the node's own term folded in through C_ii = -sum_{j != i} C_ij,
+// which holds since a simplex's node normals sum to zero; no partial sums).  A block takes one 64-node slice: each of its
+// kGradNodeGroups wavefronts takes an equal share of the fields for the
+// slice's 64 nodes (lane = node), so the loads of a neighbour index, its coefficients and a field row
 // are coalesced across the wavefront.  G is node-major (the NR * ND
 // components of a node contiguous, component v * ND + d, rows of
 // node_row(NR * ND)): the block gathers the slice's rows in LDS and writes
@@ -902,11 +903,14 @@ __device__ inline void grad_node_body(const DevMesh& m, const double* __restrict
   if (lane < nb && v0 < NR) {
     const long long o0 = m.ng_off[sl];
     const int w = (int)((m.ng_off[sl + 1] - o0) >> 6);
-    double acc[FG][ND];
+    double acc[FG][ND], wi[FG];
 #pragma unroll
-    for (int f = 0; f < FG; ++f)
+    for (int f = 0; f < FG; ++f) {
+      wi[f] = 0.0;
+      if (v0 + f < NR) wi[f] = WSR ? WS[(size_t)i * ldws + v0 + f] : W[(size_t)(v0 + f) * m.nn + i];
 #pragma unroll
       for (int d = 0; d < ND; ++d) acc[f][d] = 0.0;
+    }
 #pragma unroll 2
     for (int k = 0; k < w; ++k) {
       const long long q = o0 + (long long)k * 64 + lane;
@@ -917,9 +921,9 @@ __device__ inline void grad_node_body(const DevMesh& m, const double* __restrict
 #pragma unroll
       for (int f = 0; f < FG; ++f) {
         if (v0 + f < NR) {
-          const double wv = WSR ? WS[(size_t)j * ldws + v0 + f] : W[(size_t)(v0 + f) * m.nn + j];
+          const double dw = (WSR ? WS[(size_t)j * ldws + v0 + f] : W[(size_t)(v0 + f) * m.nn + j]) - wi[f];
 #pragma unroll
-          for (int d = 0; d < ND; ++d) acc[f][d] += wv * c[d];
+          for (int d = 0; d < ND; ++d) acc[f][d] += dw * c[d];
         }
       }
     }

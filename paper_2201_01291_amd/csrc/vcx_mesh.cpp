@@ -169,9 +169,9 @@ std::string build_tiling(const HostMesh& m, TileLimits lim, Tiling& out) {
   return "";
 }
 
-// Node-gradient tables: neighbours of each node (itself included) in
-// ascending order and C_ij = sum over the cells c holding i and j of S_j^c,
-// accumulated in ascending cell order; then the 64-node slices.
+// Node-gradient tables: neighbours j != i of each node in ascending order
+// and C_ij = sum over the cells c holding i and j of S_j^c, accumulated in
+// ascending cell order; then the 64-node slices.
 std::string build_node_gradient(HostMesh& m) {
   const int nd = m.nd, nv = m.nv;
   const int64_t nn = m.nn, nc = m.nc;
@@ -197,6 +197,10 @@ std::string build_node_gradient(HostMesh& m) {
       for (int k = 0; k < nv; ++k) tmp.push_back(m.cell[(size_t)k * nc + cells_of[q]]);
     std::sort(tmp.begin(), tmp.end());
     tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
+    // the node itself is left out: a simplex's node normals sum to zero, so
+    // its coefficient is minus the sum of the others and the gradient takes
+    // the differences W_j - W_i instead
+    tmp.erase(std::lower_bound(tmp.begin(), tmp.end(), (int32_t)i));
     nb.insert(nb.end(), tmp.begin(), tmp.end());
     np[i + 1] = (int64_t)nb.size();
   }
@@ -212,6 +216,7 @@ std::string build_node_gradient(HostMesh& m) {
       relative_coords(m, m.x.data(), v, m.shift[c], e);
       node_normals(nd, e, S);
       for (int k = 0; k < nv; ++k) {
+        if (v[k] == i) continue;
         const int64_t at = std::lower_bound(row, row + deg, (int32_t)v[k]) - row;
         for (int d = 0; d < nd; ++d) cv[(size_t)(np[i] + at) * nd + d] += S[k][d];
       }

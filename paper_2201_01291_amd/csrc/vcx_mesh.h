@@ -109,13 +109,14 @@ struct HostMesh {
   std::vector<uint16_t> einc;      // [2E] per slot: (tile edge << 1) | (1 if the slot's node is end b)
   int max_tile_edges = 0;
 
-  // node gradient (the multi-species gradient pass; built on demand by
-  // build_node_gradient): for each node i its neighbours j, the nodes of its
-  // cells with i itself, ascending, and C_ij, the sum of the node normals
-  // S_j of the cells holding both i and j, so that the cell-sum gradient is
-  // G_i = -1/(nd nv V_i) sum_j W_j C_ij.  Nodes in slices of 64 (one per
-  // wavefront), each slice padded to its largest neighbour count (pad
-  // entries: j = i, C = 0); entry k of the slice's node l at off + 64 k + l.
+  // node gradient (built by build_node_gradient): for each node i its
+  // neighbours j, the other nodes of its cells, ascending, and C_ij, the sum
+  // of the node normals S_j of the cells holding both i and j.  A simplex's
+  // node normals sum to zero, so C_ii = -sum_{j != i} C_ij and the cell-sum
+  // gradient is G_i = -1/(nd nv V_i) sum_{j != i} (W_j - W_i) C_ij.  Nodes in
+  // slices of 64 (one per wavefront), each slice padded to its largest
+  // neighbour count (pad entries: j = i, C = 0); entry k of the slice's node
+  // l at off + 64 k + l.
   static constexpr int kNgSlice = 64;
   bool has_ngrad = false;
   std::vector<int64_t> ng_off;  // [nslices + 1]
