@@ -56,7 +56,7 @@ struct vcx_solver_s {
   vcx_mesh mesh = nullptr;
   vcx_physics ph{};
   int nd = 0, nvar = 0, nr = 0;
-  int nw = 0;   // rows of a state buffer (conserved, pressure, Navier-Stokes primitives and aux)
+  int nw = 0;   // rows of a state buffer (conserved, then pressure unless drift-diffusion)
   int ngf = 0;  // fields whose nodal gradients are computed
   double* W[2] = {nullptr, nullptr};
   // multi-species: node-major copies [nn][ldws] of the first nws rows of each
@@ -218,9 +218,9 @@ struct Impl {
   static constexpr int NR = MODEL == 1 ? NVAR : NVAR + 1;
   static constexpr bool SIMPLEX = NV == ND + 1;
   static constexpr int NP = MODEL == 2 ? ND + 1 + NSP : 0;   // primitives (u, T, Y)
-  static constexpr int NA = MODEL == 2 ? 3 + 2 * NSP : 0;    // gamma, mu, lambda, D_k, hs_k
   static constexpr int NGF = NR + NP;                        // fields with gradients
-  static constexpr int NW = NR + NP + NA;                    // rows of a state buffer
+  static constexpr int NW = NR;  // rows of a state buffer: U, then p (the multi-species
+                                 // primitives and aux live in the staged rows WS)
 
   static size_t lds_grad(int maxn, int maxc) {
     constexpr int FG = grad_group(NGF);  // fields staged per pass
@@ -407,9 +407,13 @@ struct Impl {
   }
   static vcx_status update_shared(vcx_solver s, const Finish& f) {
     const DevMesh& m = s->mesh->d;
+    Finish g = f;
+    g.WSin = ws_of(s, f.Win);  // the stage input's staged rows (multi-species)
+    if (MODEL == 2 && (!g.WSin || (!g.residual_only && !g.WSout)))
+      return fail(VCX_E_STATE, "multi-species update without its staged rows");
     return launch(s, "update", [&](hipEvent_t ea, hipEvent_t eb) {
       hipExtLaunchKernelGGL((k_update_shared<ND, NSP, MODEL>), dim3(s->nsh_blocks), dim3(kNodeBlock), 0,
-                         s->mesh->stream, ea, eb, 0, m, (const double*)s->PR, f);
+                         s->mesh->stream, ea, eb, 0, m, (const double*)s->PR, g);
     });
   }
   static vcx_status node_dt(vcx_solver s, const double* W) {

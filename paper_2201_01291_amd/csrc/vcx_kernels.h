@@ -985,8 +985,10 @@ struct Finish {
   double alpha;
   int closure, final_stage, residual_only;
   const double* cbuf;   // second closure option: [nb][NVAR] closure fluxes of the stage input
-  // multi-species: node-major copy of the stage output's first nws rows
-  // ([nn][ldws]), written beside Wout, or null
+  // multi-species: node-major rows ([nn][ldws], the first nws used) of the
+  // stage input and output; the primitives and transport data of a node
+  // are kept there only (the component-major buffers hold U and p)
+  const double* WSin;
   double* WSout;
   int nws, ldws;
 };
@@ -1088,14 +1090,16 @@ __device__ inline void closure_flux(const DevMesh& m, const Finish& f, int k, bo
 // Axisymmetric multi-species: the hoop stress tau_theta_theta of node i,
 // 2 eta u_r/r + lambda (u_r/r + du_r/dr + du_x/dx) with lambda = -2/3 eta
 // (Stokes), u_r/r taking its limit du_r/dr on the axis.  The two velocity
-// derivatives come from the node's (node-major) gradient row.
+// derivatives come from the node's (node-major) gradient row, u_r and eta
+// from its staged row.
 template <int ND, int NSP>
 __device__ inline double ns_hoop_stress(const DevMesh& m, const Finish& f, int i) {
   constexpr int NVAR = 2 + ND + NSP, NR = NVAR + 1, NP = ND + 1 + NSP, NCP = node_row((NR + NP) * ND);
   constexpr int CR = (NR + 1) * ND + 1, CX = NR * ND;  // du_r/dr, du_x/dx
   const double durdr = f.G[(size_t)i * NCP + CR];
   const double duxdx = f.G[(size_t)i * NCP + CX];
-  const double eta = f.Win[(size_t)(NR + NP + 1) * m.nn + i], ur = f.Win[(size_t)(NR + 1) * m.nn + i];
+  const double* row = f.WSin + (size_t)i * f.ldws;
+  const double eta = row[NR + NP + 1], ur = row[NR + 1];  // aux[1], prim[1]
   const double rr = m.x[(size_t)m.nn + i];
   const double hoop = rr > 0.0 ? ur / rr : durdr;
   return 2.0 * eta * hoop - 2.0 / 3.0 * eta * (hoop + durdr + duxdx);
@@ -1186,11 +1190,7 @@ __device__ inline double finish_node(const DevMesh& m, const Finish& f, int i, b
     double prim[NP], aux[NA];
     ok = ns_node_state<ND, NSP>(f.mix, u, p, prim, aux);
     f.Wout[(size_t)NVAR * m.nn + i] = p;
-#pragma unroll
-    for (int q = 0; q < NP; ++q) f.Wout[(size_t)(NVAR + 1 + q) * m.nn + i] = prim[q];
-#pragma unroll
-    for (int q = 0; q < NA; ++q) f.Wout[(size_t)(NVAR + 1 + NP + q) * m.nn + i] = aux[q];
-    if (f.WSout) ns_store_node_row<ND, NSP>(f.WSout + (size_t)i * f.ldws, f.nws, u, p, prim, aux);
+    ns_store_node_row<ND, NSP>(f.WSout + (size_t)i * f.ldws, f.nws, u, p, prim, aux);
 #pragma unroll
     for (int v = 0; v < NVAR; ++v) ok = ok && isfinite(u[v]);
     if (!f.final_stage) return INFINITY;
@@ -2338,7 +2338,8 @@ __global__ void __launch_bounds__(256) k_prim_to_cons(double* __restrict__ W, in
   W[(size_t)(1 + ND) * nn + i] = e;
 }
 
-// multi-species node rows (p, primitives, aux) of an uploaded state
+// multi-species node data of an uploaded state: p (component-major, beside U)
+// and the node-major staged row
 template <int ND, int NSP>
 __global__ void __launch_bounds__(256) k_ns_aux(double* __restrict__ W, int nn, MixParams mp,
                                                 double* __restrict__ WS, int nws, int ldws) {
@@ -2350,11 +2351,7 @@ __global__ void __launch_bounds__(256) k_ns_aux(double* __restrict__ W, int nn, 
   for (int v = 0; v < NVAR; ++v) u[v] = W[(size_t)v * nn + i];
   ns_node_state<ND, NSP>(mp, u, p, prim, aux);
   W[(size_t)NVAR * nn + i] = p;
-#pragma unroll
-  for (int q = 0; q < NP; ++q) W[(size_t)(NVAR + 1 + q) * nn + i] = prim[q];
-#pragma unroll
-  for (int q = 0; q < NA; ++q) W[(size_t)(NVAR + 1 + NP + q) * nn + i] = aux[q];
-  if (WS) ns_store_node_row<ND, NSP>(WS + (size_t)i * ldws, nws, u, p, prim, aux);
+  ns_store_node_row<ND, NSP>(WS + (size_t)i * ldws, nws, u, p, prim, aux);
 }
 
 // ---------------------------------------------------------------------------
@@ -2414,14 +2411,13 @@ __global__ void __launch_bounds__(256) k_node_dt(DevMesh m, const double* __rest
     double u[NVAR];
 #pragma unroll
     for (int v = 0; v < NVAR; ++v) u[v] = W[(size_t)v * m.nn + i];
-    const double p = MODEL != 1 ? W[(size_t)NVAR * m.nn + i] : 0.0;
+    double p = MODEL != 1 ? W[(size_t)NVAR * m.nn + i] : 0.0;
     if constexpr (MODEL == 2) {
+      // primitives and transport data formed again from U, as the update
+      // and the upload form them (the same function of U, so the same values)
       constexpr int NP = ND + 1 + NSP, NA = 3 + 2 * NSP;
       double prim[NP], aux[NA];
-#pragma unroll
-      for (int q = 0; q < NP; ++q) prim[q] = W[(size_t)(NVAR + 1 + q) * m.nn + i];
-#pragma unroll
-      for (int q = 0; q < NA; ++q) aux[q] = W[(size_t)(NVAR + 1 + NP + q) * m.nn + i];
+      ns_node_state<ND, NSP>(mp, u, p, prim, aux);
       const bool ok = u[0] > 0.0 && prim[ND] > 0.0 && isfinite(prim[ND]);
       cand = ns_node_dt<ND, NSP>(m.dxmin[i], dc, mp, u[0], prim, p, aux, ok);
     } else {
@@ -2535,6 +2531,7 @@ __device__ inline Finish batch_finish(const BatchEntry& e, const BatchStage& st,
   Finish f{};
   f.Un = e.W[cur];
   f.Wout = e.W[cur ^ 1];
+  f.WSin = st.stage == 1 ? e.WS[cur] : e.WS[cur ^ 1];
   f.WSout = e.WS[cur ^ 1];
   f.nws = e.nws;
   f.ldws = e.ldws;
