@@ -765,7 +765,7 @@ extern "C" vcx_status vcx_gradient(vcx_solver s, double* G, int is_device) {
   if (!s || !G) return fail(VCX_E_ARG, "NULL argument");
   if (!s->has_state) return fail(VCX_E_STATE, "no state uploaded");
   GradCtl gc{nullptr, 0, 0};
-  VCX_TRY(s->kt->grad(s, s->W[s->cur], gc));
+  VCX_TRY(s->kt->grad(s, s->W[s->cur], gc, true));
   VCX_TRY(s->kt->grad_complete(s));
   if (node_gradient(s->ph.model, s->nd, s->mesh->h.nv) || s->dd_ngrad) {
     // node-major gradient rows: their first nr * nd components
@@ -796,7 +796,7 @@ extern "C" vcx_status vcx_residual(vcx_solver s, double dt, double* r, int is_de
     VCX_TRY(s->kt->fused(s, Win, f, fc, dt));
   } else {
     GradCtl gc{nullptr, 0, 0};
-    VCX_TRY(s->kt->grad(s, Win, gc));
+    VCX_TRY(s->kt->grad(s, Win, gc, false));
     if (s->ph.closure == 2) VCX_TRY(s->kt->closure2(s, f));
     VCX_TRY(s->kt->flux(s, Win, f, dt));
   }
@@ -871,7 +871,7 @@ static vcx_status enqueue_step(vcx_solver s) {
       VCX_TRY(s->kt->fused(s, Win, f, fc, 0.0));
     } else {
       GradCtl gc{s->lp, par, k == 1 ? 1 : 0};
-      VCX_TRY(s->kt->grad(s, Win, gc));
+      VCX_TRY(s->kt->grad(s, Win, gc, false));
       if (s->ph.closure == 2) VCX_TRY(s->kt->closure2(s, f));
       VCX_TRY(s->kt->flux(s, Win, f, 0.0));
     }
@@ -986,6 +986,7 @@ static BatchEntry entry_of(vcx_solver s) {
   e.WS[1] = s->WS[1];
   e.nws = s->nws;
   e.ldws = s->ldws;
+  e.g32 = g_fp32(s) ? 1 : 0;
   e.G = s->G;
   e.PG = s->PG;
   e.PR = s->PR;

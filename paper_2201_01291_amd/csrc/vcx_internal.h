@@ -146,7 +146,8 @@ inline vcx_status launch(vcx_solver s, const char* name, F&& f) {
 // ---------------------------------------------------------------------------
 
 struct KernelTable {
-  vcx_status (*grad)(vcx_solver, const double* Win, const GradCtl& gc);
+  // fp64_out: G in FP64 whatever the flux pass stages (the gradient query)
+  vcx_status (*grad)(vcx_solver, const double* Win, const GradCtl& gc, bool fp64_out);
   vcx_status (*grad_complete)(vcx_solver);
   vcx_status (*flux)(vcx_solver, const double* Win, const Finish& f, double dt_host);
   vcx_status (*update_shared)(vcx_solver, const Finish& f);
@@ -277,13 +278,22 @@ struct Impl {
       return vcx::fail(VCX_E_ARG, "no fused pass for this model");
     }
   }
-  static vcx_status grad(vcx_solver s, const double* Win, const GradCtl& gc) {
+  static vcx_status grad(vcx_solver s, const double* Win, const GradCtl& gc, bool fp64_out) {
     const DevMesh& m = s->mesh->d;
     const int lead = gc.lp && gc.first_stage ? 1 : 0;
     if constexpr (node_gradient(MODEL, ND, NV)) {
       // the node-gradient pass (node-major G, complete); the multi-species
-      // fields from the node-major staged rows
+      // fields from the node-major staged rows, and G in the type the
+      // multi-species flux pass stages
       const double* WS = ws_of(s, Win);
+      if constexpr (MODEL == 2 && !std::is_same<CT, double>::value) {
+        if (!fp64_out)
+          return launch(s, "gradient", [&](hipEvent_t ea, hipEvent_t eb) {
+            hipExtLaunchKernelGGL((k_grad_node<ND, NGF, true, CT>), dim3(xcd_grid(m.ng_nslices) + lead),
+                                  dim3(64 * kGradNodeGroups), 0, s->mesh->stream, ea, eb, 0, m, Win, WS, s->ldws,
+                                  reinterpret_cast<CT*>(s->G), gc);
+          });
+      }
       return launch(s, "gradient", [&](hipEvent_t ea, hipEvent_t eb) {
         hipExtLaunchKernelGGL((k_grad_node<ND, NGF, MODEL == 2>), dim3(xcd_grid(m.ng_nslices) + lead),
                               dim3(64 * kGradNodeGroups), 0, s->mesh->stream, ea, eb, 0, m, Win, WS, s->ldws, s->G,
@@ -511,7 +521,8 @@ struct Impl {
     }
     if constexpr (node_gradient(MODEL, ND, NV)) {
       VCX_TRY(launch_on(s, stream, prof, "gradient", [&](hipEvent_t ea, hipEvent_t eb) {
-        hipExtLaunchKernelGGL((k_grad_node_batch<ND, NGF, MODEL == 2>), dim3(xcd_grid(br.ngrad_blocks)),
+        hipExtLaunchKernelGGL((k_grad_node_batch<ND, NGF, MODEL == 2, typename std::conditional<MODEL == 2, CT, double>::type>),
+                              dim3(xcd_grid(br.ngrad_blocks)),
                               dim3(64 * kGradNodeGroups), 0,
                               stream, ea, eb, 0, (const BatchEntry*)br.tab, (const int2*)br.grad_map,
                               br.ngrad_blocks, st);
@@ -591,6 +602,12 @@ struct Impl {
   }
 };
 
+// Multi-species FP32 path: the gradient pass stores G in FP32, the values the
+// flux pass stages.
+inline bool g_fp32(vcx_solver s) {
+  return s->ph.model == VCX_MODEL_NAVIER_STOKES && s->ph.precision == VCX_PREC_MIXED;
+}
+
 inline Finish make_finish(vcx_solver s) {
   Finish f{};
   f.cbuf = s->cbuf;
@@ -606,6 +623,7 @@ inline Finish make_finish(vcx_solver s) {
   // node; so do the node-gradient passes
   f.gfull = (s->fused && s->gout != nullptr) || s->ph.model == VCX_MODEL_NAVIER_STOKES || s->dd_ngrad;
   f.gnode = s->dd_ngrad ? 1 : 0;
+  f.g32 = g_fp32(s) ? 1 : 0;
   return f;
 }
 

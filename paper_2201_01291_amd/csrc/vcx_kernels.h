@@ -15,6 +15,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "vcx_device.h"
 
 namespace vcx {
@@ -738,22 +740,46 @@ __device__ inline void shared_gradient(const DevMesh& m, const double* __restric
   for (int j = 0; j < NC; ++j) out[j] *= coef;
 }
 
-// Gradient components [C0, C0 + NCS) of node g from the node-major G (NC
-// components per node, contiguous) into LDS (sG [NCS][maxn]).
-// The row is read in 16-byte pairs from its first even component (NC is
-// the row stride, even: every node's row starts 16-byte aligned).
-template <int NC, int C0, int NCS, typename CT>
-__device__ inline void stage_gradient_row(const double* __restrict__ G, int g, CT* sG, int maxn, int q) {
+// Components [C0, C0 + NCS) of node g from node-major rows (NC components
+// per node, contiguous, of type ST) into LDS (sG [NCS][maxn]).
+// The row is read in pairs from its first even component (NC is the row
+// stride, even: every node's row starts pair-aligned).
+template <int NC, int C0, int NCS, typename CT, typename ST = double>
+__device__ inline void stage_gradient_row(const ST* __restrict__ G, int g, CT* sG, int maxn, int q) {
   static_assert(NC % 2 == 0, "node rows of an even stride");
+  if constexpr (std::is_same<ST, float>::value && NC % 4 == 0) {
+    // FP32 rows of a stride divisible by 4: 16-byte quads between leading
+    // and trailing singles
+    constexpr int HL = (4 - C0 % 4) % 4 < NCS ? (4 - C0 % 4) % 4 : NCS;
+    constexpr int NQ = (NCS - HL) / 4, TL = NCS - HL - 4 * NQ;
+    const float* src = G + (size_t)g * NC + C0;
+#pragma unroll
+    for (int k = 0; k < HL; ++k) sG[k * maxn + q] = CT(src[k]);
+    const float4* p4 = reinterpret_cast<const float4*>(src + HL);
+    float4 v[NQ == 0 ? 1 : NQ];
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) v[k] = p4[k];
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) {
+      sG[(HL + 4 * k) * maxn + q] = CT(v[k].x);
+      sG[(HL + 4 * k + 1) * maxn + q] = CT(v[k].y);
+      sG[(HL + 4 * k + 2) * maxn + q] = CT(v[k].z);
+      sG[(HL + 4 * k + 3) * maxn + q] = CT(v[k].w);
+    }
+#pragma unroll
+    for (int k = 0; k < TL; ++k) sG[(HL + 4 * NQ + k) * maxn + q] = CT(src[HL + 4 * NQ + k]);
+    return;
+  }
+  using P2 = typename std::conditional<std::is_same<ST, double>::value, double2, float2>::type;
   constexpr int H = C0 % 2;                // a leading odd component, read alone
   constexpr int NPAIR = (NCS - H) / 2;     // then pairs
   constexpr int T = NCS - H - 2 * NPAIR;   // and a trailing single
-  const double* src = G + (size_t)g * NC + C0;
+  const ST* src = G + (size_t)g * NC + C0;
   if constexpr (H) sG[q] = CT(src[0]);
-  const double2* p2 = reinterpret_cast<const double2*>(src + H);
+  const P2* p2 = reinterpret_cast<const P2*>(src + H);
   constexpr int PC = NPAIR == 0 ? 1 : (NPAIR <= 16 ? NPAIR : 8);
   for (int k0 = 0; k0 < NPAIR; k0 += PC) {
-    double2 v[PC];
+    P2 v[PC];
 #pragma unroll
     for (int kk = 0; kk < PC; ++kk)
       if (k0 + kk < NPAIR) v[kk] = p2[k0 + kk];
@@ -887,11 +913,13 @@ __global__ void __launch_bounds__(256) k_grad_shared(DevMesh m, const double* __
 #endif
 constexpr int kGradNodeGroups = VCX_GRAD_NODE_GROUPS;
 // WSR: the fields come from the node-major staged rows WS ([nn][ldws]) of
-// the multi-species model instead of the component-major W.
-template <int ND, int NR, bool WSR = false>
+// the multi-species model instead of the component-major W.  GT: the type
+// G is stored in (sums in FP64 either way; FP32 for a flux pass that stages
+// its gradients in FP32, which then reads the same values).
+template <int ND, int NR, bool WSR = false, typename GT = double>
 __device__ inline void grad_node_body(const DevMesh& m, const double* __restrict__ W,
                                       const double* __restrict__ WS, int ldws,
-                                      double* __restrict__ G, const GradCtl& ctl, int sl) {
+                                      GT* __restrict__ G, const GradCtl& ctl, int sl) {
   constexpr int FG = (NR + kGradNodeGroups - 1) / kGradNodeGroups, NC = NR * ND, NCP = node_row(NC);
   constexpr int LD = NCP + 1;
   __shared__ double sg[64 * LD];
@@ -935,17 +963,17 @@ __device__ inline void grad_node_body(const DevMesh& m, const double* __restrict
         for (int d = 0; d < ND; ++d) sg[lane * LD + (v0 + f) * ND + d] = coef * acc[f][d];
   }
   __syncthreads();
-  double* out = G + (size_t)sl * 64 * NCP;
+  GT* out = G + (size_t)sl * 64 * NCP;
   for (int idx = threadIdx.x; idx < nb * NCP; idx += blockDim.x) {
     const int l = idx / NCP, c = idx - l * NCP;
-    out[idx] = c < NC ? sg[l * LD + c] : 0.0;  // (the padding component of an odd row: 0)
+    out[idx] = GT(c < NC ? sg[l * LD + c] : 0.0);  // (the padding component of an odd row: 0)
   }
 }
 
-template <int ND, int NR, bool WSR = false>
+template <int ND, int NR, bool WSR = false, typename GT = double>
 __global__ void __launch_bounds__(64 * kGradNodeGroups) k_grad_node(DevMesh m, const double* __restrict__ W,
                                                    const double* __restrict__ WS, int ldws,
-                                                   double* __restrict__ G, GradCtl ctl) {
+                                                   GT* __restrict__ G, GradCtl ctl) {
   // in the first stage of a step, block 0 reduces the time-step candidates
   // and commits (the slices take the other blocks)
   const int lead = ctl.lp && ctl.first_stage ? 1 : 0;
@@ -955,7 +983,7 @@ __global__ void __launch_bounds__(64 * kGradNodeGroups) k_grad_node(DevMesh m, c
   }
   const int sl = xcd_tile_of((int)blockIdx.x - lead, m.ng_nslices);
   if (sl >= m.ng_nslices) return;
-  grad_node_body<ND, NR, WSR>(m, W, WS, ldws, G, ctl, sl);
+  grad_node_body<ND, NR, WSR, GT>(m, W, WS, ldws, G, ctl, sl);
 }
 
 // ---------------------------------------------------------------------------
@@ -980,6 +1008,7 @@ struct Finish {
                         // closure, the node-gradient passes, the drift-diffusion flux
                         // pass after the shared-node completion)
   int gnode;            // drift-diffusion: G is node-major (rows of node_row(NSP * ND))
+  int g32;              // multi-species FP32 path: G holds FP32 values
   DtCoef dc;
   MixParams mix;        // Navier-Stokes species data
   double alpha;
@@ -1096,8 +1125,9 @@ template <int ND, int NSP>
 __device__ inline double ns_hoop_stress(const DevMesh& m, const Finish& f, int i) {
   constexpr int NVAR = 2 + ND + NSP, NR = NVAR + 1, NP = ND + 1 + NSP, NCP = node_row((NR + NP) * ND);
   constexpr int CR = (NR + 1) * ND + 1, CX = NR * ND;  // du_r/dr, du_x/dx
-  const double durdr = f.G[(size_t)i * NCP + CR];
-  const double duxdx = f.G[(size_t)i * NCP + CX];
+  const float* G32 = reinterpret_cast<const float*>(f.G);
+  const double durdr = f.g32 ? double(G32[(size_t)i * NCP + CR]) : f.G[(size_t)i * NCP + CR];
+  const double duxdx = f.g32 ? double(G32[(size_t)i * NCP + CX]) : f.G[(size_t)i * NCP + CX];
   const double* row = f.WSin + (size_t)i * f.ldws;
   const double eta = row[NR + NP + 1], ur = row[NR + 1];  // aux[1], prim[1]
   const double rr = m.x[(size_t)m.nn + i];
@@ -2037,6 +2067,7 @@ __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ WS,
   constexpr int NP = ND + 1 + NSP, NC = (NR + NP) * ND;
   constexpr int RA = L::RA, CA = L::CA, RB = L::RB, CB = L::CB;
   static_assert(RB == 1 + NP + (NWS - NR - NP - 1), "phase B stages rho, the primitives and the staged tail");
+  const CT* GC = reinterpret_cast<const CT*>(G);  // G is stored in the staging type
   if (step_inactive(f.sc)) return;
   const int c0 = m.tile_cell[t], nc = m.tile_cell[t + 1] - c0;
   const int s0 = m.tile_slot[t], ns = m.tile_slot[t + 1] - s0;
@@ -2094,13 +2125,13 @@ __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ WS,
         stage_gradient_row<LWS, 0, NR, CT>(WS, g, sW, maxn, q);
         sW[NR * maxn + q] = CT(WS[(size_t)g * LWS + NR + NP]);
         if (tps == 2)
-          stage_gradient_row<node_row(NC), 0, CA0, CT>(G, g, sG, maxn, q);
+          stage_gradient_row<node_row(NC), 0, CA0, CT, CT>(GC, g, sG, maxn, q);
         else
-          stage_gradient_row<node_row(NC), 0, CA, CT>(G, g, sG, maxn, q);
+          stage_gradient_row<node_row(NC), 0, CA, CT, CT>(GC, g, sG, maxn, q);
 #pragma unroll
         for (int d = 0; d < ND; ++d) sX[d * maxn + q] = xx[d];
       } else {
-        stage_gradient_row<node_row(NC), CA0, CA - CA0, CT>(G, g, sG + CA0 * maxn, maxn, q);
+        stage_gradient_row<node_row(NC), CA0, CA - CA0, CT, CT>(GC, g, sG + CA0 * maxn, maxn, q);
       }
     }
     for (int p = threadIdx.x; p < ninc; p += blockDim.x) sEi[p] = m.einc[pb + p];
@@ -2193,11 +2224,11 @@ __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ WS,
         stage_gradient_row<LWS, NR, NP, CT>(WS, g, sW + maxn, maxn, q);
         stage_gradient_row<LWS, NR + NP + 1, NWS - NR - NP - 1, CT>(WS, g, sW + (1 + NP) * maxn, maxn, q);
         if (tps == 2)
-          stage_gradient_row<node_row(NC), CA, CB0, CT>(G, g, sG, maxn, q);
+          stage_gradient_row<node_row(NC), CA, CB0, CT, CT>(GC, g, sG, maxn, q);
         else
-          stage_gradient_row<node_row(NC), CA, CB, CT>(G, g, sG, maxn, q);
+          stage_gradient_row<node_row(NC), CA, CB, CT, CT>(GC, g, sG, maxn, q);
       } else {
-        stage_gradient_row<node_row(NC), CA + CB0, CB - CB0, CT>(G, g, sG + CB0 * maxn, maxn, q);
+        stage_gradient_row<node_row(NC), CA + CB0, CB - CB0, CT, CT>(GC, g, sG + CB0 * maxn, maxn, q);
       }
     }
   }
@@ -2500,6 +2531,7 @@ struct BatchEntry {
   double* WS[2];    // multi-species: their node-major staged rows, or null
   int nws, ldws;
   double* G;
+  int g32;          // multi-species FP32 path: G holds FP32 values
   double* PG;
   double* PR;
   const double* E;
@@ -2537,6 +2569,7 @@ __device__ inline Finish batch_finish(const BatchEntry& e, const BatchStage& st,
   f.ldws = e.ldws;
   f.Win = st.stage == 1 ? e.W[cur] : e.W[cur ^ 1];
   f.G = e.G;
+  f.g32 = e.g32;
   f.PG = e.PG;
   f.E = e.E;
   const int par = (st.step + e.spar) & 1;
@@ -2582,7 +2615,7 @@ __global__ void __launch_bounds__(256) k_grad_tile_batch(const BatchEntry* __res
 
 // node gradient of every solve of a batch (block map: solve, node slice;
 // slice -1 is the solve's decision entry)
-template <int ND, int NR, bool WSR = false>
+template <int ND, int NR, bool WSR = false, typename GT = double>
 __global__ void __launch_bounds__(64 * kGradNodeGroups) k_grad_node_batch(const BatchEntry* __restrict__ tab,
                                                          const int2* __restrict__ map, int nblocks,
                                                          BatchStage st) {
@@ -2599,7 +2632,7 @@ __global__ void __launch_bounds__(64 * kGradNodeGroups) k_grad_node_batch(const 
   const double* Win = st.stage == 1 ? e.W[cur] : e.W[cur ^ 1];
   GradCtl ctl{e.lp, par, st.stage == 1 ? 1 : 0};
   const double* WSin = st.stage == 1 ? e.WS[cur] : e.WS[cur ^ 1];
-  grad_node_body<ND, NR, WSR>(e.m, Win, WSin, e.ldws, e.G, ctl, ml.y);
+  grad_node_body<ND, NR, WSR, GT>(e.m, Win, WSin, e.ldws, reinterpret_cast<GT*>(e.G), ctl, ml.y);
 }
 
 template <int ND, int NSP, int FLUX, typename CT>

@@ -105,7 +105,7 @@ extern "C" vcx_status vcx_residual_noalloc(vcx_mesh mesh, const vcx_physics* phy
     VCX_TRY(kt->fused(&s, Win, f, fc, dt));
   } else {
     GradCtl gc{nullptr, 0, 0};
-    VCX_TRY(kt->grad(&s, Win, gc));
+    VCX_TRY(kt->grad(&s, Win, gc, false));
     if (ph.closure == 2) VCX_TRY(kt->closure2(&s, f));
     VCX_TRY(kt->flux(&s, Win, f, dt));
   }
