@@ -418,17 +418,19 @@ struct SolverSizes {
 };
 
 // Row stride of the multi-species node-major staged rows (0: other models).
+// FP64 staged rows: conserved, p, primitives, gamma, mu, lambda (the FP32
+// path stages the species D and h_s rows from its FP32 copy)
 static int staged_row_stride(int nd, const vcx_physics& ph) {
   if (ph.model != VCX_MODEL_NAVIER_STOKES) return 0;
-  return node_row(ns_staged_rows(nd, ph.nspecies, ph.precision != VCX_PREC_MIXED));
+  return ns_row64(ns_staged_rows(nd, ph.nspecies, true));
 }
 
 static SolverSizes solver_sizes(const DevMesh& d, int nd, int nvar, int nr, int nw, int ngf, int model,
-                                int ldws) {
+                                size_t ws_doubles) {
   SolverSizes z;
   const size_t nn = (size_t)d.nn, P = (size_t)d.nslots;
   z.W = (size_t)nw * nn;
-  z.WS = (size_t)ldws * nn;
+  z.WS = ws_doubles;
   z.G = (size_t)node_row(ngf * nd) * nn;  // (node-major rows are padded to an even stride)
   z.PG = (size_t)ngf * nd * P;
   z.PR = (size_t)nvar * P;
@@ -576,7 +578,7 @@ vcx_status vcx::configure_solver(vcx_solver s, vcx_mesh mesh, const vcx_physics&
   s->nw = kt->nw;
   s->ngf = kt->ngf;
   s->ldws = staged_row_stride(nd, ph);
-  s->nws = s->ldws ? ns_staged_rows(nd, ph.nspecies, ph.precision != VCX_PREC_MIXED) : 0;
+  s->nws = s->ldws ? ns_staged_rows(nd, ph.nspecies, true) : 0;
   s->kt = kt;
   const DevMesh& d = mesh->d;
   // (the node-gradient pass takes no dynamic LDS)
@@ -646,7 +648,8 @@ extern "C" vcx_status vcx_solver_create(vcx_mesh mesh, const vcx_physics* phys, 
     }
   }
   const DevMesh& d = mesh->d;
-  const SolverSizes z = solver_sizes(d, nd, s->nvar, s->nr, s->nw, s->ngf, ph.model, s->ldws);
+  const SolverSizes z = solver_sizes(d, nd, s->nvar, s->nr, s->nw, s->ngf, ph.model,
+                                     staged_doubles((size_t)d.nn, s->ldws, nd, ph.nspecies, g_fp32(s)));
   s->bytes = z.bytes();
   vcx_status st = VCX_OK;
   auto chk = [&](vcx_status x) {
@@ -1190,7 +1193,10 @@ vcx_status vcx::solver_footprint(vcx_mesh mesh, const vcx_physics* ph, size_t* b
   const int nd = mesh->h.nd;
   const int nvar = ph->model == VCX_MODEL_DRIFT_DIFFUSION ? ph->nspecies : 2 + nd + ph->nspecies;
   const int nr = ph->model == VCX_MODEL_DRIFT_DIFFUSION ? nvar : nvar + 1;
-  *bytes = solver_sizes(mesh->d, nd, nvar, nr, kt->nw, kt->ngf, ph->model, staged_row_stride(nd, *ph)).bytes();
+  const bool ws32 = ph->model == VCX_MODEL_NAVIER_STOKES && ph->precision == VCX_PREC_MIXED;
+  *bytes = solver_sizes(mesh->d, nd, nvar, nr, kt->nw, kt->ngf, ph->model,
+                        staged_doubles((size_t)mesh->d.nn, staged_row_stride(nd, *ph), nd, ph->nspecies, ws32))
+               .bytes();
   return VCX_OK;
 }
 

@@ -329,7 +329,8 @@ struct Impl {
                          m.nd, NSP, s->ph.gamma);
     } else if constexpr (MODEL == 2) {
       hipLaunchKernelGGL((k_ns_aux<ND, NSP>), dim3((m.nn + 255) / 256), dim3(256), 0, s->mesh->stream,
-                         W, m.nn, mix_params(s->ph), const_cast<double*>(ws_of(s, W)), s->nws, s->ldws);
+                         W, m.nn, mix_params(s->ph), const_cast<double*>(ws_of(s, W)), s->nws, s->ldws,
+                         std::is_same<CT, double>::value ? 0 : 1);
     }
     VCX_HIP(hipGetLastError());
     return VCX_OK;
@@ -606,6 +607,13 @@ struct Impl {
 // flux pass stages.
 inline bool g_fp32(vcx_solver s) {
   return s->ph.model == VCX_MODEL_NAVIER_STOKES && s->ph.precision == VCX_PREC_MIXED;
+}
+
+// Doubles of one staged-row buffer: nn FP64 rows of ldws, then on the FP32
+// path the FP32 rows (nn rows of ns_row32 of the FP32 path's staged count).
+inline size_t staged_doubles(size_t nn, int ldws, int nd, int nsp, bool fp32) {
+  if (!ldws) return 0;
+  return (size_t)ldws * nn + (fp32 ? ((size_t)ns_row32(ns_staged_rows(nd, nsp, false)) * nn + 1) / 2 : 0);
 }
 
 inline Finish make_finish(vcx_solver s) {

@@ -190,6 +190,16 @@ __host__ __device__ constexpr int node_row(int nc) { return nc + (nc & 1); }
 __host__ __device__ constexpr int ns_staged_rows(int nd, int nsp, bool fp64) {
   return (2 + nd + nsp) + 1 + (nd + 1 + nsp) + (fp64 ? 3 : 3 + 2 * nsp);
 }
+// The FP64 rows of a staged-row buffer hold the FP64 path's staged values
+// (ns_staged_rows(nd, nsp, true)); after its nn rows the FP32 path keeps its
+// own staged values in FP32 ([nn][ns_row32(ns_staged_rows(nd, nsp, false))],
+// rows 16-byte aligned) for its flux staging: the values that staging
+// rounded FP64 rows to.
+__host__ __device__ constexpr int ns_row32(int nws) { return (nws + 3) & ~3; }
+// Stride of the FP64 staged rows: even (rows 16-byte aligned) and an odd
+// number of 16-byte units, so that a field of many rows does not fall on a
+// few memory channels as with a power-of-two stride.
+__host__ __device__ constexpr int ns_row64(int nws) { return node_row(nws) % 4 == 0 ? node_row(nws) + 2 : node_row(nws); }
 
 __device__ inline bool step_inactive(const DevScalars* sc) {
   return sc != nullptr && sc->active == 0;
@@ -1139,6 +1149,26 @@ __device__ inline double ns_hoop_stress(const DevMesh& m, const Finish& f, int i
 // (conserved, p, primitives, then the transport/thermo rows) contiguous.
 // The row starts 16-byte aligned (an even stride): it is written in pairs.
 template <int ND, int NSP>
+__device__ inline void ns_store_node_row32(float* row, const double (&u)[2 + ND + NSP], double p,
+                                           const double (&prim)[ND + 1 + NSP], const double (&aux)[3 + 2 * NSP]) {
+  constexpr int NVAR = 2 + ND + NSP, NP = ND + 1 + NSP, NA = 3 + 2 * NSP, NT = NVAR + 1 + NP + NA;
+  constexpr int L = ns_row32(NT);
+  float r[L];
+#pragma unroll
+  for (int v = 0; v < NVAR; ++v) r[v] = float(u[v]);
+  r[NVAR] = float(p);
+#pragma unroll
+  for (int q = 0; q < NP; ++q) r[NVAR + 1 + q] = float(prim[q]);
+#pragma unroll
+  for (int q = 0; q < NA; ++q) r[NVAR + 1 + NP + q] = float(aux[q]);
+#pragma unroll
+  for (int c = NT; c < L; ++c) r[c] = 0.0f;
+  float4* r4 = reinterpret_cast<float4*>(row);
+#pragma unroll
+  for (int c = 0; c < L; c += 4) r4[c / 4] = make_float4(r[c], r[c + 1], r[c + 2], r[c + 3]);
+}
+
+template <int ND, int NSP>
 __device__ inline void ns_store_node_row(double* row, int nws, const double (&u)[2 + ND + NSP], double p,
                                          const double (&prim)[ND + 1 + NSP], const double (&aux)[3 + 2 * NSP]) {
   constexpr int NVAR = 2 + ND + NSP, NP = ND + 1 + NSP, NA = 3 + 2 * NSP, NT = NVAR + 1 + NP + NA;
@@ -1221,6 +1251,10 @@ __device__ inline double finish_node(const DevMesh& m, const Finish& f, int i, b
     ok = ns_node_state<ND, NSP>(f.mix, u, p, prim, aux);
     f.Wout[(size_t)NVAR * m.nn + i] = p;
     ns_store_node_row<ND, NSP>(f.WSout + (size_t)i * f.ldws, f.nws, u, p, prim, aux);
+    if (f.g32)
+      ns_store_node_row32<ND, NSP>(reinterpret_cast<float*>(f.WSout + (size_t)m.nn * f.ldws) +
+                                       (size_t)i * ns_row32(ns_staged_rows(ND, NSP, false)),
+                                   u, p, prim, aux);
 #pragma unroll
     for (int v = 0; v < NVAR; ++v) ok = ok && isfinite(u[v]);
     if (!f.final_stage) return INFINITY;
@@ -2063,11 +2097,17 @@ __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ WS,
   constexpr int NV = ND + 1, NVAR = 2 + ND + NSP, NR = NVAR + 1, NCE = L::NCE;
   // the node-major staged rows: all but the species D and h_s rows where
   // FP64 forms them (ns_staged_rows)
-  constexpr int NWS = ns_staged_rows(ND, NSP, L::RECOMPUTE), LWS = node_row(NWS);
+  constexpr int NWS = ns_staged_rows(ND, NSP, L::RECOMPUTE), LWS = ns_row64(NWS);
   constexpr int NP = ND + 1 + NSP, NC = (NR + NP) * ND;
   constexpr int RA = L::RA, CA = L::CA, RB = L::RB, CB = L::CB;
   static_assert(RB == 1 + NP + (NWS - NR - NP - 1), "phase B stages rho, the primitives and the staged tail");
   const CT* GC = reinterpret_cast<const CT*>(G);  // G is stored in the staging type
+  // the staged rows in the staging type: FP64, or the FP32 rows after the
+  // FP64 ones (of the FP64 path's stride)
+  constexpr bool R32 = std::is_same<CT, float>::value;
+  constexpr int LWR = R32 ? ns_row32(NWS) : LWS;
+  constexpr int LW64 = ns_row64(ns_staged_rows(ND, NSP, true));
+  const CT* WR = R32 ? reinterpret_cast<const CT*>(WS + (size_t)m.nn * LW64) : reinterpret_cast<const CT*>(WS);
   if (step_inactive(f.sc)) return;
   const int c0 = m.tile_cell[t], nc = m.tile_cell[t + 1] - c0;
   const int s0 = m.tile_slot[t], ns = m.tile_slot[t + 1] - s0;
@@ -2122,8 +2162,8 @@ __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ WS,
         double xx[ND];
 #pragma unroll
         for (int d = 0; d < ND; ++d) xx[d] = m.x[(size_t)d * m.nn + g];
-        stage_gradient_row<LWS, 0, NR, CT>(WS, g, sW, maxn, q);
-        sW[NR * maxn + q] = CT(WS[(size_t)g * LWS + NR + NP]);
+        stage_gradient_row<LWR, 0, NR, CT, CT>(WR, g, sW, maxn, q);
+        sW[NR * maxn + q] = WR[(size_t)g * LWR + NR + NP];
         if (tps == 2)
           stage_gradient_row<node_row(NC), 0, CA0, CT, CT>(GC, g, sG, maxn, q);
         else
@@ -2220,9 +2260,9 @@ __device__ inline void flux_ns_body(DevMesh m, const double* __restrict__ WS,
       const int h = t >= ns ? 1 : 0, q = t - h * ns;
       const int g = slot_node_id(sSl[q]);
       if (h == 0) {
-        sW[q] = CT(WS[(size_t)g * LWS]);
-        stage_gradient_row<LWS, NR, NP, CT>(WS, g, sW + maxn, maxn, q);
-        stage_gradient_row<LWS, NR + NP + 1, NWS - NR - NP - 1, CT>(WS, g, sW + (1 + NP) * maxn, maxn, q);
+        sW[q] = WR[(size_t)g * LWR];
+        stage_gradient_row<LWR, NR, NP, CT, CT>(WR, g, sW + maxn, maxn, q);
+        stage_gradient_row<LWR, NR + NP + 1, NWS - NR - NP - 1, CT, CT>(WR, g, sW + (1 + NP) * maxn, maxn, q);
         if (tps == 2)
           stage_gradient_row<node_row(NC), CA, CB0, CT, CT>(GC, g, sG, maxn, q);
         else
@@ -2373,7 +2413,7 @@ __global__ void __launch_bounds__(256) k_prim_to_cons(double* __restrict__ W, in
 // and the node-major staged row
 template <int ND, int NSP>
 __global__ void __launch_bounds__(256) k_ns_aux(double* __restrict__ W, int nn, MixParams mp,
-                                                double* __restrict__ WS, int nws, int ldws) {
+                                                double* __restrict__ WS, int nws, int ldws, int ws32) {
   constexpr int NVAR = 2 + ND + NSP, NP = ND + 1 + NSP, NA = 3 + 2 * NSP;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nn) return;
@@ -2383,6 +2423,10 @@ __global__ void __launch_bounds__(256) k_ns_aux(double* __restrict__ W, int nn, 
   ns_node_state<ND, NSP>(mp, u, p, prim, aux);
   W[(size_t)NVAR * nn + i] = p;
   ns_store_node_row<ND, NSP>(WS + (size_t)i * ldws, nws, u, p, prim, aux);
+  if (ws32)
+    ns_store_node_row32<ND, NSP>(reinterpret_cast<float*>(WS + (size_t)nn * ldws) +
+                                     (size_t)i * ns_row32(ns_staged_rows(ND, NSP, false)),
+                                 u, p, prim, aux);
 }
 
 // ---------------------------------------------------------------------------

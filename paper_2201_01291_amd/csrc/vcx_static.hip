@@ -66,7 +66,8 @@ extern "C" vcx_status vcx_residual_noalloc(vcx_mesh mesh, const vcx_physics* phy
   const bool dd = ph.model == VCX_MODEL_DRIFT_DIFFUSION;
   // required doubles, each array rounded up to 256 bytes
   auto rnd = [](size_t n) { return (std::max<size_t>(n, 1) + 31) / 32 * 32; };
-  const size_t need = rnd((size_t)s.nw * nn) + (s.ldws ? rnd((size_t)s.ldws * nn) : 0) + rnd((size_t)node_row(s.ngf * s.nd) * nn) +
+  const size_t nws_d = staged_doubles(nn, s.ldws, s.nd, ph.nspecies, g_fp32(&s));
+  const size_t need = rnd((size_t)s.nw * nn) + (s.ldws ? rnd(nws_d) : 0) + rnd((size_t)node_row(s.ngf * s.nd) * nn) +
                       rnd((size_t)s.ngf * s.nd * P) + rnd((size_t)s.nvar * P) + rnd((size_t)s.nvar * nn) +
                       (dd ? rnd((size_t)s.nd * nn) : 0) +
                       (ph.closure == 2 && d.nb > 0 ? rnd((size_t)d.nb * s.nvar) : 0);
@@ -78,7 +79,7 @@ extern "C" vcx_status vcx_residual_noalloc(vcx_mesh mesh, const vcx_physics* phy
   VCX_TRY(scratch_on(mesh->device, &base));
   size_t off = 0;
   s.W[0] = carve(base, off, (size_t)s.nw * nn);
-  if (s.ldws) s.WS[0] = carve(base, off, (size_t)s.ldws * nn);
+  if (s.ldws) s.WS[0] = carve(base, off, nws_d);
   s.cur = 0;
   s.G = carve(base, off, (size_t)node_row(s.ngf * s.nd) * nn);
   s.PG = carve(base, off, (size_t)s.ngf * s.nd * P);

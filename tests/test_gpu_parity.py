@@ -52,6 +52,23 @@ def test_gradient_parity(name):
     assert err.max() <= FP64_TOL
 
 
+@pytest.mark.parametrize("name", ["ns3d-sp9", "ns2d-sp2-open"])
+def test_gradient_query_of_a_mixed_solver_is_fp64(name):
+    """The multi-species FP32 path keeps G in FP32 between its passes; the
+    gradient query still runs the FP64 pass, so a mixed solver returns the
+    FP64 solver's gradient exactly."""
+    case = make_case(name)
+    _, _, s64 = _setup(case)
+    _, _, s32 = _setup(case, precision=1)
+    G64, G32 = s64.gradient(), s32.gradient()
+    assert np.array_equal(G64, G32)
+    # after a step (whose gradient passes stored FP32 rows) the query is the
+    # FP64 gradient of the stepped state
+    s32.step(1)
+    s64.upload(s32.download())
+    assert np.array_equal(s32.gradient(), s64.gradient())
+
+
 @pytest.mark.parametrize("name", CASE_NAMES)
 def test_residual_parity_fp64(name):
     case = make_case(name)
